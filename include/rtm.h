@@ -1,0 +1,189 @@
+/*
+ * rtm.h - C ABI of librtm: acoustic finite-difference modeling and reverse
+ * time migration with random boundaries and source-wavefield
+ * reconstruction, for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Barbosa & Coutinho, "Seismic Modeling and Migration with Random
+ * Boundaries on the NEC SX-Aurora TSUBASA", arXiv 2204.03380.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers named "device" are HIP device allocations owned by the caller;
+ *    pointers named "host" are ordinary host memory owned by the caller and
+ *    read only during the call.  The library never allocates, frees or
+ *    retains device memory: scratch comes from the caller's workspace `ws`
+ *    (size from rtm_workspace_bytes, base aligned to 256 bytes).
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is queued
+ *    asynchronously on it; outputs are valid after the stream completes.
+ *    Calls that validate velocities (CFL and NaN check) synchronise the
+ *    stream once before the first propagation kernel, see RTM_F_SKIP_CHECK.
+ *  - Grids: interior extents nx, ny, nz (ny = 1 in 2-D), spacing h in
+ *    metres, a random boundary of nb cells on every face.  Padded extents
+ *    are NX = nx + 2nb, NZ = nz + 2nb, NY = ny + 2nb (3-D) or 1 (2-D).
+ *    Dense fields are row-major [NZ][NY][NX] (x fastest); interior-sized
+ *    fields are [nz][ny][nx].  Outside the padded grid the wavefield is zero
+ *    (the Dirichlet condition stated with Eq. (1)).
+ *  - Positions are float triples (x, y, z) in interior grid units, 0-based,
+ *    relative to interior cell (0, 0, 0); y is ignored in 2-D.  Off-grid
+ *    positions use multilinear interpolation weights for both injection and
+ *    sampling.  Every position must lie inside the interior (RTM_ERANGE).
+ *  - Time: nt steps of dt seconds; the wavelet has nt samples w[0..nt-1];
+ *    traces are [nrec][nt + 1] (time fastest), sample n taken at t = n dt,
+ *    as the seismogram of Sec. 3 has N_rec x (N_t + 1) entries.
+ *  - Discretisation (Sec. 3): 2nd order in time, 8th order in space:
+ *      p^{n+1} = 2 p^n - p^{n-1} + (v dt)^2 (L_h p^n + w^n delta_s / h^d)
+ *    with L_h the 9-point 8th-order Laplacian and delta_s the interpolated
+ *    source.  The source enters with a positive sign (the polarity of -f in
+ *    Eq. (1)); images do not depend on this choice.
+ *  - Errors: every entry point returns RTM_OK (0) or a negative status.  All
+ *    argument checks run on the host before any work is queued, so on an
+ *    argument error nothing was launched; outputs are unspecified after any
+ *    error.  rtm_last_error() describes the last failure of the calling
+ *    thread.  No C++ exception crosses this interface.
+ */
+#ifndef RTM_H
+#define RTM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RTM_ABI_VERSION 1
+
+/* Status codes. */
+#define RTM_OK 0
+#define RTM_EINVAL (-1)     /* bad argument: null pointer, size, dimension      */
+#define RTM_ECFL (-2)       /* max(v) dt / h >= sqrt(315 / (512 d)): unstable   */
+#define RTM_ERANGE (-3)     /* a source or receiver lies outside the interior   */
+#define RTM_EWORKSPACE (-4) /* workspace null or smaller than required          */
+#define RTM_EHIP (-5)       /* a HIP runtime call or kernel launch failed       */
+#define RTM_ENUMERIC (-6)   /* velocity non-finite or not strictly positive     */
+
+/* Operations, for rtm_workspace_bytes. */
+#define RTM_OP_RBC_PAD 0 /* rtm_rbc_pad and rtm_pad_adjoint with v_cap <= 0 */
+#define RTM_OP_MODEL 1   /* rtm_model_shot                                  */
+#define RTM_OP_RTM 2     /* rtm_rtm_shot                                    */
+#define RTM_OP_VJP 3     /* rtm_model_shot_vjp                              */
+
+/* Flags for rtm_model_shot, rtm_rtm_shot and rtm_model_shot_vjp. */
+#define RTM_F_SKIP_CHECK 0x1u /* skip the velocity check and its stream sync */
+#define RTM_F_NO_REINJECT 0x2u /* rtm_rtm_shot: reconstruct with a zero right
+                                  side, as Eq. (6) is written (the wavelet is
+                                  then not removed while it is active) */
+
+/* Grid descriptor; read during the call only. */
+typedef struct rtm_grid {
+    int32_t ndim; /* 2 or 3 */
+    int32_t nb;   /* random-boundary width in cells, on every face, >= 0 */
+    int64_t nx, ny, nz; /* interior extents (ny = 1 in 2-D) */
+    double h;     /* grid spacing in metres, > 0 */
+} rtm_grid_t;
+
+/* Optional wavefield probe of rtm_rtm_shot: copies the reconstructed source
+ * wavefield p^k and the receiver wavefield mu^k at step k = snap_k
+ * (0 <= snap_k <= nt - 2) into dense padded device fields. */
+typedef struct rtm_probe {
+    int32_t snap_k;
+    float *snap_p;  /* device [NZ][NY][NX] or NULL */
+    float *snap_mu; /* device [NZ][NY][NX] or NULL */
+} rtm_probe_t;
+
+/* ABI version implemented by the loaded library (RTM_ABI_VERSION). */
+int rtm_abi_version(void);
+
+/* Message for the last failing call on this thread ("" if none).  The
+ * string is owned by the library and valid until the next call. */
+const char *rtm_last_error(void);
+
+/* Bytes of device workspace needed by `op` on `grid` with nrec receivers
+ * and nt time steps (nrec, nt ignored for RTM_OP_RBC_PAD).  Writes *bytes. */
+int rtm_workspace_bytes(const rtm_grid_t *grid, int op, int32_t nrec, int32_t nt,
+                        size_t *bytes);
+
+/* Random boundary padding (Sec. "Wavefield Reconstruction": velocities in
+ * the boundary band are randomised so that boundary returns do not
+ * correlate coherently; they must respect the stability limit).
+ *   v_int  device [nz][ny][nx] interior velocities (m/s), > 0.
+ *   v_pad  device [NZ][NY][NX] output: interior copied; a band cell j takes
+ *          min(f_j * v_edge(j), v_cap) in FP32, where v_edge(j) is the
+ *          interior velocity at j's coordinates clamped into the interior,
+ *          f_j = fmaf(0.6f, u_j, 0.7f) is uniform in [0.7, 1.3), and u_j is
+ *          the top 24 bits of SplitMix64 (Steele, Lea & Flood 2014) output
+ *          number j + 1 of the stream seeded with `seed`, times 2^-24, j the
+ *          padded linear index.  The result is a pure function of
+ *          (v_int, seed, v_cap): bit-for-bit reproducible.
+ *   v_cap  cap in m/s; v_cap <= 0 uses max(v_int), which needs `ws` of
+ *          rtm_workspace_bytes(RTM_OP_RBC_PAD) bytes (else ws may be NULL). */
+int rtm_rbc_pad(const rtm_grid_t *grid, const float *v_int, uint64_t seed, float v_cap,
+                float *v_pad, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of rtm_rbc_pad with respect to v_int, the random factors and
+ * v_cap held fixed: grad_v_int[i] = grad_v_pad[i] + sum of f_j grad_v_pad[j]
+ * over band cells j whose edge cell is i and whose value was not capped.
+ *   grad_v_pad device [NZ][NY][NX]; grad_v_int device [nz][ny][nx] output.
+ *   Deterministic (gather, no atomics).  ws as for rtm_rbc_pad. */
+int rtm_pad_adjoint(const rtm_grid_t *grid, const float *v_int, uint64_t seed, float v_cap,
+                    const float *grad_v_pad, float *grad_v_int, void *ws, size_t ws_bytes,
+                    void *stream);
+
+/* Seismic modeling of one shot (Algorithm 1 / Algorithm 4): zero initial
+ * state, nt steps of Eq. (1), recording at the receivers.
+ *   v_pad    device [NZ][NY][NX] padded velocity (from rtm_rbc_pad).
+ *   wavelet  device [nt].
+ *   src      host float[3]; rec host float[nrec][3] (nrec >= 1).
+ *   traces   device [nrec][nt + 1] output.
+ *   p_last, p_prev  device [NZ][NY][NX] or NULL: the final states p^nt and
+ *            p^(nt-1), the two panels reconstruction starts from.
+ *   flags    RTM_F_SKIP_CHECK or 0. */
+int rtm_model_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt,
+                   const float *wavelet, const float *src, int32_t nrec, const float *rec,
+                   float *traces, float *p_last, float *p_prev, uint32_t flags, void *ws,
+                   size_t ws_bytes, void *stream);
+
+/* Reverse time migration of one shot with random boundaries and source
+ * wavefield reconstruction (Algorithm 3 / Algorithm 6, Eqs. (2), (3), (6)).
+ * Forward pass as rtm_model_shot keeping the last two panels in device
+ * memory; reverse pass k = nt-1 .. 0 stepping, in one fused kernel per step,
+ *  - the reconstructed source wavefield, re-injecting the wavelet so that
+ *    the reversal is exact up to rounding (RTM_F_NO_REINJECT: Eq. (6) as
+ *    written);
+ *  - the receiver wavefield as the exact adjoint of the forward scheme,
+ *    driven by `traces` (mu^k = 2mu^{k+1} - mu^{k+2} + (v dt)^2 (L_h mu^{k+1}
+ *    + R^T g^k)), from mu^{nt+1} = mu^{nt+2} = 0;
+ *  - the two integrals of Eq. (3), pairing p^k with mu^{k+1}:
+ *    num += p^k mu^{k+1}, den += (p^k)^2 (FP32 accumulators).
+ * Output: image = num / (den + eps_rel * max(den)) on the interior.
+ *   traces   device [nrec][nt + 1] recorded data.
+ *   image    device [nz][ny][nx] output; num, den likewise or NULL.
+ *   eps_rel  stabiliser >= 0 (1e-6 recommended).
+ *   probe    NULL or a wavefield probe (see rtm_probe_t).
+ *   flags    RTM_F_SKIP_CHECK | RTM_F_NO_REINJECT or 0.
+ * The caller stacks images over shots (Algorithm 3, stacking step). */
+int rtm_rtm_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt,
+                 const float *wavelet, const float *src, int32_t nrec, const float *rec,
+                 const float *traces, float eps_rel, float *image, float *num, float *den,
+                 const rtm_probe_t *probe, uint32_t flags, void *ws, size_t ws_bytes,
+                 void *stream);
+
+/* Vector-Jacobian product of rtm_model_shot with respect to the padded
+ * velocity: given dJ/dtraces, returns dJ/dv_pad = 2 G / (v^3 dt^2) with
+ * G = sum_k mu^{k+1} (p^{k+1} - 2p^k + p^{k-1}), mu driven by grad_traces
+ * as in rtm_rtm_shot and p reconstructed from the last two panels (no
+ * wavefield storage).
+ *   grad_traces  device [nrec][nt + 1].
+ *   grad_v_pad   device [NZ][NY][NX] output.
+ *   grad_wavelet device [nt] output or NULL: dJ/dw^n = <delta_s / h^d, mu^{n+1}>. */
+int rtm_model_shot_vjp(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt,
+                       const float *wavelet, const float *src, int32_t nrec,
+                       const float *rec, const float *grad_traces, float *grad_v_pad,
+                       float *grad_wavelet, uint32_t flags, void *ws, size_t ws_bytes,
+                       void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTM_H */
