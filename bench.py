@@ -1,0 +1,175 @@
+#!/usr/bin/env python3
+"""Benchmark of the random-boundary RTM hot path on one MI355X.
+
+Workload: the 2-D folded-layer survey (2301 x 751 cells at 4 m, velocities
+1500-5500 m/s, 60-cell random boundary, 25 Hz Ricker, dt = 0.4 ms, nt = 5000,
+240 shots every 38 m, 2301 receivers), seeded and synthetic.  One step
+processes a batch of shots through the whole path: random-boundary padding,
+modeling of the observed data (forward propagation with receiver sampling),
+then RTM of each shot (forward propagation keeping two panels, fused reverse
+reconstruction + receiver back-propagation + imaging, normalisation) and
+stacking.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line.  The metric is Gcell-updates/s: padded cells x nt x
+propagations (1 for modeling, 3 for RTM) per second of device time.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--shots-per-step", type=int, default=4)
+    ap.add_argument("--nt", type=int, default=5000)
+    ap.add_argument("--cpu-sample-nt", type=int, default=240,
+                    help="time steps of the oracle's timed sample (one shot, modeling + RTM)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(survey, nt_sample):
+    """The FP64 oracle on a bounded sample of the same workload: one shot
+    (the first, on-grid source), modeling + RTM, nt_sample steps."""
+    import numpy as np
+
+    import oracle
+    s = survey
+    v_pad = oracle.rbc_pad(s.v_int, s.nb, s.seed, 0.0)
+    w = s.wavelet[:nt_sample].astype(np.float64)
+    t0 = time.perf_counter()
+    d = oracle.model_shot(v_pad, s.h, s.nb, s.dt, w, s.src[0], s.rec)
+    oracle.rtm_shot(v_pad, s.h, s.nb, s.dt, w, s.src[0], s.rec, d, eps_rel=1e-3)
+    sec = time.perf_counter() - t0
+    updates = v_pad.size * nt_sample * 4
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": updates / sec / 1e9, "unit": "Gcell-updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 shot, modeling + RTM (4 propagations), {nt_sample} of {s.nt} steps, FP64, "
+                      f"{sec:.1f} s"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE={world}): shots are "
+              "independent and a multi-GPU run would be a shot partition plus one image all-reduce, which this "
+              "build does not include.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2204_03380_amd as rtm
+    import synth
+
+    dev = torch.device("cuda:0")
+    s = synth.config_c2(nt=args.nt)
+    g = rtm.Grid.for_model(s.v_int, s.h, s.nb)
+    v_int = torch.from_numpy(s.v_int).to(dev)
+    wav = torch.from_numpy(s.wavelet).to(dev)
+    NZ, NX = g.padded_shape
+    cells = NX * NZ
+    interior = s.v_int.size
+    B = args.shots_per_step
+    nshot = s.src.shape[0]
+
+    def step(i):
+        v_pad = rtm.rtm_rbc_pad(g, v_int, s.seed, 0.0)
+        stack = torch.zeros(g.interior_shape, dtype=torch.float32, device=dev)
+        for j in range(B):
+            src = s.src[(i * B + j) % nshot]
+            d = rtm.rtm_model_shot(g, v_pad, s.dt, wav, src, s.rec)
+            out = rtm.rtm_rtm_shot(g, v_pad, s.dt, wav, src, s.rec, d, eps_rel=1e-3)
+            stack += out["image"]
+        return stack
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    rtm.rtm_timing_read()
+    rtm.rtm_timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(args.steps):
+        stack = step(args.warmup + i)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    rtm.rtm_timing_enable(False)
+    loops = rtm.rtm_timing_read()
+    dev_ms = e0.elapsed_time(e1)
+    assert torch.isfinite(stack).all()
+
+    shots = args.steps * B
+    updates = cells * args.nt * 4 * shots
+    ms_per_step = dev_ms / args.steps
+    value = updates / (dev_ms * 1e-3) / 1e9
+
+    # Dominant kernel: the fused reverse step (two stencils, imaging sums).
+    rev_ms, rev_n = loops["reverse_image"]
+    rev_us = rev_ms * 1e3 / max(rev_n, 1)
+    rev_bytes = 28 * cells + 16 * interior   # per launch (one shot, one step)
+    achieved = rev_bytes / (rev_us * 1e-6) / 1e9
+    fwd_ms, fwd_n = loops["model_forward"]
+    rf_ms, rf_n = loops["rtm_forward"]
+    line = {
+        "metric": "Gcell-updates/s",
+        "value": round(value, 3),
+        "unit": "Gcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"folded-layer 2-D survey 2301x751 @ 4 m, nb 60, nt {args.nt}, 25 Hz, 2301 receivers: "
+                        f"modeling + RTM with random boundaries, {B} shots per step, images stacked",
+            "padded_cells": cells,
+            "shots_per_step": B,
+            "propagations_per_shot": 4,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "rev2d_kernel (fused reconstruction + receiver field + imaging)",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+            "avg_launch_us": round(rev_us, 3),
+            "algorithmic_bytes_per_launch": rev_bytes,
+        },
+        "rtm_shots_per_s": round(shots / (dev_ms * 1e-3), 4),
+        "loop_us_per_launch": {
+            "model_forward": round(fwd_ms * 1e3 / max(fwd_n, 1), 3),
+            "rtm_forward": round(rf_ms * 1e3 / max(rf_n, 1), 3),
+            "reverse_image": round(rev_us, 3),
+        },
+        "wall_s": round(wall, 3),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(s, args.cpu_sample_nt)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -15,8 +15,10 @@
  *    (size from rtm_workspace_bytes, base aligned to 256 bytes).
  *  - `stream` is a hipStream_t (NULL = the default stream).  Work is queued
  *    asynchronously on it; outputs are valid after the stream completes.
- *    Calls that validate velocities (CFL and NaN check) synchronise the
- *    stream once before the first propagation kernel, see RTM_F_SKIP_CHECK.
+ *    rtm_model_shot, rtm_rtm_shot and rtm_model_shot_vjp synchronise the
+ *    stream once, before their first propagation kernel, after uploading
+ *    their acquisition tables and (unless RTM_F_SKIP_CHECK) reading back the
+ *    velocity range for the stability and finiteness check.
  *  - Grids: interior extents nx, ny, nz (ny = 1 in 2-D), spacing h in
  *    metres, a random boundary of nb cells on every face.  Padded extents
  *    are NX = nx + 2nb, NZ = nz + 2nb, NY = ny + 2nb (3-D) or 1 (2-D).
@@ -69,7 +71,7 @@ extern "C" {
 #define RTM_OP_VJP 3     /* rtm_model_shot_vjp                              */
 
 /* Flags for rtm_model_shot, rtm_rtm_shot and rtm_model_shot_vjp. */
-#define RTM_F_SKIP_CHECK 0x1u /* skip the velocity check and its stream sync */
+#define RTM_F_SKIP_CHECK 0x1u /* skip the velocity range check            */
 #define RTM_F_NO_REINJECT 0x2u /* rtm_rtm_shot: reconstruct with a zero right
                                   side, as Eq. (6) is written (the wavelet is
                                   then not removed while it is active) */
@@ -97,6 +99,27 @@ int rtm_abi_version(void);
 /* Message for the last failing call on this thread ("" if none).  The
  * string is owned by the library and valid until the next call. */
 const char *rtm_last_error(void);
+
+/* Launch shape of the 2-D propagation kernels, process-wide, for the
+ * autotuner: `op` RTM_OP_MODEL selects the forward kernel, RTM_OP_RTM or
+ * RTM_OP_VJP the reverse kernels; vec in {1, 2, 4} floats per lane (strips
+ * of 64 * vec columns), zseg in [4, 4096] rows per tile.  Results do not
+ * depend on the shape.  Not synchronised with concurrent calls. */
+int rtm_set_tuning(int op, int vec, int zseg);
+
+/* Event timing of the time loops, for measurement.  While enabled, every
+ * propagation call records a HIP event pair on its stream around each of
+ * its time loops (no host synchronisation is added).  rtm_timing_read waits
+ * for the recorded events, returns the summed loop times in milliseconds
+ * and the number of kernel launches they cover, per loop kind:
+ *   [0] forward with receiver sampling (rtm_model_shot),
+ *   [1] forward without sampling (rtm_rtm_shot, rtm_model_shot_vjp),
+ *   [2] fused reverse with imaging (rtm_rtm_shot),
+ *   [3] fused reverse with the gradient (rtm_model_shot_vjp),
+ * and clears the record.  ms and launches point to 4 elements each.
+ * Loops of calls given a probe are not recorded. */
+int rtm_timing_enable(int on);
+int rtm_timing_read(double *ms, int64_t *launches);
 
 /* Bytes of device workspace needed by `op` on `grid` with nrec receivers
  * and nt time steps (nrec, nt ignored for RTM_OP_RBC_PAD).  Writes *bytes. */
@@ -158,7 +181,10 @@ int rtm_model_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_
  * Output: image = num / (den + eps_rel * max(den)) on the interior.
  *   traces   device [nrec][nt + 1] recorded data.
  *   image    device [nz][ny][nx] output; num, den likewise or NULL.
- *   eps_rel  stabiliser >= 0 (1e-6 recommended).
+ *   eps_rel  stabiliser >= 0.  1e-3 is recommended: with much smaller values
+ *            the ratio divides by illumination far below its peak, where the
+ *            FP32 wavefields carry large relative errors (the image error
+ *            grows roughly like 1e-9 / eps_rel).
  *   probe    NULL or a wavefield probe (see rtm_probe_t).
  *   flags    RTM_F_SKIP_CHECK | RTM_F_NO_REINJECT or 0.
  * The caller stacks images over shots (Algorithm 3, stacking step). */

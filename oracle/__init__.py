@@ -14,7 +14,8 @@ import os
 
 import numpy as np
 
-from .build import LIB, build
+from .build import LIB
+from .build import build as build_library
 
 _lib = None
 
@@ -23,7 +24,7 @@ def _load():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB):
-            build()
+            build_library()
         lib = ctypes.CDLL(LIB)
         c_long, c_int, c_double, c_u64 = ctypes.c_long, ctypes.c_int, ctypes.c_double, ctypes.c_uint64
         P = ctypes.c_void_p

@@ -1,0 +1,215 @@
+"""Random-boundary RTM on MI355X: Python binding of librtm.
+
+Every function here marshals arguments for the C ABI of include/rtm.h and
+calls it; all computation runs in the library's HIP kernels.  PyTorch only
+provides device memory and the current stream.  Arrays are torch tensors on
+the GPU (float32, contiguous); positions are host arrays of (x, y, z) in
+interior grid units.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (RTM_F_NO_REINJECT, RTM_F_SKIP_CHECK, RTM_OP_MODEL, RTM_OP_RBC_PAD, RTM_OP_RTM, RTM_OP_VJP,
+                   RtmError)
+
+__all__ = [
+    "Grid", "RtmError", "rtm_workspace_bytes", "rtm_set_tuning", "rtm_timing_enable", "rtm_timing_read", "rtm_rbc_pad", "rtm_pad_adjoint",
+    "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "RTM_F_SKIP_CHECK", "RTM_F_NO_REINJECT",
+    "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD",
+]
+
+
+@dataclass(frozen=True)
+class Grid:
+    """Interior extents, spacing (m) and random-boundary width (cells)."""
+    ndim: int
+    nx: int
+    ny: int
+    nz: int
+    h: float
+    nb: int
+
+    @staticmethod
+    def for_model(v_int, h: float, nb: int) -> "Grid":
+        shape = tuple(v_int.shape)
+        if len(shape) == 2:
+            return Grid(2, shape[1], 1, shape[0], float(h), int(nb))
+        return Grid(3, shape[2], shape[1], shape[0], float(h), int(nb))
+
+    @property
+    def padded_shape(self):
+        nb = self.nb
+        if self.ndim == 2:
+            return (self.nz + 2 * nb, self.nx + 2 * nb)
+        return (self.nz + 2 * nb, self.ny + 2 * nb, self.nx + 2 * nb)
+
+    @property
+    def interior_shape(self):
+        return (self.nz, self.nx) if self.ndim == 2 else (self.nz, self.ny, self.nx)
+
+    def c(self) -> _lib.RtmGrid:
+        return _lib.RtmGrid(self.ndim, self.nb, self.nx, self.ny if self.ndim == 3 else 1, self.nz, self.h)
+
+
+def _dev(t: torch.Tensor, name: str, shape=None) -> int:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return t.data_ptr()
+
+
+def _pos(a, name) -> np.ndarray:
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float32).reshape(-1, 3))
+    if a.shape[0] < 1:
+        raise ValueError(f"{name} is empty")
+    return a
+
+
+def _fp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def rtm_workspace_bytes(grid: Grid, op: int, nrec: int = 0, nt: int = 0) -> int:
+    out = ctypes.c_size_t(0)
+    g = grid.c()
+    _lib.check(_lib.load().rtm_workspace_bytes(ctypes.byref(g), op, nrec, nt, ctypes.byref(out)))
+    return int(out.value)
+
+
+def _workspace(grid: Grid, op: int, nrec: int, nt: int, device) -> torch.Tensor:
+    n = rtm_workspace_bytes(grid, op, nrec, nt)
+    return torch.empty(max(n, 256), dtype=torch.uint8, device=device)
+
+
+def rtm_set_tuning(op: int, vec: int, zseg: int) -> None:
+    _lib.check(_lib.load().rtm_set_tuning(op, vec, zseg))
+
+
+LOOP_KINDS = ("model_forward", "rtm_forward", "reverse_image", "reverse_grad")
+
+
+def rtm_timing_enable(on: bool = True) -> None:
+    _lib.check(_lib.load().rtm_timing_enable(1 if on else 0))
+
+
+def rtm_timing_read() -> dict:
+    """{kind: (milliseconds, launches)} of the loops recorded since the last
+    read (see rtm_timing_enable)."""
+    ms = (ctypes.c_double * 4)()
+    n = (ctypes.c_int64 * 4)()
+    _lib.check(_lib.load().rtm_timing_read(ms, n))
+    return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(LOOP_KINDS)}
+
+
+def rtm_rbc_pad(grid: Grid, v_int: torch.Tensor, seed: int, v_cap: float = 0.0) -> torch.Tensor:
+    """Padded FP32 velocity with the seeded random boundary (see rtm.h)."""
+    _dev(v_int, "v_int", grid.interior_shape)
+    v_pad = torch.empty(grid.padded_shape, dtype=torch.float32, device=v_int.device)
+    ws = _workspace(grid, RTM_OP_RBC_PAD, 0, 0, v_int.device)
+    g = grid.c()
+    _lib.check(_lib.load().rtm_rbc_pad(ctypes.byref(g), v_int.data_ptr(), int(seed), float(v_cap), v_pad.data_ptr(),
+                                       ws.data_ptr(), ws.numel(), _stream(v_int.device)))
+    return v_pad
+
+
+def rtm_pad_adjoint(grid: Grid, v_int: torch.Tensor, seed: int, v_cap: float,
+                    grad_v_pad: torch.Tensor) -> torch.Tensor:
+    _dev(v_int, "v_int", grid.interior_shape)
+    _dev(grad_v_pad, "grad_v_pad", grid.padded_shape)
+    out = torch.empty(grid.interior_shape, dtype=torch.float32, device=v_int.device)
+    ws = _workspace(grid, RTM_OP_RBC_PAD, 0, 0, v_int.device)
+    g = grid.c()
+    _lib.check(_lib.load().rtm_pad_adjoint(ctypes.byref(g), v_int.data_ptr(), int(seed), float(v_cap),
+                                           grad_v_pad.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                           _stream(v_int.device)))
+    return out
+
+
+def rtm_model_shot(grid: Grid, v_pad: torch.Tensor, dt: float, wavelet: torch.Tensor, src, rec,
+                   want_last: bool = False, flags: int = 0):
+    """Traces [nrec, nt + 1] of one shot; with want_last also the final two
+    padded states (p^nt, p^(nt-1))."""
+    dev = v_pad.device
+    _dev(v_pad, "v_pad", grid.padded_shape)
+    nt = int(wavelet.numel())
+    _dev(wavelet, "wavelet", (nt,))
+    src = _pos(src, "src")[0].copy()
+    rec = _pos(rec, "rec")
+    nrec = rec.shape[0]
+    traces = torch.empty((nrec, nt + 1), dtype=torch.float32, device=dev)
+    p_last = torch.empty(grid.padded_shape, dtype=torch.float32, device=dev) if want_last else None
+    p_prev = torch.empty(grid.padded_shape, dtype=torch.float32, device=dev) if want_last else None
+    ws = _workspace(grid, RTM_OP_MODEL, nrec, nt, dev)
+    g = grid.c()
+    _lib.check(_lib.load().rtm_model_shot(
+        ctypes.byref(g), v_pad.data_ptr(), float(dt), nt, wavelet.data_ptr(), _fp(src), nrec, _fp(rec),
+        traces.data_ptr(), p_last.data_ptr() if want_last else None, p_prev.data_ptr() if want_last else None,
+        int(flags), ws.data_ptr(), ws.numel(), _stream(dev)))
+    return (traces, p_last, p_prev) if want_last else traces
+
+
+def rtm_rtm_shot(grid: Grid, v_pad: torch.Tensor, dt: float, wavelet: torch.Tensor, src, rec,
+                 traces: torch.Tensor, eps_rel: float = 1e-3, want_numden: bool = False, snap_k: int = -1,
+                 flags: int = 0) -> dict:
+    """Image of one shot (interior); optionally num, den and the probe
+    snapshots snap_p, snap_mu at step snap_k."""
+    dev = v_pad.device
+    _dev(v_pad, "v_pad", grid.padded_shape)
+    nt = int(wavelet.numel())
+    _dev(wavelet, "wavelet", (nt,))
+    src = _pos(src, "src")[0].copy()
+    rec = _pos(rec, "rec")
+    nrec = rec.shape[0]
+    _dev(traces, "traces", (nrec, nt + 1))
+    out = {"image": torch.empty(grid.interior_shape, dtype=torch.float32, device=dev)}
+    if want_numden:
+        out["num"] = torch.empty(grid.interior_shape, dtype=torch.float32, device=dev)
+        out["den"] = torch.empty(grid.interior_shape, dtype=torch.float32, device=dev)
+    probe = None
+    if snap_k >= 0:
+        out["snap_p"] = torch.zeros(grid.padded_shape, dtype=torch.float32, device=dev)
+        out["snap_mu"] = torch.zeros(grid.padded_shape, dtype=torch.float32, device=dev)
+        probe = _lib.RtmProbe(snap_k, out["snap_p"].data_ptr(), out["snap_mu"].data_ptr())
+    ws = _workspace(grid, RTM_OP_RTM, nrec, nt, dev)
+    g = grid.c()
+    _lib.check(_lib.load().rtm_rtm_shot(
+        ctypes.byref(g), v_pad.data_ptr(), float(dt), nt, wavelet.data_ptr(), _fp(src), nrec, _fp(rec),
+        traces.data_ptr(), float(eps_rel), out["image"].data_ptr(),
+        out["num"].data_ptr() if want_numden else None, out["den"].data_ptr() if want_numden else None,
+        ctypes.byref(probe) if probe is not None else None, int(flags), ws.data_ptr(), ws.numel(), _stream(dev)))
+    return out
+
+
+def rtm_model_shot_vjp(grid: Grid, v_pad: torch.Tensor, dt: float, wavelet: torch.Tensor, src, rec,
+                       grad_traces: torch.Tensor, want_wavelet_grad: bool = False, flags: int = 0):
+    """dJ/dv_pad (padded) for upstream dJ/dtraces; optionally dJ/dwavelet."""
+    dev = v_pad.device
+    _dev(v_pad, "v_pad", grid.padded_shape)
+    nt = int(wavelet.numel())
+    _dev(wavelet, "wavelet", (nt,))
+    src = _pos(src, "src")[0].copy()
+    rec = _pos(rec, "rec")
+    nrec = rec.shape[0]
+    _dev(grad_traces, "grad_traces", (nrec, nt + 1))
+    gv = torch.empty(grid.padded_shape, dtype=torch.float32, device=dev)
+    gw = torch.empty((nt,), dtype=torch.float32, device=dev) if want_wavelet_grad else None
+    ws = _workspace(grid, RTM_OP_VJP, nrec, nt, dev)
+    g = grid.c()
+    _lib.check(_lib.load().rtm_model_shot_vjp(
+        ctypes.byref(g), v_pad.data_ptr(), float(dt), nt, wavelet.data_ptr(), _fp(src), nrec, _fp(rec),
+        grad_traces.data_ptr(), gv.data_ptr(), gw.data_ptr() if want_wavelet_grad else None, int(flags),
+        ws.data_ptr(), ws.numel(), _stream(dev)))
+    return (gv, gw) if want_wavelet_grad else gv

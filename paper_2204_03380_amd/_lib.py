@@ -1,0 +1,89 @@
+"""ctypes loader for librtm.so (the HIP library).  Raises if the library is
+missing: there is no fallback path."""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librtm.so")
+
+RTM_OK = 0
+RTM_EINVAL = -1
+RTM_ECFL = -2
+RTM_ERANGE = -3
+RTM_EWORKSPACE = -4
+RTM_EHIP = -5
+RTM_ENUMERIC = -6
+
+RTM_OP_RBC_PAD = 0
+RTM_OP_MODEL = 1
+RTM_OP_RTM = 2
+RTM_OP_VJP = 3
+
+RTM_F_SKIP_CHECK = 0x1
+RTM_F_NO_REINJECT = 0x2
+
+# Every symbol declared in include/rtm.h.
+EXPORTS = (
+    "rtm_abi_version", "rtm_last_error", "rtm_set_tuning", "rtm_timing_enable", "rtm_timing_read",
+    "rtm_workspace_bytes", "rtm_rbc_pad",
+    "rtm_pad_adjoint", "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp",
+)
+
+
+class RtmGrid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("nb", ctypes.c_int32), ("nx", ctypes.c_int64),
+                ("ny", ctypes.c_int64), ("nz", ctypes.c_int64), ("h", ctypes.c_double)]
+
+
+class RtmProbe(ctypes.Structure):
+    _fields_ = [("snap_k", ctypes.c_int32), ("snap_p", ctypes.c_void_p), ("snap_mu", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """The loaded library (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise OSError(f"{LIB_PATH} not found: build it with `python -m paper_2204_03380_amd.build` "
+                      "(no CPU fallback exists)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, D, F, U32, U64, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                                        ctypes.c_float, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t)
+    G = ctypes.POINTER(RtmGrid)
+    sig = {
+        "rtm_abi_version": ([], ctypes.c_int),
+        "rtm_last_error": ([], ctypes.c_char_p),
+        "rtm_set_tuning": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "rtm_timing_enable": ([ctypes.c_int], ctypes.c_int),
+        "rtm_timing_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+        "rtm_workspace_bytes": ([G, ctypes.c_int, I32, I32, ctypes.POINTER(SZ)], ctypes.c_int),
+        "rtm_rbc_pad": ([G, P, U64, F, P, P, SZ, P], ctypes.c_int),
+        "rtm_pad_adjoint": ([G, P, U64, F, P, P, P, SZ, P], ctypes.c_int),
+        "rtm_model_shot": ([G, P, D, I32, P, P, I32, P, P, P, P, U32, P, SZ, P], ctypes.c_int),
+        "rtm_rtm_shot": ([G, P, D, I32, P, P, I32, P, P, F, P, P, P, ctypes.POINTER(RtmProbe), U32, P, SZ, P],
+                         ctypes.c_int),
+        "rtm_model_shot_vjp": ([G, P, D, I32, P, P, I32, P, P, P, P, U32, P, SZ, P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+class RtmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"librtm status {status}: {message}")
+        self.status = status
+
+
+def check(status):
+    if status != RTM_OK:
+        msg = load().rtm_last_error()
+        raise RtmError(status, msg.decode() if msg else "")
+    return status

@@ -1,0 +1,81 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol,
+and rejects bad arguments on the host before any GPU work is queued."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2204_03380_amd as rtm
+from paper_2204_03380_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "rtm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rtm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    names = _declared()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(_lib.EXPORTS) == names
+    assert lib.rtm_abi_version() == 1
+
+
+def test_workspace_bytes_and_grid_validation():
+    g = rtm.Grid(2, 201, 1, 201, 10.0, 40)
+    sizes = [rtm.rtm_workspace_bytes(g, op, 201, 1000) for op in range(4)]
+    assert sizes[0] > 0 and sizes[1] < sizes[3] <= sizes[2] * 2
+    assert rtm.rtm_workspace_bytes(g, rtm.RTM_OP_RTM, 201, 2000) > sizes[2]
+    for bad in (rtm.Grid(4, 10, 1, 10, 10.0, 2), rtm.Grid(2, 0, 1, 10, 10.0, 2), rtm.Grid(2, 10, 1, 10, 0.0, 2),
+                rtm.Grid(2, 10, 1, 10, 10.0, -1), rtm.Grid(3, 10, 0, 10, 10.0, 2)):
+        with pytest.raises(rtm.RtmError) as e:
+            rtm.rtm_workspace_bytes(bad, rtm.RTM_OP_MODEL, 1, 1)
+        assert e.value.status == _lib.RTM_EINVAL
+    with pytest.raises(rtm.RtmError):
+        rtm.rtm_workspace_bytes(g, 7, 1, 1)
+
+
+def test_set_tuning_validation():
+    with pytest.raises(rtm.RtmError):
+        rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 3, 16)
+    with pytest.raises(rtm.RtmError):
+        rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 2)
+    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 16)
+
+
+def _call_model(grid, nt=10, src=(5.0, 0.0, 3.0), rec=((1.0, 0.0, 2.0),), ws_bytes=None, ws=0x100000,
+                nrec=None, traces=0x3000):
+    """Call rtm_model_shot with fake (never dereferenced) device addresses:
+    every case below fails host validation before any device work."""
+    lib = _lib.load()
+    g = grid.c()
+    s = np.ascontiguousarray(np.array(src, np.float32))
+    r = np.ascontiguousarray(np.array(rec, np.float32).reshape(-1, 3))
+    n = r.shape[0] if nrec is None else nrec
+    if ws_bytes is None:
+        ws_bytes = rtm.rtm_workspace_bytes(grid, rtm.RTM_OP_MODEL, max(n, 1), max(nt, 1))
+    return lib.rtm_model_shot(ctypes.byref(g), 0x1000, 1e-3, nt, 0x2000, s.ctypes.data_as(ctypes.c_void_p), n,
+                              r.ctypes.data_as(ctypes.c_void_p), traces, None, None, 0, ws, ws_bytes, None)
+
+
+def test_host_validation_errors():
+    g = rtm.Grid(2, 20, 1, 12, 10.0, 4)
+    assert _call_model(g, nt=0) == _lib.RTM_EINVAL
+    assert _call_model(g, nrec=0) == _lib.RTM_EINVAL
+    assert _call_model(g, traces=None) == _lib.RTM_EINVAL
+    assert _call_model(g, src=(20.0, 0.0, 3.0)) == _lib.RTM_ERANGE      # x == nx: outside
+    assert _call_model(g, src=(-0.01, 0.0, 3.0)) == _lib.RTM_ERANGE
+    assert _call_model(g, rec=((1.0, 0.0, 11.5),)) == _lib.RTM_ERANGE   # z > nz - 1
+    assert _call_model(g, ws=None) == _lib.RTM_EWORKSPACE
+    assert _call_model(g, ws=0x100010) == _lib.RTM_EWORKSPACE           # misaligned
+    assert _call_model(g, ws_bytes=1024) == _lib.RTM_EWORKSPACE
+    msg = _lib.load().rtm_last_error().decode()
+    assert "workspace" in msg

@@ -1,0 +1,245 @@
+"""GPU parity of the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerance: relative L2 <= 1e-4 on wavefields, traces, images and gradients;
+random-boundary velocities bit-exact.  Inputs are seeded and shared: the
+oracle never sees a value produced by the GPU path.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2204_03380_amd as rtm
+import synth
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+EPS = 1e-3   # image stabiliser: a water level of 0.1 % of the peak illumination
+DEV = "cuda:0"
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def _n(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def _case(name):
+    if name == "small2d":
+        return synth.config_small2d()
+    if name == "c1":
+        return synth.config_c1()
+    if name == "ragged2d":
+        s = synth.config_small2d(nx=131, nz=37, nb=9, nt=180, seed=9)
+        return s
+    raise KeyError(name)
+
+
+def _setup(s):
+    g = rtm.Grid.for_model(s.v_int, s.h, s.nb)
+    v_pad_gpu = rtm.rtm_rbc_pad(g, _t(s.v_int), s.seed, 0.0)
+    v_pad_orc = oracle.rbc_pad(s.v_int, s.nb, s.seed, 0.0)
+    return g, v_pad_gpu, v_pad_orc
+
+
+@pytest.fixture(autouse=True)
+def _default_tuning():
+    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 16)
+    rtm.rtm_set_tuning(rtm.RTM_OP_RTM, 1, 16)
+    yield
+
+
+# ---------------------------------------------------------------------------
+
+def test_rbc_pad_bit_exact():
+    for s in (synth.config_c1(), synth.config_small2d()):
+        g, vg, vo = _setup(s)
+        assert np.array_equal(_n(vg), vo)
+    v3 = synth.random_model((20, 18, 16), 3, 1500, 3000)
+    g3 = rtm.Grid.for_model(v3, 10.0, 7)
+    for cap in (0.0, 2400.0):
+        vg = rtm.rtm_rbc_pad(g3, _t(v3), 123456789, cap)
+        assert np.array_equal(_n(vg), oracle.rbc_pad(v3, 7, 123456789, cap))
+
+
+def test_pad_adjoint_parity():
+    v = synth.random_model((33, 47), 2, 1500, 2500)
+    for nb, cap in ((6, 0.0), (6, 2300.0), (0, 0.0)):
+        g = rtm.Grid.for_model(v, 10.0, nb)
+        gp = np.random.default_rng(1).standard_normal(g.padded_shape).astype(np.float32)
+        gi = rtm.rtm_pad_adjoint(g, _t(v), 31, cap, _t(gp))
+        ref = oracle.pad_adjoint(v, nb, 31, cap, gp.astype(np.float64))
+        assert rel_l2(_n(gi), ref) < 1e-6
+
+
+@pytest.mark.parametrize("name", ["small2d", "ragged2d", "c1"])
+def test_model_shot_parity(name):
+    s = _case(name)
+    g, vg, vo = _setup(s)
+    w = s.wavelet
+    tr, pl, pp = rtm.rtm_model_shot(g, vg, s.dt, _t(w), s.src[0], s.rec, want_last=True)
+    tr_o, pl_o, pp_o = oracle.model_shot(vo, s.h, s.nb, s.dt, w.astype(np.float64), s.src[0], s.rec, want_last=True)
+    e_tr, e_pl, e_pp = rel_l2(_n(tr), tr_o), rel_l2(_n(pl), pl_o), rel_l2(_n(pp), pp_o)
+    print(f"{name}: traces {e_tr:.2e} p_last {e_pl:.2e} p_prev {e_pp:.2e}")
+    assert e_tr < TOL and e_pl < TOL and e_pp < TOL
+
+
+@pytest.mark.parametrize("name", ["small2d", "ragged2d", "c1"])
+def test_rtm_shot_parity(name):
+    s = _case(name)
+    g, vg, vo = _setup(s)
+    w = s.wavelet
+    d_obs = oracle.model_shot(vo, s.h, s.nb, s.dt, w.astype(np.float64), s.src[0], s.rec).astype(np.float32)
+    out = rtm.rtm_rtm_shot(g, vg, s.dt, _t(w), s.src[0], s.rec, _t(d_obs), eps_rel=EPS, want_numden=True)
+    ref = oracle.rtm_shot(vo, s.h, s.nb, s.dt, w.astype(np.float64), s.src[0], s.rec, d_obs.astype(np.float64),
+                          eps_rel=EPS)
+    errs = {k: rel_l2(_n(out[k]), ref[k]) for k in ("num", "den", "image")}
+    print(name, errs)
+    assert all(e < TOL for e in errs.values()), errs
+
+
+def test_image_conditioning_small_eps():
+    """With a tiny stabiliser the normalised image divides by illumination
+    1e6 below its peak, where FP32 wavefields carry relative errors of
+    ~1e-3: the image error then grows like ~1e-9 / eps while the Eq. (3)
+    integrals stay at ~1e-6.  This pins that the growth is the ratio's
+    conditioning, not a drift of num or den."""
+    s = synth.config_c1()
+    g, vg, vo = _setup(s)
+    w = s.wavelet
+    d_obs = oracle.model_shot(vo, s.h, s.nb, s.dt, w.astype(np.float64), s.src[0], s.rec).astype(np.float32)
+    out = rtm.rtm_rtm_shot(g, vg, s.dt, _t(w), s.src[0], s.rec, _t(d_obs), eps_rel=1e-6, want_numden=True)
+    ref = oracle.rtm_shot(vo, s.h, s.nb, s.dt, w.astype(np.float64), s.src[0], s.rec, d_obs.astype(np.float64),
+                          eps_rel=1e-6)
+    assert rel_l2(_n(out["num"]), ref["num"]) < TOL and rel_l2(_n(out["den"]), ref["den"]) < TOL
+    assert rel_l2(_n(out["image"]), ref["image"]) < 5e-3
+
+
+def test_time_reversal_and_probe():
+    """The reconstructed source wavefield equals the forward one (Sec. on
+    wavefield reconstruction), and the receiver wavefield matches the oracle."""
+    s = synth.config_c1()
+    g, vg, vo = _setup(s)
+    w = s.wavelet
+    d_obs = oracle.model_shot(vo, s.h, s.nb, s.dt, w.astype(np.float64), s.src[0], s.rec).astype(np.float32)
+    for k in (150, 400, 700):
+        out = rtm.rtm_rtm_shot(g, vg, s.dt, _t(w), s.src[0], s.rec, _t(d_obs), snap_k=k)
+        _, p_k, _ = rtm.rtm_model_shot(g, vg, s.dt, _t(w[:k]), s.src[0], s.rec, want_last=True)
+        ref = oracle.rtm_shot(vo, s.h, s.nb, s.dt, w.astype(np.float64), s.src[0], s.rec, d_obs.astype(np.float64),
+                              snap_k=k)
+        e_rev = rel_l2(_n(out["snap_p"]), _n(p_k))
+        e_p = rel_l2(_n(out["snap_p"]), ref["snap_p"])
+        e_mu = rel_l2(_n(out["snap_mu"]), ref["snap_mu"])
+        print(f"k={k}: reversal {e_rev:.2e} p vs oracle {e_p:.2e} mu vs oracle {e_mu:.2e}")
+        assert e_rev < TOL and e_p < TOL and e_mu < TOL
+
+
+def test_vjp_parity():
+    s = synth.config_small2d(nt=260)
+    g, vg, vo = _setup(s)
+    w = s.wavelet
+    rng = np.random.default_rng(3)
+    gt = rng.standard_normal((s.rec.shape[0], s.nt + 1)).astype(np.float32)
+    gv, gw = rtm.rtm_model_shot_vjp(g, vg, s.dt, _t(w), s.src[0], s.rec, _t(gt), want_wavelet_grad=True)
+    ref = oracle.rtm_shot(vo, s.h, s.nb, s.dt, w.astype(np.float64), s.src[0], s.rec, gt.astype(np.float64),
+                          want_grad=True, want_wadj=True)
+    e_g, e_w = rel_l2(_n(gv), ref["grad"]), rel_l2(_n(gw), ref["w_adj"])
+    print(f"grad {e_g:.2e} wavelet grad {e_w:.2e}")
+    assert e_g < TOL and e_w < TOL
+
+
+def test_dot_product_gpu():
+    s = synth.config_small2d(nt=200)
+    g, vg, _ = _setup(s)
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal(s.nt).astype(np.float32)
+    gt = rng.standard_normal((s.rec.shape[0], s.nt + 1)).astype(np.float32)
+    d = _n(rtm.rtm_model_shot(g, vg, s.dt, _t(w), s.src[0], s.rec))
+    _, gw = rtm.rtm_model_shot_vjp(g, vg, s.dt, _t(np.zeros_like(w)), s.src[0], s.rec, _t(gt), want_wavelet_grad=True)
+    lhs = float(np.sum(gt.astype(np.float64) * d))
+    rhs = float(np.dot(w.astype(np.float64), _n(gw)))
+    assert abs(lhs - rhs) <= TOL * abs(lhs), (lhs, rhs)
+
+
+def test_tuning_invariance():
+    """Results do not depend on the launch shape: bit-identical."""
+    s = synth.config_small2d(nx=150, nz=41, nb=10, nt=150)
+    g, vg, vo = _setup(s)
+    w = _t(s.wavelet)
+    d_obs = _t(oracle.model_shot(vo, s.h, s.nb, s.dt, s.wavelet.astype(np.float64), s.src[0], s.rec))
+    outs = []
+    for vec, zseg in ((1, 16), (2, 8), (4, 5), (1, 4), (4, 64)):
+        rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, vec, zseg)
+        rtm.rtm_set_tuning(rtm.RTM_OP_RTM, vec, zseg)
+        tr = _n(rtm.rtm_model_shot(g, vg, s.dt, w, s.src[0], s.rec))
+        im = _n(rtm.rtm_rtm_shot(g, vg, s.dt, w, s.src[0], s.rec, d_obs)["image"])
+        outs.append((tr, im))
+    for tr, im in outs[1:]:
+        assert np.array_equal(tr, outs[0][0]) and np.array_equal(im, outs[0][1])
+
+
+def test_edge_cases():
+    # No random boundary, tiny grid, one receiver on the last interior cell, nt = 1.
+    v = np.full((5, 7), 2000.0, np.float32)
+    for nb, nt in ((0, 1), (0, 30), (3, 25)):
+        g = rtm.Grid.for_model(v, 10.0, nb)
+        vg = rtm.rtm_rbc_pad(g, _t(v), 1, 0.0)
+        vo = oracle.rbc_pad(v, nb, 1, 0.0)
+        # Unit-scale random wavelet: a Ricker that has barely started would
+        # leave every value near zero and the comparison ill-conditioned.
+        w = np.random.default_rng(nt).standard_normal(nt).astype(np.float32)
+        src = np.array([[3.0, 0, 2.0]])
+        rec = np.array([[6.0, 0, 4.0]])
+        tr = _n(rtm.rtm_model_shot(g, vg, 1e-3, _t(w), src[0], rec))
+        tr_o = oracle.model_shot(vo, 10.0, nb, 1e-3, w.astype(np.float64), src[0], rec)
+        assert rel_l2(tr, tr_o) < TOL or np.abs(tr_o).max() == 0.0
+        if nt >= 2:
+            out = rtm.rtm_rtm_shot(g, vg, 1e-3, _t(w), src[0], rec, _t(tr_o), want_numden=True)
+            ref = oracle.rtm_shot(vo, 10.0, nb, 1e-3, w.astype(np.float64), src[0], rec, tr_o.astype(np.float32).astype(np.float64))
+            assert rel_l2(_n(out["num"]), ref["num"]) < TOL
+
+
+def test_error_codes_on_device():
+    s = synth.config_small2d()
+    g, vg, _ = _setup(s)
+    w = _t(s.wavelet)
+    with pytest.raises(rtm.RtmError) as e:
+        rtm.rtm_model_shot(g, vg, 0.05, w, s.src[0], s.rec)  # Courant far above the limit
+    assert e.value.status == -2
+    bad = vg.clone()
+    bad[5, 5] = float("nan")
+    with pytest.raises(rtm.RtmError) as e:
+        rtm.rtm_model_shot(g, bad, s.dt, w, s.src[0], s.rec)
+    assert e.value.status == -6
+    bad[5, 5] = -1.0
+    with pytest.raises(rtm.RtmError) as e:
+        rtm.rtm_model_shot(g, bad, s.dt, w, s.src[0], s.rec)
+    assert e.value.status == -6
+
+
+def test_folded_grid_full_size_reduced_nt():
+    """The 2301 x 751 folded-layer grid at full size (the benchmark's shot
+    shape), with a half-cell source, for 400 steps: traces and image."""
+    s = synth.config_c2(nshot=2, nt=400)
+    g, vg, vo = _setup(s)
+    src = s.src[1]  # x = 24.5: half-cell
+    w = s.wavelet
+    tr = _n(rtm.rtm_model_shot(g, vg, s.dt, _t(w), src, s.rec))
+    tr_o = oracle.model_shot(vo, s.h, s.nb, s.dt, w.astype(np.float64), src, s.rec)
+    assert rel_l2(tr, tr_o) < TOL
+    d_obs = tr_o.astype(np.float32)
+    out = rtm.rtm_rtm_shot(g, vg, s.dt, _t(w), src, s.rec, _t(d_obs), eps_rel=EPS)
+    ref = oracle.rtm_shot(vo, s.h, s.nb, s.dt, w.astype(np.float64), src, s.rec, d_obs.astype(np.float64),
+                          eps_rel=EPS)
+    e = rel_l2(_n(out["image"]), ref["image"])
+    print(f"folded grid: traces {rel_l2(tr, tr_o):.2e} image {e:.2e}")
+    assert e < TOL
