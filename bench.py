@@ -31,7 +31,10 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--shots-per-step", type=int, default=4)
+    ap.add_argument("--shots-per-step", type=int, default=16)
+    ap.add_argument("--plain-shots", type=int, default=2, help="shots timed through the plain per-shot calls")
+    ap.add_argument("--vec", type=int, default=1, help="floats per lane of the propagation kernels")
+    ap.add_argument("--zseg", type=int, default=16, help="rows per tile of the propagation kernels")
     ap.add_argument("--nt", type=int, default=5000)
     ap.add_argument("--cpu-sample-nt", type=int, default=240,
                     help="time steps of the oracle's timed sample (one shot, modeling + RTM)")
@@ -84,16 +87,38 @@ def main():
     interior = s.v_int.size
     B = args.shots_per_step
     nshot = s.src.shape[0]
+    nrec = s.rec.shape[0]
+    nt = args.nt
+    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, args.vec, args.zseg)
+    rtm.rtm_set_tuning(rtm.RTM_OP_RTM, args.vec, args.zseg)
+
+    # Buffers resident in HBM before timing: padded model, B traces, stack.
+    v_pad = rtm.rtm_rbc_pad(g, v_int, s.seed, 0.0)
+    traces = [torch.zeros((nrec, nt + 1), dtype=torch.float32, device=dev) for _ in range(B)]
+    stack = torch.zeros(g.interior_shape, dtype=torch.float32, device=dev)
+    ngroups = max(1, nshot // B)
+    groups = [[(k * B + j) % nshot for j in range(B)] for k in range(ngroups)]
+    plans = []
+    ws = None
+    for grp in groups:
+        mp = rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, v_pad, wav, s.src[i], s.rec, traces_out=traces[j])
+                                              for j, i in enumerate(grp)], s.dt, nt, ws=ws)
+        if ws is None:
+            need = mp.ws_bytes
+        rp = rtm.BatchPlan(rtm.RTM_OP_RTM, [rtm.BatchShot(g, v_pad, wav, s.src[i], s.rec, traces_in=traces[j],
+                                                          image=stack) for j, i in enumerate(grp)],
+                           s.dt, nt, eps_rel=1e-3, flags=rtm.RTM_F_ACCUMULATE, ws=ws)
+        if ws is None:
+            ws = torch.empty(max(need, rp.ws_bytes), dtype=torch.uint8, device=dev)
+            mp.bind_workspace(ws)
+            rp.bind_workspace(ws)
+        plans.append((mp, rp))
 
     def step(i):
-        v_pad = rtm.rtm_rbc_pad(g, v_int, s.seed, 0.0)
-        stack = torch.zeros(g.interior_shape, dtype=torch.float32, device=dev)
-        for j in range(B):
-            src = s.src[(i * B + j) % nshot]
-            d = rtm.rtm_model_shot(g, v_pad, s.dt, wav, src, s.rec)
-            out = rtm.rtm_rtm_shot(g, v_pad, s.dt, wav, src, s.rec, d, eps_rel=1e-3)
-            stack += out["image"]
-        return stack
+        rtm.rtm_rbc_pad(g, v_int, s.seed, 0.0, out=v_pad)
+        mp, rp = plans[i % ngroups]
+        mp.run()
+        rp.run()
 
     for i in range(args.warmup):
         step(i)
@@ -106,7 +131,7 @@ def main():
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
     for i in range(args.steps):
-        stack = step(args.warmup + i)
+        step(args.warmup + i)
     e1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -116,14 +141,39 @@ def main():
     assert torch.isfinite(stack).all()
 
     shots = args.steps * B
-    updates = cells * args.nt * 4 * shots
+    updates = cells * nt * 4 * shots
     ms_per_step = dev_ms / args.steps
     value = updates / (dev_ms * 1e-3) / 1e9
 
-    # Dominant kernel: the fused reverse step (two stencils, imaging sums).
+    # Plain per-shot calls on the same GPU (modeling + RTM), same shots as
+    # the first batch; their images must equal the batched ones bit for bit.
+    plain_shots = groups[0][:min(B, args.plain_shots)]
+    torch.cuda.synchronize()
+    p0 = time.perf_counter()
+    plain_imgs = []
+    for i in plain_shots:
+        d = rtm.rtm_model_shot(g, v_pad, s.dt, wav, s.src[i], s.rec)
+        plain_imgs.append(rtm.rtm_rtm_shot(g, v_pad, s.dt, wav, s.src[i], s.rec, d, eps_rel=1e-3)["image"])
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - p0
+    one = torch.zeros_like(stack)
+    check = rtm.BatchPlan(rtm.RTM_OP_RTM, [rtm.BatchShot(g, v_pad, wav, s.src[i], s.rec, traces_in=traces[j],
+                                                         image=one) for j, i in enumerate(plain_shots)],
+                          s.dt, nt, eps_rel=1e-3, flags=rtm.RTM_F_ACCUMULATE, ws=ws)
+    mp0, _ = plans[0]
+    mp0.run()
+    check.run()
+    ref = torch.zeros_like(stack)
+    for im in plain_imgs:
+        ref += im
+    torch.cuda.synchronize()
+    batch_vs_plain = float(torch.linalg.norm(one - ref) / torch.linalg.norm(ref))
+
+    # Dominant kernel: the fused reverse step (two stencils, imaging sums),
+    # one launch covering the B shots of a batch.
     rev_ms, rev_n = loops["reverse_image"]
     rev_us = rev_ms * 1e3 / max(rev_n, 1)
-    rev_bytes = 28 * cells + 16 * interior   # per launch (one shot, one step)
+    rev_bytes = B * (28 * cells + 16 * interior)
     achieved = rev_bytes / (rev_us * 1e-6) / 1e9
     fwd_ms, fwd_n = loops["model_forward"]
     rf_ms, rf_n = loops["rtm_forward"]
@@ -141,15 +191,17 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": f"folded-layer 2-D survey 2301x751 @ 4 m, nb 60, nt {args.nt}, 25 Hz, 2301 receivers: "
-                        f"modeling + RTM with random boundaries, {B} shots per step, images stacked",
+            "workload": f"folded-layer 2-D survey 2301x751 @ 4 m, nb 60, nt {nt}, 25 Hz, 2301 receivers, 240 shots: "
+                        f"per step {B} shots modeled then migrated (random boundaries, reconstruction), one launch "
+                        f"per time step for the {B} shots, images stacked",
             "padded_cells": cells,
             "shots_per_step": B,
             "propagations_per_shot": 4,
+            "launch_shape": {"vec": args.vec, "zseg": args.zseg},
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": "rev2d_kernel (fused reconstruction + receiver field + imaging)",
+            "kernel": f"rev2d_kernel<{args.vec},false> (fused reconstruction + receiver field + imaging, {B} shots)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -158,7 +210,10 @@ def main():
             "avg_launch_us": round(rev_us, 3),
             "algorithmic_bytes_per_launch": rev_bytes,
         },
-        "rtm_shots_per_s": round(shots / (dev_ms * 1e-3), 4),
+        "rtm_shots_per_s": {"batched": round(shots / (dev_ms * 1e-3), 4),
+                            "plain": round(len(plain_shots) / plain_s, 4),
+                            "image_rel_l2_batched_vs_plain": batch_vs_plain,
+                            "note": "one shot = modeling + RTM; plain = sequential single-shot calls"},
         "loop_us_per_launch": {
             "model_forward": round(fwd_ms * 1e3 / max(fwd_n, 1), 3),
             "rtm_forward": round(rf_ms * 1e3 / max(rf_n, 1), 3),

@@ -75,6 +75,13 @@ extern "C" {
 #define RTM_F_NO_REINJECT 0x2u /* rtm_rtm_shot: reconstruct with a zero right
                                   side, as Eq. (6) is written (the wavelet is
                                   then not removed while it is active) */
+#define RTM_F_ACCUMULATE 0x4u  /* batch RTM: add each shot's image into its
+                                  image buffer (shots may share one buffer:
+                                  the stacking of Algorithm 3) */
+#define RTM_F_GRAPH 0x8u       /* batch: capture the launch schedule in a
+                                  hipGraph on the first run and replay it on
+                                  later runs with the same workspace and
+                                  stream (stream must not be NULL) */
 
 /* Grid descriptor; read during the call only. */
 typedef struct rtm_grid {
@@ -207,6 +214,50 @@ int rtm_model_shot_vjp(const rtm_grid_t *grid, const float *v_pad, double dt, in
                        const float *rec, const float *grad_traces, float *grad_v_pad,
                        float *grad_wavelet, uint32_t flags, void *ws, size_t ws_bytes,
                        void *stream);
+
+/* ---------------------------------------------------------------------
+ * Batches: many shots, possibly of different grids (uneven apertures),
+ * propagated together.  Every time step is one kernel launch covering all
+ * tiles of all shots; shots given the same v_pad pointer and grid share one
+ * scaled-velocity array.  All shots use the same dt and nt.
+ * --------------------------------------------------------------------- */
+
+/* One shot of a batch.  Device buffers must stay valid while the plan is
+ * run; `rec` (host) is read by rtm_batch_plan only. */
+typedef struct rtm_shot_desc {
+    rtm_grid_t grid;          /* this shot's grid */
+    const float *v_pad;       /* device [NZ][NY][NX] padded velocity */
+    const float *wavelet;     /* device [nt] */
+    float src[3];             /* source position (interior grid units) */
+    int32_t nrec;             /* >= 1 */
+    const float *rec;         /* host [nrec][3] */
+    const float *traces_in;   /* device [nrec][nt + 1]: recorded data (RTM) or
+                                 dJ/dtraces (VJP); unused for modeling */
+    float *traces_out;        /* device [nrec][nt + 1]: modeling output */
+    float *image;             /* device [nz][ny][nx]: RTM image, written or
+                                 accumulated (RTM_F_ACCUMULATE) */
+    float *grad_v_pad;        /* device [NZ][NY][NX]: VJP output */
+} rtm_shot_desc_t;
+
+typedef struct rtm_plan rtm_plan_t;
+
+/* Validates the shots, builds their tiles and injection tables with the
+ * current launch shapes, and returns an opaque plan (host memory only)
+ * plus the workspace size its runs need.  op is RTM_OP_MODEL, RTM_OP_RTM
+ * or RTM_OP_VJP; flags: RTM_F_SKIP_CHECK, RTM_F_NO_REINJECT (RTM),
+ * RTM_F_ACCUMULATE (RTM), RTM_F_GRAPH.  eps_rel as in rtm_rtm_shot. */
+int rtm_batch_plan(int op, int32_t nshots, const rtm_shot_desc_t *shots, double dt, int32_t nt,
+                   float eps_rel, uint32_t flags, rtm_plan_t **plan, size_t *ws_bytes);
+
+/* Runs a plan on `stream` with a workspace of at least the planned size
+ * (256-byte aligned).  Uploads the tables, checks velocities (one stream
+ * synchronisation), then queues the propagation.  Results equal those of
+ * the single-shot entry points bit for bit.  Runs of one plan must not
+ * overlap in time. */
+int rtm_batch_run(rtm_plan_t *plan, void *ws, size_t ws_bytes, void *stream);
+
+/* Releases a plan (and its graph); NULL is allowed. */
+int rtm_batch_free(rtm_plan_t *plan);
 
 #ifdef __cplusplus
 }

@@ -15,13 +15,14 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (RTM_F_NO_REINJECT, RTM_F_SKIP_CHECK, RTM_OP_MODEL, RTM_OP_RBC_PAD, RTM_OP_RTM, RTM_OP_VJP,
-                   RtmError)
+from ._lib import (RTM_F_ACCUMULATE, RTM_F_GRAPH, RTM_F_NO_REINJECT, RTM_F_SKIP_CHECK, RTM_OP_MODEL,
+                   RTM_OP_RBC_PAD, RTM_OP_RTM, RTM_OP_VJP, RtmError)
 
 __all__ = [
     "Grid", "RtmError", "rtm_workspace_bytes", "rtm_set_tuning", "rtm_timing_enable", "rtm_timing_read", "rtm_rbc_pad", "rtm_pad_adjoint",
     "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "RTM_F_SKIP_CHECK", "RTM_F_NO_REINJECT",
-    "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD",
+    "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD", "RTM_F_ACCUMULATE", "RTM_F_GRAPH",
+    "BatchShot", "BatchPlan",
 ]
 
 
@@ -114,10 +115,15 @@ def rtm_timing_read() -> dict:
     return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(LOOP_KINDS)}
 
 
-def rtm_rbc_pad(grid: Grid, v_int: torch.Tensor, seed: int, v_cap: float = 0.0) -> torch.Tensor:
+def rtm_rbc_pad(grid: Grid, v_int: torch.Tensor, seed: int, v_cap: float = 0.0,
+                out: torch.Tensor = None) -> torch.Tensor:
     """Padded FP32 velocity with the seeded random boundary (see rtm.h)."""
     _dev(v_int, "v_int", grid.interior_shape)
-    v_pad = torch.empty(grid.padded_shape, dtype=torch.float32, device=v_int.device)
+    if out is None:
+        v_pad = torch.empty(grid.padded_shape, dtype=torch.float32, device=v_int.device)
+    else:
+        _dev(out, "out", grid.padded_shape)
+        v_pad = out
     ws = _workspace(grid, RTM_OP_RBC_PAD, 0, 0, v_int.device)
     g = grid.c()
     _lib.check(_lib.load().rtm_rbc_pad(ctypes.byref(g), v_int.data_ptr(), int(seed), float(v_cap), v_pad.data_ptr(),
@@ -213,3 +219,90 @@ def rtm_model_shot_vjp(grid: Grid, v_pad: torch.Tensor, dt: float, wavelet: torc
         grad_traces.data_ptr(), gv.data_ptr(), gw.data_ptr() if want_wavelet_grad else None, int(flags),
         ws.data_ptr(), ws.numel(), _stream(dev)))
     return (gv, gw) if want_wavelet_grad else gv
+
+
+@dataclass
+class BatchShot:
+    """One shot of a batch (see rtm_shot_desc_t): its grid, padded model,
+    wavelet, positions and the device buffers the operation reads or writes."""
+    grid: Grid
+    v_pad: torch.Tensor
+    wavelet: torch.Tensor
+    src: object
+    rec: object
+    traces_in: torch.Tensor = None
+    traces_out: torch.Tensor = None
+    image: torch.Tensor = None
+    grad_v_pad: torch.Tensor = None
+
+
+class BatchPlan:
+    """rtm_batch_plan / rtm_batch_run / rtm_batch_free over torch tensors.
+    The plan keeps references to every tensor it was given."""
+
+    def __init__(self, op: int, shots, dt: float, nt: int, eps_rel: float = 1e-3, flags: int = 0,
+                 ws: torch.Tensor = None):
+        self._shots = list(shots)
+        n = len(self._shots)
+        descs = (_lib.RtmShotDesc * n)()
+        self._recs = []
+        dev = None
+        for i, s in enumerate(self._shots):
+            _dev(s.v_pad, "v_pad", s.grid.padded_shape)
+            _dev(s.wavelet, "wavelet", (nt,))
+            rec = _pos(s.rec, "rec")
+            self._recs.append(rec)
+            nrec = rec.shape[0]
+            d = descs[i]
+            d.grid = s.grid.c()
+            d.v_pad = s.v_pad.data_ptr()
+            d.wavelet = s.wavelet.data_ptr()
+            src = _pos(s.src, "src")[0]
+            for k in range(3):
+                d.src[k] = float(src[k])
+            d.nrec = nrec
+            d.rec = rec.ctypes.data
+            if s.traces_in is not None:
+                d.traces_in = _dev(s.traces_in, "traces_in", (nrec, nt + 1))
+            if s.traces_out is not None:
+                d.traces_out = _dev(s.traces_out, "traces_out", (nrec, nt + 1))
+            if s.image is not None:
+                d.image = _dev(s.image, "image", s.grid.interior_shape)
+            if s.grad_v_pad is not None:
+                d.grad_v_pad = _dev(s.grad_v_pad, "grad_v_pad", s.grid.padded_shape)
+            dev = s.v_pad.device
+        self.device = dev
+        self.flags = flags
+        shared_ws = ws
+        plan = ctypes.c_void_p()
+        ws = ctypes.c_size_t(0)
+        _lib.check(_lib.load().rtm_batch_plan(op, n, descs, float(dt), int(nt), float(eps_rel), int(flags),
+                                              ctypes.byref(plan), ctypes.byref(ws)))
+        self._plan = plan
+        self.ws_bytes = int(ws.value)
+        self.ws = None
+        self.bind_workspace(shared_ws)
+
+    def bind_workspace(self, ws: torch.Tensor = None) -> None:
+        """Use `ws` (uint8, at least ws_bytes) as workspace, else allocate one."""
+        if ws is not None:
+            if ws.dtype != torch.uint8 or ws.numel() < self.ws_bytes or not ws.is_cuda:
+                raise ValueError(f"workspace must be a CUDA uint8 tensor of >= {self.ws_bytes} bytes")
+            self.ws = ws
+        else:
+            self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
+
+    def run(self, stream: "torch.cuda.Stream" = None) -> None:
+        st = stream.cuda_stream if stream is not None else _stream(self.device)
+        _lib.check(_lib.load().rtm_batch_run(self._plan, self.ws.data_ptr(), self.ws.numel(), st))
+
+    def free(self) -> None:
+        if getattr(self, "_plan", None) is not None and self._plan.value:
+            _lib.load().rtm_batch_free(self._plan)
+            self._plan = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

@@ -26,13 +26,24 @@ RTM_F_NO_REINJECT = 0x2
 EXPORTS = (
     "rtm_abi_version", "rtm_last_error", "rtm_set_tuning", "rtm_timing_enable", "rtm_timing_read",
     "rtm_workspace_bytes", "rtm_rbc_pad",
-    "rtm_pad_adjoint", "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp",
+    "rtm_pad_adjoint", "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "rtm_batch_plan", "rtm_batch_run",
+    "rtm_batch_free",
 )
+
+RTM_F_ACCUMULATE = 0x4
+RTM_F_GRAPH = 0x8
 
 
 class RtmGrid(ctypes.Structure):
     _fields_ = [("ndim", ctypes.c_int32), ("nb", ctypes.c_int32), ("nx", ctypes.c_int64),
                 ("ny", ctypes.c_int64), ("nz", ctypes.c_int64), ("h", ctypes.c_double)]
+
+
+class RtmShotDesc(ctypes.Structure):
+    _fields_ = [("grid", RtmGrid), ("v_pad", ctypes.c_void_p), ("wavelet", ctypes.c_void_p),
+                ("src", ctypes.c_float * 3), ("nrec", ctypes.c_int32), ("rec", ctypes.c_void_p),
+                ("traces_in", ctypes.c_void_p), ("traces_out", ctypes.c_void_p), ("image", ctypes.c_void_p),
+                ("grad_v_pad", ctypes.c_void_p)]
 
 
 class RtmProbe(ctypes.Structure):
@@ -67,6 +78,10 @@ def load():
         "rtm_rtm_shot": ([G, P, D, I32, P, P, I32, P, P, F, P, P, P, ctypes.POINTER(RtmProbe), U32, P, SZ, P],
                          ctypes.c_int),
         "rtm_model_shot_vjp": ([G, P, D, I32, P, P, I32, P, P, P, P, U32, P, SZ, P], ctypes.c_int),
+        "rtm_batch_plan": ([ctypes.c_int, I32, ctypes.POINTER(RtmShotDesc), D, I32, F, U32,
+                            ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SZ)], ctypes.c_int),
+        "rtm_batch_run": ([P, P, SZ, P], ctypes.c_int),
+        "rtm_batch_free": ([P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

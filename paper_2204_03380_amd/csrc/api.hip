@@ -2,6 +2,7 @@
 // workspace carving and the launch sequences behind the C ABI of
 // include/rtm.h.  Every device buffer comes from the caller.
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
@@ -9,6 +10,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <new>
 #include <string>
 #include <tuple>
 #include <vector>
@@ -35,11 +37,11 @@ hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
 hipError_t launch_build_dp(const Layout &L, const float *v_pad, float dt_over_h, float *Dp, hipStream_t st);
 hipError_t launch_unpack(const Layout &L, const float *f, float *out, hipStream_t st);
 hipError_t launch_transpose(const float *in, float *out, int64_t R, int64_t C, hipStream_t st);
-hipError_t launch_inj_set(const ShotDev *shots, int shot, const InjEnt *ents, int ebeg, int eend,
-                          const Contrib *cont, int step, hipStream_t st);
+hipError_t launch_inj_set(const ShotDev *shots, const InjEnt *ents, int ebeg, int eend, const Contrib *cont, int step,
+                          hipStream_t st);
 hipError_t launch_sample(const ShotDev *shots, const SampleTask *stasks, int ntask, int n, hipStream_t st);
 hipError_t launch_image(const ShotDev *shots, int shot, int64_t ninterior, unsigned *dmax_bits, float eps_rel,
-                        float *image, float *num, float *den, hipStream_t st);
+                        float *image, int accumulate, float *num, float *den, hipStream_t st);
 hipError_t launch_grad(const ShotDev *shots, int shot, int64_t npad, const float *v_pad, float dt, float *grad,
                        hipStream_t st);
 hipError_t launch_wadj(const float *parts, int nt, float scale, float *out, hipStream_t st);
@@ -212,149 +214,179 @@ bool make_point(const GridInfo &g, const float *pos, PointOp *P)
 }
 
 // ---------------------------------------------------------------------------
-// Workspace carving
+// Jobs: one or many shots propagated together.  Every time step is one
+// kernel launch covering all tiles of all shots; shots with the same padded
+// model and grid share their D' array.
 // ---------------------------------------------------------------------------
 
-struct Carve {
-    char *base;
-    size_t off = 0;
-    explicit Carve(void *b) : base((char *)b) {}
-    template <class T>
-    T *take(size_t count)
-    {
-        off = (off + 255) & ~(size_t)255;
-        T *p = base ? (T *)(base + off) : nullptr;
-        off += count * sizeof(T);
-        return p;
-    }
+struct ShotIn {
+    GridInfo g;
+    const float *v_pad = nullptr;
+    const float *wavelet = nullptr;
+    float src[3] = {0, 0, 0};
+    int nrec = 0;
+    std::vector<float> rec;             // [nrec][3]
+    const float *traces_in = nullptr;   // RTM data / VJP upstream gradient, [nrec][nt + 1]
+    float *traces_out = nullptr;        // modeling output, [nrec][nt + 1]
+    float *image = nullptr, *num = nullptr, *den = nullptr;  // RTM outputs (interior)
+    float *grad_v_pad = nullptr, *grad_wavelet = nullptr;    // VJP outputs
+    float *p_last = nullptr, *p_prev = nullptr;              // modeling: final panels
 };
 
-// Device buffers of one single-shot call.
-struct ShotBufs {
-    float *Dp = nullptr;
-    float *fld[4] = {nullptr, nullptr, nullptr, nullptr};
-    float *acc0 = nullptr, *acc1 = nullptr;
-    float *traces = nullptr;  // [nt + 1][nrec]
-    float *wadj = nullptr;    // [nt][kMaxNodes]
-    ShotDev *shot = nullptr;
-    Tile2D *tiles = nullptr;
-    InjEnt *ents = nullptr;
-    Contrib *cont = nullptr;
-    SampleTask *stasks = nullptr;
-    int *rnode = nullptr;
-    float *rw = nullptr;
-    unsigned *scal = nullptr;  // 4 words of scratch
+// Tiles and injection entries of one launch shape.  ents holds all source
+// entries of all shots, then all receiver entries (when present).
+struct Tiling {
+    Tune tune{1, 16};
+    std::vector<Tile2D> tiles;
+    std::vector<InjEnt> ents;
+    std::vector<Contrib> cont;
+    int nsrc_ent = 0, nrec_ent = 0, nslots = 0;
+};
+
+struct Counts {
+    int64_t tiles_f = 0, ents_f = 0, cont_f = 0;  // forward tiling
+    int64_t tiles_r = 0, ents_r = 0, cont_r = 0;  // reverse tiling
+    int64_t stasks = 0, rnode = 0;
+};
+
+// Byte offsets of every device buffer inside the workspace.
+struct WsLayout {
+    size_t scal = 0, shots = 0, tiles_f = 0, ents_f = 0, cont_f = 0, tiles_r = 0, ents_r = 0, cont_r = 0;
+    size_t stasks = 0, rnode = 0, rw = 0;
+    std::vector<size_t> dp;                  // per D' slot
+    std::vector<std::array<size_t, 4>> fld;  // per shot
+    std::vector<size_t> acc0, acc1, trint, wadj;
     size_t bytes = 0;
 };
+
+struct Job {
+    int op = RTM_OP_MODEL;
+    int nt = 0;
+    double dt = 0.0;
+    float eps = 1e-3f;
+    uint32_t flags = 0;
+    std::vector<ShotIn> shots;
+    Tiling fw, rv;  // rv unused for modeling
+    std::vector<SampleTask> stasks;
+    std::vector<int> rnode;
+    std::vector<float> rw;
+    std::vector<int64_t> rbase;      // per shot: offset of its receivers in rnode / rw (in receivers)
+    std::vector<int> dslot;          // per shot: D' slot
+    std::vector<int> slot_shot;      // per slot: first shot using it
+    WsLayout ws;
+    // hipGraph of the launch schedule (plans with RTM_F_GRAPH)
+    hipGraphExec_t gexec = nullptr;
+    void *g_ws = nullptr;
+    hipStream_t g_st = nullptr;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int nfields(int op) { return op == RTM_OP_MODEL ? 2 : 4; }
+
+WsLayout make_ws_layout(const Job &J, const Counts &c)
+{
+    WsLayout w;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        off = align256(off);
+        size_t o = off;
+        off += bytes;
+        return o;
+    };
+    const int nsh = (int)J.shots.size();
+    const int nslot = (int)J.slot_shot.size();
+    w.scal = take(sizeof(unsigned) * (64 + 2 * (size_t)nslot + (size_t)nsh));
+    w.shots = take(sizeof(ShotDev) * nsh);
+    w.tiles_f = take(sizeof(Tile2D) * c.tiles_f);
+    w.ents_f = take(sizeof(InjEnt) * c.ents_f);
+    w.cont_f = take(sizeof(Contrib) * c.cont_f);
+    w.tiles_r = take(sizeof(Tile2D) * c.tiles_r);
+    w.ents_r = take(sizeof(InjEnt) * c.ents_r);
+    w.cont_r = take(sizeof(Contrib) * c.cont_r);
+    w.stasks = take(sizeof(SampleTask) * c.stasks);
+    w.rnode = take(sizeof(int) * c.rnode * kMaxNodes);
+    w.rw = take(sizeof(float) * c.rnode * kMaxNodes);
+    for (int d = 0; d < nslot; ++d) w.dp.push_back(take(sizeof(float) * J.shots[J.slot_shot[d]].g.L.total));
+    const int nf = nfields(J.op);
+    for (int i = 0; i < nsh; ++i) {
+        const ShotIn &S = J.shots[i];
+        const int64_t F = S.g.L.total;
+        std::array<size_t, 4> f{0, 0, 0, 0};
+        for (int k = 0; k < nf; ++k) f[k] = take(sizeof(float) * F);
+        w.fld.push_back(f);
+        w.acc0.push_back(J.op == RTM_OP_MODEL ? 0 : take(sizeof(float) * F));
+        w.acc1.push_back(J.op == RTM_OP_RTM ? take(sizeof(float) * F) : 0);
+        w.trint.push_back(take(sizeof(float) * (size_t)(J.nt + 1) * S.nrec));
+        w.wadj.push_back(J.op == RTM_OP_VJP ? take(sizeof(float) * (size_t)J.nt * kMaxNodes) : 0);
+    }
+    w.bytes = align256(off);
+    return w;
+}
 
 int max_tiles(const GridInfo &g)
 {
     return (int)(((int64_t)(g.NX + 63) / 64) * ((g.NZ + kMinZseg - 1) / kMinZseg));
 }
 
-ShotBufs carve(void *ws, const GridInfo &g, int op, int nrec, int nt)
-{
-    Carve c(ws);
-    ShotBufs b;
-    const int64_t F = g.L.total;
-    b.scal = c.take<unsigned>(64);
-    if (op != RTM_OP_RBC_PAD) {
-        b.Dp = c.take<float>(F);
-        int nf = (op == RTM_OP_MODEL) ? 2 : 4;
-        for (int i = 0; i < nf; ++i) b.fld[i] = c.take<float>(F);
-        if (op == RTM_OP_RTM) {
-            b.acc0 = c.take<float>(F);
-            b.acc1 = c.take<float>(F);
-        } else if (op == RTM_OP_VJP) {
-            b.acc0 = c.take<float>(F);
-            b.wadj = c.take<float>((size_t)nt * kMaxNodes);
-        }
-        b.traces = c.take<float>((size_t)(nt + 1) * (size_t)nrec);
-        b.shot = c.take<ShotDev>(1);
-        int mt = max_tiles(g);
-        b.tiles = c.take<Tile2D>(mt);
-        int ment = kMaxNodes + kMaxNodes * nrec;
-        b.ents = c.take<InjEnt>(ment);
-        b.cont = c.take<Contrib>(ment);
-        b.stasks = c.take<SampleTask>((nrec + 63) / 64 + 1);
-        b.rnode = c.take<int>((size_t)nrec * kMaxNodes);
-        b.rw = c.take<float>((size_t)nrec * kMaxNodes);
-    }
-    b.bytes = c.off;
-    return b;
-}
-
-// ---------------------------------------------------------------------------
-// Acquisition tables (host side) for one shot on the 2-D tiling
-// ---------------------------------------------------------------------------
-
-struct HostTables {
-    std::vector<Tile2D> tiles;
-    std::vector<InjEnt> ents;
-    std::vector<Contrib> cont;
-    std::vector<SampleTask> stasks;
-    std::vector<int> rnode;
-    std::vector<float> rw;
-    int nsrc_ent = 0, nrec_ent = 0;  // ents = [source entries][receiver entries]
-    int nslots = 0;
-};
-
 struct RawEnt {
     int tile, z, y, x;
     std::vector<Contrib> c;
-    int slot;
+    int slot, shot;
 };
 
-int build_tables_2d(const GridInfo &g, Tune tune, const float *src, int nrec, const float *rec, HostTables *T)
+// Builds the tiles and injection entries of every shot for one launch shape.
+int build_tiling(Job &J, Tiling &T, bool with_receivers)
 {
-    const int strip = 64 * tune.vec;
-    const int ns = (g.NX + strip - 1) / strip;
-    const int nzs = (g.NZ + tune.zseg - 1) / tune.zseg;
-    T->tiles.clear();
-    for (int s = 0; s < ns; ++s)
-        for (int zs = 0; zs < nzs; ++zs) {
-            Tile2D t{};
-            t.shot = 0;
-            t.x0 = s * strip;
-            t.z0 = zs * tune.zseg;
-            t.z1 = std::min(t.z0 + tune.zseg, g.NZ);
-            T->tiles.push_back(t);
-        }
-    auto tile_of = [&](int z, int x) { return (x / strip) * nzs + z / tune.zseg; };
-
-    PointOp sp;
-    if (!make_point(g, src, &sp))
-        return fail(RTM_ERANGE, "source (%g, %g, %g) outside the interior", src[0], src[1], src[2]);
-    const double hd = std::pow(g.h, g.ndim);
-    const double h2 = g.h * g.h;
+    T.tiles.clear();
+    T.ents.clear();
+    T.cont.clear();
     std::vector<RawEnt> se, re;
-    for (int q = 0; q < sp.n; ++q) {
-        RawEnt e{tile_of(sp.z[q], sp.x[q]), sp.z[q], sp.y[q], sp.x[q], {}, q};
-        // s = W h^2 / h^d: the source term D (B w) expressed with D' = D / h^2.
-        e.c.push_back(Contrib{0, (float)(sp.w[q] * h2 / hd)});
-        se.push_back(e);
-    }
-    std::map<std::tuple<int, int, int>, size_t> node_of;
-    T->rnode.assign((size_t)nrec * kMaxNodes, 0);
-    T->rw.assign((size_t)nrec * kMaxNodes, 0.f);
-    for (int r = 0; r < nrec; ++r) {
-        PointOp rp;
-        if (!make_point(g, rec + 3 * (size_t)r, &rp))
-            return fail(RTM_ERANGE, "receiver %d (%g, %g, %g) outside the interior", r, rec[3 * r], rec[3 * r + 1],
-                        rec[3 * r + 2]);
-        for (int q = 0; q < rp.n; ++q) {
-            T->rnode[(size_t)r * kMaxNodes + q] =
-                (int)((int64_t)rp.z[q] * g.L.plane + (int64_t)rp.y[q] * g.L.pitch + rp.x[q]);
-            T->rw[(size_t)r * kMaxNodes + q] = (float)rp.w[q];
-            auto key = std::make_tuple(rp.z[q], rp.y[q], rp.x[q]);
-            auto it = node_of.find(key);
-            if (it == node_of.end()) {
-                node_of[key] = re.size();
-                re.push_back(RawEnt{tile_of(rp.z[q], rp.x[q]), rp.z[q], rp.y[q], rp.x[q], {}, 0});
-                it = node_of.find(key);
+    const int strip = 64 * T.tune.vec;
+    for (int s = 0; s < (int)J.shots.size(); ++s) {
+        const ShotIn &S = J.shots[s];
+        const GridInfo &g = S.g;
+        const int ns = (g.NX + strip - 1) / strip;
+        const int nzs = (g.NZ + T.tune.zseg - 1) / T.tune.zseg;
+        const int tbase = (int)T.tiles.size();
+        for (int xs = 0; xs < ns; ++xs)
+            for (int zs = 0; zs < nzs; ++zs) {
+                Tile2D t{};
+                t.shot = s;
+                t.x0 = xs * strip;
+                t.z0 = zs * T.tune.zseg;
+                t.z1 = std::min(t.z0 + T.tune.zseg, g.NZ);
+                T.tiles.push_back(t);
             }
-            // Receiver injection D R^T g = D' h^2 W g.
-            re[it->second].c.push_back(Contrib{r, (float)(rp.w[q] * h2)});
+        auto tile_of = [&](int z, int x) { return tbase + (x / strip) * nzs + z / T.tune.zseg; };
+        PointOp sp;
+        if (!make_point(g, S.src, &sp))
+            return fail(RTM_ERANGE, "shot %d: source (%g, %g, %g) outside the interior", s, S.src[0], S.src[1],
+                        S.src[2]);
+        const double hd = std::pow(g.h, g.ndim);
+        const double h2 = g.h * g.h;
+        for (int q = 0; q < sp.n; ++q) {
+            RawEnt e{tile_of(sp.z[q], sp.x[q]), sp.z[q], sp.y[q], sp.x[q], {}, q, s};
+            // D (B w) = D' (h^2 W / h^d) w with D' = (v dt / h)^2.
+            e.c.push_back(Contrib{0, (float)(sp.w[q] * h2 / hd)});
+            se.push_back(e);
+        }
+        if (!with_receivers) continue;
+        std::map<std::tuple<int, int, int>, size_t> node_of;
+        for (int r = 0; r < S.nrec; ++r) {
+            PointOp rp;
+            if (!make_point(g, &S.rec[3 * (size_t)r], &rp))
+                return fail(RTM_ERANGE, "shot %d: receiver %d outside the interior", s, r);
+            for (int q = 0; q < rp.n; ++q) {
+                auto key = std::make_tuple(rp.z[q], rp.y[q], rp.x[q]);
+                auto it = node_of.find(key);
+                if (it == node_of.end()) {
+                    it = node_of.emplace(key, re.size()).first;
+                    re.push_back(RawEnt{tile_of(rp.z[q], rp.x[q]), rp.z[q], rp.y[q], rp.x[q], {}, 0, s});
+                }
+                // D R^T g = D' h^2 W g.
+                re[it->second].c.push_back(Contrib{r, (float)(rp.w[q] * h2)});
+            }
         }
     }
     auto order = [](const RawEnt &a, const RawEnt &b) {
@@ -362,17 +394,15 @@ int build_tables_2d(const GridInfo &g, Tune tune, const float *src, int nrec, co
     };
     std::sort(se.begin(), se.end(), order);
     std::sort(re.begin(), re.end(), order);
-    T->ents.clear();
-    T->cont.clear();
-    for (auto &t : T->tiles) t.sbeg = t.send = t.rbeg = t.rend = 0;
+    for (auto &t : T.tiles) t.sbeg = t.send = t.rbeg = t.rend = 0;
     auto emit = [&](std::vector<RawEnt> &v, bool is_src) {
         for (auto &e : v) {
-            InjEnt E{e.z, e.y, e.x, (int)T->cont.size(), 0, e.slot};
-            for (auto &c : e.c) T->cont.push_back(c);
-            E.cend = (int)T->cont.size();
-            int idx = (int)T->ents.size();
-            T->ents.push_back(E);
-            Tile2D &t = T->tiles[e.tile];
+            InjEnt E{e.z, e.y, e.x, (int)T.cont.size(), 0, e.slot, e.shot, 0};
+            for (auto &c : e.c) T.cont.push_back(c);
+            E.cend = (int)T.cont.size();
+            const int idx = (int)T.ents.size();
+            T.ents.push_back(E);
+            Tile2D &t = T.tiles[e.tile];
             if (is_src) {
                 if (t.send == t.sbeg) t.sbeg = idx;
                 t.send = idx + 1;
@@ -383,33 +413,301 @@ int build_tables_2d(const GridInfo &g, Tune tune, const float *src, int nrec, co
         }
     };
     emit(se, true);
-    T->nsrc_ent = (int)se.size();
+    T.nsrc_ent = (int)se.size();
     emit(re, false);
-    T->nrec_ent = (int)re.size();
-    T->stasks.clear();
-    for (int r0 = 0; r0 < nrec; r0 += 64) T->stasks.push_back(SampleTask{0, r0});
-    const int nt_ = (int)T->tiles.size();
-    T->nslots = (nt_ + kNumXcd - 1) / kNumXcd * kNumXcd;
+    T.nrec_ent = (int)re.size();
+    T.nslots = ((int)T.tiles.size() + kNumXcd - 1) / kNumXcd * kNumXcd;
     return RTM_OK;
 }
 
-// ---------------------------------------------------------------------------
-// Common call preparation
-// ---------------------------------------------------------------------------
+// Receiver sampling tables, D' sharing and tilings of a job.
+int build_job_tables(Job &J)
+{
+    J.stasks.clear();
+    J.rnode.clear();
+    J.rw.clear();
+    J.rbase.clear();
+    J.dslot.clear();
+    J.slot_shot.clear();
+    int64_t base = 0;
+    for (int s = 0; s < (int)J.shots.size(); ++s) {
+        const ShotIn &S = J.shots[s];
+        J.rbase.push_back(base);
+        for (int r = 0; r < S.nrec; ++r) {
+            PointOp rp;
+            if (!make_point(S.g, &S.rec[3 * (size_t)r], &rp))
+                return fail(RTM_ERANGE, "shot %d: receiver %d (%g, %g, %g) outside the interior", s, r,
+                            S.rec[3 * r], S.rec[3 * r + 1], S.rec[3 * r + 2]);
+            for (int q = 0; q < kMaxNodes; ++q) {
+                if (q < rp.n) {
+                    J.rnode.push_back((int)((int64_t)rp.z[q] * S.g.L.plane + (int64_t)rp.y[q] * S.g.L.pitch + rp.x[q]));
+                    J.rw.push_back((float)rp.w[q]);
+                } else {
+                    J.rnode.push_back(0);
+                    J.rw.push_back(0.f);
+                }
+            }
+        }
+        base += S.nrec;
+        for (int r0 = 0; r0 < S.nrec; r0 += 64) J.stasks.push_back(SampleTask{s, r0});
+        int slot = -1;
+        for (int d = 0; d < (int)J.slot_shot.size(); ++d) {
+            const ShotIn &o = J.shots[J.slot_shot[d]];
+            if (o.v_pad == S.v_pad && o.g.NX == S.g.NX && o.g.NY == S.g.NY && o.g.NZ == S.g.NZ && o.g.h == S.g.h) {
+                slot = d;
+                break;
+            }
+        }
+        if (slot < 0) {
+            slot = (int)J.slot_shot.size();
+            J.slot_shot.push_back(s);
+        }
+        J.dslot.push_back(slot);
+    }
+    J.fw.tune = get_tune(0);
+    int rc = build_tiling(J, J.fw, false);
+    if (rc) return rc;
+    if (J.op != RTM_OP_MODEL) {
+        J.rv.tune = get_tune(1);
+        rc = build_tiling(J, J.rv, true);
+        if (rc) return rc;
+    }
+    return RTM_OK;
+}
 
-struct Prepared {
-    GridInfo g;
-    ShotBufs b;
-    HostTables T;
-    Tune tune;
-    hipStream_t st;
+Counts exact_counts(const Job &J)
+{
+    Counts c;
+    c.tiles_f = J.fw.tiles.size();
+    c.ents_f = J.fw.ents.size();
+    c.cont_f = J.fw.cont.size();
+    c.tiles_r = J.rv.tiles.size();
+    c.ents_r = J.rv.ents.size();
+    c.cont_r = J.rv.cont.size();
+    c.stasks = J.stasks.size();
+    c.rnode = J.rnode.size() / kMaxNodes;
+    return c;
+}
+
+// Upper bounds for one shot, independent of positions and launch shape.
+Counts bound_counts(const GridInfo &g, int op, int nrec)
+{
+    Counts c;
+    c.tiles_f = max_tiles(g);
+    c.ents_f = c.cont_f = kMaxNodes;
+    if (op != RTM_OP_MODEL) {
+        c.tiles_r = max_tiles(g);
+        c.ents_r = c.cont_r = kMaxNodes + (int64_t)kMaxNodes * nrec;
+    }
+    c.stasks = (nrec + 63) / 64;
+    c.rnode = nrec;
+    return c;
+}
+
+// Device addresses of the job's buffers inside `ws`.
+struct Dev {
+    char *base;
+    template <class T>
+    T *at(size_t off) const { return (T *)(base + off); }
 };
+
+void fill_shot_devs(const Job &J, const Dev &D, std::vector<ShotDev> &out)
+{
+    out.resize(J.shots.size());
+    for (size_t i = 0; i < J.shots.size(); ++i) {
+        const ShotIn &S = J.shots[i];
+        ShotDev &d = out[i];
+        std::memset(&d, 0, sizeof d);
+        for (int k = 0; k < nfields(J.op); ++k) d.fld[k] = D.at<float>(J.ws.fld[i][k]);
+        d.acc0 = J.op == RTM_OP_MODEL ? nullptr : D.at<float>(J.ws.acc0[i]);
+        d.acc1 = J.op == RTM_OP_RTM ? D.at<float>(J.ws.acc1[i]) : nullptr;
+        d.Dp = D.at<float>(J.ws.dp[J.dslot[i]]);
+        d.wav = S.wavelet;
+        float *trint = D.at<float>(J.ws.trint[i]);
+        d.sig = J.op == RTM_OP_MODEL ? nullptr : trint;
+        d.rec_out = J.op == RTM_OP_MODEL ? trint : nullptr;
+        d.rnode = D.at<int>(J.ws.rnode) + J.rbase[i] * kMaxNodes;
+        d.rw = D.at<float>(J.ws.rw) + J.rbase[i] * kMaxNodes;
+        d.nrec = S.nrec;
+        d.ix0 = S.g.nb;
+        d.ix1 = S.g.nb + (int)S.g.nx;
+        d.iy0 = S.g.ndim == 3 ? S.g.nb : 0;
+        d.iy1 = S.g.ndim == 3 ? S.g.nb + (int)S.g.ny : 1;
+        d.iz0 = S.g.nb;
+        d.iz1 = S.g.nb + (int)S.g.nz;
+        d.L = S.g.L;
+    }
+}
+
+template <class T>
+int upload(const Dev &D, size_t off, const std::vector<T> &v, hipStream_t st)
+{
+    if (v.empty()) return RTM_OK;
+    RTM_HIP(hipMemcpyAsync(D.at<char>(off), v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+    return RTM_OK;
+}
+
+// Copies the tables and shot descriptors into the workspace and, unless
+// skipped, checks every D' slot's velocity range; synchronises once.
+int job_upload_and_check(const Job &J, const Dev &D, std::vector<ShotDev> &shot_devs, hipStream_t st)
+{
+    int rc;
+    fill_shot_devs(J, D, shot_devs);
+    if ((rc = upload(D, J.ws.shots, shot_devs, st))) return rc;
+    if ((rc = upload(D, J.ws.tiles_f, J.fw.tiles, st))) return rc;
+    if ((rc = upload(D, J.ws.ents_f, J.fw.ents, st))) return rc;
+    if ((rc = upload(D, J.ws.cont_f, J.fw.cont, st))) return rc;
+    if ((rc = upload(D, J.ws.tiles_r, J.rv.tiles, st))) return rc;
+    if ((rc = upload(D, J.ws.ents_r, J.rv.ents, st))) return rc;
+    if ((rc = upload(D, J.ws.cont_r, J.rv.cont, st))) return rc;
+    if ((rc = upload(D, J.ws.stasks, J.stasks, st))) return rc;
+    if ((rc = upload(D, J.ws.rnode, J.rnode, st))) return rc;
+    if ((rc = upload(D, J.ws.rw, J.rw, st))) return rc;
+    const int nslot = (int)J.slot_shot.size();
+    std::vector<unsigned> vr(2 * (size_t)nslot, 0u);
+    const bool check = !(J.flags & RTM_F_SKIP_CHECK);
+    unsigned *scal = D.at<unsigned>(J.ws.scal);
+    if (check) {
+        for (int d = 0; d < nslot; ++d) {
+            const GridInfo &g = J.shots[J.slot_shot[d]].g;
+            RTM_HIP(launch_vrange(J.shots[J.slot_shot[d]].v_pad, (int64_t)g.NX * g.NY * g.NZ, scal + 64 + 2 * d, st));
+        }
+        RTM_HIP(hipMemcpyAsync(vr.data(), scal + 64, vr.size() * sizeof(unsigned), hipMemcpyDeviceToHost, st));
+    }
+    RTM_HIP(hipStreamSynchronize(st));
+    if (check) {
+        for (int d = 0; d < nslot; ++d) {
+            const ShotIn &S = J.shots[J.slot_shot[d]];
+            float vmax, vmin;
+            std::memcpy(&vmax, &vr[2 * d], 4);
+            std::memcpy(&vmin, &vr[2 * d + 1], 4);
+            if (vr[2 * d] >= 0x7f800000u || !(vmin > 0.f))
+                return fail(RTM_ENUMERIC, "shot %d: velocity must be finite and > 0 (max bits 0x%08x, min %g)",
+                            J.slot_shot[d], vr[2 * d], (double)vmin);
+            const double limit = std::sqrt(315.0 / (512.0 * S.g.ndim));
+            const double courant = (double)vmax * J.dt / S.g.h;
+            if (!(courant < limit))
+                return fail(RTM_ECFL, "shot %d: max(v) dt / h = %.6f >= stability limit %.6f", J.slot_shot[d],
+                            courant, limit);
+        }
+    }
+    return RTM_OK;
+}
+
+// The device work of a job, after the upload (capturable in a hipGraph:
+// kernel launches only).
+int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *probe, bool timed)
+{
+    const ShotDev *shots = D.at<ShotDev>(J.ws.shots);
+    const int nsh = (int)J.shots.size();
+    const int nt = J.nt;
+    unsigned *scal = D.at<unsigned>(J.ws.scal);
+    for (int d = 0; d < (int)J.slot_shot.size(); ++d) {
+        const ShotIn &S = J.shots[J.slot_shot[d]];
+        RTM_HIP(launch_build_dp(S.g.L, S.v_pad, (float)(J.dt / S.g.h), D.at<float>(J.ws.dp[d]), st));
+    }
+    for (int i = 0; i < nsh; ++i) {
+        const int64_t F = J.shots[i].g.L.total;
+        for (int k = 0; k < nfields(J.op); ++k) RTM_HIP(launch_fill(D.at<float>(J.ws.fld[i][k]), F, 0.f, st));
+        if (J.op != RTM_OP_MODEL) RTM_HIP(launch_fill(D.at<float>(J.ws.acc0[i]), F, 0.f, st));
+        if (J.op == RTM_OP_RTM) RTM_HIP(launch_fill(D.at<float>(J.ws.acc1[i]), F, 0.f, st));
+        if (J.op == RTM_OP_VJP && J.shots[i].grad_wavelet)
+            RTM_HIP(launch_fill(D.at<float>(J.ws.wadj[i]), (int64_t)nt * kMaxNodes, 0.f, st));
+        if (J.op != RTM_OP_MODEL)
+            RTM_HIP(launch_transpose(J.shots[i].traces_in, D.at<float>(J.ws.trint[i]), J.shots[i].nrec, nt + 1, st));
+    }
+    // Forward pass (Algorithm 1; in RTM only the last two panels are kept).
+    {
+        const bool sample = J.op == RTM_OP_MODEL;
+        const Tile2D *tiles = D.at<Tile2D>(J.ws.tiles_f);
+        const InjEnt *ents = D.at<InjEnt>(J.ws.ents_f);
+        const Contrib *cont = D.at<Contrib>(J.ws.cont_f);
+        const SampleTask *stasks = D.at<SampleTask>(J.ws.stasks);
+        const int ntiles = (int)J.fw.tiles.size();
+        const int nsample = sample ? (int)J.stasks.size() : 0;
+        LoopTimer timer(sample ? kLoopModelFwd : kLoopRtmFwd, nt, st, timed);
+        for (int n = 0; n < nt; ++n)
+            RTM_HIP(launch_fwd2d(J.fw.tune.vec, shots, tiles, ntiles, J.fw.nslots, ents, cont,
+                                 sample ? stasks : nullptr, nsample, n, st));
+        timer.finish();
+        if (sample) RTM_HIP(launch_sample(shots, stasks, (int)J.stasks.size(), nt, st));
+    }
+    if (J.op == RTM_OP_MODEL) {
+        for (int i = 0; i < nsh; ++i) {
+            const ShotIn &S = J.shots[i];
+            RTM_HIP(launch_transpose(D.at<float>(J.ws.trint[i]), S.traces_out, nt + 1, S.nrec, st));
+            if (S.p_last) RTM_HIP(launch_unpack(S.g.L, D.at<float>(J.ws.fld[i][nt & 1]), S.p_last, st));
+            if (S.p_prev) RTM_HIP(launch_unpack(S.g.L, D.at<float>(J.ws.fld[i][(nt + 1) & 1]), S.p_prev, st));
+        }
+        return RTM_OK;
+    }
+    // Reverse pass (Algorithm 3): mu^{nt} = D' h^2 R^T g^{nt}, mu^{nt+1} = 0,
+    // then one fused launch per step k = nt-1 .. 0.
+    const bool grad = J.op == RTM_OP_VJP;
+    const Tile2D *tiles = D.at<Tile2D>(J.ws.tiles_r);
+    const InjEnt *ents = D.at<InjEnt>(J.ws.ents_r);
+    const Contrib *cont = D.at<Contrib>(J.ws.cont_r);
+    RTM_HIP(launch_inj_set(shots, ents, J.rv.nsrc_ent, J.rv.nsrc_ent + J.rv.nrec_ent, cont, nt, st));
+    const int ntiles = (int)J.rv.tiles.size();
+    const int reinject = (J.flags & RTM_F_NO_REINJECT) ? 0 : 1;
+    const bool probing = probe && probe->snap_k >= 0;
+    // wadj is recorded for a single-shot job only (its kernel argument is one
+    // buffer); batched VJPs do not return wavelet gradients.
+    float *wadj = (grad && nsh == 1 && J.shots[0].grad_wavelet) ? D.at<float>(J.ws.wadj[0]) : nullptr;
+    LoopTimer timer(grad ? kLoopRevGrad : kLoopRevImage, nt, st, timed && !probing);
+    for (int k = nt - 1; k >= 0; --k) {
+        RTM_HIP(launch_rev2d(J.rv.tune.vec, grad, shots, tiles, ntiles, J.rv.nslots, ents, cont, k, reinject, wadj,
+                             st));
+        if (probing) {
+            const ShotIn &S = J.shots[0];
+            if (k - 1 == probe->snap_k && probe->snap_p)
+                RTM_HIP(launch_unpack(S.g.L, D.at<float>(J.ws.fld[0][(k - 1) & 1]), probe->snap_p, st));
+            if (k == probe->snap_k && probe->snap_mu)
+                RTM_HIP(launch_unpack(S.g.L, D.at<float>(J.ws.fld[0][2 + (k & 1)]), probe->snap_mu, st));
+        }
+    }
+    timer.finish();
+    // Finalisation, shot by shot (stream-ordered, so shots may share an
+    // accumulated image buffer).
+    for (int i = 0; i < nsh; ++i) {
+        const ShotIn &S = J.shots[i];
+        if (grad) {
+            RTM_HIP(launch_grad(shots, i, (int64_t)S.g.NX * S.g.NY * S.g.NZ, S.v_pad, (float)J.dt, S.grad_v_pad, st));
+            if (S.grad_wavelet && nsh == 1)
+                RTM_HIP(launch_wadj(D.at<float>(J.ws.wadj[i]), nt, (float)(1.0 / (S.g.h * S.g.h)), S.grad_wavelet, st));
+        } else {
+            RTM_HIP(launch_image(shots, i, S.g.nx * S.g.ny * S.g.nz, scal + 64 + 2 * J.slot_shot.size() + i, J.eps,
+                                 S.image, (J.flags & RTM_F_ACCUMULATE) ? 1 : 0, S.num, S.den, st));
+        }
+    }
+    return RTM_OK;
+}
+
+int check_ws(const Job &J, void *ws, size_t ws_bytes)
+{
+    if (!ws) return fail(RTM_EWORKSPACE, "workspace is NULL (%zu bytes needed)", J.ws.bytes);
+    if (((uintptr_t)ws & 255) != 0) return fail(RTM_EWORKSPACE, "workspace must be 256-byte aligned");
+    if (ws_bytes < J.ws.bytes) return fail(RTM_EWORKSPACE, "workspace of %zu bytes < %zu needed", ws_bytes, J.ws.bytes);
+    return RTM_OK;
+}
+
+// Eager execution of a job (single-shot entry points and plans without a graph).
+int job_run(Job &J, void *ws, size_t ws_bytes, hipStream_t st, const rtm_probe_t *probe)
+{
+    int rc = check_ws(J, ws, ws_bytes);
+    if (rc) return rc;
+    Dev D{(char *)ws};
+    std::vector<ShotDev> shot_devs;
+    if ((rc = job_upload_and_check(J, D, shot_devs, st))) return rc;
+    return job_launch(J, D, st, probe, true);
+}
 
 int check_common(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt, const float *wavelet,
                  const float *src, int32_t nrec, const float *rec, GridInfo *g)
 {
     int rc = grid_info(grid, g);
     if (rc) return rc;
+    if (g->ndim != 2) return fail(RTM_EINVAL, "3-D propagation is not available in this build");
     if (!v_pad) return fail(RTM_EINVAL, "v_pad is NULL");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RTM_EINVAL, "dt must be positive and finite");
     if (nt < 1) return fail(RTM_EINVAL, "nt must be >= 1");
@@ -421,105 +719,52 @@ int check_common(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t 
     return RTM_OK;
 }
 
-// Validates the workspace, builds and uploads the tables, checks the
-// velocity model (unless skipped) and synchronises the stream once.
-int prepare(const GridInfo &g, int op, const float *v_pad, double dt, int32_t nt, const float *src, int32_t nrec,
-            const float *rec, uint32_t flags, void *ws, size_t ws_bytes, void *stream, Prepared *P)
+// A one-shot job whose workspace layout uses position-independent bounds,
+// so that rtm_workspace_bytes can size it without the acquisition.
+int single_job(Job &J, int op, const GridInfo &g, const float *v_pad, double dt, int nt, const float *wavelet,
+               const float *src, int nrec, const float *rec, uint32_t flags)
 {
-    P->g = g;
-    P->st = (hipStream_t)stream;
-    P->tune = get_tune(op == RTM_OP_MODEL ? 0 : 1);
-    if (g.ndim != 2) return fail(RTM_EINVAL, "3-D propagation is not available in this build");
-    ShotBufs need = carve(nullptr, g, op, nrec, nt);
-    if (!ws) return fail(RTM_EWORKSPACE, "workspace is NULL (%zu bytes needed)", need.bytes);
-    if (((uintptr_t)ws & 255) != 0) return fail(RTM_EWORKSPACE, "workspace must be 256-byte aligned");
-    if (ws_bytes < need.bytes) return fail(RTM_EWORKSPACE, "workspace of %zu bytes < %zu needed", ws_bytes, need.bytes);
-    int rc = build_tables_2d(g, P->tune, src, nrec, rec, &P->T);
+    J.op = op;
+    J.nt = nt;
+    J.dt = dt;
+    J.flags = flags;
+    ShotIn S;
+    S.g = g;
+    S.v_pad = v_pad;
+    S.wavelet = wavelet;
+    std::memcpy(S.src, src, sizeof S.src);
+    S.nrec = nrec;
+    S.rec.assign(rec, rec + 3 * (size_t)nrec);
+    J.shots.push_back(std::move(S));
+    int rc = build_job_tables(J);
     if (rc) return rc;
-    P->b = carve(ws, g, op, nrec, nt);
-    hipStream_t st = P->st;
-    const HostTables &T = P->T;
-    RTM_HIP(hipMemcpyAsync(P->b.tiles, T.tiles.data(), T.tiles.size() * sizeof(Tile2D), hipMemcpyHostToDevice, st));
-    if (!T.ents.empty()) {
-        RTM_HIP(hipMemcpyAsync(P->b.ents, T.ents.data(), T.ents.size() * sizeof(InjEnt), hipMemcpyHostToDevice, st));
-        RTM_HIP(hipMemcpyAsync(P->b.cont, T.cont.data(), T.cont.size() * sizeof(Contrib), hipMemcpyHostToDevice, st));
-    }
-    RTM_HIP(hipMemcpyAsync(P->b.stasks, T.stasks.data(), T.stasks.size() * sizeof(SampleTask), hipMemcpyHostToDevice, st));
-    RTM_HIP(hipMemcpyAsync(P->b.rnode, T.rnode.data(), T.rnode.size() * sizeof(int), hipMemcpyHostToDevice, st));
-    RTM_HIP(hipMemcpyAsync(P->b.rw, T.rw.data(), T.rw.size() * sizeof(float), hipMemcpyHostToDevice, st));
-    unsigned vr[2] = {0u, 0xffffffffu};
-    const bool check = !(flags & RTM_F_SKIP_CHECK);
-    if (check) {
-        RTM_HIP(launch_vrange(v_pad, (int64_t)g.NX * g.NY * g.NZ, P->b.scal, st));
-        RTM_HIP(hipMemcpyAsync(vr, P->b.scal, sizeof vr, hipMemcpyDeviceToHost, st));
-    }
-    RTM_HIP(hipStreamSynchronize(st));
-    if (check) {
-        float vmax, vmin;
-        std::memcpy(&vmax, &vr[0], 4);
-        std::memcpy(&vmin, &vr[1], 4);
-        if (vr[0] >= 0x7f800000u || !(vmin > 0.f))
-            return fail(RTM_ENUMERIC, "velocity must be finite and > 0 (max bits 0x%08x, min %g)", vr[0], (double)vmin);
-        const double limit = std::sqrt(315.0 / (512.0 * g.ndim));
-        const double courant = (double)vmax * dt / g.h;
-        if (!(courant < limit))
-            return fail(RTM_ECFL, "max(v) dt / h = %.6f >= stability limit %.6f", courant, limit);
-    }
+    J.ws = make_ws_layout(J, bound_counts(g, op, nrec));
     return RTM_OK;
 }
 
-void fill_shot(const Prepared &P, ShotDev *S, const float *wavelet, const float *sig, float *rec_out, int nrec)
+size_t single_bytes(const GridInfo &g, int op, int nrec, int nt)
 {
-    std::memset(S, 0, sizeof *S);
-    for (int i = 0; i < 4; ++i) S->fld[i] = P.b.fld[i];
-    S->acc0 = P.b.acc0;
-    S->acc1 = P.b.acc1;
-    S->Dp = P.b.Dp;
-    S->wav = wavelet;
-    S->sig = sig;
-    S->rec_out = rec_out;
-    S->rnode = P.b.rnode;
-    S->rw = P.b.rw;
-    S->nrec = nrec;
-    const GridInfo &g = P.g;
-    S->ix0 = g.nb;
-    S->ix1 = g.nb + (int)g.nx;
-    S->iy0 = g.ndim == 3 ? g.nb : 0;
-    S->iy1 = g.ndim == 3 ? g.nb + (int)g.ny : 1;
-    S->iz0 = g.nb;
-    S->iz1 = g.nb + (int)g.nz;
-    S->L = g.L;
-}
-
-int upload_shot(const Prepared &P, const ShotDev &S)
-{
-    // The descriptor is small; it is copied from a host value that lives
-    // until the call returns, after the stream synchronisation below.
-    RTM_HIP(hipMemcpyAsync(P.b.shot, &S, sizeof S, hipMemcpyHostToDevice, P.st));
-    RTM_HIP(hipStreamSynchronize(P.st));
-    return RTM_OK;
-}
-
-int forward_loop(const Prepared &P, int nt, bool sample)
-{
-    const HostTables &T = P.T;
-    const int ntiles = (int)T.tiles.size();
-    const int nsample = sample ? (int)T.stasks.size() : 0;
-    LoopTimer timer(sample ? kLoopModelFwd : kLoopRtmFwd, nt, P.st);
-    for (int n = 0; n < nt; ++n)
-        RTM_HIP(launch_fwd2d(P.tune.vec, P.b.shot, P.b.tiles, ntiles, T.nslots, P.b.ents, P.b.cont,
-                             sample ? P.b.stasks : nullptr, nsample, n, P.st));
-    timer.finish();
-    return RTM_OK;
-}
-
-int zero_fields(const Prepared &P, int nf)
-{
-    for (int i = 0; i < nf; ++i) RTM_HIP(launch_fill(P.b.fld[i], P.g.L.total, 0.f, P.st));
-    return RTM_OK;
+    Job J;
+    J.op = op;
+    J.nt = nt;
+    ShotIn S;
+    S.g = g;
+    S.nrec = nrec;
+    J.shots.push_back(S);
+    J.slot_shot.push_back(0);
+    J.dslot.push_back(0);
+    return make_ws_layout(J, bound_counts(g, op, nrec)).bytes;
 }
 
 }  // namespace
+
+// ===========================================================================
+// Batch plans
+// ===========================================================================
+
+struct rtm_plan {
+    Job job;
+};
 
 // ===========================================================================
 // C ABI
@@ -585,8 +830,12 @@ int rtm_workspace_bytes(const rtm_grid_t *grid, int op, int32_t nrec, int32_t nt
     if (rc) return rc;
     if (!bytes) return fail(RTM_EINVAL, "bytes is NULL");
     if (op < RTM_OP_RBC_PAD || op > RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
-    if (op != RTM_OP_RBC_PAD && (nrec < 1 || nt < 1)) return fail(RTM_EINVAL, "nrec and nt must be >= 1");
-    *bytes = carve(nullptr, g, op, nrec, nt).bytes;
+    if (op == RTM_OP_RBC_PAD) {
+        *bytes = 256;
+        return RTM_OK;
+    }
+    if (nrec < 1 || nt < 1) return fail(RTM_EINVAL, "nrec and nt must be >= 1");
+    *bytes = single_bytes(g, op, nrec, nt);
     return RTM_OK;
 }
 
@@ -601,12 +850,10 @@ int rtm_rbc_pad(const rtm_grid_t *grid, const float *v_int, uint64_t seed, float
     hipStream_t st = (hipStream_t)stream;
     const unsigned *cap_bits = nullptr;
     if (!(v_cap > 0.f)) {
-        size_t need = carve(nullptr, g, RTM_OP_RBC_PAD, 0, 0).bytes;
-        if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
-            return fail(RTM_EWORKSPACE, "v_cap <= 0 needs an aligned workspace of %zu bytes", need);
-        unsigned *slot = carve(ws, g, RTM_OP_RBC_PAD, 0, 0).scal;
-        RTM_HIP(launch_vmax(v_int, g.nx * g.ny * g.nz, slot, st));
-        cap_bits = slot;
+        if (!ws || ws_bytes < 256 || ((uintptr_t)ws & 255))
+            return fail(RTM_EWORKSPACE, "v_cap <= 0 needs an aligned workspace of 256 bytes");
+        RTM_HIP(launch_vmax(v_int, g.nx * g.ny * g.nz, (unsigned *)ws, st));
+        cap_bits = (const unsigned *)ws;
     }
     RTM_HIP(launch_rbc_pad(g.ndim, g.nb, g.nx, g.ny, g.nz, v_int, seed, v_cap, cap_bits, v_pad, st));
     return RTM_OK;
@@ -623,12 +870,10 @@ int rtm_pad_adjoint(const rtm_grid_t *grid, const float *v_int, uint64_t seed, f
     hipStream_t st = (hipStream_t)stream;
     const unsigned *cap_bits = nullptr;
     if (!(v_cap > 0.f)) {
-        size_t need = carve(nullptr, g, RTM_OP_RBC_PAD, 0, 0).bytes;
-        if (!ws || ws_bytes < need || ((uintptr_t)ws & 255))
-            return fail(RTM_EWORKSPACE, "v_cap <= 0 needs an aligned workspace of %zu bytes", need);
-        unsigned *slot = carve(ws, g, RTM_OP_RBC_PAD, 0, 0).scal;
-        RTM_HIP(launch_vmax(v_int, g.nx * g.ny * g.nz, slot, st));
-        cap_bits = slot;
+        if (!ws || ws_bytes < 256 || ((uintptr_t)ws & 255))
+            return fail(RTM_EWORKSPACE, "v_cap <= 0 needs an aligned workspace of 256 bytes");
+        RTM_HIP(launch_vmax(v_int, g.nx * g.ny * g.nz, (unsigned *)ws, st));
+        cap_bits = (const unsigned *)ws;
     }
     RTM_HIP(launch_pad_adjoint(g.ndim, g.nb, g.nx, g.ny, g.nz, v_int, seed, v_cap, cap_bits, grad_v_pad, grad_v_int,
                                st));
@@ -644,65 +889,12 @@ int rtm_model_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_
     int rc = check_common(grid, v_pad, dt, nt, wavelet, src, nrec, rec, &g);
     if (rc) return rc;
     if (!traces) return fail(RTM_EINVAL, "traces is NULL");
-    Prepared P;
-    rc = prepare(g, RTM_OP_MODEL, v_pad, dt, nt, src, nrec, rec, flags, ws, ws_bytes, stream, &P);
-    if (rc) return rc;
-    ShotDev S;
-    fill_shot(P, &S, wavelet, nullptr, P.b.traces, nrec);
-    hipStream_t st = P.st;
-    RTM_HIP(launch_build_dp(g.L, v_pad, (float)(dt / g.h), P.b.Dp, st));
-    if ((rc = zero_fields(P, 2))) return rc;
-    if ((rc = upload_shot(P, S))) return rc;
-    if ((rc = forward_loop(P, nt, true))) return rc;
-    RTM_HIP(launch_sample(P.b.shot, P.b.stasks, (int)P.T.stasks.size(), nt, st));
-    RTM_HIP(launch_transpose(P.b.traces, traces, nt + 1, nrec, st));
-    if (p_last) RTM_HIP(launch_unpack(g.L, P.b.fld[nt & 1], p_last, st));
-    if (p_prev) RTM_HIP(launch_unpack(g.L, P.b.fld[(nt + 1) & 1], p_prev, st));
-    return RTM_OK;
-}
-
-static int reverse_common(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt, const float *wavelet,
-                          const float *src, int32_t nrec, const float *rec, const float *traces, bool grad,
-                          int reinject, const rtm_probe_t *probe, uint32_t flags, void *ws, size_t ws_bytes,
-                          void *stream, Prepared *P, bool want_wadj)
-{
-    GridInfo g;
-    int rc = check_common(grid, v_pad, dt, nt, wavelet, src, nrec, rec, &g);
-    if (rc) return rc;
-    if (!traces) return fail(RTM_EINVAL, "traces is NULL");
-    if (probe && probe->snap_k >= 0 && probe->snap_k > nt - 2)
-        return fail(RTM_EINVAL, "probe step %d outside [0, nt - 2]", (int)probe->snap_k);
-    rc = prepare(g, grad ? RTM_OP_VJP : RTM_OP_RTM, v_pad, dt, nt, src, nrec, rec, flags, ws, ws_bytes, stream, P);
-    if (rc) return rc;
-    ShotDev S;
-    fill_shot(*P, &S, wavelet, P->b.traces, nullptr, nrec);
-    hipStream_t st = P->st;
-    RTM_HIP(launch_build_dp(g.L, v_pad, (float)(dt / g.h), P->b.Dp, st));
-    if ((rc = zero_fields(*P, 4))) return rc;
-    RTM_HIP(launch_fill(P->b.acc0, g.L.total, 0.f, st));
-    if (!grad) RTM_HIP(launch_fill(P->b.acc1, g.L.total, 0.f, st));
-    if (want_wadj) RTM_HIP(launch_fill(P->b.wadj, (int64_t)nt * kMaxNodes, 0.f, st));
-    RTM_HIP(launch_transpose(traces, P->b.traces, nrec, nt + 1, st));
-    if ((rc = upload_shot(*P, S))) return rc;
-    // Forward pass: only the last two panels are kept (Algorithm 3).
-    if ((rc = forward_loop(*P, nt, false))) return rc;
-    // Receiver field start: mu^{nt} = D' h^2 R^T g^{nt}, mu^{nt+1} = 0.
-    const HostTables &T = P->T;
-    RTM_HIP(launch_inj_set(P->b.shot, 0, P->b.ents, T.nsrc_ent, T.nsrc_ent + T.nrec_ent, P->b.cont, nt, st));
-    const int ntiles = (int)T.tiles.size();
-    const bool probing = probe && probe->snap_k >= 0;
-    // Probe copies would be timed with the loop: such calls are not recorded.
-    LoopTimer timer(grad ? kLoopRevGrad : kLoopRevImage, nt, st, !probing);
-    for (int k = nt - 1; k >= 0; --k) {
-        RTM_HIP(launch_rev2d(P->tune.vec, grad, P->b.shot, P->b.tiles, ntiles, T.nslots, P->b.ents, P->b.cont, k,
-                             reinject, want_wadj ? P->b.wadj : nullptr, st));
-        if (probe && probe->snap_k >= 0) {
-            if (k - 1 == probe->snap_k && probe->snap_p) RTM_HIP(launch_unpack(g.L, P->b.fld[(k - 1) & 1], probe->snap_p, st));
-            if (k == probe->snap_k && probe->snap_mu) RTM_HIP(launch_unpack(g.L, P->b.fld[2 + (k & 1)], probe->snap_mu, st));
-        }
-    }
-    timer.finish();
-    return RTM_OK;
+    Job J;
+    if ((rc = single_job(J, RTM_OP_MODEL, g, v_pad, dt, nt, wavelet, src, nrec, rec, flags))) return rc;
+    J.shots[0].traces_out = traces;
+    J.shots[0].p_last = p_last;
+    J.shots[0].p_prev = p_prev;
+    return job_run(J, ws, ws_bytes, (hipStream_t)stream, nullptr);
 }
 
 int rtm_rtm_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt, const float *wavelet,
@@ -711,15 +903,23 @@ int rtm_rtm_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t 
                  void *stream)
 {
     t_err.clear();
+    GridInfo g;
+    int rc = check_common(grid, v_pad, dt, nt, wavelet, src, nrec, rec, &g);
+    if (rc) return rc;
+    if (!traces) return fail(RTM_EINVAL, "traces is NULL");
     if (!image) return fail(RTM_EINVAL, "image is NULL");
     if (!(eps_rel >= 0.f) || !std::isfinite(eps_rel)) return fail(RTM_EINVAL, "eps_rel must be finite and >= 0");
-    Prepared P;
-    int reinject = (flags & RTM_F_NO_REINJECT) ? 0 : 1;
-    int rc = reverse_common(grid, v_pad, dt, nt, wavelet, src, nrec, rec, traces, false, reinject, probe, flags, ws,
-                            ws_bytes, stream, &P, false);
-    if (rc) return rc;
-    RTM_HIP(launch_image(P.b.shot, 0, P.g.nx * P.g.ny * P.g.nz, P.b.scal, eps_rel, image, num, den, P.st));
-    return RTM_OK;
+    if (probe && probe->snap_k >= 0 && probe->snap_k > nt - 2)
+        return fail(RTM_EINVAL, "probe step %d outside [0, nt - 2]", (int)probe->snap_k);
+    Job J;
+    if ((rc = single_job(J, RTM_OP_RTM, g, v_pad, dt, nt, wavelet, src, nrec, rec, flags & ~RTM_F_ACCUMULATE)))
+        return rc;
+    J.eps = eps_rel;
+    J.shots[0].traces_in = traces;
+    J.shots[0].image = image;
+    J.shots[0].num = num;
+    J.shots[0].den = den;
+    return job_run(J, ws, ws_bytes, (hipStream_t)stream, probe);
 }
 
 int rtm_model_shot_vjp(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt, const float *wavelet,
@@ -727,14 +927,123 @@ int rtm_model_shot_vjp(const rtm_grid_t *grid, const float *v_pad, double dt, in
                        float *grad_wavelet, uint32_t flags, void *ws, size_t ws_bytes, void *stream)
 {
     t_err.clear();
-    if (!grad_v_pad) return fail(RTM_EINVAL, "grad_v_pad is NULL");
-    Prepared P;
-    int rc = reverse_common(grid, v_pad, dt, nt, wavelet, src, nrec, rec, grad_traces, true, 1, nullptr, flags, ws,
-                            ws_bytes, stream, &P, grad_wavelet != nullptr);
+    GridInfo g;
+    int rc = check_common(grid, v_pad, dt, nt, wavelet, src, nrec, rec, &g);
     if (rc) return rc;
-    const GridInfo &g = P.g;
-    RTM_HIP(launch_grad(P.b.shot, 0, (int64_t)g.NX * g.NY * g.NZ, v_pad, (float)dt, grad_v_pad, P.st));
-    if (grad_wavelet) RTM_HIP(launch_wadj(P.b.wadj, nt, (float)(1.0 / (g.h * g.h)), grad_wavelet, P.st));
+    if (!grad_traces) return fail(RTM_EINVAL, "grad_traces is NULL");
+    if (!grad_v_pad) return fail(RTM_EINVAL, "grad_v_pad is NULL");
+    Job J;
+    if ((rc = single_job(J, RTM_OP_VJP, g, v_pad, dt, nt, wavelet, src, nrec, rec, flags & ~RTM_F_NO_REINJECT)))
+        return rc;
+    J.shots[0].traces_in = grad_traces;
+    J.shots[0].grad_v_pad = grad_v_pad;
+    J.shots[0].grad_wavelet = grad_wavelet;
+    return job_run(J, ws, ws_bytes, (hipStream_t)stream, nullptr);
+}
+
+int rtm_batch_plan(int op, int32_t nshots, const rtm_shot_desc_t *descs, double dt, int32_t nt, float eps_rel,
+                   uint32_t flags, rtm_plan_t **plan, size_t *ws_bytes)
+{
+    t_err.clear();
+    if (!plan || !ws_bytes) return fail(RTM_EINVAL, "plan and ws_bytes must be non-NULL");
+    *plan = nullptr;
+    if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
+    if (nshots < 1 || !descs) return fail(RTM_EINVAL, "need at least one shot");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RTM_EINVAL, "dt must be positive and finite");
+    if (nt < 1) return fail(RTM_EINVAL, "nt must be >= 1");
+    if (op == RTM_OP_RTM && (!(eps_rel >= 0.f) || !std::isfinite(eps_rel)))
+        return fail(RTM_EINVAL, "eps_rel must be finite and >= 0");
+    rtm_plan *P = new (std::nothrow) rtm_plan;
+    if (!P) return fail(RTM_EINVAL, "out of host memory");
+    Job &J = P->job;
+    J.op = op;
+    J.nt = nt;
+    J.dt = dt;
+    J.eps = eps_rel;
+    J.flags = flags;
+    for (int s = 0; s < nshots; ++s) {
+        const rtm_shot_desc_t &d = descs[s];
+        ShotIn S;
+        int rc = grid_info(&d.grid, &S.g);
+        if (!rc && S.g.ndim != 2) rc = fail(RTM_EINVAL, "3-D propagation is not available in this build");
+        if (!rc && (!d.v_pad || !d.wavelet)) rc = fail(RTM_EINVAL, "shot %d: v_pad and wavelet are required", s);
+        if (!rc && (d.nrec < 1 || !d.rec)) rc = fail(RTM_EINVAL, "shot %d: at least one receiver is required", s);
+        if (!rc && (int64_t)(nt + 1) * d.nrec >= ((int64_t)1 << 31)) rc = fail(RTM_EINVAL, "shot %d: too many samples", s);
+        if (!rc && op == RTM_OP_MODEL && !d.traces_out) rc = fail(RTM_EINVAL, "shot %d: traces_out is required", s);
+        if (!rc && op != RTM_OP_MODEL && !d.traces_in) rc = fail(RTM_EINVAL, "shot %d: traces_in is required", s);
+        if (!rc && op == RTM_OP_RTM && !d.image) rc = fail(RTM_EINVAL, "shot %d: image is required", s);
+        if (!rc && op == RTM_OP_VJP && !d.grad_v_pad) rc = fail(RTM_EINVAL, "shot %d: grad_v_pad is required", s);
+        if (rc) {
+            delete P;
+            return rc;
+        }
+        S.v_pad = d.v_pad;
+        S.wavelet = d.wavelet;
+        std::memcpy(S.src, d.src, sizeof S.src);
+        S.nrec = d.nrec;
+        S.rec.assign(d.rec, d.rec + 3 * (size_t)d.nrec);
+        S.traces_in = d.traces_in;
+        S.traces_out = d.traces_out;
+        S.image = d.image;
+        S.grad_v_pad = d.grad_v_pad;
+        J.shots.push_back(std::move(S));
+    }
+    int rc = build_job_tables(J);
+    if (rc) {
+        delete P;
+        return rc;
+    }
+    J.ws = make_ws_layout(J, exact_counts(J));
+    *ws_bytes = J.ws.bytes;
+    *plan = P;
+    return RTM_OK;
+}
+
+int rtm_batch_run(rtm_plan_t *plan, void *ws, size_t ws_bytes, void *stream)
+{
+    t_err.clear();
+    if (!plan) return fail(RTM_EINVAL, "plan is NULL");
+    Job &J = plan->job;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = check_ws(J, ws, ws_bytes);
+    if (rc) return rc;
+    Dev D{(char *)ws};
+    std::vector<ShotDev> shot_devs;
+    if ((rc = job_upload_and_check(J, D, shot_devs, st))) return rc;
+    if (!(J.flags & RTM_F_GRAPH)) return job_launch(J, D, st, nullptr, true);
+    if (!st) return fail(RTM_EINVAL, "RTM_F_GRAPH needs a non-NULL stream (the NULL stream cannot be captured)");
+    if (J.gexec && (J.g_ws != ws || J.g_st != st)) {
+        (void)hipGraphExecDestroy(J.gexec);
+        J.gexec = nullptr;
+    }
+    if (!J.gexec) {
+        hipGraph_t graph = nullptr;
+        RTM_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        rc = job_launch(J, D, st, nullptr, false);
+        hipError_t e = hipStreamEndCapture(st, &graph);
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(RTM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&J.gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            J.gexec = nullptr;
+            return fail(RTM_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+        J.g_ws = ws;
+        J.g_st = st;
+    }
+    RTM_HIP(hipGraphLaunch(J.gexec, st));
+    return RTM_OK;
+}
+
+int rtm_batch_free(rtm_plan_t *plan)
+{
+    if (!plan) return RTM_OK;
+    if (plan->job.gexec) (void)hipGraphExecDestroy(plan->job.gexec);
+    delete plan;
     return RTM_OK;
 }
 

@@ -20,6 +20,15 @@ inline unsigned grid_for(int64_t n)
     return (unsigned)b;
 }
 
+// Grid for reductions: a few blocks per CU, each striding over the data.
+inline unsigned grid_reduce(int64_t n)
+{
+    int64_t b = (n + kBlock - 1) / kBlock;
+    if (b < 1) b = 1;
+    if (b > 1024) b = 1024;
+    return (unsigned)b;
+}
+
 // SplitMix64 (Steele, Lea & Flood 2014): output number k + 1 of the stream
 // seeded with `seed` (state advanced by the golden-ratio increment, then the
 // 64-bit finaliser).
@@ -48,22 +57,41 @@ struct PadDims {
 
 __device__ __forceinline__ int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-__global__ void vmax_bits_kernel(const float *__restrict__ v, int64_t n, unsigned *__restrict__ out)
+// Block-wide max / min of unsigned values (kBlock threads), then one
+// atomic per block.
+template <bool MAX>
+__device__ __forceinline__ void block_reduce_atomic(unsigned m, unsigned *out)
+{
+    __shared__ unsigned part[kBlock / 64];
+    for (int off = 32; off > 0; off >>= 1) {
+        unsigned o = (unsigned)__shfl_xor((int)m, off);
+        m = MAX ? max(m, o) : min(m, o);
+    }
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kBlock / 64; ++w) m = MAX ? max(m, part[w]) : min(m, part[w]);
+        if (MAX) atomicMax(out, m);
+        else atomicMin(out, m);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void vmax_bits_kernel(const float *__restrict__ v, int64_t n,
+                                                           unsigned *__restrict__ out)
 {
     // Largest IEEE bit pattern: for positive finite data it is the maximum;
     // a NaN, infinity or negative value compares above +inf's pattern.
     unsigned m = 0u;
     for (int64_t i = gid(); i < n; i += gstride()) m = max(m, __float_as_uint(v[i]));
-    for (int off = 32; off > 0; off >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+    block_reduce_atomic<true>(m, out);
 }
 
-__global__ void vmin_bits_kernel(const float *__restrict__ v, int64_t n, unsigned *__restrict__ out)
+__global__ __launch_bounds__(kBlock) void vmin_bits_kernel(const float *__restrict__ v, int64_t n,
+                                                           unsigned *__restrict__ out)
 {
     unsigned m = 0xffffffffu;
     for (int64_t i = gid(); i < n; i += gstride()) m = min(m, __float_as_uint(v[i]));
-    for (int off = 32; off > 0; off >>= 1) m = min(m, (unsigned)__shfl_xor((int)m, off));
-    if ((threadIdx.x & 63) == 0) atomicMin(out, m);
+    block_reduce_atomic<false>(m, out);
 }
 
 __global__ void set_u32_kernel(unsigned *__restrict__ p, int n, unsigned v)
@@ -185,21 +213,20 @@ __global__ void transpose_kernel(const float *__restrict__ in, float *__restrict
     }
 }
 
-// mu^N = D' (R^T g^N): one thread per receiver injection node.
-__global__ void inj_set_kernel(const ShotDev *__restrict__ shots, int shot, const InjEnt *__restrict__ ents,
-                               int ebeg, int eend, const Contrib *__restrict__ cont, int step, float *const *fld_sel)
+// mu^N = D' (R^T g^N): one thread per receiver injection node, any shot.
+__global__ void inj_set_kernel(const ShotDev *__restrict__ shots, const InjEnt *__restrict__ ents, int ebeg, int eend,
+                               const Contrib *__restrict__ cont, int step)
 {
     const int e = ebeg + (int)gid();
     if (e >= eend) return;
-    const ShotDev &S = shots[shot];
     const InjEnt E = ents[e];
+    const ShotDev &S = shots[E.shot];
     const float *sig = S.sig + (int64_t)step * S.nrec;
     float s = 0.f;
     for (int c = E.cbeg; c < E.cend; ++c) s = fmaf(cont[c].w, sig[cont[c].idx], s);
     const int64_t off = S.L.org + (int64_t)E.z * S.L.plane + (int64_t)E.y * S.L.pitch + E.x;
     float *mu = S.fld[2 + (step & 1)];
     mu[off] = S.Dp[off] * s;
-    (void)fld_sel;
 }
 
 // d^n = R p^n for all receivers of every shot (used for the last sample).
@@ -216,7 +243,7 @@ __global__ void sample_kernel(const ShotDev *__restrict__ shots, const SampleTas
 }
 
 // max of den over the interior box, as float bits (den >= 0).
-__global__ void den_max_kernel(const ShotDev *__restrict__ shots, int shot, unsigned *__restrict__ out)
+__global__ __launch_bounds__(kBlock) void den_max_kernel(const ShotDev *__restrict__ shots, int shot, unsigned *__restrict__ out)
 {
     const ShotDev &S = shots[shot];
     const int64_t nx = S.ix1 - S.ix0, ny = S.iy1 - S.iy0, nz = S.iz1 - S.iz0;
@@ -227,13 +254,12 @@ __global__ void den_max_kernel(const ShotDev *__restrict__ shots, int shot, unsi
         const int64_t off = S.L.org + (z + S.iz0) * S.L.plane + (y + S.iy0) * S.L.pitch + (x + S.ix0);
         m = max(m, __float_as_uint(fmaxf(S.acc1[off], 0.f)));
     }
-    for (int o = 32; o > 0; o >>= 1) m = max(m, (unsigned)__shfl_xor((int)m, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+    block_reduce_atomic<true>(m, out);
 }
 
 // image = num / (den + eps max(den)) on the interior crop (Eq. (3)).
 __global__ void image_kernel(const ShotDev *__restrict__ shots, int shot, const unsigned *__restrict__ dmax_bits,
-                             float eps_rel, float *__restrict__ image, float *__restrict__ num_out,
+                             float eps_rel, float *__restrict__ image, int accumulate, float *__restrict__ num_out,
                              float *__restrict__ den_out)
 {
     const ShotDev &S = shots[shot];
@@ -244,7 +270,10 @@ __global__ void image_kernel(const ShotDev *__restrict__ shots, int shot, const 
         const int64_t x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
         const int64_t off = S.L.org + (z + S.iz0) * S.L.plane + (y + S.iy0) * S.L.pitch + (x + S.ix0);
         const float a = S.acc0[off], b = S.acc1[off];
-        if (image) image[i] = a / (b + stab);
+        if (image) {
+            const float v = a / (b + stab);
+            image[i] = accumulate ? image[i] + v : v;
+        }
         if (num_out) num_out[i] = a;
         if (den_out) den_out[i] = b;
     }
@@ -300,15 +329,15 @@ hipError_t launch_vrange(const float *v, int64_t n, unsigned *maxmin2, hipStream
 {
     hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(64), 0, st, maxmin2, 1, 0u);
     hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(64), 0, st, maxmin2 + 1, 1, 0xffffffffu);
-    hipLaunchKernelGGL(vmax_bits_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, v, n, maxmin2);
-    hipLaunchKernelGGL(vmin_bits_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, v, n, maxmin2 + 1);
+    hipLaunchKernelGGL(vmax_bits_kernel, dim3(grid_reduce(n)), dim3(kBlock), 0, st, v, n, maxmin2);
+    hipLaunchKernelGGL(vmin_bits_kernel, dim3(grid_reduce(n)), dim3(kBlock), 0, st, v, n, maxmin2 + 1);
     return hipGetLastError();
 }
 
 hipError_t launch_vmax(const float *v, int64_t n, unsigned *out, hipStream_t st)
 {
     hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(64), 0, st, out, 1, 0u);
-    hipLaunchKernelGGL(vmax_bits_kernel, dim3(grid_for(n)), dim3(kBlock), 0, st, v, n, out);
+    hipLaunchKernelGGL(vmax_bits_kernel, dim3(grid_reduce(n)), dim3(kBlock), 0, st, v, n, out);
     return hipGetLastError();
 }
 
@@ -357,13 +386,13 @@ hipError_t launch_transpose(const float *in, float *out, int64_t R, int64_t C, h
     return hipGetLastError();
 }
 
-hipError_t launch_inj_set(const ShotDev *shots, int shot, const InjEnt *ents, int ebeg, int eend,
-                          const Contrib *cont, int step, hipStream_t st)
+hipError_t launch_inj_set(const ShotDev *shots, const InjEnt *ents, int ebeg, int eend, const Contrib *cont, int step,
+                          hipStream_t st)
 {
     int n = eend - ebeg;
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(inj_set_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, shots, shot, ents, ebeg,
-                       eend, cont, step, (float *const *)nullptr);
+    hipLaunchKernelGGL(inj_set_kernel, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, st, shots, ents, ebeg, eend,
+                       cont, step);
     return hipGetLastError();
 }
 
@@ -375,12 +404,12 @@ hipError_t launch_sample(const ShotDev *shots, const SampleTask *stasks, int nta
 }
 
 hipError_t launch_image(const ShotDev *shots, int shot, int64_t ninterior, unsigned *dmax_bits, float eps_rel,
-                        float *image, float *num, float *den, hipStream_t st)
+                        float *image, int accumulate, float *num, float *den, hipStream_t st)
 {
     hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(64), 0, st, dmax_bits, 1, 0u);
-    hipLaunchKernelGGL(den_max_kernel, dim3(grid_for(ninterior)), dim3(kBlock), 0, st, shots, shot, dmax_bits);
+    hipLaunchKernelGGL(den_max_kernel, dim3(grid_reduce(ninterior)), dim3(kBlock), 0, st, shots, shot, dmax_bits);
     hipLaunchKernelGGL(image_kernel, dim3(grid_for(ninterior)), dim3(kBlock), 0, st, shots, shot,
-                       (const unsigned *)dmax_bits, eps_rel, image, num, den);
+                       (const unsigned *)dmax_bits, eps_rel, image, accumulate, num, den);
     return hipGetLastError();
 }
 

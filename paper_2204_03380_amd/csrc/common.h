@@ -90,11 +90,13 @@ struct Tile3D {
 // One injection node: padded coordinates and the contributions
 // cont[cbeg, cend) whose weighted signal sum is added at the node.  `slot`
 // numbers the nodes of the source point (0 .. 2^ndim - 1), for the wavelet
-// adjoint.
+// adjoint; `shot` is the owning shot.
 struct InjEnt {
     int z, y, x;
     int cbeg, cend;
     int slot;
+    int shot;
+    int pad_;
 };
 
 // Contribution to an injection node: signal index (receiver number, or 0
