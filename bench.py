@@ -33,12 +33,16 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--shots-per-step", type=int, default=16)
     ap.add_argument("--plain-shots", type=int, default=2, help="shots timed through the plain per-shot calls")
-    ap.add_argument("--vec", type=int, default=1, help="floats per lane of the propagation kernels")
-    ap.add_argument("--zseg", type=int, default=16, help="rows per tile of the propagation kernels")
+    ap.add_argument("--vec", type=int, default=0, help="floats per lane of both propagation kernels (0: tuned)")
+    ap.add_argument("--zseg", type=int, default=0, help="rows per tile of both kernels, a multiple of 9 (0: tuned)")
     ap.add_argument("--nt", type=int, default=5000)
     ap.add_argument("--cpu-sample-nt", type=int, default=240,
                     help="time steps of the oracle's timed sample (one shot, modeling + RTM)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before the benchmark, copy a device buffer of this many MiB once (a plain copy kernel of "
+                         "known size, to scale hardware byte counters)")
+    ap.add_argument("--autotune", action="store_true", help="pick launch shapes with the autotuner first")
     return ap.parse_args()
 
 
@@ -89,8 +93,23 @@ def main():
     nshot = s.src.shape[0]
     nrec = s.rec.shape[0]
     nt = args.nt
-    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, args.vec, args.zseg)
-    rtm.rtm_set_tuning(rtm.RTM_OP_RTM, args.vec, args.zseg)
+    if args.copy_probe_mib > 0:
+        a = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+    if args.vec and args.zseg:
+        rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, args.vec, args.zseg)
+        rtm.rtm_set_tuning(rtm.RTM_OP_RTM, args.vec, args.zseg)
+    tuned = None
+    if args.autotune:
+        from paper_2204_03380_amd import autotune
+        v_tmp = rtm.rtm_rbc_pad(g, v_int, s.seed, 0.0)
+        tuned = autotune.tune_batch(g, v_tmp, wav, [s.src[i] for i in range(B)], s.rec, s.dt, nt_probe=90, reps=2)
+        del v_tmp
+    fwd_shape = rtm.rtm_get_tuning(rtm.RTM_OP_MODEL)
+    rev_shape = rtm.rtm_get_tuning(rtm.RTM_OP_RTM)
 
     # Buffers resident in HBM before timing: padded model, B traces, stack.
     v_pad = rtm.rtm_rbc_pad(g, v_int, s.seed, 0.0)
@@ -197,11 +216,14 @@ def main():
             "padded_cells": cells,
             "shots_per_step": B,
             "propagations_per_shot": 4,
-            "launch_shape": {"vec": args.vec, "zseg": args.zseg},
+            "launch_shape": {"forward": {"vec": fwd_shape[0], "zseg": fwd_shape[1]},
+                             "reverse": {"vec": rev_shape[0], "zseg": rev_shape[1]},
+                             "autotuned": tuned is not None},
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": f"rev2d_kernel<{args.vec},false> (fused reconstruction + receiver field + imaging, {B} shots)",
+            "kernel": f"rev2d_kernel<{rev_shape[0]},false> (fused reconstruction + receiver field + imaging, "
+                      f"{B} shots per launch)",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",

@@ -110,9 +110,16 @@ const char *rtm_last_error(void);
 /* Launch shape of the 2-D propagation kernels, process-wide, for the
  * autotuner: `op` RTM_OP_MODEL selects the forward kernel, RTM_OP_RTM or
  * RTM_OP_VJP the reverse kernels; vec in {1, 2, 4} floats per lane (strips
- * of 64 * vec columns), zseg in [4, 4096] rows per tile.  Results do not
- * depend on the shape.  Not synchronised with concurrent calls. */
+ * of 64 * vec columns), zseg rows per tile, a multiple of 9 in [9, 4095]
+ * (the march is unrolled by the 9-row register queue).  A job with too few
+ * tiles to fill the GPU gets a narrower shape automatically, unless
+ * rtm_set_tuning(RTM_TUNE_EXACT, 1, 0) was called (RTM_TUNE_EXACT, 0, 0
+ * re-enables narrowing).  Results do not depend on the shape.  Not
+ * synchronised with concurrent calls. */
+#define RTM_TUNE_EXACT 0x100
 int rtm_set_tuning(int op, int vec, int zseg);
+/* Current launch shape for `op` (same selection as rtm_set_tuning). */
+int rtm_get_tuning(int op, int *vec, int *zseg);
 
 /* Event timing of the time loops, for measurement.  While enabled, every
  * propagation call records a HIP event pair on its stream around each of

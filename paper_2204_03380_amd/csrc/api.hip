@@ -83,8 +83,10 @@ struct Tune {
     int zseg;
 };
 
-std::atomic<int> g_tune2d_fwd{(1 << 16) | 16};
-std::atomic<int> g_tune2d_rev{(1 << 16) | 16};
+// Defaults from a sweep on 16 shots of the 2301 x 751 folded grid.
+std::atomic<int> g_tune2d_fwd{(4 << 16) | 36};
+std::atomic<int> g_tune2d_rev{(2 << 16) | 63};
+std::atomic<int> g_tune_exact{0};  // 1: never narrow the configured shapes
 
 Tune get_tune(int which)
 {
@@ -92,7 +94,7 @@ Tune get_tune(int which)
     return Tune{v >> 16, v & 0xffff};
 }
 
-constexpr int kMinZseg = 4;
+constexpr int kMinZseg = kZUnroll;
 
 // ---------------------------------------------------------------------------
 // Optional event timing of the time loops (measurement only).
@@ -326,7 +328,7 @@ WsLayout make_ws_layout(const Job &J, const Counts &c)
 
 int max_tiles(const GridInfo &g)
 {
-    return (int)(((int64_t)(g.NX + 63) / 64) * ((g.NZ + kMinZseg - 1) / kMinZseg));
+    return (int)(((int64_t)(g.NX + 63) / 64) * (g.L.NZr / kMinZseg));
 }
 
 struct RawEnt {
@@ -347,7 +349,8 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
         const ShotIn &S = J.shots[s];
         const GridInfo &g = S.g;
         const int ns = (g.NX + strip - 1) / strip;
-        const int nzs = (g.NZ + T.tune.zseg - 1) / T.tune.zseg;
+        const int NZr = g.L.NZr;
+        const int nzs = (NZr + T.tune.zseg - 1) / T.tune.zseg;
         const int tbase = (int)T.tiles.size();
         for (int xs = 0; xs < ns; ++xs)
             for (int zs = 0; zs < nzs; ++zs) {
@@ -355,7 +358,7 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
                 t.shot = s;
                 t.x0 = xs * strip;
                 t.z0 = zs * T.tune.zseg;
-                t.z1 = std::min(t.z0 + T.tune.zseg, g.NZ);
+                t.z1 = std::min(t.z0 + T.tune.zseg, NZr);
                 T.tiles.push_back(t);
             }
         auto tile_of = [&](int z, int x) { return tbase + (x / strip) * nzs + z / T.tune.zseg; };
@@ -420,6 +423,32 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
     return RTM_OK;
 }
 
+// Wavefronts a launch shape gives a job.
+int64_t count_tiles(const Job &J, Tune t)
+{
+    int64_t n = 0;
+    for (const ShotIn &S : J.shots)
+        n += (int64_t)((S.g.NX + 64 * t.vec - 1) / (64 * t.vec)) * ((S.g.L.NZr + t.zseg - 1) / t.zseg);
+    return n;
+}
+
+// The configured shape is meant for large batches; a small job (a single
+// shot of a modest grid) would leave most of the 256 CUs idle, so the shape
+// is narrowed (fewer rows per tile first, then fewer floats per lane) until
+// the job has at least kMinWaves wavefronts or the smallest shape is
+// reached.  Results do not depend on the shape.
+constexpr int64_t kMinWaves = 256 * 16;
+
+Tune fit_tune(const Job &J, Tune t)
+{
+    while (!g_tune_exact.load() && count_tiles(J, t) < kMinWaves) {
+        if (t.zseg > kMinZseg) t.zseg = std::max(kMinZseg, t.zseg / 2 / kZUnroll * kZUnroll);
+        else if (t.vec > 1) t.vec /= 2;
+        else break;
+    }
+    return t;
+}
+
 // Receiver sampling tables, D' sharing and tilings of a job.
 int build_job_tables(Job &J)
 {
@@ -464,11 +493,11 @@ int build_job_tables(Job &J)
         }
         J.dslot.push_back(slot);
     }
-    J.fw.tune = get_tune(0);
+    J.fw.tune = fit_tune(J, get_tune(0));
     int rc = build_tiling(J, J.fw, false);
     if (rc) return rc;
     if (J.op != RTM_OP_MODEL) {
-        J.rv.tune = get_tune(1);
+        J.rv.tune = fit_tune(J, get_tune(1));
         rc = build_tiling(J, J.rv, true);
         if (rc) return rc;
     }
@@ -778,12 +807,27 @@ const char *rtm_last_error(void) { return t_err.c_str(); }
 
 int rtm_set_tuning(int op, int vec, int zseg)
 {
+    if (op == RTM_TUNE_EXACT || op == 0) {
+        g_tune_exact = (op == RTM_TUNE_EXACT) ? (vec != 0) : 0;
+        return RTM_OK;
+    }
     if (vec != 1 && vec != 2 && vec != 4) return fail(RTM_EINVAL, "vec must be 1, 2 or 4");
-    if (zseg < kMinZseg || zseg > 4096) return fail(RTM_EINVAL, "zseg must be in [%d, 4096]", kMinZseg);
+    if (zseg < kMinZseg || zseg > 4095 || zseg % kZUnroll != 0)
+        return fail(RTM_EINVAL, "zseg must be a multiple of %d in [%d, 4095]", kZUnroll, kMinZseg);
     int packed = (vec << 16) | zseg;
     if (op == RTM_OP_MODEL) g_tune2d_fwd = packed;
     else if (op == RTM_OP_RTM || op == RTM_OP_VJP) g_tune2d_rev = packed;
     else return fail(RTM_EINVAL, "unknown op %d", op);
+    return RTM_OK;
+}
+
+int rtm_get_tuning(int op, int *vec, int *zseg)
+{
+    if (!vec || !zseg) return fail(RTM_EINVAL, "NULL output");
+    if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
+    Tune t = get_tune(op == RTM_OP_MODEL ? 0 : 1);
+    *vec = t.vec;
+    *zseg = t.zseg;
     return RTM_OK;
 }
 

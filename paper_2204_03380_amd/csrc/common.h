@@ -17,11 +17,17 @@ constexpr int kMaxNodes = 8;
 // Number of XCDs on MI355X; workgroups are dispatched to them round robin.
 constexpr int kNumXcd = 8;
 
+// Tiles march down z in groups of kZUnroll rows (the length of the register
+// queue), so the stored rows are rounded up to a multiple of it.
+constexpr int kZUnroll = 9;
+
 // Storage of one wavefield-sized array with a zero halo of kRadius cells on
-// every side of the padded grid.  Cell (z, y, x) of the padded grid lives at
-// org + z * plane + y * pitch + x.
+// every side of the padded grid (and, below it, up to kZUnroll - 1 further
+// zero rows so that every tile marches a multiple of kZUnroll rows).  Cell
+// (z, y, x) of the padded grid lives at org + z * plane + y * pitch + x.
 struct Layout {
     int NX, NY, NZ;   // padded extents (NY = 1 in 2-D)
+    int NZr;          // NZ rounded up to a multiple of kZUnroll
     int ndim;
     int64_t pitch;    // floats per stored row
     int64_t plane;    // floats per stored z-plane (== pitch in 2-D)
@@ -36,6 +42,7 @@ inline Layout make_layout(int ndim, int NX, int NY, int NZ)
     L.NX = NX;
     L.NY = (ndim == 3) ? NY : 1;
     L.NZ = NZ;
+    L.NZr = (NZ + kZUnroll - 1) / kZUnroll * kZUnroll;
     // Loads reach column kXOff + NX + 6 at most: a lane starting at or below
     // cell NX + 3 reads up to 4 floats, and the right strip halo likewise.
     int64_t row = kXOff + NX + 2 * kRadius;
@@ -47,7 +54,7 @@ inline Layout make_layout(int ndim, int NX, int NY, int NZ)
         L.plane = L.pitch;
         L.org = kRadius * L.pitch + kXOff;
     }
-    L.total = (int64_t)(NZ + 2 * kRadius) * L.plane;
+    L.total = (int64_t)(L.NZr + 2 * kRadius) * L.plane;
     return L;
 }
 
@@ -70,9 +77,10 @@ struct ShotDev {
 };
 
 // A 2-D stencil tile: one wavefront marches down rows [z0, z1) of a strip
-// of 64 * VEC columns starting at x0.  Injection entries of the tile are
-// ents[sbeg, send) (source, into p) and ents[rbeg, rend) (receivers, into mu),
-// sorted by row.
+// of 64 * VEC columns starting at x0; z1 - z0 is a multiple of kZUnroll
+// (rows at or below NZ are zero halo rows and stay zero).  Injection entries
+// of the tile are ents[sbeg, send) (source, into p) and ents[rbeg, rend)
+// (receivers, into mu).
 struct Tile2D {
     int shot;
     int x0, z0, z1;

@@ -4,14 +4,16 @@
 // marches down the rows [z0, z1) of its tile.  Each lane keeps the nine rows
 // z-4 .. z+4 of its VEC cells in registers (a register queue), so every
 // stored value of the input field is read from memory once per tile plus the
-// 8-row overlap with the tiles above and below.  The x-neighbours of the
-// centre row come from the adjacent lanes through DPP wave shifts; lanes 0
-// and 63 supply the 4-cell halo at the strip ends from one extra load.
+// 8-row overlap with the tiles above and below.  The march is unrolled by
+// nine so that the queue rotates by register renaming, not by moves.  The
+// x-neighbours of the centre row come from the adjacent lanes through DPP
+// wave shifts; lanes 0 and 63 supply the 4-cell halo at the strip ends with
+// one extra load.
 //
-// The stencil is evaluated as a sum of differences,
-//   L p_i = sum_axis sum_{m=1..4} c_m ((p_{i+m} - p_i) + (p_{i-m} - p_i)),
-// which is algebraically the 8th-order Laplacian of Sec. 3 but annihilates
-// constants exactly in FP32: the rounded weights then cannot add a spurious
+// The stencil is evaluated as
+//   L p_i = sum_axis sum_{m=1..4} c_m ((p_{i+m} + p_{i-m}) - 2 p_i),
+// algebraically the 8th-order Laplacian of Sec. 3, but exactly zero on a
+// constant field in FP32: the rounded weights then cannot add a spurious
 // mass term, which would otherwise accumulate into a phase error of ~1e-3
 // after a few thousand steps.
 //
@@ -28,6 +30,16 @@ constexpr float kC2 = -0.2f;
 constexpr float kC3 = 8.0f / 315.0f;
 constexpr float kC4 = -1.0f / 560.0f;
 
+// Global-address-space views: plain global loads and stores instead of
+// flat ones (which would also count against the scalar-memory wait).
+typedef __attribute__((address_space(1))) float gfloat;
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) f2v gf2v;
+typedef __attribute__((address_space(1))) f4v gf4v;
+__device__ __forceinline__ gfloat *gp(float *p) { return (gfloat *)p; }
+__device__ __forceinline__ const gfloat *gp(const float *p) { return (const gfloat *)p; }
+
 __device__ __forceinline__ float dpp_shr1(float old, float src)
 {
     // wave_shr:1 - lane i receives lane i-1; lane 0 keeps `old`.
@@ -43,13 +55,13 @@ __device__ __forceinline__ float dpp_shl1(float old, float src)
 }
 
 template <int VEC>
-__device__ __forceinline__ void ldv(const float *p, float (&v)[VEC])
+__device__ __forceinline__ void ldv(const gfloat *p, float (&v)[VEC])
 {
     if constexpr (VEC == 4) {
-        float4 t = *reinterpret_cast<const float4 *>(p);
+        const f4v t = *(const gf4v *)p;
         v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
     } else if constexpr (VEC == 2) {
-        float2 t = *reinterpret_cast<const float2 *>(p);
+        const f2v t = *(const gf2v *)p;
         v[0] = t.x; v[1] = t.y;
     } else {
         v[0] = *p;
@@ -57,26 +69,26 @@ __device__ __forceinline__ void ldv(const float *p, float (&v)[VEC])
 }
 
 template <int VEC>
-__device__ __forceinline__ void stv(float *p, const float (&v)[VEC])
+__device__ __forceinline__ void stv(gfloat *p, const float (&v)[VEC])
 {
     if constexpr (VEC == 4) {
-        *reinterpret_cast<float4 *>(p) = make_float4(v[0], v[1], v[2], v[3]);
+        *(gf4v *)p = f4v{v[0], v[1], v[2], v[3]};
     } else if constexpr (VEC == 2) {
-        *reinterpret_cast<float2 *>(p) = make_float2(v[0], v[1]);
+        *(gf2v *)p = f2v{v[0], v[1]};
     } else {
         *p = v[0];
     }
 }
 
-// Unscaled 8th-order second difference along one direction from the
-// neighbours at -4..4 (a[4] is the centre), in difference form.
-__device__ __forceinline__ float d2_diff(float c, float m1, float p1, float m2, float p2, float m3, float p3,
-                                         float m4, float p4)
+// Unscaled 8th-order second difference along one direction: c2 = 2 p_i,
+// (m_k, p_k) the neighbours at distance k.
+__device__ __forceinline__ float d2(float c2, float m1, float p1, float m2, float p2, float m3, float p3, float m4,
+                                    float p4)
 {
-    float s = kC1 * ((p1 - c) + (m1 - c));
-    s = fmaf(kC2, (p2 - c) + (m2 - c), s);
-    s = fmaf(kC3, (p3 - c) + (m3 - c), s);
-    s = fmaf(kC4, (p4 - c) + (m4 - c), s);
+    float s = kC1 * ((p1 + m1) - c2);
+    s = fmaf(kC2, (p2 + m2) - c2, s);
+    s = fmaf(kC3, (p3 + m3) - c2, s);
+    s = fmaf(kC4, (p4 + m4) - c2, s);
     return s;
 }
 
@@ -108,45 +120,19 @@ __device__ __forceinline__ void exchange_row(const float (&c)[VEC], const float 
     }
 }
 
-// Loads the strip-end halo of one row: lane 0 the 4 cells left of the
-// strip, lane 63 the 4 cells right of it (zeros past the stored columns).
+// Strip-end halo of one row: lane 0 loads the 4 cells left of the strip,
+// lane 63 the 4 cells right of it (zeros past the stored columns); one load
+// instruction for both.
 template <int VEC>
-__device__ __forceinline__ void load_halo(const float *row, int x0, int NX, int lane, float (&hl)[4], float (&hr)[4])
+__device__ __forceinline__ void load_halo(const gfloat *row, int x0, int NX, int lane, float (&hl)[4],
+                                          float (&hr)[4])
 {
-    hl[0] = hl[1] = hl[2] = hl[3] = 0.f;
-    hr[0] = hr[1] = hr[2] = hr[3] = 0.f;
-    if (lane == 0) {
-        float4 t = *reinterpret_cast<const float4 *>(row + x0 - 4);
-        hl[0] = t.x; hl[1] = t.y; hl[2] = t.z; hl[3] = t.w;
-    } else if (lane == 63) {
-        int xr = x0 + 64 * VEC;
-        if (xr < NX + kRadius) {
-            float4 t = *reinterpret_cast<const float4 *>(row + xr);
-            hr[0] = t.x; hr[1] = t.y; hr[2] = t.z; hr[3] = t.w;
-        }
-    }
-}
-
-// Weighted signal sum of the injection nodes of this lane's cells in row z.
-// `e` walks the row-sorted entries [e, eend); `sig` is indexed by each
-// contribution's signal index.  Adds into add[0..VEC).
-template <int VEC>
-__device__ __forceinline__ void gather_inj(int &e, int eend, int z, int x, const InjEnt *__restrict__ ents,
-                                           const Contrib *__restrict__ cont, const float *__restrict__ sig,
-                                           float (&add)[VEC])
-{
-    while (e < eend && ents[e].z == z) {
-        const InjEnt E = ents[e];
-        int j = E.x - x;
-        if (j >= 0 && j < VEC) {
-            float s = 0.f;
-            for (int c = E.cbeg; c < E.cend; ++c) s = fmaf(cont[c].w, sig[cont[c].idx], s);
-#pragma unroll
-            for (int jj = 0; jj < VEC; ++jj)
-                if (jj == j) add[jj] += s;
-        }
-        ++e;
-    }
+    const int xr = x0 + 64 * VEC;
+    const bool left = lane == 0, right = lane == 63 && xr < NX + kRadius;
+    f4v t = f4v{0.f, 0.f, 0.f, 0.f};
+    if (left || right) t = *(const gf4v *)(row + (left ? x0 - 4 : xr));
+    hl[0] = left ? t.x : 0.f; hl[1] = left ? t.y : 0.f; hl[2] = left ? t.z : 0.f; hl[3] = left ? t.w : 0.f;
+    hr[0] = right ? t.x : 0.f; hr[1] = right ? t.y : 0.f; hr[2] = right ? t.z : 0.f; hr[3] = right ? t.w : 0.f;
 }
 
 // Receivers [r0, r0 + 64) of one shot: d[n][r] = sum_q w_q p^n[node_q].
@@ -155,7 +141,7 @@ __device__ __forceinline__ void sample_body(const ShotDev *__restrict__ shots, S
     const ShotDev &S = shots[task.shot];
     int r = task.r0 + (int)threadIdx.x;
     if (r >= S.nrec) return;
-    const float *p = S.fld[n & 1] + S.L.org;
+    const gfloat *p = gp(S.fld[n & 1] + S.L.org);
     float s = 0.f;
 #pragma unroll
     for (int q = 0; q < kMaxNodes; ++q) {
@@ -163,13 +149,163 @@ __device__ __forceinline__ void sample_body(const ShotDev *__restrict__ shots, S
         int off = S.rnode[r * kMaxNodes + q];
         s = fmaf(w, p[off], s);
     }
-    S.rec_out[(int64_t)n * S.nrec + r] = s;
+    gp(S.rec_out)[(int64_t)n * S.nrec + r] = s;
 }
+
+// Weighted signal sum of one injection entry.
+__device__ __forceinline__ float inj_sum(const InjEnt &E, const Contrib *__restrict__ cont, const float *sig)
+{
+    float s = 0.f;
+    for (int c = E.cbeg; c < E.cend; ++c) s = fmaf(cont[c].w, sig[cont[c].idx], s);
+    return s;
+}
+
+// Does this lane own padded column x of a strip starting at x0?
+template <int VEC>
+__device__ __forceinline__ bool owns(int x, int x0, int lane)
+{
+    return x >= x0 + lane * VEC && x < x0 + (lane + 1) * VEC;
+}
+
+// --------------------------------------------------------------------------
+// Forward step
+// --------------------------------------------------------------------------
+
+template <int VEC>
+struct FwdCtx {
+    const gfloat *pc;  // p^n
+    gfloat *po;        // p^{n-1}, overwritten by p^{n+1}
+    const gfloat *Dp;
+    int64_t pitch;
+    int x, x0, NX, lane;
+    bool live, own;
+};
+
+// Row z of the march.  Queue slot (S + i) % 9 holds row z - 4 + i; the slot
+// of row z + 4 is refilled here.
+template <int VEC, int S>
+__device__ __forceinline__ void fwd_row(const FwdCtx<VEC> &C, float (&q)[9][VEC], int z)
+{
+    constexpr int r0 = (S + 0) % 9, r1 = (S + 1) % 9, r2 = (S + 2) % 9, r3 = (S + 3) % 9, r4 = (S + 4) % 9,
+                  r5 = (S + 5) % 9, r6 = (S + 6) % 9, r7 = (S + 7) % 9, r8 = (S + 8) % 9;
+    const int64_t o = (int64_t)z * C.pitch + C.x;
+    float old[VEC], d[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) q[r8][j] = old[j] = d[j] = 0.f;
+    if (C.live) {
+        ldv<VEC>(C.pc + o + 4 * C.pitch, q[r8]);
+        ldv<VEC>(C.po + o, old);
+        ldv<VEC>(C.Dp + o, d);
+    }
+    float hl[4], hr[4], ext[VEC + 8];
+    load_halo<VEC>(C.pc + (int64_t)z * C.pitch, C.x0, C.NX, C.lane, hl, hr);
+    exchange_row<VEC>(q[r4], hl, hr, ext);
+    float out[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const float c = q[r4][j], c2 = c + c;
+        float lap = d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
+        lap += d2(c2, q[r3][j], q[r5][j], q[r2][j], q[r6][j], q[r1][j], q[r7][j], q[r0][j], q[r8][j]);
+        out[j] = fmaf(d[j], lap, c2 - old[j]);
+    }
+    if (C.own) stv<VEC>(C.po + o, out);
+}
+
+// --------------------------------------------------------------------------
+// Reverse step
+// --------------------------------------------------------------------------
+
+template <int VEC>
+struct RevCtx {
+    const gfloat *P0;  // p^k
+    gfloat *P1;        // p^{k+1} -> p^{k-1}
+    const gfloat *M0;  // mu^{k+1}
+    gfloat *M1;        // mu^{k+2} -> mu^k
+    const gfloat *Dp;
+    gfloat *A0, *A1;   // num, den | G
+    int64_t pitch;
+    int x, x0, NX, lane, iz0, iz1;
+    bool live, own, own_img, reinject;
+};
+
+template <int VEC, bool GRAD, int S>
+__device__ __forceinline__ void rev_row(const RevCtx<VEC> &C, float (&qp)[9][VEC], float (&qm)[9][VEC], int z)
+{
+    constexpr int r0 = (S + 0) % 9, r1 = (S + 1) % 9, r2 = (S + 2) % 9, r3 = (S + 3) % 9, r4 = (S + 4) % 9,
+                  r5 = (S + 5) % 9, r6 = (S + 6) % 9, r7 = (S + 7) % 9, r8 = (S + 8) % 9;
+    const int64_t o = (int64_t)z * C.pitch + C.x;
+    float p1[VEC], m1[VEC], d[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) qp[r8][j] = qm[r8][j] = p1[j] = m1[j] = d[j] = 0.f;
+    if (C.live) {
+        ldv<VEC>(C.P0 + o + 4 * C.pitch, qp[r8]);
+        ldv<VEC>(C.M0 + o + 4 * C.pitch, qm[r8]);
+        ldv<VEC>(C.P1 + o, p1);
+        ldv<VEC>(C.M1 + o, m1);
+        ldv<VEC>(C.Dp + o, d);
+    }
+    float hl[4], hr[4], ext[VEC + 8];
+    float np[VEC], nm[VEC], inc[VEC];
+    load_halo<VEC>(C.P0 + (int64_t)z * C.pitch, C.x0, C.NX, C.lane, hl, hr);
+    exchange_row<VEC>(qp[r4], hl, hr, ext);
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const float c = qp[r4][j], c2 = c + c;
+        float lap = d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
+        lap += d2(c2, qp[r3][j], qp[r5][j], qp[r2][j], qp[r6][j], qp[r1][j], qp[r7][j], qp[r0][j], qp[r8][j]);
+        inc[j] = d[j] * lap;
+        np[j] = inc[j] + (c2 - p1[j]);
+    }
+    if (C.own) stv<VEC>(C.P1 + o, np);
+    load_halo<VEC>(C.M0 + (int64_t)z * C.pitch, C.x0, C.NX, C.lane, hl, hr);
+    exchange_row<VEC>(qm[r4], hl, hr, ext);
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const float c = qm[r4][j], c2 = c + c;
+        float lap = d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
+        lap += d2(c2, qm[r3][j], qm[r5][j], qm[r2][j], qm[r6][j], qm[r1][j], qm[r7][j], qm[r0][j], qm[r8][j]);
+        nm[j] = fmaf(d[j], lap, c2 - m1[j]);
+    }
+    if (C.own) stv<VEC>(C.M1 + o, nm);
+    if constexpr (GRAD) {
+        if (C.own) {
+            float g[VEC];
+            ldv<VEC>(C.A0 + o, g);
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) g[j] = fmaf(qm[r4][j], inc[j], g[j]);
+            stv<VEC>(C.A0 + o, g);
+        }
+    } else {
+        if (z >= C.iz0 && z < C.iz1 && C.own_img) {
+            float a[VEC], b[VEC];
+            ldv<VEC>(C.A0 + o, a);
+            ldv<VEC>(C.A1 + o, b);
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                a[j] = fmaf(qp[r4][j], qm[r4][j], a[j]);
+                b[j] = fmaf(qp[r4][j], qp[r4][j], b[j]);
+            }
+            stv<VEC>(C.A0 + o, a);
+            stv<VEC>(C.A1 + o, b);
+        }
+    }
+}
+
+// Runs ROWCALL(S, z) over the tile's rows, nine per trip (z1 - z0 is a
+// multiple of nine), so that S = (z - z0) mod 9 is a compile-time constant.
+#define RTM_MARCH(ROWCALL)                                                                     \
+    for (int z = T.z0; z < T.z1; z += kZUnroll) {                                              \
+        ROWCALL(0, z); ROWCALL(1, z + 1); ROWCALL(2, z + 2); ROWCALL(3, z + 3);                \
+        ROWCALL(4, z + 4); ROWCALL(5, z + 5); ROWCALL(6, z + 6); ROWCALL(7, z + 7);            \
+        ROWCALL(8, z + 8);                                                                     \
+    }
 
 }  // namespace
 
 // Forward step n of every tile:  p^{n+1} = 2 p^n - p^{n-1} + D' (L p^n + s^n),
 // written over p^{n-1}; workgroups past the stencil slots record d^n = R p^n.
+// The source term is added to the stored value after the march by the lane
+// that stored it (same thread, so program order makes the value visible).
 template <int VEC>
 __global__ __launch_bounds__(64) void fwd2d_kernel(const ShotDev *__restrict__ shots,
                                                    const Tile2D *__restrict__ tiles, int ntiles, int nslots,
@@ -177,7 +313,6 @@ __global__ __launch_bounds__(64) void fwd2d_kernel(const ShotDev *__restrict__ s
                                                    const Contrib *__restrict__ cont,
                                                    const SampleTask *__restrict__ stasks, int n)
 {
-    const int lane = threadIdx.x;
     const int b = blockIdx.x;
     if (b >= nslots) {
         sample_body(shots, stasks[b - nslots], n);
@@ -187,59 +322,36 @@ __global__ __launch_bounds__(64) void fwd2d_kernel(const ShotDev *__restrict__ s
     if (t >= ntiles) return;
     const Tile2D T = tiles[t];
     const ShotDev &S = shots[T.shot];
-    const int64_t pitch = S.L.pitch;
-    const int NX = S.L.NX;
-    const float *__restrict__ pc = S.fld[n & 1] + S.L.org;
-    float *__restrict__ po = S.fld[(n + 1) & 1] + S.L.org;
-    const float *__restrict__ Dp = S.Dp + S.L.org;
-    const float *__restrict__ wav = S.wav + n;
-
-    const int x = T.x0 + lane * VEC;
-    const bool live = x < NX + kRadius;
-    const bool own = x < NX;
+    FwdCtx<VEC> C;
+    C.pitch = S.L.pitch;
+    C.NX = S.L.NX;
+    C.pc = gp(S.fld[n & 1] + S.L.org);
+    C.po = gp(S.fld[(n + 1) & 1] + S.L.org);
+    C.Dp = gp(S.Dp + S.L.org);
+    C.lane = threadIdx.x;
+    C.x0 = T.x0;
+    C.x = T.x0 + C.lane * VEC;
+    C.live = C.x < C.NX + kRadius;
+    C.own = C.x < C.NX;
 
     float q[9][VEC];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
 #pragma unroll
         for (int j = 0; j < VEC; ++j) q[i][j] = 0.f;
-        if (live) ldv<VEC>(pc + (int64_t)(T.z0 - 4 + i) * pitch + x, q[i]);
+        if (C.live) ldv<VEC>(C.pc + (int64_t)(T.z0 - 4 + i) * C.pitch + C.x, q[i]);
     }
-    int es = T.sbeg;
-    for (int z = T.z0; z < T.z1; ++z) {
-        const float *row = pc + (int64_t)z * pitch;
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) q[8][j] = 0.f;
-        float old[VEC], d[VEC];
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) old[j] = d[j] = 0.f;
-        if (live) {
-            ldv<VEC>(pc + (int64_t)(z + 4) * pitch + x, q[8]);
-            ldv<VEC>(po + (int64_t)z * pitch + x, old);
-            ldv<VEC>(Dp + (int64_t)z * pitch + x, d);
+#define RTM_FWD_ROW(SS, ZZ) fwd_row<VEC, SS>(C, q, ZZ)
+    RTM_MARCH(RTM_FWD_ROW)
+#undef RTM_FWD_ROW
+    // Source injection: p^{n+1} += D' s^n at the source nodes of this tile.
+    const float *wav = S.wav + n;
+    for (int e = T.sbeg; e < T.send; ++e) {
+        const InjEnt E = ents[e];
+        if (owns<VEC>(E.x, T.x0, C.lane)) {
+            const int64_t o = (int64_t)E.z * C.pitch + E.x;
+            C.po[o] = fmaf(C.Dp[o], inj_sum(E, cont, wav), C.po[o]);
         }
-        float hl[4], hr[4];
-        load_halo<VEC>(row, T.x0, NX, lane, hl, hr);
-        float ext[VEC + 8];
-        exchange_row<VEC>(q[4], hl, hr, ext);
-        float add[VEC];
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) add[j] = 0.f;
-        gather_inj<VEC>(es, T.send, z, x, ents, cont, wav, add);
-        float out[VEC];
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            const float c = q[4][j];
-            float lap = d2_diff(c, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j],
-                                ext[8 + j]);
-            lap += d2_diff(c, q[3][j], q[5][j], q[2][j], q[6][j], q[1][j], q[7][j], q[0][j], q[8][j]);
-            out[j] = fmaf(d[j], lap + add[j], 2.f * c - old[j]);
-        }
-        if (own) stv<VEC>(po + (int64_t)z * pitch + x, out);
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) q[i][j] = q[i + 1][j];
     }
 }
 
@@ -249,9 +361,10 @@ __global__ __launch_bounds__(64) void fwd2d_kernel(const ShotDev *__restrict__ s
 // and either the imaging sums num += p^k mu^{k+1}, den += (p^k)^2 on the
 // interior (GRAD = false) or the gradient sum G += mu^{k+1} D' (L p^k + s^k)
 // on the whole padded grid (GRAD = true).  With reinject = 0 the source term
-// is left out of the reconstruction (Eq. (6) as written).  When wadj is
-// non-null, the lane owning each source node writes its coefficient times
-// mu^{k+1} to wadj[k * kMaxNodes + node] for the wavelet adjoint.
+// is left out of the reconstruction (Eq. (6) as written).  The source and
+// receiver terms are added after the march by the lanes that stored the
+// cells.  When wadj is non-null, those lanes also write each source node's
+// coefficient times mu^{k+1} to wadj[k * kMaxNodes + node].
 template <int VEC, bool GRAD>
 __global__ __launch_bounds__(64) void rev2d_kernel(const ShotDev *__restrict__ shots,
                                                    const Tile2D *__restrict__ tiles, int ntiles, int nslots,
@@ -259,136 +372,69 @@ __global__ __launch_bounds__(64) void rev2d_kernel(const ShotDev *__restrict__ s
                                                    const Contrib *__restrict__ cont, int k, int reinject,
                                                    float *__restrict__ wadj)
 {
-    const int lane = threadIdx.x;
     const int t = xcd_tile(blockIdx.x, nslots);
     if (t >= ntiles) return;
     const Tile2D T = tiles[t];
     const ShotDev &S = shots[T.shot];
-    const int64_t pitch = S.L.pitch;
-    const int NX = S.L.NX;
-    const float *__restrict__ P0 = S.fld[k & 1] + S.L.org;            // p^k
-    float *__restrict__ P1 = S.fld[(k + 1) & 1] + S.L.org;            // p^{k+1} -> p^{k-1}
-    const float *__restrict__ M0 = S.fld[2 + ((k + 1) & 1)] + S.L.org;  // mu^{k+1}
-    float *__restrict__ M1 = S.fld[2 + (k & 1)] + S.L.org;            // mu^{k+2} -> mu^k
-    const float *__restrict__ Dp = S.Dp + S.L.org;
-    float *__restrict__ A0 = S.acc0 + S.L.org;
-    float *__restrict__ A1 = GRAD ? nullptr : S.acc1 + S.L.org;
-    const float *__restrict__ wav = S.wav + k;
-    const float *__restrict__ sig = S.sig + (int64_t)k * S.nrec;
-
-    const int x = T.x0 + lane * VEC;
-    const bool live = x < NX + kRadius;
-    const bool own = x < NX;
+    RevCtx<VEC> C;
+    C.pitch = S.L.pitch;
+    C.NX = S.L.NX;
+    C.P0 = gp(S.fld[k & 1] + S.L.org);
+    C.P1 = gp(S.fld[(k + 1) & 1] + S.L.org);
+    C.M0 = gp(S.fld[2 + ((k + 1) & 1)] + S.L.org);
+    C.M1 = gp(S.fld[2 + (k & 1)] + S.L.org);
+    C.Dp = gp(S.Dp + S.L.org);
+    C.A0 = gp(S.acc0 + S.L.org);
+    C.A1 = GRAD ? nullptr : gp(S.acc1 + S.L.org);
+    C.lane = threadIdx.x;
+    C.x0 = T.x0;
+    C.x = T.x0 + C.lane * VEC;
+    C.live = C.x < C.NX + kRadius;
+    C.own = C.x < C.NX;
     // Lanes whose cells overlap the interior accumulate the image sums (their
     // other cells lie in the band or halo, whose sums are never read).
-    const bool own_img = own && x + VEC > S.ix0 && x < S.ix1;
+    C.own_img = C.own && C.x + VEC > S.ix0 && C.x < S.ix1;
+    C.iz0 = S.iz0;
+    C.iz1 = S.iz1;
+    C.reinject = reinject != 0;
 
     float qp[9][VEC], qm[9][VEC];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
 #pragma unroll
         for (int j = 0; j < VEC; ++j) qp[i][j] = qm[i][j] = 0.f;
-        if (live) {
-            ldv<VEC>(P0 + (int64_t)(T.z0 - 4 + i) * pitch + x, qp[i]);
-            ldv<VEC>(M0 + (int64_t)(T.z0 - 4 + i) * pitch + x, qm[i]);
+        if (C.live) {
+            ldv<VEC>(C.P0 + (int64_t)(T.z0 - 4 + i) * C.pitch + C.x, qp[i]);
+            ldv<VEC>(C.M0 + (int64_t)(T.z0 - 4 + i) * C.pitch + C.x, qm[i]);
         }
     }
-    int es = T.sbeg, er = T.rbeg;
-    for (int z = T.z0; z < T.z1; ++z) {
-        const int64_t o = (int64_t)z * pitch + x;
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) qp[8][j] = qm[8][j] = 0.f;
-        float p1[VEC], m1[VEC], d[VEC];
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) p1[j] = m1[j] = d[j] = 0.f;
-        if (live) {
-            ldv<VEC>(P0 + o + 4 * pitch, qp[8]);
-            ldv<VEC>(M0 + o + 4 * pitch, qm[8]);
-            ldv<VEC>(P1 + o, p1);
-            ldv<VEC>(M1 + o, m1);
-            ldv<VEC>(Dp + o, d);
-        }
-        float hl[4], hr[4], ext_p[VEC + 8], ext_m[VEC + 8];
-        load_halo<VEC>(P0 + (int64_t)z * pitch, T.x0, NX, lane, hl, hr);
-        exchange_row<VEC>(qp[4], hl, hr, ext_p);
-        load_halo<VEC>(M0 + (int64_t)z * pitch, T.x0, NX, lane, hl, hr);
-        exchange_row<VEC>(qm[4], hl, hr, ext_m);
-
-        float sadd[VEC], radd[VEC];
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) sadd[j] = radd[j] = 0.f;
-        if (wadj) {
-            // Source nodes of this row: record coefficient * mu^{k+1}.
-            while (es < T.send && ents[es].z == z) {
-                const InjEnt E = ents[es];
-                int j = E.x - x;
-                if (j >= 0 && j < VEC) {
-                    float s = 0.f, mval = 0.f;
-                    for (int c = E.cbeg; c < E.cend; ++c) s = fmaf(cont[c].w, wav[0], s);
-#pragma unroll
-                    for (int jj = 0; jj < VEC; ++jj)
-                        if (jj == j) {
-                            sadd[jj] += s;
-                            mval = qm[4][jj];
-                        }
-                    float wsum = 0.f;
-                    for (int c = E.cbeg; c < E.cend; ++c) wsum += cont[c].w;
-                    wadj[(int64_t)k * kMaxNodes + E.slot] = wsum * mval;
-                }
-                ++es;
+#define RTM_REV_ROW(SS, ZZ) rev_row<VEC, GRAD, SS>(C, qp, qm, ZZ)
+    RTM_MARCH(RTM_REV_ROW)
+#undef RTM_REV_ROW
+    // Source term at step k: reconstruction (re-injection), gradient, wavelet adjoint.
+    const float *wav = S.wav + k;
+    for (int e = T.sbeg; e < T.send; ++e) {
+        const InjEnt E = ents[e];
+        if (owns<VEC>(E.x, T.x0, C.lane)) {
+            const int64_t o = (int64_t)E.z * C.pitch + E.x;
+            const float ds = C.Dp[o] * inj_sum(E, cont, wav);
+            if (C.reinject) C.P1[o] = C.P1[o] + ds;
+            if (GRAD) C.A0[o] = fmaf(C.M0[o], ds, C.A0[o]);
+            if (wadj) {
+                float wsum = 0.f;
+                for (int c = E.cbeg; c < E.cend; ++c) wsum += cont[c].w;
+                wadj[(int64_t)k * kMaxNodes + E.slot] = wsum * C.M0[o];
             }
-        } else {
-            gather_inj<VEC>(es, T.send, z, x, ents, cont, wav, sadd);
         }
-        gather_inj<VEC>(er, T.rend, z, x, ents, cont, sig, radd);
-
-        float np[VEC], nm[VEC];
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) {
-            const float c = qp[4][j];
-            float lap = d2_diff(c, ext_p[3 + j], ext_p[5 + j], ext_p[2 + j], ext_p[6 + j], ext_p[1 + j],
-                                ext_p[7 + j], ext_p[j], ext_p[8 + j]);
-            lap += d2_diff(c, qp[3][j], qp[5][j], qp[2][j], qp[6][j], qp[1][j], qp[7][j], qp[0][j], qp[8][j]);
-            const float inc = d[j] * (lap + sadd[j]);
-            np[j] = (reinject ? inc : d[j] * lap) + (2.f * c - p1[j]);
-            const float cm = qm[4][j];
-            float lapm = d2_diff(cm, ext_m[3 + j], ext_m[5 + j], ext_m[2 + j], ext_m[6 + j], ext_m[1 + j],
-                                 ext_m[7 + j], ext_m[j], ext_m[8 + j]);
-            lapm += d2_diff(cm, qm[3][j], qm[5][j], qm[2][j], qm[6][j], qm[1][j], qm[7][j], qm[0][j], qm[8][j]);
-            nm[j] = fmaf(d[j], lapm + radd[j], 2.f * cm - m1[j]);
-            if (GRAD) sadd[j] = inc;  // reuse: second time difference of p at step k
+    }
+    // Receiver term: mu^k += D' R^T g^k.
+    const float *sig = S.sig + (int64_t)k * S.nrec;
+    for (int e = T.rbeg; e < T.rend; ++e) {
+        const InjEnt E = ents[e];
+        if (owns<VEC>(E.x, T.x0, C.lane)) {
+            const int64_t o = (int64_t)E.z * C.pitch + E.x;
+            C.M1[o] = fmaf(C.Dp[o], inj_sum(E, cont, sig), C.M1[o]);
         }
-        if (own) {
-            stv<VEC>(P1 + o, np);
-            stv<VEC>(M1 + o, nm);
-        }
-        if (GRAD) {
-            if (own) {
-                float g[VEC];
-                ldv<VEC>(A0 + o, g);
-#pragma unroll
-                for (int j = 0; j < VEC; ++j) g[j] = fmaf(qm[4][j], sadd[j], g[j]);
-                stv<VEC>(A0 + o, g);
-            }
-        } else if (z >= S.iz0 && z < S.iz1 && own_img) {
-            float a[VEC], bb[VEC];
-            ldv<VEC>(A0 + o, a);
-            ldv<VEC>(A1 + o, bb);
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                a[j] = fmaf(qp[4][j], qm[4][j], a[j]);
-                bb[j] = fmaf(qp[4][j], qp[4][j], bb[j]);
-            }
-            stv<VEC>(A0 + o, a);
-            stv<VEC>(A1 + o, bb);
-        }
-#pragma unroll
-        for (int i = 0; i < 8; ++i)
-#pragma unroll
-            for (int j = 0; j < VEC; ++j) {
-                qp[i][j] = qp[i + 1][j];
-                qm[i][j] = qm[i + 1][j];
-            }
     }
 }
 

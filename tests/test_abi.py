@@ -48,7 +48,9 @@ def test_set_tuning_validation():
         rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 3, 16)
     with pytest.raises(rtm.RtmError):
         rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 2)
-    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 16)
+    with pytest.raises(rtm.RtmError):
+        rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 16)   # not a multiple of 9
+    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 18)
 
 
 def _call_model(grid, nt=10, src=(5.0, 0.0, 3.0), rec=((1.0, 0.0, 2.0),), ws_bytes=None, ws=0x100000,

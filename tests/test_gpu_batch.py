@@ -42,8 +42,8 @@ def _uneven_shots(nshot=4, nt=160, seed=21):
 
 
 def test_batch_model_rtm_vjp_equal_single_shots():
-    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 16)
-    rtm.rtm_set_tuning(rtm.RTM_OP_RTM, 2, 8)
+    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 18)
+    rtm.rtm_set_tuning(rtm.RTM_OP_RTM, 2, 9)
     shots, nt = _uneven_shots()
     dt = 1e-3
     w = _t(synth.ricker(20.0, dt, nt))
@@ -87,8 +87,8 @@ def test_batch_stack_same_grid_and_graph_replay():
     """Shots on one model stacked into one image (Algorithm 3's stacking);
     the hipGraph replay equals the eager run on every replay, with eager
     work and synchronisation between replays."""
-    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 16)
-    rtm.rtm_set_tuning(rtm.RTM_OP_RTM, 1, 16)
+    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 18)
+    rtm.rtm_set_tuning(rtm.RTM_OP_RTM, 1, 18)
     s = synth.config_small2d(nx=97, nz=45, nb=10, nt=170)
     g = rtm.Grid.for_model(s.v_int, s.h, s.nb)
     vp = rtm.rtm_rbc_pad(g, _t(s.v_int), s.seed, 0.0)

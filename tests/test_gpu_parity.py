@@ -53,8 +53,8 @@ def _setup(s):
 
 @pytest.fixture(autouse=True)
 def _default_tuning():
-    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 16)
-    rtm.rtm_set_tuning(rtm.RTM_OP_RTM, 1, 16)
+    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 18)
+    rtm.rtm_set_tuning(rtm.RTM_OP_RTM, 1, 18)
     yield
 
 
@@ -177,12 +177,14 @@ def test_tuning_invariance():
     w = _t(s.wavelet)
     d_obs = _t(oracle.model_shot(vo, s.h, s.nb, s.dt, s.wavelet.astype(np.float64), s.src[0], s.rec))
     outs = []
-    for vec, zseg in ((1, 16), (2, 8), (4, 5), (1, 4), (4, 64)):
+    rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
+    for vec, zseg in ((1, 18), (2, 9), (4, 27), (1, 9), (4, 63)):
         rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, vec, zseg)
         rtm.rtm_set_tuning(rtm.RTM_OP_RTM, vec, zseg)
         tr = _n(rtm.rtm_model_shot(g, vg, s.dt, w, s.src[0], s.rec))
         im = _n(rtm.rtm_rtm_shot(g, vg, s.dt, w, s.src[0], s.rec, d_obs)["image"])
         outs.append((tr, im))
+    rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 0, 0)
     for tr, im in outs[1:]:
         assert np.array_equal(tr, outs[0][0]) and np.array_equal(im, outs[0][1])
 
