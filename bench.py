@@ -29,9 +29,10 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--shots-per-step", type=int, default=16)
+    ap.add_argument("--shots-per-step", type=int, default=48,
+                    help="shots per step; 5 steps of 48 cover the 240-shot survey once")
     ap.add_argument("--plain-shots", type=int, default=2, help="shots timed through the plain per-shot calls")
     ap.add_argument("--vec", type=int, default=0, help="floats per lane of both propagation kernels (0: tuned)")
     ap.add_argument("--zseg", type=int, default=0, help="rows per tile of both kernels, a multiple of 9 (0: tuned)")

@@ -83,9 +83,9 @@ struct Tune {
     int zseg;
 };
 
-// Defaults from a sweep on 16 shots of the 2301 x 751 folded grid.
+// Defaults from sweeps over 16-64 shots of the 2301 x 751 folded grid.
 std::atomic<int> g_tune2d_fwd{(4 << 16) | 36};
-std::atomic<int> g_tune2d_rev{(2 << 16) | 63};
+std::atomic<int> g_tune2d_rev{(1 << 16) | 9};
 std::atomic<int> g_tune_exact{0};  // 1: never narrow the configured shapes
 
 Tune get_tune(int which)

@@ -68,6 +68,47 @@ __device__ __forceinline__ void ldv(const gfloat *p, float (&v)[VEC])
     }
 }
 
+// Streams read or written once per step: non-temporal hints (RTM_NT_STREAMS).
+#ifndef RTM_NT_STREAMS
+#define RTM_NT_STREAMS 0
+#endif
+template <int VEC>
+__device__ __forceinline__ void ldv_s(const gfloat *p, float (&v)[VEC])
+{
+#if RTM_NT_STREAMS
+    if constexpr (VEC == 4) {
+        const f4v t = __builtin_nontemporal_load((const gf4v *)p);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else if constexpr (VEC == 2) {
+        const f2v t = __builtin_nontemporal_load((const gf2v *)p);
+        v[0] = t.x; v[1] = t.y;
+    } else {
+        v[0] = __builtin_nontemporal_load(p);
+    }
+#else
+    ldv<VEC>(p, v);
+#endif
+}
+
+template <int VEC>
+__device__ __forceinline__ void stv(gfloat *p, const float (&v)[VEC]);
+
+template <int VEC>
+__device__ __forceinline__ void stv_s(gfloat *p, const float (&v)[VEC])
+{
+#if RTM_NT_STREAMS
+    if constexpr (VEC == 4) {
+        __builtin_nontemporal_store(f4v{v[0], v[1], v[2], v[3]}, (gf4v *)p);
+    } else if constexpr (VEC == 2) {
+        __builtin_nontemporal_store(f2v{v[0], v[1]}, (gf2v *)p);
+    } else {
+        __builtin_nontemporal_store(v[0], p);
+    }
+#else
+    stv<VEC>(p, v);
+#endif
+}
+
 template <int VEC>
 __device__ __forceinline__ void stv(gfloat *p, const float (&v)[VEC])
 {
@@ -240,9 +281,9 @@ __device__ __forceinline__ void rev_row(const RevCtx<VEC> &C, float (&qp)[9][VEC
     if (C.live) {
         ldv<VEC>(C.P0 + o + 4 * C.pitch, qp[r8]);
         ldv<VEC>(C.M0 + o + 4 * C.pitch, qm[r8]);
-        ldv<VEC>(C.P1 + o, p1);
-        ldv<VEC>(C.M1 + o, m1);
-        ldv<VEC>(C.Dp + o, d);
+        ldv_s<VEC>(C.P1 + o, p1);
+        ldv_s<VEC>(C.M1 + o, m1);
+        ldv_s<VEC>(C.Dp + o, d);
     }
     float hl[4], hr[4], ext[VEC + 8];
     float np[VEC], nm[VEC], inc[VEC];
@@ -278,15 +319,15 @@ __device__ __forceinline__ void rev_row(const RevCtx<VEC> &C, float (&qp)[9][VEC
     } else {
         if (z >= C.iz0 && z < C.iz1 && C.own_img) {
             float a[VEC], b[VEC];
-            ldv<VEC>(C.A0 + o, a);
-            ldv<VEC>(C.A1 + o, b);
+            ldv_s<VEC>(C.A0 + o, a);
+            ldv_s<VEC>(C.A1 + o, b);
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
                 a[j] = fmaf(qp[r4][j], qm[r4][j], a[j]);
                 b[j] = fmaf(qp[r4][j], qp[r4][j], b[j]);
             }
-            stv<VEC>(C.A0 + o, a);
-            stv<VEC>(C.A1 + o, b);
+            stv_s<VEC>(C.A0 + o, a);
+            stv_s<VEC>(C.A1 + o, b);
         }
     }
 }
@@ -365,8 +406,12 @@ __global__ __launch_bounds__(64) void fwd2d_kernel(const ShotDev *__restrict__ s
 // receiver terms are added after the march by the lanes that stored the
 // cells.  When wadj is non-null, those lanes also write each source node's
 // coefficient times mu^{k+1} to wadj[k * kMaxNodes + node].
+// With one float per lane the reverse kernel fits in 64 registers; asking
+// for 8 waves per SIMD then hides more latency (measured: 4.5 vs 4.2 TB/s
+// on 16 shots of the 2301 x 751 grid).  Wider lanes would spill.
 template <int VEC, bool GRAD>
-__global__ __launch_bounds__(64) void rev2d_kernel(const ShotDev *__restrict__ shots,
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VEC == 1 ? 8 : 1, 8)))
+void rev2d_kernel(const ShotDev *__restrict__ shots,
                                                    const Tile2D *__restrict__ tiles, int ntiles, int nslots,
                                                    const InjEnt *__restrict__ ents,
                                                    const Contrib *__restrict__ cont, int k, int reinject,
