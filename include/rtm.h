@@ -121,6 +121,12 @@ int rtm_set_tuning(int op, int vec, int zseg);
 /* Current launch shape for `op` (same selection as rtm_set_tuning). */
 int rtm_get_tuning(int op, int *vec, int *zseg);
 
+/* Launch shape of the 3-D kernels: vec floats per lane (x strips of
+ * 64 * vec cells), ty in {4, 8} wavefronts per workgroup (rows in y), zseg
+ * planes per tile (a multiple of 9).  Same rules as rtm_set_tuning. */
+int rtm_set_tuning3d(int op, int vec, int ty, int zseg);
+int rtm_get_tuning3d(int op, int *vec, int *ty, int *zseg);
+
 /* Event timing of the time loops, for measurement.  While enabled, every
  * propagation call records a HIP event pair on its stream around each of
  * its time loops (no host synchronisation is added).  rtm_timing_read waits

@@ -19,7 +19,7 @@ from ._lib import (RTM_F_ACCUMULATE, RTM_F_GRAPH, RTM_F_NO_REINJECT, RTM_F_SKIP_
                    RTM_OP_RBC_PAD, RTM_OP_RTM, RTM_OP_VJP, RTM_TUNE_EXACT, RtmError)
 
 __all__ = [
-    "Grid", "RtmError", "rtm_workspace_bytes", "rtm_set_tuning", "rtm_get_tuning", "rtm_timing_enable", "rtm_timing_read", "rtm_rbc_pad", "rtm_pad_adjoint",
+    "Grid", "RtmError", "rtm_workspace_bytes", "rtm_set_tuning", "rtm_get_tuning", "rtm_set_tuning3d", "rtm_get_tuning3d", "rtm_timing_enable", "rtm_timing_read", "rtm_rbc_pad", "rtm_pad_adjoint",
     "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "RTM_F_SKIP_CHECK", "RTM_F_NO_REINJECT",
     "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD", "RTM_F_ACCUMULATE", "RTM_F_GRAPH", "RTM_TUNE_EXACT",
     "BatchShot", "BatchPlan",
@@ -97,6 +97,17 @@ def _workspace(grid: Grid, op: int, nrec: int, nt: int, device) -> torch.Tensor:
 
 def rtm_set_tuning(op: int, vec: int, zseg: int) -> None:
     _lib.check(_lib.load().rtm_set_tuning(op, vec, zseg))
+
+
+def rtm_set_tuning3d(op: int, vec: int, ty: int, zseg: int) -> None:
+    _lib.check(_lib.load().rtm_set_tuning3d(op, vec, ty, zseg))
+
+
+def rtm_get_tuning3d(op: int):
+    """(vec, ty, zseg) currently used for `op` on 3-D grids."""
+    v, y, z = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    _lib.check(_lib.load().rtm_get_tuning3d(op, ctypes.byref(v), ctypes.byref(y), ctypes.byref(z)))
+    return int(v.value), int(y.value), int(z.value)
 
 
 def rtm_get_tuning(op: int):

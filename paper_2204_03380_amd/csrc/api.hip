@@ -25,6 +25,12 @@ hipError_t launch_fwd2d(int vec, const ShotDev *shots, const Tile2D *tiles, int 
                         hipStream_t st);
 hipError_t launch_rev2d(int vec, bool grad, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                         const InjEnt *ents, const Contrib *cont, int k, int reinject, float *wadj, hipStream_t st);
+// prop3d.hip
+hipError_t launch_fwd3d(int vec, int ty, const ShotDev *shots, const Tile3D *tiles, int ntiles, int nslots,
+                        const InjEnt *ents, const Contrib *cont, const SampleTask *stasks, int nsample, int n,
+                        hipStream_t st);
+hipError_t launch_rev3d(int vec, int ty, bool grad, const ShotDev *shots, const Tile3D *tiles, int ntiles, int nslots,
+                        const InjEnt *ents, const Contrib *cont, int k, int reinject, float *wadj, hipStream_t st);
 // aux.hip
 hipError_t launch_vrange(const float *v, int64_t n, unsigned *maxmin2, hipStream_t st);
 hipError_t launch_vmax(const float *v, int64_t n, unsigned *out, hipStream_t st);
@@ -81,6 +87,7 @@ int fail(int code, const char *fmt, ...)
 struct Tune {
     int vec;
     int zseg;
+    int ty;  // 3-D: wavefronts (y rows) per workgroup
 };
 
 // Defaults from sweeps over 16-64 shots of the 2301 x 751 folded grid.
@@ -88,10 +95,18 @@ std::atomic<int> g_tune2d_fwd{(4 << 16) | 36};
 std::atomic<int> g_tune2d_rev{(1 << 16) | 9};
 std::atomic<int> g_tune_exact{0};  // 1: never narrow the configured shapes
 
-Tune get_tune(int which)
+// 3-D shapes: (vec << 24) | (ty << 16) | zseg.
+std::atomic<int> g_tune3d_fwd{(2 << 24) | (8 << 16) | 36};
+std::atomic<int> g_tune3d_rev{(1 << 24) | (8 << 16) | 36};
+
+Tune get_tune(int which, int ndim)
 {
+    if (ndim == 3) {
+        int v = (which == 0 ? g_tune3d_fwd : g_tune3d_rev).load();
+        return Tune{v >> 24, v & 0xffff, (v >> 16) & 0xff};
+    }
     int v = (which == 0 ? g_tune2d_fwd : g_tune2d_rev).load();
-    return Tune{v >> 16, v & 0xffff};
+    return Tune{v >> 16, v & 0xffff, 1};
 }
 
 constexpr int kMinZseg = kZUnroll;
@@ -238,11 +253,14 @@ struct ShotIn {
 // Tiles and injection entries of one launch shape.  ents holds all source
 // entries of all shots, then all receiver entries (when present).
 struct Tiling {
-    Tune tune{1, 16};
-    std::vector<Tile2D> tiles;
+    Tune tune{1, 18, 1};
+    int ndim = 2;
+    std::vector<Tile2D> tiles;   // 2-D jobs
+    std::vector<Tile3D> tiles3;  // 3-D jobs
     std::vector<InjEnt> ents;
     std::vector<Contrib> cont;
     int nsrc_ent = 0, nrec_ent = 0, nslots = 0;
+    int count() const { return ndim == 3 ? (int)tiles3.size() : (int)tiles.size(); }
 };
 
 struct Counts {
@@ -300,10 +318,10 @@ WsLayout make_ws_layout(const Job &J, const Counts &c)
     const int nslot = (int)J.slot_shot.size();
     w.scal = take(sizeof(unsigned) * (64 + 2 * (size_t)nslot + (size_t)nsh));
     w.shots = take(sizeof(ShotDev) * nsh);
-    w.tiles_f = take(sizeof(Tile2D) * c.tiles_f);
+    w.tiles_f = take(sizeof(Tile3D) * c.tiles_f);
     w.ents_f = take(sizeof(InjEnt) * c.ents_f);
     w.cont_f = take(sizeof(Contrib) * c.cont_f);
-    w.tiles_r = take(sizeof(Tile2D) * c.tiles_r);
+    w.tiles_r = take(sizeof(Tile3D) * c.tiles_r);
     w.ents_r = take(sizeof(InjEnt) * c.ents_r);
     w.cont_r = take(sizeof(Contrib) * c.cont_r);
     w.stasks = take(sizeof(SampleTask) * c.stasks);
@@ -328,7 +346,8 @@ WsLayout make_ws_layout(const Job &J, const Counts &c)
 
 int max_tiles(const GridInfo &g)
 {
-    return (int)(((int64_t)(g.NX + 63) / 64) * (g.L.NZr / kMinZseg));
+    const int64_t ny = g.ndim == 3 ? (g.NY + 3) / 4 : 1;
+    return (int)(((int64_t)(g.NX + 63) / 64) * ny * (g.L.NZr / kMinZseg));
 }
 
 struct RawEnt {
@@ -341,27 +360,44 @@ struct RawEnt {
 int build_tiling(Job &J, Tiling &T, bool with_receivers)
 {
     T.tiles.clear();
+    T.tiles3.clear();
     T.ents.clear();
     T.cont.clear();
     std::vector<RawEnt> se, re;
     const int strip = 64 * T.tune.vec;
+    const int ty = T.ndim == 3 ? T.tune.ty : 1;
     for (int s = 0; s < (int)J.shots.size(); ++s) {
         const ShotIn &S = J.shots[s];
         const GridInfo &g = S.g;
-        const int ns = (g.NX + strip - 1) / strip;
         const int NZr = g.L.NZr;
+        const int ns = (g.NX + strip - 1) / strip;
+        const int nys = T.ndim == 3 ? (g.NY + ty - 1) / ty : 1;
         const int nzs = (NZr + T.tune.zseg - 1) / T.tune.zseg;
-        const int tbase = (int)T.tiles.size();
+        const int tbase = T.count();
         for (int xs = 0; xs < ns; ++xs)
-            for (int zs = 0; zs < nzs; ++zs) {
-                Tile2D t{};
-                t.shot = s;
-                t.x0 = xs * strip;
-                t.z0 = zs * T.tune.zseg;
-                t.z1 = std::min(t.z0 + T.tune.zseg, NZr);
-                T.tiles.push_back(t);
-            }
-        auto tile_of = [&](int z, int x) { return tbase + (x / strip) * nzs + z / T.tune.zseg; };
+            for (int ys = 0; ys < nys; ++ys)
+                for (int zs = 0; zs < nzs; ++zs) {
+                    const int z0 = zs * T.tune.zseg, z1 = std::min(z0 + T.tune.zseg, NZr);
+                    if (T.ndim == 3) {
+                        Tile3D t{};
+                        t.shot = s;
+                        t.x0 = xs * strip;
+                        t.y0 = ys * ty;
+                        t.z0 = z0;
+                        t.z1 = z1;
+                        T.tiles3.push_back(t);
+                    } else {
+                        Tile2D t{};
+                        t.shot = s;
+                        t.x0 = xs * strip;
+                        t.z0 = z0;
+                        t.z1 = z1;
+                        T.tiles.push_back(t);
+                    }
+                }
+        auto tile_of = [&](int z, int y, int x) {
+            return tbase + ((x / strip) * nys + (T.ndim == 3 ? y / ty : 0)) * nzs + z / T.tune.zseg;
+        };
         PointOp sp;
         if (!make_point(g, S.src, &sp))
             return fail(RTM_ERANGE, "shot %d: source (%g, %g, %g) outside the interior", s, S.src[0], S.src[1],
@@ -369,7 +405,7 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
         const double hd = std::pow(g.h, g.ndim);
         const double h2 = g.h * g.h;
         for (int q = 0; q < sp.n; ++q) {
-            RawEnt e{tile_of(sp.z[q], sp.x[q]), sp.z[q], sp.y[q], sp.x[q], {}, q, s};
+            RawEnt e{tile_of(sp.z[q], sp.y[q], sp.x[q]), sp.z[q], sp.y[q], sp.x[q], {}, q, s};
             // D (B w) = D' (h^2 W / h^d) w with D' = (v dt / h)^2.
             e.c.push_back(Contrib{0, (float)(sp.w[q] * h2 / hd)});
             se.push_back(e);
@@ -385,7 +421,7 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
                 auto it = node_of.find(key);
                 if (it == node_of.end()) {
                     it = node_of.emplace(key, re.size()).first;
-                    re.push_back(RawEnt{tile_of(rp.z[q], rp.x[q]), rp.z[q], rp.y[q], rp.x[q], {}, 0, s});
+                    re.push_back(RawEnt{tile_of(rp.z[q], rp.y[q], rp.x[q]), rp.z[q], rp.y[q], rp.x[q], {}, 0, s});
                 }
                 // D R^T g = D' h^2 W g.
                 re[it->second].c.push_back(Contrib{r, (float)(rp.w[q] * h2)});
@@ -398,6 +434,7 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
     std::sort(se.begin(), se.end(), order);
     std::sort(re.begin(), re.end(), order);
     for (auto &t : T.tiles) t.sbeg = t.send = t.rbeg = t.rend = 0;
+    for (auto &t : T.tiles3) t.sbeg = t.send = t.rbeg = t.rend = 0;
     auto emit = [&](std::vector<RawEnt> &v, bool is_src) {
         for (auto &e : v) {
             InjEnt E{e.z, e.y, e.x, (int)T.cont.size(), 0, e.slot, e.shot, 0};
@@ -405,13 +442,20 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
             E.cend = (int)T.cont.size();
             const int idx = (int)T.ents.size();
             T.ents.push_back(E);
-            Tile2D &t = T.tiles[e.tile];
-            if (is_src) {
-                if (t.send == t.sbeg) t.sbeg = idx;
-                t.send = idx + 1;
+            int *sb, *sn, *rb, *rn;
+            if (T.ndim == 3) {
+                Tile3D &t = T.tiles3[e.tile];
+                sb = &t.sbeg; sn = &t.send; rb = &t.rbeg; rn = &t.rend;
             } else {
-                if (t.rend == t.rbeg) t.rbeg = idx;
-                t.rend = idx + 1;
+                Tile2D &t = T.tiles[e.tile];
+                sb = &t.sbeg; sn = &t.send; rb = &t.rbeg; rn = &t.rend;
+            }
+            if (is_src) {
+                if (*sn == *sb) *sb = idx;
+                *sn = idx + 1;
+            } else {
+                if (*rn == *rb) *rb = idx;
+                *rn = idx + 1;
             }
         }
     };
@@ -419,7 +463,7 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
     T.nsrc_ent = (int)se.size();
     emit(re, false);
     T.nrec_ent = (int)re.size();
-    T.nslots = ((int)T.tiles.size() + kNumXcd - 1) / kNumXcd * kNumXcd;
+    T.nslots = (T.count() + kNumXcd - 1) / kNumXcd * kNumXcd;
     return RTM_OK;
 }
 
@@ -427,8 +471,10 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
 int64_t count_tiles(const Job &J, Tune t)
 {
     int64_t n = 0;
-    for (const ShotIn &S : J.shots)
-        n += (int64_t)((S.g.NX + 64 * t.vec - 1) / (64 * t.vec)) * ((S.g.L.NZr + t.zseg - 1) / t.zseg);
+    for (const ShotIn &S : J.shots) {
+        const int64_t ny = S.g.ndim == 3 ? (S.g.NY + t.ty - 1) / t.ty * t.ty : 1;  // wavefronts per column
+        n += (int64_t)((S.g.NX + 64 * t.vec - 1) / (64 * t.vec)) * ny * ((S.g.L.NZr + t.zseg - 1) / t.zseg);
+    }
     return n;
 }
 
@@ -443,6 +489,7 @@ Tune fit_tune(const Job &J, Tune t)
 {
     while (!g_tune_exact.load() && count_tiles(J, t) < kMinWaves) {
         if (t.zseg > kMinZseg) t.zseg = std::max(kMinZseg, t.zseg / 2 / kZUnroll * kZUnroll);
+        else if (t.ty > 4) t.ty = 4;
         else if (t.vec > 1) t.vec /= 2;
         else break;
     }
@@ -493,11 +540,13 @@ int build_job_tables(Job &J)
         }
         J.dslot.push_back(slot);
     }
-    J.fw.tune = fit_tune(J, get_tune(0));
+    const int ndim = J.shots[0].g.ndim;
+    J.fw.ndim = J.rv.ndim = ndim;
+    J.fw.tune = fit_tune(J, get_tune(0, ndim));
     int rc = build_tiling(J, J.fw, false);
     if (rc) return rc;
     if (J.op != RTM_OP_MODEL) {
-        J.rv.tune = fit_tune(J, get_tune(1));
+        J.rv.tune = fit_tune(J, get_tune(1, ndim));
         rc = build_tiling(J, J.rv, true);
         if (rc) return rc;
     }
@@ -507,10 +556,10 @@ int build_job_tables(Job &J)
 Counts exact_counts(const Job &J)
 {
     Counts c;
-    c.tiles_f = J.fw.tiles.size();
+    c.tiles_f = J.fw.count();
     c.ents_f = J.fw.ents.size();
     c.cont_f = J.fw.cont.size();
-    c.tiles_r = J.rv.tiles.size();
+    c.tiles_r = J.rv.count();
     c.ents_r = J.rv.ents.size();
     c.cont_r = J.rv.cont.size();
     c.stasks = J.stasks.size();
@@ -584,6 +633,8 @@ int job_upload_and_check(const Job &J, const Dev &D, std::vector<ShotDev> &shot_
     fill_shot_devs(J, D, shot_devs);
     if ((rc = upload(D, J.ws.shots, shot_devs, st))) return rc;
     if ((rc = upload(D, J.ws.tiles_f, J.fw.tiles, st))) return rc;
+    if ((rc = upload(D, J.ws.tiles_f, J.fw.tiles3, st))) return rc;
+    if ((rc = upload(D, J.ws.tiles_r, J.rv.tiles3, st))) return rc;
     if ((rc = upload(D, J.ws.ents_f, J.fw.ents, st))) return rc;
     if ((rc = upload(D, J.ws.cont_f, J.fw.cont, st))) return rc;
     if ((rc = upload(D, J.ws.tiles_r, J.rv.tiles, st))) return rc;
@@ -652,12 +703,17 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
         const InjEnt *ents = D.at<InjEnt>(J.ws.ents_f);
         const Contrib *cont = D.at<Contrib>(J.ws.cont_f);
         const SampleTask *stasks = D.at<SampleTask>(J.ws.stasks);
-        const int ntiles = (int)J.fw.tiles.size();
+        const int ntiles = J.fw.count();
         const int nsample = sample ? (int)J.stasks.size() : 0;
         LoopTimer timer(sample ? kLoopModelFwd : kLoopRtmFwd, nt, st, timed);
-        for (int n = 0; n < nt; ++n)
-            RTM_HIP(launch_fwd2d(J.fw.tune.vec, shots, tiles, ntiles, J.fw.nslots, ents, cont,
-                                 sample ? stasks : nullptr, nsample, n, st));
+        for (int n = 0; n < nt; ++n) {
+            if (J.fw.ndim == 3)
+                RTM_HIP(launch_fwd3d(J.fw.tune.vec, J.fw.tune.ty, shots, (const Tile3D *)tiles, ntiles, J.fw.nslots,
+                                     ents, cont, sample ? stasks : nullptr, nsample, n, st));
+            else
+                RTM_HIP(launch_fwd2d(J.fw.tune.vec, shots, tiles, ntiles, J.fw.nslots, ents, cont,
+                                     sample ? stasks : nullptr, nsample, n, st));
+        }
         timer.finish();
         if (sample) RTM_HIP(launch_sample(shots, stasks, (int)J.stasks.size(), nt, st));
     }
@@ -677,7 +733,7 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
     const InjEnt *ents = D.at<InjEnt>(J.ws.ents_r);
     const Contrib *cont = D.at<Contrib>(J.ws.cont_r);
     RTM_HIP(launch_inj_set(shots, ents, J.rv.nsrc_ent, J.rv.nsrc_ent + J.rv.nrec_ent, cont, nt, st));
-    const int ntiles = (int)J.rv.tiles.size();
+    const int ntiles = J.rv.count();
     const int reinject = (J.flags & RTM_F_NO_REINJECT) ? 0 : 1;
     const bool probing = probe && probe->snap_k >= 0;
     // wadj is recorded for a single-shot job only (its kernel argument is one
@@ -685,8 +741,12 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
     float *wadj = (grad && nsh == 1 && J.shots[0].grad_wavelet) ? D.at<float>(J.ws.wadj[0]) : nullptr;
     LoopTimer timer(grad ? kLoopRevGrad : kLoopRevImage, nt, st, timed && !probing);
     for (int k = nt - 1; k >= 0; --k) {
-        RTM_HIP(launch_rev2d(J.rv.tune.vec, grad, shots, tiles, ntiles, J.rv.nslots, ents, cont, k, reinject, wadj,
-                             st));
+        if (J.rv.ndim == 3)
+            RTM_HIP(launch_rev3d(J.rv.tune.vec, J.rv.tune.ty, grad, shots, (const Tile3D *)tiles, ntiles, J.rv.nslots,
+                                 ents, cont, k, reinject, wadj, st));
+        else
+            RTM_HIP(launch_rev2d(J.rv.tune.vec, grad, shots, tiles, ntiles, J.rv.nslots, ents, cont, k, reinject,
+                                 wadj, st));
         if (probing) {
             const ShotIn &S = J.shots[0];
             if (k - 1 == probe->snap_k && probe->snap_p)
@@ -736,7 +796,6 @@ int check_common(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t 
 {
     int rc = grid_info(grid, g);
     if (rc) return rc;
-    if (g->ndim != 2) return fail(RTM_EINVAL, "3-D propagation is not available in this build");
     if (!v_pad) return fail(RTM_EINVAL, "v_pad is NULL");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RTM_EINVAL, "dt must be positive and finite");
     if (nt < 1) return fail(RTM_EINVAL, "nt must be >= 1");
@@ -821,11 +880,35 @@ int rtm_set_tuning(int op, int vec, int zseg)
     return RTM_OK;
 }
 
+int rtm_set_tuning3d(int op, int vec, int ty, int zseg)
+{
+    if (vec != 1 && vec != 2 && vec != 4) return fail(RTM_EINVAL, "vec must be 1, 2 or 4");
+    if (ty != 4 && ty != 8) return fail(RTM_EINVAL, "ty must be 4 or 8");
+    if (zseg < kMinZseg || zseg > 4095 || zseg % kZUnroll != 0)
+        return fail(RTM_EINVAL, "zseg must be a multiple of %d in [%d, 4095]", kZUnroll, kMinZseg);
+    int packed = (vec << 24) | (ty << 16) | zseg;
+    if (op == RTM_OP_MODEL) g_tune3d_fwd = packed;
+    else if (op == RTM_OP_RTM || op == RTM_OP_VJP) g_tune3d_rev = packed;
+    else return fail(RTM_EINVAL, "unknown op %d", op);
+    return RTM_OK;
+}
+
+int rtm_get_tuning3d(int op, int *vec, int *ty, int *zseg)
+{
+    if (!vec || !ty || !zseg) return fail(RTM_EINVAL, "NULL output");
+    if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
+    Tune t = get_tune(op == RTM_OP_MODEL ? 0 : 1, 3);
+    *vec = t.vec;
+    *ty = t.ty;
+    *zseg = t.zseg;
+    return RTM_OK;
+}
+
 int rtm_get_tuning(int op, int *vec, int *zseg)
 {
     if (!vec || !zseg) return fail(RTM_EINVAL, "NULL output");
     if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
-    Tune t = get_tune(op == RTM_OP_MODEL ? 0 : 1);
+    Tune t = get_tune(op == RTM_OP_MODEL ? 0 : 1, 2);
     *vec = t.vec;
     *zseg = t.zseg;
     return RTM_OK;
@@ -1009,7 +1092,8 @@ int rtm_batch_plan(int op, int32_t nshots, const rtm_shot_desc_t *descs, double 
         const rtm_shot_desc_t &d = descs[s];
         ShotIn S;
         int rc = grid_info(&d.grid, &S.g);
-        if (!rc && S.g.ndim != 2) rc = fail(RTM_EINVAL, "3-D propagation is not available in this build");
+        if (!rc && s > 0 && S.g.ndim != J.shots[0].g.ndim)
+            rc = fail(RTM_EINVAL, "shot %d: all shots of a batch must have the same dimension", s);
         if (!rc && (!d.v_pad || !d.wavelet)) rc = fail(RTM_EINVAL, "shot %d: v_pad and wavelet are required", s);
         if (!rc && (d.nrec < 1 || !d.rec)) rc = fail(RTM_EINVAL, "shot %d: at least one receiver is required", s);
         if (!rc && (int64_t)(nt + 1) * d.nrec >= ((int64_t)1 << 31)) rc = fail(RTM_EINVAL, "shot %d: too many samples", s);

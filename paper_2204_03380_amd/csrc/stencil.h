@@ -1,0 +1,196 @@
+// Device helpers shared by the 2-D and 3-D propagation kernels: global
+// address-space views, vector loads and stores, DPP lane shifts, the
+// 8th-order second difference, strip halos and injection sums.
+#pragma once
+
+#include "common.h"
+
+namespace rtm {
+namespace {
+
+constexpr float kC1 = 1.6f;
+constexpr float kC2 = -0.2f;
+constexpr float kC3 = 8.0f / 315.0f;
+constexpr float kC4 = -1.0f / 560.0f;
+
+// Global-address-space views: plain global loads and stores instead of
+// flat ones (which would also count against the scalar-memory wait).
+typedef __attribute__((address_space(1))) float gfloat;
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) f2v gf2v;
+typedef __attribute__((address_space(1))) f4v gf4v;
+__device__ __forceinline__ gfloat *gp(float *p) { return (gfloat *)p; }
+__device__ __forceinline__ const gfloat *gp(const float *p) { return (const gfloat *)p; }
+
+__device__ __forceinline__ float dpp_shr1(float old, float src)
+{
+    // wave_shr:1 - lane i receives lane i-1; lane 0 keeps `old`.
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), 0x138, 0xf,
+                                                      0xf, false));
+}
+
+__device__ __forceinline__ float dpp_shl1(float old, float src)
+{
+    // wave_shl:1 - lane i receives lane i+1; lane 63 keeps `old`.
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(src), 0x130, 0xf,
+                                                      0xf, false));
+}
+
+template <int VEC>
+__device__ __forceinline__ void ldv(const gfloat *p, float (&v)[VEC])
+{
+    if constexpr (VEC == 4) {
+        const f4v t = *(const gf4v *)p;
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else if constexpr (VEC == 2) {
+        const f2v t = *(const gf2v *)p;
+        v[0] = t.x; v[1] = t.y;
+    } else {
+        v[0] = *p;
+    }
+}
+
+// Streams read or written once per step: non-temporal hints (RTM_NT_STREAMS).
+#ifndef RTM_NT_STREAMS
+#define RTM_NT_STREAMS 0
+#endif
+template <int VEC>
+__device__ __forceinline__ void ldv_s(const gfloat *p, float (&v)[VEC])
+{
+#if RTM_NT_STREAMS
+    if constexpr (VEC == 4) {
+        const f4v t = __builtin_nontemporal_load((const gf4v *)p);
+        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
+    } else if constexpr (VEC == 2) {
+        const f2v t = __builtin_nontemporal_load((const gf2v *)p);
+        v[0] = t.x; v[1] = t.y;
+    } else {
+        v[0] = __builtin_nontemporal_load(p);
+    }
+#else
+    ldv<VEC>(p, v);
+#endif
+}
+
+template <int VEC>
+__device__ __forceinline__ void stv(gfloat *p, const float (&v)[VEC]);
+
+template <int VEC>
+__device__ __forceinline__ void stv_s(gfloat *p, const float (&v)[VEC])
+{
+#if RTM_NT_STREAMS
+    if constexpr (VEC == 4) {
+        __builtin_nontemporal_store(f4v{v[0], v[1], v[2], v[3]}, (gf4v *)p);
+    } else if constexpr (VEC == 2) {
+        __builtin_nontemporal_store(f2v{v[0], v[1]}, (gf2v *)p);
+    } else {
+        __builtin_nontemporal_store(v[0], p);
+    }
+#else
+    stv<VEC>(p, v);
+#endif
+}
+
+template <int VEC>
+__device__ __forceinline__ void stv(gfloat *p, const float (&v)[VEC])
+{
+    if constexpr (VEC == 4) {
+        *(gf4v *)p = f4v{v[0], v[1], v[2], v[3]};
+    } else if constexpr (VEC == 2) {
+        *(gf2v *)p = f2v{v[0], v[1]};
+    } else {
+        *p = v[0];
+    }
+}
+
+// Unscaled 8th-order second difference along one direction: c2 = 2 p_i,
+// (m_k, p_k) the neighbours at distance k.
+__device__ __forceinline__ float d2(float c2, float m1, float p1, float m2, float p2, float m3, float p3, float m4,
+                                    float p4)
+{
+    float s = kC1 * ((p1 + m1) - c2);
+    s = fmaf(kC2, (p2 + m2) - c2, s);
+    s = fmaf(kC3, (p3 + m3) - c2, s);
+    s = fmaf(kC4, (p4 + m4) - c2, s);
+    return s;
+}
+
+// Row of 4 + VEC + 4 values around the lane's VEC centre cells, built from
+// the neighbouring lanes by DPP shifts.  hl / hr are the halo floats at the
+// strip ends (meaningful in lanes 0 and 63 only).
+template <int VEC>
+__device__ __forceinline__ void exchange_row(const float (&c)[VEC], const float (&hl)[4], const float (&hr)[4],
+                                             float (&ext)[VEC + 8])
+{
+    constexpr int K = 4 / VEC;
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) ext[4 + j] = c[j];
+    float L[VEC], Rr[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        L[j] = c[j];
+        Rr[j] = c[j];
+    }
+#pragma unroll
+    for (int k = 1; k <= K; ++k) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            L[j] = dpp_shr1(hl[4 - k * VEC + j], L[j]);
+            Rr[j] = dpp_shl1(hr[(k - 1) * VEC + j], Rr[j]);
+            ext[4 - k * VEC + j] = L[j];
+            ext[4 + VEC + (k - 1) * VEC + j] = Rr[j];
+        }
+    }
+}
+
+// Strip-end halo of one row: lane 0 loads the 4 cells left of the strip,
+// lane 63 the 4 cells right of it (zeros past the stored columns); one load
+// instruction for both.
+template <int VEC>
+__device__ __forceinline__ void load_halo(const gfloat *row, int x0, int NX, int lane, float (&hl)[4],
+                                          float (&hr)[4], bool enable = true)
+{
+    // enable = false (a row outside the stored grid): no load, zero halo.
+    const int xr = x0 + 64 * VEC;
+    const bool left = enable && lane == 0, right = enable && lane == 63 && xr < NX + kRadius;
+    f4v t = f4v{0.f, 0.f, 0.f, 0.f};
+    if (left || right) t = *(const gf4v *)(row + (left ? x0 - 4 : xr));
+    hl[0] = left ? t.x : 0.f; hl[1] = left ? t.y : 0.f; hl[2] = left ? t.z : 0.f; hl[3] = left ? t.w : 0.f;
+    hr[0] = right ? t.x : 0.f; hr[1] = right ? t.y : 0.f; hr[2] = right ? t.z : 0.f; hr[3] = right ? t.w : 0.f;
+}
+
+// Receivers [r0, r0 + 64) of one shot: d[n][r] = sum_q w_q p^n[node_q].
+__device__ __forceinline__ void sample_body(const ShotDev *__restrict__ shots, SampleTask task, int n, int lane)
+{
+    const ShotDev &S = shots[task.shot];
+    int r = task.r0 + lane;
+    if (r >= S.nrec) return;
+    const gfloat *p = gp(S.fld[n & 1] + S.L.org);
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < kMaxNodes; ++q) {
+        float w = S.rw[r * kMaxNodes + q];
+        int off = S.rnode[r * kMaxNodes + q];
+        s = fmaf(w, p[off], s);
+    }
+    gp(S.rec_out)[(int64_t)n * S.nrec + r] = s;
+}
+
+// Weighted signal sum of one injection entry.
+__device__ __forceinline__ float inj_sum(const InjEnt &E, const Contrib *__restrict__ cont, const float *sig)
+{
+    float s = 0.f;
+    for (int c = E.cbeg; c < E.cend; ++c) s = fmaf(cont[c].w, sig[cont[c].idx], s);
+    return s;
+}
+
+// Does this lane own padded column x of a strip starting at x0?
+template <int VEC>
+__device__ __forceinline__ bool owns(int x, int x0, int lane)
+{
+    return x >= x0 + lane * VEC && x < x0 + (lane + 1) * VEC;
+}
+
+}  // namespace
+}  // namespace rtm
