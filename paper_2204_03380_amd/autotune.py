@@ -17,19 +17,26 @@ from typing import Iterable, Sequence
 import torch
 
 from . import (RTM_F_SKIP_CHECK, RTM_OP_MODEL, RTM_OP_RTM, RTM_TUNE_EXACT, BatchPlan, BatchShot, Grid,
-               rtm_set_tuning, rtm_timing_enable, rtm_timing_read)
+               rtm_set_tuning, rtm_set_tuning3d, rtm_timing_enable, rtm_timing_read)
 
 DEFAULT_SHAPES = tuple((v, z) for v in (1, 2, 4) for z in (9, 18, 36, 63))
+DEFAULT_SHAPES_3D = tuple((v, y, z) for v in (1, 2, 4) for y in (4, 8) for z in (18, 36))
 
 
 def signature(grid: Grid, nshots: int) -> str:
     return f"{grid.ndim}d:{grid.nx}x{grid.ny}x{grid.nz}:nb{grid.nb}:shots{nshots}"
 
 
+def _install(shape, op):
+    if len(shape) == 3:
+        rtm_set_tuning3d(op, *shape)
+    else:
+        rtm_set_tuning(op, *shape)
+
+
 def _time_shape(shape, grid, v_pad, wavelet, srcs, rec, dt, nt_probe, reps, ws):
-    vec, zseg = shape
-    rtm_set_tuning(RTM_OP_MODEL, vec, zseg)
-    rtm_set_tuning(RTM_OP_RTM, vec, zseg)
+    _install(shape, RTM_OP_MODEL)
+    _install(shape, RTM_OP_RTM)
     dev = v_pad.device
     w = wavelet[:nt_probe].contiguous()
     nrec = len(rec)
@@ -59,34 +66,37 @@ def _time_shape(shape, grid, v_pad, wavelet, srcs, rec, dt, nt_probe, reps, ws):
 
 
 def tune_batch(grid: Grid, v_pad: torch.Tensor, wavelet: torch.Tensor, srcs: Sequence, rec, dt: float,
-               nt_probe: int = 120, reps: int = 2, shapes: Iterable = DEFAULT_SHAPES,
+               nt_probe: int = 120, reps: int = 2, shapes: Iterable = None,
                cache_path: str | None = None, verbose: bool = False) -> dict:
     """Picks and installs the fastest forward and reverse shapes for a batch
-    of shots on one grid.  Returns {"forward": (vec, zseg, us),
-    "reverse": (vec, zseg, us), "table": {...}}."""
+    of shots on one grid.  Shapes are (vec, zseg) in 2-D and (vec, ty, zseg)
+    in 3-D.  Returns {"forward": (*shape, us), "reverse": (*shape, us),
+    "table": {...}}."""
+    if shapes is None:
+        shapes = DEFAULT_SHAPES_3D if grid.ndim == 3 else DEFAULT_SHAPES
     key = signature(grid, len(srcs))
     if cache_path and os.path.exists(cache_path):
         cache = json.load(open(cache_path))
         if key in cache:
             res = cache[key]
-            rtm_set_tuning(RTM_OP_MODEL, *res["forward"][:2])
-            rtm_set_tuning(RTM_OP_RTM, *res["reverse"][:2])
+            _install(tuple(res["forward"][:-1]), RTM_OP_MODEL)
+            _install(tuple(res["reverse"][:-1]), RTM_OP_RTM)
             return res
     table = {}
     best_f = best_r = None
     rtm_set_tuning(RTM_TUNE_EXACT, 1, 0)   # time each shape as given
     for shape in shapes:
         fwd, rev, _ = _time_shape(shape, grid, v_pad, wavelet, srcs, rec, dt, nt_probe, reps, None)
-        table[f"{shape[0]}x{shape[1]}"] = (fwd, rev)
+        table["x".join(str(v) for v in shape)] = (fwd, rev)
         if verbose:
-            print(f"  vec {shape[0]} zseg {shape[1]:3d}: forward {fwd:9.2f} us  reverse {rev:9.2f} us", flush=True)
-        if best_f is None or fwd < best_f[2]:
-            best_f = (shape[0], shape[1], fwd)
-        if best_r is None or rev < best_r[2]:
-            best_r = (shape[0], shape[1], rev)
+            print(f"  shape {shape}: forward {fwd:9.2f} us  reverse {rev:9.2f} us", flush=True)
+        if best_f is None or fwd < best_f[-1]:
+            best_f = (*shape, fwd)
+        if best_r is None or rev < best_r[-1]:
+            best_r = (*shape, rev)
     rtm_set_tuning(RTM_TUNE_EXACT, 0, 0)
-    rtm_set_tuning(RTM_OP_MODEL, best_f[0], best_f[1])
-    rtm_set_tuning(RTM_OP_RTM, best_r[0], best_r[1])
+    _install(tuple(best_f[:-1]), RTM_OP_MODEL)
+    _install(tuple(best_r[:-1]), RTM_OP_RTM)
     res = {"forward": best_f, "reverse": best_r, "table": table}
     if cache_path:
         cache = json.load(open(cache_path)) if os.path.exists(cache_path) else {}

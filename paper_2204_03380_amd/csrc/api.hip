@@ -95,9 +95,10 @@ std::atomic<int> g_tune2d_fwd{(4 << 16) | 36};
 std::atomic<int> g_tune2d_rev{(1 << 16) | 9};
 std::atomic<int> g_tune_exact{0};  // 1: never narrow the configured shapes
 
-// 3-D shapes: (vec << 24) | (ty << 16) | zseg.
-std::atomic<int> g_tune3d_fwd{(2 << 24) | (8 << 16) | 36};
-std::atomic<int> g_tune3d_rev{(1 << 24) | (8 << 16) | 36};
+// 3-D shapes: (vec << 24) | (ty << 16) | zseg; defaults from a sweep on
+// the 612 x 612 x 356 padded layered-salt grid.
+std::atomic<int> g_tune3d_fwd{(2 << 24) | (8 << 16) | 18};
+std::atomic<int> g_tune3d_rev{(1 << 24) | (4 << 16) | 18};
 
 Tune get_tune(int which, int ndim)
 {

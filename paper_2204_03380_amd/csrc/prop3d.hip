@@ -22,25 +22,71 @@ struct Lds {
     float row[2][TY + 8][64 * VEC];
 };
 
-// Writes this wave's centre row and its share of the 8 y-halo rows of plane
-// z into LDS buffer `buf`.
+// Number of y-halo rows a wave loads per plane (8 halo rows over TY waves).
+template <int TY>
+constexpr int halo_per_wave() { return (8 + TY - 1) / TY; }
+
+// Everything one field needs from memory for one plane of one row, loaded
+// one plane ahead (software pipelining across the per-plane barrier).
 template <int VEC, int TY>
-__device__ __forceinline__ void lds_fill(Lds<VEC, TY> &L, int buf, int w, int lane, const float (&c)[VEC],
-                                         const gfloat *plane_z, int64_t pitch, int x, int y0, int NY, bool liveX)
+struct FieldNext {
+    float q[VEC];                         // row z + 4 of the register queue
+    float halo[halo_per_wave<TY>()][VEC];  // this wave's y-halo rows of plane z
+    f4v hv;                               // strip-end x-halo (lanes 0 and 63)
+};
+
+template <int VEC>
+struct Ctx3 {
+    int64_t pitch, plane;
+    int x, x0, y, y0, NX, NY, lane, w;
+    bool liveX, live, own, rowlive;
+};
+
+// Issues the loads of field f for plane z (queue row z + 4, y-halo rows and
+// x-halo of plane z).
+template <int VEC, int TY>
+__device__ __forceinline__ void field_prefetch(const Ctx3<VEC> &C, const gfloat *f, int z, FieldNext<VEC, TY> &nx)
+{
+    const gfloat *pz = f + (int64_t)z * C.plane;
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) nx.q[j] = 0.f;
+    if (C.live) ldv<VEC>(pz + 4 * C.plane + (int64_t)C.y * C.pitch + C.x, nx.q);
+#pragma unroll
+    for (int i = 0; i < halo_per_wave<TY>(); ++i) {
+        const int h = C.w + i * TY;
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) nx.halo[i][j] = 0.f;
+        if (h < 8) {
+            const int yh = h < 4 ? C.y0 - 4 + h : C.y0 + TY + (h - 4);
+            if (C.liveX && yh < C.NY + kRadius) ldv<VEC>(pz + (int64_t)yh * C.pitch + C.x, nx.halo[i]);
+        }
+    }
+    const int xr = C.x0 + 64 * VEC;
+    const bool left = C.rowlive && C.lane == 0, right = C.rowlive && C.lane == 63 && xr < C.NX + kRadius;
+    nx.hv = f4v{0.f, 0.f, 0.f, 0.f};
+    if (left || right) nx.hv = *(const gf4v *)(pz + (int64_t)C.y * C.pitch + (left ? C.x0 - 4 : xr));
+}
+
+// Writes the centre row (queue slot of plane z) and the y-halo rows into
+// LDS buffer `buf`; returns the x-halo split into left / right.
+template <int VEC, int TY>
+__device__ __forceinline__ void field_publish(const Ctx3<VEC> &C, Lds<VEC, TY> &L, int buf, const float (&c)[VEC],
+                                              const FieldNext<VEC, TY> &nx, float (&hl)[4], float (&hr)[4])
 {
 #pragma unroll
-    for (int j = 0; j < VEC; ++j) L.row[buf][4 + w][lane * VEC + j] = c[j];
+    for (int j = 0; j < VEC; ++j) L.row[buf][4 + C.w][C.lane * VEC + j] = c[j];
 #pragma unroll
-    for (int h = w; h < 8; h += TY) {
-        const int yh = h < 4 ? y0 - 4 + h : y0 + TY + (h - 4);
-        const int slot = h < 4 ? h : TY + 4 + (h - 4);
-        float v[VEC];
+    for (int i = 0; i < halo_per_wave<TY>(); ++i) {
+        const int h = C.w + i * TY;
+        if (h < 8) {
+            const int slot = h < 4 ? h : TY + 4 + (h - 4);
 #pragma unroll
-        for (int j = 0; j < VEC; ++j) v[j] = 0.f;
-        if (liveX && yh < NY + kRadius) ldv<VEC>(plane_z + (int64_t)yh * pitch + x, v);
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) L.row[buf][slot][lane * VEC + j] = v[j];
+            for (int j = 0; j < VEC; ++j) L.row[buf][slot][C.lane * VEC + j] = nx.halo[i][j];
+        }
     }
+    const bool left = C.lane == 0, right = C.lane == 63;
+    hl[0] = left ? nx.hv.x : 0.f; hl[1] = left ? nx.hv.y : 0.f; hl[2] = left ? nx.hv.z : 0.f; hl[3] = left ? nx.hv.w : 0.f;
+    hr[0] = right ? nx.hv.x : 0.f; hr[1] = right ? nx.hv.y : 0.f; hr[2] = right ? nx.hv.z : 0.f; hr[3] = right ? nx.hv.w : 0.f;
 }
 
 // Unscaled 3-D Laplacian of the centre cells of this wave.
@@ -65,32 +111,35 @@ __device__ __forceinline__ void lap3(const Lds<VEC, TY> &L, int buf, int w, int 
 }
 
 template <int VEC>
-struct Ctx3 {
-    int64_t pitch, plane;
-    int x, x0, y, y0, NX, NY, lane, w;
-    bool liveX, live, own;
-};
+__device__ __forceinline__ void plane_prefetch(const Ctx3<VEC> &C, const gfloat *f, int z, float (&v)[VEC])
+{
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) v[j] = 0.f;
+    if (C.live) ldv<VEC>(f + (int64_t)z * C.plane + (int64_t)C.y * C.pitch + C.x, v);
+}
 
 template <int VEC, int TY, int S>
 __device__ __forceinline__ void fwd3_plane(const Ctx3<VEC> &C, Lds<VEC, TY> &L, const gfloat *pc, gfloat *po,
-                                           const gfloat *Dp, float (&q)[9][VEC], int z, int z0)
+                                           const gfloat *Dp, float (&q)[9][VEC], FieldNext<VEC, TY> &nx,
+                                           float (&nold)[VEC], float (&nd)[VEC], int z, int z0, int z1)
 {
     constexpr int r0 = (S + 0) % 9, r1 = (S + 1) % 9, r2 = (S + 2) % 9, r3 = (S + 3) % 9, r4 = (S + 4) % 9,
                   r5 = (S + 5) % 9, r6 = (S + 6) % 9, r7 = (S + 7) % 9, r8 = (S + 8) % 9;
     const int buf = (z - z0) & 1;
-    const int64_t o = (int64_t)z * C.plane + (int64_t)C.y * C.pitch + C.x;
-    float old[VEC], d[VEC];
+    float old[VEC], d[VEC], hl[4], hr[4];
 #pragma unroll
-    for (int j = 0; j < VEC; ++j) q[r8][j] = old[j] = d[j] = 0.f;
-    if (C.live) {
-        ldv<VEC>(pc + o + 4 * C.plane, q[r8]);
-        ldv<VEC>(po + o, old);
-        ldv<VEC>(Dp + o, d);
+    for (int j = 0; j < VEC; ++j) {
+        q[r8][j] = nx.q[j];
+        old[j] = nold[j];
+        d[j] = nd[j];
     }
-    lds_fill<VEC, TY>(L, buf, C.w, C.lane, q[r4], pc + (int64_t)z * C.plane, C.pitch, C.x, C.y0, C.NY, C.liveX);
-    float hl[4], hr[4], ext[VEC + 8];
-    load_halo<VEC>(pc + (int64_t)z * C.plane + (int64_t)C.y * C.pitch, C.x0, C.NX, C.lane, hl, hr,
-                   C.y < C.NY + kRadius);
+    field_publish<VEC, TY>(C, L, buf, q[r4], nx, hl, hr);
+    if (z + 1 < z1) {
+        field_prefetch<VEC, TY>(C, pc, z + 1, nx);
+        plane_prefetch<VEC>(C, po, z + 1, nold);
+        plane_prefetch<VEC>(C, Dp, z + 1, nd);
+    }
+    float ext[VEC + 8];
     exchange_row<VEC>(q[r4], hl, hr, ext);
     __syncthreads();
     float lap[VEC], out[VEC];
@@ -100,38 +149,41 @@ __device__ __forceinline__ void fwd3_plane(const Ctx3<VEC> &C, Lds<VEC, TY> &L, 
         const float c = q[r4][j];
         out[j] = fmaf(d[j], lap[j], (c + c) - old[j]);
     }
-    if (C.own) stv<VEC>(po + o, out);
+    if (C.own) stv<VEC>(po + (int64_t)z * C.plane + (int64_t)C.y * C.pitch + C.x, out);
 }
 
 template <int VEC, int TY, bool GRAD, int S>
 __device__ __forceinline__ void rev3_plane(const Ctx3<VEC> &C, Lds<VEC, TY> &LP, Lds<VEC, TY> &LM,
                                            const gfloat *P0, gfloat *P1, const gfloat *M0, gfloat *M1,
                                            const gfloat *Dp, gfloat *A0, gfloat *A1, float (&qp)[9][VEC],
-                                           float (&qm)[9][VEC], int z, int z0, bool img_row)
+                                           float (&qm)[9][VEC], FieldNext<VEC, TY> &np_, FieldNext<VEC, TY> &nm_,
+                                           float (&np1)[VEC], float (&nm1)[VEC], float (&nd)[VEC], int z, int z0,
+                                           int z1, bool img_row)
 {
     constexpr int r0 = (S + 0) % 9, r1 = (S + 1) % 9, r2 = (S + 2) % 9, r3 = (S + 3) % 9, r4 = (S + 4) % 9,
                   r5 = (S + 5) % 9, r6 = (S + 6) % 9, r7 = (S + 7) % 9, r8 = (S + 8) % 9;
     const int buf = (z - z0) & 1;
-    const int64_t o = (int64_t)z * C.plane + (int64_t)C.y * C.pitch + C.x;
-    const int64_t ro = (int64_t)z * C.plane + (int64_t)C.y * C.pitch;
-    float p1[VEC], m1[VEC], d[VEC];
+    float p1[VEC], m1[VEC], d[VEC], hlp[4], hrp[4], hlm[4], hrm[4];
 #pragma unroll
-    for (int j = 0; j < VEC; ++j) qp[r8][j] = qm[r8][j] = p1[j] = m1[j] = d[j] = 0.f;
-    if (C.live) {
-        ldv<VEC>(P0 + o + 4 * C.plane, qp[r8]);
-        ldv<VEC>(M0 + o + 4 * C.plane, qm[r8]);
-        ldv<VEC>(P1 + o, p1);
-        ldv<VEC>(M1 + o, m1);
-        ldv<VEC>(Dp + o, d);
+    for (int j = 0; j < VEC; ++j) {
+        qp[r8][j] = np_.q[j];
+        qm[r8][j] = nm_.q[j];
+        p1[j] = np1[j];
+        m1[j] = nm1[j];
+        d[j] = nd[j];
     }
-    lds_fill<VEC, TY>(LP, buf, C.w, C.lane, qp[r4], P0 + (int64_t)z * C.plane, C.pitch, C.x, C.y0, C.NY, C.liveX);
-    lds_fill<VEC, TY>(LM, buf, C.w, C.lane, qm[r4], M0 + (int64_t)z * C.plane, C.pitch, C.x, C.y0, C.NY, C.liveX);
-    const bool rowlive = C.y < C.NY + kRadius;
-    float hl[4], hr[4], extp[VEC + 8], extm[VEC + 8];
-    load_halo<VEC>(P0 + ro, C.x0, C.NX, C.lane, hl, hr, rowlive);
-    exchange_row<VEC>(qp[r4], hl, hr, extp);
-    load_halo<VEC>(M0 + ro, C.x0, C.NX, C.lane, hl, hr, rowlive);
-    exchange_row<VEC>(qm[r4], hl, hr, extm);
+    field_publish<VEC, TY>(C, LP, buf, qp[r4], np_, hlp, hrp);
+    field_publish<VEC, TY>(C, LM, buf, qm[r4], nm_, hlm, hrm);
+    if (z + 1 < z1) {
+        field_prefetch<VEC, TY>(C, P0, z + 1, np_);
+        field_prefetch<VEC, TY>(C, M0, z + 1, nm_);
+        plane_prefetch<VEC>(C, P1, z + 1, np1);
+        plane_prefetch<VEC>(C, M1, z + 1, nm1);
+        plane_prefetch<VEC>(C, Dp, z + 1, nd);
+    }
+    float extp[VEC + 8], extm[VEC + 8];
+    exchange_row<VEC>(qp[r4], hlp, hrp, extp);
+    exchange_row<VEC>(qm[r4], hlm, hrm, extm);
     __syncthreads();
     float lp[VEC], lm[VEC];
     lap3<VEC, TY>(LP, buf, C.w, C.lane, extp, qp[r0], qp[r1], qp[r2], qp[r3], qp[r4], qp[r5], qp[r6], qp[r7], qp[r8], lp);
@@ -145,6 +197,7 @@ __device__ __forceinline__ void rev3_plane(const Ctx3<VEC> &C, Lds<VEC, TY> &LP,
         nm[j] = fmaf(d[j], lm[j], (cm + cm) - m1[j]);
     }
     if (C.own) {
+        const int64_t o = (int64_t)z * C.plane + (int64_t)C.y * C.pitch + C.x;
         stv<VEC>(P1 + o, np);
         stv<VEC>(M1 + o, nm);
         if constexpr (GRAD) {
@@ -190,7 +243,8 @@ __device__ __forceinline__ Ctx3<VEC> make_ctx3(const ShotDev &S, const Tile3D &T
     C.x = T.x0 + C.lane * VEC;
     C.y = T.y0 + C.w;
     C.liveX = C.x < C.NX + kRadius;
-    C.live = C.liveX && C.y < C.NY + kRadius;
+    C.rowlive = C.y < C.NY + kRadius;
+    C.live = C.liveX && C.rowlive;
     C.own = C.x < C.NX && C.y < C.NY;
     return C;
 }
@@ -231,12 +285,13 @@ __global__ __launch_bounds__(64 * TY) void fwd3d_kernel(const ShotDev *__restric
     const gfloat *Dp = gp(S.Dp + S.L.org);
     float q[9][VEC];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) q[i][j] = 0.f;
-        if (C.live) ldv<VEC>(pc + (int64_t)(T.z0 - 4 + i) * C.plane + (int64_t)C.y * C.pitch + C.x, q[i]);
-    }
-#define RTM_FWD3(SS, ZZ) fwd3_plane<VEC, TY, SS>(C, L, pc, po, Dp, q, ZZ, T.z0)
+    for (int i = 0; i < 8; ++i) plane_prefetch<VEC>(C, pc, T.z0 - 4 + i, q[i]);
+    FieldNext<VEC, TY> nx;
+    float nold[VEC], nd[VEC];
+    field_prefetch<VEC, TY>(C, pc, T.z0, nx);
+    plane_prefetch<VEC>(C, po, T.z0, nold);
+    plane_prefetch<VEC>(C, Dp, T.z0, nd);
+#define RTM_FWD3(SS, ZZ) fwd3_plane<VEC, TY, SS>(C, L, pc, po, Dp, q, nx, nold, nd, ZZ, T.z0, T.z1)
     RTM_MARCH3(RTM_FWD3)
 #undef RTM_FWD3
     const float *wav = S.wav + n;
@@ -274,17 +329,19 @@ __global__ __launch_bounds__(64 * TY) void rev3d_kernel(const ShotDev *__restric
     float qp[9][VEC], qm[9][VEC];
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-#pragma unroll
-        for (int j = 0; j < VEC; ++j) qp[i][j] = qm[i][j] = 0.f;
-        if (C.live) {
-            const int64_t o = (int64_t)(T.z0 - 4 + i) * C.plane + (int64_t)C.y * C.pitch + C.x;
-            ldv<VEC>(P0 + o, qp[i]);
-            ldv<VEC>(M0 + o, qm[i]);
-        }
+        plane_prefetch<VEC>(C, P0, T.z0 - 4 + i, qp[i]);
+        plane_prefetch<VEC>(C, M0, T.z0 - 4 + i, qm[i]);
     }
+    FieldNext<VEC, TY> npf, nmf;
+    float np1[VEC], nm1[VEC], nd[VEC];
+    field_prefetch<VEC, TY>(C, P0, T.z0, npf);
+    field_prefetch<VEC, TY>(C, M0, T.z0, nmf);
+    plane_prefetch<VEC>(C, P1, T.z0, np1);
+    plane_prefetch<VEC>(C, M1, T.z0, nm1);
+    plane_prefetch<VEC>(C, Dp, T.z0, nd);
 #define RTM_REV3(SS, ZZ) \
-    rev3_plane<VEC, TY, GRAD, SS>(C, LP, LM, P0, P1, M0, M1, Dp, A0, A1, qp, qm, ZZ, T.z0, \
-                                  img_lane && (ZZ) >= S.iz0 && (ZZ) < S.iz1)
+    rev3_plane<VEC, TY, GRAD, SS>(C, LP, LM, P0, P1, M0, M1, Dp, A0, A1, qp, qm, npf, nmf, np1, nm1, nd, ZZ, T.z0, \
+                                  T.z1, img_lane && (ZZ) >= S.iz0 && (ZZ) < S.iz1)
     RTM_MARCH3(RTM_REV3)
 #undef RTM_REV3
     const float *wav = S.wav + k;
