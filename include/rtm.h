@@ -272,6 +272,26 @@ int rtm_batch_run(rtm_plan_t *plan, void *ws, size_t ws_bytes, void *stream);
 /* Releases a plan (and its graph); NULL is allowed. */
 int rtm_batch_free(rtm_plan_t *plan);
 
+/* Shots of uneven aperture see windows of one wide 2-D model.  For
+ * [nz][nx_global] device arrays and 0 <= x0, x0 + width <= nx_global:
+ * rtm_window_extract copies columns [x0, x0 + width) into a dense
+ * [nz][width] window; rtm_window_accumulate adds a window back into them
+ * (the adjoint of the extraction).  Calls on one stream run in order, so
+ * accumulating overlapping windows one after another is deterministic. */
+int rtm_window_extract(int64_t nz, int64_t nx_global, int64_t x0, int64_t width, const float *global,
+                       float *window, void *stream);
+int rtm_window_accumulate(int64_t nz, int64_t nx_global, int64_t x0, int64_t width, const float *window,
+                          float *global, void *stream);
+
+/* Receiver subtraction and the L2 misfit of modeled traces: residual =
+ * d - d_obs (device [n], may be NULL) and *J = 0.5 sum residual^2 written to
+ * a device double.  The sum runs in a fixed order (per-block partials in
+ * FP64, then one block over the partials): deterministic.  ws: device,
+ * 256-byte aligned, rtm_misfit_ws_bytes bytes. */
+int rtm_misfit_ws_bytes(size_t *bytes);
+int rtm_l2_misfit(int64_t n, const float *d, const float *d_obs, float *residual, double *J, void *ws,
+                  size_t ws_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,7 @@ __all__ = [
     "Grid", "RtmError", "rtm_workspace_bytes", "rtm_set_tuning", "rtm_get_tuning", "rtm_set_tuning3d", "rtm_get_tuning3d", "rtm_timing_enable", "rtm_timing_read", "rtm_rbc_pad", "rtm_pad_adjoint",
     "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "RTM_F_SKIP_CHECK", "RTM_F_NO_REINJECT",
     "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD", "RTM_F_ACCUMULATE", "RTM_F_GRAPH", "RTM_TUNE_EXACT",
-    "BatchShot", "BatchPlan",
+    "BatchShot", "BatchPlan", "rtm_window_extract", "rtm_window_accumulate", "rtm_l2_misfit",
 ]
 
 
@@ -237,6 +237,40 @@ def rtm_model_shot_vjp(grid: Grid, v_pad: torch.Tensor, dt: float, wavelet: torc
         grad_traces.data_ptr(), gv.data_ptr(), gw.data_ptr() if want_wavelet_grad else None, int(flags),
         ws.data_ptr(), ws.numel(), _stream(dev)))
     return (gv, gw) if want_wavelet_grad else gv
+
+
+def rtm_window_extract(global_model: torch.Tensor, x0: int, width: int) -> torch.Tensor:
+    """Columns [x0, x0 + width) of a [nz][nx] device array, as a new tensor."""
+    _dev(global_model, "global_model")
+    nz, nxg = global_model.shape
+    out = torch.empty((nz, width), dtype=torch.float32, device=global_model.device)
+    _lib.check(_lib.load().rtm_window_extract(nz, nxg, int(x0), int(width), global_model.data_ptr(), out.data_ptr(),
+                                              _stream(global_model.device)))
+    return out
+
+
+def rtm_window_accumulate(global_model: torch.Tensor, x0: int, window: torch.Tensor) -> None:
+    """global_model[:, x0:x0 + w] += window, in the library's kernel."""
+    _dev(global_model, "global_model")
+    nz, nxg = global_model.shape
+    _dev(window, "window", (nz, window.shape[1]))
+    _lib.check(_lib.load().rtm_window_accumulate(nz, nxg, int(x0), int(window.shape[1]), window.data_ptr(),
+                                                 global_model.data_ptr(), _stream(global_model.device)))
+
+
+def rtm_l2_misfit(d: torch.Tensor, d_obs: torch.Tensor, want_residual: bool = True):
+    """(J, residual): J = 0.5 sum (d - d_obs)^2 as a float64 device scalar,
+    residual = d - d_obs (or None)."""
+    _dev(d, "d")
+    _dev(d_obs, "d_obs", tuple(d.shape))
+    nb = ctypes.c_size_t(0)
+    _lib.check(_lib.load().rtm_misfit_ws_bytes(ctypes.byref(nb)))
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=d.device)
+    J = torch.empty((), dtype=torch.float64, device=d.device)
+    r = torch.empty_like(d) if want_residual else None
+    _lib.check(_lib.load().rtm_l2_misfit(d.numel(), d.data_ptr(), d_obs.data_ptr(), r.data_ptr() if r is not None
+                                         else None, J.data_ptr(), ws.data_ptr(), ws.numel(), _stream(d.device)))
+    return J, r
 
 
 @dataclass

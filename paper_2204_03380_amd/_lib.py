@@ -29,7 +29,7 @@ EXPORTS = (
     "rtm_get_tuning3d", "rtm_timing_enable", "rtm_timing_read",
     "rtm_workspace_bytes", "rtm_rbc_pad",
     "rtm_pad_adjoint", "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "rtm_batch_plan", "rtm_batch_run",
-    "rtm_batch_free",
+    "rtm_batch_free", "rtm_window_extract", "rtm_window_accumulate", "rtm_misfit_ws_bytes", "rtm_l2_misfit",
 )
 
 RTM_F_ACCUMULATE = 0x4
@@ -87,6 +87,10 @@ def load():
                             ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SZ)], ctypes.c_int),
         "rtm_batch_run": ([P, P, SZ, P], ctypes.c_int),
         "rtm_batch_free": ([P], ctypes.c_int),
+        "rtm_window_extract": ([I64, I64, I64, I64, P, P, P], ctypes.c_int),
+        "rtm_misfit_ws_bytes": ([ctypes.POINTER(SZ)], ctypes.c_int),
+        "rtm_l2_misfit": ([I64, P, P, P, P, P, SZ, P], ctypes.c_int),
+        "rtm_window_accumulate": ([I64, I64, I64, I64, P, P, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

@@ -51,6 +51,10 @@ hipError_t launch_image(const ShotDev *shots, int shot, int64_t ninterior, unsig
 hipError_t launch_grad(const ShotDev *shots, int shot, int64_t npad, const float *v_pad, float dt, float *grad,
                        hipStream_t st);
 hipError_t launch_wadj(const float *parts, int nt, float scale, float *out, hipStream_t st);
+size_t misfit_ws_bytes();
+hipError_t launch_misfit(const float *d, const float *dobs, float *r, int64_t n, void *ws, double *J, hipStream_t st);
+hipError_t launch_window(float *global, const float *win_in, float *win_out, int64_t nz, int64_t nxg, int64_t x0,
+                         int64_t w, int mode, hipStream_t st);
 }  // namespace rtm
 
 using namespace rtm;
@@ -1165,6 +1169,48 @@ int rtm_batch_run(rtm_plan_t *plan, void *ws, size_t ws_bytes, void *stream)
         J.g_st = st;
     }
     RTM_HIP(hipGraphLaunch(J.gexec, st));
+    return RTM_OK;
+}
+
+int rtm_window_extract(int64_t nz, int64_t nx_global, int64_t x0, int64_t width, const float *global, float *window,
+                       void *stream)
+{
+    t_err.clear();
+    if (nz < 1 || nx_global < 1 || width < 1 || x0 < 0 || x0 + width > nx_global)
+        return fail(RTM_EINVAL, "window [%lld, %lld) outside [0, %lld)", (long long)x0, (long long)(x0 + width),
+                    (long long)nx_global);
+    if (!global || !window) return fail(RTM_EINVAL, "NULL array");
+    RTM_HIP(launch_window((float *)global, nullptr, window, nz, nx_global, x0, width, 0, (hipStream_t)stream));
+    return RTM_OK;
+}
+
+int rtm_window_accumulate(int64_t nz, int64_t nx_global, int64_t x0, int64_t width, const float *window,
+                          float *global, void *stream)
+{
+    t_err.clear();
+    if (nz < 1 || nx_global < 1 || width < 1 || x0 < 0 || x0 + width > nx_global)
+        return fail(RTM_EINVAL, "window [%lld, %lld) outside [0, %lld)", (long long)x0, (long long)(x0 + width),
+                    (long long)nx_global);
+    if (!global || !window) return fail(RTM_EINVAL, "NULL array");
+    RTM_HIP(launch_window(global, window, nullptr, nz, nx_global, x0, width, 1, (hipStream_t)stream));
+    return RTM_OK;
+}
+
+int rtm_misfit_ws_bytes(size_t *bytes)
+{
+    if (!bytes) return fail(RTM_EINVAL, "bytes is NULL");
+    *bytes = align256(misfit_ws_bytes());
+    return RTM_OK;
+}
+
+int rtm_l2_misfit(int64_t n, const float *d, const float *d_obs, float *residual, double *J, void *ws,
+                  size_t ws_bytes, void *stream)
+{
+    t_err.clear();
+    if (n < 1 || !d || !d_obs || !J) return fail(RTM_EINVAL, "bad arguments");
+    if (!ws || ws_bytes < misfit_ws_bytes() || ((uintptr_t)ws & 255))
+        return fail(RTM_EWORKSPACE, "misfit workspace of %zu aligned bytes needed", misfit_ws_bytes());
+    RTM_HIP(launch_misfit(d, d_obs, residual, n, ws, J, (hipStream_t)stream));
     return RTM_OK;
 }
 

@@ -2,6 +2,8 @@
 // preparation of the scaled velocity term, trace transposes, receiver-field
 // start, last-sample recording, image and gradient finalisation, and field
 // unpacking.  All run once per call (not per time step).
+#include <algorithm>
+
 #include "common.h"
 
 namespace rtm {
@@ -305,6 +307,61 @@ __global__ void wadj_kernel(const float *__restrict__ parts, int nt, float scale
     out[n] = s * scale;
 }
 
+// Columns [x0, x0 + w) of a [nz][nxg] array into (mode 0) or added from
+// (mode 1) a dense [nz][w] window.
+__global__ void window_kernel(float *__restrict__ global, const float *__restrict__ win_in,
+                              float *__restrict__ win_out, int64_t nz, int64_t nxg, int64_t x0, int64_t w, int mode)
+{
+    const int64_t n = nz * w;
+    for (int64_t i = gid(); i < n; i += gstride()) {
+        const int64_t z = i / w, x = i % w;
+        const int64_t g = z * nxg + x0 + x;
+        if (mode == 0) win_out[i] = global[g];
+        else global[g] += win_in[i];
+    }
+}
+
+// Residual r = d - d_obs and per-block partial sums of r^2 (fixed order
+// within a block); a second single-block pass adds the partials in order,
+// so J = 0.5 sum r^2 is deterministic.
+constexpr int kMisfitBlocks = 1024;
+
+__global__ __launch_bounds__(kBlock) void misfit_partial_kernel(const float *__restrict__ d,
+                                                                const float *__restrict__ dobs,
+                                                                float *__restrict__ r, int64_t n,
+                                                                double *__restrict__ part)
+{
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int64_t i = gid(); i < n; i += gstride()) {
+        const float v = d[i] - dobs[i];
+        if (r) r[i] = v;
+        acc += (double)v * (double)v;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
+}
+
+__global__ __launch_bounds__(kBlock) void misfit_final_kernel(const double *__restrict__ part, int nparts,
+                                                              double *__restrict__ out)
+{
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = 0.5 * sh[0];
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -417,6 +474,25 @@ hipError_t launch_grad(const ShotDev *shots, int shot, int64_t npad, const float
                        hipStream_t st)
 {
     hipLaunchKernelGGL(grad_kernel, dim3(grid_for(npad)), dim3(kBlock), 0, st, shots, shot, v_pad, dt, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_window(float *global, const float *win_in, float *win_out, int64_t nz, int64_t nxg, int64_t x0,
+                         int64_t w, int mode, hipStream_t st)
+{
+    hipLaunchKernelGGL(window_kernel, dim3(grid_for(nz * w)), dim3(kBlock), 0, st, global, win_in, win_out, nz, nxg, x0,
+                       w, mode);
+    return hipGetLastError();
+}
+
+size_t misfit_ws_bytes() { return sizeof(double) * (kMisfitBlocks + 1); }
+
+hipError_t launch_misfit(const float *d, const float *dobs, float *r, int64_t n, void *ws, double *J, hipStream_t st)
+{
+    double *part = (double *)ws;
+    const unsigned nb = std::min<int64_t>(kMisfitBlocks, std::max<int64_t>(1, (n + kBlock - 1) / kBlock));
+    hipLaunchKernelGGL(misfit_partial_kernel, dim3(nb), dim3(kBlock), 0, st, d, dobs, r, n, part);
+    hipLaunchKernelGGL(misfit_final_kernel, dim3(1), dim3(kBlock), 0, st, (const double *)part, (int)nb, J);
     return hipGetLastError();
 }
 
