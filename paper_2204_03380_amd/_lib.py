@@ -23,13 +23,16 @@ RTM_TUNE_EXACT = 0x100
 RTM_F_SKIP_CHECK = 0x1
 RTM_F_NO_REINJECT = 0x2
 
-# Every symbol declared in include/rtm.h.
+# Every symbol declared in include/rtm.h and include/unet.h.
 EXPORTS = (
     "rtm_abi_version", "rtm_last_error", "rtm_set_tuning", "rtm_get_tuning", "rtm_set_tuning3d",
     "rtm_get_tuning3d", "rtm_timing_enable", "rtm_timing_read",
     "rtm_workspace_bytes", "rtm_rbc_pad",
     "rtm_pad_adjoint", "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "rtm_batch_plan", "rtm_batch_run",
     "rtm_batch_free", "rtm_window_extract", "rtm_window_accumulate", "rtm_misfit_ws_bytes", "rtm_l2_misfit",
+    "unet_weight_pack", "unet_conv3d_fwd", "unet_conv3d_dgrad", "unet_wgrad_ws_bytes", "unet_conv3d_wgrad",
+    "unet_embed", "unet_pool2", "unet_up2", "unet_up2_bwd", "unet_relu_grad", "unet_mse_ws_bytes", "unet_mse",
+    "unet_adam",
 )
 
 RTM_F_ACCUMULATE = 0x4
@@ -46,6 +49,11 @@ class RtmShotDesc(ctypes.Structure):
                 ("src", ctypes.c_float * 3), ("nrec", ctypes.c_int32), ("rec", ctypes.c_void_p),
                 ("traces_in", ctypes.c_void_p), ("traces_out", ctypes.c_void_p), ("image", ctypes.c_void_p),
                 ("grad_v_pad", ctypes.c_void_p)]
+
+
+class UnetConvDesc(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("d", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
+                ("cin", ctypes.c_int32), ("cout", ctypes.c_int32)]
 
 
 class RtmProbe(ctypes.Structure):
@@ -67,6 +75,7 @@ def load():
     P, I32, I64, D, F, U32, U64, SZ = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
                                         ctypes.c_float, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_size_t)
     G = ctypes.POINTER(RtmGrid)
+    C = ctypes.POINTER(UnetConvDesc)
     sig = {
         "rtm_abi_version": ([], ctypes.c_int),
         "rtm_last_error": ([], ctypes.c_char_p),
@@ -91,6 +100,19 @@ def load():
         "rtm_misfit_ws_bytes": ([ctypes.POINTER(SZ)], ctypes.c_int),
         "rtm_l2_misfit": ([I64, P, P, P, P, P, SZ, P], ctypes.c_int),
         "rtm_window_accumulate": ([I64, I64, I64, I64, P, P, P], ctypes.c_int),
+        "unet_weight_pack": ([C, P, P, P, P], ctypes.c_int),
+        "unet_conv3d_fwd": ([C, P, P, P, I32, P, P, I32, P, P, P], ctypes.c_int),
+        "unet_conv3d_dgrad": ([C, P, P, P, P], ctypes.c_int),
+        "unet_wgrad_ws_bytes": ([C, ctypes.POINTER(SZ)], ctypes.c_int),
+        "unet_conv3d_wgrad": ([C, P, P, P, P, P, SZ, P], ctypes.c_int),
+        "unet_embed": ([I64, I32, P, F, P, P], ctypes.c_int),
+        "unet_pool2": ([I32] * 5 + [P, P, P], ctypes.c_int),
+        "unet_up2": ([I32] * 5 + [P, P, P], ctypes.c_int),
+        "unet_up2_bwd": ([I32] * 5 + [P, P, P], ctypes.c_int),
+        "unet_relu_grad": ([I32] * 5 + [P, P, P, P, P, P], ctypes.c_int),
+        "unet_mse_ws_bytes": ([I64, ctypes.POINTER(SZ)], ctypes.c_int),
+        "unet_mse": ([I64, I32, P, P, P, P, P, ctypes.POINTER(D), P, SZ, P], ctypes.c_int),
+        "unet_adam": ([I64, P, P, P, P, D, D, D, D, I32, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

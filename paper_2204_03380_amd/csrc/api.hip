@@ -78,6 +78,16 @@ int fail(int code, const char *fmt, ...)
     return code;
 }
 
+}  // namespace
+
+// Error state shared with the other sources of the library.
+namespace rtm {
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+void clear_error() { t_err.clear(); }
+}  // namespace rtm
+
+namespace {
+
 #define RTM_HIP(call)                                                                         \
     do {                                                                                      \
         hipError_t e_ = (call);                                                               \

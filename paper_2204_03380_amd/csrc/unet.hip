@@ -1,0 +1,857 @@
+// Kernels of the learned crosstalk filter: a 3-D U-Net on channels-last
+// bfloat16 activations.  Convolutions are implicit GEMMs on the gfx950
+// bfloat16 matrix cores (v_mfma_f32_16x16x32_bf16, float32 accumulation):
+//
+//   forward / input gradient  M = voxels, N = output channels,
+//                             K = 27 taps x input channels
+//   weight gradient           M = output channels, N = input channels,
+//                             K = voxels (one x-segment of a row at a time)
+//
+// MFMA 16x16x32 operand layout (lane l, element e): A[l % 16][8 (l / 16) + e],
+// B[8 (l / 16) + e][l % 16]; the 4 results of lane l are D[4 (l / 16) + e][l % 16].
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "common.h"
+#include "rtm.h"
+#include "unet.h"
+
+namespace rtm {
+int set_error(int code, const char *msg);
+void clear_error();
+}  // namespace rtm
+
+namespace {
+
+using rtm::kNumXcd;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// float32 -> bfloat16, round to nearest even (values here are finite).
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ f32x4 mfma16(const uint4 &a, const uint4 &b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
+// Contiguous ranges of work items per XCD (blocks are dealt to the 8 XCDs
+// round-robin): neighbouring tiles share halo rows in the same L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks)
+{
+    const int64_t per = nblocks / kNumXcd;
+    return (b % kNumXcd) * per + b / kNumXcd;
+}
+
+struct ConvArgs {
+    const uint16_t *x;
+    const uint16_t *wt;
+    const float *bias;
+    const uint16_t *skip;
+    float *y;
+    uint16_t *r;
+    uint16_t *out;
+    int64_t nvox;
+    int d, h, w;
+    int relu;
+    int ych;
+    int64_t nblocks;  // grid size (multiple of 8)
+};
+
+// ---------------------------------------------------------------------------
+// Forward convolution (and input gradient with flipped weights).  One
+// wavefront computes 64 consecutive voxels x all COUT channels; the four
+// 16-voxel row blocks share each weight fragment and each activation
+// fragment feeds COUT / 16 MFMAs.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a)
+{
+    constexpr int K = 27 * CIN;
+    constexpr int KP = (K + 31) / 32 * 32;
+    constexpr int CB = COUT / 16;
+    const int lane = threadIdx.x & 63;
+    const int r16 = lane & 15, g = lane >> 4;
+    const int64_t blk = xcd_block(blockIdx.x, a.nblocks);
+    const int64_t vb = (blk * 4 + (threadIdx.x >> 6)) * 64;
+    if (vb >= a.nvox) return;  // whole wavefront; the kernel has no barriers
+
+    const int D = a.d, H = a.h, W = a.w;
+    int vz[4], vy[4], vx[4];
+    bool vin[4];
+    int64_t vv[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int64_t v = vb + rb * 16 + r16;
+        vin[rb] = v < a.nvox;
+        vv[rb] = v;
+        int64_t t = v / W;
+        vx[rb] = (int)(v - t * W);
+        const int64_t t2 = t / H;
+        vy[rb] = (int)(t - t2 * H);
+        vz[rb] = (int)(t2 % D);
+    }
+    f32x4 acc[4][CB];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const uint4 zero = {0u, 0u, 0u, 0u};
+    const int64_t HW = (int64_t)H * W;
+#pragma unroll 2
+    for (int kc = 0; kc < KP; kc += 32) {
+        const int kk = kc + 8 * g;
+        const int tap = kk / CIN;
+        const int ci0 = kk - tap * CIN;
+        const bool tv = tap < 27;
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        const int64_t off = dz * HW + (int64_t)dy * W + dx;
+        uint4 A[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            const bool ok = tv && vin[rb] && (unsigned)(vz[rb] + dz) < (unsigned)D &&
+                            (unsigned)(vy[rb] + dy) < (unsigned)H && (unsigned)(vx[rb] + dx) < (unsigned)W;
+            A[rb] = ok ? *reinterpret_cast<const uint4 *>(a.x + (vv[rb] + off) * CIN + ci0) : zero;
+        }
+        uint4 B[CB];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+            B[cb] = tv ? *reinterpret_cast<const uint4 *>(a.wt + (int64_t)(cb * 16 + r16) * K + kk) : zero;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(A[rb], B[cb], acc[rb][cb]);
+    }
+
+    // Epilogue: lane holds voxels vb + rb*16 + 4g + e of channel cb*16 + r16.
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int co = cb * 16 + r16;
+        const float bias = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t v = vb + rb * 16 + 4 * g + e;
+                if (v >= a.nvox) continue;
+                float val = acc[rb][cb][e] + bias;
+                if (a.relu) val = fmaxf(val, 0.f);
+                if (a.y && co < a.ych) a.y[v * a.ych + co] = val;
+                const int64_t o = v * COUT + co;
+                if (a.r) a.r[o] = f2bf(val);
+                if (a.out) a.out[o] = f2bf(a.skip ? val + bf2f(a.skip[o]) : val);
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient.  Block (s, q): q = (dz, dy) neighbour-row pair, s = a
+// contiguous range of output rows (n, z, y).  For each row and each
+// 32-voxel x-segment the block stages dy^T [COUT][32] and three x-shifted
+// copies of x^T [3][CIN][32] of the source row in LDS, then every MFMA
+// reads aligned 16-byte fragments: dw[o][tap(dz,dy,dx)][i] +=
+// sum_j dy[j][o] x[j + dx - 1][i].  RS row groups of WS waves: the WS waves
+// of a group split the output channels, the groups split the rows.  Each
+// (s, group) writes its own partial sums; a second kernel adds them in a
+// fixed order.  Blocks of the centre pair also sum dy for the bias.
+// ---------------------------------------------------------------------------
+template <int CIN, int COUT>
+struct WgCfg {
+    static constexpr int CB = COUT / 16, IB = CIN / 16;
+    static constexpr int WS = CB < 4 ? CB : 4;
+    static constexpr int RS = 4 / WS;
+    static constexpr int CPW = CB / WS;
+    static constexpr int SEG = 32;
+    static constexpr int LDS_U16 = SEG * (COUT + 3 * CIN);  // per row group
+};
+
+struct WgArgs {
+    const uint16_t *x;
+    const uint16_t *dy;
+    float *part;    // [S*RS][COUT][27][CIN]
+    float *bpart;   // [S*RS][COUT]
+    int64_t rows;   // N*D*H
+    int d, h, w;
+    int S;
+};
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void conv_wgrad_kernel(WgArgs a)
+{
+    using C = WgCfg<CIN, COUT>;
+    constexpr int SEG = C::SEG;
+    __shared__ __attribute__((aligned(16))) uint16_t lds[C::RS * C::LDS_U16];
+    const int s = blockIdx.x, q = blockIdx.y;
+    const int dz = q / 3 - 1, dy = q % 3 - 1;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int rg = wave / C::WS, wi = wave % C::WS;
+    const int gt = wi * 64 + lane;  // thread index within the row group
+    const int r16 = lane & 15, g = lane >> 4;
+    uint16_t *dyT = lds + rg * C::LDS_U16;  // [COUT][SEG]
+    uint16_t *xT = dyT + COUT * SEG;        // [3][CIN][SEG]
+    const int D = a.d, H = a.h, W = a.w;
+    const int64_t r0 = a.rows * s / a.S, r1 = a.rows * (s + 1) / a.S;
+    const bool centre = (q == 4);
+
+    f32x4 acc[C::CPW][3][C::IB];
+#pragma unroll
+    for (int i = 0; i < C::CPW; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+#pragma unroll
+            for (int k = 0; k < C::IB; ++k) acc[i][j][k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+
+    for (int64_t base = r0; base < r1; base += C::RS) {
+        const int64_t r = base + rg;
+        const int64_t t = r / H;
+        const int yy = (int)(r - t * H), zz = (int)(t % D);
+        const bool act = r < r1 && (unsigned)(zz + dz) < (unsigned)D && (unsigned)(yy + dy) < (unsigned)H;
+        const int64_t src = r + (int64_t)dz * H + dy;  // source row index
+        for (int x0 = 0; x0 < W; x0 += SEG) {
+            __syncthreads();
+            if (act) {
+                // dy^T: 32 voxels x COUT channels, 8 channels per 16-byte chunk
+                for (int c = gt; c < SEG * COUT / 8; c += 64 * C::WS) {
+                    const int j = c / (COUT / 8), c0 = (c % (COUT / 8)) * 8;
+                    uint4 v = {0u, 0u, 0u, 0u};
+                    if (x0 + j < W) v = *reinterpret_cast<const uint4 *>(a.dy + ((r * W + x0 + j) * COUT + c0));
+                    const uint16_t *e = reinterpret_cast<const uint16_t *>(&v);
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) dyT[(c0 + i) * SEG + j] = e[i];
+                }
+                // x^T of the source row, voxels x0 - 1 .. x0 + 32, into the
+                // three shifted copies xT[dx][i][j] = x[x0 + j + dx - 1][i]
+                for (int c = gt; c < (SEG + 2) * CIN / 8; c += 64 * C::WS) {
+                    const int jj = c / (CIN / 8), c0 = (c % (CIN / 8)) * 8;
+                    const int xg = x0 + jj - 1;
+                    uint4 v = {0u, 0u, 0u, 0u};
+                    if (xg >= 0 && xg < W) v = *reinterpret_cast<const uint4 *>(a.x + ((src * W + xg) * CIN + c0));
+                    const uint16_t *e = reinterpret_cast<const uint16_t *>(&v);
+#pragma unroll
+                    for (int dxi = 0; dxi < 3; ++dxi) {
+                        const int j = jj - dxi;
+                        if (j < 0 || j >= SEG) continue;
+#pragma unroll
+                        for (int i = 0; i < 8; ++i) xT[(dxi * CIN + c0 + i) * SEG + j] = e[i];
+                    }
+                }
+            }
+            __syncthreads();
+            if (act) {
+#pragma unroll
+                for (int cl = 0; cl < C::CPW; ++cl) {
+                    const int co = (wi * C::CPW + cl) * 16 + r16;
+                    const uint4 A = *reinterpret_cast<const uint4 *>(dyT + co * SEG + 8 * g);
+#pragma unroll
+                    for (int dxi = 0; dxi < 3; ++dxi)
+#pragma unroll
+                        for (int ib = 0; ib < C::IB; ++ib) {
+                            const uint4 B =
+                                *reinterpret_cast<const uint4 *>(xT + (dxi * CIN + ib * 16 + r16) * SEG + 8 * g);
+                            acc[cl][dxi][ib] = mfma16(A, B, acc[cl][dxi][ib]);
+                        }
+                }
+                if (centre && gt < COUT) {
+#pragma unroll 8
+                    for (int j = 0; j < SEG; ++j) bacc += bf2f(dyT[gt * SEG + j]);
+                }
+            }
+        }
+    }
+    // Partial sums of this (s, row group): lane holds o = cb*16 + 4g + e,
+    // i = ib*16 + r16.
+    const int64_t p = (int64_t)s * C::RS + rg;
+    float *part = a.part + p * (int64_t)COUT * 27 * CIN;
+#pragma unroll
+    for (int cl = 0; cl < C::CPW; ++cl)
+#pragma unroll
+        for (int dxi = 0; dxi < 3; ++dxi)
+#pragma unroll
+            for (int ib = 0; ib < C::IB; ++ib)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int o = (wi * C::CPW + cl) * 16 + 4 * g + e;
+                    const int tap = q * 3 + dxi;
+                    part[((int64_t)o * 27 + tap) * CIN + ib * 16 + r16] = acc[cl][dxi][ib][e];
+                }
+    if (centre && gt < COUT) a.bpart[p * COUT + gt] = bacc;
+}
+
+// Fixed-order sum of P partial arrays of n floats.
+__global__ void sum_parts_kernel(const float *__restrict__ part, int64_t P, int64_t n, float *__restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float s = 0.f;
+    for (int64_t p = 0; p < P; ++p) s += part[p * n + i];
+    out[i] = s;
+}
+
+// ---------------------------------------------------------------------------
+// Element-wise and resampling kernels
+// ---------------------------------------------------------------------------
+__global__ void weight_pack_kernel(const float *__restrict__ w, int cin, int cout, uint16_t *__restrict__ wf,
+                                   uint16_t *__restrict__ wb)
+{
+    const int64_t n = (int64_t)cout * 27 * cin;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int ci = (int)(i % cin);
+    const int t = (int)((i / cin) % 27);
+    const int co = (int)(i / (27 * (int64_t)cin));
+    const uint16_t b = f2bf(w[i]);
+    if (wf) wf[i] = b;
+    if (wb) wb[(int64_t)ci * 27 * cout + (int64_t)(26 - t) * cout + co] = b;
+}
+
+__global__ void embed_kernel(int64_t nvox, int ch, const float *__restrict__ img, float scale,
+                             uint16_t *__restrict__ x)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nvox * ch) return;
+    const int64_t v = i / ch;
+    x[i] = (i - v * ch) == 0 ? f2bf(img[v] * scale) : (uint16_t)0;
+}
+
+// One thread per (coarse voxel, 8-channel group).
+__global__ void pool2_kernel(int n, int d, int h, int w, int c, const uint16_t *__restrict__ x,
+                             uint16_t *__restrict__ y)
+{
+    const int d2 = d / 2, h2 = h / 2, w2 = w / 2, cg = c / 8;
+    const int64_t total = (int64_t)n * d2 * h2 * w2 * cg;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    int64_t t = i;
+    const int gi = (int)(t % cg);
+    t /= cg;
+    const int xo = (int)(t % w2);
+    t /= w2;
+    const int yo = (int)(t % h2);
+    t /= h2;
+    const int zo = (int)(t % d2);
+    const int64_t nn = t / d2;
+    float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k = 0; k < 8; ++k) {
+        const int64_t v = ((nn * d + 2 * zo + (k >> 2)) * h + 2 * yo + ((k >> 1) & 1)) * w + 2 * xo + (k & 1);
+        const uint4 q = *reinterpret_cast<const uint4 *>(x + v * c + gi * 8);
+        const uint16_t *e = reinterpret_cast<const uint16_t *>(&q);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) s[j] += bf2f(e[j]);
+    }
+    uint4 o;
+    uint16_t *oe = reinterpret_cast<uint16_t *>(&o);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) oe[j] = f2bf(s[j] * 0.125f);
+    const int64_t vo = ((nn * d2 + zo) * h2 + yo) * w2 + xo;
+    *reinterpret_cast<uint4 *>(y + vo * c + gi * 8) = o;
+}
+
+// One thread per (fine voxel, 8-channel group): nearest-neighbour copy.
+__global__ void up2_kernel(int n, int d, int h, int w, int c, const uint16_t *__restrict__ x,
+                           uint16_t *__restrict__ y)
+{
+    const int D = 2 * d, H = 2 * h, W = 2 * w, cg = c / 8;
+    const int64_t total = (int64_t)n * D * H * W * cg;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    int64_t t = i;
+    const int gi = (int)(t % cg);
+    t /= cg;
+    const int xf = (int)(t % W);
+    t /= W;
+    const int yf = (int)(t % H);
+    t /= H;
+    const int zf = (int)(t % D);
+    const int64_t nn = t / D;
+    const int64_t vc = ((nn * d + zf / 2) * h + yf / 2) * w + xf / 2;
+    const int64_t vf = ((nn * D + zf) * H + yf) * W + xf;
+    *reinterpret_cast<uint4 *>(y + vf * c + gi * 8) = *reinterpret_cast<const uint4 *>(x + vc * c + gi * 8);
+}
+
+// One thread per (coarse voxel, channel): sum of the 8 children in a fixed order.
+__global__ void up2_bwd_kernel(int n, int d, int h, int w, int c, const float *__restrict__ gf,
+                               float *__restrict__ gc)
+{
+    const int64_t total = (int64_t)n * d * h * w * c;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    int64_t t = i;
+    const int ch = (int)(t % c);
+    t /= c;
+    const int xc = (int)(t % w);
+    t /= w;
+    const int yc = (int)(t % h);
+    t /= h;
+    const int zc = (int)(t % d);
+    const int64_t nn = t / d;
+    const int D = 2 * d, H = 2 * h, W = 2 * w;
+    float s = 0.f;
+    for (int k = 0; k < 8; ++k) {
+        const int64_t v = ((nn * D + 2 * zc + (k >> 2)) * H + 2 * yc + ((k >> 1) & 1)) * W + 2 * xc + (k & 1);
+        s += gf[v * c + ch];
+    }
+    gc[i] = s;
+}
+
+__global__ void relu_grad_kernel(int n, int d, int h, int w, int c, const float *__restrict__ g1,
+                                 const float *__restrict__ g2, const float *__restrict__ gp,
+                                 const uint16_t *__restrict__ mask, uint16_t *__restrict__ out)
+{
+    const int64_t total = (int64_t)n * d * h * w * c;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    float g = g1[i];
+    if (g2) g += g2[i];
+    if (gp) {
+        int64_t t = i;
+        const int ch = (int)(t % c);
+        t /= c;
+        const int xf = (int)(t % w);
+        t /= w;
+        const int yf = (int)(t % h);
+        t /= h;
+        const int zf = (int)(t % d);
+        const int64_t nn = t / d;
+        const int64_t vc = ((nn * (d / 2) + zf / 2) * (h / 2) + yf / 2) * (w / 2) + xf / 2;
+        g += gp[vc * c + ch] * 0.125f;
+    }
+    out[i] = bf2f(mask[i]) > 0.f ? f2bf(g) : (uint16_t)0;
+}
+
+constexpr int kMseBlocks = 1024;
+
+__global__ void mse_kernel(int64_t nvox, int ch, const float *__restrict__ img, const float *__restrict__ y,
+                           const float *__restrict__ tgt, float *__restrict__ out, uint16_t *__restrict__ gy,
+                           double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    const float gscale = 2.0f / (float)nvox;
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * blockDim.x) {
+        const float o = img[v] + y[v];
+        if (out) out[v] = o;
+        if (tgt) {
+            const float df = o - tgt[v];
+            s += (double)df * (double)df;
+            if (gy) {
+                gy[v * ch] = f2bf(gscale * df);
+                for (int k = 1; k < ch; ++k) gy[v * ch + k] = 0;
+            }
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void mse_final_kernel(const double *__restrict__ part, int nparts, int64_t nvox, double *__restrict__ loss)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += part[i];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = red[0] / (double)nvox;
+}
+
+__global__ void adam_kernel(int64_t n, float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, float lr, float b1, float b2, float omb1, float omb2, float eps,
+                            float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float vi = b2 * v[i] + omb2 * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+int bad(const char *msg) { return rtm::set_error(RTM_EINVAL, msg); }
+
+#define UNET_HIP(call)                                                        \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess) return rtm::set_error(RTM_EHIP, hipGetErrorString(e_)); \
+    } while (0)
+
+bool ch_ok(int c) { return c == 16 || c == 32 || c == 64 || c == 128; }
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+int check_desc(const unet_conv_desc_t *d)
+{
+    if (!d) return bad("desc is NULL");
+    if (d->n < 1 || d->d < 1 || d->h < 1 || d->w < 1) return bad("extents must be >= 1");
+    if (!ch_ok(d->cin) || !ch_ok(d->cout)) return bad("channel counts must be 16, 32, 64 or 128");
+    const int64_t nvox = (int64_t)d->n * d->d * d->h * d->w;
+    if (nvox * (int64_t)(d->cin > d->cout ? d->cin : d->cout) >= ((int64_t)1 << 40))
+        return bad("tensor too large");
+    return RTM_OK;
+}
+
+dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
+
+template <int CI, int CO>
+void launch_fwd_t(const ConvArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((conv_fwd_kernel<CI, CO>), dim3((unsigned)a.nblocks), dim3(256), 0, st, a);
+}
+
+template <int CI>
+int launch_fwd_ci(int co, const ConvArgs &a, hipStream_t st)
+{
+    switch (co) {
+    case 16: launch_fwd_t<CI, 16>(a, st); return 0;
+    case 32: launch_fwd_t<CI, 32>(a, st); return 0;
+    case 64: launch_fwd_t<CI, 64>(a, st); return 0;
+    case 128: launch_fwd_t<CI, 128>(a, st); return 0;
+    }
+    return -1;
+}
+
+int launch_fwd(int ci, int co, ConvArgs a, hipStream_t st)
+{
+    const int64_t waves = (a.nvox + 63) / 64;
+    const int64_t blocks = (waves + 3) / 4;
+    a.nblocks = (blocks + kNumXcd - 1) / kNumXcd * kNumXcd;
+    switch (ci) {
+    case 16: return launch_fwd_ci<16>(co, a, st);
+    case 32: return launch_fwd_ci<32>(co, a, st);
+    case 64: return launch_fwd_ci<64>(co, a, st);
+    case 128: return launch_fwd_ci<128>(co, a, st);
+    }
+    return -1;
+}
+
+constexpr int kWgMaxSplits = 64;
+
+template <int CI, int CO>
+int wg_splits(int64_t rows)
+{
+    constexpr int RS = WgCfg<CI, CO>::RS;
+    int64_t s = rows / (4 * RS);
+    if (s < 1) s = 1;
+    if (s > kWgMaxSplits) s = kWgMaxSplits;
+    return (int)s;
+}
+
+template <int CI, int CO>
+void wg_sizes(int64_t rows, int64_t *parts, int *S)
+{
+    *S = wg_splits<CI, CO>(rows);
+    *parts = (int64_t)*S * WgCfg<CI, CO>::RS;
+}
+
+template <int CI>
+int wg_sizes_ci(int co, int64_t rows, int64_t *parts, int *S)
+{
+    switch (co) {
+    case 16: wg_sizes<CI, 16>(rows, parts, S); return 0;
+    case 32: wg_sizes<CI, 32>(rows, parts, S); return 0;
+    case 64: wg_sizes<CI, 64>(rows, parts, S); return 0;
+    case 128: wg_sizes<CI, 128>(rows, parts, S); return 0;
+    }
+    return -1;
+}
+
+int wg_layout(const unet_conv_desc_t *d, int64_t *parts, int *S)
+{
+    const int64_t rows = (int64_t)d->n * d->d * d->h;
+    switch (d->cin) {
+    case 16: return wg_sizes_ci<16>(d->cout, rows, parts, S);
+    case 32: return wg_sizes_ci<32>(d->cout, rows, parts, S);
+    case 64: return wg_sizes_ci<64>(d->cout, rows, parts, S);
+    case 128: return wg_sizes_ci<128>(d->cout, rows, parts, S);
+    }
+    return -1;
+}
+
+size_t wg_bytes(const unet_conv_desc_t *d, int64_t parts)
+{
+    const size_t w = (size_t)parts * d->cout * 27 * d->cin * sizeof(float);
+    const size_t b = (size_t)parts * d->cout * sizeof(float);
+    return ((w + 255) & ~(size_t)255) + ((b + 255) & ~(size_t)255);
+}
+
+template <int CI, int CO>
+void launch_wg_t(const WgArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL((conv_wgrad_kernel<CI, CO>), dim3((unsigned)a.S, 9), dim3(256), 0, st, a);
+}
+
+template <int CI>
+int launch_wg_ci(int co, const WgArgs &a, hipStream_t st)
+{
+    switch (co) {
+    case 16: launch_wg_t<CI, 16>(a, st); return 0;
+    case 32: launch_wg_t<CI, 32>(a, st); return 0;
+    case 64: launch_wg_t<CI, 64>(a, st); return 0;
+    case 128: launch_wg_t<CI, 128>(a, st); return 0;
+    }
+    return -1;
+}
+
+int launch_wg(int ci, int co, const WgArgs &a, hipStream_t st)
+{
+    switch (ci) {
+    case 16: return launch_wg_ci<16>(co, a, st);
+    case 32: return launch_wg_ci<32>(co, a, st);
+    case 64: return launch_wg_ci<64>(co, a, st);
+    case 128: return launch_wg_ci<128>(co, a, st);
+    }
+    return -1;
+}
+
+int check_resample(int n, int d, int h, int w, int c)
+{
+    if (n < 1 || d < 1 || h < 1 || w < 1) return bad("extents must be >= 1");
+    if (c < 8 || c % 8) return bad("channels must be a positive multiple of 8");
+    return RTM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int unet_weight_pack(const unet_conv_desc_t *desc, const float *w, uint16_t *w_fwd, uint16_t *w_bwd, void *stream)
+{
+    rtm::clear_error();
+    if (int e = check_desc(desc)) return e;
+    if (!w) return bad("w is NULL");
+    const int64_t n = (int64_t)desc->cout * 27 * desc->cin;
+    hipLaunchKernelGGL(weight_pack_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, w, desc->cin, desc->cout,
+                       w_fwd, w_bwd);
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+int unet_conv3d_fwd(const unet_conv_desc_t *desc, const uint16_t *x, const uint16_t *w_fwd, const float *bias,
+                    int32_t relu, const uint16_t *skip, float *y, int32_t y_channels, uint16_t *r, uint16_t *out,
+                    void *stream)
+{
+    rtm::clear_error();
+    if (int e = check_desc(desc)) return e;
+    if (!x || !w_fwd) return bad("x and w_fwd are required");
+    if (!y && !r && !out) return bad("no output requested");
+    if (y && (y_channels < 1 || y_channels > desc->cout)) return bad("y_channels must be in [1, cout]");
+    if (skip && !out) return bad("skip needs out");
+    if (!aligned16(x) || !aligned16(w_fwd)) return bad("x and w_fwd must be 16-byte aligned");
+    ConvArgs a{};
+    a.x = x;
+    a.wt = w_fwd;
+    a.bias = bias;
+    a.skip = skip;
+    a.y = y;
+    a.r = r;
+    a.out = out;
+    a.nvox = (int64_t)desc->n * desc->d * desc->h * desc->w;
+    a.d = desc->d;
+    a.h = desc->h;
+    a.w = desc->w;
+    a.relu = relu ? 1 : 0;
+    a.ych = y ? y_channels : 0;
+    if (launch_fwd(desc->cin, desc->cout, a, (hipStream_t)stream)) return bad("unsupported channel pair");
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+int unet_conv3d_dgrad(const unet_conv_desc_t *desc, const uint16_t *dy, const uint16_t *w_bwd, float *dx,
+                      void *stream)
+{
+    rtm::clear_error();
+    if (int e = check_desc(desc)) return e;
+    if (!dy || !w_bwd || !dx) return bad("dy, w_bwd and dx are required");
+    if (!aligned16(dy) || !aligned16(w_bwd)) return bad("dy and w_bwd must be 16-byte aligned");
+    ConvArgs a{};
+    a.x = dy;
+    a.wt = w_bwd;
+    a.y = dx;
+    a.nvox = (int64_t)desc->n * desc->d * desc->h * desc->w;
+    a.d = desc->d;
+    a.h = desc->h;
+    a.w = desc->w;
+    a.ych = desc->cin;
+    if (launch_fwd(desc->cout, desc->cin, a, (hipStream_t)stream)) return bad("unsupported channel pair");
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+int unet_wgrad_ws_bytes(const unet_conv_desc_t *desc, size_t *bytes)
+{
+    rtm::clear_error();
+    if (int e = check_desc(desc)) return e;
+    if (!bytes) return bad("bytes is NULL");
+    int64_t parts;
+    int S;
+    if (wg_layout(desc, &parts, &S)) return bad("unsupported channel pair");
+    *bytes = wg_bytes(desc, parts);
+    return RTM_OK;
+}
+
+int unet_conv3d_wgrad(const unet_conv_desc_t *desc, const uint16_t *x, const uint16_t *dy, float *dw, float *db,
+                      void *ws, size_t ws_bytes, void *stream)
+{
+    rtm::clear_error();
+    if (int e = check_desc(desc)) return e;
+    if (!x || !dy || !dw) return bad("x, dy and dw are required");
+    if (!aligned16(x) || !aligned16(dy)) return bad("x and dy must be 16-byte aligned");
+    int64_t parts;
+    int S;
+    if (wg_layout(desc, &parts, &S)) return bad("unsupported channel pair");
+    if (!ws || ws_bytes < wg_bytes(desc, parts) || ((uintptr_t)ws & 255u))
+        return rtm::set_error(RTM_EWORKSPACE, "workspace missing, too small or not 256-byte aligned");
+    const int64_t nw = (int64_t)desc->cout * 27 * desc->cin;
+    WgArgs a{};
+    a.x = x;
+    a.dy = dy;
+    a.part = static_cast<float *>(ws);
+    a.bpart = reinterpret_cast<float *>(static_cast<char *>(ws) + ((nw * parts * sizeof(float) + 255) & ~(size_t)255));
+    a.rows = (int64_t)desc->n * desc->d * desc->h;
+    a.d = desc->d;
+    a.h = desc->h;
+    a.w = desc->w;
+    a.S = S;
+    hipStream_t st = (hipStream_t)stream;
+    launch_wg(desc->cin, desc->cout, a, st);
+    hipLaunchKernelGGL(sum_parts_kernel, grid1(nw), dim3(256), 0, st, a.part, parts, nw, dw);
+    if (db) hipLaunchKernelGGL(sum_parts_kernel, grid1(desc->cout), dim3(256), 0, st, a.bpart, parts,
+                               (int64_t)desc->cout, db);
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+int unet_embed(int64_t nvox, int32_t channels, const float *img, float scale, uint16_t *x, void *stream)
+{
+    rtm::clear_error();
+    if (nvox < 1 || channels < 1 || !img || !x) return bad("invalid embed arguments");
+    hipLaunchKernelGGL(embed_kernel, grid1(nvox * channels), dim3(256), 0, (hipStream_t)stream, nvox, channels, img,
+                       scale, x);
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+int unet_pool2(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const uint16_t *x, uint16_t *y, void *stream)
+{
+    rtm::clear_error();
+    if (int e = check_resample(n, d, h, w, c)) return e;
+    if ((d | h | w) & 1) return bad("pooled extents must be even");
+    if (!x || !y || !aligned16(x) || !aligned16(y)) return bad("x and y must be 16-byte aligned device pointers");
+    const int64_t total = (int64_t)n * (d / 2) * (h / 2) * (w / 2) * (c / 8);
+    hipLaunchKernelGGL(pool2_kernel, grid1(total), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c, x, y);
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+int unet_up2(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const uint16_t *x, uint16_t *y, void *stream)
+{
+    rtm::clear_error();
+    if (int e = check_resample(n, d, h, w, c)) return e;
+    if (!x || !y || !aligned16(x) || !aligned16(y)) return bad("x and y must be 16-byte aligned device pointers");
+    const int64_t total = (int64_t)n * 8 * d * h * w * (c / 8);
+    hipLaunchKernelGGL(up2_kernel, grid1(total), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c, x, y);
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+int unet_up2_bwd(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const float *g_fine, float *g_coarse,
+                 void *stream)
+{
+    rtm::clear_error();
+    if (n < 1 || d < 1 || h < 1 || w < 1 || c < 1 || !g_fine || !g_coarse) return bad("invalid up2_bwd arguments");
+    const int64_t total = (int64_t)n * d * h * w * c;
+    hipLaunchKernelGGL(up2_bwd_kernel, grid1(total), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c, g_fine,
+                       g_coarse);
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+int unet_relu_grad(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const float *g1, const float *g2,
+                   const float *g_pool, const uint16_t *mask, uint16_t *out, void *stream)
+{
+    rtm::clear_error();
+    if (n < 1 || d < 1 || h < 1 || w < 1 || c < 1 || !g1 || !mask || !out) return bad("invalid relu_grad arguments");
+    if (g_pool && ((d | h | w) & 1)) return bad("g_pool needs even extents");
+    const int64_t total = (int64_t)n * d * h * w * c;
+    hipLaunchKernelGGL(relu_grad_kernel, grid1(total), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c, g1, g2,
+                       g_pool, mask, out);
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+int unet_mse_ws_bytes(int64_t nvox, size_t *bytes)
+{
+    rtm::clear_error();
+    if (nvox < 1 || !bytes) return bad("invalid mse_ws_bytes arguments");
+    *bytes = (kMseBlocks + 1) * sizeof(double);
+    return RTM_OK;
+}
+
+int unet_mse(int64_t nvox, int32_t channels, const float *img, const float *y, const float *target, float *out,
+             uint16_t *gy, double *loss, void *ws, size_t ws_bytes, void *stream)
+{
+    rtm::clear_error();
+    if (nvox < 1 || channels < 1 || !img || !y) return bad("invalid mse arguments");
+    if ((gy || loss) && !target) return bad("gy and loss need target");
+    if (target && (!ws || ws_bytes < (kMseBlocks + 1) * sizeof(double)))
+        return rtm::set_error(RTM_EWORKSPACE, "workspace missing or too small");
+    hipStream_t st = (hipStream_t)stream;
+    double *part = static_cast<double *>(ws);
+    int nb = (int)((nvox + 255) / 256);
+    if (nb > kMseBlocks) nb = kMseBlocks;
+    hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, st, nvox, channels, img, y, target, out, gy, part);
+    if (target) {
+        hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(256), 0, st, part, nb, nvox, part + kMseBlocks);
+        if (loss) {
+            UNET_HIP(hipMemcpyAsync(loss, part + kMseBlocks, sizeof(double), hipMemcpyDeviceToHost, st));
+            UNET_HIP(hipStreamSynchronize(st));
+        }
+    }
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+int unet_adam(int64_t n, float *p, const float *g, float *m, float *v, double lr, double b1, double b2, double eps,
+              int32_t step, void *stream)
+{
+    rtm::clear_error();
+    if (n < 1 || !p || !g || !m || !v) return bad("invalid adam arguments");
+    if (step < 1 || !(b1 >= 0.0 && b1 < 1.0) || !(b2 >= 0.0 && b2 < 1.0) || !(eps > 0.0))
+        return bad("adam needs step >= 1, 0 <= b1, b2 < 1, eps > 0");
+    // 1 - b and the bias corrections are formed in double: 1 - b in float32
+    // from a float32 b (0.999 -> 0.99900001) loses 4 digits.
+    const float c1 = (float)(1.0 - std::pow(b1, step));
+    const float c2 = (float)(1.0 - std::pow(b2, step));
+    const float omb1 = (float)(1.0 - b1), omb2 = (float)(1.0 - b2);
+    hipLaunchKernelGGL(adam_kernel, grid1(n), dim3(256), 0, (hipStream_t)stream, n, p, g, m, v, (float)lr, (float)b1,
+                       (float)b2, omb1, omb2, (float)eps, c1, c2);
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+}  // extern "C"

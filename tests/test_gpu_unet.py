@@ -1,0 +1,214 @@
+"""GPU parity of the U-Net kernels against the FP64 oracle on the same
+bfloat16-quantised operands (only float32 accumulation order differs), on
+ragged extents that leave partial 64-voxel tiles and partial 32-voxel
+weight-gradient segments, and of the whole network's output and parameter
+gradients."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import unet as U
+from paper_2204_03380_amd import unet as N
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+PAIRS = ((16, 16), (16, 32), (32, 64), (64, 128), (128, 64), (64, 32), (32, 16))
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def bf_tensor(a):
+    """bfloat16 device tensor holding a (which must be bf16-representable)."""
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV).to(torch.bfloat16)
+
+
+def f32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+def to_cf(a, shape, c):
+    """channels-last (N*D*H*W, C) -> list of (C, D, H, W) per sample."""
+    n, d, h, w = shape
+    a = np.asarray(a).reshape(n, d, h, w, c)
+    return [np.transpose(a[i], (3, 0, 1, 2)) for i in range(n)]
+
+
+def from_cf(lst):
+    return np.stack([np.transpose(x, (1, 2, 3, 0)) for x in lst]).reshape(-1, lst[0].shape[0])
+
+
+def pack(w_oracle):
+    co, ci = w_oracle.shape[:2]
+    wm = f32(np.transpose(w_oracle.reshape(co, ci, 27), (0, 2, 1)))
+    wf = torch.empty((co, 27 * ci), dtype=torch.bfloat16, device=DEV)
+    wb = torch.empty((ci, 27 * co), dtype=torch.bfloat16, device=DEV)
+    N.weight_pack(wm, ci, co, wf, wb)
+    return wf, wb
+
+
+def _operands(shape, ci, co, seed):
+    rng = np.random.default_rng(seed)
+    n, d, h, w = shape
+    x = U.bf16(rng.standard_normal((n * d * h * w, ci)))
+    wo = rng.standard_normal((co, ci, 3, 3, 3)) * np.sqrt(2.0 / (27 * ci))
+    b = rng.standard_normal(co) * 0.1
+    return rng, x, wo, b
+
+
+@pytest.mark.parametrize("ci,co", PAIRS)
+def test_conv_forward_parity(ci, co):
+    shape = (2, 5, 6, 37) if ci <= 32 else (1, 5, 6, 37)
+    rng, x, wo, b = _operands(shape, ci, co, ci * 1000 + co)
+    wf, _ = pack(wo)
+    y = torch.empty((x.shape[0], co), dtype=torch.float32, device=DEV)
+    N.conv3d_fwd(shape, ci, co, bf_tensor(x), wf, f32(b), False, y=y)
+    ref = from_cf([U.conv3d(xc, U.bf16(wo), b) for xc in to_cf(x, shape, ci)])
+    e = rel_l2(host(y), ref)
+    print(f"conv fwd {ci}->{co} {shape}: rel-L2 {e:.2e}")
+    assert e < 1e-5
+    # fused epilogue: relu, stored relu value, skip-add, all rounded once
+    skip = U.bf16(rng.standard_normal(y.shape))
+    y2 = torch.empty_like(y)
+    r = torch.empty(y.shape, dtype=torch.bfloat16, device=DEV)
+    out = torch.empty_like(r)
+    N.conv3d_fwd(shape, ci, co, bf_tensor(x), wf, f32(b), True, skip=bf_tensor(skip), y=y2, r=r, out=out)
+    yg = host(y2).astype(np.float32)
+    assert np.array_equal(yg, np.maximum(host(y).astype(np.float32), 0))
+    assert np.array_equal(host(r), U.bf16(yg))
+    assert np.array_equal(host(out), U.bf16(yg + skip.astype(np.float32)))
+
+
+@pytest.mark.parametrize("ci,co", PAIRS)
+def test_conv_dgrad_parity(ci, co):
+    shape = (1, 6, 5, 41)
+    rng, _, wo, _ = _operands(shape, ci, co, 7 + ci + co)
+    dy = U.bf16(rng.standard_normal((int(np.prod(shape)), co)))
+    _, wb = pack(wo)
+    dx = torch.empty((dy.shape[0], ci), dtype=torch.float32, device=DEV)
+    N.conv3d_dgrad(shape, ci, co, bf_tensor(dy), wb, dx)
+    ref = from_cf([U.conv3d_dgrad(g, U.bf16(wo)) for g in to_cf(dy, shape, co)])
+    e = rel_l2(host(dx), ref)
+    print(f"conv dgrad {ci}->{co}: rel-L2 {e:.2e}")
+    assert e < 1e-5
+
+
+@pytest.mark.parametrize("ci,co", PAIRS)
+def test_conv_wgrad_parity_and_determinism(ci, co):
+    shape = (2, 4, 7, 45)
+    rng, x, _, _ = _operands(shape, ci, co, 11 + ci * co)
+    dy = U.bf16(rng.standard_normal((x.shape[0], co)))
+    ws = torch.empty(N.wgrad_ws_bytes(shape, ci, co), dtype=torch.uint8, device=DEV)
+    outs = []
+    for _ in range(2):
+        dw = torch.empty((co, 27, ci), dtype=torch.float32, device=DEV)
+        db = torch.empty(co, dtype=torch.float32, device=DEV)
+        N.conv3d_wgrad(shape, ci, co, bf_tensor(x), bf_tensor(dy), dw, db, ws)
+        outs.append((host(dw), host(db)))
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+    ref_w, ref_b = 0.0, 0.0
+    for xc, gc in zip(to_cf(x, shape, ci), to_cf(dy, shape, co)):
+        a, bb = U.conv3d_wgrad(xc, gc)
+        ref_w, ref_b = ref_w + a, ref_b + bb
+    ref_w = np.transpose(ref_w.reshape(co, ci, 27), (0, 2, 1))
+    e, eb = rel_l2(outs[0][0], ref_w), rel_l2(outs[0][1], ref_b)
+    print(f"conv wgrad {ci}->{co}: dw rel-L2 {e:.2e} db {eb:.2e}")
+    assert e < 1e-5 and eb < 1e-5
+
+
+def test_resampling_and_elementwise_kernels():
+    rng = np.random.default_rng(3)
+    shape, c = (2, 6, 4, 10), 32
+    n, d, h, w = shape
+    cs = (n, d // 2, h // 2, w // 2)
+    x = U.bf16(rng.standard_normal((n * d * h * w, c)))
+    y = torch.empty((n * d * h * w // 8, c), dtype=torch.bfloat16, device=DEV)
+    N.pool2(shape, c, bf_tensor(x), y)
+    ref = from_cf([U.bf16(U.pool2(a)) for a in to_cf(x, shape, c)])
+    assert np.array_equal(host(y), ref)
+    xc = U.bf16(rng.standard_normal((int(np.prod(cs)), c)))
+    up = torch.empty((n * d * h * w, c), dtype=torch.bfloat16, device=DEV)
+    N.up2(cs, c, bf_tensor(xc), up)
+    assert np.array_equal(host(up), from_cf([U.up2(a) for a in to_cf(xc, cs, c)]))
+    gf = rng.standard_normal((n * d * h * w, c)).astype(np.float32)
+    gc = torch.empty((int(np.prod(cs)), c), dtype=torch.float32, device=DEV)
+    N.up2_bwd(cs, c, f32(gf), gc)
+    assert rel_l2(host(gc), from_cf([U.up2_bwd(a) for a in to_cf(gf, shape, c)])) < 1e-6
+    # relu gradient with skip gradient and fused pooling adjoint
+    g1 = rng.standard_normal(gf.shape).astype(np.float32)
+    gp = rng.standard_normal((int(np.prod(cs)), c)).astype(np.float32)
+    mask = U.bf16(np.maximum(rng.standard_normal(gf.shape), 0))
+    out = torch.empty(gf.shape, dtype=torch.bfloat16, device=DEV)
+    N.relu_grad(shape, c, f32(g1), None, f32(gp), bf_tensor(mask), out)
+    ref = from_cf([U.bf16((a + U.pool2_bwd(b)) * (m > 0)) for a, b, m in
+                   zip(to_cf(g1, shape, c), to_cf(gp, cs, c), to_cf(mask, shape, c))])
+    got = host(out)
+    # float32 sum vs float64 sum may straddle a bf16 rounding boundary
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1e-30)) <= 2.0 ** -7
+    assert np.mean(got == ref) > 0.999
+    # embed, residual output, loss and gradient
+    img = rng.standard_normal(n * d * h * w).astype(np.float32)
+    x0 = torch.empty((img.size, 16), dtype=torch.bfloat16, device=DEV)
+    N.embed(f32(img), 16, 1.0, x0)
+    xh = host(x0)
+    assert np.array_equal(xh[:, 0], U.bf16(img)) and not xh[:, 1:].any()
+    yv, tg = rng.standard_normal(img.size).astype(np.float32), rng.standard_normal(img.size).astype(np.float32)
+    o = torch.empty(img.size, dtype=torch.float32, device=DEV)
+    gy = torch.empty((img.size, 16), dtype=torch.bfloat16, device=DEV)
+    ws = torch.empty(N.mse_ws_bytes(img.size), dtype=torch.uint8, device=DEV)
+    loss = N.mse(f32(img), f32(yv), f32(tg), o, gy, 16, ws)
+    L, g = U.mse(img.astype(np.float64) + yv, tg)
+    assert np.array_equal(host(o), (img + yv).astype(np.float64))
+    assert loss == pytest.approx(L, rel=1e-6)
+    gyh = host(gy)
+    assert np.max(np.abs(gyh[:, 0] - U.bf16(g)) / np.abs(U.bf16(g))) <= 2.0 ** -7 and not gyh[:, 1:].any()
+    # Adam: three steps against the oracle's update
+    p, m, v = (rng.standard_normal(1000) for _ in range(3))
+    m, v = m * 0.1, np.abs(v) * 0.01
+    pt, mt, vt = f32(p), f32(m), f32(v)
+    for step in (1, 2, 3):
+        gg = rng.standard_normal(1000)
+        N.adam(pt, f32(gg), mt, vt, 1e-3, 0.9, 0.999, 1e-8, step)
+        p, m, v = U.adam(p.astype(np.float32).astype(np.float64), gg.astype(np.float32).astype(np.float64),
+                         m.astype(np.float32).astype(np.float64), v.astype(np.float32).astype(np.float64), step,
+                         lr=1e-3)
+        for a, b_ in ((pt, p), (mt, m), (vt, v)):
+            assert rel_l2(host(a), b_) < 1e-6
+        p, m, v = host(pt), host(mt), host(vt)
+
+
+def _random_params(seed):
+    rng = np.random.default_rng(seed)
+    P = U.init_params(seed)
+    P["c8.w"] = rng.standard_normal(P["c8.w"].shape) * 0.05
+    for n, _, co in U.LAYERS:
+        P[n + ".b"] = rng.standard_normal(co) * 0.05
+    return P
+
+
+def test_network_forward_and_gradients_vs_oracle():
+    rng = np.random.default_rng(21)
+    P = _random_params(4)
+    img = rng.standard_normal((16, 16, 24)).astype(np.float32)
+    tgt = (img + 0.3 * rng.standard_normal(img.shape)).astype(np.float32)
+    net = N.UNet(P)
+    out, loss = net.forward(f32(img)[None], f32(tgt)[None])
+    net.backward()
+    L, G, out_o = U.backward(P, img.astype(np.float64), tgt.astype(np.float64), quant=True)
+    e_out = rel_l2(host(out)[0], out_o)
+    print(f"network: loss {loss:.6e} vs {L:.6e}; output rel-L2 {e_out:.2e}")
+    assert abs(loss - L) <= 1e-4 * L and e_out < 1e-4
+    Gg = net.grads()
+    errs = {k: rel_l2(Gg[k], G[k]) for k in G}
+    print("gradient rel-L2:", {k: f"{v:.1e}" for k, v in errs.items()})
+    assert max(errs.values()) < 1e-3, errs
+    # padded channels stay exactly zero
+    assert not host(net.view(net.g, "c8.w"))[1:].any() and not host(net.view(net.g, "c1.w"))[:, :, 1:].any()
