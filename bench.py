@@ -67,6 +67,10 @@ def parse():
                     help="before the benchmark, copy a device buffer of this many MiB once (a plain copy kernel of "
                          "known size, to scale hardware byte counters)")
     ap.add_argument("--autotune", action="store_true", help="pick launch shapes with the autotuner first")
+    ap.add_argument("--no-unet", action="store_true", help="skip the learned-filter training-step timing")
+    ap.add_argument("--paper-shapes", action="store_true",
+                    help="instead of the survey benchmark: single-shot modeling and RTM at the grid sizes of the "
+                         "paper's Tables 1-4, timed over a shortened nt and scaled to the paper's nt")
     return ap.parse_args()
 
 
@@ -90,6 +94,110 @@ def cpu_baseline(survey, nt_sample):
                       f"{sec:.1f} s"}
 
 
+def unet_report(steps=10):
+    """Training step of the learned crosstalk filter on one 128^3 image
+    (forward, backward, Adam) and each convolution's MFMA throughput."""
+    import torch
+
+    from paper_2204_03380_amd import unet as U
+    g = torch.Generator(device="cuda").manual_seed(0)
+    img = torch.randn((1, 128, 128, 128), device="cuda", generator=g)
+    tgt = img + 0.1 * torch.randn((1, 128, 128, 128), device="cuda", generator=g)
+    net = U.UNet(seed=0)
+    for _ in range(2):
+        net.train_step(img, tgt, 1e-4)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        net.forward(img, tgt, want_loss=False)
+        net.backward()
+        net.step(1e-4)
+    e1.record()
+    e1.synchronize()
+    layers = U.layer_timings(net, img, tgt)
+    conv_ms = sum(r["fwd_ms"] + r["wgrad_ms"] + r.get("dgrad_ms", 0.0) for r in layers)
+    gflop = sum(r["gflop"] * (3 if "dgrad_ms" in r else 2) for r in layers)
+    return {"image": "128^3, batch 1, bf16 MFMA (peak 2500 TFLOP/s)",
+            "train_step_ms": round(e0.elapsed_time(e1) / steps, 3),
+            "conv_ms": round(conv_ms, 3), "conv_tflops": round(gflop / conv_ms, 2),
+            "layers": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()} for r in layers]}
+
+
+# The paper's single-shot times (seconds) on its hardware: one V100 (OpenACC)
+# and one SX-Aurora TSUBASA 10B vector engine.  Grid sizes are the padded
+# grids of Tables 1-4 (2-D: nx x nz, 4 s at 0.5 ms = 8000 steps; 3-D:
+# nx x ny x nz, 6 s at 1 ms = 6000 steps).
+PAPER_CASES = (
+    ("modeling", (837, 1, 294), 8000, {"V100": 1.132, "SX-Aurora": 0.488}, "Table 1"),
+    ("modeling", (1574, 1, 534), 8000, {"V100": 1.875, "SX-Aurora": 0.912}, "Table 1"),
+    ("modeling", (3048, 1, 1014), 8000, {"V100": 2.615, "SX-Aurora": 2.416}, "Table 1"),
+    ("modeling", (5996, 1, 1974), 8000, {"V100": 6.962, "SX-Aurora": 7.885}, "Table 1"),
+    ("rtm", (1574, 1, 534), 8000, {"V100": 3.500, "SX-Aurora": 4.489}, "Table 2"),
+    ("modeling", (501, 501, 235), 6000, {"V100": 42.1505, "SX-Aurora": 43.132}, "Table 3"),
+    ("modeling", (901, 901, 416), 6000, {"V100": 330.363, "SX-Aurora": 203.940}, "Table 3"),
+    ("rtm", (501, 501, 235), 6000, {"V100": 139.786, "SX-Aurora": 108.582}, "Table 4"),
+)
+
+
+def paper_shapes(nb=50, reps_2d=400, reps_3d=60):
+    """Per-step device time of one shot on each paper grid (synthetic smooth
+    velocity, runtime does not depend on the values), scaled to the paper's
+    nt, against the paper's times."""
+    import numpy as np
+    import torch
+
+    import paper_2204_03380_amd as rtm
+    import synth
+    dev = torch.device("cuda:0")
+    out = []
+    for kind, (nx, ny, nz), nt_paper, paper, table in PAPER_CASES:
+        ndim = 2 if ny == 1 else 3
+        shape_int = (nz - 2 * nb, nx - 2 * nb) if ndim == 2 else (nz - 2 * nb, ny - 2 * nb, nx - 2 * nb)
+        if ndim == 2:
+            v = synth.random_model(shape_int, 7, 1500.0, 4000.0, sigma=4.0)
+        else:
+            v = synth.layered_salt_3d(shape_int[2], shape_int[1], shape_int[0], 7, vmax=4000.0, salt=False)
+        h = 10.0
+        dt = 0.45 * h / 4000.0 * (0.8 if ndim == 3 else 1.0)
+        g = rtm.Grid.for_model(v, h, nb)
+        vp = rtm.rtm_rbc_pad(g, torch.from_numpy(v).to(dev), 11, 0.0)
+        steps = reps_2d if ndim == 2 else reps_3d
+        w = torch.from_numpy(synth.ricker(15.0, dt, steps)).to(dev)
+        src = np.array([shape_int[-1] / 2.0, (shape_int[1] / 2.0 if ndim == 3 else 0.0), 2.0])
+        if ndim == 2:
+            rec = synth.line_receivers(np.arange(0, shape_int[-1], 1, dtype=np.float64), 2.0)
+        else:
+            rec = synth.grid_receivers(np.arange(0, shape_int[-1], 2, dtype=np.float64),
+                                       np.arange(0, shape_int[1], 2, dtype=np.float64), 2.0)
+        run = (lambda: rtm.rtm_model_shot(g, vp, dt, w, src, rec)) if kind == "modeling" else None
+        if kind == "rtm":
+            d = rtm.rtm_model_shot(g, vp, dt, w, src, rec)
+            run = lambda: rtm.rtm_rtm_shot(g, vp, dt, w, src, rec, d)  # noqa: E731
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        run()
+        e1.record()
+        e1.synchronize()
+        ms = e0.elapsed_time(e1)
+        props = 1 if kind == "modeling" else 3
+        cells = nx * ny * nz
+        t_paper_nt = ms * 1e-3 * nt_paper / steps
+        row = {"case": f"{kind} {nx}x{nz}" if ndim == 2 else f"{kind} {nx}x{ny}x{nz}", "source": table,
+               "padded_cells": cells, "steps_timed": steps, "ms_per_step": round(ms / steps, 4),
+               "gcell_updates_per_s": round(cells * props * steps / (ms * 1e-3) / 1e9, 2),
+               "seconds_at_paper_nt": round(t_paper_nt, 4),
+               "paper_seconds": paper,
+               "speedup": {k: round(v_ / t_paper_nt, 1) for k, v_ in paper.items()}}
+        out.append(row)
+        print(json.dumps(row), file=sys.stderr, flush=True)
+        del vp
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -98,6 +206,13 @@ def main():
               "independent and a multi-GPU run would be a shot partition plus one image all-reduce, which this "
               "build does not include.", file=sys.stderr)
         sys.exit(2)
+
+    if args.paper_shapes:
+        rows = paper_shapes()
+        print(json.dumps({"metric": "single-shot time at the paper's grid sizes", "unit": "s", "n_gpus": 1,
+                          "higher_is_better": False, "dtype": "f32", "data": "synthetic", "cases": rows}),
+              flush=True)
+        return
 
     import numpy as np
     import torch
@@ -267,6 +382,8 @@ def main():
         },
         "wall_s": round(wall, 3),
     }
+    if not args.no_unet:
+        line["unet_train_step"] = unet_report()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(s, args.cpu_sample_nt)
     print(json.dumps(line), flush=True)

@@ -290,14 +290,32 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(WgArgs a)
     if (centre && gt < COUT) a.bpart[p * COUT + gt] = bacc;
 }
 
-// Fixed-order sum of P partial arrays of n floats.
-__global__ void sum_parts_kernel(const float *__restrict__ part, int64_t P, int64_t n, float *__restrict__ out)
+// Fixed-order sum of P partial arrays of n floats: out[c][i] = sum of
+// partials c*chunk .. min(P, (c+1)*chunk) - 1 in increasing order (blockIdx.y
+// = c).  Two passes (chunks, then the chunk sums) give the same result on
+// every run.
+constexpr int kSumChunk = 32;
+
+__global__ void sum_parts_kernel(const float *__restrict__ part, int64_t P, int64_t n, int chunk,
+                                 float *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int64_t p0 = (int64_t)blockIdx.y * chunk;
+    const int64_t p1 = p0 + chunk < P ? p0 + chunk : P;
     float s = 0.f;
-    for (int64_t p = 0; p < P; ++p) s += part[p * n + i];
-    out[i] = s;
+    for (int64_t p = p0; p < p1; ++p) s += part[p * n + i];
+    out[(int64_t)blockIdx.y * n + i] = s;
+}
+
+hipError_t sum_parts(const float *part, int64_t P, int64_t n, float *tmp, float *out, hipStream_t st)
+{
+    const int64_t Q = (P + kSumChunk - 1) / kSumChunk;
+    const dim3 g1((unsigned)((n + 255) / 256), (unsigned)Q);
+    hipLaunchKernelGGL(sum_parts_kernel, g1, dim3(256), 0, st, part, P, n, kSumChunk, tmp);
+    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 255) / 256), 1), dim3(256), 0, st, tmp, Q, n, (int)Q,
+                       out);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
@@ -549,15 +567,21 @@ int launch_fwd(int ci, int co, ConvArgs a, hipStream_t st)
     return -1;
 }
 
-constexpr int kWgMaxSplits = 64;
+// Row splits of the weight gradient: enough workgroups to fill the chip
+// (9 x splits, several per CU) while every group keeps >= 4 rows and the
+// partial sums stay within a fixed budget.
+constexpr int kWgMaxSplits = 512;
+constexpr int64_t kWgPartBudget = (int64_t)64 << 20;
 
 template <int CI, int CO>
 int wg_splits(int64_t rows)
 {
     constexpr int RS = WgCfg<CI, CO>::RS;
     int64_t s = rows / (4 * RS);
-    if (s < 1) s = 1;
+    const int64_t by_budget = kWgPartBudget / ((int64_t)RS * 27 * CI * CO * (int64_t)sizeof(float));
+    if (s > by_budget) s = by_budget;
     if (s > kWgMaxSplits) s = kWgMaxSplits;
+    if (s < 1) s = 1;
     return (int)s;
 }
 
@@ -592,11 +616,16 @@ int wg_layout(const unet_conv_desc_t *d, int64_t *parts, int *S)
     return -1;
 }
 
+size_t rnd256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Workspace: weight partials [parts][Cout*27*Cin], bias partials
+// [parts][Cout], then the chunk sums of the two-pass reduction.
 size_t wg_bytes(const unet_conv_desc_t *d, int64_t parts)
 {
-    const size_t w = (size_t)parts * d->cout * 27 * d->cin * sizeof(float);
-    const size_t b = (size_t)parts * d->cout * sizeof(float);
-    return ((w + 255) & ~(size_t)255) + ((b + 255) & ~(size_t)255);
+    const size_t nw = (size_t)d->cout * 27 * d->cin;
+    const size_t q = (size_t)((parts + kSumChunk - 1) / kSumChunk);
+    return rnd256(parts * nw * sizeof(float)) + rnd256(parts * d->cout * sizeof(float)) +
+           rnd256(q * nw * sizeof(float)) + rnd256(q * d->cout * sizeof(float));
 }
 
 template <int CI, int CO>
@@ -730,8 +759,15 @@ int unet_conv3d_wgrad(const unet_conv_desc_t *desc, const uint16_t *x, const uin
     WgArgs a{};
     a.x = x;
     a.dy = dy;
-    a.part = static_cast<float *>(ws);
-    a.bpart = reinterpret_cast<float *>(static_cast<char *>(ws) + ((nw * parts * sizeof(float) + 255) & ~(size_t)255));
+    char *base = static_cast<char *>(ws);
+    const int64_t q = (parts + kSumChunk - 1) / kSumChunk;
+    a.part = reinterpret_cast<float *>(base);
+    base += rnd256(parts * nw * sizeof(float));
+    a.bpart = reinterpret_cast<float *>(base);
+    base += rnd256(parts * desc->cout * sizeof(float));
+    float *tmp_w = reinterpret_cast<float *>(base);
+    base += rnd256(q * nw * sizeof(float));
+    float *tmp_b = reinterpret_cast<float *>(base);
     a.rows = (int64_t)desc->n * desc->d * desc->h;
     a.d = desc->d;
     a.h = desc->h;
@@ -739,10 +775,8 @@ int unet_conv3d_wgrad(const unet_conv_desc_t *desc, const uint16_t *x, const uin
     a.S = S;
     hipStream_t st = (hipStream_t)stream;
     launch_wg(desc->cin, desc->cout, a, st);
-    hipLaunchKernelGGL(sum_parts_kernel, grid1(nw), dim3(256), 0, st, a.part, parts, nw, dw);
-    if (db) hipLaunchKernelGGL(sum_parts_kernel, grid1(desc->cout), dim3(256), 0, st, a.bpart, parts,
-                               (int64_t)desc->cout, db);
-    UNET_HIP(hipGetLastError());
+    UNET_HIP(sum_parts(a.part, parts, nw, tmp_w, dw, st));
+    if (db) UNET_HIP(sum_parts(a.bpart, parts, desc->cout, tmp_b, db, st));
     return RTM_OK;
 }
 

@@ -319,3 +319,51 @@ class UNet:
         with torch.no_grad():
             out, _ = self.forward(img)
             return out.clone()
+
+
+def layer_timings(net: UNet, img, target, reps=5):
+    """Device time of every convolution of one training step (forward,
+    input gradient, weight gradient) with torch events on the current stream
+    (the library launches on it), after a warm-up step.  Flops are the
+    algorithmic 2 x voxels x 27 x Cin x Cout of the real channel counts."""
+    net.forward(img, target)
+    net.backward()
+    t = net._acts.t
+    s = t["s"]
+    n_img = img.shape[0]
+    wsb = net._ws
+    plan = (("c1", 0, 16, 16, "x0", "e1", None, "gp1", None), ("c2", 1, 16, 32, "p1", "e2", None, "gp2", "g_p1"),
+            ("c3", 2, 32, 64, "p2", "e3", None, "gp3", "g_p2"), ("c4", 3, 64, 128, "p3", "e4", None, "gp4", "g_p3"),
+            ("c5", 2, 128, 64, "u4", "d3", "e3", "gp5", "g_u4"), ("c6", 1, 64, 32, "u3", "d2", "e2", "gp6", "g_u3"),
+            ("c7", 0, 32, 16, "u2", "d1", "e1", "gp7", "g_u2"), ("c8", 0, 16, 16, "d1", None, None, "gy8", "g_d1"))
+    real = {n: (ci, co) for n, ci, co in LAYERS}
+    b = lambda k: net.view(net.p, k)  # noqa: E731
+    G = lambda k: net.view(net.g, k)  # noqa: E731
+    out = []
+    for name, k, ci, co, xin, yout, skip, gp, gx in plan:
+        vox = int(np.prod(s[k]))
+        flops = 2.0 * vox * 27 * real[name][0] * real[name][1]
+        calls = {
+            "fwd": lambda: conv3d_fwd(s[k], ci, co, t[xin], net.wf[name], b(name + ".b"), name != "c8",
+                                      skip=t[skip] if skip else None, y=t["y8"] if yout is None else None,
+                                      y_channels=1 if yout is None else None,
+                                      r=t["r" + name[1]] if skip else None, out=t[yout] if yout else None),
+            "wgrad": lambda: conv3d_wgrad(s[k], ci, co, t[xin], t[gp], G(name + ".w"), G(name + ".b"), wsb),
+        }
+        if gx is not None:
+            calls["dgrad"] = lambda: conv3d_dgrad(s[k], ci, co, t[gp], net.wb[name], t[gx])
+        row = {"layer": name, "voxels": vox // n_img, "cin": real[name][0], "cout": real[name][1],
+               "gflop": flops / 1e9}
+        for kind, fn in calls.items():
+            fn()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            row[kind + "_ms"] = ms
+            row[kind + "_tflops"] = flops / (ms * 1e-3) / 1e12
+        out.append(row)
+    return out
