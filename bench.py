@@ -25,17 +25,19 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes of one reverse launch from two rocprofv3 counter runs (FETCH_SIZE,
-# WRITE_SIZE; KiB per dispatch) on this workload at 48 shots per launch,
-# reverse shape (vec 1, zseg 9), scaled by what the same counters read for a
-# 1 GiB device copy in the same run (FETCH x2.0, WRITE x1.0).  Valid only for
-# the kernel sources hashed here; reported as null once they change.
-PMC_REVERSE = {"sources_sha256_16": "32e916c0b32ee2a0", "shots": 48, "shape": (1, 9),
-               "fetch_kib": 1960622.9, "write_kib": 1446789.7, "fetch_scale": 2.0, "write_scale": 1.0}
+# HBM bytes of one reverse launch (48 shots, two steps per launch, shape vec 2,
+# tx 1, zseg 36) from two rocprofv3 counter runs: L2-to-memory read requests
+# by size (TCC_EA0_RDREQ_32B/64B/128B) and write requests (TCC_EA0_WRREQ,
+# TCC_EA0_WRREQ_64B; the rest are 32 B).  A 1 GiB device copy in the same
+# runs reads exactly 8388608 x 128 B and writes 16777216 x 64 B, so the
+# request counts are bytes without further scaling.  Valid only for the
+# kernel sources hashed here; reported as null once they change.
+PMC_REVERSE = {"sources_sha256_16": "613ed654b392e4dc", "shots": 48, "shape": (2, 1, 36), "steps": 2,
+               "read_bytes": 30508740 * 128 + 168714 * 64, "write_bytes": 36030114 * 64 + (37668712 - 36030114) * 32}
 KERNEL_SOURCES = ("prop2d.hip", "stencil.h", "common.h")
 
 
-def reverse_traffic(B, shape):
+def reverse_traffic(B, shape, steps=1):
     import hashlib
     csrc = os.path.join(ROOT, "paper_2204_03380_amd", "csrc")
     try:
@@ -44,9 +46,9 @@ def reverse_traffic(B, shape):
         return None
     rec = PMC_REVERSE
     if (hashlib.sha256(blob).hexdigest()[:16] != rec["sources_sha256_16"] or B != rec["shots"]
-            or tuple(shape) != rec["shape"]):
+            or tuple(shape) != rec["shape"] or steps != rec.get("steps", 1)):
         return None
-    return int(round((rec["fetch_kib"] * rec["fetch_scale"] + rec["write_kib"] * rec["write_scale"]) * 1024))
+    return int(rec["read_bytes"] + rec["write_bytes"])
 
 
 def parse():
@@ -247,8 +249,8 @@ def main():
         v_tmp = rtm.rtm_rbc_pad(g, v_int, s.seed, 0.0)
         tuned = autotune.tune_batch(g, v_tmp, wav, [s.src[i] for i in range(B)], s.rec, s.dt, nt_probe=90, reps=2)
         del v_tmp
-    fwd_shape = rtm.rtm_get_tuning(rtm.RTM_OP_MODEL)
-    rev_shape = rtm.rtm_get_tuning(rtm.RTM_OP_RTM)
+    fwd_shape = rtm.rtm_get_tuning2d(rtm.RTM_OP_MODEL)   # (vec, tx, zseg)
+    rev_shape = rtm.rtm_get_tuning2d(rtm.RTM_OP_RTM)
 
     # Buffers resident in HBM before timing: padded model, B traces, stack.
     v_pad = rtm.rtm_rbc_pad(g, v_int, s.seed, 0.0)
@@ -327,12 +329,24 @@ def main():
     torch.cuda.synchronize()
     batch_vs_plain = float(torch.linalg.norm(one - ref) / torch.linalg.norm(ref))
 
-    # Dominant kernel: the fused reverse step (two stencils, imaging sums),
-    # one launch covering the B shots of a batch.
+    # Dominant kernel: the fused reverse kernel (two stencils, imaging sums),
+    # one launch covering the B shots of a batch and one or two time steps.
+    # Algorithmic bytes per launch: one step reads p^k, p^{k+1}, mu^{k+1},
+    # mu^{k+2}, D' and writes p^{k-1}, mu^k on the padded grid (28 B) and
+    # reads and writes num, den on the interior (16 B); two steps read the
+    # same five arrays once, write four levels (36 B) and num, den once (16 B).
+    steps_f = rtm.rtm_get_steps_per_launch(rtm.RTM_OP_MODEL)
+    steps_r = rtm.rtm_get_steps_per_launch(rtm.RTM_OP_RTM)
     rev_ms, rev_n = loops["reverse_image"]
     rev_us = rev_ms * 1e3 / max(rev_n, 1)
-    rev_bytes = B * (28 * cells + 16 * interior)
+    rev_bytes = B * ((36 if steps_r == 2 else 28) * cells + 16 * interior)
     achieved = rev_bytes / (rev_us * 1e-6) / 1e9
+    one_step_bytes = B * (28 * cells + 16 * interior)
+    per_step_us = rev_us / steps_r
+    rev_kernel = (f"rev2d_t2_kernel<{rev_shape[0]}> (two reverse steps per launch: reconstruction + receiver field + "
+                  f"imaging, {B} shots per launch)" if steps_r == 2 else
+                  f"rev2d_kernel<{rev_shape[0]},false,{rev_shape[1]}> (fused reconstruction + receiver field + "
+                  f"imaging, {B} shots per launch)")
     fwd_ms, fwd_n = loops["model_forward"]
     rf_ms, rf_n = loops["rtm_forward"]
     line = {
@@ -355,26 +369,32 @@ def main():
             "padded_cells": cells,
             "shots_per_step": B,
             "propagations_per_shot": 4,
-            "launch_shape": {"forward": {"vec": fwd_shape[0], "zseg": fwd_shape[1]},
-                             "reverse": {"vec": rev_shape[0], "zseg": rev_shape[1]},
+            "launch_shape": {"forward": {"vec": fwd_shape[0], "tx": fwd_shape[1], "zseg": fwd_shape[2]},
+                             "reverse": {"vec": rev_shape[0], "tx": rev_shape[1], "zseg": rev_shape[2]},
                              "autotuned": tuned is not None},
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": f"rev2d_kernel<{rev_shape[0]},false> (fused reconstruction + receiver field + imaging, "
-                      f"{B} shots per launch)",
+            "kernel": rev_kernel,
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": reverse_traffic(B, rev_shape),
+            "traffic": reverse_traffic(B, rev_shape, steps_r),
             "avg_launch_us": round(rev_us, 3),
             "algorithmic_bytes_per_launch": rev_bytes,
+            "steps_per_launch": steps_r,
+            "per_step": {"us": round(per_step_us, 3),
+                         "one_step_algorithmic_bytes": one_step_bytes,
+                         "equivalent_GBps": round(one_step_bytes / (per_step_us * 1e-6) / 1e9, 1),
+                         "note": "rate a one-step kernel would need to move its own minimum bytes in the "
+                                 "time of one step"},
         },
         "rtm_shots_per_s": {"batched": round(shots / (dev_ms * 1e-3), 4),
                             "plain": round(len(plain_shots) / plain_s, 4),
                             "image_rel_l2_batched_vs_plain": batch_vs_plain,
                             "note": "one shot = modeling + RTM; plain = sequential single-shot calls"},
+        "steps_per_launch": {"forward": steps_f, "reverse": steps_r},
         "loop_us_per_launch": {
             "model_forward": round(fwd_ms * 1e3 / max(fwd_n, 1), 3),
             "rtm_forward": round(rf_ms * 1e3 / max(rf_n, 1), 3),

@@ -121,6 +121,26 @@ int rtm_set_tuning(int op, int vec, int zseg);
 /* Current launch shape for `op` (same selection as rtm_set_tuning). */
 int rtm_get_tuning(int op, int *vec, int *zseg);
 
+/* Full 2-D launch shape: as rtm_set_tuning plus tx in {1, 2, 4}
+ * wavefronts per workgroup, each on one of tx adjacent strips.  The strips
+ * of a workgroup pass their inner end cells to each other through LDS
+ * instead of reloading them from memory.  rtm_set_tuning keeps the current
+ * tx. */
+int rtm_set_tuning2d(int op, int vec, int tx, int zseg);
+int rtm_get_tuning2d(int op, int *vec, int *tx, int *zseg);
+
+/* Time steps per launch of the 2-D propagation, 1 or 2.  With 2, one
+ * launch advances two steps: each wavefront computes the first step on its
+ * strip plus a 4-cell margin and the second on the strip's inner columns
+ * (strips overlap by 8 columns), and the two new levels go to a second set
+ * of field buffers, so the level pairs cross HBM once per two steps.
+ * RTM_OP_MODEL sets it for every forward pass (modeling and the forward
+ * pass of RTM and VJP jobs), RTM_OP_RTM for the imaging reverse pass (the
+ * gradient pass and probed runs always take one step per launch; an odd
+ * last step is taken alone).  Results are bit-identical either way. */
+int rtm_set_steps_per_launch(int op, int steps);
+int rtm_get_steps_per_launch(int op, int *steps);
+
 /* Launch shape of the 3-D kernels: vec floats per lane (x strips of
  * 64 * vec cells), ty in {4, 8} wavefronts per workgroup (rows in y), zseg
  * planes per tile (a multiple of 9).  Same rules as rtm_set_tuning. */

@@ -110,6 +110,27 @@ def rtm_get_tuning3d(op: int):
     return int(v.value), int(y.value), int(z.value)
 
 
+def rtm_set_tuning2d(op: int, vec: int, tx: int, zseg: int) -> None:
+    _lib.check(_lib.load().rtm_set_tuning2d(op, vec, tx, zseg))
+
+
+def rtm_get_tuning2d(op: int):
+    """(vec, tx, zseg) currently used for `op` on 2-D grids."""
+    v, x, z = ctypes.c_int(0), ctypes.c_int(0), ctypes.c_int(0)
+    _lib.check(_lib.load().rtm_get_tuning2d(op, ctypes.byref(v), ctypes.byref(x), ctypes.byref(z)))
+    return int(v.value), int(x.value), int(z.value)
+
+
+def rtm_set_steps_per_launch(op: int, steps: int) -> None:
+    _lib.check(_lib.load().rtm_set_steps_per_launch(op, steps))
+
+
+def rtm_get_steps_per_launch(op: int) -> int:
+    v = ctypes.c_int(0)
+    _lib.check(_lib.load().rtm_get_steps_per_launch(op, ctypes.byref(v)))
+    return int(v.value)
+
+
 def rtm_get_tuning(op: int):
     """(vec, zseg) currently used for `op`."""
     v, z = ctypes.c_int(0), ctypes.c_int(0)

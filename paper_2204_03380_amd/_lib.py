@@ -25,7 +25,8 @@ RTM_F_NO_REINJECT = 0x2
 
 # Every symbol declared in include/rtm.h and include/unet.h.
 EXPORTS = (
-    "rtm_abi_version", "rtm_last_error", "rtm_set_tuning", "rtm_get_tuning", "rtm_set_tuning3d",
+    "rtm_abi_version", "rtm_last_error", "rtm_set_tuning", "rtm_get_tuning", "rtm_set_tuning2d",
+    "rtm_get_tuning2d", "rtm_set_steps_per_launch", "rtm_get_steps_per_launch", "rtm_set_tuning3d",
     "rtm_get_tuning3d", "rtm_timing_enable", "rtm_timing_read",
     "rtm_workspace_bytes", "rtm_rbc_pad",
     "rtm_pad_adjoint", "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "rtm_batch_plan", "rtm_batch_run",
@@ -81,6 +82,10 @@ def load():
         "rtm_last_error": ([], ctypes.c_char_p),
         "rtm_set_tuning": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
         "rtm_get_tuning": ([ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
+        "rtm_set_tuning2d": ([ctypes.c_int] * 4, ctypes.c_int),
+        "rtm_get_tuning2d": ([ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3, ctypes.c_int),
+        "rtm_set_steps_per_launch": ([ctypes.c_int] * 2, ctypes.c_int),
+        "rtm_get_steps_per_launch": ([ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rtm_set_tuning3d": ([ctypes.c_int] * 4, ctypes.c_int),
         "rtm_get_tuning3d": ([ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3, ctypes.c_int),
         "rtm_timing_enable": ([ctypes.c_int], ctypes.c_int),

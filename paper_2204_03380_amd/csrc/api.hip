@@ -20,11 +20,17 @@
 
 namespace rtm {
 // prop2d.hip
-hipError_t launch_fwd2d(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+hipError_t launch_fwd2d(int vec, int tx, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                         const InjEnt *ents, const Contrib *cont, const SampleTask *stasks, int nsample, int n,
                         hipStream_t st);
-hipError_t launch_rev2d(int vec, bool grad, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
-                        const InjEnt *ents, const Contrib *cont, int k, int reinject, float *wadj, hipStream_t st);
+hipError_t launch_rev2d(int vec, int tx, bool grad, const ShotDev *shots, const Tile2D *tiles, int ntiles,
+                        int nslots, const InjEnt *ents, const Contrib *cont, int k, int reinject, float *wadj,
+                        hipStream_t st);
+hipError_t launch_fwd2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+                           const InjEnt *ents, const Contrib *cont, const SampleTask *stasks, int nsample, int n,
+                           hipStream_t st);
+hipError_t launch_rev2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+                           const InjEnt *ents, const Contrib *cont, int k, int reinject, hipStream_t st);
 // prop3d.hip
 hipError_t launch_fwd3d(int vec, int ty, const ShotDev *shots, const Tile3D *tiles, int ntiles, int nslots,
                         const InjEnt *ents, const Contrib *cont, const SampleTask *stasks, int nsample, int n,
@@ -102,11 +108,14 @@ struct Tune {
     int vec;
     int zseg;
     int ty;  // 3-D: wavefronts (y rows) per workgroup
+    int tx;  // 2-D: wavefronts (adjacent strips) per workgroup
+    int steps = 1;  // 2-D: time steps per launch (1, or 2 with the two-step kernels)
 };
 
-// Defaults from sweeps over 16-64 shots of the 2301 x 751 folded grid.
-std::atomic<int> g_tune2d_fwd{(4 << 16) | 36};
-std::atomic<int> g_tune2d_rev{(1 << 16) | 9};
+// 2-D shapes: ((steps - 1) << 28) | (tx << 24) | (vec << 16) | zseg;
+// defaults from sweeps over 16-64 shots of the 2301 x 751 folded grid.
+std::atomic<int> g_tune2d_fwd{(1 << 28) | (1 << 24) | (4 << 16) | 36};
+std::atomic<int> g_tune2d_rev{(1 << 28) | (1 << 24) | (2 << 16) | 36};
 std::atomic<int> g_tune_exact{0};  // 1: never narrow the configured shapes
 
 // 3-D shapes: (vec << 24) | (ty << 16) | zseg; defaults from a sweep on
@@ -118,10 +127,10 @@ Tune get_tune(int which, int ndim)
 {
     if (ndim == 3) {
         int v = (which == 0 ? g_tune3d_fwd : g_tune3d_rev).load();
-        return Tune{v >> 24, v & 0xffff, (v >> 16) & 0xff};
+        return Tune{v >> 24, v & 0xffff, (v >> 16) & 0xff, 1};
     }
     int v = (which == 0 ? g_tune2d_fwd : g_tune2d_rev).load();
-    return Tune{v >> 16, v & 0xffff, 1};
+    return Tune{(v >> 16) & 0xff, v & 0xffff, 1, (v >> 24) & 0xf, ((v >> 28) & 0x3) + 1};
 }
 
 constexpr int kMinZseg = kZUnroll;
@@ -268,8 +277,9 @@ struct ShotIn {
 // Tiles and injection entries of one launch shape.  ents holds all source
 // entries of all shots, then all receiver entries (when present).
 struct Tiling {
-    Tune tune{1, 18, 1};
+    Tune tune{1, 18, 1, 1, 1};
     int ndim = 2;
+    bool two_step = false;  // overlapping strips of the two-step kernels
     std::vector<Tile2D> tiles;   // 2-D jobs
     std::vector<Tile3D> tiles3;  // 3-D jobs
     std::vector<InjEnt> ents;
@@ -281,15 +291,18 @@ struct Tiling {
 struct Counts {
     int64_t tiles_f = 0, ents_f = 0, cont_f = 0;  // forward tiling
     int64_t tiles_r = 0, ents_r = 0, cont_r = 0;  // reverse tiling
+    int64_t tiles_f2 = 0, ents_f2 = 0, cont_f2 = 0;  // two-step tilings (2-D)
+    int64_t tiles_r2 = 0, ents_r2 = 0, cont_r2 = 0;
     int64_t stasks = 0, rnode = 0;
 };
 
 // Byte offsets of every device buffer inside the workspace.
 struct WsLayout {
     size_t scal = 0, shots = 0, tiles_f = 0, ents_f = 0, cont_f = 0, tiles_r = 0, ents_r = 0, cont_r = 0;
+    size_t tiles_f2 = 0, ents_f2 = 0, cont_f2 = 0, tiles_r2 = 0, ents_r2 = 0, cont_r2 = 0;
     size_t stasks = 0, rnode = 0, rw = 0;
     std::vector<size_t> dp;                  // per D' slot
-    std::vector<std::array<size_t, 4>> fld;  // per shot
+    std::vector<std::array<size_t, 8>> fld;  // per shot
     std::vector<size_t> acc0, acc1, trint, wadj;
     size_t bytes = 0;
 };
@@ -301,7 +314,8 @@ struct Job {
     float eps = 1e-3f;
     uint32_t flags = 0;
     std::vector<ShotIn> shots;
-    Tiling fw, rv;  // rv unused for modeling
+    Tiling fw, rv;    // rv unused for modeling
+    Tiling fw2, rv2;  // two-step tilings (2-D, when the shape asks for two steps per launch)
     std::vector<SampleTask> stasks;
     std::vector<int> rnode;
     std::vector<float> rw;
@@ -317,7 +331,13 @@ struct Job {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-int nfields(int op) { return op == RTM_OP_MODEL ? 2 : 4; }
+// Field buffers per shot: p (2 levels) and mu (2 levels); 2-D jobs keep a
+// second set for the two-step kernels, so that the workspace size does not
+// depend on the launch shape.
+int nfields(int op, int ndim) { return (op == RTM_OP_MODEL ? 2 : 4) * (ndim == 2 ? 2 : 1); }
+int nfields(const Job &J) { return nfields(J.op, J.shots.empty() ? 3 : J.shots[0].g.ndim); }
+
+constexpr size_t kTileBytes = sizeof(Tile2D) > sizeof(Tile3D) ? sizeof(Tile2D) : sizeof(Tile3D);
 
 WsLayout make_ws_layout(const Job &J, const Counts &c)
 {
@@ -332,23 +352,32 @@ WsLayout make_ws_layout(const Job &J, const Counts &c)
     const int nsh = (int)J.shots.size();
     const int nslot = (int)J.slot_shot.size();
     w.scal = take(sizeof(unsigned) * (64 + 2 * (size_t)nslot + (size_t)nsh));
-    w.shots = take(sizeof(ShotDev) * nsh);
-    w.tiles_f = take(sizeof(Tile3D) * c.tiles_f);
+    w.shots = take(sizeof(ShotDev) * 2 * nsh);  // two copies: field sets in either order
+    w.tiles_f = take(kTileBytes * c.tiles_f);
     w.ents_f = take(sizeof(InjEnt) * c.ents_f);
     w.cont_f = take(sizeof(Contrib) * c.cont_f);
-    w.tiles_r = take(sizeof(Tile3D) * c.tiles_r);
+    w.tiles_r = take(kTileBytes * c.tiles_r);
     w.ents_r = take(sizeof(InjEnt) * c.ents_r);
     w.cont_r = take(sizeof(Contrib) * c.cont_r);
+    w.tiles_f2 = take(kTileBytes * c.tiles_f2);
+    w.ents_f2 = take(sizeof(InjEnt) * c.ents_f2);
+    w.cont_f2 = take(sizeof(Contrib) * c.cont_f2);
+    w.tiles_r2 = take(kTileBytes * c.tiles_r2);
+    w.ents_r2 = take(sizeof(InjEnt) * c.ents_r2);
+    w.cont_r2 = take(sizeof(Contrib) * c.cont_r2);
     w.stasks = take(sizeof(SampleTask) * c.stasks);
     w.rnode = take(sizeof(int) * c.rnode * kMaxNodes);
     w.rw = take(sizeof(float) * c.rnode * kMaxNodes);
     for (int d = 0; d < nslot; ++d) w.dp.push_back(take(sizeof(float) * J.shots[J.slot_shot[d]].g.L.total));
-    const int nf = nfields(J.op);
+    const int nf = nfields(J);
     for (int i = 0; i < nsh; ++i) {
         const ShotIn &S = J.shots[i];
         const int64_t F = S.g.L.total;
-        std::array<size_t, 4> f{0, 0, 0, 0};
-        for (int k = 0; k < nf; ++k) f[k] = take(sizeof(float) * F);
+        // fields 0..3: first set (p, p, mu, mu), 4..7: second set; a
+        // modeling job has only the two p levels of each set
+        std::array<size_t, 8> f{0, 0, 0, 0, 0, 0, 0, 0};
+        const int per = J.op == RTM_OP_MODEL ? 2 : 4;  // fields per set
+        for (int k = 0; k < nf; ++k) f[(k / per) * 4 + k % per] = take(sizeof(float) * F);
         w.fld.push_back(f);
         w.acc0.push_back(J.op == RTM_OP_MODEL ? 0 : take(sizeof(float) * F));
         w.acc1.push_back(J.op == RTM_OP_RTM ? take(sizeof(float) * F) : 0);
@@ -379,7 +408,12 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
     T.ents.clear();
     T.cont.clear();
     std::vector<RawEnt> se, re;
-    const int strip = 64 * T.tune.vec;
+    // 2-D: one tile is TX adjacent strips (one workgroup); 3-D: one strip.
+    // Two-step 2-D tiles: strips of 64 vec columns starting at j W - 4 that
+    // own W = 64 vec - 8 columns each (neighbours overlap by 8).
+    const bool two = T.two_step;
+    const int span = 64 * T.tune.vec;
+    const int strip = two ? span - 8 : span * (T.ndim == 2 ? T.tune.tx : 1);
     const int ty = T.ndim == 3 ? T.tune.ty : 1;
     for (int s = 0; s < (int)J.shots.size(); ++s) {
         const ShotIn &S = J.shots[s];
@@ -389,9 +423,15 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
         const int nys = T.ndim == 3 ? (g.NY + ty - 1) / ty : 1;
         const int nzs = (NZr + T.tune.zseg - 1) / T.tune.zseg;
         const int tbase = T.count();
-        for (int xs = 0; xs < ns; ++xs)
+        // 2-D tiles are numbered row band by row band, so that workgroups on
+        // adjacent strips run back to back on one XCD and share the strip-end
+        // lines in its L2 (measured 3-7 % faster than strip by strip).
+        const bool rowmajor = T.ndim == 2;
+        const int n_outer = rowmajor ? nzs : ns, n_inner = rowmajor ? ns : nzs;
+        for (int oi = 0; oi < n_outer; ++oi)
             for (int ys = 0; ys < nys; ++ys)
-                for (int zs = 0; zs < nzs; ++zs) {
+                for (int ii = 0; ii < n_inner; ++ii) {
+                    const int xs = rowmajor ? ii : oi, zs = rowmajor ? oi : ii;
                     const int z0 = zs * T.tune.zseg, z1 = std::min(z0 + T.tune.zseg, NZr);
                     if (T.ndim == 3) {
                         Tile3D t{};
@@ -404,13 +444,14 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
                     } else {
                         Tile2D t{};
                         t.shot = s;
-                        t.x0 = xs * strip;
+                        t.x0 = two ? xs * strip - 4 : xs * strip;
                         t.z0 = z0;
                         t.z1 = z1;
                         T.tiles.push_back(t);
                     }
                 }
         auto tile_of = [&](int z, int y, int x) {
+            if (rowmajor) return tbase + (z / T.tune.zseg) * ns + x / strip;  // (two-step: owned columns)
             return tbase + ((x / strip) * nys + (T.ndim == 3 ? y / ty : 0)) * nzs + z / T.tune.zseg;
         };
         PointOp sp;
@@ -443,41 +484,76 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
             }
         }
     }
+    // Two-step tiles also list, per tile, every node inside its strip and
+    // rows [z0 - 4, z1 + 4), where the first of the two steps is computed.
+    std::vector<RawEnt> se1, re1;
+    if (two) {
+        auto widen = [&](const std::vector<RawEnt> &v, std::vector<RawEnt> &out) {
+            for (const RawEnt &e : v) {
+                const ShotIn &S = J.shots[e.shot];
+                const int NZr = S.g.L.NZr;
+                const int ns = (S.g.NX + strip - 1) / strip;
+                const int nzs = (NZr + T.tune.zseg - 1) / T.tune.zseg;
+                int tb = 0;  // first tile of the shot
+                for (int q = 0; q < e.shot; ++q) {
+                    const ShotIn &o = J.shots[q];
+                    tb += ((o.g.NX + strip - 1) / strip) * ((o.g.L.NZr + T.tune.zseg - 1) / T.tune.zseg);
+                }
+                const int jc = (e.x + 4) / strip, zc = e.z / T.tune.zseg;
+                for (int zs = std::max(0, zc - 1); zs <= std::min(nzs - 1, zc + 1); ++zs)
+                    for (int j = std::max(0, jc - 2); j <= std::min(ns - 1, jc + 1); ++j) {
+                        const int x0 = j * strip - 4;
+                        const int z0 = zs * T.tune.zseg, z1 = std::min(z0 + T.tune.zseg, NZr);
+                        if (e.x >= x0 && e.x < x0 + span && e.z >= z0 - 4 && e.z < z1 + 4) {
+                            RawEnt w = e;
+                            w.tile = tb + zs * ns + j;
+                            out.push_back(w);
+                        }
+                    }
+            }
+        };
+        widen(se, se1);
+        widen(re, re1);
+    }
     auto order = [](const RawEnt &a, const RawEnt &b) {
         return std::tie(a.tile, a.z, a.y, a.x) < std::tie(b.tile, b.z, b.y, b.x);
     };
     std::sort(se.begin(), se.end(), order);
     std::sort(re.begin(), re.end(), order);
-    for (auto &t : T.tiles) t.sbeg = t.send = t.rbeg = t.rend = 0;
+    std::sort(se1.begin(), se1.end(), order);
+    std::sort(re1.begin(), re1.end(), order);
+    for (auto &t : T.tiles) t.sbeg = t.send = t.rbeg = t.rend = t.s1beg = t.s1end = t.r1beg = t.r1end = 0;
     for (auto &t : T.tiles3) t.sbeg = t.send = t.rbeg = t.rend = 0;
-    auto emit = [&](std::vector<RawEnt> &v, bool is_src) {
+    // kind: 0 source, 1 receivers, 2 source (first step), 3 receivers (first step)
+    auto emit = [&](std::vector<RawEnt> &v, int kind) {
         for (auto &e : v) {
             InjEnt E{e.z, e.y, e.x, (int)T.cont.size(), 0, e.slot, e.shot, 0};
             for (auto &c : e.c) T.cont.push_back(c);
             E.cend = (int)T.cont.size();
             const int idx = (int)T.ents.size();
             T.ents.push_back(E);
-            int *sb, *sn, *rb, *rn;
+            int *b, *n;
             if (T.ndim == 3) {
                 Tile3D &t = T.tiles3[e.tile];
-                sb = &t.sbeg; sn = &t.send; rb = &t.rbeg; rn = &t.rend;
+                b = kind == 0 ? &t.sbeg : &t.rbeg;
+                n = kind == 0 ? &t.send : &t.rend;
             } else {
                 Tile2D &t = T.tiles[e.tile];
-                sb = &t.sbeg; sn = &t.send; rb = &t.rbeg; rn = &t.rend;
+                int *bs[4] = {&t.sbeg, &t.rbeg, &t.s1beg, &t.r1beg};
+                int *ns_[4] = {&t.send, &t.rend, &t.s1end, &t.r1end};
+                b = bs[kind];
+                n = ns_[kind];
             }
-            if (is_src) {
-                if (*sn == *sb) *sb = idx;
-                *sn = idx + 1;
-            } else {
-                if (*rn == *rb) *rb = idx;
-                *rn = idx + 1;
-            }
+            if (*n == *b) *b = idx;
+            *n = idx + 1;
         }
     };
-    emit(se, true);
+    emit(se, 0);
     T.nsrc_ent = (int)se.size();
-    emit(re, false);
+    emit(re, 1);
     T.nrec_ent = (int)re.size();
+    emit(se1, 2);
+    emit(re1, 3);
     T.nslots = (T.count() + kNumXcd - 1) / kNumXcd * kNumXcd;
     return RTM_OK;
 }
@@ -488,7 +564,9 @@ int64_t count_tiles(const Job &J, Tune t)
     int64_t n = 0;
     for (const ShotIn &S : J.shots) {
         const int64_t ny = S.g.ndim == 3 ? (S.g.NY + t.ty - 1) / t.ty * t.ty : 1;  // wavefronts per column
-        n += (int64_t)((S.g.NX + 64 * t.vec - 1) / (64 * t.vec)) * ny * ((S.g.L.NZr + t.zseg - 1) / t.zseg);
+        const int64_t wx = S.g.ndim == 2 ? t.tx : 1;                                   // wavefronts per strip group
+        n += (int64_t)((S.g.NX + 64 * t.vec * wx - 1) / (64 * t.vec * wx)) * wx * ny *
+             ((S.g.L.NZr + t.zseg - 1) / t.zseg);
     }
     return n;
 }
@@ -556,7 +634,7 @@ int build_job_tables(Job &J)
         J.dslot.push_back(slot);
     }
     const int ndim = J.shots[0].g.ndim;
-    J.fw.ndim = J.rv.ndim = ndim;
+    J.fw.ndim = J.rv.ndim = J.fw2.ndim = J.rv2.ndim = ndim;
     J.fw.tune = fit_tune(J, get_tune(0, ndim));
     int rc = build_tiling(J, J.fw, false);
     if (rc) return rc;
@@ -564,6 +642,21 @@ int build_job_tables(Job &J)
         J.rv.tune = fit_tune(J, get_tune(1, ndim));
         rc = build_tiling(J, J.rv, true);
         if (rc) return rc;
+    }
+    // Two-step tilings (2-D): the forward one for every op, the reverse one
+    // for imaging only (the gradient pass runs one step per launch).
+    J.fw2 = Tiling{};
+    J.rv2 = Tiling{};
+    J.fw2.ndim = J.rv2.ndim = ndim;
+    if (ndim == 2 && J.fw.tune.steps == 2) {
+        J.fw2.tune = J.fw.tune;
+        J.fw2.two_step = true;
+        if ((rc = build_tiling(J, J.fw2, false))) return rc;
+    }
+    if (ndim == 2 && J.op == RTM_OP_RTM && J.rv.tune.steps == 2) {
+        J.rv2.tune = J.rv.tune;
+        J.rv2.two_step = true;
+        if ((rc = build_tiling(J, J.rv2, true))) return rc;
     }
     return RTM_OK;
 }
@@ -577,6 +670,12 @@ Counts exact_counts(const Job &J)
     c.tiles_r = J.rv.count();
     c.ents_r = J.rv.ents.size();
     c.cont_r = J.rv.cont.size();
+    c.tiles_f2 = J.fw2.count();
+    c.ents_f2 = J.fw2.ents.size();
+    c.cont_f2 = J.fw2.cont.size();
+    c.tiles_r2 = J.rv2.count();
+    c.ents_r2 = J.rv2.ents.size();
+    c.cont_r2 = J.rv2.cont.size();
     c.stasks = J.stasks.size();
     c.rnode = J.rnode.size() / kMaxNodes;
     return c;
@@ -592,6 +691,17 @@ Counts bound_counts(const GridInfo &g, int op, int nrec)
         c.tiles_r = max_tiles(g);
         c.ents_r = c.cont_r = kMaxNodes + (int64_t)kMaxNodes * nrec;
     }
+    if (g.ndim == 2) {
+        // two-step strips own >= 56 columns; a node lies in at most 2 strips
+        // x 2 tiles in z for the first step plus its owner: 5 entries
+        const int64_t t2 = ((g.NX + 55) / 56) * (g.L.NZr / kMinZseg);
+        c.tiles_f2 = t2;
+        c.ents_f2 = c.cont_f2 = 5 * kMaxNodes;
+        if (op == RTM_OP_RTM) {
+            c.tiles_r2 = t2;
+            c.ents_r2 = c.cont_r2 = 5 * (kMaxNodes + (int64_t)kMaxNodes * nrec);
+        }
+    }
     c.stasks = (nrec + 63) / 64;
     c.rnode = nrec;
     return c;
@@ -604,14 +714,18 @@ struct Dev {
     T *at(size_t off) const { return (T *)(base + off); }
 };
 
+// Two shot tables: out[0 .. nsh) addresses the field sets in order, out[nsh
+// .. 2 nsh) with the sets exchanged (current levels after an odd number of
+// two-step launches).
 void fill_shot_devs(const Job &J, const Dev &D, std::vector<ShotDev> &out)
 {
-    out.resize(J.shots.size());
-    for (size_t i = 0; i < J.shots.size(); ++i) {
+    const size_t nsh = J.shots.size();
+    out.resize(2 * nsh);
+    for (size_t i = 0; i < nsh; ++i) {
         const ShotIn &S = J.shots[i];
         ShotDev &d = out[i];
         std::memset(&d, 0, sizeof d);
-        for (int k = 0; k < nfields(J.op); ++k) d.fld[k] = D.at<float>(J.ws.fld[i][k]);
+        for (int k = 0; k < 8; ++k) d.fld[k] = J.ws.fld[i][k] ? D.at<float>(J.ws.fld[i][k]) : nullptr;
         d.acc0 = J.op == RTM_OP_MODEL ? nullptr : D.at<float>(J.ws.acc0[i]);
         d.acc1 = J.op == RTM_OP_RTM ? D.at<float>(J.ws.acc1[i]) : nullptr;
         d.Dp = D.at<float>(J.ws.dp[J.dslot[i]]);
@@ -629,6 +743,9 @@ void fill_shot_devs(const Job &J, const Dev &D, std::vector<ShotDev> &out)
         d.iz0 = S.g.nb;
         d.iz1 = S.g.nb + (int)S.g.nz;
         d.L = S.g.L;
+        ShotDev &x = out[nsh + i];
+        x = d;
+        for (int k = 0; k < 8; ++k) x.fld[k] = d.fld[k ^ 4];
     }
 }
 
@@ -655,6 +772,12 @@ int job_upload_and_check(const Job &J, const Dev &D, std::vector<ShotDev> &shot_
     if ((rc = upload(D, J.ws.tiles_r, J.rv.tiles, st))) return rc;
     if ((rc = upload(D, J.ws.ents_r, J.rv.ents, st))) return rc;
     if ((rc = upload(D, J.ws.cont_r, J.rv.cont, st))) return rc;
+    if ((rc = upload(D, J.ws.tiles_f2, J.fw2.tiles, st))) return rc;
+    if ((rc = upload(D, J.ws.ents_f2, J.fw2.ents, st))) return rc;
+    if ((rc = upload(D, J.ws.cont_f2, J.fw2.cont, st))) return rc;
+    if ((rc = upload(D, J.ws.tiles_r2, J.rv2.tiles, st))) return rc;
+    if ((rc = upload(D, J.ws.ents_r2, J.rv2.ents, st))) return rc;
+    if ((rc = upload(D, J.ws.cont_r2, J.rv2.cont, st))) return rc;
     if ((rc = upload(D, J.ws.stasks, J.stasks, st))) return rc;
     if ((rc = upload(D, J.ws.rnode, J.rnode, st))) return rc;
     if ((rc = upload(D, J.ws.rw, J.rw, st))) return rc;
@@ -693,17 +816,30 @@ int job_upload_and_check(const Job &J, const Dev &D, std::vector<ShotDev> &shot_
 // kernel launches only).
 int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *probe, bool timed)
 {
-    const ShotDev *shots = D.at<ShotDev>(J.ws.shots);
+    const ShotDev *table = D.at<ShotDev>(J.ws.shots);
     const int nsh = (int)J.shots.size();
     const int nt = J.nt;
+    // Current shot table: 0 while the latest levels are in the first field
+    // set, 1 after an odd number of two-step launches.
+    int cur = 0;
+    auto SH = [&]() { return table + (size_t)cur * nsh; };
+    auto fld_of = [&](int i, int k) { return D.at<float>(J.ws.fld[i][cur ? (k ^ 4) : k]); };
     unsigned *scal = D.at<unsigned>(J.ws.scal);
+    // Two-step launches write the second field set: every level they touch
+    // must have a buffer.
+    for (int i = 0; i < nsh; ++i) {
+        const bool need_p = J.fw2.two_step || J.rv2.two_step, need_mu = J.rv2.two_step;
+        if ((need_p && !(J.ws.fld[i][4] && J.ws.fld[i][5])) || (need_mu && !(J.ws.fld[i][6] && J.ws.fld[i][7])))
+            return fail(RTM_EINVAL, "internal: shot %d lacks the second field set of two-step launches", i);
+    }
     for (int d = 0; d < (int)J.slot_shot.size(); ++d) {
         const ShotIn &S = J.shots[J.slot_shot[d]];
         RTM_HIP(launch_build_dp(S.g.L, S.v_pad, (float)(J.dt / S.g.h), D.at<float>(J.ws.dp[d]), st));
     }
     for (int i = 0; i < nsh; ++i) {
         const int64_t F = J.shots[i].g.L.total;
-        for (int k = 0; k < nfields(J.op); ++k) RTM_HIP(launch_fill(D.at<float>(J.ws.fld[i][k]), F, 0.f, st));
+        for (int k = 0; k < 8; ++k)
+            if (J.ws.fld[i][k]) RTM_HIP(launch_fill(D.at<float>(J.ws.fld[i][k]), F, 0.f, st));
         if (J.op != RTM_OP_MODEL) RTM_HIP(launch_fill(D.at<float>(J.ws.acc0[i]), F, 0.f, st));
         if (J.op == RTM_OP_RTM) RTM_HIP(launch_fill(D.at<float>(J.ws.acc1[i]), F, 0.f, st));
         if (J.op == RTM_OP_VJP && J.shots[i].grad_wavelet)
@@ -720,54 +856,79 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
         const SampleTask *stasks = D.at<SampleTask>(J.ws.stasks);
         const int ntiles = J.fw.count();
         const int nsample = sample ? (int)J.stasks.size() : 0;
-        LoopTimer timer(sample ? kLoopModelFwd : kLoopRtmFwd, nt, st, timed);
-        for (int n = 0; n < nt; ++n) {
+        const bool two = J.fw.ndim == 2 && J.fw2.two_step;
+        LoopTimer timer(sample ? kLoopModelFwd : kLoopRtmFwd, two ? nt / 2 + nt % 2 : nt, st, timed);
+        int n = 0;
+        if (two) {
+            // steps n, n + 1 per launch; each launch records d^{n-1}, d^n
+            for (; n + 2 <= nt; n += 2) {
+                RTM_HIP(launch_fwd2d_t2(J.fw2.tune.vec, SH(), D.at<Tile2D>(J.ws.tiles_f2), J.fw2.count(),
+                                        J.fw2.nslots, D.at<InjEnt>(J.ws.ents_f2), D.at<Contrib>(J.ws.cont_f2),
+                                        sample ? stasks : nullptr, nsample, n, st));
+                cur ^= 1;
+            }
+            // an odd last step overwrites level n - 1: record it first
+            if (sample && n < nt && n >= 1) RTM_HIP(launch_sample(SH(), stasks, nsample, n - 1, st));
+        }
+        for (; n < nt; ++n) {
             if (J.fw.ndim == 3)
-                RTM_HIP(launch_fwd3d(J.fw.tune.vec, J.fw.tune.ty, shots, (const Tile3D *)tiles, ntiles, J.fw.nslots,
+                RTM_HIP(launch_fwd3d(J.fw.tune.vec, J.fw.tune.ty, SH(), (const Tile3D *)tiles, ntiles, J.fw.nslots,
                                      ents, cont, sample ? stasks : nullptr, nsample, n, st));
             else
-                RTM_HIP(launch_fwd2d(J.fw.tune.vec, shots, tiles, ntiles, J.fw.nslots, ents, cont,
+                RTM_HIP(launch_fwd2d(J.fw.tune.vec, J.fw.tune.tx, SH(), tiles, ntiles, J.fw.nslots, ents, cont,
                                      sample ? stasks : nullptr, nsample, n, st));
         }
         timer.finish();
-        if (sample) RTM_HIP(launch_sample(shots, stasks, (int)J.stasks.size(), nt, st));
+        if (sample) {
+            if (two && nt % 2 == 0 && nt >= 2) RTM_HIP(launch_sample(SH(), stasks, nsample, nt - 1, st));
+            RTM_HIP(launch_sample(SH(), stasks, nsample, nt, st));
+        }
     }
     if (J.op == RTM_OP_MODEL) {
         for (int i = 0; i < nsh; ++i) {
             const ShotIn &S = J.shots[i];
             RTM_HIP(launch_transpose(D.at<float>(J.ws.trint[i]), S.traces_out, nt + 1, S.nrec, st));
-            if (S.p_last) RTM_HIP(launch_unpack(S.g.L, D.at<float>(J.ws.fld[i][nt & 1]), S.p_last, st));
-            if (S.p_prev) RTM_HIP(launch_unpack(S.g.L, D.at<float>(J.ws.fld[i][(nt + 1) & 1]), S.p_prev, st));
+            if (S.p_last) RTM_HIP(launch_unpack(S.g.L, fld_of(i, nt & 1), S.p_last, st));
+            if (S.p_prev) RTM_HIP(launch_unpack(S.g.L, fld_of(i, (nt + 1) & 1), S.p_prev, st));
         }
         return RTM_OK;
     }
     // Reverse pass (Algorithm 3): mu^{nt} = D' h^2 R^T g^{nt}, mu^{nt+1} = 0,
-    // then one fused launch per step k = nt-1 .. 0.
+    // then one fused launch per step k = nt-1 .. 0 (or per pair of steps).
     const bool grad = J.op == RTM_OP_VJP;
     const Tile2D *tiles = D.at<Tile2D>(J.ws.tiles_r);
     const InjEnt *ents = D.at<InjEnt>(J.ws.ents_r);
     const Contrib *cont = D.at<Contrib>(J.ws.cont_r);
-    RTM_HIP(launch_inj_set(shots, ents, J.rv.nsrc_ent, J.rv.nsrc_ent + J.rv.nrec_ent, cont, nt, st));
+    RTM_HIP(launch_inj_set(SH(), ents, J.rv.nsrc_ent, J.rv.nsrc_ent + J.rv.nrec_ent, cont, nt, st));
     const int ntiles = J.rv.count();
     const int reinject = (J.flags & RTM_F_NO_REINJECT) ? 0 : 1;
     const bool probing = probe && probe->snap_k >= 0;
+    const bool two = J.rv.ndim == 2 && J.rv2.two_step && !grad && !probing;
     // wadj is recorded for a single-shot job only (its kernel argument is one
     // buffer); batched VJPs do not return wavelet gradients.
     float *wadj = (grad && nsh == 1 && J.shots[0].grad_wavelet) ? D.at<float>(J.ws.wadj[0]) : nullptr;
-    LoopTimer timer(grad ? kLoopRevGrad : kLoopRevImage, nt, st, timed && !probing);
-    for (int k = nt - 1; k >= 0; --k) {
+    LoopTimer timer(grad ? kLoopRevGrad : kLoopRevImage, two ? nt / 2 + nt % 2 : nt, st, timed && !probing);
+    int k = nt - 1;
+    if (two) {
+        for (; k >= 1; k -= 2) {
+            RTM_HIP(launch_rev2d_t2(J.rv2.tune.vec, SH(), D.at<Tile2D>(J.ws.tiles_r2), J.rv2.count(), J.rv2.nslots,
+                                    D.at<InjEnt>(J.ws.ents_r2), D.at<Contrib>(J.ws.cont_r2), k, reinject, st));
+            cur ^= 1;
+        }
+    }
+    for (; k >= 0; --k) {
         if (J.rv.ndim == 3)
-            RTM_HIP(launch_rev3d(J.rv.tune.vec, J.rv.tune.ty, grad, shots, (const Tile3D *)tiles, ntiles, J.rv.nslots,
+            RTM_HIP(launch_rev3d(J.rv.tune.vec, J.rv.tune.ty, grad, SH(), (const Tile3D *)tiles, ntiles, J.rv.nslots,
                                  ents, cont, k, reinject, wadj, st));
         else
-            RTM_HIP(launch_rev2d(J.rv.tune.vec, grad, shots, tiles, ntiles, J.rv.nslots, ents, cont, k, reinject,
-                                 wadj, st));
+            RTM_HIP(launch_rev2d(J.rv.tune.vec, J.rv.tune.tx, grad, SH(), tiles, ntiles, J.rv.nslots, ents, cont, k,
+                                 reinject, wadj, st));
         if (probing) {
             const ShotIn &S = J.shots[0];
             if (k - 1 == probe->snap_k && probe->snap_p)
-                RTM_HIP(launch_unpack(S.g.L, D.at<float>(J.ws.fld[0][(k - 1) & 1]), probe->snap_p, st));
+                RTM_HIP(launch_unpack(S.g.L, fld_of(0, (k - 1) & 1), probe->snap_p, st));
             if (k == probe->snap_k && probe->snap_mu)
-                RTM_HIP(launch_unpack(S.g.L, D.at<float>(J.ws.fld[0][2 + (k & 1)]), probe->snap_mu, st));
+                RTM_HIP(launch_unpack(S.g.L, fld_of(0, 2 + (k & 1)), probe->snap_mu, st));
         }
     }
     timer.finish();
@@ -776,11 +937,11 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
     for (int i = 0; i < nsh; ++i) {
         const ShotIn &S = J.shots[i];
         if (grad) {
-            RTM_HIP(launch_grad(shots, i, (int64_t)S.g.NX * S.g.NY * S.g.NZ, S.v_pad, (float)J.dt, S.grad_v_pad, st));
+            RTM_HIP(launch_grad(SH(), i, (int64_t)S.g.NX * S.g.NY * S.g.NZ, S.v_pad, (float)J.dt, S.grad_v_pad, st));
             if (S.grad_wavelet && nsh == 1)
                 RTM_HIP(launch_wadj(D.at<float>(J.ws.wadj[i]), nt, (float)(1.0 / (S.g.h * S.g.h)), S.grad_wavelet, st));
         } else {
-            RTM_HIP(launch_image(shots, i, S.g.nx * S.g.ny * S.g.nz, scal + 64 + 2 * J.slot_shot.size() + i, J.eps,
+            RTM_HIP(launch_image(SH(), i, S.g.nx * S.g.ny * S.g.nz, scal + 64 + 2 * J.slot_shot.size() + i, J.eps,
                                  S.image, (J.flags & RTM_F_ACCUMULATE) ? 1 : 0, S.num, S.den, st));
         }
     }
@@ -888,10 +1049,49 @@ int rtm_set_tuning(int op, int vec, int zseg)
     if (vec != 1 && vec != 2 && vec != 4) return fail(RTM_EINVAL, "vec must be 1, 2 or 4");
     if (zseg < kMinZseg || zseg > 4095 || zseg % kZUnroll != 0)
         return fail(RTM_EINVAL, "zseg must be a multiple of %d in [%d, 4095]", kZUnroll, kMinZseg);
-    int packed = (vec << 16) | zseg;
-    if (op == RTM_OP_MODEL) g_tune2d_fwd = packed;
-    else if (op == RTM_OP_RTM || op == RTM_OP_VJP) g_tune2d_rev = packed;
-    else return fail(RTM_EINVAL, "unknown op %d", op);
+    if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
+    std::atomic<int> &g = op == RTM_OP_MODEL ? g_tune2d_fwd : g_tune2d_rev;
+    g = (g.load() & ~0xffffff) | (vec << 16) | zseg;  // keeps the strips per workgroup
+    return RTM_OK;
+}
+
+int rtm_set_tuning2d(int op, int vec, int tx, int zseg)
+{
+    if (vec != 1 && vec != 2 && vec != 4) return fail(RTM_EINVAL, "vec must be 1, 2 or 4");
+    if (tx != 1 && tx != 2 && tx != 4) return fail(RTM_EINVAL, "tx must be 1, 2 or 4");
+    if (zseg < kMinZseg || zseg > 4095 || zseg % kZUnroll != 0)
+        return fail(RTM_EINVAL, "zseg must be a multiple of %d in [%d, 4095]", kZUnroll, kMinZseg);
+    if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
+    std::atomic<int> &g = op == RTM_OP_MODEL ? g_tune2d_fwd : g_tune2d_rev;
+    g = (g.load() & (0x3 << 28)) | (tx << 24) | (vec << 16) | zseg;  // keeps the steps per launch
+    return RTM_OK;
+}
+
+int rtm_set_steps_per_launch(int op, int steps)
+{
+    if (steps != 1 && steps != 2) return fail(RTM_EINVAL, "steps must be 1 or 2");
+    if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
+    std::atomic<int> &g = op == RTM_OP_MODEL ? g_tune2d_fwd : g_tune2d_rev;
+    g = (g.load() & ~(0x3 << 28)) | ((steps - 1) << 28);
+    return RTM_OK;
+}
+
+int rtm_get_steps_per_launch(int op, int *steps)
+{
+    if (!steps) return fail(RTM_EINVAL, "NULL output");
+    if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
+    *steps = get_tune(op == RTM_OP_MODEL ? 0 : 1, 2).steps;
+    return RTM_OK;
+}
+
+int rtm_get_tuning2d(int op, int *vec, int *tx, int *zseg)
+{
+    if (!vec || !tx || !zseg) return fail(RTM_EINVAL, "NULL output");
+    if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
+    Tune t = get_tune(op == RTM_OP_MODEL ? 0 : 1, 2);
+    *vec = t.vec;
+    *tx = t.tx;
+    *zseg = t.zseg;
     return RTM_OK;
 }
 

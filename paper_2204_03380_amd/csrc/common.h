@@ -60,9 +60,13 @@ inline Layout make_layout(int ndim, int NX, int NY, int NZ)
 
 // Per-shot state seen by the propagation kernels.  Wavefields are
 // addressed through `fld`: p^m lives in fld[m & 1] and the receiver
-// wavefield mu^m in fld[2 + (m & 1)].
+// wavefield mu^m in fld[2 + (m & 1)].  fld[4 .. 7] (2-D jobs) are a second
+// set with the same roles: a two-step launch reads the first set and writes
+// the second, and the host then swaps to a copy of the shot table whose two
+// sets are exchanged, so every kernel keeps addressing the current levels
+// through fld[0 .. 3].
 struct ShotDev {
-    float *fld[4];
+    float *fld[8];
     float *acc0;        // num (imaging) or G (gradient)
     float *acc1;        // den (imaging) or unused
     const float *Dp;    // (v dt / h)^2, zero in the halo
@@ -80,11 +84,14 @@ struct ShotDev {
 // of 64 * VEC columns starting at x0; z1 - z0 is a multiple of kZUnroll
 // (rows at or below NZ are zero halo rows and stay zero).  Injection entries
 // of the tile are ents[sbeg, send) (source, into p) and ents[rbeg, rend)
-// (receivers, into mu).
+// (receivers, into mu).  A two-step tile also lists the entries of its
+// whole strip and rows [z0 - 4, z1 + 4) (where the first of its two steps
+// is computed) in ents[s1beg, s1end) and ents[r1beg, r1end).
 struct Tile2D {
     int shot;
     int x0, z0, z1;
     int sbeg, send, rbeg, rend;
+    int s1beg, s1end, r1beg, r1end;
 };
 
 // A 3-D stencil tile: a workgroup covers x in [x0, x0 + TX) and y in

@@ -35,17 +35,22 @@ struct FwdCtx {
     gfloat *po;        // p^{n-1}, overwritten by p^{n+1}
     const gfloat *Dp;
     int64_t pitch;
-    int x, x0, NX, lane;
+    int x, x0, NX, lane, w;  // x0: first cell of this wave's strip; w: wave in the workgroup
     bool live, own;
 };
 
 // Row z of the march.  Queue slot (S + i) % 9 holds row z - 4 + i; the slot
-// of row z + 4 is refilled here.
-template <int VEC, int S>
-__device__ __forceinline__ void fwd_row(const FwdCtx<VEC> &C, float (&q)[9][VEC], int z)
+// of row z + 4 is refilled here.  With TX strips per workgroup the inner
+// strip ends come from the edge ring (slot S holds row z); the workgroup
+// meets at a barrier every third row, which orders each ring write (row
+// z + 4, end of this step) before its read four steps later and each read
+// before the slot is rewritten five steps later.
+template <int VEC, int TX, int S>
+__device__ __forceinline__ void fwd_row(const FwdCtx<VEC> &C, float (&q)[9][VEC], int z, EdgeRing<TX> &R)
 {
     constexpr int r0 = (S + 0) % 9, r1 = (S + 1) % 9, r2 = (S + 2) % 9, r3 = (S + 3) % 9, r4 = (S + 4) % 9,
                   r5 = (S + 5) % 9, r6 = (S + 6) % 9, r7 = (S + 7) % 9, r8 = (S + 8) % 9;
+    if constexpr (TX > 1 && S % 3 == 0) __syncthreads();
     const int64_t o = (int64_t)z * C.pitch + C.x;
     float old[VEC], d[VEC];
 #pragma unroll
@@ -56,7 +61,8 @@ __device__ __forceinline__ void fwd_row(const FwdCtx<VEC> &C, float (&q)[9][VEC]
         ldv<VEC>(C.Dp + o, d);
     }
     float hl[4], hr[4], ext[VEC + 8];
-    load_halo<VEC>(C.pc + (int64_t)z * C.pitch, C.x0, C.NX, C.lane, hl, hr);
+    load_halo_outer<VEC>(C.pc + (int64_t)z * C.pitch, C.x0, C.NX, C.lane, C.w == 0, C.w == TX - 1, hl, hr);
+    ring_get<TX>(R, S, C.w, C.lane, hl, hr);
     exchange_row<VEC>(q[r4], hl, hr, ext);
     float out[VEC];
 #pragma unroll
@@ -67,6 +73,7 @@ __device__ __forceinline__ void fwd_row(const FwdCtx<VEC> &C, float (&q)[9][VEC]
         out[j] = fmaf(d[j], lap, c2 - old[j]);
     }
     if (C.own) stv<VEC>(C.po + o, out);
+    if constexpr (TX > 1) ring_put<VEC, TX>(R, (S + 4) % 9, C.w, C.lane, q[r8]);
 }
 
 // --------------------------------------------------------------------------
@@ -82,15 +89,17 @@ struct RevCtx {
     const gfloat *Dp;
     gfloat *A0, *A1;   // num, den | G
     int64_t pitch;
-    int x, x0, NX, lane, iz0, iz1;
+    int x, x0, NX, lane, w, iz0, iz1;
     bool live, own, own_img, reinject;
 };
 
-template <int VEC, bool GRAD, int S>
-__device__ __forceinline__ void rev_row(const RevCtx<VEC> &C, float (&qp)[9][VEC], float (&qm)[9][VEC], int z)
+template <int VEC, bool GRAD, int TX, int S>
+__device__ __forceinline__ void rev_row(const RevCtx<VEC> &C, float (&qp)[9][VEC], float (&qm)[9][VEC], int z,
+                                        EdgeRing<TX> &RP, EdgeRing<TX> &RM)
 {
     constexpr int r0 = (S + 0) % 9, r1 = (S + 1) % 9, r2 = (S + 2) % 9, r3 = (S + 3) % 9, r4 = (S + 4) % 9,
                   r5 = (S + 5) % 9, r6 = (S + 6) % 9, r7 = (S + 7) % 9, r8 = (S + 8) % 9;
+    if constexpr (TX > 1 && S % 3 == 0) __syncthreads();
     const int64_t o = (int64_t)z * C.pitch + C.x;
     float p1[VEC], m1[VEC], d[VEC];
 #pragma unroll
@@ -104,18 +113,20 @@ __device__ __forceinline__ void rev_row(const RevCtx<VEC> &C, float (&qp)[9][VEC
     }
     float hl[4], hr[4], ext[VEC + 8];
     float np[VEC], nm[VEC], inc[VEC];
-    load_halo<VEC>(C.P0 + (int64_t)z * C.pitch, C.x0, C.NX, C.lane, hl, hr);
+    load_halo_outer<VEC>(C.P0 + (int64_t)z * C.pitch, C.x0, C.NX, C.lane, C.w == 0, C.w == TX - 1, hl, hr);
+    ring_get<TX>(RP, S, C.w, C.lane, hl, hr);
     exchange_row<VEC>(qp[r4], hl, hr, ext);
 #pragma unroll
     for (int j = 0; j < VEC; ++j) {
         const float c = qp[r4][j], c2 = c + c;
         float lap = d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
         lap += d2(c2, qp[r3][j], qp[r5][j], qp[r2][j], qp[r6][j], qp[r1][j], qp[r7][j], qp[r0][j], qp[r8][j]);
-        inc[j] = d[j] * lap;
-        np[j] = inc[j] + (c2 - p1[j]);
+        inc[j] = d[j] * lap;                 // gradient term (GRAD)
+        np[j] = fmaf(d[j], lap, c2 - p1[j]);  // same rounding as the two-step kernel
     }
     if (C.own) stv<VEC>(C.P1 + o, np);
-    load_halo<VEC>(C.M0 + (int64_t)z * C.pitch, C.x0, C.NX, C.lane, hl, hr);
+    load_halo_outer<VEC>(C.M0 + (int64_t)z * C.pitch, C.x0, C.NX, C.lane, C.w == 0, C.w == TX - 1, hl, hr);
+    ring_get<TX>(RM, S, C.w, C.lane, hl, hr);
     exchange_row<VEC>(qm[r4], hl, hr, ext);
 #pragma unroll
     for (int j = 0; j < VEC; ++j) {
@@ -147,6 +158,10 @@ __device__ __forceinline__ void rev_row(const RevCtx<VEC> &C, float (&qp)[9][VEC
             stv_s<VEC>(C.A1 + o, b);
         }
     }
+    if constexpr (TX > 1) {
+        ring_put<VEC, TX>(RP, (S + 4) % 9, C.w, C.lane, qp[r8]);
+        ring_put<VEC, TX>(RM, (S + 4) % 9, C.w, C.lane, qm[r8]);
+    }
 }
 
 // Runs ROWCALL(S, z) over the tile's rows, nine per trip (z1 - z0 is a
@@ -164,31 +179,36 @@ __device__ __forceinline__ void rev_row(const RevCtx<VEC> &C, float (&qp)[9][VEC
 // written over p^{n-1}; workgroups past the stencil slots record d^n = R p^n.
 // The source term is added to the stored value after the march by the lane
 // that stored it (same thread, so program order makes the value visible).
-template <int VEC>
-__global__ __launch_bounds__(64) void fwd2d_kernel(const ShotDev *__restrict__ shots,
-                                                   const Tile2D *__restrict__ tiles, int ntiles, int nslots,
-                                                   const InjEnt *__restrict__ ents,
-                                                   const Contrib *__restrict__ cont,
-                                                   const SampleTask *__restrict__ stasks, int n)
+// A workgroup of TX wavefronts covers TX adjacent strips of one tile.
+template <int VEC, int TX>
+__global__ __launch_bounds__(64 * TX) void fwd2d_kernel(const ShotDev *__restrict__ shots,
+                                                        const Tile2D *__restrict__ tiles, int ntiles, int nslots,
+                                                        const InjEnt *__restrict__ ents,
+                                                        const Contrib *__restrict__ cont,
+                                                        const SampleTask *__restrict__ stasks, int nsample, int n)
 {
     const int b = blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (b >= nslots) {
-        sample_body(shots, stasks[b - nslots], n, (int)threadIdx.x);
+        const int task = (b - nslots) * TX + w;
+        if (task < nsample) sample_body(shots, stasks[task], n, lane);
         return;
     }
     const int t = xcd_tile(b, nslots);
-    if (t >= ntiles) return;
+    if (t >= ntiles) return;  // whole workgroup
     const Tile2D T = tiles[t];
     const ShotDev &S = shots[T.shot];
+    __shared__ EdgeRing<TX> ring;
     FwdCtx<VEC> C;
     C.pitch = S.L.pitch;
     C.NX = S.L.NX;
     C.pc = gp(S.fld[n & 1] + S.L.org);
     C.po = gp(S.fld[(n + 1) & 1] + S.L.org);
     C.Dp = gp(S.Dp + S.L.org);
-    C.lane = threadIdx.x;
-    C.x0 = T.x0;
-    C.x = T.x0 + C.lane * VEC;
+    C.lane = lane;
+    C.w = w;
+    C.x0 = T.x0 + w * 64 * VEC;
+    C.x = C.x0 + lane * VEC;
     C.live = C.x < C.NX + kRadius;
     C.own = C.x < C.NX;
 
@@ -198,15 +218,19 @@ __global__ __launch_bounds__(64) void fwd2d_kernel(const ShotDev *__restrict__ s
 #pragma unroll
         for (int j = 0; j < VEC; ++j) q[i][j] = 0.f;
         if (C.live) ldv<VEC>(C.pc + (int64_t)(T.z0 - 4 + i) * C.pitch + C.x, q[i]);
+        // rows z0 .. z0 + 3 (queue slots 4..7, ring slots 0..3); the first
+        // march step opens with a barrier
+        if constexpr (TX > 1)
+            if (i >= 4) ring_put<VEC, TX>(ring, i - 4, w, lane, q[i]);
     }
-#define RTM_FWD_ROW(SS, ZZ) fwd_row<VEC, SS>(C, q, ZZ)
+#define RTM_FWD_ROW(SS, ZZ) fwd_row<VEC, TX, SS>(C, q, ZZ, ring)
     RTM_MARCH(RTM_FWD_ROW)
 #undef RTM_FWD_ROW
     // Source injection: p^{n+1} += D' s^n at the source nodes of this tile.
     const float *wav = S.wav + n;
     for (int e = T.sbeg; e < T.send; ++e) {
         const InjEnt E = ents[e];
-        if (owns<VEC>(E.x, T.x0, C.lane)) {
+        if (owns<VEC>(E.x, C.x0, C.lane)) {
             const int64_t o = (int64_t)E.z * C.pitch + E.x;
             C.po[o] = fmaf(C.Dp[o], inj_sum(E, cont, wav), C.po[o]);
         }
@@ -226,18 +250,18 @@ __global__ __launch_bounds__(64) void fwd2d_kernel(const ShotDev *__restrict__ s
 // With one float per lane the reverse kernel fits in 64 registers; asking
 // for 8 waves per SIMD then hides more latency (measured: 4.5 vs 4.2 TB/s
 // on 16 shots of the 2301 x 751 grid).  Wider lanes would spill.
-template <int VEC, bool GRAD>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VEC == 1 ? 8 : 1, 8)))
-void rev2d_kernel(const ShotDev *__restrict__ shots,
-                                                   const Tile2D *__restrict__ tiles, int ntiles, int nslots,
-                                                   const InjEnt *__restrict__ ents,
-                                                   const Contrib *__restrict__ cont, int k, int reinject,
-                                                   float *__restrict__ wadj)
+template <int VEC, bool GRAD, int TX>
+__global__ __launch_bounds__(64 * TX) __attribute__((amdgpu_waves_per_eu(VEC == 1 ? 8 : 1, 8)))
+void rev2d_kernel(const ShotDev *__restrict__ shots, const Tile2D *__restrict__ tiles, int ntiles, int nslots,
+                  const InjEnt *__restrict__ ents, const Contrib *__restrict__ cont, int k, int reinject,
+                  float *__restrict__ wadj)
 {
     const int t = xcd_tile(blockIdx.x, nslots);
-    if (t >= ntiles) return;
+    if (t >= ntiles) return;  // whole workgroup
     const Tile2D T = tiles[t];
     const ShotDev &S = shots[T.shot];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ EdgeRing<TX> ring_p, ring_m;
     RevCtx<VEC> C;
     C.pitch = S.L.pitch;
     C.NX = S.L.NX;
@@ -248,9 +272,10 @@ void rev2d_kernel(const ShotDev *__restrict__ shots,
     C.Dp = gp(S.Dp + S.L.org);
     C.A0 = gp(S.acc0 + S.L.org);
     C.A1 = GRAD ? nullptr : gp(S.acc1 + S.L.org);
-    C.lane = threadIdx.x;
-    C.x0 = T.x0;
-    C.x = T.x0 + C.lane * VEC;
+    C.lane = lane;
+    C.w = w;
+    C.x0 = T.x0 + w * 64 * VEC;
+    C.x = C.x0 + lane * VEC;
     C.live = C.x < C.NX + kRadius;
     C.own = C.x < C.NX;
     // Lanes whose cells overlap the interior accumulate the image sums (their
@@ -269,19 +294,24 @@ void rev2d_kernel(const ShotDev *__restrict__ shots,
             ldv<VEC>(C.P0 + (int64_t)(T.z0 - 4 + i) * C.pitch + C.x, qp[i]);
             ldv<VEC>(C.M0 + (int64_t)(T.z0 - 4 + i) * C.pitch + C.x, qm[i]);
         }
+        if constexpr (TX > 1)
+            if (i >= 4) {
+                ring_put<VEC, TX>(ring_p, i - 4, w, lane, qp[i]);
+                ring_put<VEC, TX>(ring_m, i - 4, w, lane, qm[i]);
+            }
     }
-#define RTM_REV_ROW(SS, ZZ) rev_row<VEC, GRAD, SS>(C, qp, qm, ZZ)
+#define RTM_REV_ROW(SS, ZZ) rev_row<VEC, GRAD, TX, SS>(C, qp, qm, ZZ, ring_p, ring_m)
     RTM_MARCH(RTM_REV_ROW)
 #undef RTM_REV_ROW
     // Source term at step k: reconstruction (re-injection), gradient, wavelet adjoint.
     const float *wav = S.wav + k;
     for (int e = T.sbeg; e < T.send; ++e) {
         const InjEnt E = ents[e];
-        if (owns<VEC>(E.x, T.x0, C.lane)) {
+        if (owns<VEC>(E.x, C.x0, C.lane)) {
             const int64_t o = (int64_t)E.z * C.pitch + E.x;
-            const float ds = C.Dp[o] * inj_sum(E, cont, wav);
-            if (C.reinject) C.P1[o] = C.P1[o] + ds;
-            if (GRAD) C.A0[o] = fmaf(C.M0[o], ds, C.A0[o]);
+            const float sv = inj_sum(E, cont, wav);
+            if (C.reinject) C.P1[o] = fmaf(C.Dp[o], sv, C.P1[o]);
+            if (GRAD) C.A0[o] = fmaf(C.M0[o], C.Dp[o] * sv, C.A0[o]);
             if (wadj) {
                 float wsum = 0.f;
                 for (int c = E.cbeg; c < E.cend; ++c) wsum += cont[c].w;
@@ -293,9 +323,406 @@ void rev2d_kernel(const ShotDev *__restrict__ shots,
     const float *sig = S.sig + (int64_t)k * S.nrec;
     for (int e = T.rbeg; e < T.rend; ++e) {
         const InjEnt E = ents[e];
-        if (owns<VEC>(E.x, T.x0, C.lane)) {
+        if (owns<VEC>(E.x, C.x0, C.lane)) {
             const int64_t o = (int64_t)E.z * C.pitch + E.x;
             C.M1[o] = fmaf(C.Dp[o], inj_sum(E, cont, sig), C.M1[o]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Two time steps per launch
+// ---------------------------------------------------------------------------
+// A wavefront covers the strip [xs, xs + 64 VEC) and owns its inner columns
+// [xs + 4, xs + 64 VEC - 4); neighbouring strips overlap by 8 columns.  It
+// marches s = 0 .. zseg + 8; at step s it
+//  (1) advances the first level at row r1 = z0 - 4 + s on the whole strip,
+//      from a register queue q1 of the level read from memory (rows r1 - 4
+//      .. r1 + 4) and that level's strip-end halo, as the one-step kernel;
+//  (2) advances the second level at row r2 = r1 - 4 from a queue q2 of the
+//      first-step rows just computed.  q2 has no halo beyond the strip, so
+//      its outer 4 columns are wrong and only owned columns are stored.
+// Row r of either level sits in queue slot (r - z0 + 8) mod 9, so both
+// queues rotate together.  Injection into the first step happens inside
+// the march in every tile whose strip and rows [z0 - 4, z1 + 4) contain the
+// node; injection into the second step after the march, by the owner.  The
+// arithmetic of every cell equals the one-step kernel's operation for
+// operation, so one launch of this kernel gives the same bits as two
+// launches of that one, with the level pairs read once and written once per
+// two steps (and the levels stay in two sets: read set, write set).
+template <int VEC>
+__device__ __forceinline__ bool own2(int x, int xs, int NX)
+{
+    return x >= xs + 4 && x + VEC <= xs + 64 * VEC - 4 && x < NX;
+}
+
+// Forward pair: level n+1 from (n, n-1), level n+2 from (n+1, n).
+template <int VEC>
+struct Fwd2Ctx {
+    const gfloat *pc, *pm;  // p^n, p^{n-1} (read set)
+    gfloat *w1, *w2;        // p^{n+1}, p^{n+2} (write set)
+    const gfloat *Dp;
+    const float *wav;       // wavelet from time n
+    const InjEnt *ents;
+    const Contrib *cont;
+    int64_t pitch;
+    int x, xs, NX, NZr, lane, z0, z1, e1end;
+    bool live, own;
+};
+
+template <int VEC, int S>
+__device__ __forceinline__ void fwd2_row(const Fwd2Ctx<VEC> &C, float (&q1)[9][VEC], float (&q2)[9][VEC],
+                                         float (&qd)[9][VEC], int s, int &e)
+{
+    constexpr int a0 = S % 9, a1 = (S + 1) % 9, a2 = (S + 2) % 9, a3 = (S + 3) % 9, a4 = (S + 4) % 9,
+                  a5 = (S + 5) % 9, a6 = (S + 6) % 9, a7 = (S + 7) % 9, a8 = (S + 8) % 9;
+    const int r1 = C.z0 - 4 + s, r2 = r1 - 4;
+    const bool in1 = r1 < C.NZr + kRadius, in_next = r1 + 4 < C.NZr + kRadius;  // stored rows: [-4, NZr + 4)
+    const int64_t o1 = (int64_t)r1 * C.pitch + C.x;
+    float old[VEC], d[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) q1[a8][j] = old[j] = d[j] = 0.f;
+    if (C.live && in_next) ldv<VEC>(C.pc + o1 + 4 * C.pitch, q1[a8]);
+    if (C.live && in1) {
+        ldv<VEC>(C.pm + o1, old);
+        ldv<VEC>(C.Dp + o1, d);
+    }
+    float hl[4], hr[4], ext[VEC + 8];
+    load_halo<VEC>(C.pc + (int64_t)r1 * C.pitch, C.xs, C.NX, C.lane, hl, hr, in1);
+    exchange_row<VEC>(q1[a4], hl, hr, ext);
+    float v1[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const float c = q1[a4][j], c2 = c + c;
+        float lap = d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
+        lap += d2(c2, q1[a3][j], q1[a5][j], q1[a2][j], q1[a6][j], q1[a1][j], q1[a7][j], q1[a0][j], q1[a8][j]);
+        v1[j] = fmaf(d[j], lap, c2 - old[j]);
+    }
+    for (; e < C.e1end && C.ents[e].z == r1; ++e) {  // source at time n, row r1
+        const InjEnt E = C.ents[e];
+        const float sv = inj_sum(E, C.cont, C.wav);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j)
+            if (E.x == C.x + j) v1[j] = fmaf(d[j], sv, v1[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        q2[a4][j] = v1[j];
+        qd[a4][j] = d[j];
+    }
+    if (C.own && r1 >= C.z0 && r1 < C.z1) stv<VEC>(C.w1 + o1, v1);
+    if (s >= 8 && r2 < C.z1) {
+        const float hz[4] = {0.f, 0.f, 0.f, 0.f};
+        exchange_row<VEC>(q2[a0], hz, hz, ext);
+        float v2[VEC];
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float c = q2[a0][j], c2 = c + c;
+            float lap =
+                d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
+            lap += d2(c2, q2[a8][j], q2[a1][j], q2[a7][j], q2[a2][j], q2[a6][j], q2[a3][j], q2[a5][j], q2[a4][j]);
+            v2[j] = fmaf(qd[a0][j], lap, c2 - q1[a0][j]);
+        }
+        if (C.own) stv<VEC>(C.w2 + (int64_t)r2 * C.pitch + C.x, v2);
+    }
+}
+
+// Runs ROWCALL(S, s) for s = 0 .. nstep - 1 (nstep a multiple of nine).
+#define RTM_MARCH2(ROWCALL, NSTEP)                                                             \
+    for (int s = 0; s < (NSTEP); s += kZUnroll) {                                              \
+        ROWCALL(0, s); ROWCALL(1, s + 1); ROWCALL(2, s + 2); ROWCALL(3, s + 3);                \
+        ROWCALL(4, s + 4); ROWCALL(5, s + 5); ROWCALL(6, s + 6); ROWCALL(7, s + 7);            \
+        ROWCALL(8, s + 8);                                                                     \
+    }
+
+// Steps n and n + 1 of every tile; workgroups past the stencil slots record
+// d^{n-1} (n > 0) and d^n from the read set.
+template <int VEC>
+__global__ __launch_bounds__(64) void fwd2d_t2_kernel(const ShotDev *__restrict__ shots,
+                                                      const Tile2D *__restrict__ tiles, int ntiles, int nslots,
+                                                      const InjEnt *__restrict__ ents,
+                                                      const Contrib *__restrict__ cont,
+                                                      const SampleTask *__restrict__ stasks, int nsample, int n)
+{
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (b >= nslots) {
+        const int t = b - nslots;
+        const int level = t < nsample ? n - 1 : n;
+        if (level >= 0) sample_body(shots, stasks[t < nsample ? t : t - nsample], level, lane);
+        return;
+    }
+    const int t = xcd_tile(b, nslots);
+    if (t >= ntiles) return;
+    const Tile2D T = tiles[t];
+    const ShotDev &S = shots[T.shot];
+    Fwd2Ctx<VEC> C;
+    C.pitch = S.L.pitch;
+    C.NX = S.L.NX;
+    C.NZr = S.L.NZr;
+    C.pc = gp(S.fld[n & 1] + S.L.org);
+    C.pm = gp(S.fld[(n + 1) & 1] + S.L.org);
+    C.w1 = gp(S.fld[4 + ((n + 1) & 1)] + S.L.org);
+    C.w2 = gp(S.fld[4 + (n & 1)] + S.L.org);
+    C.Dp = gp(S.Dp + S.L.org);
+    C.wav = S.wav + n;
+    C.ents = ents;
+    C.cont = cont;
+    C.lane = lane;
+    C.xs = T.x0;
+    C.x = T.x0 + lane * VEC;
+    C.z0 = T.z0;
+    C.z1 = T.z1;
+    C.e1end = T.s1end;
+    C.live = C.x >= -kRadius && C.x < C.NX + kRadius;
+    C.own = own2<VEC>(C.x, C.xs, C.NX);
+
+    float q1[9][VEC], q2[9][VEC], qd[9][VEC];
+    // level n rows z0 - 8 .. z0 - 1 (rows above -4 do not exist: zero)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) q1[i][j] = q2[i][j] = qd[i][j] = 0.f;
+        const int r = T.z0 - 8 + i;
+        if (C.live && r >= -kRadius) ldv<VEC>(C.pc + (int64_t)r * C.pitch + C.x, q1[i]);
+    }
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) q2[8][j] = qd[8][j] = 0.f;
+    int e = T.s1beg;
+    const int nstep = T.z1 - T.z0 + kZUnroll;
+#define RTM_FWD2_ROW(SS, ZZ) fwd2_row<VEC, SS>(C, q1, q2, qd, ZZ, e)
+    RTM_MARCH2(RTM_FWD2_ROW, nstep)
+#undef RTM_FWD2_ROW
+    // Source at time n + 1 into the owned cells of level n + 2.
+    const float *wav1 = S.wav + n + 1;
+    for (int k = T.sbeg; k < T.send; ++k) {
+        const InjEnt E = ents[k];
+        if (owns<VEC>(E.x, C.xs, lane)) {
+            const int64_t o = (int64_t)E.z * C.pitch + E.x;
+            C.w2[o] = fmaf(C.Dp[o], inj_sum(E, cont, wav1), C.w2[o]);
+        }
+    }
+}
+
+// Reverse pair (imaging): steps k and k - 1 of the reconstruction and the
+// receiver field, and both steps' imaging sums.
+template <int VEC>
+struct Rev2Ctx {
+    const gfloat *P0, *P1, *M0, *M1;  // p^k, p^{k+1}, mu^{k+1}, mu^{k+2} (read set)
+    gfloat *WP1, *WP2, *WM1, *WM2;    // p^{k-1}, p^{k-2}, mu^k, mu^{k-1} (write set)
+    const gfloat *Dp;
+    gfloat *A0, *A1;                  // num, den
+    const float *wav, *sig;           // wavelet and receiver signal at time k
+    const InjEnt *ents;
+    const Contrib *cont;
+    int64_t pitch;
+    int nrec;
+    int x, xs, NX, NZr, lane, z0, z1, iz0, iz1, s1end, r1end;
+    bool live, own, own_img, reinject;
+};
+
+template <int VEC, int S>
+__device__ __forceinline__ void rev2_row(const Rev2Ctx<VEC> &C, float (&q1p)[9][VEC], float (&q1m)[9][VEC],
+                                         float (&q2p)[9][VEC], float (&q2m)[9][VEC], float (&qd)[9][VEC],
+                                         float (&qa)[9][VEC], float (&qb)[9][VEC], int s, int &es, int &er)
+{
+    constexpr int a0 = S % 9, a1 = (S + 1) % 9, a2 = (S + 2) % 9, a3 = (S + 3) % 9, a4 = (S + 4) % 9,
+                  a5 = (S + 5) % 9, a6 = (S + 6) % 9, a7 = (S + 7) % 9, a8 = (S + 8) % 9;
+    const int r1 = C.z0 - 4 + s, r2 = r1 - 4;
+    const bool in1 = r1 < C.NZr + kRadius, in_next = r1 + 4 < C.NZr + kRadius;
+    const int64_t o1 = (int64_t)r1 * C.pitch + C.x;
+    float p1[VEC], m1[VEC], d[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) q1p[a8][j] = q1m[a8][j] = p1[j] = m1[j] = d[j] = 0.f;
+    if (C.live && in_next) {
+        ldv<VEC>(C.P0 + o1 + 4 * C.pitch, q1p[a8]);
+        ldv<VEC>(C.M0 + o1 + 4 * C.pitch, q1m[a8]);
+    }
+    if (C.live && in1) {
+        ldv_s<VEC>(C.P1 + o1, p1);
+        ldv_s<VEC>(C.M1 + o1, m1);
+        ldv_s<VEC>(C.Dp + o1, d);
+    }
+    const bool img1 = C.own_img && r1 >= C.z0 && r1 < C.z1 && r1 >= C.iz0 && r1 < C.iz1;
+    if (img1) {
+        ldv_s<VEC>(C.A0 + o1, qa[a4]);
+        ldv_s<VEC>(C.A1 + o1, qb[a4]);
+    }
+    float hl[4], hr[4], ext[VEC + 8];
+    float np[VEC], nm[VEC];
+    load_halo<VEC>(C.P0 + (int64_t)r1 * C.pitch, C.xs, C.NX, C.lane, hl, hr, in1);
+    exchange_row<VEC>(q1p[a4], hl, hr, ext);
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const float c = q1p[a4][j], c2 = c + c;
+        float lap = d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
+        lap += d2(c2, q1p[a3][j], q1p[a5][j], q1p[a2][j], q1p[a6][j], q1p[a1][j], q1p[a7][j], q1p[a0][j], q1p[a8][j]);
+        np[j] = fmaf(d[j], lap, c2 - p1[j]);
+    }
+    load_halo<VEC>(C.M0 + (int64_t)r1 * C.pitch, C.xs, C.NX, C.lane, hl, hr, in1);
+    exchange_row<VEC>(q1m[a4], hl, hr, ext);
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const float c = q1m[a4][j], c2 = c + c;
+        float lap = d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
+        lap += d2(c2, q1m[a3][j], q1m[a5][j], q1m[a2][j], q1m[a6][j], q1m[a1][j], q1m[a7][j], q1m[a0][j], q1m[a8][j]);
+        nm[j] = fmaf(d[j], lap, c2 - m1[j]);
+    }
+    if (img1) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            qa[a4][j] = fmaf(q1p[a4][j], q1m[a4][j], qa[a4][j]);
+            qb[a4][j] = fmaf(q1p[a4][j], q1p[a4][j], qb[a4][j]);
+        }
+    }
+    // time-k terms in row r1: source re-injection into p^{k-1}, receivers into mu^k
+    for (; es < C.s1end && C.ents[es].z == r1; ++es) {
+        const InjEnt E = C.ents[es];
+        const float sv = inj_sum(E, C.cont, C.wav);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j)
+            if (C.reinject && E.x == C.x + j) np[j] = fmaf(d[j], sv, np[j]);
+    }
+    for (; er < C.r1end && C.ents[er].z == r1; ++er) {
+        const InjEnt E = C.ents[er];
+        const float sv = inj_sum(E, C.cont, C.sig);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j)
+            if (E.x == C.x + j) nm[j] = fmaf(d[j], sv, nm[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        q2p[a4][j] = np[j];
+        q2m[a4][j] = nm[j];
+        qd[a4][j] = d[j];
+    }
+    if (C.own && r1 >= C.z0 && r1 < C.z1) {
+        stv<VEC>(C.WP1 + o1, np);
+        stv<VEC>(C.WM1 + o1, nm);
+    }
+    if (s >= 8 && r2 < C.z1) {
+        const float hz[4] = {0.f, 0.f, 0.f, 0.f};
+        const int64_t o2 = (int64_t)r2 * C.pitch + C.x;
+        float vp[VEC], vm[VEC];
+        exchange_row<VEC>(q2p[a0], hz, hz, ext);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float c = q2p[a0][j], c2 = c + c;
+            float lap =
+                d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
+            lap += d2(c2, q2p[a8][j], q2p[a1][j], q2p[a7][j], q2p[a2][j], q2p[a6][j], q2p[a3][j], q2p[a5][j],
+                      q2p[a4][j]);
+            vp[j] = fmaf(qd[a0][j], lap, c2 - q1p[a0][j]);
+        }
+        exchange_row<VEC>(q2m[a0], hz, hz, ext);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float c = q2m[a0][j], c2 = c + c;
+            float lap =
+                d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
+            lap += d2(c2, q2m[a8][j], q2m[a1][j], q2m[a7][j], q2m[a2][j], q2m[a6][j], q2m[a3][j], q2m[a5][j],
+                      q2m[a4][j]);
+            vm[j] = fmaf(qd[a0][j], lap, c2 - q1m[a0][j]);
+        }
+        if (C.own) {
+            stv<VEC>(C.WP2 + o2, vp);
+            stv<VEC>(C.WM2 + o2, vm);
+        }
+        if (C.own_img && r2 >= C.iz0 && r2 < C.iz1) {
+            float a[VEC], bb[VEC];
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                a[j] = fmaf(q2p[a0][j], q2m[a0][j], qa[a0][j]);
+                bb[j] = fmaf(q2p[a0][j], q2p[a0][j], qb[a0][j]);
+            }
+            stv_s<VEC>(C.A0 + o2, a);
+            stv_s<VEC>(C.A1 + o2, bb);
+        }
+    }
+}
+
+// One float per lane fits in 82 registers; asking for 5 waves per SIMD
+// keeps the compiler there (it otherwise allocates 128, i.e. 4 waves).
+template <int VEC>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VEC == 1 ? 5 : 1, 8)))
+void rev2d_t2_kernel(const ShotDev *__restrict__ shots,
+                                                      const Tile2D *__restrict__ tiles, int ntiles, int nslots,
+                                                      const InjEnt *__restrict__ ents,
+                                                      const Contrib *__restrict__ cont, int k, int reinject)
+{
+    const int t = xcd_tile(blockIdx.x, nslots);
+    if (t >= ntiles) return;
+    const Tile2D T = tiles[t];
+    const ShotDev &S = shots[T.shot];
+    const int lane = threadIdx.x;
+    Rev2Ctx<VEC> C;
+    C.pitch = S.L.pitch;
+    C.NX = S.L.NX;
+    C.NZr = S.L.NZr;
+    C.P0 = gp(S.fld[k & 1] + S.L.org);
+    C.P1 = gp(S.fld[(k + 1) & 1] + S.L.org);
+    C.M0 = gp(S.fld[2 + ((k + 1) & 1)] + S.L.org);
+    C.M1 = gp(S.fld[2 + (k & 1)] + S.L.org);
+    C.WP1 = gp(S.fld[4 + ((k + 1) & 1)] + S.L.org);
+    C.WP2 = gp(S.fld[4 + (k & 1)] + S.L.org);
+    C.WM1 = gp(S.fld[6 + (k & 1)] + S.L.org);
+    C.WM2 = gp(S.fld[6 + ((k + 1) & 1)] + S.L.org);
+    C.Dp = gp(S.Dp + S.L.org);
+    C.A0 = gp(S.acc0 + S.L.org);
+    C.A1 = gp(S.acc1 + S.L.org);
+    C.wav = S.wav + k;
+    C.sig = S.sig + (int64_t)k * S.nrec;
+    C.nrec = S.nrec;
+    C.ents = ents;
+    C.cont = cont;
+    C.lane = lane;
+    C.xs = T.x0;
+    C.x = T.x0 + lane * VEC;
+    C.z0 = T.z0;
+    C.z1 = T.z1;
+    C.iz0 = S.iz0;
+    C.iz1 = S.iz1;
+    C.s1end = T.s1end;
+    C.r1end = T.r1end;
+    C.live = C.x >= -kRadius && C.x < C.NX + kRadius;
+    C.own = own2<VEC>(C.x, C.xs, C.NX);
+    C.own_img = C.own && C.x + VEC > S.ix0 && C.x < S.ix1;
+    C.reinject = reinject != 0;
+
+    float q1p[9][VEC], q1m[9][VEC], q2p[9][VEC], q2m[9][VEC], qd[9][VEC], qa[9][VEC], qb[9][VEC];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j)
+            q1p[i][j] = q1m[i][j] = q2p[i][j] = q2m[i][j] = qd[i][j] = qa[i][j] = qb[i][j] = 0.f;
+        const int r = T.z0 - 8 + i;
+        if (i < 8 && C.live && r >= -kRadius) {
+            ldv<VEC>(C.P0 + (int64_t)r * C.pitch + C.x, q1p[i]);
+            ldv<VEC>(C.M0 + (int64_t)r * C.pitch + C.x, q1m[i]);
+        }
+    }
+    int es = T.s1beg, er = T.r1beg;
+    const int nstep = T.z1 - T.z0 + kZUnroll;
+#define RTM_REV2_ROW(SS, ZZ) rev2_row<VEC, SS>(C, q1p, q1m, q2p, q2m, qd, qa, qb, ZZ, es, er)
+    RTM_MARCH2(RTM_REV2_ROW, nstep)
+#undef RTM_REV2_ROW
+    // time k - 1 terms into the owned cells of p^{k-2} and mu^{k-1}
+    const float *wav1 = S.wav + (k - 1);
+    if (C.reinject) {
+        for (int e = T.sbeg; e < T.send; ++e) {
+            const InjEnt E = ents[e];
+            if (owns<VEC>(E.x, C.xs, lane)) {
+                const int64_t o = (int64_t)E.z * C.pitch + E.x;
+                C.WP2[o] = fmaf(C.Dp[o], inj_sum(E, cont, wav1), C.WP2[o]);
+            }
+        }
+    }
+    const float *sig1 = S.sig + (int64_t)(k - 1) * S.nrec;
+    for (int e = T.rbeg; e < T.rend; ++e) {
+        const InjEnt E = ents[e];
+        if (owns<VEC>(E.x, C.xs, lane)) {
+            const int64_t o = (int64_t)E.z * C.pitch + E.x;
+            C.WM2[o] = fmaf(C.Dp[o], inj_sum(E, cont, sig1), C.WM2[o]);
         }
     }
 }
@@ -304,42 +731,89 @@ void rev2d_kernel(const ShotDev *__restrict__ shots,
 // Host launchers
 // ---------------------------------------------------------------------------
 
-hipError_t launch_fwd2d(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+hipError_t launch_fwd2d(int vec, int tx, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                         const InjEnt *ents, const Contrib *cont, const SampleTask *stasks, int nsample, int n,
                         hipStream_t st)
 {
-    dim3 grid(nslots + nsample), block(64);
+    dim3 grid(nslots + (nsample + tx - 1) / tx), block(64 * tx);
+#define RTM_FWD2D(V, X) \
+    hipLaunchKernelGGL((fwd2d_kernel<V, X>), grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, stasks, nsample, n)
+#define RTM_FWD2D_X(V)                              \
+    switch (tx) {                                   \
+    case 1: RTM_FWD2D(V, 1); break;                 \
+    case 2: RTM_FWD2D(V, 2); break;                 \
+    case 4: RTM_FWD2D(V, 4); break;                 \
+    default: return hipErrorInvalidValue;           \
+    }
     switch (vec) {
-    case 1: hipLaunchKernelGGL(fwd2d_kernel<1>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, stasks, n); break;
-    case 2: hipLaunchKernelGGL(fwd2d_kernel<2>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, stasks, n); break;
-    case 4: hipLaunchKernelGGL(fwd2d_kernel<4>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, stasks, n); break;
+    case 1: RTM_FWD2D_X(1); break;
+    case 2: RTM_FWD2D_X(2); break;
+    case 4: RTM_FWD2D_X(4); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef RTM_FWD2D_X
+#undef RTM_FWD2D
+    return hipGetLastError();
+}
+
+hipError_t launch_rev2d(int vec, int tx, bool grad, const ShotDev *shots, const Tile2D *tiles, int ntiles,
+                        int nslots, const InjEnt *ents, const Contrib *cont, int k, int reinject, float *wadj,
+                        hipStream_t st)
+{
+    dim3 grid(nslots), block(64 * tx);
+#define RTM_REV2D(V, G, X) \
+    hipLaunchKernelGGL((rev2d_kernel<V, G, X>), grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject, wadj)
+#define RTM_REV2D_X(V, G)                           \
+    switch (tx) {                                   \
+    case 1: RTM_REV2D(V, G, 1); break;              \
+    case 2: RTM_REV2D(V, G, 2); break;              \
+    case 4: RTM_REV2D(V, G, 4); break;              \
+    default: return hipErrorInvalidValue;           \
+    }
+    if (grad) {
+        switch (vec) {
+        case 1: RTM_REV2D_X(1, true); break;
+        case 2: RTM_REV2D_X(2, true); break;
+        case 4: RTM_REV2D_X(4, true); break;
+        default: return hipErrorInvalidValue;
+        }
+    } else {
+        switch (vec) {
+        case 1: RTM_REV2D_X(1, false); break;
+        case 2: RTM_REV2D_X(2, false); break;
+        case 4: RTM_REV2D_X(4, false); break;
+        default: return hipErrorInvalidValue;
+        }
+    }
+#undef RTM_REV2D_X
+#undef RTM_REV2D
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+                           const InjEnt *ents, const Contrib *cont, const SampleTask *stasks, int nsample, int n,
+                           hipStream_t st)
+{
+    dim3 grid(nslots + 2 * nsample), block(64);
+    switch (vec) {
+    case 1: hipLaunchKernelGGL(fwd2d_t2_kernel<1>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, stasks, nsample, n); break;
+    case 2: hipLaunchKernelGGL(fwd2d_t2_kernel<2>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, stasks, nsample, n); break;
+    case 4: hipLaunchKernelGGL(fwd2d_t2_kernel<4>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, stasks, nsample, n); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_rev2d(int vec, bool grad, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
-                        const InjEnt *ents, const Contrib *cont, int k, int reinject, float *wadj, hipStream_t st)
+hipError_t launch_rev2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+                           const InjEnt *ents, const Contrib *cont, int k, int reinject, hipStream_t st)
 {
     dim3 grid(nslots), block(64);
-#define RTM_REV2D(V, G) \
-    hipLaunchKernelGGL((rev2d_kernel<V, G>), grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject, wadj)
-    if (grad) {
-        switch (vec) {
-        case 1: RTM_REV2D(1, true); break;
-        case 2: RTM_REV2D(2, true); break;
-        case 4: RTM_REV2D(4, true); break;
-        default: return hipErrorInvalidValue;
-        }
-    } else {
-        switch (vec) {
-        case 1: RTM_REV2D(1, false); break;
-        case 2: RTM_REV2D(2, false); break;
-        case 4: RTM_REV2D(4, false); break;
-        default: return hipErrorInvalidValue;
-        }
+    switch (vec) {
+    case 1: hipLaunchKernelGGL(rev2d_t2_kernel<1>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject); break;
+    case 2: hipLaunchKernelGGL(rev2d_t2_kernel<2>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject); break;
+    case 4: hipLaunchKernelGGL(rev2d_t2_kernel<4>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject); break;
+    default: return hipErrorInvalidValue;
     }
-#undef RTM_REV2D
     return hipGetLastError();
 }
 

@@ -160,6 +160,56 @@ __device__ __forceinline__ void load_halo(const gfloat *row, int x0, int NX, int
     hr[0] = right ? t.x : 0.f; hr[1] = right ? t.y : 0.f; hr[2] = right ? t.z : 0.f; hr[3] = right ? t.w : 0.f;
 }
 
+// Strip-end halo of one row for a wave inside a workgroup of strips: only
+// the workgroup's outer ends (do_left in the first wave, do_right in the
+// last) are loaded from memory; inner ends come from the edge ring.
+template <int VEC>
+__device__ __forceinline__ void load_halo_outer(const gfloat *row, int x0, int NX, int lane, bool do_left,
+                                                bool do_right, float (&hl)[4], float (&hr)[4])
+{
+    const int xr = x0 + 64 * VEC;
+    const bool left = do_left && lane == 0, right = do_right && lane == 63 && xr < NX + kRadius;
+    f4v t = f4v{0.f, 0.f, 0.f, 0.f};
+    if (left || right) t = *(const gf4v *)(row + (left ? x0 - 4 : xr));
+    hl[0] = left ? t.x : 0.f; hl[1] = left ? t.y : 0.f; hl[2] = left ? t.z : 0.f; hl[3] = left ? t.w : 0.f;
+    hr[0] = right ? t.x : 0.f; hr[1] = right ? t.y : 0.f; hr[2] = right ? t.z : 0.f; hr[3] = right ? t.w : 0.f;
+}
+
+// Edge ring of a workgroup of TX strip wavefronts (LDS): slot s, wave w
+// holds the 4 leftmost (side 0) and 4 rightmost (side 1) cells of one row of
+// the wave's strip.  A row is published when it enters the register queue
+// and read when it reaches the queue centre, four rows later.
+template <int TX>
+struct EdgeRing {
+    float v[9][TX][2][4];
+};
+
+template <int VEC, int TX>
+__device__ __forceinline__ void ring_put(EdgeRing<TX> &R, int s, int w, int lane, const float (&c)[VEC])
+{
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const int cl = lane * VEC + j;
+        if (cl < 4) R.v[s][w][0][cl] = c[j];
+        const int cr = cl - (64 * VEC - 4);
+        if (cr >= 0) R.v[s][w][1][cr] = c[j];
+    }
+}
+
+template <int TX>
+__device__ __forceinline__ void ring_get(const EdgeRing<TX> &R, int s, int w, int lane, float (&hl)[4],
+                                         float (&hr)[4])
+{
+    if (lane == 0 && w > 0) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) hl[k] = R.v[s][w - 1][1][k];
+    }
+    if (lane == 63 && w < TX - 1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) hr[k] = R.v[s][w + 1][0][k];
+    }
+}
+
 // Receivers [r0, r0 + 64) of one shot: d[n][r] = sum_q w_q p^n[node_q].
 __device__ __forceinline__ void sample_body(const ShotDev *__restrict__ shots, SampleTask task, int n, int lane)
 {

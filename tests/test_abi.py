@@ -54,6 +54,14 @@ def test_set_tuning_validation():
         rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 2)
     with pytest.raises(rtm.RtmError):
         rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 16)   # not a multiple of 9
+    old = rtm.rtm_get_tuning2d(rtm.RTM_OP_RTM)
+    with pytest.raises(rtm.RtmError):
+        rtm.rtm_set_tuning2d(rtm.RTM_OP_RTM, 1, 3, 9)    # tx must be 1, 2 or 4
+    rtm.rtm_set_tuning2d(rtm.RTM_OP_RTM, 2, 4, 27)
+    assert rtm.rtm_get_tuning2d(rtm.RTM_OP_RTM) == (2, 4, 27)
+    rtm.rtm_set_tuning(rtm.RTM_OP_RTM, 1, 9)              # keeps tx
+    assert rtm.rtm_get_tuning2d(rtm.RTM_OP_RTM) == (1, 4, 9)
+    rtm.rtm_set_tuning2d(rtm.RTM_OP_RTM, *old)
     rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 18)
 
 

@@ -53,8 +53,8 @@ def _setup(s):
 
 @pytest.fixture(autouse=True)
 def _default_tuning():
-    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 18)
-    rtm.rtm_set_tuning(rtm.RTM_OP_RTM, 1, 18)
+    rtm.rtm_set_tuning2d(rtm.RTM_OP_MODEL, 1, 1, 18)
+    rtm.rtm_set_tuning2d(rtm.RTM_OP_RTM, 1, 1, 18)
     yield
 
 
@@ -178,15 +178,49 @@ def test_tuning_invariance():
     d_obs = _t(oracle.model_shot(vo, s.h, s.nb, s.dt, s.wavelet.astype(np.float64), s.src[0], s.rec))
     outs = []
     rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
-    for vec, zseg in ((1, 18), (2, 9), (4, 27), (1, 9), (4, 63)):
-        rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, vec, zseg)
-        rtm.rtm_set_tuning(rtm.RTM_OP_RTM, vec, zseg)
+    # vec floats per lane, tx strips per workgroup (inner strip ends passed
+    # through LDS), zseg rows per tile
+    for vec, tx, zseg in ((1, 1, 18), (2, 2, 9), (4, 4, 27), (1, 4, 9), (4, 1, 63), (1, 2, 18), (2, 4, 36)):
+        rtm.rtm_set_tuning2d(rtm.RTM_OP_MODEL, vec, tx, zseg)
+        rtm.rtm_set_tuning2d(rtm.RTM_OP_RTM, vec, tx, zseg)
         tr = _n(rtm.rtm_model_shot(g, vg, s.dt, w, s.src[0], s.rec))
         im = _n(rtm.rtm_rtm_shot(g, vg, s.dt, w, s.src[0], s.rec, d_obs)["image"])
         outs.append((tr, im))
     rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 0, 0)
     for tr, im in outs[1:]:
         assert np.array_equal(tr, outs[0][0]) and np.array_equal(im, outs[0][1])
+
+
+@pytest.mark.parametrize("nt", [150, 151])
+def test_two_step_launches_bit_identical(nt):
+    """Two time steps per launch (overlapping strips, first step on a 4-cell
+    margin) give the same bits as one step per launch, for modeling (traces
+    and final panels) and RTM (num, den, image), for even and odd nt and
+    several strip widths; off-grid source and receivers near strip joins."""
+    s = synth.config_small2d(nx=150, nz=41, nb=10, nt=nt)
+    g, vg, vo = _setup(s)
+    w = _t(s.wavelet)
+    d_obs = _t(oracle.model_shot(vo, s.h, s.nb, s.dt, s.wavelet.astype(np.float64), s.src[0], s.rec))
+    rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
+    outs = []
+    try:
+        for steps, vec, zseg in ((1, 1, 18), (2, 1, 9), (2, 2, 18), (2, 4, 36), (2, 1, 27)):
+            for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
+                rtm.rtm_set_tuning2d(op, vec, 1, zseg)
+                rtm.rtm_set_steps_per_launch(op, steps)
+            tr, pl, pp = rtm.rtm_model_shot(g, vg, s.dt, w, s.src[0], s.rec, want_last=True)
+            out = rtm.rtm_rtm_shot(g, vg, s.dt, w, s.src[0], s.rec, d_obs, want_numden=True)
+            outs.append([_n(tr), _n(pl), _n(pp), _n(out["num"]), _n(out["den"]), _n(out["image"])])
+    finally:
+        rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 0, 0)
+        for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
+            rtm.rtm_set_steps_per_launch(op, 1)
+    ref = oracle.rtm_shot(vo, s.h, s.nb, s.dt, s.wavelet.astype(np.float64), s.src[0], s.rec,
+                          _n(d_obs).astype(np.float64), eps_rel=1e-3)
+    assert rel_l2(outs[0][5], ref["image"]) < TOL
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
 
 
 def test_edge_cases():
