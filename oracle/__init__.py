@@ -3,7 +3,7 @@
 Only tests/, the smoke check and the CPU-baseline leg of bench.py may import
 this package.  The product library never calls it: it is an independent,
 plain C implementation written from the paper (arXiv 2204.03380, Eqs. (1)-(3)
-and (6), Algorithms 1 and 3), used to prove the GPU path right.
+and (6), Algorithms 1 to 3 with the snapshot decimation of Eq. (7)), used to prove the GPU path right.
 
 Array conventions: padded fields are numpy arrays of shape (NZ, NX) in 2-D or
 (NZ, NY, NX) in 3-D; positions are (x, y, z) in interior grid units; traces
@@ -37,7 +37,10 @@ def _load():
                                        P, P, c_int, P, P, P, P, P]
         lib.orc_rtm_shot.argtypes = [c_int, c_long, c_long, c_long, c_int, c_double, P, c_double, c_int,
                                      P, P, c_int, P, P, c_int, c_double, P, P, P, P, P, c_int, P, P]
-        for f in ("orc_rbc_pad", "orc_pad_adjoint", "orc_laplacian", "orc_model_shot", "orc_rtm_shot"):
+        lib.orc_rtm_storage_shot.argtypes = [c_int, c_long, c_long, c_long, c_int, c_double, P, c_double, c_int,
+                                             P, P, c_int, P, P, c_int, c_int, c_double, P, P, P]
+        for f in ("orc_rbc_pad", "orc_pad_adjoint", "orc_laplacian", "orc_model_shot", "orc_rtm_shot",
+                  "orc_rtm_storage_shot"):
             getattr(lib, f).restype = c_int
         _lib = lib
     return _lib
@@ -163,4 +166,31 @@ def rtm_shot(v_pad, h, nb, dt, wavelet, src, rec, g, reinject=True, eps_rel=1e-6
         out["w_adj"] = wadj
     if snap_k >= 0:
         out["snap_p"], out["snap_mu"] = sp, sm
+    return out
+
+
+def nyquist_stride(dt, f_max, f_min=0.0):
+    """Steps between stored panels: the Nyquist interval of Eq. (7),
+    1 / (2 (f_max - f_min)), in whole time steps (at least 1)."""
+    dtn = 1.0 / (2.0 * (f_max - f_min))
+    return max(1, int(np.floor(dtn / dt + 1e-9)))
+
+
+def rtm_storage_shot(v_pad, h, nb, dt, wavelet, src, rec, g, stride, phase=0, eps_rel=1e-3):
+    """RTM with source-wavefield storage every `stride` steps (Algorithm 2
+    with the decimation of Eq. (7)); returns num, den, image (interior)."""
+    v_pad = np.ascontiguousarray(v_pad, dtype=np.float32)
+    ndim, nx, ny, nz = _dims(v_pad.shape, nb)
+    w = np.ascontiguousarray(wavelet, dtype=np.float64)
+    nt = w.shape[0]
+    src, rec = _geom(src, rec)
+    nrec = rec.shape[0]
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    assert g.shape == (nrec, nt + 1)
+    ishape = (nz, nx) if ndim == 2 else (nz, ny, nx)
+    out = {k: np.empty(ishape, np.float64) for k in ("num", "den", "image")}
+    rc = _load().orc_rtm_storage_shot(ndim, nx, ny, nz, nb, h, _ptr(v_pad), dt, nt, _ptr(w), _ptr(src), nrec,
+                                      _ptr(rec), _ptr(g), int(stride), int(phase), eps_rel, _ptr(out["num"]),
+                                      _ptr(out["den"]), _ptr(out["image"]))
+    _check(rc, "orc_rtm_storage_shot")
     return out

@@ -9,7 +9,7 @@
  * on the NEC SX-Aurora TSUBASA", arXiv 2204.03380).  It shares no code,
  * header, constant or helper with the HIP library.
  *
- * Conventions (all readings of the paper are listed in the design doc):
+ * Conventions:
  *  - Grids: interior extents nx, ny, nz (ny = 1 in 2-D), spacing h, padded
  *    with nb random-boundary cells on every face.  Padded arrays are stored
  *    [NZ][NY][NX], x fastest, with NX = nx + 2nb, NZ = nz + 2nb and
@@ -491,6 +491,110 @@ int orc_rtm_shot(int ndim, long nx, long ny, long nz, int nb, double h, const fl
     free(den);
     free(G);
     free(src_term);
+    free(rp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Migration with wavefield storage: Algorithm 2, with the source      */
+/* wavefield kept only every `stride` steps (the decimation of         */
+/* Eq. (7)).                                                           */
+/* ------------------------------------------------------------------ */
+
+/* One shot of RTM that stores the source wavefield instead of
+ * reconstructing it.
+ * Forward pass: the scheme of orc_model_shot; p^k is kept for every
+ * k in [0, nt-1] with k = phase (mod stride).
+ * Reverse pass, k = nt-1 down to 0: only the receiver wavefield (Eq. (2),
+ * the same discrete adjoint as orc_rtm_shot); at every kept k the imaging
+ * sums of Eq. (3) take the stored p^k with mu^(k+1):
+ *     num += p^k mu^(k+1),  den += (p^k)^2.
+ * image = num / (den + eps_rel * max(den)) on the interior crop.
+ * With stride = 1 the sums equal those of the reconstruction.
+ * Returns 0, -1 or -3. */
+int orc_rtm_storage_shot(int ndim, long nx, long ny, long nz, int nb, double h, const float *v_pad,
+                         double dt, int nt, const double *w, const double *src, int nrec,
+                         const double *rec, const double *g_in, int stride, int phase, double eps_rel,
+                         double *num_out, double *den_out, double *image)
+{
+    og_grid g;
+    og_point sp, *rp = NULL;
+    int rc = og_setup(&g, ndim, nx, ny, nz, nb, h, nt, src, nrec, rec, &sp, &rp);
+    if (rc != 0) return rc;
+    if (!v_pad || !w || (nrec > 0 && !g_in) || stride < 1 || phase < 0 || phase >= stride) {
+        free(rp);
+        return -1;
+    }
+    long n = og_cells(&g);
+    long nkeep = 0;
+    for (int k = phase; k < nt; k += stride) ++nkeep;
+    double *D = (double *)malloc(sizeof(double) * n);
+    double *a = (double *)calloc(n, sizeof(double));
+    double *b = (double *)calloc(n, sizeof(double));
+    double *lap = (double *)malloc(sizeof(double) * n);
+    double *store = (double *)calloc((size_t)(nkeep > 0 ? nkeep : 1) * n, sizeof(double));
+    for (long i = 0; i < n; ++i) D[i] = ((double)v_pad[i] * dt) * ((double)v_pad[i] * dt);
+
+    /* Forward: a = p^it before the step.  Keep p^it for kept it. */
+    for (int it = 0; it < nt; ++it) {
+        if (it >= phase && (it - phase) % stride == 0)
+            memcpy(store + (size_t)((it - phase) / stride) * n, a, sizeof(double) * n);
+        og_step(&g, D, a, b, b, lap, &sp, w[it], NULL);
+        double *t = a;
+        a = b;
+        b = t;
+    }
+    /* Reverse: M0 = mu^(k+1), M1 = mu^(k+2). */
+    double *M0 = a, *M1 = b;
+    double *num = (double *)calloc(n, sizeof(double));
+    double *den = (double *)calloc(n, sizeof(double));
+    for (long i = 0; i < n; ++i) M1[i] = 0.0;
+    for (long i = 0; i < n; ++i) M0[i] = 0.0;
+    for (int r = 0; r < nrec; ++r)
+        for (int q = 0; q < rp[r].n; ++q)
+            M0[rp[r].idx[q]] += D[rp[r].idx[q]] * rp[r].w[q] * g_in[(long)r * (nt + 1) + nt];
+    for (int k = nt - 1; k >= 0; --k) {
+        if (k >= phase && (k - phase) % stride == 0) {
+            const double *pk = store + (size_t)((k - phase) / stride) * n;
+#pragma omp parallel for schedule(static)
+            for (long i = 0; i < n; ++i) {
+                num[i] += pk[i] * M0[i];
+                den[i] += pk[i] * pk[i];
+            }
+        }
+        og_laplacian(&g, M0, lap);
+#pragma omp parallel for schedule(static)
+        for (long i = 0; i < n; ++i) M1[i] = 2.0 * M0[i] - M1[i] + D[i] * lap[i];
+        for (int r = 0; r < nrec; ++r)
+            for (int q = 0; q < rp[r].n; ++q)
+                M1[rp[r].idx[q]] += D[rp[r].idx[q]] * rp[r].w[q] * g_in[(long)r * (nt + 1) + k];
+        double *t = M1;
+        M1 = M0;
+        M0 = t;
+    }
+    double dmax = 0.0;
+    for (long z = 0; z < g.nz; ++z)
+        for (long y = 0; y < g.ny; ++y)
+            for (long x = 0; x < g.nx; ++x) {
+                long j = og_index(&g, z + nb, g.ndim == 3 ? y + nb : 0, x + nb);
+                if (den[j] > dmax) dmax = den[j];
+            }
+    for (long z = 0; z < g.nz; ++z)
+        for (long y = 0; y < g.ny; ++y)
+            for (long x = 0; x < g.nx; ++x) {
+                long j = og_index(&g, z + nb, g.ndim == 3 ? y + nb : 0, x + nb);
+                long o = (z * g.ny + y) * g.nx + x;
+                if (num_out) num_out[o] = num[j];
+                if (den_out) den_out[o] = den[j];
+                if (image) image[o] = num[j] / (den[j] + eps_rel * dmax);
+            }
+    free(D);
+    free(a);
+    free(b);
+    free(lap);
+    free(store);
+    free(num);
+    free(den);
     free(rp);
     return 0;
 }
