@@ -69,6 +69,7 @@ extern "C" {
 #define RTM_OP_MODEL 1   /* rtm_model_shot                                  */
 #define RTM_OP_RTM 2     /* rtm_rtm_shot                                    */
 #define RTM_OP_VJP 3     /* rtm_model_shot_vjp                              */
+#define RTM_OP_STORAGE 4 /* rtm_storage_shot                                */
 
 /* Flags for rtm_model_shot, rtm_rtm_shot and rtm_model_shot_vjp. */
 #define RTM_F_SKIP_CHECK 0x1u /* skip the velocity range check            */
@@ -153,8 +154,10 @@ int rtm_get_tuning3d(int op, int *vec, int *ty, int *zseg);
  * for the recorded events, returns the summed loop times in milliseconds
  * and the number of kernel launches they cover, per loop kind:
  *   [0] forward with receiver sampling (rtm_model_shot),
- *   [1] forward without sampling (rtm_rtm_shot, rtm_model_shot_vjp),
- *   [2] fused reverse with imaging (rtm_rtm_shot),
+ *   [1] forward without sampling (rtm_rtm_shot, rtm_model_shot_vjp,
+ *       rtm_storage_shot, whose snapshot copies it includes),
+ *   [2] reverse with imaging (rtm_rtm_shot: fused reconstruction and
+ *       receiver wavefield; rtm_storage_shot: receiver wavefield alone),
  *   [3] fused reverse with the gradient (rtm_model_shot_vjp),
  * and clears the record.  ms and launches point to 4 elements each.
  * Loops of calls given a probe are not recorded. */
@@ -233,6 +236,47 @@ int rtm_rtm_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t 
                  const float *traces, float eps_rel, float *image, float *num, float *den,
                  const rtm_probe_t *probe, uint32_t flags, void *ws, size_t ws_bytes,
                  void *stream);
+
+/* Snapshot step of the stored source wavefield (Eq. (7)): the Nyquist
+ * interval 1 / (2 (f_max - f_min)) of a source band [f_min, f_max] Hz, in
+ * whole time steps of dt seconds, at least 1.  Host only.
+ * RTM_EINVAL unless dt > 0, 0 <= f_min < f_max, all finite. */
+int rtm_nyquist_stride(double dt, double f_max, double f_min, int32_t *stride);
+
+/* Number of stored levels of rtm_storage_shot: the k in [0, nt - 1] with
+ * k = phase (mod stride).  Host only.  RTM_EINVAL unless nt >= 1,
+ * stride >= 1 and 0 <= phase < stride. */
+int rtm_storage_count(int32_t nt, int32_t stride, int32_t phase, int64_t *count);
+
+/* Reverse time migration of one shot with a stored source wavefield
+ * (Algorithm 2, the paper's comparison method), the snapshots kept in
+ * device memory instead of on disk and decimated in time as in Eq. (7).
+ * Forward pass as in rtm_rtm_shot; after reaching each stored level p^k
+ * (k in [0, nt - 1], k = phase mod stride) its interior is copied into
+ * `snapshots`.  Reverse pass k = nt-1 .. 0: only the receiver wavefield
+ * (the same scheme and arithmetic as rtm_rtm_shot's), and at every stored
+ * level the sums of Eq. (3) with the stored p^k:
+ *    num += p^k mu^{k+1},  den += (p^k)^2.
+ * With stride 1 the sums are those of rtm_rtm_shot up to the rounding of
+ * its reconstructed p; a larger stride sums over the stored levels only
+ * (no interpolation between them).
+ *   traces     device [nrec][nt + 1] recorded data.
+ *   stride, phase  decimation (see rtm_storage_count; rtm_nyquist_stride
+ *              gives the paper's stride).
+ *   eps_rel, image, num, den  as in rtm_rtm_shot.
+ *   snapshots  device, caller-owned, count * nz * ny * nx floats: level i
+ *              of the count stored ones (k = phase + i stride) at offset
+ *              i * nz * ny * nx, dense interior [nz][ny][nx].  Valid after
+ *              the call (the stored source wavefield).
+ *   snapshot_bytes  size of `snapshots`; RTM_EINVAL if smaller than needed.
+ *   flags      RTM_F_SKIP_CHECK or 0.
+ *   ws         rtm_workspace_bytes(RTM_OP_STORAGE) bytes. */
+int rtm_storage_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt,
+                     const float *wavelet, const float *src, int32_t nrec, const float *rec,
+                     const float *traces, int32_t stride, int32_t phase, float eps_rel,
+                     float *image, float *num, float *den, float *snapshots,
+                     size_t snapshot_bytes, uint32_t flags, void *ws, size_t ws_bytes,
+                     void *stream);
 
 /* Vector-Jacobian product of rtm_model_shot with respect to the padded
  * velocity: given dJ/dtraces, returns dJ/dv_pad = 2 G / (v^3 dt^2) with

@@ -16,11 +16,12 @@ import torch
 
 from . import _lib
 from ._lib import (RTM_F_ACCUMULATE, RTM_F_GRAPH, RTM_F_NO_REINJECT, RTM_F_SKIP_CHECK, RTM_OP_MODEL,
-                   RTM_OP_RBC_PAD, RTM_OP_RTM, RTM_OP_VJP, RTM_TUNE_EXACT, RtmError)
+                   RTM_OP_RBC_PAD, RTM_OP_RTM, RTM_OP_STORAGE, RTM_OP_VJP, RTM_TUNE_EXACT, RtmError)
 
 __all__ = [
     "Grid", "RtmError", "rtm_workspace_bytes", "rtm_set_tuning", "rtm_get_tuning", "rtm_set_tuning3d", "rtm_get_tuning3d", "rtm_timing_enable", "rtm_timing_read", "rtm_rbc_pad", "rtm_pad_adjoint",
     "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "RTM_F_SKIP_CHECK", "RTM_F_NO_REINJECT",
+    "rtm_nyquist_stride", "rtm_storage_count", "rtm_storage_shot", "RTM_OP_STORAGE",
     "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD", "RTM_F_ACCUMULATE", "RTM_F_GRAPH", "RTM_TUNE_EXACT",
     "BatchShot", "BatchPlan", "rtm_window_extract", "rtm_window_accumulate", "rtm_l2_misfit",
 ]
@@ -235,6 +236,53 @@ def rtm_rtm_shot(grid: Grid, v_pad: torch.Tensor, dt: float, wavelet: torch.Tens
         traces.data_ptr(), float(eps_rel), out["image"].data_ptr(),
         out["num"].data_ptr() if want_numden else None, out["den"].data_ptr() if want_numden else None,
         ctypes.byref(probe) if probe is not None else None, int(flags), ws.data_ptr(), ws.numel(), _stream(dev)))
+    return out
+
+
+def rtm_nyquist_stride(dt: float, f_max: float, f_min: float = 0.0) -> int:
+    """Snapshot step of the stored source wavefield, Eq. (7), in time steps."""
+    out = ctypes.c_int32()
+    _lib.check(_lib.load().rtm_nyquist_stride(float(dt), float(f_max), float(f_min), ctypes.byref(out)))
+    return out.value
+
+
+def rtm_storage_count(nt: int, stride: int, phase: int = 0) -> int:
+    """Number of levels k in [0, nt) with k = phase (mod stride)."""
+    out = ctypes.c_int64()
+    _lib.check(_lib.load().rtm_storage_count(int(nt), int(stride), int(phase), ctypes.byref(out)))
+    return out.value
+
+
+def rtm_storage_shot(grid: Grid, v_pad: torch.Tensor, dt: float, wavelet: torch.Tensor, src, rec,
+                     traces: torch.Tensor, stride: int, phase: int = 0, eps_rel: float = 1e-3,
+                     want_numden: bool = False, snapshots: torch.Tensor = None, flags: int = 0) -> dict:
+    """Image of one shot with the source wavefield stored every `stride`
+    steps in device memory (Algorithm 2 with Eq. (7)).  Returns image
+    (interior), the snapshots [count, *interior] and optionally num, den.
+    A preallocated `snapshots` tensor of at least that size may be passed."""
+    dev = v_pad.device
+    _dev(v_pad, "v_pad", grid.padded_shape)
+    nt = int(wavelet.numel())
+    _dev(wavelet, "wavelet", (nt,))
+    src = _pos(src, "src")[0].copy()
+    rec = _pos(rec, "rec")
+    nrec = rec.shape[0]
+    _dev(traces, "traces", (nrec, nt + 1))
+    count = rtm_storage_count(nt, stride, phase)
+    if snapshots is None:
+        snapshots = torch.empty((count,) + tuple(grid.interior_shape), dtype=torch.float32, device=dev)
+    _dev(snapshots, "snapshots")
+    out = {"image": torch.empty(grid.interior_shape, dtype=torch.float32, device=dev), "snapshots": snapshots}
+    if want_numden:
+        out["num"] = torch.empty(grid.interior_shape, dtype=torch.float32, device=dev)
+        out["den"] = torch.empty(grid.interior_shape, dtype=torch.float32, device=dev)
+    ws = _workspace(grid, RTM_OP_STORAGE, nrec, nt, dev)
+    g = grid.c()
+    _lib.check(_lib.load().rtm_storage_shot(
+        ctypes.byref(g), v_pad.data_ptr(), float(dt), nt, wavelet.data_ptr(), _fp(src), nrec, _fp(rec),
+        traces.data_ptr(), int(stride), int(phase), float(eps_rel), out["image"].data_ptr(),
+        out["num"].data_ptr() if want_numden else None, out["den"].data_ptr() if want_numden else None,
+        snapshots.data_ptr(), snapshots.numel() * 4, int(flags), ws.data_ptr(), ws.numel(), _stream(dev)))
     return out
 
 

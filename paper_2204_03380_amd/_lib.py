@@ -18,6 +18,7 @@ RTM_OP_RBC_PAD = 0
 RTM_OP_MODEL = 1
 RTM_OP_RTM = 2
 RTM_OP_VJP = 3
+RTM_OP_STORAGE = 4
 RTM_TUNE_EXACT = 0x100
 
 RTM_F_SKIP_CHECK = 0x1
@@ -29,7 +30,8 @@ EXPORTS = (
     "rtm_get_tuning2d", "rtm_set_steps_per_launch", "rtm_get_steps_per_launch", "rtm_set_tuning3d",
     "rtm_get_tuning3d", "rtm_timing_enable", "rtm_timing_read",
     "rtm_workspace_bytes", "rtm_rbc_pad",
-    "rtm_pad_adjoint", "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "rtm_batch_plan", "rtm_batch_run",
+    "rtm_pad_adjoint", "rtm_model_shot", "rtm_rtm_shot", "rtm_nyquist_stride", "rtm_storage_count",
+    "rtm_storage_shot", "rtm_model_shot_vjp", "rtm_batch_plan", "rtm_batch_run",
     "rtm_batch_free", "rtm_window_extract", "rtm_window_accumulate", "rtm_misfit_ws_bytes", "rtm_l2_misfit",
     "unet_weight_pack", "unet_conv3d_fwd", "unet_conv3d_dgrad", "unet_wgrad_ws_bytes", "unet_conv3d_wgrad",
     "unet_embed", "unet_pool2", "unet_up2", "unet_up2_bwd", "unet_relu_grad", "unet_mse_ws_bytes", "unet_mse",
@@ -96,6 +98,10 @@ def load():
         "rtm_model_shot": ([G, P, D, I32, P, P, I32, P, P, P, P, U32, P, SZ, P], ctypes.c_int),
         "rtm_rtm_shot": ([G, P, D, I32, P, P, I32, P, P, F, P, P, P, ctypes.POINTER(RtmProbe), U32, P, SZ, P],
                          ctypes.c_int),
+        "rtm_nyquist_stride": ([D, D, D, ctypes.POINTER(I32)], ctypes.c_int),
+        "rtm_storage_count": ([I32, I32, I32, ctypes.POINTER(I64)], ctypes.c_int),
+        "rtm_storage_shot": ([G, P, D, I32, P, P, I32, P, P, I32, I32, F, P, P, P, P, SZ, U32, P, SZ, P],
+                             ctypes.c_int),
         "rtm_model_shot_vjp": ([G, P, D, I32, P, P, I32, P, P, P, P, U32, P, SZ, P], ctypes.c_int),
         "rtm_batch_plan": ([ctypes.c_int, I32, ctypes.POINTER(RtmShotDesc), D, I32, F, U32,
                             ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(SZ)], ctypes.c_int),

@@ -31,12 +31,16 @@ hipError_t launch_fwd2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, i
                            hipStream_t st);
 hipError_t launch_rev2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                            const InjEnt *ents, const Contrib *cont, int k, int reinject, hipStream_t st);
+hipError_t launch_recv2d(int vec, int tx, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+                         const InjEnt *ents, const Contrib *cont, int k, const float *snap, hipStream_t st);
 // prop3d.hip
 hipError_t launch_fwd3d(int vec, int ty, const ShotDev *shots, const Tile3D *tiles, int ntiles, int nslots,
                         const InjEnt *ents, const Contrib *cont, const SampleTask *stasks, int nsample, int n,
                         hipStream_t st);
 hipError_t launch_rev3d(int vec, int ty, bool grad, const ShotDev *shots, const Tile3D *tiles, int ntiles, int nslots,
                         const InjEnt *ents, const Contrib *cont, int k, int reinject, float *wadj, hipStream_t st);
+hipError_t launch_recv3d(int vec, int ty, const ShotDev *shots, const Tile3D *tiles, int ntiles, int nslots,
+                         const InjEnt *ents, const Contrib *cont, int k, const float *snap, hipStream_t st);
 // aux.hip
 hipError_t launch_vrange(const float *v, int64_t n, unsigned *maxmin2, hipStream_t st);
 hipError_t launch_vmax(const float *v, int64_t n, unsigned *out, hipStream_t st);
@@ -56,6 +60,7 @@ hipError_t launch_image(const ShotDev *shots, int shot, int64_t ninterior, unsig
                         float *image, int accumulate, float *num, float *den, hipStream_t st);
 hipError_t launch_grad(const ShotDev *shots, int shot, int64_t npad, const float *v_pad, float dt, float *grad,
                        hipStream_t st);
+hipError_t launch_snap_store(const ShotDev *shots, int shot, int lev, int64_t ninterior, float *out, hipStream_t st);
 hipError_t launch_wadj(const float *parts, int nt, float scale, float *out, hipStream_t st);
 size_t misfit_ws_bytes();
 hipError_t launch_misfit(const float *d, const float *dobs, float *r, int64_t n, void *ws, double *J, hipStream_t st);
@@ -272,6 +277,8 @@ struct ShotIn {
     float *image = nullptr, *num = nullptr, *den = nullptr;  // RTM outputs (interior)
     float *grad_v_pad = nullptr, *grad_wavelet = nullptr;    // VJP outputs
     float *p_last = nullptr, *p_prev = nullptr;              // modeling: final panels
+    float *snaps = nullptr;             // storage RTM: stored interior levels
+    int stride = 1, phase = 0;          // storage RTM: levels k = phase (mod stride)
 };
 
 // Tiles and injection entries of one launch shape.  ents holds all source
@@ -336,6 +343,8 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // depend on the launch shape.
 int nfields(int op, int ndim) { return (op == RTM_OP_MODEL ? 2 : 4) * (ndim == 2 ? 2 : 1); }
 int nfields(const Job &J) { return nfields(J.op, J.shots.empty() ? 3 : J.shots[0].g.ndim); }
+// Ops with the imaging sums num (acc0) and den (acc1).
+bool has_den(int op) { return op == RTM_OP_RTM || op == RTM_OP_STORAGE; }
 
 constexpr size_t kTileBytes = sizeof(Tile2D) > sizeof(Tile3D) ? sizeof(Tile2D) : sizeof(Tile3D);
 
@@ -380,7 +389,7 @@ WsLayout make_ws_layout(const Job &J, const Counts &c)
         for (int k = 0; k < nf; ++k) f[(k / per) * 4 + k % per] = take(sizeof(float) * F);
         w.fld.push_back(f);
         w.acc0.push_back(J.op == RTM_OP_MODEL ? 0 : take(sizeof(float) * F));
-        w.acc1.push_back(J.op == RTM_OP_RTM ? take(sizeof(float) * F) : 0);
+        w.acc1.push_back(has_den(J.op) ? take(sizeof(float) * F) : 0);
         w.trint.push_back(take(sizeof(float) * (size_t)(J.nt + 1) * S.nrec));
         w.wadj.push_back(J.op == RTM_OP_VJP ? take(sizeof(float) * (size_t)J.nt * kMaxNodes) : 0);
     }
@@ -639,7 +648,8 @@ int build_job_tables(Job &J)
     int rc = build_tiling(J, J.fw, false);
     if (rc) return rc;
     if (J.op != RTM_OP_MODEL) {
-        J.rv.tune = fit_tune(J, get_tune(1, ndim));
+        // the storage reverse pass steps one field, as the forward pass does
+        J.rv.tune = fit_tune(J, get_tune(J.op == RTM_OP_STORAGE ? 0 : 1, ndim));
         rc = build_tiling(J, J.rv, true);
         if (rc) return rc;
     }
@@ -727,7 +737,7 @@ void fill_shot_devs(const Job &J, const Dev &D, std::vector<ShotDev> &out)
         std::memset(&d, 0, sizeof d);
         for (int k = 0; k < 8; ++k) d.fld[k] = J.ws.fld[i][k] ? D.at<float>(J.ws.fld[i][k]) : nullptr;
         d.acc0 = J.op == RTM_OP_MODEL ? nullptr : D.at<float>(J.ws.acc0[i]);
-        d.acc1 = J.op == RTM_OP_RTM ? D.at<float>(J.ws.acc1[i]) : nullptr;
+        d.acc1 = has_den(J.op) ? D.at<float>(J.ws.acc1[i]) : nullptr;
         d.Dp = D.at<float>(J.ws.dp[J.dslot[i]]);
         d.wav = S.wavelet;
         float *trint = D.at<float>(J.ws.trint[i]);
@@ -841,7 +851,7 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
         for (int k = 0; k < 8; ++k)
             if (J.ws.fld[i][k]) RTM_HIP(launch_fill(D.at<float>(J.ws.fld[i][k]), F, 0.f, st));
         if (J.op != RTM_OP_MODEL) RTM_HIP(launch_fill(D.at<float>(J.ws.acc0[i]), F, 0.f, st));
-        if (J.op == RTM_OP_RTM) RTM_HIP(launch_fill(D.at<float>(J.ws.acc1[i]), F, 0.f, st));
+        if (has_den(J.op)) RTM_HIP(launch_fill(D.at<float>(J.ws.acc1[i]), F, 0.f, st));
         if (J.op == RTM_OP_VJP && J.shots[i].grad_wavelet)
             RTM_HIP(launch_fill(D.at<float>(J.ws.wadj[i]), (int64_t)nt * kMaxNodes, 0.f, st));
         if (J.op != RTM_OP_MODEL)
@@ -858,19 +868,34 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
         const int nsample = sample ? (int)J.stasks.size() : 0;
         const bool two = J.fw.ndim == 2 && J.fw2.two_step;
         LoopTimer timer(sample ? kLoopModelFwd : kLoopRtmFwd, two ? nt / 2 + nt % 2 : nt, st, timed);
+        // Storage RTM: copy the interior of each stored level p^m once it
+        // is current (before the step that overwrites p^{m-1} with p^{m+1}).
+        auto keep = [&](int m) -> int {
+            if (J.op != RTM_OP_STORAGE || m >= nt) return RTM_OK;
+            const ShotIn &S = J.shots[0];
+            if (m < S.phase || (m - S.phase) % S.stride != 0) return RTM_OK;
+            const int64_t ncell = S.g.nx * S.g.ny * S.g.nz;
+            RTM_HIP(launch_snap_store(SH(), 0, m & 1, ncell, S.snaps + (int64_t)((m - S.phase) / S.stride) * ncell,
+                                      st));
+            return RTM_OK;
+        };
+        int rc = RTM_OK;
         int n = 0;
         if (two) {
             // steps n, n + 1 per launch; each launch records d^{n-1}, d^n
             for (; n + 2 <= nt; n += 2) {
+                if ((rc = keep(n))) return rc;
                 RTM_HIP(launch_fwd2d_t2(J.fw2.tune.vec, SH(), D.at<Tile2D>(J.ws.tiles_f2), J.fw2.count(),
                                         J.fw2.nslots, D.at<InjEnt>(J.ws.ents_f2), D.at<Contrib>(J.ws.cont_f2),
                                         sample ? stasks : nullptr, nsample, n, st));
                 cur ^= 1;
+                if ((rc = keep(n + 1))) return rc;
             }
             // an odd last step overwrites level n - 1: record it first
             if (sample && n < nt && n >= 1) RTM_HIP(launch_sample(SH(), stasks, nsample, n - 1, st));
         }
         for (; n < nt; ++n) {
+            if ((rc = keep(n))) return rc;
             if (J.fw.ndim == 3)
                 RTM_HIP(launch_fwd3d(J.fw.tune.vec, J.fw.tune.ty, SH(), (const Tile3D *)tiles, ntiles, J.fw.nslots,
                                      ents, cont, sample ? stasks : nullptr, nsample, n, st));
@@ -901,6 +926,26 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
     const Contrib *cont = D.at<Contrib>(J.ws.cont_r);
     RTM_HIP(launch_inj_set(SH(), ents, J.rv.nsrc_ent, J.rv.nsrc_ent + J.rv.nrec_ent, cont, nt, st));
     const int ntiles = J.rv.count();
+    if (J.op == RTM_OP_STORAGE) {
+        // Algorithm 2: the receiver wavefield alone, imaging at the stored levels.
+        const ShotIn &S = J.shots[0];
+        const int64_t ncell = S.g.nx * S.g.ny * S.g.nz;
+        LoopTimer timer(kLoopRevImage, nt, st, timed);
+        for (int k = nt - 1; k >= 0; --k) {
+            const bool stored = k >= S.phase && (k - S.phase) % S.stride == 0;
+            const float *snap = stored ? S.snaps + (int64_t)((k - S.phase) / S.stride) * ncell : nullptr;
+            if (J.rv.ndim == 3)
+                RTM_HIP(launch_recv3d(J.rv.tune.vec, J.rv.tune.ty, SH(), (const Tile3D *)tiles, ntiles, J.rv.nslots,
+                                      ents, cont, k, snap, st));
+            else
+                RTM_HIP(launch_recv2d(J.rv.tune.vec, J.rv.tune.tx, SH(), tiles, ntiles, J.rv.nslots, ents, cont, k,
+                                      snap, st));
+        }
+        timer.finish();
+        RTM_HIP(launch_image(SH(), 0, ncell, scal + 64 + 2 * J.slot_shot.size(), J.eps, S.image, 0, S.num, S.den,
+                             st));
+        return RTM_OK;
+    }
     const int reinject = (J.flags & RTM_F_NO_REINJECT) ? 0 : 1;
     const bool probing = probe && probe->snap_k >= 0;
     const bool two = J.rv.ndim == 2 && J.rv2.two_step && !grad && !probing;
@@ -1171,7 +1216,7 @@ int rtm_workspace_bytes(const rtm_grid_t *grid, int op, int32_t nrec, int32_t nt
     int rc = grid_info(grid, &g);
     if (rc) return rc;
     if (!bytes) return fail(RTM_EINVAL, "bytes is NULL");
-    if (op < RTM_OP_RBC_PAD || op > RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
+    if (op < RTM_OP_RBC_PAD || op > RTM_OP_STORAGE) return fail(RTM_EINVAL, "unknown op %d", op);
     if (op == RTM_OP_RBC_PAD) {
         *bytes = 256;
         return RTM_OK;
@@ -1262,6 +1307,65 @@ int rtm_rtm_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t 
     J.shots[0].num = num;
     J.shots[0].den = den;
     return job_run(J, ws, ws_bytes, (hipStream_t)stream, probe);
+}
+
+int rtm_nyquist_stride(double dt, double f_max, double f_min, int32_t *stride)
+{
+    t_err.clear();
+    if (!stride) return fail(RTM_EINVAL, "stride is NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(RTM_EINVAL, "dt must be positive and finite");
+    if (!(f_min >= 0.0) || !(f_max > f_min) || !std::isfinite(f_max))
+        return fail(RTM_EINVAL, "need 0 <= f_min < f_max, finite (got %g, %g)", f_min, f_max);
+    // Eq. (7); the small allowance keeps exact ratios such as 5 ms / 0.5 ms at 10
+    const double ratio = 1.0 / (2.0 * (f_max - f_min) * dt);
+    const double steps = std::floor(ratio * (1.0 + 1e-12));
+    *stride = (int32_t)std::max(1.0, std::min(steps, 1073741824.0));
+    return RTM_OK;
+}
+
+int rtm_storage_count(int32_t nt, int32_t stride, int32_t phase, int64_t *count)
+{
+    t_err.clear();
+    if (!count) return fail(RTM_EINVAL, "count is NULL");
+    if (nt < 1) return fail(RTM_EINVAL, "nt must be >= 1");
+    if (stride < 1 || phase < 0 || phase >= stride)
+        return fail(RTM_EINVAL, "need stride >= 1 and 0 <= phase < stride (got %d, %d)", (int)stride, (int)phase);
+    *count = phase < nt ? (int64_t)(nt - 1 - phase) / stride + 1 : 0;
+    return RTM_OK;
+}
+
+int rtm_storage_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt, const float *wavelet,
+                     const float *src, int32_t nrec, const float *rec, const float *traces, int32_t stride,
+                     int32_t phase, float eps_rel, float *image, float *num, float *den, float *snapshots,
+                     size_t snapshot_bytes, uint32_t flags, void *ws, size_t ws_bytes, void *stream)
+{
+    t_err.clear();
+    GridInfo g;
+    int rc = check_common(grid, v_pad, dt, nt, wavelet, src, nrec, rec, &g);
+    if (rc) return rc;
+    if (!traces) return fail(RTM_EINVAL, "traces is NULL");
+    if (!image) return fail(RTM_EINVAL, "image is NULL");
+    if (!(eps_rel >= 0.f) || !std::isfinite(eps_rel)) return fail(RTM_EINVAL, "eps_rel must be finite and >= 0");
+    int64_t count = 0;
+    if ((rc = rtm_storage_count(nt, stride, phase, &count))) return rc;
+    const int64_t ncell = g.nx * g.ny * g.nz;
+    if (count > 0 && !snapshots) return fail(RTM_EINVAL, "snapshots is NULL");
+    if ((double)count * (double)ncell * 4.0 > (double)snapshot_bytes)
+        return fail(RTM_EINVAL, "snapshots: %lld levels of %lld cells need %.0f bytes, %zu given", (long long)count,
+                    (long long)ncell, (double)count * (double)ncell * 4.0, snapshot_bytes);
+    if (flags & ~RTM_F_SKIP_CHECK) return fail(RTM_EINVAL, "unsupported flags 0x%x", (unsigned)flags);
+    Job J;
+    if ((rc = single_job(J, RTM_OP_STORAGE, g, v_pad, dt, nt, wavelet, src, nrec, rec, flags))) return rc;
+    J.eps = eps_rel;
+    ShotIn &S = J.shots[0];
+    S.traces_in = traces;
+    S.image = image;
+    S.num = num;
+    S.den = den;
+    S.snaps = snapshots;
+    S.stride = stride;
+    S.phase = phase;
+    return job_run(J, ws, ws_bytes, (hipStream_t)stream, nullptr);
 }
 
 int rtm_model_shot_vjp(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt, const float *wavelet,

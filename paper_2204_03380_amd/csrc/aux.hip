@@ -281,6 +281,21 @@ __global__ void image_kernel(const ShotDev *__restrict__ shots, int shot, const 
     }
 }
 
+// Dense interior copy of p^m (field fld[lev] of the shot table) for the
+// migration with a stored source wavefield: out[(z ny + y) nx + x] = p at
+// interior cell (x, y, z).
+__global__ void snap_store_kernel(const ShotDev *__restrict__ shots, int shot, int lev, float *__restrict__ out)
+{
+    const ShotDev &S = shots[shot];
+    const int64_t nx = S.ix1 - S.ix0, ny = S.iy1 - S.iy0, nz = S.iz1 - S.iz0;
+    const int64_t n = nx * ny * nz;
+    const float *f = S.fld[lev];
+    for (int64_t i = gid(); i < n; i += gstride()) {
+        const int64_t x = i % nx, y = (i / nx) % ny, z = i / (nx * ny);
+        out[i] = f[S.L.org + (z + S.iz0) * S.L.plane + (y + S.iy0) * S.L.pitch + (x + S.ix0)];
+    }
+}
+
 // grad_v = 2 G / (v^3 dt^2) on the dense padded grid.
 __global__ void grad_kernel(const ShotDev *__restrict__ shots, int shot, const float *__restrict__ v_pad, float dt,
                             float *__restrict__ grad)
@@ -467,6 +482,12 @@ hipError_t launch_image(const ShotDev *shots, int shot, int64_t ninterior, unsig
     hipLaunchKernelGGL(den_max_kernel, dim3(grid_reduce(ninterior)), dim3(kBlock), 0, st, shots, shot, dmax_bits);
     hipLaunchKernelGGL(image_kernel, dim3(grid_for(ninterior)), dim3(kBlock), 0, st, shots, shot,
                        (const unsigned *)dmax_bits, eps_rel, image, accumulate, num, den);
+    return hipGetLastError();
+}
+
+hipError_t launch_snap_store(const ShotDev *shots, int shot, int lev, int64_t ninterior, float *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(snap_store_kernel, dim3(grid_for(ninterior)), dim3(kBlock), 0, st, shots, shot, lev, out);
     return hipGetLastError();
 }
 

@@ -330,6 +330,67 @@ void rev2d_kernel(const ShotDev *__restrict__ shots, const Tile2D *__restrict__ 
     }
 }
 
+// Receiver wavefield alone, for migration with a stored source wavefield
+// (Algorithm 2): mu^k = 2 mu^{k+1} - mu^{k+2} + D' (L mu^{k+1} + r^k), the
+// forward row update applied to mu (same operations as the mu half of the
+// fused reverse kernel), with the receiver term added after the march.  At
+// a stored level (snap non-null: the dense interior p^k) the imaging sums
+// num += p^k mu^{k+1}, den += (p^k)^2 take mu^{k+1} from the register queue.
+template <int VEC, int TX>
+__global__ __launch_bounds__(64 * TX) void recv2d_kernel(const ShotDev *__restrict__ shots,
+                                                         const Tile2D *__restrict__ tiles, int ntiles, int nslots,
+                                                         const InjEnt *__restrict__ ents,
+                                                         const Contrib *__restrict__ cont, int k,
+                                                         const float *__restrict__ snap)
+{
+    const int t = xcd_tile(blockIdx.x, nslots);
+    if (t >= ntiles) return;  // whole workgroup
+    const Tile2D T = tiles[t];
+    const ShotDev &S = shots[T.shot];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __shared__ EdgeRing<TX> ring;
+    FwdCtx<VEC> C;
+    C.pitch = S.L.pitch;
+    C.NX = S.L.NX;
+    C.pc = gp(S.fld[2 + ((k + 1) & 1)] + S.L.org);  // mu^{k+1}
+    C.po = gp(S.fld[2 + (k & 1)] + S.L.org);        // mu^{k+2} -> mu^k
+    C.Dp = gp(S.Dp + S.L.org);
+    C.lane = lane;
+    C.w = w;
+    C.x0 = T.x0 + w * 64 * VEC;
+    C.x = C.x0 + lane * VEC;
+    C.live = C.x < C.NX + kRadius;
+    C.own = C.x < C.NX;
+    const bool img = snap && C.own && C.x + VEC > S.ix0 && C.x < S.ix1;
+    const SnapImg I{snap, S.ix1 - S.ix0, 1, S.ix0, S.ix1, 0, S.iz0};
+    gfloat *A0 = gp(S.acc0 + S.L.org), *A1 = gp(S.acc1 + S.L.org);
+
+    float q[9][VEC];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) q[i][j] = 0.f;
+        if (C.live) ldv<VEC>(C.pc + (int64_t)(T.z0 - 4 + i) * C.pitch + C.x, q[i]);
+        if constexpr (TX > 1)
+            if (i >= 4) ring_put<VEC, TX>(ring, i - 4, w, lane, q[i]);
+    }
+#define RTM_RECV_ROW(SS, ZZ)                                                                        \
+    fwd_row<VEC, TX, SS>(C, q, ZZ, ring);                                                          \
+    if (img && (ZZ) >= S.iz0 && (ZZ) < S.iz1)                                                      \
+        snap_image<VEC>(I, A0, A1, (int64_t)(ZZ) * C.pitch + C.x, ZZ, 0, C.x, q[((SS) + 4) % 9]);
+    RTM_MARCH(RTM_RECV_ROW)
+#undef RTM_RECV_ROW
+    // Receiver term: mu^k += D' R^T g^k.
+    const float *sig = S.sig + (int64_t)k * S.nrec;
+    for (int e = T.rbeg; e < T.rend; ++e) {
+        const InjEnt E = ents[e];
+        if (owns<VEC>(E.x, C.x0, C.lane)) {
+            const int64_t o = (int64_t)E.z * C.pitch + E.x;
+            C.po[o] = fmaf(C.Dp[o], inj_sum(E, cont, sig), C.po[o]);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Two time steps per launch
 // ---------------------------------------------------------------------------
@@ -787,6 +848,30 @@ hipError_t launch_rev2d(int vec, int tx, bool grad, const ShotDev *shots, const 
     }
 #undef RTM_REV2D_X
 #undef RTM_REV2D
+    return hipGetLastError();
+}
+
+hipError_t launch_recv2d(int vec, int tx, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+                         const InjEnt *ents, const Contrib *cont, int k, const float *snap, hipStream_t st)
+{
+    dim3 grid(nslots), block(64 * tx);
+#define RTM_RECV2D(V, X) \
+    hipLaunchKernelGGL((recv2d_kernel<V, X>), grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, snap)
+#define RTM_RECV2D_X(V)                             \
+    switch (tx) {                                   \
+    case 1: RTM_RECV2D(V, 1); break;                \
+    case 2: RTM_RECV2D(V, 2); break;                \
+    case 4: RTM_RECV2D(V, 4); break;                \
+    default: return hipErrorInvalidValue;           \
+    }
+    switch (vec) {
+    case 1: RTM_RECV2D_X(1); break;
+    case 2: RTM_RECV2D_X(2); break;
+    case 4: RTM_RECV2D_X(4); break;
+    default: return hipErrorInvalidValue;
+    }
+#undef RTM_RECV2D_X
+#undef RTM_RECV2D
     return hipGetLastError();
 }
 

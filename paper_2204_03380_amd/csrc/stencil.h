@@ -242,5 +242,39 @@ __device__ __forceinline__ bool owns(int x, int x0, int lane)
     return x >= x0 + lane * VEC && x < x0 + (lane + 1) * VEC;
 }
 
+// Imaging from a stored source level (migration with wavefield storage,
+// Algorithm 2): for the lane's cells x .. x + VEC - 1 of padded row (z, y),
+// num += p^k mu^{k+1} and den += (p^k)^2, p^k read from the dense interior
+// snapshot [nz][ny][nx] of that level.  The caller checks that (z, y) is an
+// interior row and the lane overlaps the interior columns; cells outside
+// them add zero.
+struct SnapImg {
+    const float *snap;
+    int64_t nxi, nyi;
+    int ix0, ix1, iy0, iz0;
+};
+
+template <int VEC>
+__device__ __forceinline__ void snap_image(const SnapImg &I, gfloat *A0, gfloat *A1, int64_t o, int z, int y, int x,
+                                           const float (&mu)[VEC])
+{
+    const int64_t row = ((int64_t)(z - I.iz0) * I.nyi + (y - I.iy0)) * I.nxi;
+    float s[VEC], a[VEC], b[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const int xx = x + j;
+        s[j] = (xx >= I.ix0 && xx < I.ix1) ? I.snap[row + (xx - I.ix0)] : 0.f;
+    }
+    ldv<VEC>(A0 + o, a);
+    ldv<VEC>(A1 + o, b);
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        a[j] = fmaf(s[j], mu[j], a[j]);
+        b[j] = fmaf(s[j], s[j], b[j]);
+    }
+    stv<VEC>(A0 + o, a);
+    stv<VEC>(A1 + o, b);
+}
+
 }  // namespace
 }  // namespace rtm

@@ -93,3 +93,45 @@ def test_host_validation_errors():
     assert _call_model(g, ws_bytes=1024) == _lib.RTM_EWORKSPACE
     msg = _lib.load().rtm_last_error().decode()
     assert "workspace" in msg
+
+
+def test_storage_host_helpers():
+    """Eq. (7) step and stored-level count (host-only entry points), against
+    the paper's printed examples and enumeration."""
+    assert rtm.rtm_nyquist_stride(0.5e-3, 100.0, 0.0) == 10     # 5 ms / 0.5 ms
+    assert rtm.rtm_nyquist_stride(1e-3, 50.0) == 10             # 10 ms / 1 ms (3-D)
+    assert rtm.rtm_nyquist_stride(1e-3, 1000.0) == 1
+    assert rtm.rtm_nyquist_stride(1e-3, 60.0, 10.0) == 10       # band of 50 Hz
+    for bad in ((0.0, 100.0, 0.0), (1e-3, 10.0, 10.0), (1e-3, 10.0, -1.0), (1e-3, float("inf"), 0.0)):
+        with pytest.raises(rtm.RtmError):
+            rtm.rtm_nyquist_stride(*bad)
+    assert rtm.rtm_storage_count(6001, 10, 0) == 601            # 0 .. 6 s every 10 ms
+    for nt, stride, phase in ((1, 1, 0), (10, 3, 2), (9, 3, 2), (5, 7, 6), (100, 10, 9)):
+        assert rtm.rtm_storage_count(nt, stride, phase) == len([k for k in range(nt) if k % stride == phase])
+    for bad in ((0, 1, 0), (10, 0, 0), (10, 3, 3), (10, 3, -1)):
+        with pytest.raises(rtm.RtmError):
+            rtm.rtm_storage_count(*bad)
+
+
+def test_storage_shot_validation():
+    """rtm_storage_shot rejects a short snapshot buffer and a bad
+    decimation before any device work (fake device addresses)."""
+    lib = _lib.load()
+    grid = rtm.Grid(2, 20, 1, 12, 10.0, 4)
+    g = grid.c()
+    nt = 10
+    s = np.ascontiguousarray(np.array((5.0, 0.0, 3.0), np.float32))
+    r = np.ascontiguousarray(np.array(((1.0, 0.0, 2.0),), np.float32))
+    ws_bytes = rtm.rtm_workspace_bytes(grid, rtm.RTM_OP_STORAGE, 1, nt)
+    assert ws_bytes > 0
+
+    def call(stride, phase, snap_bytes, snaps=0x4000):
+        return lib.rtm_storage_shot(ctypes.byref(g), 0x1000, 1e-3, nt, 0x2000, s.ctypes.data_as(ctypes.c_void_p), 1,
+                                    r.ctypes.data_as(ctypes.c_void_p), 0x3000, stride, phase, 1e-3, 0x5000, None,
+                                    None, snaps, snap_bytes, 0, 0x100000, ws_bytes, None)
+
+    need = 4 * 20 * 12 * 4      # stride 3: levels 0, 3, 6, 9
+    assert call(3, 0, need - 1) == _lib.RTM_EINVAL
+    assert call(3, 0, need, snaps=None) == _lib.RTM_EINVAL
+    assert call(0, 0, need) == _lib.RTM_EINVAL
+    assert call(3, 3, need) == _lib.RTM_EINVAL
