@@ -72,7 +72,10 @@ def parse():
     ap.add_argument("--no-unet", action="store_true", help="skip the learned-filter training-step timing")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="instead of the survey benchmark: single-shot modeling and RTM at the grid sizes of the "
-                         "paper's Tables 1-4, timed over a shortened nt and scaled to the paper's nt")
+                         "paper's Tables 1-4 (modeling timed over a shortened nt and scaled to the paper's nt; "
+                         "RTM with reconstruction and with storage at the paper's nt)")
+    ap.add_argument("--paper-kinds", default="modeling,rtm,storage",
+                    help="with --paper-shapes: comma-separated kinds to run")
     return ap.parse_args()
 
 
@@ -136,16 +139,24 @@ PAPER_CASES = (
     ("modeling", (3048, 1, 1014), 8000, {"V100": 2.615, "SX-Aurora": 2.416}, "Table 1"),
     ("modeling", (5996, 1, 1974), 8000, {"V100": 6.962, "SX-Aurora": 7.885}, "Table 1"),
     ("rtm", (1574, 1, 534), 8000, {"V100": 3.500, "SX-Aurora": 4.489}, "Table 2"),
+    ("storage", (1574, 1, 534), 8000, {"V100": 7.969, "SX-Aurora": 9.016}, "Table 2"),
     ("modeling", (501, 501, 235), 6000, {"V100": 42.1505, "SX-Aurora": 43.132}, "Table 3"),
     ("modeling", (901, 901, 416), 6000, {"V100": 330.363, "SX-Aurora": 203.940}, "Table 3"),
     ("rtm", (501, 501, 235), 6000, {"V100": 139.786, "SX-Aurora": 108.582}, "Table 4"),
+    ("storage", (501, 501, 235), 6000, {"V100": 256.166, "SX-Aurora": 430.944}, "Table 4"),
 )
+# Stored-wavefield size the paper prints for its storage runs (GB), Tables 2 and 4.
+PAPER_STORAGE_GB = {"Table 2": 2.638, "Table 4": 132.062}
+# Snapshot step of the paper's storage runs: dt_nyq / dt = 10 in 2-D and 3-D (Eq. (7)).
+PAPER_STRIDE = 10
 
 
-def paper_shapes(nb=50, reps_2d=400, reps_3d=60):
-    """Per-step device time of one shot on each paper grid (synthetic smooth
-    velocity, runtime does not depend on the values), scaled to the paper's
-    nt, against the paper's times."""
+def paper_shapes(nb=50, reps_2d=400, reps_3d=60, kinds=("modeling", "rtm", "storage")):
+    """Device time of one shot on each paper grid (synthetic smooth velocity;
+    runtime does not depend on the values) against the paper's times.
+    Modeling: a reduced number of steps, scaled to the paper's nt.  RTM with
+    reconstruction and with storage: the paper's full nt, the storage run
+    keeping every 10th level in device memory."""
     import numpy as np
     import torch
 
@@ -154,6 +165,8 @@ def paper_shapes(nb=50, reps_2d=400, reps_3d=60):
     dev = torch.device("cuda:0")
     out = []
     for kind, (nx, ny, nz), nt_paper, paper, table in PAPER_CASES:
+        if kind not in kinds:
+            continue
         ndim = 2 if ny == 1 else 3
         shape_int = (nz - 2 * nb, nx - 2 * nb) if ndim == 2 else (nz - 2 * nb, ny - 2 * nb, nx - 2 * nb)
         if ndim == 2:
@@ -164,7 +177,7 @@ def paper_shapes(nb=50, reps_2d=400, reps_3d=60):
         dt = 0.45 * h / 4000.0 * (0.8 if ndim == 3 else 1.0)
         g = rtm.Grid.for_model(v, h, nb)
         vp = rtm.rtm_rbc_pad(g, torch.from_numpy(v).to(dev), 11, 0.0)
-        steps = reps_2d if ndim == 2 else reps_3d
+        steps = (reps_2d if ndim == 2 else reps_3d) if kind == "modeling" else nt_paper
         w = torch.from_numpy(synth.ricker(15.0, dt, steps)).to(dev)
         src = np.array([shape_int[-1] / 2.0, (shape_int[1] / 2.0 if ndim == 3 else 0.0), 2.0])
         if ndim == 2:
@@ -172,10 +185,23 @@ def paper_shapes(nb=50, reps_2d=400, reps_3d=60):
         else:
             rec = synth.grid_receivers(np.arange(0, shape_int[-1], 2, dtype=np.float64),
                                        np.arange(0, shape_int[1], 2, dtype=np.float64), 2.0)
-        run = (lambda: rtm.rtm_model_shot(g, vp, dt, w, src, rec)) if kind == "modeling" else None
-        if kind == "rtm":
+        extra = {}
+        if kind == "modeling":
+            run = lambda: rtm.rtm_model_shot(g, vp, dt, w, src, rec)  # noqa: E731
+        else:
             d = rtm.rtm_model_shot(g, vp, dt, w, src, rec)
+        if kind == "rtm":
             run = lambda: rtm.rtm_rtm_shot(g, vp, dt, w, src, rec, d)  # noqa: E731
+            extra["kept_levels"] = 2
+            extra["kept_GiB"] = round(2 * nx * ny * nz * 4 / 2 ** 30, 4)
+        if kind == "storage":
+            count = rtm.rtm_storage_count(steps, PAPER_STRIDE, 0)
+            snaps = torch.empty((count,) + tuple(g.interior_shape), dtype=torch.float32, device=dev)
+            run = lambda: rtm.rtm_storage_shot(g, vp, dt, w, src, rec, d, PAPER_STRIDE, 0, snapshots=snaps)  # noqa
+            extra["stride"] = PAPER_STRIDE
+            extra["kept_levels"] = count
+            extra["kept_GiB"] = round(snaps.numel() * 4 / 2 ** 30, 3)
+            extra["paper_stored_GB"] = PAPER_STORAGE_GB[table]
         run()
         torch.cuda.synchronize()
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -184,7 +210,7 @@ def paper_shapes(nb=50, reps_2d=400, reps_3d=60):
         e1.record()
         e1.synchronize()
         ms = e0.elapsed_time(e1)
-        props = 1 if kind == "modeling" else 3
+        props = {"modeling": 1, "rtm": 3, "storage": 2}[kind]
         cells = nx * ny * nz
         t_paper_nt = ms * 1e-3 * nt_paper / steps
         row = {"case": f"{kind} {nx}x{nz}" if ndim == 2 else f"{kind} {nx}x{ny}x{nz}", "source": table,
@@ -193,9 +219,14 @@ def paper_shapes(nb=50, reps_2d=400, reps_3d=60):
                "seconds_at_paper_nt": round(t_paper_nt, 4),
                "paper_seconds": paper,
                "speedup": {k: round(v_ / t_paper_nt, 1) for k, v_ in paper.items()}}
+        row.update(extra)
         out.append(row)
         print(json.dumps(row), file=sys.stderr, flush=True)
         del vp
+        if kind != "modeling":
+            del d
+        if kind == "storage":
+            del snaps
         torch.cuda.empty_cache()
     return out
 
@@ -210,7 +241,7 @@ def main():
         sys.exit(2)
 
     if args.paper_shapes:
-        rows = paper_shapes()
+        rows = paper_shapes(kinds=tuple(args.paper_kinds.split(",")))
         print(json.dumps({"metric": "single-shot time at the paper's grid sizes", "unit": "s", "n_gpus": 1,
                           "higher_is_better": False, "dtype": "f32", "data": "synthetic", "cases": rows}),
               flush=True)

@@ -320,14 +320,7 @@ void rev2d_kernel(const ShotDev *__restrict__ shots, const Tile2D *__restrict__ 
         }
     }
     // Receiver term: mu^k += D' R^T g^k.
-    const float *sig = S.sig + (int64_t)k * S.nrec;
-    for (int e = T.rbeg; e < T.rend; ++e) {
-        const InjEnt E = ents[e];
-        if (owns<VEC>(E.x, C.x0, C.lane)) {
-            const int64_t o = (int64_t)E.z * C.pitch + E.x;
-            C.M1[o] = fmaf(C.Dp[o], inj_sum(E, cont, sig), C.M1[o]);
-        }
-    }
+    inject_nodes(C.M1, C.Dp, ents, T.rbeg, T.rend, cont, S.sig + (int64_t)k * S.nrec, C.pitch, C.pitch);
 }
 
 // Receiver wavefield alone, for migration with a stored source wavefield
@@ -336,7 +329,9 @@ void rev2d_kernel(const ShotDev *__restrict__ shots, const Tile2D *__restrict__ 
 // fused reverse kernel), with the receiver term added after the march.  At
 // a stored level (snap non-null: the dense interior p^k) the imaging sums
 // num += p^k mu^{k+1}, den += (p^k)^2 take mu^{k+1} from the register queue.
-template <int VEC, int TX>
+// IMG selects the imaging variant at compile time, so that the other steps
+// run the plain forward code.
+template <int VEC, int TX, bool IMG>
 __global__ __launch_bounds__(64 * TX) void recv2d_kernel(const ShotDev *__restrict__ shots,
                                                          const Tile2D *__restrict__ tiles, int ntiles, int nslots,
                                                          const InjEnt *__restrict__ ents,
@@ -361,7 +356,7 @@ __global__ __launch_bounds__(64 * TX) void recv2d_kernel(const ShotDev *__restri
     C.x = C.x0 + lane * VEC;
     C.live = C.x < C.NX + kRadius;
     C.own = C.x < C.NX;
-    const bool img = snap && C.own && C.x + VEC > S.ix0 && C.x < S.ix1;
+    const bool img = IMG && C.own && C.x + VEC > S.ix0 && C.x < S.ix1;
     const SnapImg I{snap, S.ix1 - S.ix0, 1, S.ix0, S.ix1, 0, S.iz0};
     gfloat *A0 = gp(S.acc0 + S.L.org), *A1 = gp(S.acc1 + S.L.org);
 
@@ -376,19 +371,13 @@ __global__ __launch_bounds__(64 * TX) void recv2d_kernel(const ShotDev *__restri
     }
 #define RTM_RECV_ROW(SS, ZZ)                                                                        \
     fwd_row<VEC, TX, SS>(C, q, ZZ, ring);                                                          \
-    if (img && (ZZ) >= S.iz0 && (ZZ) < S.iz1)                                                      \
-        snap_image<VEC>(I, A0, A1, (int64_t)(ZZ) * C.pitch + C.x, ZZ, 0, C.x, q[((SS) + 4) % 9]);
+    if constexpr (IMG)                                                                             \
+        if (img && (ZZ) >= S.iz0 && (ZZ) < S.iz1)                                                  \
+            snap_image<VEC>(I, A0, A1, (int64_t)(ZZ) * C.pitch + C.x, ZZ, 0, C.x, q[((SS) + 4) % 9]);
     RTM_MARCH(RTM_RECV_ROW)
 #undef RTM_RECV_ROW
     // Receiver term: mu^k += D' R^T g^k.
-    const float *sig = S.sig + (int64_t)k * S.nrec;
-    for (int e = T.rbeg; e < T.rend; ++e) {
-        const InjEnt E = ents[e];
-        if (owns<VEC>(E.x, C.x0, C.lane)) {
-            const int64_t o = (int64_t)E.z * C.pitch + E.x;
-            C.po[o] = fmaf(C.Dp[o], inj_sum(E, cont, sig), C.po[o]);
-        }
-    }
+    inject_nodes(C.po, C.Dp, ents, T.rbeg, T.rend, cont, S.sig + (int64_t)k * S.nrec, C.pitch, C.pitch);
 }
 
 // ---------------------------------------------------------------------------
@@ -576,6 +565,8 @@ struct Rev2Ctx {
     const float *wav, *sig;           // wavelet and receiver signal at time k
     const InjEnt *ents;
     const Contrib *cont;
+    float *isv;                       // LDS: receiver sums of one row (row_inject)
+    int *ihas;
     int64_t pitch;
     int nrec;
     int x, xs, NX, NZr, lane, z0, z1, iz0, iz1, s1end, r1end;
@@ -644,13 +635,7 @@ __device__ __forceinline__ void rev2_row(const Rev2Ctx<VEC> &C, float (&q1p)[9][
         for (int j = 0; j < VEC; ++j)
             if (C.reinject && E.x == C.x + j) np[j] = fmaf(d[j], sv, np[j]);
     }
-    for (; er < C.r1end && C.ents[er].z == r1; ++er) {
-        const InjEnt E = C.ents[er];
-        const float sv = inj_sum(E, C.cont, C.sig);
-#pragma unroll
-        for (int j = 0; j < VEC; ++j)
-            if (E.x == C.x + j) nm[j] = fmaf(d[j], sv, nm[j]);
-    }
+    row_inject<VEC>(C.ents, C.cont, C.sig, r1, er, C.r1end, C.xs, C.lane, d, nm, C.isv, C.ihas);
 #pragma unroll
     for (int j = 0; j < VEC; ++j) {
         q2p[a4][j] = np[j];
@@ -745,6 +730,13 @@ void rev2d_t2_kernel(const ShotDev *__restrict__ shots,
     C.iz1 = S.iz1;
     C.s1end = T.s1end;
     C.r1end = T.r1end;
+    __shared__ float isv[64 * VEC];
+    __shared__ int ihas[64 * VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) ihas[lane * VEC + j] = 0;
+    __syncthreads();
+    C.isv = isv;
+    C.ihas = ihas;
     C.live = C.x >= -kRadius && C.x < C.NX + kRadius;
     C.own = own2<VEC>(C.x, C.xs, C.NX);
     C.own_img = C.own && C.x + VEC > S.ix0 && C.x < S.ix1;
@@ -778,14 +770,7 @@ void rev2d_t2_kernel(const ShotDev *__restrict__ shots,
             }
         }
     }
-    const float *sig1 = S.sig + (int64_t)(k - 1) * S.nrec;
-    for (int e = T.rbeg; e < T.rend; ++e) {
-        const InjEnt E = ents[e];
-        if (owns<VEC>(E.x, C.xs, lane)) {
-            const int64_t o = (int64_t)E.z * C.pitch + E.x;
-            C.WM2[o] = fmaf(C.Dp[o], inj_sum(E, cont, sig1), C.WM2[o]);
-        }
-    }
+    inject_nodes(C.WM2, C.Dp, ents, T.rbeg, T.rend, cont, S.sig + (int64_t)(k - 1) * S.nrec, C.pitch, C.pitch);
 }
 
 // ---------------------------------------------------------------------------
@@ -855,8 +840,13 @@ hipError_t launch_recv2d(int vec, int tx, const ShotDev *shots, const Tile2D *ti
                          const InjEnt *ents, const Contrib *cont, int k, const float *snap, hipStream_t st)
 {
     dim3 grid(nslots), block(64 * tx);
-#define RTM_RECV2D(V, X) \
-    hipLaunchKernelGGL((recv2d_kernel<V, X>), grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, snap)
+#define RTM_RECV2D(V, X)                                                                                             \
+    if (snap)                                                                                                        \
+        hipLaunchKernelGGL((recv2d_kernel<V, X, true>), grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, \
+                           snap);                                                                                    \
+    else                                                                                                             \
+        hipLaunchKernelGGL((recv2d_kernel<V, X, false>), grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, \
+                           k, snap)
 #define RTM_RECV2D_X(V)                             \
     switch (tx) {                                   \
     case 1: RTM_RECV2D(V, 1); break;                \

@@ -359,20 +359,13 @@ __global__ __launch_bounds__(64 * TY) void rev3d_kernel(const ShotDev *__restric
             }
         }
     }
-    const float *sig = S.sig + (int64_t)k * S.nrec;
-    for (int e = T.rbeg; e < T.rend; ++e) {
-        const InjEnt E = ents[e];
-        if (owns3<VEC>(C, E.y, E.x)) {
-            const int64_t o = (int64_t)E.z * C.plane + (int64_t)E.y * C.pitch + E.x;
-            M1[o] = fmaf(Dp[o], inj_sum(E, cont, sig), M1[o]);
-        }
-    }
+    inject_nodes(M1, Dp, ents, T.rbeg, T.rend, cont, S.sig + (int64_t)k * S.nrec, C.plane, C.pitch);
 }
 
 // Receiver wavefield alone, for migration with a stored source wavefield
 // (see the 2-D kernel): the forward plane update applied to mu, with the
-// imaging sums at a stored level taking p^k from the dense snapshot.
-template <int VEC, int TY>
+// imaging sums at a stored level taking p^k from the dense snapshot (IMG).
+template <int VEC, int TY, bool IMG>
 __global__ __launch_bounds__(64 * TY) void recv3d_kernel(const ShotDev *__restrict__ shots,
                                                          const Tile3D *__restrict__ tiles, int ntiles, int nslots,
                                                          const InjEnt *__restrict__ ents,
@@ -389,7 +382,7 @@ __global__ __launch_bounds__(64 * TY) void recv3d_kernel(const ShotDev *__restri
     gfloat *po = gp(S.fld[2 + (k & 1)] + S.L.org);              // mu^{k+2} -> mu^k
     const gfloat *Dp = gp(S.Dp + S.L.org);
     gfloat *A0 = gp(S.acc0 + S.L.org), *A1 = gp(S.acc1 + S.L.org);
-    const bool img = snap && C.own && C.x + VEC > S.ix0 && C.x < S.ix1 && C.y >= S.iy0 && C.y < S.iy1;
+    const bool img = IMG && C.own && C.x + VEC > S.ix0 && C.x < S.ix1 && C.y >= S.iy0 && C.y < S.iy1;
     const SnapImg I{snap, S.ix1 - S.ix0, S.iy1 - S.iy0, S.ix0, S.ix1, S.iy0, S.iz0};
     float q[9][VEC];
 #pragma unroll
@@ -401,19 +394,13 @@ __global__ __launch_bounds__(64 * TY) void recv3d_kernel(const ShotDev *__restri
     plane_prefetch<VEC>(C, Dp, T.z0, nd);
 #define RTM_RECV3(SS, ZZ)                                                                                       \
     fwd3_plane<VEC, TY, SS>(C, L, pc, po, Dp, q, nx, nold, nd, ZZ, T.z0, T.z1);                                  \
-    if (img && (ZZ) >= S.iz0 && (ZZ) < S.iz1)                                                                    \
-        snap_image<VEC>(I, A0, A1, (int64_t)(ZZ) * C.plane + (int64_t)C.y * C.pitch + C.x, ZZ, C.y, C.x,         \
-                        q[((SS) + 4) % 9]);
+    if constexpr (IMG)                                                                                           \
+        if (img && (ZZ) >= S.iz0 && (ZZ) < S.iz1)                                                                \
+            snap_image<VEC>(I, A0, A1, (int64_t)(ZZ) * C.plane + (int64_t)C.y * C.pitch + C.x, ZZ, C.y, C.x,     \
+                            q[((SS) + 4) % 9]);
     RTM_MARCH3(RTM_RECV3)
 #undef RTM_RECV3
-    const float *sig = S.sig + (int64_t)k * S.nrec;
-    for (int e = T.rbeg; e < T.rend; ++e) {
-        const InjEnt E = ents[e];
-        if (owns3<VEC>(C, E.y, E.x)) {
-            const int64_t o = (int64_t)E.z * C.plane + (int64_t)E.y * C.pitch + E.x;
-            po[o] = fmaf(Dp[o], inj_sum(E, cont, sig), po[o]);
-        }
-    }
+    inject_nodes(po, Dp, ents, T.rbeg, T.rend, cont, S.sig + (int64_t)k * S.nrec, C.plane, C.pitch);
 }
 
 // ---------------------------------------------------------------------------
@@ -478,8 +465,13 @@ hipError_t launch_recv3d(int vec, int ty, const ShotDev *shots, const Tile3D *ti
                          const InjEnt *ents, const Contrib *cont, int k, const float *snap, hipStream_t st)
 {
     dim3 grid(nslots), block(64 * ty);
-#define RTM_RC3(V, Y) \
-    hipLaunchKernelGGL((recv3d_kernel<V, Y>), grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, snap)
+#define RTM_RC3(V, Y)                                                                                              \
+    if (snap)                                                                                                      \
+        hipLaunchKernelGGL((recv3d_kernel<V, Y, true>), grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, \
+                           snap);                                                                                  \
+    else                                                                                                           \
+        hipLaunchKernelGGL((recv3d_kernel<V, Y, false>), grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, \
+                           k, snap)
 #define RTM_RC3V(Y)                            \
     switch (vec) {                             \
     case 1: RTM_RC3(1, Y); break;              \

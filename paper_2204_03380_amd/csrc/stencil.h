@@ -235,6 +235,64 @@ __device__ __forceinline__ float inj_sum(const InjEnt &E, const Contrib *__restr
     return s;
 }
 
+// Receiver term of a reverse step at the tile's receiver nodes
+// ents[beg, end): f += Dp * (weighted signal sum).  Every node lies in the
+// tile and appears once, so the workgroup's threads take the nodes in
+// parallel, after a barrier that orders the march's stores of f before
+// these read-modify-writes (one thread per node would otherwise walk the
+// whole list: at a receiver line with a receiver per column that serial
+// walk outlasts the march).  plane == pitch and y == 0 in 2-D.
+__device__ __forceinline__ void inject_nodes(gfloat *f, const gfloat *Dp, const InjEnt *__restrict__ ents, int beg,
+                                             int end, const Contrib *__restrict__ cont, const float *sig,
+                                             int64_t plane, int64_t pitch)
+{
+    __syncthreads();
+    for (int e = beg + (int)threadIdx.x; e < end; e += (int)blockDim.x) {
+        const InjEnt E = ents[e];
+        const int64_t o = (int64_t)E.z * plane + (int64_t)E.y * pitch + E.x;
+        f[o] = fmaf(Dp[o], inj_sum(E, cont, sig), f[o]);
+    }
+}
+
+// Inside a wavefront's march: adds Dp * (weighted signal sum) into v at the
+// lane's VEC cells for every entry ents[e ..) of row r (entries sorted by
+// row, each column at most once per row; e advances past them).  The lanes
+// take up to 64 entries at a time and hand each sum to the owning lane
+// through LDS (sv, has: 64 * VEC slots, has zero on entry), instead of every
+// lane walking the list.  The workgroup is this one wavefront, and e and r
+// are uniform, so the barriers are reached by every lane.
+template <int VEC>
+__device__ __forceinline__ void row_inject(const InjEnt *ents, const Contrib *__restrict__ cont, const float *sig,
+                                           int r, int &e, int eend, int xs, int lane, const float (&d)[VEC],
+                                           float (&v)[VEC], float *sv, int *has)
+{
+    if (e >= eend || ents[e].z != r) return;
+    while (true) {
+        const int i = e + lane;
+        const bool mine = i < eend && ents[i].z == r;
+        const unsigned long long m = __ballot(mine);
+        if (mine) {
+            const InjEnt E = ents[i];
+            const int col = E.x - xs;
+            sv[col] = inj_sum(E, cont, sig);
+            has[col] = 1;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const int c = lane * VEC + j;
+            if (has[c]) {
+                v[j] = fmaf(d[j], sv[c], v[j]);
+                has[c] = 0;
+            }
+        }
+        __syncthreads();
+        const int n = __popcll(m);
+        e += n;
+        if (n < 64) break;
+    }
+}
+
 // Does this lane own padded column x of a strip starting at x0?
 template <int VEC>
 __device__ __forceinline__ bool owns(int x, int x0, int lane)
