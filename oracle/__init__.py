@@ -32,6 +32,11 @@ def _load():
         lib.orc_splitmix64.restype = c_u64
         lib.orc_rbc_pad.argtypes = [c_int, c_long, c_long, c_long, c_int, P, c_u64, ctypes.c_float, P]
         lib.orc_pad_adjoint.argtypes = [c_int, c_long, c_long, c_long, c_int, P, c_u64, ctypes.c_float, P, P]
+        lib.orc_rbc_pad_ex.argtypes = [c_int, c_long, c_long, c_long, c_int, P, c_u64, ctypes.c_float, ctypes.c_uint,
+                                       c_double, P]
+        lib.orc_pad_adjoint_ex.argtypes = [c_int, c_long, c_long, c_long, c_int, P, c_u64, ctypes.c_float,
+                                           ctypes.c_uint, c_double, P, P]
+        lib.orc_taper.argtypes = [c_int, c_double, P]
         lib.orc_laplacian.argtypes = [c_int, c_long, c_long, c_long, c_double, P, P]
         lib.orc_model_shot.argtypes = [c_int, c_long, c_long, c_long, c_int, c_double, P, c_double, c_int,
                                        P, P, c_int, P, P, P, P, P]
@@ -40,7 +45,7 @@ def _load():
         lib.orc_rtm_storage_shot.argtypes = [c_int, c_long, c_long, c_long, c_int, c_double, P, c_double, c_int,
                                              P, P, c_int, P, P, c_int, c_int, c_double, P, P, P]
         for f in ("orc_rbc_pad", "orc_pad_adjoint", "orc_laplacian", "orc_model_shot", "orc_rtm_shot",
-                  "orc_rtm_storage_shot"):
+                  "orc_rtm_storage_shot", "orc_rbc_pad_ex", "orc_pad_adjoint_ex", "orc_taper"):
             getattr(lib, f).restype = c_int
         _lib = lib
     return _lib
@@ -72,8 +77,20 @@ def splitmix64(seed: int, k: int) -> int:
     return int(_load().orc_splitmix64(seed, k))
 
 
-def rbc_pad(v_int, nb: int, seed: int, v_cap: float = 0.0):
-    """Padded FP32 velocity with random boundaries (bit-exact definition)."""
+RBC_TAPER = 1
+RBC_FREE_SURFACE = 2
+
+
+def _rbc_flags(free_surface, taper):
+    flags = (RBC_FREE_SURFACE if free_surface else 0) | (RBC_TAPER if taper is not None else 0)
+    return flags, float(taper) if taper is not None else 0.0
+
+
+def rbc_pad(v_int, nb: int, seed: int, v_cap: float = 0.0, free_surface: bool = False, taper=None):
+    """Padded FP32 velocity with random boundaries (bit-exact definition).
+    taper: None, or the weight alpha in [0, 1] of Eq. (4)'s linear taper
+    against Eq. (5)'s Gaussian one; free_surface: zero velocity above the
+    interior."""
     v_int = np.ascontiguousarray(v_int, dtype=np.float32)
     if v_int.ndim == 2:
         nz, nx = v_int.shape
@@ -82,11 +99,13 @@ def rbc_pad(v_int, nb: int, seed: int, v_cap: float = 0.0):
         nz, ny, nx = v_int.shape
         ndim, shape = 3, (nz + 2 * nb, ny + 2 * nb, nx + 2 * nb)
     out = np.empty(shape, dtype=np.float32)
-    _check(_load().orc_rbc_pad(ndim, nx, ny, nz, nb, _ptr(v_int), seed, v_cap, _ptr(out)), "orc_rbc_pad")
+    flags, alpha = _rbc_flags(free_surface, taper)
+    _check(_load().orc_rbc_pad_ex(ndim, nx, ny, nz, nb, _ptr(v_int), seed, v_cap, flags, alpha, _ptr(out)),
+           "orc_rbc_pad_ex")
     return out
 
 
-def pad_adjoint(v_int, nb: int, seed: int, v_cap: float, grad_pad):
+def pad_adjoint(v_int, nb: int, seed: int, v_cap: float, grad_pad, free_surface: bool = False, taper=None):
     v_int = np.ascontiguousarray(v_int, dtype=np.float32)
     grad_pad = np.ascontiguousarray(grad_pad, dtype=np.float64)
     if v_int.ndim == 2:
@@ -96,8 +115,16 @@ def pad_adjoint(v_int, nb: int, seed: int, v_cap: float, grad_pad):
         nz, ny, nx = v_int.shape
         ndim = 3
     out = np.empty(v_int.shape, dtype=np.float64)
-    _check(_load().orc_pad_adjoint(ndim, nx, ny, nz, nb, _ptr(v_int), seed, v_cap, _ptr(grad_pad), _ptr(out)),
-           "orc_pad_adjoint")
+    flags, alpha = _rbc_flags(free_surface, taper)
+    _check(_load().orc_pad_adjoint_ex(ndim, nx, ny, nz, nb, _ptr(v_int), seed, v_cap, flags, alpha, _ptr(grad_pad),
+                                      _ptr(out)), "orc_pad_adjoint_ex")
+    return out
+
+
+def taper(nb: int, alpha: float):
+    """c_i, i = 1 .. nb, of the band taper (FP32)."""
+    out = np.empty(nb, dtype=np.float32)
+    _check(_load().orc_taper(nb, float(alpha), _ptr(out)), "orc_taper")
     return out
 
 

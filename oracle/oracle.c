@@ -88,80 +88,147 @@ uint64_t orc_splitmix64(uint64_t seed, uint64_t k)
 
 static long og_clampl(long v, long lo, long hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
-/* v_pad[j] = v_int[j - nb] inside; in the band, fminf(f_j * v_edge, v_cap)
- * with f_j = fmaf(0.6f, u_j, 0.7f) and u_j the top 24 bits of
- * SplitMix64(seed, j) scaled by 2^-24, j the padded linear index.  These
- * values are FP32 by definition and must match the GPU bit for bit.
+/* Band options (the paper's setup, Sec. "Wavefield Reconstruction" and the
+ * model description of the 2-D and 3-D tests). */
+#define ORC_RBC_TAPER 1u        /* scale band velocities by c_i, Eqs. (4)-(5) */
+#define ORC_RBC_FREE_SURFACE 2u /* top band: v = 0 (p stays 0 above the surface) */
+
+/* Taper coefficient of band depth i = 1 .. nb (i = 1 touches the interior):
+ * c_i = alpha g(i) + (1 - alpha) h(i) with Eq. (4) g(i) = (nb - i)/(nb - 1)
+ * and Eq. (5) h(i) = exp(-120 (i - 1)^2 / (nb - 1)^2), evaluated in double
+ * and rounded once to FP32; nb = 1 gives c_1 = 1.  For alpha in [0, 1] the
+ * value lies between h and g. */
+static float og_taper(int nb, int i, double alpha)
+{
+    if (nb <= 1) return 1.0f;
+    double x = (double)i, n1 = (double)(nb - 1);
+    double g = ((double)nb - x) / n1;
+    double hh = exp(-120.0 * (x - 1.0) * (x - 1.0) / (n1 * n1));
+    return (float)(alpha * g + (1.0 - alpha) * hh);
+}
+
+/* Distance of padded cell coordinate a (interior at [0, n)) from the
+ * interior along one axis: 0 inside. */
+static long og_depth(long a, long n) { return a < 0 ? -a : (a >= n ? a - n + 1 : 0); }
+
+/* Random factor of band cell j: f_j = fmaf(0.6f, u_j, 0.7f), u_j the top 24
+ * bits of SplitMix64(seed, j) scaled by 2^-24. */
+static float og_rbc_factor(uint64_t seed, long j)
+{
+    uint64_t r = orc_splitmix64(seed, (uint64_t)j);
+    float u = (float)(r >> 40) * (1.0f / 16777216.0f);
+    return fmaf(0.6f, u, 0.7f);
+}
+
+static float og_vmax(const float *v, long n)
+{
+    float m = v[0];
+    for (long i = 0; i < n; ++i)
+        if (v[i] > m) m = v[i];
+    return m;
+}
+
+/* Random boundary with options.  Interior: v_pad = v_int.  Band cell j at
+ * depth i (the largest per-axis distance from the interior) with edge value
+ * v_edge (the nearest interior cell):
+ *   default:   fminf(f_j * v_edge, v_cap)
+ *   TAPER:     fminf(c_i * (f_j * v_edge), v_cap)
+ *   FREE_SURFACE and the cell lies above the interior (z < 0): 0.
+ * All values are FP32 by definition and match the GPU bit for bit.
  * v_cap <= 0 selects the interior maximum.  Returns 0, or -1 on bad args. */
-int orc_rbc_pad(int ndim, long nx, long ny, long nz, int nb, const float *v_int,
-                uint64_t seed, float v_cap, float *v_pad)
+int orc_rbc_pad_ex(int ndim, long nx, long ny, long nz, int nb, const float *v_int, uint64_t seed, float v_cap,
+                   unsigned flags, double alpha, float *v_pad)
 {
     og_grid g;
     if (og_make(&g, ndim, nx, ny, nz, nb, 1.0) != 0 || !v_int || !v_pad) return -1;
-    if (!(v_cap > 0.0f)) {
-        float vmax = v_int[0];
-        for (long i = 0; i < g.nx * g.ny * g.nz; ++i)
-            if (v_int[i] > vmax) vmax = v_int[i];
-        v_cap = vmax;
-    }
+    if ((flags & ORC_RBC_TAPER) && !(alpha >= 0.0 && alpha <= 1.0)) return -1;
+    if (!(v_cap > 0.0f)) v_cap = og_vmax(v_int, g.nx * g.ny * g.nz);
     for (long z = 0; z < g.NZ; ++z)
         for (long y = 0; y < g.NY; ++y)
             for (long x = 0; x < g.NX; ++x) {
                 long iz = z - nb, ix = x - nb, iy = (ndim == 3) ? y - nb : 0;
-                int inside = (ix >= 0 && ix < g.nx && iz >= 0 && iz < g.nz && iy >= 0 && iy < g.ny);
+                long d = og_depth(ix, g.nx), dz = og_depth(iz, g.nz), dy = ndim == 3 ? og_depth(iy, g.ny) : 0;
+                if (dz > d) d = dz;
+                if (dy > d) d = dy;
                 long ez = og_clampl(iz, 0, g.nz - 1);
                 long ey = og_clampl(iy, 0, g.ny - 1);
                 long ex = og_clampl(ix, 0, g.nx - 1);
                 float v_edge = v_int[(ez * g.ny + ey) * g.nx + ex];
                 long j = og_index(&g, z, y, x);
-                if (inside) {
+                if (d == 0) {
                     v_pad[j] = v_edge;
+                } else if ((flags & ORC_RBC_FREE_SURFACE) && iz < 0) {
+                    v_pad[j] = 0.0f;
                 } else {
-                    uint64_t r = orc_splitmix64(seed, (uint64_t)j);
-                    float u = (float)(r >> 40) * (1.0f / 16777216.0f);
-                    float f = fmaf(0.6f, u, 0.7f);
-                    float v = f * v_edge;
+                    float v = og_rbc_factor(seed, j) * v_edge;
+                    if (flags & ORC_RBC_TAPER) v = og_taper(nb, (int)d, alpha) * v;
                     v_pad[j] = fminf(v, v_cap);
                 }
             }
     return 0;
 }
 
-/* Adjoint of the padding with respect to v_int, with the random factors
- * and v_cap held fixed: interior cells pass their gradient through, each
- * band cell adds f_j times its gradient to its edge cell unless it was
- * capped (f_j * v_edge >= v_cap, where the derivative is zero). */
-int orc_pad_adjoint(int ndim, long nx, long ny, long nz, int nb, const float *v_int,
-                    uint64_t seed, float v_cap, const double *grad_pad, double *grad_int)
+int orc_rbc_pad(int ndim, long nx, long ny, long nz, int nb, const float *v_int,
+                uint64_t seed, float v_cap, float *v_pad)
+{
+    return orc_rbc_pad_ex(ndim, nx, ny, nz, nb, v_int, seed, v_cap, 0u, 0.0, v_pad);
+}
+
+/* Adjoint of the padding with respect to v_int, with the random factors,
+ * the taper and v_cap held fixed: interior cells pass their gradient
+ * through; a band cell adds (c_i) f_j times its gradient to its edge cell
+ * unless it was capped (value >= v_cap, where the derivative is zero); a
+ * free-surface cell (v = 0 whatever v_int) adds nothing. */
+int orc_pad_adjoint_ex(int ndim, long nx, long ny, long nz, int nb, const float *v_int, uint64_t seed, float v_cap,
+                       unsigned flags, double alpha, const double *grad_pad, double *grad_int)
 {
     og_grid g;
     if (og_make(&g, ndim, nx, ny, nz, nb, 1.0) != 0 || !v_int || !grad_pad || !grad_int) return -1;
-    if (!(v_cap > 0.0f)) {
-        float vmax = v_int[0];
-        for (long i = 0; i < g.nx * g.ny * g.nz; ++i)
-            if (v_int[i] > vmax) vmax = v_int[i];
-        v_cap = vmax;
-    }
+    if ((flags & ORC_RBC_TAPER) && !(alpha >= 0.0 && alpha <= 1.0)) return -1;
+    if (!(v_cap > 0.0f)) v_cap = og_vmax(v_int, g.nx * g.ny * g.nz);
     for (long i = 0; i < g.nx * g.ny * g.nz; ++i) grad_int[i] = 0.0;
     for (long z = 0; z < g.NZ; ++z)
         for (long y = 0; y < g.NY; ++y)
             for (long x = 0; x < g.NX; ++x) {
                 long iz = z - nb, ix = x - nb, iy = (ndim == 3) ? y - nb : 0;
-                int inside = (ix >= 0 && ix < g.nx && iz >= 0 && iz < g.nz && iy >= 0 && iy < g.ny);
+                long d = og_depth(ix, g.nx), dz = og_depth(iz, g.nz), dy = ndim == 3 ? og_depth(iy, g.ny) : 0;
+                if (dz > d) d = dz;
+                if (dy > d) d = dy;
                 long ez = og_clampl(iz, 0, g.nz - 1);
                 long ey = og_clampl(iy, 0, g.ny - 1);
                 long ex = og_clampl(ix, 0, g.nx - 1);
                 long e = (ez * g.ny + ey) * g.nx + ex;
                 long j = og_index(&g, z, y, x);
-                if (inside) {
+                if (d == 0) {
                     grad_int[e] += grad_pad[j];
+                } else if ((flags & ORC_RBC_FREE_SURFACE) && iz < 0) {
+                    /* constant zero */
                 } else {
-                    uint64_t r = orc_splitmix64(seed, (uint64_t)j);
-                    float u = (float)(r >> 40) * (1.0f / 16777216.0f);
-                    float f = fmaf(0.6f, u, 0.7f);
-                    if (f * v_int[e] < v_cap) grad_int[e] += (double)f * grad_pad[j];
+                    float f = og_rbc_factor(seed, j);
+                    float v = f * v_int[e];
+                    double scale = (double)f;
+                    if (flags & ORC_RBC_TAPER) {
+                        float c = og_taper(nb, (int)d, alpha);
+                        v = c * v;
+                        scale *= (double)c;
+                    }
+                    if (v < v_cap) grad_int[e] += scale * grad_pad[j];
                 }
             }
+    return 0;
+}
+
+int orc_pad_adjoint(int ndim, long nx, long ny, long nz, int nb, const float *v_int,
+                    uint64_t seed, float v_cap, const double *grad_pad, double *grad_int)
+{
+    return orc_pad_adjoint_ex(ndim, nx, ny, nz, nb, v_int, seed, v_cap, 0u, 0.0, grad_pad, grad_int);
+}
+
+/* Taper table for the pins: c[i - 1] for i = 1 .. nb. */
+int orc_taper(int nb, double alpha, float *c)
+{
+    if (nb < 1 || !c || !(alpha >= 0.0 && alpha <= 1.0)) return -1;
+    for (int i = 1; i <= nb; ++i) c[i - 1] = og_taper(nb, i, alpha);
     return 0;
 }
 
@@ -477,8 +544,9 @@ int orc_rtm_shot(int ndim, long nx, long ny, long nz, int nb, double h, const fl
             }
     if (grad_pad)
         for (long i = 0; i < n; ++i) {
+            /* dJ/dv = 2 v dt^2 dJ/dD: zero where v = 0 (a free-surface band) */
             double v = (double)v_pad[i];
-            grad_pad[i] = 2.0 * G[i] / (v * v * v * dt * dt);
+            grad_pad[i] = v == 0.0 ? 0.0 : 2.0 * G[i] / (v * v * v * dt * dt);
         }
     free(D);
     free(pa);
