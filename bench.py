@@ -74,6 +74,9 @@ def parse():
                     help="instead of the survey benchmark: single-shot modeling and RTM at the grid sizes of the "
                          "paper's Tables 1-4 (modeling timed over a shortened nt and scaled to the paper's nt; "
                          "RTM with reconstruction and with storage at the paper's nt)")
+    ap.add_argument("--boundary-study", action="store_true",
+                    help="instead of the survey benchmark: RTM crosstalk of one shot for the band setups (uniform "
+                         "random factors, Eqs. (4)-(5) tapers, free surface)")
     ap.add_argument("--paper-kinds", default="modeling,rtm,storage",
                     help="with --paper-shapes: comma-separated kinds to run")
     return ap.parse_args()
@@ -231,6 +234,85 @@ def paper_shapes(nb=50, reps_2d=400, reps_3d=60, kinds=("modeling", "rtm", "stor
     return out
 
 
+BAND_MODES = (("uniform factors", None), ("taper Gaussian h (alpha 0)", 0.0), ("taper midway (alpha 0.5)", 0.5),
+              ("taper linear g (alpha 1)", 1.0))
+
+
+def boundary_study(K=8, seed0=500):
+    """Boundary crosstalk of one RTM shot against the band setup: the
+    uniform random factors, the tapers of Eqs. (4)-(5), each with and
+    without the free-surface top.  Crosstalk index = mean over K seeds of
+    |I_s - I_mean| / |I_mean| (the boundary noise differs between seeds, the
+    reflector image does not), over the whole image and below the near
+    surface (z >= 20 cells), where it is also given against the first
+    setup's stack norm.  Observed data: the same shot on the model
+    extended far enough that no boundary energy returns within nt (top
+    extended too, or a free surface), direct wave removed."""
+    import numpy as np
+    import torch
+
+    import paper_2204_03380_amd as rtm
+    import synth
+    dev = torch.device("cuda:0")
+    # three flat layers within two-way reach of the recording time, one dipping
+    nz, nx, h, nb, dt, nt = 201, 301, 10.0, 40, 1e-3, 1200
+    zz, xx = np.meshgrid(np.arange(nz), np.arange(nx), indexing="ij")
+    v = np.full((nz, nx), 1500.0, np.float32)
+    v[zz >= 40 + 0.15 * (xx - nx / 2)] = 2000.0
+    v[zz >= 80] = 2500.0
+    w = torch.from_numpy(synth.ricker(15.0, dt, nt)).to(dev)
+    src, rec = np.array([nx / 2.0, 0.0, 2.0]), synth.line_receivers(np.arange(nx), 2.0)
+    name = f"three-layer 2-D {nx}x{nz} @ {h:g} m, nb {nb}, dt {dt * 1e3:g} ms, nt {nt}, 15 Hz"
+    ext = int(nt * dt * float(v.max()) / (2 * h)) + 2
+    g = rtm.Grid.for_model(v, h, nb)
+    vt = torch.from_numpy(v).to(dev)
+    cap = float(v.max())
+    rows = []
+    ref_norm = None  # the stack of the first setup (uniform factors, no free surface) below the near surface
+    for fs in (False, True):
+        top = 0 if fs else ext
+        v_ext = np.pad(v, ((top, ext), (ext, ext)), mode="edge")
+        ge = rtm.Grid.for_model(v_ext, h, 16)
+        shift = np.array([ext, 0.0, top])
+        v0 = float(v[int(round(src[2])), int(round(src[0]))])
+
+        def model(vm):
+            vp = rtm.rtm_rbc_pad(ge, torch.from_numpy(np.ascontiguousarray(vm)).to(dev), 1, float(vm.max()),
+                                 free_surface=fs)
+            return rtm.rtm_model_shot(ge, vp, dt, w, src + shift, rec + shift.astype(np.float32))
+
+        d_obs = model(v_ext) - model(np.full(v_ext.shape, v0, np.float32))
+        for name, alpha in BAND_MODES:
+            seeds = [seed0 + k for k in range(K)]
+            imgs = torch.empty((K,) + tuple(v.shape), dtype=torch.float32, device=dev)
+            shots = [rtm.BatchShot(g, rtm.rtm_rbc_pad(g, vt, sd, cap, free_surface=fs, taper=alpha), w, src, rec,
+                                   traces_in=d_obs, image=imgs[i]) for i, sd in enumerate(seeds)]
+            rtm.BatchPlan(rtm.RTM_OP_RTM, shots, dt, nt, eps_rel=1e-3).run()
+            mean = imgs.double().mean(0)
+            nsr = float(np.mean([float(torch.linalg.norm(imgs[i].double() - mean) / torch.linalg.norm(mean))
+                                 for i in range(K)]))
+            # below the near surface (z >= 20 cells), where the reflectors are
+            win = (slice(20, None), slice(None))
+            noise = float(np.mean([float(torch.linalg.norm((imgs[i].double() - mean)[win])) for i in range(K)]))
+            if ref_norm is None:
+                ref_norm = float(torch.linalg.norm(mean[win]))
+            # reconstruction still exact: probe p^k against the forward field
+            k = nt // 2
+            vp0 = shots[0].v_pad
+            _, pk, _ = rtm.rtm_model_shot(g, vp0, dt, w[:k].contiguous(), src, rec, want_last=True)
+            probe = rtm.rtm_rtm_shot(g, vp0, dt, w, src, rec, d_obs, snap_k=k)["snap_p"]
+            rev = float(torch.linalg.norm((probe - pk).double()) / torch.linalg.norm(pk.double()))
+            vmax_band = float(vp0.max())
+            row = {"band": name, "free_surface": fs, "crosstalk_index": round(nsr, 4),
+                   "crosstalk_index_below_20": round(noise / float(torch.linalg.norm(mean[win])), 4),
+                   "noise_below_20_vs_uniform_stack": round(noise / ref_norm, 4),
+                   "reconstruction_rel_err": float(f"{rev:.2e}"),
+                   "courant_max": round(vmax_band * dt / h, 4), "courant_limit": round((315 / 1024) ** 0.5, 4)}
+            rows.append(row)
+            print(json.dumps(row), file=sys.stderr, flush=True)
+    return {"model": name, "seeds": K, "rows": rows}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -239,6 +321,12 @@ def main():
               "independent and a multi-GPU run would be a shot partition plus one image all-reduce, which this "
               "build does not include.", file=sys.stderr)
         sys.exit(2)
+
+    if args.boundary_study:
+        out = boundary_study()
+        print(json.dumps({"metric": "RTM boundary crosstalk index by band setup", "unit": "ratio", "n_gpus": 1,
+                          "higher_is_better": False, "dtype": "f32", "data": "synthetic", **out}), flush=True)
+        return
 
     if args.paper_shapes:
         rows = paper_shapes(kinds=tuple(args.paper_kinds.split(",")))

@@ -62,7 +62,7 @@ extern "C" {
 #define RTM_ERANGE (-3)     /* a source or receiver lies outside the interior   */
 #define RTM_EWORKSPACE (-4) /* workspace null or smaller than required          */
 #define RTM_EHIP (-5)       /* a HIP runtime call or kernel launch failed       */
-#define RTM_ENUMERIC (-6)   /* velocity non-finite or not strictly positive     */
+#define RTM_ENUMERIC (-6)   /* velocity non-finite, negative or all zero        */
 
 /* Operations, for rtm_workspace_bytes. */
 #define RTM_OP_RBC_PAD 0 /* rtm_rbc_pad and rtm_pad_adjoint with v_cap <= 0 */
@@ -185,6 +185,44 @@ int rtm_workspace_bytes(const rtm_grid_t *grid, int op, int32_t nrec, int32_t nt
  *          rtm_workspace_bytes(RTM_OP_RBC_PAD) bytes (else ws may be NULL). */
 int rtm_rbc_pad(const rtm_grid_t *grid, const float *v_int, uint64_t seed, float v_cap,
                 float *v_pad, void *ws, size_t ws_bytes, void *stream);
+
+/* Band options of the random boundary: the paper's setup (Sec. "Wavefield
+ * Reconstruction", Eqs. (4)-(5); the models of the 2-D and 3-D tests put
+ * no band above the surface). */
+#define RTM_RBC_TAPER 0x1u        /* scale band velocities by c_i, see below */
+#define RTM_RBC_FREE_SURFACE 0x2u /* zero velocity above the interior       */
+
+typedef struct rtm_rbc_opts {
+    uint64_t seed;
+    float v_cap;         /* as in rtm_rbc_pad */
+    uint32_t flags;      /* RTM_RBC_TAPER | RTM_RBC_FREE_SURFACE or 0 */
+    double taper_alpha;  /* RTM_RBC_TAPER: weight in [0, 1] of Eq. (4) */
+} rtm_rbc_opts_t;
+
+/* rtm_rbc_pad with band options.  Let i in [1, nb] be a band cell's depth,
+ * the largest per-axis distance from the interior (i = 1 touches it).
+ *  - RTM_RBC_TAPER: the value is min(c_i * (f_j * v_edge), v_cap) (FP32
+ *    products in that order) with c_i = a g(i) + (1 - a) h(i), a =
+ *    taper_alpha, g(i) = (nb - i)/(nb - 1) (Eq. (4)) and h(i) =
+ *    exp(-120 (i - 1)^2 / (nb - 1)^2) (Eq. (5)), evaluated in double and
+ *    rounded once to FP32 (c_1 = 1; nb = 1 gives 1).  So h <= c_i <= g and
+ *    the band slows to ~0 at the outer face.  Needs nb <= 256.
+ *  - RTM_RBC_FREE_SURFACE: every cell above the interior (z < nb) gets
+ *    v = 0.  D' = 0 there, so p stays zero: the pressure-release surface of
+ *    Eq. (1)'s Dirichlet condition sits one row above the interior, as with
+ *    the paper's half-stencil top pad.
+ * Propagation calls accept zero velocities (and return a zero velocity
+ * gradient there).  opts is read during the call; other arguments and
+ * errors as in rtm_rbc_pad. */
+int rtm_rbc_pad_ex(const rtm_grid_t *grid, const float *v_int, const rtm_rbc_opts_t *opts,
+                   float *v_pad, void *ws, size_t ws_bytes, void *stream);
+
+/* Adjoint of rtm_rbc_pad_ex with respect to v_int: as rtm_pad_adjoint with
+ * the factor c_i f_j (FP32 product) under RTM_RBC_TAPER; free-surface cells
+ * contribute nothing. */
+int rtm_pad_adjoint_ex(const rtm_grid_t *grid, const float *v_int, const rtm_rbc_opts_t *opts,
+                       const float *grad_v_pad, float *grad_v_int, void *ws, size_t ws_bytes,
+                       void *stream);
 
 /* Adjoint of rtm_rbc_pad with respect to v_int, the random factors and
  * v_cap held fixed: grad_v_int[i] = grad_v_pad[i] + sum of f_j grad_v_pad[j]

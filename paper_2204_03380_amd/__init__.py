@@ -155,9 +155,17 @@ def rtm_timing_read() -> dict:
     return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(LOOP_KINDS)}
 
 
+def _rbc_opts(seed, v_cap, free_surface, taper):
+    flags = (_lib.RTM_RBC_FREE_SURFACE if free_surface else 0) | (_lib.RTM_RBC_TAPER if taper is not None else 0)
+    return _lib.RtmRbcOpts(int(seed), float(v_cap), flags, float(taper) if taper is not None else 0.0)
+
+
 def rtm_rbc_pad(grid: Grid, v_int: torch.Tensor, seed: int, v_cap: float = 0.0,
-                out: torch.Tensor = None) -> torch.Tensor:
-    """Padded FP32 velocity with the seeded random boundary (see rtm.h)."""
+                out: torch.Tensor = None, free_surface: bool = False, taper=None) -> torch.Tensor:
+    """Padded FP32 velocity with the seeded random boundary (see rtm.h);
+    taper: None or the weight in [0, 1] of the linear profile against the
+    Gaussian one (Eqs. (4)-(5)); free_surface: zero velocity above the
+    interior."""
     _dev(v_int, "v_int", grid.interior_shape)
     if out is None:
         v_pad = torch.empty(grid.padded_shape, dtype=torch.float32, device=v_int.device)
@@ -166,21 +174,23 @@ def rtm_rbc_pad(grid: Grid, v_int: torch.Tensor, seed: int, v_cap: float = 0.0,
         v_pad = out
     ws = _workspace(grid, RTM_OP_RBC_PAD, 0, 0, v_int.device)
     g = grid.c()
-    _lib.check(_lib.load().rtm_rbc_pad(ctypes.byref(g), v_int.data_ptr(), int(seed), float(v_cap), v_pad.data_ptr(),
-                                       ws.data_ptr(), ws.numel(), _stream(v_int.device)))
+    o = _rbc_opts(seed, v_cap, free_surface, taper)
+    _lib.check(_lib.load().rtm_rbc_pad_ex(ctypes.byref(g), v_int.data_ptr(), ctypes.byref(o), v_pad.data_ptr(),
+                                          ws.data_ptr(), ws.numel(), _stream(v_int.device)))
     return v_pad
 
 
 def rtm_pad_adjoint(grid: Grid, v_int: torch.Tensor, seed: int, v_cap: float,
-                    grad_v_pad: torch.Tensor) -> torch.Tensor:
+                    grad_v_pad: torch.Tensor, free_surface: bool = False, taper=None) -> torch.Tensor:
     _dev(v_int, "v_int", grid.interior_shape)
     _dev(grad_v_pad, "grad_v_pad", grid.padded_shape)
     out = torch.empty(grid.interior_shape, dtype=torch.float32, device=v_int.device)
     ws = _workspace(grid, RTM_OP_RBC_PAD, 0, 0, v_int.device)
     g = grid.c()
-    _lib.check(_lib.load().rtm_pad_adjoint(ctypes.byref(g), v_int.data_ptr(), int(seed), float(v_cap),
-                                           grad_v_pad.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
-                                           _stream(v_int.device)))
+    o = _rbc_opts(seed, v_cap, free_surface, taper)
+    _lib.check(_lib.load().rtm_pad_adjoint_ex(ctypes.byref(g), v_int.data_ptr(), ctypes.byref(o),
+                                              grad_v_pad.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                              _stream(v_int.device)))
     return out
 
 

@@ -29,7 +29,7 @@ EXPORTS = (
     "rtm_abi_version", "rtm_last_error", "rtm_set_tuning", "rtm_get_tuning", "rtm_set_tuning2d",
     "rtm_get_tuning2d", "rtm_set_steps_per_launch", "rtm_get_steps_per_launch", "rtm_set_tuning3d",
     "rtm_get_tuning3d", "rtm_timing_enable", "rtm_timing_read",
-    "rtm_workspace_bytes", "rtm_rbc_pad",
+    "rtm_workspace_bytes", "rtm_rbc_pad", "rtm_rbc_pad_ex", "rtm_pad_adjoint_ex",
     "rtm_pad_adjoint", "rtm_model_shot", "rtm_rtm_shot", "rtm_nyquist_stride", "rtm_storage_count",
     "rtm_storage_shot", "rtm_model_shot_vjp", "rtm_batch_plan", "rtm_batch_run",
     "rtm_batch_free", "rtm_window_extract", "rtm_window_accumulate", "rtm_misfit_ws_bytes", "rtm_l2_misfit",
@@ -57,6 +57,15 @@ class RtmShotDesc(ctypes.Structure):
 class UnetConvDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("d", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("cin", ctypes.c_int32), ("cout", ctypes.c_int32)]
+
+
+class RtmRbcOpts(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("v_cap", ctypes.c_float), ("flags", ctypes.c_uint32),
+                ("taper_alpha", ctypes.c_double)]
+
+
+RTM_RBC_TAPER = 0x1
+RTM_RBC_FREE_SURFACE = 0x2
 
 
 class RtmProbe(ctypes.Structure):
@@ -95,6 +104,8 @@ def load():
         "rtm_workspace_bytes": ([G, ctypes.c_int, I32, I32, ctypes.POINTER(SZ)], ctypes.c_int),
         "rtm_rbc_pad": ([G, P, U64, F, P, P, SZ, P], ctypes.c_int),
         "rtm_pad_adjoint": ([G, P, U64, F, P, P, P, SZ, P], ctypes.c_int),
+        "rtm_rbc_pad_ex": ([G, P, ctypes.POINTER(RtmRbcOpts), P, P, SZ, P], ctypes.c_int),
+        "rtm_pad_adjoint_ex": ([G, P, ctypes.POINTER(RtmRbcOpts), P, P, P, SZ, P], ctypes.c_int),
         "rtm_model_shot": ([G, P, D, I32, P, P, I32, P, P, P, P, U32, P, SZ, P], ctypes.c_int),
         "rtm_rtm_shot": ([G, P, D, I32, P, P, I32, P, P, F, P, P, P, ctypes.POINTER(RtmProbe), U32, P, SZ, P],
                          ctypes.c_int),

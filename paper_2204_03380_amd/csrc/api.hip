@@ -45,10 +45,10 @@ hipError_t launch_recv3d(int vec, int ty, const ShotDev *shots, const Tile3D *ti
 hipError_t launch_vrange(const float *v, int64_t n, unsigned *maxmin2, hipStream_t st);
 hipError_t launch_vmax(const float *v, int64_t n, unsigned *out, hipStream_t st);
 hipError_t launch_rbc_pad(int ndim, int nb, int64_t nx, int64_t ny, int64_t nz, const float *v_int, uint64_t seed,
-                          float v_cap, const unsigned *cap_bits, float *v_pad, hipStream_t st);
+                          float v_cap, const unsigned *cap_bits, const BandOpts &o, float *v_pad, hipStream_t st);
 hipError_t launch_pad_adjoint(int ndim, int nb, int64_t nx, int64_t ny, int64_t nz, const float *v_int,
-                              uint64_t seed, float v_cap, const unsigned *cap_bits, const float *g_pad,
-                              float *g_int, hipStream_t st);
+                              uint64_t seed, float v_cap, const unsigned *cap_bits, const BandOpts &o,
+                              const float *g_pad, float *g_int, hipStream_t st);
 hipError_t launch_fill(float *p, int64_t n, float v, hipStream_t st);
 hipError_t launch_build_dp(const Layout &L, const float *v_pad, float dt_over_h, float *Dp, hipStream_t st);
 hipError_t launch_unpack(const Layout &L, const float *f, float *out, hipStream_t st);
@@ -809,8 +809,8 @@ int job_upload_and_check(const Job &J, const Dev &D, std::vector<ShotDev> &shot_
             float vmax, vmin;
             std::memcpy(&vmax, &vr[2 * d], 4);
             std::memcpy(&vmin, &vr[2 * d + 1], 4);
-            if (vr[2 * d] >= 0x7f800000u || !(vmin > 0.f))
-                return fail(RTM_ENUMERIC, "shot %d: velocity must be finite and > 0 (max bits 0x%08x, min %g)",
+            if (vr[2 * d] >= 0x7f800000u || !(vmin >= 0.f) || !(vmax > 0.f))
+                return fail(RTM_ENUMERIC, "shot %d: velocity must be finite, >= 0 and not all 0 (max bits 0x%08x, min %g)",
                             J.slot_shot[d], vr[2 * d], (double)vmin);
             const double limit = std::sqrt(315.0 / (512.0 * S.g.ndim));
             const double courant = (double)vmax * J.dt / S.g.h;
@@ -1065,6 +1065,59 @@ size_t single_bytes(const GridInfo &g, int op, int nrec, int nt)
     return make_ws_layout(J, bound_counts(g, op, nrec)).bytes;
 }
 
+// Band options from the ABI struct: flags checked, taper table built on the
+// host (Eqs. (4)-(5) in double, rounded once to FP32).
+int band_opts(const GridInfo &g, const rtm_rbc_opts_t *o, BandOpts *b)
+{
+    std::memset(b, 0, sizeof *b);
+    if (!o) return RTM_OK;
+    if (o->flags & ~(RTM_RBC_TAPER | RTM_RBC_FREE_SURFACE)) return fail(RTM_EINVAL, "unknown band flags 0x%x", o->flags);
+    b->flags = (o->flags & RTM_RBC_TAPER ? kBandTaper : 0u) | (o->flags & RTM_RBC_FREE_SURFACE ? kBandFreeSurface : 0u);
+    if (o->flags & RTM_RBC_TAPER) {
+        const double a = o->taper_alpha;
+        if (!(a >= 0.0 && a <= 1.0)) return fail(RTM_EINVAL, "taper_alpha must be in [0, 1] (got %g)", a);
+        if (g.nb > kMaxTaper) return fail(RTM_EINVAL, "taper needs nb <= %d (got %d)", kMaxTaper, g.nb);
+        for (int i = 1; i <= g.nb; ++i) {
+            if (g.nb == 1) {
+                b->c[0] = 1.0f;
+                break;
+            }
+            const double x = (double)i, n1 = (double)(g.nb - 1);
+            const double lin = ((double)g.nb - x) / n1;                       // Eq. (4)
+            const double gau = std::exp(-120.0 * (x - 1.0) * (x - 1.0) / (n1 * n1));  // Eq. (5)
+            b->c[i - 1] = (float)(a * lin + (1.0 - a) * gau);
+        }
+    }
+    return RTM_OK;
+}
+
+int pad_common(const rtm_grid_t *grid, const float *v_int, const rtm_rbc_opts_t *opts, const float *g_pad,
+               float *out, void *ws, size_t ws_bytes, void *stream, bool adjoint)
+{
+    t_err.clear();
+    GridInfo g;
+    int rc = grid_info(grid, &g);
+    if (rc) return rc;
+    if (!v_int || !out || (adjoint && !g_pad)) return fail(RTM_EINVAL, "NULL array argument");
+    if (!opts) return fail(RTM_EINVAL, "opts is NULL");
+    BandOpts b;
+    if ((rc = band_opts(g, opts, &b))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned *cap_bits = nullptr;
+    if (!(opts->v_cap > 0.f)) {
+        if (!ws || ws_bytes < 256 || ((uintptr_t)ws & 255))
+            return fail(RTM_EWORKSPACE, "v_cap <= 0 needs an aligned workspace of 256 bytes");
+        RTM_HIP(launch_vmax(v_int, g.nx * g.ny * g.nz, (unsigned *)ws, st));
+        cap_bits = (const unsigned *)ws;
+    }
+    if (adjoint)
+        RTM_HIP(launch_pad_adjoint(g.ndim, g.nb, g.nx, g.ny, g.nz, v_int, opts->seed, opts->v_cap, cap_bits, b, g_pad,
+                                   out, st));
+    else
+        RTM_HIP(launch_rbc_pad(g.ndim, g.nb, g.nx, g.ny, g.nz, v_int, opts->seed, opts->v_cap, cap_bits, b, out, st));
+    return RTM_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -1226,45 +1279,30 @@ int rtm_workspace_bytes(const rtm_grid_t *grid, int op, int32_t nrec, int32_t nt
     return RTM_OK;
 }
 
+int rtm_rbc_pad_ex(const rtm_grid_t *grid, const float *v_int, const rtm_rbc_opts_t *opts, float *v_pad, void *ws,
+                   size_t ws_bytes, void *stream)
+{
+    return pad_common(grid, v_int, opts, nullptr, v_pad, ws, ws_bytes, stream, false);
+}
+
+int rtm_pad_adjoint_ex(const rtm_grid_t *grid, const float *v_int, const rtm_rbc_opts_t *opts, const float *grad_v_pad,
+                       float *grad_v_int, void *ws, size_t ws_bytes, void *stream)
+{
+    return pad_common(grid, v_int, opts, grad_v_pad, grad_v_int, ws, ws_bytes, stream, true);
+}
+
 int rtm_rbc_pad(const rtm_grid_t *grid, const float *v_int, uint64_t seed, float v_cap, float *v_pad, void *ws,
                 size_t ws_bytes, void *stream)
 {
-    t_err.clear();
-    GridInfo g;
-    int rc = grid_info(grid, &g);
-    if (rc) return rc;
-    if (!v_int || !v_pad) return fail(RTM_EINVAL, "v_int and v_pad must be non-NULL");
-    hipStream_t st = (hipStream_t)stream;
-    const unsigned *cap_bits = nullptr;
-    if (!(v_cap > 0.f)) {
-        if (!ws || ws_bytes < 256 || ((uintptr_t)ws & 255))
-            return fail(RTM_EWORKSPACE, "v_cap <= 0 needs an aligned workspace of 256 bytes");
-        RTM_HIP(launch_vmax(v_int, g.nx * g.ny * g.nz, (unsigned *)ws, st));
-        cap_bits = (const unsigned *)ws;
-    }
-    RTM_HIP(launch_rbc_pad(g.ndim, g.nb, g.nx, g.ny, g.nz, v_int, seed, v_cap, cap_bits, v_pad, st));
-    return RTM_OK;
+    const rtm_rbc_opts_t o{seed, v_cap, 0u, 0.0};
+    return pad_common(grid, v_int, &o, nullptr, v_pad, ws, ws_bytes, stream, false);
 }
 
 int rtm_pad_adjoint(const rtm_grid_t *grid, const float *v_int, uint64_t seed, float v_cap, const float *grad_v_pad,
                     float *grad_v_int, void *ws, size_t ws_bytes, void *stream)
 {
-    t_err.clear();
-    GridInfo g;
-    int rc = grid_info(grid, &g);
-    if (rc) return rc;
-    if (!v_int || !grad_v_pad || !grad_v_int) return fail(RTM_EINVAL, "NULL array argument");
-    hipStream_t st = (hipStream_t)stream;
-    const unsigned *cap_bits = nullptr;
-    if (!(v_cap > 0.f)) {
-        if (!ws || ws_bytes < 256 || ((uintptr_t)ws & 255))
-            return fail(RTM_EWORKSPACE, "v_cap <= 0 needs an aligned workspace of 256 bytes");
-        RTM_HIP(launch_vmax(v_int, g.nx * g.ny * g.nz, (unsigned *)ws, st));
-        cap_bits = (const unsigned *)ws;
-    }
-    RTM_HIP(launch_pad_adjoint(g.ndim, g.nb, g.nx, g.ny, g.nz, v_int, seed, v_cap, cap_bits, grad_v_pad, grad_v_int,
-                               st));
-    return RTM_OK;
+    const rtm_rbc_opts_t o{seed, v_cap, 0u, 0.0};
+    return pad_common(grid, v_int, &o, grad_v_pad, grad_v_int, ws, ws_bytes, stream, true);
 }
 
 int rtm_model_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt, const float *wavelet,

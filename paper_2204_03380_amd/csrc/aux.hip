@@ -59,6 +59,18 @@ struct PadDims {
 
 __device__ __forceinline__ int64_t clampi(int64_t v, int64_t lo, int64_t hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Distance of a padded coordinate from the interior [0, n) along one axis.
+__device__ __forceinline__ int64_t band_depth(int64_t a, int64_t n) { return a < 0 ? -a : (a >= n ? a - n + 1 : 0); }
+
+// Depth of a band cell: the largest per-axis distance from the interior.
+__device__ __forceinline__ int64_t cell_depth(const PadDims &d, int64_t ix, int64_t iy, int64_t iz)
+{
+    int64_t m = band_depth(ix, d.nx);
+    m = max(m, band_depth(iz, d.nz));
+    if (d.ndim == 3) m = max(m, band_depth(iy, d.ny));
+    return m;
+}
+
 // Block-wide max / min of unsigned values (kBlock threads), then one
 // atomic per block.
 template <bool MAX>
@@ -102,8 +114,10 @@ __global__ void set_u32_kernel(unsigned *__restrict__ p, int n, unsigned v)
     if (i < n) p[i] = v;
 }
 
+// Band cell value: min(f_j v_edge, cap); with the taper min(c_i (f_j v_edge),
+// cap) at depth i; 0 above the interior with the free surface.
 __global__ void rbc_pad_kernel(PadDims d, const float *__restrict__ v_int, uint64_t seed, float v_cap,
-                               const unsigned *__restrict__ cap_bits, float *__restrict__ v_pad)
+                               const unsigned *__restrict__ cap_bits, BandOpts o, float *__restrict__ v_pad)
 {
     const float cap = cap_bits ? __uint_as_float(*cap_bits) : v_cap;
     const int64_t n = d.NX * d.NY * d.NZ;
@@ -117,20 +131,23 @@ __global__ void rbc_pad_kernel(PadDims d, const float *__restrict__ v_int, uint6
         const float ve = v_int[e];
         if (inside) {
             v_pad[j] = ve;
+        } else if ((o.flags & kBandFreeSurface) && iz < 0) {
+            v_pad[j] = 0.f;
         } else {
             const float f = rbc_factor(seed, (uint64_t)j);
-            const float v = __fmul_rn(f, ve);
+            float v = __fmul_rn(f, ve);
+            if (o.flags & kBandTaper) v = __fmul_rn(o.c[cell_depth(d, ix, iy, iz) - 1], v);
             v_pad[j] = fminf(v, cap);
         }
     }
 }
 
 // Gather form of the padding adjoint: each interior cell collects its own
-// gradient and f_j times the gradient of every uncapped band cell j whose
-// clamped coordinates are this cell.
+// gradient and (c_i) f_j times the gradient of every uncapped band cell j
+// whose clamped coordinates are this cell (free-surface cells are constant).
 __global__ void pad_adjoint_kernel(PadDims d, const float *__restrict__ v_int, uint64_t seed, float v_cap,
-                                   const unsigned *__restrict__ cap_bits, const float *__restrict__ g_pad,
-                                   float *__restrict__ g_int)
+                                   const unsigned *__restrict__ cap_bits, BandOpts o,
+                                   const float *__restrict__ g_pad, float *__restrict__ g_int)
 {
     const float cap = cap_bits ? __uint_as_float(*cap_bits) : v_cap;
     const int64_t n = d.nx * d.ny * d.nz;
@@ -155,9 +172,15 @@ __global__ void pad_adjoint_kernel(PadDims d, const float *__restrict__ v_int, u
                     const int64_t j = (z * d.NY + y) * d.NX + x;
                     if (z == cz && y == cy && x == cx) {
                         acc += g_pad[j];
-                    } else {
-                        const float f = rbc_factor(seed, (uint64_t)j);
-                        if (__fmul_rn(f, ve) < cap) acc = fmaf(f, g_pad[j], acc);
+                    } else if (!((o.flags & kBandFreeSurface) && z < d.nb)) {
+                        float f = rbc_factor(seed, (uint64_t)j);
+                        float v = __fmul_rn(f, ve);
+                        if (o.flags & kBandTaper) {
+                            const float c = o.c[cell_depth(d, x - d.nb, (d.ndim == 3) ? y - d.nb : 0, z - d.nb) - 1];
+                            v = __fmul_rn(c, v);
+                            f = __fmul_rn(c, f);
+                        }
+                        if (v < cap) acc = fmaf(f, g_pad[j], acc);
                     }
                 }
         g_int[i] = acc;
@@ -308,7 +331,7 @@ __global__ void grad_kernel(const ShotDev *__restrict__ shots, int shot, const f
         const int64_t x = j % L.NX, y = (j / L.NX) % L.NY, z = j / ((int64_t)L.NX * L.NY);
         const float G = S.acc0[L.org + z * L.plane + y * L.pitch + x];
         const float v = v_pad[j];
-        grad[j] = two_over_dt2 * G / (v * v * v);
+        grad[j] = v > 0.f ? two_over_dt2 * G / (v * v * v) : 0.f;  // dJ/dv = 2 v dt^2 dJ/dD
     }
 }
 
@@ -414,21 +437,21 @@ hipError_t launch_vmax(const float *v, int64_t n, unsigned *out, hipStream_t st)
 }
 
 hipError_t launch_rbc_pad(int ndim, int nb, int64_t nx, int64_t ny, int64_t nz, const float *v_int, uint64_t seed,
-                          float v_cap, const unsigned *cap_bits, float *v_pad, hipStream_t st)
+                          float v_cap, const unsigned *cap_bits, const BandOpts &o, float *v_pad, hipStream_t st)
 {
     PadDims d = pad_dims(ndim, nb, nx, ny, nz);
     hipLaunchKernelGGL(rbc_pad_kernel, dim3(grid_for(d.NX * d.NY * d.NZ)), dim3(kBlock), 0, st, d, v_int, seed,
-                       v_cap, cap_bits, v_pad);
+                       v_cap, cap_bits, o, v_pad);
     return hipGetLastError();
 }
 
 hipError_t launch_pad_adjoint(int ndim, int nb, int64_t nx, int64_t ny, int64_t nz, const float *v_int,
-                              uint64_t seed, float v_cap, const unsigned *cap_bits, const float *g_pad,
-                              float *g_int, hipStream_t st)
+                              uint64_t seed, float v_cap, const unsigned *cap_bits, const BandOpts &o,
+                              const float *g_pad, float *g_int, hipStream_t st)
 {
     PadDims d = pad_dims(ndim, nb, nx, ny, nz);
     hipLaunchKernelGGL(pad_adjoint_kernel, dim3(grid_for(d.nx * d.ny * d.nz)), dim3(kBlock), 0, st, d, v_int, seed,
-                       v_cap, cap_bits, g_pad, g_int);
+                       v_cap, cap_bits, o, g_pad, g_int);
     return hipGetLastError();
 }
 

@@ -127,6 +127,16 @@ struct SampleTask {
     int r0;
 };
 
+// Band options of the random-boundary padding (Eqs. (4)-(5) taper, free
+// surface): passed to the padding kernels by value.
+constexpr int kMaxTaper = 256;
+constexpr unsigned kBandTaper = 0x1u;
+constexpr unsigned kBandFreeSurface = 0x2u;
+struct BandOpts {
+    unsigned flags;
+    float c[kMaxTaper];  // taper coefficient of band depth i at c[i - 1]
+};
+
 // Map a workgroup index onto a tile index so that each XCD processes a
 // contiguous range of tiles (neighbouring tiles share halo rows in that
 // XCD's L2).  `nslots` is a multiple of kNumXcd; slot values >= ntiles are

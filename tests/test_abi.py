@@ -135,3 +135,17 @@ def test_storage_shot_validation():
     assert call(3, 0, need, snaps=None) == _lib.RTM_EINVAL
     assert call(0, 0, need) == _lib.RTM_EINVAL
     assert call(3, 3, need) == _lib.RTM_EINVAL
+
+
+def test_band_options_validation():
+    """rtm_rbc_pad_ex / rtm_pad_adjoint_ex reject bad options on the host
+    (fake device addresses, never dereferenced)."""
+    lib = _lib.load()
+    for nb, flags, alpha in ((4, 0x1, 1.5), (4, 0x1, -0.1), (4, 0x4, 0.0), (300, 0x1, 0.5)):
+        g = rtm.Grid(2, 20, 1, 12, 10.0, nb).c()
+        o = _lib.RtmRbcOpts(1, 3000.0, flags, alpha)
+        assert lib.rtm_rbc_pad_ex(ctypes.byref(g), 0x1000, ctypes.byref(o), 0x2000, None, 0, None) == _lib.RTM_EINVAL
+        assert lib.rtm_pad_adjoint_ex(ctypes.byref(g), 0x1000, ctypes.byref(o), 0x3000, 0x2000, None, 0,
+                                      None) == _lib.RTM_EINVAL
+    g = rtm.Grid(2, 20, 1, 12, 10.0, 4).c()
+    assert lib.rtm_rbc_pad_ex(ctypes.byref(g), 0x1000, None, 0x2000, None, 0, None) == _lib.RTM_EINVAL
