@@ -20,7 +20,7 @@ import torch
 from . import (RTM_F_SKIP_CHECK, RTM_OP_MODEL, RTM_OP_RTM, RTM_TUNE_EXACT, BatchPlan, BatchShot, Grid,
                rtm_set_tuning, rtm_set_tuning2d, rtm_set_tuning3d, rtm_timing_enable, rtm_timing_read)
 
-DEFAULT_SHAPES = tuple((v, x, z) for v in (1, 2, 4) for x in (1, 4) for z in (9, 18, 36))
+DEFAULT_SHAPES = tuple((v, x, z) for v in (1, 2, 4) for x in (1, 4) for z in (9, 18, 36, 72, 108))
 DEFAULT_SHAPES_3D = tuple((v, y, z) for v in (1, 2, 4) for y in (4, 8) for z in (18, 36))
 
 

@@ -118,9 +118,11 @@ struct Tune {
 };
 
 // 2-D shapes: ((steps - 1) << 28) | (tx << 24) | (vec << 16) | zseg;
-// defaults from sweeps over 16-64 shots of the 2301 x 751 folded grid.
-std::atomic<int> g_tune2d_fwd{(1 << 28) | (1 << 24) | (4 << 16) | 36};
-std::atomic<int> g_tune2d_rev{(1 << 28) | (1 << 24) | (2 << 16) | 36};
+// defaults from sweeps over 48 shots of the 2301 x 751 folded grid with two
+// steps per launch (forward 428 us, reverse pair 1165 us per launch; zseg 36
+// and vec 2 were 449 and 1247 us).
+std::atomic<int> g_tune2d_fwd{(1 << 28) | (1 << 24) | (4 << 16) | 108};
+std::atomic<int> g_tune2d_rev{(1 << 28) | (1 << 24) | (4 << 16) | 108};
 std::atomic<int> g_tune_exact{0};  // 1: never narrow the configured shapes
 
 // 3-D shapes: (vec << 24) | (ty << 16) | zseg; defaults from a sweep on

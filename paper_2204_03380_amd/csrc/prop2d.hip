@@ -556,6 +556,16 @@ __global__ __launch_bounds__(64) void fwd2d_t2_kernel(const ShotDev *__restrict_
 
 // Reverse pair (imaging): steps k and k - 1 of the reconstruction and the
 // receiver field, and both steps' imaging sums.
+//
+// Strip-end halo one row ahead (halo_ahead<VEC>): with four floats per lane
+// the kernel runs at one wavefront per SIMD (256 registers), so nothing
+// hides the latency of the halo load that each row's stencil waits for;
+// fetching it one march step early took the 48-shot reverse pair from 1349
+// to 1167 us.  With two floats per lane (three wavefronts per SIMD) the
+// eight extra registers cost more than the early fetch gains (1223 -> 1264
+// us), so that shape keeps the in-step load.
+template <int VEC>
+constexpr bool halo_ahead() { return VEC == 4; }
 template <int VEC>
 struct Rev2Ctx {
     const gfloat *P0, *P1, *M0, *M1;  // p^k, p^{k+1}, mu^{k+1}, mu^{k+2} (read set)
@@ -576,7 +586,8 @@ struct Rev2Ctx {
 template <int VEC, int S>
 __device__ __forceinline__ void rev2_row(const Rev2Ctx<VEC> &C, float (&q1p)[9][VEC], float (&q1m)[9][VEC],
                                          float (&q2p)[9][VEC], float (&q2m)[9][VEC], float (&qd)[9][VEC],
-                                         float (&qa)[9][VEC], float (&qb)[9][VEC], int s, int &es, int &er)
+                                         float (&qa)[9][VEC], float (&qb)[9][VEC], f4v &hp, f4v &hm, int s,
+                                         int &es, int &er)
 {
     constexpr int a0 = S % 9, a1 = (S + 1) % 9, a2 = (S + 2) % 9, a3 = (S + 3) % 9, a4 = (S + 4) % 9,
                   a5 = (S + 5) % 9, a6 = (S + 6) % 9, a7 = (S + 7) % 9, a8 = (S + 8) % 9;
@@ -602,7 +613,17 @@ __device__ __forceinline__ void rev2_row(const Rev2Ctx<VEC> &C, float (&q1p)[9][
     }
     float hl[4], hr[4], ext[VEC + 8];
     float np[VEC], nm[VEC];
-    load_halo<VEC>(C.P0 + (int64_t)r1 * C.pitch, C.xs, C.NX, C.lane, hl, hr, in1);
+    f4v tm = hm;
+    if constexpr (halo_ahead<VEC>()) {
+        // row r1's strip-end halo was fetched one step ago; fetch row r1 + 1's
+        const f4v tp = hp;
+        const bool in_n1 = r1 + 1 < C.NZr + kRadius;
+        hp = halo_fetch<VEC>(C.P0 + (int64_t)(r1 + 1) * C.pitch, C.xs, C.NX, C.lane, in_n1);
+        hm = halo_fetch<VEC>(C.M0 + (int64_t)(r1 + 1) * C.pitch, C.xs, C.NX, C.lane, in_n1);
+        halo_split(tp, C.lane, hl, hr);
+    } else {
+        load_halo<VEC>(C.P0 + (int64_t)r1 * C.pitch, C.xs, C.NX, C.lane, hl, hr, in1);
+    }
     exchange_row<VEC>(q1p[a4], hl, hr, ext);
 #pragma unroll
     for (int j = 0; j < VEC; ++j) {
@@ -611,7 +632,10 @@ __device__ __forceinline__ void rev2_row(const Rev2Ctx<VEC> &C, float (&q1p)[9][
         lap += d2(c2, q1p[a3][j], q1p[a5][j], q1p[a2][j], q1p[a6][j], q1p[a1][j], q1p[a7][j], q1p[a0][j], q1p[a8][j]);
         np[j] = fmaf(d[j], lap, c2 - p1[j]);
     }
-    load_halo<VEC>(C.M0 + (int64_t)r1 * C.pitch, C.xs, C.NX, C.lane, hl, hr, in1);
+    if constexpr (halo_ahead<VEC>())
+        halo_split(tm, C.lane, hl, hr);
+    else
+        load_halo<VEC>(C.M0 + (int64_t)r1 * C.pitch, C.xs, C.NX, C.lane, hl, hr, in1);
     exchange_row<VEC>(q1m[a4], hl, hr, ext);
 #pragma unroll
     for (int j = 0; j < VEC; ++j) {
@@ -756,7 +780,10 @@ void rev2d_t2_kernel(const ShotDev *__restrict__ shots,
     }
     int es = T.s1beg, er = T.r1beg;
     const int nstep = T.z1 - T.z0 + kZUnroll;
-#define RTM_REV2_ROW(SS, ZZ) rev2_row<VEC, SS>(C, q1p, q1m, q2p, q2m, qd, qa, qb, ZZ, es, er)
+    // strip-end halo of the first march row (z0 - 4 >= -4: stored)
+    f4v hp = halo_fetch<VEC>(C.P0 + (int64_t)(T.z0 - 4) * C.pitch, C.xs, C.NX, lane, halo_ahead<VEC>());
+    f4v hm = halo_fetch<VEC>(C.M0 + (int64_t)(T.z0 - 4) * C.pitch, C.xs, C.NX, lane, halo_ahead<VEC>());
+#define RTM_REV2_ROW(SS, ZZ) rev2_row<VEC, SS>(C, q1p, q1m, q2p, q2m, qd, qa, qb, hp, hm, ZZ, es, er)
     RTM_MARCH2(RTM_REV2_ROW, nstep)
 #undef RTM_REV2_ROW
     // time k - 1 terms into the owned cells of p^{k-2} and mu^{k-1}

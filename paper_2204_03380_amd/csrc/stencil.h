@@ -160,6 +160,26 @@ __device__ __forceinline__ void load_halo(const gfloat *row, int x0, int NX, int
     hr[0] = right ? t.x : 0.f; hr[1] = right ? t.y : 0.f; hr[2] = right ? t.z : 0.f; hr[3] = right ? t.w : 0.f;
 }
 
+// The same halo in two parts, so that the load can be issued rows before
+// its use: halo_fetch loads the 4 cells beyond the strip's left end (lane 0)
+// or right end (lane 63) of a row; halo_split hands them out as hl / hr.
+template <int VEC>
+__device__ __forceinline__ f4v halo_fetch(const gfloat *row, int x0, int NX, int lane, bool enable)
+{
+    const int xr = x0 + 64 * VEC;
+    const bool left = enable && lane == 0, right = enable && lane == 63 && xr < NX + kRadius;
+    f4v t = f4v{0.f, 0.f, 0.f, 0.f};
+    if (left || right) t = *(const gf4v *)(row + (left ? x0 - 4 : xr));
+    return t;
+}
+
+__device__ __forceinline__ void halo_split(f4v t, int lane, float (&hl)[4], float (&hr)[4])
+{
+    const bool left = lane == 0, right = lane == 63;
+    hl[0] = left ? t.x : 0.f; hl[1] = left ? t.y : 0.f; hl[2] = left ? t.z : 0.f; hl[3] = left ? t.w : 0.f;
+    hr[0] = right ? t.x : 0.f; hr[1] = right ? t.y : 0.f; hr[2] = right ? t.z : 0.f; hr[3] = right ? t.w : 0.f;
+}
+
 // Strip-end halo of one row for a wave inside a workgroup of strips: only
 // the workgroup's outer ends (do_left in the first wave, do_right in the
 // last) are loaded from memory; inner ends come from the edge ring.

@@ -204,7 +204,7 @@ def test_two_step_launches_bit_identical(nt):
     rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
     outs = []
     try:
-        for steps, vec, zseg in ((1, 1, 18), (2, 1, 9), (2, 2, 18), (2, 4, 36), (2, 1, 27)):
+        for steps, vec, zseg in ((1, 1, 18), (2, 1, 9), (2, 2, 18), (2, 4, 36), (2, 1, 27), (2, 4, 9), (2, 4, 108)):
             for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
                 rtm.rtm_set_tuning2d(op, vec, 1, zseg)
                 rtm.rtm_set_steps_per_launch(op, steps)
