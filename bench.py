@@ -313,6 +313,27 @@ def boundary_study(K=8, seed0=500):
     return {"model": name, "seeds": K, "rows": rows}
 
 
+def copy_rate(dev, mib=2048, reps=5):
+    """Device-to-device copy rate (read + write bytes / time) of a 2 GiB
+    buffer: what a plain streaming kernel reaches on this GPU, beside the
+    8 TB/s peak."""
+    import torch
+    a = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    gbps = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return round(gbps, 1)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -359,6 +380,7 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    copy_gbps = copy_rate(dev)
     if args.vec and args.zseg:
         rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, args.vec, args.zseg)
         rtm.rtm_set_tuning(rtm.RTM_OP_RTM, args.vec, args.zseg)
@@ -502,6 +524,7 @@ def main():
             "traffic": reverse_traffic(B, rev_shape, steps_r),
             "avg_launch_us": round(rev_us, 3),
             "algorithmic_bytes_per_launch": rev_bytes,
+            "device_copy_GBps": copy_gbps,
             "steps_per_launch": steps_r,
             "per_step": {"us": round(per_step_us, 3),
                          "one_step_algorithmic_bytes": one_step_bytes,

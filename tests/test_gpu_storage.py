@@ -39,6 +39,8 @@ def _case(name):
         return synth.config_small2d(nx=131, nz=37, nb=9, nt=180, seed=9)
     if name == "c1":
         return synth.config_c1(nt=600)
+    if name == "odd2d":
+        return synth.config_small2d(nx=97, nz=53, nb=11, nt=151, seed=13)
     raise KeyError(name)
 
 
@@ -69,7 +71,7 @@ def _check_levels(out, vo, s, w, stride, phase, which):
 
 @pytest.mark.parametrize("name,stride,phase,steps", [
     ("small2d", 1, 0, 2), ("small2d", 10, 0, 1), ("small2d", 10, 0, 2), ("ragged2d", 7, 3, 2),
-    ("ragged2d", 4, 1, 1), ("c1", 10, 0, 2)])
+    ("ragged2d", 4, 1, 1), ("c1", 10, 0, 2), ("odd2d", 3, 2, 2), ("odd2d", 5, 0, 1)])
 def test_storage_shot_parity(name, stride, phase, steps):
     s = _case(name)
     rtm.rtm_set_steps_per_launch(rtm.RTM_OP_MODEL, steps)
