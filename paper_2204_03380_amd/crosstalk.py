@@ -235,6 +235,9 @@ def main(argv=None):
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--nt", type=int, default=1100)
+    ap.add_argument("--infer-shape", default=None,
+                    help="after training, migrate one model of this interior shape NZ,NY,NX (multiples of 8) with "
+                         "the same acquisition and realisations, and report the filter's gain on it and its time")
     ap.add_argument("--out", default=None, help="write a JSON summary here")
     a = ap.parse_args(argv)
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -259,6 +262,25 @@ def main(argv=None):
            "config": {"n": a.n, "geometries": a.geometries, "held_out": a.held_out, "realisations": a.realisations,
                       "epochs": a.epochs, "batch": a.batch, "lr": a.lr, "nt": a.nt, "pairs_train": len(train_set),
                       "pairs_held_out": len(test_set)}}
+    if a.infer_shape:
+        nz, ny, nx = (int(v) for v in a.infer_shape.split(","))
+        big = synth.layered_salt_3d(nx, ny, nz, 7777)
+        t0 = time.time()
+        bset = build_dataset([big], 10.0, 30, 1e-3, synth.ricker(15.0, 1e-3, a.nt), a.realisations, seed0=900,
+                             log=log)
+        torch.cuda.synchronize()
+        t_big = time.time() - t0
+        x = bset.inputs[0][None]
+        net(x)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        net(x)
+        e1.record()
+        e1.synchronize()
+        res["infer"] = {"shape": [nz, ny, nx], "data_s": t_big, "forward_ms": e0.elapsed_time(e1),
+                        **evaluate(net, bset)}
+        log(f"inference on {nz}x{ny}x{nx}: {res['infer']}")
     print(json.dumps(res), flush=True)
     if a.out:
         with open(a.out, "w") as f:
