@@ -62,7 +62,8 @@ extern "C" {
 #define RTM_ERANGE (-3)     /* a source or receiver lies outside the interior   */
 #define RTM_EWORKSPACE (-4) /* workspace null or smaller than required          */
 #define RTM_EHIP (-5)       /* a HIP runtime call or kernel launch failed       */
-#define RTM_ENUMERIC (-6)   /* velocity non-finite, negative or all zero        */
+#define RTM_ENUMERIC (-6)   /* velocity non-finite, negative or all zero; or a  */
+                            /* non-finite output under RTM_F_CHECK_FINITE       */
 
 /* Operations, for rtm_workspace_bytes. */
 #define RTM_OP_RBC_PAD 0 /* rtm_rbc_pad and rtm_pad_adjoint with v_cap <= 0 */
@@ -83,6 +84,10 @@ extern "C" {
                                   hipGraph on the first run and replay it on
                                   later runs with the same workspace and
                                   stream (stream must not be NULL) */
+#define RTM_F_CHECK_FINITE 0x10u /* single-shot calls: after the run, check
+                                  the outputs (traces, image, or velocity
+                                  gradient) for NaN / Inf; synchronises the
+                                  stream and returns RTM_ENUMERIC if found */
 
 /* Grid descriptor; read during the call only. */
 typedef struct rtm_grid {
@@ -241,7 +246,7 @@ int rtm_pad_adjoint(const rtm_grid_t *grid, const float *v_int, uint64_t seed, f
  *   traces   device [nrec][nt + 1] output.
  *   p_last, p_prev  device [NZ][NY][NX] or NULL: the final states p^nt and
  *            p^(nt-1), the two panels reconstruction starts from.
- *   flags    RTM_F_SKIP_CHECK or 0. */
+ *   flags    RTM_F_SKIP_CHECK | RTM_F_CHECK_FINITE or 0. */
 int rtm_model_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt,
                    const float *wavelet, const float *src, int32_t nrec, const float *rec,
                    float *traces, float *p_last, float *p_prev, uint32_t flags, void *ws,
@@ -267,7 +272,7 @@ int rtm_model_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_
  *            FP32 wavefields carry large relative errors (the image error
  *            grows roughly like 1e-9 / eps_rel).
  *   probe    NULL or a wavefield probe (see rtm_probe_t).
- *   flags    RTM_F_SKIP_CHECK | RTM_F_NO_REINJECT or 0.
+ *   flags    RTM_F_SKIP_CHECK | RTM_F_NO_REINJECT | RTM_F_CHECK_FINITE or 0.
  * The caller stacks images over shots (Algorithm 3, stacking step). */
 int rtm_rtm_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt,
                  const float *wavelet, const float *src, int32_t nrec, const float *rec,
@@ -307,7 +312,7 @@ int rtm_storage_count(int32_t nt, int32_t stride, int32_t phase, int64_t *count)
  *              i * nz * ny * nx, dense interior [nz][ny][nx].  Valid after
  *              the call (the stored source wavefield).
  *   snapshot_bytes  size of `snapshots`; RTM_EINVAL if smaller than needed.
- *   flags      RTM_F_SKIP_CHECK or 0.
+ *   flags      RTM_F_SKIP_CHECK | RTM_F_CHECK_FINITE or 0.
  *   ws         rtm_workspace_bytes(RTM_OP_STORAGE) bytes. */
 int rtm_storage_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt,
                      const float *wavelet, const float *src, int32_t nrec, const float *rec,

@@ -15,14 +15,14 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (RTM_F_ACCUMULATE, RTM_F_GRAPH, RTM_F_NO_REINJECT, RTM_F_SKIP_CHECK, RTM_OP_MODEL,
+from ._lib import (RTM_F_ACCUMULATE, RTM_F_CHECK_FINITE, RTM_F_GRAPH, RTM_F_NO_REINJECT, RTM_F_SKIP_CHECK, RTM_OP_MODEL,
                    RTM_OP_RBC_PAD, RTM_OP_RTM, RTM_OP_STORAGE, RTM_OP_VJP, RTM_TUNE_EXACT, RtmError)
 
 __all__ = [
     "Grid", "RtmError", "rtm_workspace_bytes", "rtm_set_tuning", "rtm_get_tuning", "rtm_set_tuning3d", "rtm_get_tuning3d", "rtm_timing_enable", "rtm_timing_read", "rtm_rbc_pad", "rtm_pad_adjoint",
     "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "RTM_F_SKIP_CHECK", "RTM_F_NO_REINJECT",
     "rtm_nyquist_stride", "rtm_storage_count", "rtm_storage_shot", "RTM_OP_STORAGE",
-    "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD", "RTM_F_ACCUMULATE", "RTM_F_GRAPH", "RTM_TUNE_EXACT",
+    "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD", "RTM_F_ACCUMULATE", "RTM_F_GRAPH", "RTM_F_CHECK_FINITE", "RTM_TUNE_EXACT",
     "BatchShot", "BatchPlan", "rtm_window_extract", "rtm_window_accumulate", "rtm_l2_misfit",
 ]
 

@@ -40,6 +40,7 @@ EXPORTS = (
 
 RTM_F_ACCUMULATE = 0x4
 RTM_F_GRAPH = 0x8
+RTM_F_CHECK_FINITE = 0x10
 
 
 class RtmGrid(ctypes.Structure):

@@ -61,6 +61,7 @@ hipError_t launch_image(const ShotDev *shots, int shot, int64_t ninterior, unsig
 hipError_t launch_grad(const ShotDev *shots, int shot, int64_t npad, const float *v_pad, float dt, float *grad,
                        hipStream_t st);
 hipError_t launch_snap_store(const ShotDev *shots, int shot, int lev, int64_t ninterior, float *out, hipStream_t st);
+hipError_t launch_nonfinite(const float *x, int64_t n, unsigned *flag, hipStream_t st);
 hipError_t launch_wadj(const float *parts, int nt, float scale, float *out, hipStream_t st);
 size_t misfit_ws_bytes();
 hipError_t launch_misfit(const float *d, const float *dobs, float *r, int64_t n, void *ws, double *J, hipStream_t st);
@@ -1011,7 +1012,24 @@ int job_run(Job &J, void *ws, size_t ws_bytes, hipStream_t st, const rtm_probe_t
     Dev D{(char *)ws};
     std::vector<ShotDev> shot_devs;
     if ((rc = job_upload_and_check(J, D, shot_devs, st))) return rc;
-    return job_launch(J, D, st, probe, true);
+    if ((rc = job_launch(J, D, st, probe, true))) return rc;
+    if (!(J.flags & RTM_F_CHECK_FINITE)) return RTM_OK;
+    // Outputs checked for NaN / Inf: an unstable run (or a non-finite input
+    // that the velocity check does not cover, such as the wavelet or the
+    // traces) is reported instead of returned silently.
+    unsigned *flag = D.at<unsigned>(J.ws.scal);
+    RTM_HIP(launch_fill((float *)flag, 1, 0.f, st));  // zero bits
+    for (const ShotIn &S : J.shots) {
+        const int64_t ni = S.g.nx * S.g.ny * S.g.nz, np = (int64_t)S.g.NX * S.g.NY * S.g.NZ;
+        if (J.op == RTM_OP_MODEL) RTM_HIP(launch_nonfinite(S.traces_out, (int64_t)S.nrec * (J.nt + 1), flag, st));
+        if (has_den(J.op)) RTM_HIP(launch_nonfinite(S.image, ni, flag, st));
+        if (J.op == RTM_OP_VJP) RTM_HIP(launch_nonfinite(S.grad_v_pad, np, flag, st));
+    }
+    unsigned h = 0;
+    RTM_HIP(hipMemcpyAsync(&h, flag, sizeof h, hipMemcpyDeviceToHost, st));
+    RTM_HIP(hipStreamSynchronize(st));
+    if (h) return fail(RTM_ENUMERIC, "non-finite values in the output (unstable run or non-finite wavelet / traces)");
+    return RTM_OK;
 }
 
 int check_common(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt, const float *wavelet,
@@ -1393,7 +1411,8 @@ int rtm_storage_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int3
     if ((double)count * (double)ncell * 4.0 > (double)snapshot_bytes)
         return fail(RTM_EINVAL, "snapshots: %lld levels of %lld cells need %.0f bytes, %zu given", (long long)count,
                     (long long)ncell, (double)count * (double)ncell * 4.0, snapshot_bytes);
-    if (flags & ~RTM_F_SKIP_CHECK) return fail(RTM_EINVAL, "unsupported flags 0x%x", (unsigned)flags);
+    if (flags & ~(RTM_F_SKIP_CHECK | RTM_F_CHECK_FINITE))
+        return fail(RTM_EINVAL, "unsupported flags 0x%x", (unsigned)flags);
     Job J;
     if ((rc = single_job(J, RTM_OP_STORAGE, g, v_pad, dt, nt, wavelet, src, nrec, rec, flags))) return rc;
     J.eps = eps_rel;

@@ -319,6 +319,15 @@ __global__ void snap_store_kernel(const ShotDev *__restrict__ shots, int shot, i
     }
 }
 
+// flag |= 1 if any of x[0 .. n) is NaN or infinite (one atomic per block).
+__global__ __launch_bounds__(kBlock) void nonfinite_kernel(const float *__restrict__ x, int64_t n,
+                                                           unsigned *__restrict__ flag)
+{
+    unsigned m = 0u;
+    for (int64_t i = gid(); i < n; i += gstride()) m = max(m, __float_as_uint(x[i]) & 0x7fffffffu);
+    block_reduce_atomic<true>(m >= 0x7f800000u ? 1u : 0u, flag);
+}
+
 // grad_v = 2 G / (v^3 dt^2) on the dense padded grid.
 __global__ void grad_kernel(const ShotDev *__restrict__ shots, int shot, const float *__restrict__ v_pad, float dt,
                             float *__restrict__ grad)
@@ -511,6 +520,13 @@ hipError_t launch_image(const ShotDev *shots, int shot, int64_t ninterior, unsig
 hipError_t launch_snap_store(const ShotDev *shots, int shot, int lev, int64_t ninterior, float *out, hipStream_t st)
 {
     hipLaunchKernelGGL(snap_store_kernel, dim3(grid_for(ninterior)), dim3(kBlock), 0, st, shots, shot, lev, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_nonfinite(const float *x, int64_t n, unsigned *flag, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(nonfinite_kernel, dim3(grid_reduce(n)), dim3(kBlock), 0, st, x, n, flag);
     return hipGetLastError();
 }
 

@@ -279,3 +279,26 @@ def test_folded_grid_full_size_reduced_nt():
     e = rel_l2(_n(out["image"]), ref["image"])
     print(f"folded grid: traces {rel_l2(tr, tr_o):.2e} image {e:.2e}")
     assert e < TOL
+
+
+def test_check_finite_flag():
+    """RTM_F_CHECK_FINITE reports non-finite outputs (here forced by a NaN
+    wavelet sample and an infinite trace sample) as RTM_ENUMERIC; the same
+    inputs without the flag return normally, and finite runs pass the check."""
+    s = synth.config_small2d(nt=80)
+    g, vg, vo = _setup(s)
+    w = s.wavelet.copy()
+    tr = rtm.rtm_model_shot(g, vg, s.dt, _t(w), s.src[0], s.rec, flags=rtm.RTM_F_CHECK_FINITE)
+    out = rtm.rtm_rtm_shot(g, vg, s.dt, _t(w), s.src[0], s.rec, tr, flags=rtm.RTM_F_CHECK_FINITE)
+    assert np.isfinite(_n(out["image"])).all()
+    wbad = w.copy()
+    wbad[10] = np.nan
+    rtm.rtm_model_shot(g, vg, s.dt, _t(wbad), s.src[0], s.rec)   # no check: returns
+    with pytest.raises(rtm.RtmError):
+        rtm.rtm_model_shot(g, vg, s.dt, _t(wbad), s.src[0], s.rec, flags=rtm.RTM_F_CHECK_FINITE)
+    tbad = _n(tr).copy()
+    tbad[3, 40] = np.inf
+    with pytest.raises(rtm.RtmError):
+        rtm.rtm_rtm_shot(g, vg, s.dt, _t(w), s.src[0], s.rec, _t(tbad), flags=rtm.RTM_F_CHECK_FINITE)
+    with pytest.raises(rtm.RtmError):
+        rtm.rtm_model_shot_vjp(g, vg, s.dt, _t(w), s.src[0], s.rec, _t(tbad), flags=rtm.RTM_F_CHECK_FINITE)
