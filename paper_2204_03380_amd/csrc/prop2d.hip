@@ -45,8 +45,32 @@ struct FwdCtx {
 // meets at a barrier every third row, which orders each ring write (row
 // z + 4, end of this step) before its read four steps later and each read
 // before the slot is rewritten five steps later.
+// The one-step forward row (forward and receiver-only kernels) with one
+// strip per workgroup fetches each row's strip-end halo one march step early
+// (hc: the halo of row z, fetched at row z - 1), as the two-step kernels do:
+// 326 -> 339 us without it for 48 shots at vec 1.  The one-step reverse
+// kernel keeps the in-step load (no consistent gain: 854 -> 874 us at vec 1,
+// 868 -> 849 at vec 4).
+template <int VEC, int TX>
+constexpr bool ahead1() { return TX == 1 && VEC != 2; }
+
+// Strip-end halo of row z into hl / hr: the early-fetched one (then fetch
+// row z + 1's, always a stored row as z < NZr) or a load now.
+template <int VEC, int TX, bool AHEAD>
+__device__ __forceinline__ void row_halo(const gfloat *f, int64_t pitch, int z, int x0, int NX, int lane, int w,
+                                         f4v &hc, float (&hl)[4], float (&hr)[4])
+{
+    if constexpr (AHEAD) {
+        const f4v t = hc;
+        hc = halo_fetch<VEC>(f + (int64_t)(z + 1) * pitch, x0, NX, lane, true);
+        halo_split(t, lane, hl, hr);
+    } else {
+        load_halo_outer<VEC>(f + (int64_t)z * pitch, x0, NX, lane, w == 0, w == TX - 1, hl, hr);
+    }
+}
+
 template <int VEC, int TX, int S>
-__device__ __forceinline__ void fwd_row(const FwdCtx<VEC> &C, float (&q)[9][VEC], int z, EdgeRing<TX> &R)
+__device__ __forceinline__ void fwd_row(const FwdCtx<VEC> &C, float (&q)[9][VEC], int z, EdgeRing<TX> &R, f4v &hc)
 {
     constexpr int r0 = (S + 0) % 9, r1 = (S + 1) % 9, r2 = (S + 2) % 9, r3 = (S + 3) % 9, r4 = (S + 4) % 9,
                   r5 = (S + 5) % 9, r6 = (S + 6) % 9, r7 = (S + 7) % 9, r8 = (S + 8) % 9;
@@ -61,7 +85,7 @@ __device__ __forceinline__ void fwd_row(const FwdCtx<VEC> &C, float (&q)[9][VEC]
         ldv<VEC>(C.Dp + o, d);
     }
     float hl[4], hr[4], ext[VEC + 8];
-    load_halo_outer<VEC>(C.pc + (int64_t)z * C.pitch, C.x0, C.NX, C.lane, C.w == 0, C.w == TX - 1, hl, hr);
+    row_halo<VEC, TX, ahead1<VEC, TX>()>(C.pc, C.pitch, z, C.x0, C.NX, C.lane, C.w, hc, hl, hr);
     ring_get<TX>(R, S, C.w, C.lane, hl, hr);
     exchange_row<VEC>(q[r4], hl, hr, ext);
     float out[VEC];
@@ -95,7 +119,7 @@ struct RevCtx {
 
 template <int VEC, bool GRAD, int TX, int S>
 __device__ __forceinline__ void rev_row(const RevCtx<VEC> &C, float (&qp)[9][VEC], float (&qm)[9][VEC], int z,
-                                        EdgeRing<TX> &RP, EdgeRing<TX> &RM)
+                                        EdgeRing<TX> &RP, EdgeRing<TX> &RM, f4v &hp, f4v &hm)
 {
     constexpr int r0 = (S + 0) % 9, r1 = (S + 1) % 9, r2 = (S + 2) % 9, r3 = (S + 3) % 9, r4 = (S + 4) % 9,
                   r5 = (S + 5) % 9, r6 = (S + 6) % 9, r7 = (S + 7) % 9, r8 = (S + 8) % 9;
@@ -113,7 +137,7 @@ __device__ __forceinline__ void rev_row(const RevCtx<VEC> &C, float (&qp)[9][VEC
     }
     float hl[4], hr[4], ext[VEC + 8];
     float np[VEC], nm[VEC], inc[VEC];
-    load_halo_outer<VEC>(C.P0 + (int64_t)z * C.pitch, C.x0, C.NX, C.lane, C.w == 0, C.w == TX - 1, hl, hr);
+    row_halo<VEC, TX, false>(C.P0, C.pitch, z, C.x0, C.NX, C.lane, C.w, hp, hl, hr);
     ring_get<TX>(RP, S, C.w, C.lane, hl, hr);
     exchange_row<VEC>(qp[r4], hl, hr, ext);
 #pragma unroll
@@ -125,7 +149,7 @@ __device__ __forceinline__ void rev_row(const RevCtx<VEC> &C, float (&qp)[9][VEC
         np[j] = fmaf(d[j], lap, c2 - p1[j]);  // same rounding as the two-step kernel
     }
     if (C.own) stv<VEC>(C.P1 + o, np);
-    load_halo_outer<VEC>(C.M0 + (int64_t)z * C.pitch, C.x0, C.NX, C.lane, C.w == 0, C.w == TX - 1, hl, hr);
+    row_halo<VEC, TX, false>(C.M0, C.pitch, z, C.x0, C.NX, C.lane, C.w, hm, hl, hr);
     ring_get<TX>(RM, S, C.w, C.lane, hl, hr);
     exchange_row<VEC>(qm[r4], hl, hr, ext);
 #pragma unroll
@@ -223,7 +247,8 @@ __global__ __launch_bounds__(64 * TX) void fwd2d_kernel(const ShotDev *__restric
         if constexpr (TX > 1)
             if (i >= 4) ring_put<VEC, TX>(ring, i - 4, w, lane, q[i]);
     }
-#define RTM_FWD_ROW(SS, ZZ) fwd_row<VEC, TX, SS>(C, q, ZZ, ring)
+    f4v hc = halo_fetch<VEC>(C.pc + (int64_t)T.z0 * C.pitch, C.x0, C.NX, lane, ahead1<VEC, TX>());
+#define RTM_FWD_ROW(SS, ZZ) fwd_row<VEC, TX, SS>(C, q, ZZ, ring, hc)
     RTM_MARCH(RTM_FWD_ROW)
 #undef RTM_FWD_ROW
     // Source injection: p^{n+1} += D' s^n at the source nodes of this tile.
@@ -300,7 +325,8 @@ void rev2d_kernel(const ShotDev *__restrict__ shots, const Tile2D *__restrict__ 
                 ring_put<VEC, TX>(ring_m, i - 4, w, lane, qm[i]);
             }
     }
-#define RTM_REV_ROW(SS, ZZ) rev_row<VEC, GRAD, TX, SS>(C, qp, qm, ZZ, ring_p, ring_m)
+    f4v hp = f4v{0.f, 0.f, 0.f, 0.f}, hm = hp;  // (the reverse rows load their halo in-step)
+#define RTM_REV_ROW(SS, ZZ) rev_row<VEC, GRAD, TX, SS>(C, qp, qm, ZZ, ring_p, ring_m, hp, hm)
     RTM_MARCH(RTM_REV_ROW)
 #undef RTM_REV_ROW
     // Source term at step k: reconstruction (re-injection), gradient, wavelet adjoint.
@@ -369,8 +395,9 @@ __global__ __launch_bounds__(64 * TX) void recv2d_kernel(const ShotDev *__restri
         if constexpr (TX > 1)
             if (i >= 4) ring_put<VEC, TX>(ring, i - 4, w, lane, q[i]);
     }
+    f4v hc = halo_fetch<VEC>(C.pc + (int64_t)T.z0 * C.pitch, C.x0, C.NX, lane, ahead1<VEC, TX>());
 #define RTM_RECV_ROW(SS, ZZ)                                                                        \
-    fwd_row<VEC, TX, SS>(C, q, ZZ, ring);                                                          \
+    fwd_row<VEC, TX, SS>(C, q, ZZ, ring, hc);                                                      \
     if constexpr (IMG)                                                                             \
         if (img && (ZZ) >= S.iz0 && (ZZ) < S.iz1)                                                  \
             snap_image<VEC>(I, A0, A1, (int64_t)(ZZ) * C.pitch + C.x, ZZ, 0, C.x, q[((SS) + 4) % 9]);
@@ -420,9 +447,12 @@ struct Fwd2Ctx {
     bool live, own;
 };
 
+// The forward pair fetches each row's strip-end halo one march step early
+// at every width (1574 x 534 single shot, vec 1: 9.3 -> 7.0 us per step;
+// 48 shots at vec 4: 428 -> 426 us per launch).
 template <int VEC, int S>
 __device__ __forceinline__ void fwd2_row(const Fwd2Ctx<VEC> &C, float (&q1)[9][VEC], float (&q2)[9][VEC],
-                                         float (&qd)[9][VEC], int s, int &e)
+                                         float (&qd)[9][VEC], f4v &hc, int s, int &e)
 {
     constexpr int a0 = S % 9, a1 = (S + 1) % 9, a2 = (S + 2) % 9, a3 = (S + 3) % 9, a4 = (S + 4) % 9,
                   a5 = (S + 5) % 9, a6 = (S + 6) % 9, a7 = (S + 7) % 9, a8 = (S + 8) % 9;
@@ -438,7 +468,11 @@ __device__ __forceinline__ void fwd2_row(const Fwd2Ctx<VEC> &C, float (&q1)[9][V
         ldv<VEC>(C.Dp + o1, d);
     }
     float hl[4], hr[4], ext[VEC + 8];
-    load_halo<VEC>(C.pc + (int64_t)r1 * C.pitch, C.xs, C.NX, C.lane, hl, hr, in1);
+    {
+        const f4v t = hc;
+        hc = halo_fetch<VEC>(C.pc + (int64_t)(r1 + 1) * C.pitch, C.xs, C.NX, C.lane, r1 + 1 < C.NZr + kRadius);
+        halo_split(t, C.lane, hl, hr);
+    }
     exchange_row<VEC>(q1[a4], hl, hr, ext);
     float v1[VEC];
 #pragma unroll
@@ -540,7 +574,9 @@ __global__ __launch_bounds__(64) void fwd2d_t2_kernel(const ShotDev *__restrict_
     for (int j = 0; j < VEC; ++j) q2[8][j] = qd[8][j] = 0.f;
     int e = T.s1beg;
     const int nstep = T.z1 - T.z0 + kZUnroll;
-#define RTM_FWD2_ROW(SS, ZZ) fwd2_row<VEC, SS>(C, q1, q2, qd, ZZ, e)
+    // strip-end halo of the first march row (z0 - 4 >= -4: stored)
+    f4v hc = halo_fetch<VEC>(C.pc + (int64_t)(T.z0 - 4) * C.pitch, C.xs, C.NX, lane, true);
+#define RTM_FWD2_ROW(SS, ZZ) fwd2_row<VEC, SS>(C, q1, q2, qd, hc, ZZ, e)
     RTM_MARCH2(RTM_FWD2_ROW, nstep)
 #undef RTM_FWD2_ROW
     // Source at time n + 1 into the owned cells of level n + 2.
@@ -561,11 +597,13 @@ __global__ __launch_bounds__(64) void fwd2d_t2_kernel(const ShotDev *__restrict_
 // the kernel runs at one wavefront per SIMD (256 registers), so nothing
 // hides the latency of the halo load that each row's stencil waits for;
 // fetching it one march step early took the 48-shot reverse pair from 1349
-// to 1167 us.  With two floats per lane (three wavefronts per SIMD) the
-// eight extra registers cost more than the early fetch gains (1223 -> 1264
-// us), so that shape keeps the in-step load.
+// to 1167 us.  With one float per lane (the narrow tiles of a single small
+// shot, whose march is latency-bound) it saves 13% (1574 x 534: 12.2 ->
+// 10.7 us per step).  With two floats per lane (three wavefronts per SIMD)
+// the eight extra registers cost more than the early fetch gains (1223 ->
+// 1264 us), so that shape keeps the in-step load.
 template <int VEC>
-constexpr bool halo_ahead() { return VEC == 4; }
+constexpr bool halo_ahead() { return VEC != 2; }
 template <int VEC>
 struct Rev2Ctx {
     const gfloat *P0, *P1, *M0, *M1;  // p^k, p^{k+1}, mu^{k+1}, mu^{k+2} (read set)
