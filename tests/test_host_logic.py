@@ -1,7 +1,8 @@
 """Host logic of the runtime on the CPU: the tile and injection tables, the
 workspace layout and the storage-RTM launch schedule, checked by a C++
 program that includes the runtime with the device launchers replaced by
-recorders (no GPU call), built with host AddressSanitizer and UBSan."""
+recorders (no GPU call), built with host AddressSanitizer and UBSan; and
+every entry point of the oracle under the same sanitizers."""
 import os
 import re
 import shutil
@@ -55,4 +56,19 @@ def test_host_tables_layout_and_storage_schedule(tmp_path):
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
     print(r.stdout[-2000:], r.stderr[-2000:])
+    assert r.returncode == 0 and "ALL OK" in r.stdout, (r.stdout[-2000:], r.stderr[-2000:])
+
+
+@pytest.mark.timeout(300)
+def test_oracle_under_sanitizers(tmp_path):
+    """Every oracle entry point on tiny 2-D and 3-D grids, built with
+    AddressSanitizer and UBSan (plain gcc, no GPU)."""
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("gcc not available")
+    exe = os.path.join(str(tmp_path), "oracle_driver")
+    flags = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=all"]
+    subprocess.run([gcc, *flags, os.path.join(ROOT, "oracle", "oracle.c"), os.path.join(ROOT, "tests", "host",
+                   "oracle_driver.c"), "-o", exe, "-lm"], check=True, capture_output=True, text=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=120, env=dict(os.environ, ASAN_OPTIONS=""))
     assert r.returncode == 0 and "ALL OK" in r.stdout, (r.stdout[-2000:], r.stderr[-2000:])
