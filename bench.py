@@ -472,21 +472,22 @@ def main():
     batch_vs_plain = float(torch.linalg.norm(one - ref) / torch.linalg.norm(ref))
 
     # Dominant kernel: the fused reverse kernel (two stencils, imaging sums),
-    # one launch covering the B shots of a batch and one or two time steps.
+    # one launch covering the B shots of a batch and one to three time steps.
     # Algorithmic bytes per launch: one step reads p^k, p^{k+1}, mu^{k+1},
     # mu^{k+2}, D' and writes p^{k-1}, mu^k on the padded grid (28 B) and
-    # reads and writes num, den on the interior (16 B); two steps read the
-    # same five arrays once, write four levels (36 B) and num, den once (16 B).
+    # reads and writes num, den on the interior (16 B); two or three steps
+    # read the same five arrays once, write the last two levels of each field
+    # (36 B) and num, den once (16 B).
     steps_f = rtm.rtm_get_steps_per_launch(rtm.RTM_OP_MODEL)
     steps_r = rtm.rtm_get_steps_per_launch(rtm.RTM_OP_RTM)
     rev_ms, rev_n = loops["reverse_image"]
     rev_us = rev_ms * 1e3 / max(rev_n, 1)
-    rev_bytes = B * ((36 if steps_r == 2 else 28) * cells + 16 * interior)
+    rev_bytes = B * ((36 if steps_r >= 2 else 28) * cells + 16 * interior)
     achieved = rev_bytes / (rev_us * 1e-6) / 1e9
     one_step_bytes = B * (28 * cells + 16 * interior)
     per_step_us = rev_us / steps_r
-    rev_kernel = (f"rev2d_t2_kernel<{rev_shape[0]}> (two reverse steps per launch: reconstruction + receiver field + "
-                  f"imaging, {B} shots per launch)" if steps_r == 2 else
+    rev_kernel = (f"rev2d_t{steps_r}_kernel<{rev_shape[0]}> ({steps_r} reverse steps per launch: reconstruction + "
+                  f"receiver field + imaging, {B} shots per launch)" if steps_r >= 2 else
                   f"rev2d_kernel<{rev_shape[0]},false,{rev_shape[1]}> (fused reconstruction + receiver field + "
                   f"imaging, {B} shots per launch)")
     fwd_ms, fwd_n = loops["model_forward"]
@@ -506,8 +507,8 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"folded-layer 2-D survey 2301x751 @ 4 m, nb 60, nt {nt}, 25 Hz, 2301 receivers, 240 shots: "
-                        f"per step {B} shots modeled then migrated (random boundaries, reconstruction), one launch "
-                        f"per time step for the {B} shots, images stacked",
+                        f"per step {B} shots modeled then migrated (random boundaries, reconstruction), each launch "
+                        f"advancing the {B} shots by up to three time steps, images stacked",
             "padded_cells": cells,
             "shots_per_step": B,
             "propagations_per_shot": 4,

@@ -135,15 +135,19 @@ int rtm_get_tuning(int op, int *vec, int *zseg);
 int rtm_set_tuning2d(int op, int vec, int tx, int zseg);
 int rtm_get_tuning2d(int op, int *vec, int *tx, int *zseg);
 
-/* Time steps per launch of the 2-D propagation, 1 or 2.  With 2, one
+/* Time steps per launch of the 2-D propagation, 1, 2 or 3.  With 2, one
  * launch advances two steps: each wavefront computes the first step on its
  * strip plus a 4-cell margin and the second on the strip's inner columns
  * (strips overlap by 8 columns), and the two new levels go to a second set
- * of field buffers, so the level pairs cross HBM once per two steps.
- * RTM_OP_MODEL sets it for every forward pass (modeling and the forward
- * pass of RTM and VJP jobs), RTM_OP_RTM for the imaging reverse pass (the
- * gradient pass and probed runs always take one step per launch; an odd
- * last step is taken alone).  Results are bit-identical either way. */
+ * of field buffers, so the level pairs cross HBM once per two steps.  With
+ * 3 the strips overlap by 16 columns, the middle level stays in registers
+ * and the last two levels are stored: the pairs cross HBM once per three
+ * steps.  RTM_OP_MODEL sets it for every forward pass (modeling and the
+ * forward pass of RTM and VJP jobs; modeling and storage RTM, which need
+ * every level in memory, take 2 when 3 is set), RTM_OP_RTM for the imaging
+ * reverse pass (the gradient pass and probed runs always take one step per
+ * launch; the last nt mod S steps are taken one at a time).  Results are
+ * bit-identical whatever the setting.  Returns RTM_EINVAL for other values. */
 int rtm_set_steps_per_launch(int op, int steps);
 int rtm_get_steps_per_launch(int op, int *steps);
 

@@ -31,6 +31,10 @@ hipError_t launch_fwd2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, i
                            hipStream_t st);
 hipError_t launch_rev2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                            const InjEnt *ents, const Contrib *cont, int k, int reinject, hipStream_t st);
+hipError_t launch_fwd2d_t3(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+                           const InjEnt *ents, const Contrib *cont, int n, hipStream_t st);
+hipError_t launch_rev2d_t3(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+                           const InjEnt *ents, const Contrib *cont, int k, int reinject, hipStream_t st);
 hipError_t launch_recv2d(int vec, int tx, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                          const InjEnt *ents, const Contrib *cont, int k, const float *snap, hipStream_t st);
 // prop3d.hip
@@ -115,15 +119,17 @@ struct Tune {
     int zseg;
     int ty;  // 3-D: wavefronts (y rows) per workgroup
     int tx;  // 2-D: wavefronts (adjacent strips) per workgroup
-    int steps = 1;  // 2-D: time steps per launch (1, or 2 with the two-step kernels)
+    int steps = 1;  // 2-D: time steps per launch (1, 2 or 3)
 };
 
 // 2-D shapes: ((steps - 1) << 28) | (tx << 24) | (vec << 16) | zseg;
-// defaults from sweeps over 48 shots of the 2301 x 751 folded grid with two
-// steps per launch (forward 428 us, reverse pair 1165 us per launch; zseg 36
-// and vec 2 were 449 and 1247 us).
-std::atomic<int> g_tune2d_fwd{(1 << 28) | (1 << 24) | (4 << 16) | 108};
-std::atomic<int> g_tune2d_rev{(1 << 28) | (1 << 24) | (4 << 16) | 108};
+// defaults from sweeps over 48 shots of the 2301 x 751 folded grid: three
+// steps per launch at vec 2, 108-row tiles (reverse 412 us per step, RTM
+// forward 153; two steps at vec 4 took 584 and 212, three at vec 4 545 and
+// 201).  Modeling, which takes two steps per launch, then runs at vec 2
+// (232 us per step against 213 at vec 4).
+std::atomic<int> g_tune2d_fwd{(2 << 28) | (1 << 24) | (2 << 16) | 108};
+std::atomic<int> g_tune2d_rev{(2 << 28) | (1 << 24) | (2 << 16) | 108};
 std::atomic<int> g_tune_exact{0};  // 1: never narrow the configured shapes
 
 // 3-D shapes: (vec << 24) | (ty << 16) | zseg; defaults from a sweep on
@@ -289,7 +295,7 @@ struct ShotIn {
 struct Tiling {
     Tune tune{1, 18, 1, 1, 1};
     int ndim = 2;
-    bool two_step = false;  // overlapping strips of the two-step kernels
+    int steps = 1;  // 2-D: time steps per launch of the tiles (> 1: overlapping strips)
     std::vector<Tile2D> tiles;   // 2-D jobs
     std::vector<Tile3D> tiles3;  // 3-D jobs
     std::vector<InjEnt> ents;
@@ -301,7 +307,7 @@ struct Tiling {
 struct Counts {
     int64_t tiles_f = 0, ents_f = 0, cont_f = 0;  // forward tiling
     int64_t tiles_r = 0, ents_r = 0, cont_r = 0;  // reverse tiling
-    int64_t tiles_f2 = 0, ents_f2 = 0, cont_f2 = 0;  // two-step tilings (2-D)
+    int64_t tiles_f2 = 0, ents_f2 = 0, cont_f2 = 0;  // multi-step tilings (2-D)
     int64_t tiles_r2 = 0, ents_r2 = 0, cont_r2 = 0;
     int64_t stasks = 0, rnode = 0;
 };
@@ -325,7 +331,7 @@ struct Job {
     uint32_t flags = 0;
     std::vector<ShotIn> shots;
     Tiling fw, rv;    // rv unused for modeling
-    Tiling fw2, rv2;  // two-step tilings (2-D, when the shape asks for two steps per launch)
+    Tiling fw2, rv2;  // multi-step tilings (2-D, when the shape asks for two or three steps per launch)
     std::vector<SampleTask> stasks;
     std::vector<int> rnode;
     std::vector<float> rw;
@@ -342,7 +348,7 @@ struct Job {
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Field buffers per shot: p (2 levels) and mu (2 levels); 2-D jobs keep a
-// second set for the two-step kernels, so that the workspace size does not
+// second set for the multi-step kernels, so that the workspace size does not
 // depend on the launch shape.
 int nfields(int op, int ndim) { return (op == RTM_OP_MODEL ? 2 : 4) * (ndim == 2 ? 2 : 1); }
 int nfields(const Job &J) { return nfields(J.op, J.shots.empty() ? 3 : J.shots[0].g.ndim); }
@@ -421,11 +427,13 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
     T.cont.clear();
     std::vector<RawEnt> se, re;
     // 2-D: one tile is TX adjacent strips (one workgroup); 3-D: one strip.
-    // Two-step 2-D tiles: strips of 64 vec columns starting at j W - 4 that
-    // own W = 64 vec - 8 columns each (neighbours overlap by 8).
-    const bool two = T.two_step;
+    // 2-D tiles of S > 1 steps per launch: strips of 64 vec columns starting
+    // at j W - 4 (S - 1) that own W = 64 vec - 8 (S - 1) columns each
+    // (neighbours overlap by 8 (S - 1)).
+    const bool two = T.ndim == 2 && T.steps > 1;
+    const int off = two ? 4 * (T.steps - 1) : 0;
     const int span = 64 * T.tune.vec;
-    const int strip = two ? span - 8 : span * (T.ndim == 2 ? T.tune.tx : 1);
+    const int strip = two ? span - 2 * off : span * (T.ndim == 2 ? T.tune.tx : 1);
     const int ty = T.ndim == 3 ? T.tune.ty : 1;
     for (int s = 0; s < (int)J.shots.size(); ++s) {
         const ShotIn &S = J.shots[s];
@@ -456,14 +464,14 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
                     } else {
                         Tile2D t{};
                         t.shot = s;
-                        t.x0 = two ? xs * strip - 4 : xs * strip;
+                        t.x0 = xs * strip - off;
                         t.z0 = z0;
                         t.z1 = z1;
                         T.tiles.push_back(t);
                     }
                 }
         auto tile_of = [&](int z, int y, int x) {
-            if (rowmajor) return tbase + (z / T.tune.zseg) * ns + x / strip;  // (two-step: owned columns)
+            if (rowmajor) return tbase + (z / T.tune.zseg) * ns + x / strip;  // (multi-step: owned columns)
             return tbase + ((x / strip) * nys + (T.ndim == 3 ? y / ty : 0)) * nzs + z / T.tune.zseg;
         };
         PointOp sp;
@@ -496,11 +504,13 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
             }
         }
     }
-    // Two-step tiles also list, per tile, every node inside its strip and
-    // rows [z0 - 4, z1 + 4), where the first of the two steps is computed.
-    std::vector<RawEnt> se1, re1;
+    // Multi-step tiles also list, per tile, every node inside its strip and
+    // rows [z0 - 4 (S - 1), z1 + 4 (S - 1)), where the first step is
+    // computed; three-step tiles also those of rows [z0 - 4, z1 + 4), where
+    // the second is.
+    std::vector<RawEnt> se1, re1, se2, re2;
     if (two) {
-        auto widen = [&](const std::vector<RawEnt> &v, std::vector<RawEnt> &out) {
+        auto widen = [&](const std::vector<RawEnt> &v, std::vector<RawEnt> &out, int ext) {
             for (const RawEnt &e : v) {
                 const ShotIn &S = J.shots[e.shot];
                 const int NZr = S.g.L.NZr;
@@ -511,12 +521,14 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
                     const ShotIn &o = J.shots[q];
                     tb += ((o.g.NX + strip - 1) / strip) * ((o.g.L.NZr + T.tune.zseg - 1) / T.tune.zseg);
                 }
-                const int jc = (e.x + 4) / strip, zc = e.z / T.tune.zseg;
+                // ext <= 8 < zseg and 2 off < strip: the node lies in z tiles
+                // zc - 1 .. zc + 1 and strips jc - 1 .. jc at most
+                const int jc = (e.x + off) / strip, zc = e.z / T.tune.zseg;
                 for (int zs = std::max(0, zc - 1); zs <= std::min(nzs - 1, zc + 1); ++zs)
                     for (int j = std::max(0, jc - 2); j <= std::min(ns - 1, jc + 1); ++j) {
-                        const int x0 = j * strip - 4;
+                        const int x0 = j * strip - off;
                         const int z0 = zs * T.tune.zseg, z1 = std::min(z0 + T.tune.zseg, NZr);
-                        if (e.x >= x0 && e.x < x0 + span && e.z >= z0 - 4 && e.z < z1 + 4) {
+                        if (e.x >= x0 && e.x < x0 + span && e.z >= z0 - ext && e.z < z1 + ext) {
                             RawEnt w = e;
                             w.tile = tb + zs * ns + j;
                             out.push_back(w);
@@ -524,8 +536,12 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
                     }
             }
         };
-        widen(se, se1);
-        widen(re, re1);
+        widen(se, se1, off);
+        widen(re, re1, off);
+        if (T.steps == 3) {
+            widen(se, se2, 4);
+            widen(re, re2, 4);
+        }
     }
     auto order = [](const RawEnt &a, const RawEnt &b) {
         return std::tie(a.tile, a.z, a.y, a.x) < std::tie(b.tile, b.z, b.y, b.x);
@@ -534,9 +550,14 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
     std::sort(re.begin(), re.end(), order);
     std::sort(se1.begin(), se1.end(), order);
     std::sort(re1.begin(), re1.end(), order);
-    for (auto &t : T.tiles) t.sbeg = t.send = t.rbeg = t.rend = t.s1beg = t.s1end = t.r1beg = t.r1end = 0;
+    std::sort(se2.begin(), se2.end(), order);
+    std::sort(re2.begin(), re2.end(), order);
+    for (auto &t : T.tiles)
+        t.sbeg = t.send = t.rbeg = t.rend = t.s1beg = t.s1end = t.r1beg = t.r1end = t.s2beg = t.s2end = t.r2beg =
+            t.r2end = 0;
     for (auto &t : T.tiles3) t.sbeg = t.send = t.rbeg = t.rend = 0;
-    // kind: 0 source, 1 receivers, 2 source (first step), 3 receivers (first step)
+    // kind: 0 source, 1 receivers, 2 source (first step), 3 receivers (first
+    // step), 4 source (second step), 5 receivers (second step)
     auto emit = [&](std::vector<RawEnt> &v, int kind) {
         for (auto &e : v) {
             InjEnt E{e.z, e.y, e.x, (int)T.cont.size(), 0, e.slot, e.shot, 0};
@@ -551,8 +572,8 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
                 n = kind == 0 ? &t.send : &t.rend;
             } else {
                 Tile2D &t = T.tiles[e.tile];
-                int *bs[4] = {&t.sbeg, &t.rbeg, &t.s1beg, &t.r1beg};
-                int *ns_[4] = {&t.send, &t.rend, &t.s1end, &t.r1end};
+                int *bs[6] = {&t.sbeg, &t.rbeg, &t.s1beg, &t.r1beg, &t.s2beg, &t.r2beg};
+                int *ns_[6] = {&t.send, &t.rend, &t.s1end, &t.r1end, &t.s2end, &t.r2end};
                 b = bs[kind];
                 n = ns_[kind];
             }
@@ -566,6 +587,8 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
     T.nrec_ent = (int)re.size();
     emit(se1, 2);
     emit(re1, 3);
+    emit(se2, 4);
+    emit(re2, 5);
     T.nslots = (T.count() + kNumXcd - 1) / kNumXcd * kNumXcd;
     return RTM_OK;
 }
@@ -656,19 +679,22 @@ int build_job_tables(Job &J)
         rc = build_tiling(J, J.rv, true);
         if (rc) return rc;
     }
-    // Two-step tilings (2-D): the forward one for every op, the reverse one
-    // for imaging only (the gradient pass runs one step per launch).
+    // Multi-step tilings (2-D): the forward one for every op, the reverse
+    // one for imaging only (the gradient pass runs one step per launch).
+    // Three steps per launch never store the middle level, so modeling
+    // (which samples every level) and storage RTM (which copies stored
+    // levels) take two.
     J.fw2 = Tiling{};
     J.rv2 = Tiling{};
     J.fw2.ndim = J.rv2.ndim = ndim;
-    if (ndim == 2 && J.fw.tune.steps == 2) {
+    if (ndim == 2 && J.fw.tune.steps >= 2) {
         J.fw2.tune = J.fw.tune;
-        J.fw2.two_step = true;
+        J.fw2.steps = (J.op == RTM_OP_MODEL || J.op == RTM_OP_STORAGE) ? 2 : J.fw.tune.steps;
         if ((rc = build_tiling(J, J.fw2, false))) return rc;
     }
-    if (ndim == 2 && J.op == RTM_OP_RTM && J.rv.tune.steps == 2) {
+    if (ndim == 2 && J.op == RTM_OP_RTM && J.rv.tune.steps >= 2) {
         J.rv2.tune = J.rv.tune;
-        J.rv2.two_step = true;
+        J.rv2.steps = J.rv.tune.steps;
         if ((rc = build_tiling(J, J.rv2, true))) return rc;
     }
     return RTM_OK;
@@ -705,14 +731,15 @@ Counts bound_counts(const GridInfo &g, int op, int nrec)
         c.ents_r = c.cont_r = kMaxNodes + (int64_t)kMaxNodes * nrec;
     }
     if (g.ndim == 2) {
-        // two-step strips own >= 56 columns; a node lies in at most 2 strips
-        // x 2 tiles in z for the first step plus its owner: 5 entries
-        const int64_t t2 = ((g.NX + 55) / 56) * (g.L.NZr / kMinZseg);
+        // multi-step strips own >= 48 columns; a node lies in at most 2
+        // strips x 3 tiles in z for the first step, 2 x 2 for the second
+        // (three steps) and its owner: 11 entries
+        const int64_t t2 = ((g.NX + 47) / 48) * (g.L.NZr / kMinZseg);
         c.tiles_f2 = t2;
-        c.ents_f2 = c.cont_f2 = 5 * kMaxNodes;
+        c.ents_f2 = c.cont_f2 = 11 * kMaxNodes;
         if (op == RTM_OP_RTM) {
             c.tiles_r2 = t2;
-            c.ents_r2 = c.cont_r2 = 5 * (kMaxNodes + (int64_t)kMaxNodes * nrec);
+            c.ents_r2 = c.cont_r2 = 11 * (kMaxNodes + (int64_t)kMaxNodes * nrec);
         }
     }
     c.stasks = (nrec + 63) / 64;
@@ -729,7 +756,7 @@ struct Dev {
 
 // Two shot tables: out[0 .. nsh) addresses the field sets in order, out[nsh
 // .. 2 nsh) with the sets exchanged (current levels after an odd number of
-// two-step launches).
+// multi-step launches).
 void fill_shot_devs(const Job &J, const Dev &D, std::vector<ShotDev> &out)
 {
     const size_t nsh = J.shots.size();
@@ -833,7 +860,7 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
     const int nsh = (int)J.shots.size();
     const int nt = J.nt;
     // Current shot table: 0 while the latest levels are in the first field
-    // set, 1 after an odd number of two-step launches.
+    // set, 1 after an odd number of multi-step launches.
     int cur = 0;
     auto SH = [&]() { return table + (size_t)cur * nsh; };
     auto fld_of = [&](int i, int k) { return D.at<float>(J.ws.fld[i][cur ? (k ^ 4) : k]); };
@@ -841,9 +868,9 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
     // Two-step launches write the second field set: every level they touch
     // must have a buffer.
     for (int i = 0; i < nsh; ++i) {
-        const bool need_p = J.fw2.two_step || J.rv2.two_step, need_mu = J.rv2.two_step;
+        const bool need_p = J.fw2.steps > 1 || J.rv2.steps > 1, need_mu = J.rv2.steps > 1;
         if ((need_p && !(J.ws.fld[i][4] && J.ws.fld[i][5])) || (need_mu && !(J.ws.fld[i][6] && J.ws.fld[i][7])))
-            return fail(RTM_EINVAL, "internal: shot %d lacks the second field set of two-step launches", i);
+            return fail(RTM_EINVAL, "internal: shot %d lacks the second field set of multi-step launches", i);
     }
     for (int d = 0; d < (int)J.slot_shot.size(); ++d) {
         const ShotIn &S = J.shots[J.slot_shot[d]];
@@ -869,8 +896,9 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
         const SampleTask *stasks = D.at<SampleTask>(J.ws.stasks);
         const int ntiles = J.fw.count();
         const int nsample = sample ? (int)J.stasks.size() : 0;
-        const bool two = J.fw.ndim == 2 && J.fw2.two_step;
-        LoopTimer timer(sample ? kLoopModelFwd : kLoopRtmFwd, two ? nt / 2 + nt % 2 : nt, st, timed);
+        const bool two = J.fw.ndim == 2 && J.fw2.steps > 1;
+        const int fs = two ? J.fw2.steps : 1;
+        LoopTimer timer(sample ? kLoopModelFwd : kLoopRtmFwd, nt / fs + nt % fs, st, timed);
         // Storage RTM: copy the interior of each stored level p^m once it
         // is current (before the step that overwrites p^{m-1} with p^{m+1}).
         auto keep = [&](int m) -> int {
@@ -884,7 +912,14 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
         };
         int rc = RTM_OK;
         int n = 0;
-        if (two) {
+        if (fs == 3) {
+            // steps n .. n + 2 per launch (no sampling, no stored levels)
+            for (; n + 3 <= nt; n += 3) {
+                RTM_HIP(launch_fwd2d_t3(J.fw2.tune.vec, SH(), D.at<Tile2D>(J.ws.tiles_f2), J.fw2.count(),
+                                        J.fw2.nslots, D.at<InjEnt>(J.ws.ents_f2), D.at<Contrib>(J.ws.cont_f2), n, st));
+                cur ^= 1;
+            }
+        } else if (two) {
             // steps n, n + 1 per launch; each launch records d^{n-1}, d^n
             for (; n + 2 <= nt; n += 2) {
                 if ((rc = keep(n))) return rc;
@@ -908,7 +943,7 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
         }
         timer.finish();
         if (sample) {
-            if (two && nt % 2 == 0 && nt >= 2) RTM_HIP(launch_sample(SH(), stasks, nsample, nt - 1, st));
+            if (fs == 2 && nt % 2 == 0 && nt >= 2) RTM_HIP(launch_sample(SH(), stasks, nsample, nt - 1, st));
             RTM_HIP(launch_sample(SH(), stasks, nsample, nt, st));
         }
     }
@@ -951,13 +986,20 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
     }
     const int reinject = (J.flags & RTM_F_NO_REINJECT) ? 0 : 1;
     const bool probing = probe && probe->snap_k >= 0;
-    const bool two = J.rv.ndim == 2 && J.rv2.two_step && !grad && !probing;
+    const bool two = J.rv.ndim == 2 && J.rv2.steps > 1 && !grad && !probing;
+    const int rs = two ? J.rv2.steps : 1;
     // wadj is recorded for a single-shot job only (its kernel argument is one
     // buffer); batched VJPs do not return wavelet gradients.
     float *wadj = (grad && nsh == 1 && J.shots[0].grad_wavelet) ? D.at<float>(J.ws.wadj[0]) : nullptr;
-    LoopTimer timer(grad ? kLoopRevGrad : kLoopRevImage, two ? nt / 2 + nt % 2 : nt, st, timed && !probing);
+    LoopTimer timer(grad ? kLoopRevGrad : kLoopRevImage, nt / rs + nt % rs, st, timed && !probing);
     int k = nt - 1;
-    if (two) {
+    if (rs == 3) {
+        for (; k >= 2; k -= 3) {
+            RTM_HIP(launch_rev2d_t3(J.rv2.tune.vec, SH(), D.at<Tile2D>(J.ws.tiles_r2), J.rv2.count(), J.rv2.nslots,
+                                    D.at<InjEnt>(J.ws.ents_r2), D.at<Contrib>(J.ws.cont_r2), k, reinject, st));
+            cur ^= 1;
+        }
+    } else if (two) {
         for (; k >= 1; k -= 2) {
             RTM_HIP(launch_rev2d_t2(J.rv2.tune.vec, SH(), D.at<Tile2D>(J.ws.tiles_r2), J.rv2.count(), J.rv2.nslots,
                                     D.at<InjEnt>(J.ws.ents_r2), D.at<Contrib>(J.ws.cont_r2), k, reinject, st));
@@ -1187,7 +1229,7 @@ int rtm_set_tuning2d(int op, int vec, int tx, int zseg)
 
 int rtm_set_steps_per_launch(int op, int steps)
 {
-    if (steps != 1 && steps != 2) return fail(RTM_EINVAL, "steps must be 1 or 2");
+    if (steps < 1 || steps > 3) return fail(RTM_EINVAL, "steps must be 1, 2 or 3");
     if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
     std::atomic<int> &g = op == RTM_OP_MODEL ? g_tune2d_fwd : g_tune2d_rev;
     g = (g.load() & ~(0x3 << 28)) | ((steps - 1) << 28);

@@ -84,14 +84,18 @@ struct ShotDev {
 // of 64 * VEC columns starting at x0; z1 - z0 is a multiple of kZUnroll
 // (rows at or below NZ are zero halo rows and stay zero).  Injection entries
 // of the tile are ents[sbeg, send) (source, into p) and ents[rbeg, rend)
-// (receivers, into mu).  A two-step tile also lists the entries of its
-// whole strip and rows [z0 - 4, z1 + 4) (where the first of its two steps
-// is computed) in ents[s1beg, s1end) and ents[r1beg, r1end).
+// (receivers, into mu).  A tile of T > 1 steps per launch also lists the
+// entries of its whole strip and rows [z0 - 4 (T - 1), z1 + 4 (T - 1)) (where
+// the first step is computed) in ents[s1beg, s1end) and ents[r1beg, r1end),
+// and with T = 3 those of rows [z0 - 4, z1 + 4) (where the second step is
+// computed) in ents[s2beg, s2end) and ents[r2beg, r2end).  The tile's own
+// list (sbeg .. rend) feeds the last step.
 struct Tile2D {
     int shot;
     int x0, z0, z1;
     int sbeg, send, rbeg, rend;
     int s1beg, s1end, r1beg, r1end;
+    int s2beg, s2end, r2beg, r2end;
 };
 
 // A 3-D stencil tile: a workgroup covers x in [x0, x0 + TX) and y in

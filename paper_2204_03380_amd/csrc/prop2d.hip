@@ -839,6 +839,455 @@ void rev2d_t2_kernel(const ShotDev *__restrict__ shots,
 }
 
 // ---------------------------------------------------------------------------
+// Three steps per launch
+// ---------------------------------------------------------------------------
+//
+// The scheme of the two-step kernels carried one step further.  A strip of
+// 64 * VEC columns starting at xs overlaps its neighbours by 16 and owns the
+// inner 64 * VEC - 16.  Step one (level n + 1 from n, n - 1) runs on the
+// whole strip with the strip-end halo, over rows [z0 - 8, z1 + 8); step two
+// runs four rows behind it and is exact on [xs + 4, xs + 64 VEC - 4) for rows
+// [z0 - 4, z1 + 4); step three runs eight rows behind and is exact on the
+// owned columns and rows [z0, z1).  Queue slot (S + i) % 9 holds row
+// r1 - 4 + i of every queue (r1: step one's row at march step S), so step
+// two's centre row r1 - 4 sits in slot S and step three's r1 - 8 in slot
+// (S + 5) % 9.  Steps one and two add their sources in the march (their
+// values feed the next step); step three's are added after the march by
+// the owner.  Only the last two levels are stored: level n + 1 never leaves
+// the registers, so the launch reads two levels and D' and writes two
+// levels once per three steps.  Every cell's arithmetic equals the one-step
+// kernel's, operation for operation.
+template <int VEC>
+__device__ __forceinline__ bool own3(int x, int xs, int NX)
+{
+    return x >= xs + 8 && x + VEC <= xs + 64 * VEC - 8 && x < NX;
+}
+
+// Rows that exist in storage: [-4, NZr + 4).
+__device__ __forceinline__ bool stored_row(int r, int NZr) { return r >= -kRadius && r < NZr + kRadius; }
+
+// Laplacian sum of a queue's centre row: slots (c - m) and (c + m) hold
+// rows -m and +m for the centre slot C (indices mod 9).
+template <int VEC, int C>
+__device__ __forceinline__ void lap_rows(const float (&q)[9][VEC], const float (&ext)[VEC + 8], float c2, int j,
+                                         float &lap)
+{
+    constexpr int m1 = (C + 8) % 9, p1 = (C + 1) % 9, m2 = (C + 7) % 9, p2 = (C + 2) % 9, m3 = (C + 6) % 9,
+                  p3 = (C + 3) % 9, m4 = (C + 5) % 9, p4 = (C + 4) % 9;
+    lap = d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
+    lap += d2(c2, q[m1][j], q[p1][j], q[m2][j], q[p2][j], q[m3][j], q[p3][j], q[m4][j], q[p4][j]);
+}
+
+// Forward triple: levels n + 1, n + 2, n + 3 from (n, n - 1); n + 2 and
+// n + 3 are stored.
+template <int VEC>
+struct Fwd3Ctx {
+    const gfloat *pc, *pm;  // p^n, p^{n-1} (read set)
+    gfloat *w2, *w3;        // p^{n+2}, p^{n+3} (write set)
+    const gfloat *Dp;
+    const float *wav;       // wavelet from time n
+    const InjEnt *ents;
+    const Contrib *cont;
+    int64_t pitch;
+    int x, xs, NX, NZr, lane, z0, z1, e1end, e2end;
+    bool live, own;
+};
+
+template <int VEC, int S>
+__device__ __forceinline__ void fwd3_row(const Fwd3Ctx<VEC> &C, float (&q1)[9][VEC], float (&q2)[9][VEC],
+                                         float (&q3)[9][VEC], float (&qd)[9][VEC], f4v &hc, int s, int &e1,
+                                         int &e2)
+{
+    constexpr int a0 = S % 9, a4 = (S + 4) % 9, a5 = (S + 5) % 9, a8 = (S + 8) % 9;
+    const int r1 = C.z0 - 8 + s, r2 = r1 - 4, r3 = r1 - 8;
+    const int64_t o1 = (int64_t)r1 * C.pitch + C.x;
+    float old[VEC], d[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) q1[a8][j] = old[j] = d[j] = 0.f;
+    if (C.live && stored_row(r1 + 4, C.NZr)) ldv<VEC>(C.pc + o1 + 4 * C.pitch, q1[a8]);
+    if (C.live && stored_row(r1, C.NZr)) {
+        ldv<VEC>(C.pm + o1, old);
+        ldv<VEC>(C.Dp + o1, d);
+    }
+    float hl[4], hr[4], ext[VEC + 8];
+    {
+        const f4v t = hc;
+        hc = halo_fetch<VEC>(C.pc + (int64_t)(r1 + 1) * C.pitch, C.xs, C.NX, C.lane, stored_row(r1 + 1, C.NZr));
+        halo_split(t, C.lane, hl, hr);
+    }
+    exchange_row<VEC>(q1[a4], hl, hr, ext);
+    float v1[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const float c = q1[a4][j], c2 = c + c;
+        float lap;
+        lap_rows<VEC, a4>(q1, ext, c2, j, lap);
+        v1[j] = fmaf(d[j], lap, c2 - old[j]);
+    }
+    for (; e1 < C.e1end && C.ents[e1].z == r1; ++e1) {  // source at time n, row r1
+        const InjEnt E = C.ents[e1];
+        const float sv = inj_sum(E, C.cont, C.wav);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j)
+            if (E.x == C.x + j) v1[j] = fmaf(d[j], sv, v1[j]);
+    }
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        q2[a4][j] = v1[j];
+        qd[a4][j] = d[j];
+    }
+    const float hz[4] = {0.f, 0.f, 0.f, 0.f};
+    if (s >= 8 && r2 < C.z1 + 4) {
+        exchange_row<VEC>(q2[a0], hz, hz, ext);
+        float v2[VEC];
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float c = q2[a0][j], c2 = c + c;
+            float lap;
+            lap_rows<VEC, a0>(q2, ext, c2, j, lap);
+            v2[j] = fmaf(qd[a0][j], lap, c2 - q1[a0][j]);
+        }
+        for (; e2 < C.e2end && C.ents[e2].z == r2; ++e2) {  // source at time n + 1, row r2
+            const InjEnt E = C.ents[e2];
+            const float sv = inj_sum(E, C.cont, C.wav + 1);
+#pragma unroll
+            for (int j = 0; j < VEC; ++j)
+                if (E.x == C.x + j) v2[j] = fmaf(qd[a0][j], sv, v2[j]);
+        }
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) q3[a0][j] = v2[j];
+        if (C.own && r2 >= C.z0 && r2 < C.z1) stv<VEC>(C.w2 + (int64_t)r2 * C.pitch + C.x, v2);
+    }
+    if (s >= 16 && r3 < C.z1) {
+        exchange_row<VEC>(q3[a5], hz, hz, ext);
+        float v3[VEC];
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float c = q3[a5][j], c2 = c + c;
+            float lap;
+            lap_rows<VEC, a5>(q3, ext, c2, j, lap);
+            v3[j] = fmaf(qd[a5][j], lap, c2 - q2[a5][j]);
+        }
+        if (C.own) stv<VEC>(C.w3 + (int64_t)r3 * C.pitch + C.x, v3);
+    }
+}
+
+// Steps n, n + 1 and n + 2 of every tile (no receiver sampling: level n + 1
+// is not stored).
+template <int VEC>
+__global__ __launch_bounds__(64) void fwd2d_t3_kernel(const ShotDev *__restrict__ shots,
+                                                      const Tile2D *__restrict__ tiles, int ntiles, int nslots,
+                                                      const InjEnt *__restrict__ ents,
+                                                      const Contrib *__restrict__ cont, int n)
+{
+    const int t = xcd_tile(blockIdx.x, nslots);
+    if (t >= ntiles) return;
+    const Tile2D T = tiles[t];
+    const ShotDev &S = shots[T.shot];
+    const int lane = threadIdx.x;
+    Fwd3Ctx<VEC> C;
+    C.pitch = S.L.pitch;
+    C.NX = S.L.NX;
+    C.NZr = S.L.NZr;
+    C.pc = gp(S.fld[n & 1] + S.L.org);
+    C.pm = gp(S.fld[(n + 1) & 1] + S.L.org);
+    C.w2 = gp(S.fld[4 + (n & 1)] + S.L.org);
+    C.w3 = gp(S.fld[4 + ((n + 1) & 1)] + S.L.org);
+    C.Dp = gp(S.Dp + S.L.org);
+    C.wav = S.wav + n;
+    C.ents = ents;
+    C.cont = cont;
+    C.lane = lane;
+    C.xs = T.x0;
+    C.x = T.x0 + lane * VEC;
+    C.z0 = T.z0;
+    C.z1 = T.z1;
+    C.e1end = T.s1end;
+    C.e2end = T.s2end;
+    C.live = C.x >= -kRadius && C.x < C.NX + kRadius;
+    C.own = own3<VEC>(C.x, C.xs, C.NX);
+
+    float q1[9][VEC], q2[9][VEC], q3[9][VEC], qd[9][VEC];
+    // level n rows z0 - 12 .. z0 - 5 (rows above -4 do not exist: zero)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) q1[i][j] = q2[i][j] = q3[i][j] = qd[i][j] = 0.f;
+        const int r = T.z0 - 12 + i;
+        if (i < 8 && C.live && stored_row(r, C.NZr)) ldv<VEC>(C.pc + (int64_t)r * C.pitch + C.x, q1[i]);
+    }
+    int e1 = T.s1beg, e2 = T.s2beg;
+    // step one covers rows [z0 - 8, z1 + 8): z1 - z0 + 16 march steps,
+    // rounded up to the unroll
+    const int nstep = T.z1 - T.z0 + 2 * kZUnroll;
+    f4v hc = halo_fetch<VEC>(C.pc + (int64_t)(T.z0 - 8) * C.pitch, C.xs, C.NX, lane, stored_row(T.z0 - 8, C.NZr));
+#define RTM_FWD3_ROW(SS, ZZ) fwd3_row<VEC, SS>(C, q1, q2, q3, qd, hc, ZZ, e1, e2)
+    RTM_MARCH2(RTM_FWD3_ROW, nstep)
+#undef RTM_FWD3_ROW
+    // Source at time n + 2 into the owned cells of level n + 3.
+    const float *wav2 = S.wav + n + 2;
+    for (int k = T.sbeg; k < T.send; ++k) {
+        const InjEnt E = ents[k];
+        if (owns<VEC>(E.x, C.xs, lane)) {
+            const int64_t o = (int64_t)E.z * C.pitch + E.x;
+            C.w3[o] = fmaf(C.Dp[o], inj_sum(E, cont, wav2), C.w3[o]);
+        }
+    }
+}
+
+// Reverse triple (imaging): steps k, k - 1 and k - 2 of the reconstruction
+// and the receiver field.  All three imaging terms of a row are added at
+// step two's row r2, where p^k, mu^{k+1} (step two's previous levels),
+// p^{k-1}, mu^k (its centre) and the new p^{k-2}, mu^{k-1} are all in
+// registers: num and den are read and written once per three steps.
+template <int VEC>
+struct Rev3Ctx {
+    const gfloat *P0, *P1, *M0, *M1;  // p^k, p^{k+1}, mu^{k+1}, mu^{k+2} (read set)
+    gfloat *WP2, *WP3, *WM2, *WM3;    // p^{k-2}, p^{k-3}, mu^{k-1}, mu^{k-2} (write set)
+    const gfloat *Dp;
+    gfloat *A0, *A1;                  // num, den
+    const float *wav, *sig;           // wavelet and receiver signal at time k
+    const InjEnt *ents;
+    const Contrib *cont;
+    float *isv;                       // LDS: receiver sums of one row (row_inject)
+    int *ihas;
+    int64_t pitch;
+    int nrec;
+    int x, xs, NX, NZr, lane, z0, z1, iz0, iz1, s1end, r1end, s2end, r2end;
+    bool live, own, own_img, reinject;
+};
+
+template <int VEC, int S>
+__device__ __forceinline__ void rev3_row(const Rev3Ctx<VEC> &C, float (&q1p)[9][VEC], float (&q1m)[9][VEC],
+                                         float (&q2p)[9][VEC], float (&q2m)[9][VEC], float (&q3p)[9][VEC],
+                                         float (&q3m)[9][VEC], float (&qd)[9][VEC], f4v &hp, f4v &hm, int s,
+                                         int &es1, int &er1, int &es2, int &er2)
+{
+    constexpr int a0 = S % 9, a4 = (S + 4) % 9, a5 = (S + 5) % 9, a8 = (S + 8) % 9;
+    const int r1 = C.z0 - 8 + s, r2 = r1 - 4, r3 = r1 - 8;
+    const int64_t o1 = (int64_t)r1 * C.pitch + C.x, o2 = (int64_t)r2 * C.pitch + C.x;
+    float p1[VEC], m1[VEC], d[VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) q1p[a8][j] = q1m[a8][j] = p1[j] = m1[j] = d[j] = 0.f;
+    if (C.live && stored_row(r1 + 4, C.NZr)) {
+        ldv<VEC>(C.P0 + o1 + 4 * C.pitch, q1p[a8]);
+        ldv<VEC>(C.M0 + o1 + 4 * C.pitch, q1m[a8]);
+    }
+    if (C.live && stored_row(r1, C.NZr)) {
+        ldv_s<VEC>(C.P1 + o1, p1);
+        ldv_s<VEC>(C.M1 + o1, m1);
+        ldv_s<VEC>(C.Dp + o1, d);
+    }
+    const bool do2 = s >= 8 && r2 < C.z1 + 4;
+    const bool img = do2 && C.own_img && r2 >= C.z0 && r2 < C.z1 && r2 >= C.iz0 && r2 < C.iz1;
+    float ia[VEC], ib[VEC];
+    if (img) {
+        ldv_s<VEC>(C.A0 + o2, ia);
+        ldv_s<VEC>(C.A1 + o2, ib);
+    }
+    float hl[4], hr[4], ext[VEC + 8];
+    float np[VEC], nm[VEC];
+    const f4v tp = hp, tm = hm;
+    {
+        const bool en = stored_row(r1 + 1, C.NZr);
+        hp = halo_fetch<VEC>(C.P0 + (int64_t)(r1 + 1) * C.pitch, C.xs, C.NX, C.lane, en);
+        hm = halo_fetch<VEC>(C.M0 + (int64_t)(r1 + 1) * C.pitch, C.xs, C.NX, C.lane, en);
+    }
+    halo_split(tp, C.lane, hl, hr);
+    exchange_row<VEC>(q1p[a4], hl, hr, ext);
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const float c = q1p[a4][j], c2 = c + c;
+        float lap;
+        lap_rows<VEC, a4>(q1p, ext, c2, j, lap);
+        np[j] = fmaf(d[j], lap, c2 - p1[j]);
+    }
+    halo_split(tm, C.lane, hl, hr);
+    exchange_row<VEC>(q1m[a4], hl, hr, ext);
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        const float c = q1m[a4][j], c2 = c + c;
+        float lap;
+        lap_rows<VEC, a4>(q1m, ext, c2, j, lap);
+        nm[j] = fmaf(d[j], lap, c2 - m1[j]);
+    }
+    // time-k terms in row r1: source re-injection into p^{k-1}, receivers into mu^k
+    for (; es1 < C.s1end && C.ents[es1].z == r1; ++es1) {
+        const InjEnt E = C.ents[es1];
+        const float sv = inj_sum(E, C.cont, C.wav);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j)
+            if (C.reinject && E.x == C.x + j) np[j] = fmaf(d[j], sv, np[j]);
+    }
+    row_inject<VEC>(C.ents, C.cont, C.sig, r1, er1, C.r1end, C.xs, C.lane, d, nm, C.isv, C.ihas);
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) {
+        q2p[a4][j] = np[j];
+        q2m[a4][j] = nm[j];
+        qd[a4][j] = d[j];
+    }
+    const float hz[4] = {0.f, 0.f, 0.f, 0.f};
+    if (do2) {
+        float vp[VEC], vm[VEC];
+        exchange_row<VEC>(q2p[a0], hz, hz, ext);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float c = q2p[a0][j], c2 = c + c;
+            float lap;
+            lap_rows<VEC, a0>(q2p, ext, c2, j, lap);
+            vp[j] = fmaf(qd[a0][j], lap, c2 - q1p[a0][j]);
+        }
+        exchange_row<VEC>(q2m[a0], hz, hz, ext);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float c = q2m[a0][j], c2 = c + c;
+            float lap;
+            lap_rows<VEC, a0>(q2m, ext, c2, j, lap);
+            vm[j] = fmaf(qd[a0][j], lap, c2 - q1m[a0][j]);
+        }
+        // time k - 1 terms in row r2
+        for (; es2 < C.s2end && C.ents[es2].z == r2; ++es2) {
+            const InjEnt E = C.ents[es2];
+            const float sv = inj_sum(E, C.cont, C.wav - 1);
+#pragma unroll
+            for (int j = 0; j < VEC; ++j)
+                if (C.reinject && E.x == C.x + j) vp[j] = fmaf(qd[a0][j], sv, vp[j]);
+        }
+        row_inject<VEC>(C.ents, C.cont, C.sig - C.nrec, r2, er2, C.r2end, C.xs, C.lane, qd[a0], vm, C.isv,
+                        C.ihas);
+        if (C.own && r2 >= C.z0 && r2 < C.z1) {
+            stv<VEC>(C.WP2 + o2, vp);
+            stv<VEC>(C.WM2 + o2, vm);
+        }
+        if (img) {
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {  // levels k, k - 1, k - 2 in turn
+                ia[j] = fmaf(vp[j], vm[j], fmaf(q2p[a0][j], q2m[a0][j], fmaf(q1p[a0][j], q1m[a0][j], ia[j])));
+                ib[j] = fmaf(vp[j], vp[j], fmaf(q2p[a0][j], q2p[a0][j], fmaf(q1p[a0][j], q1p[a0][j], ib[j])));
+            }
+            stv_s<VEC>(C.A0 + o2, ia);
+            stv_s<VEC>(C.A1 + o2, ib);
+        }
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            q3p[a0][j] = vp[j];
+            q3m[a0][j] = vm[j];
+        }
+    }
+    if (s >= 16 && r3 < C.z1) {
+        const int64_t o3 = (int64_t)r3 * C.pitch + C.x;
+        float vp[VEC], vm[VEC];
+        exchange_row<VEC>(q3p[a5], hz, hz, ext);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float c = q3p[a5][j], c2 = c + c;
+            float lap;
+            lap_rows<VEC, a5>(q3p, ext, c2, j, lap);
+            vp[j] = fmaf(qd[a5][j], lap, c2 - q2p[a5][j]);
+        }
+        exchange_row<VEC>(q3m[a5], hz, hz, ext);
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) {
+            const float c = q3m[a5][j], c2 = c + c;
+            float lap;
+            lap_rows<VEC, a5>(q3m, ext, c2, j, lap);
+            vm[j] = fmaf(qd[a5][j], lap, c2 - q2m[a5][j]);
+        }
+        if (C.own) {
+            stv<VEC>(C.WP3 + o3, vp);
+            stv<VEC>(C.WM3 + o3, vm);
+        }
+    }
+}
+
+template <int VEC>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 8)))
+void rev2d_t3_kernel(const ShotDev *__restrict__ shots, const Tile2D *__restrict__ tiles, int ntiles, int nslots,
+                     const InjEnt *__restrict__ ents, const Contrib *__restrict__ cont, int k, int reinject)
+{
+    const int t = xcd_tile(blockIdx.x, nslots);
+    if (t >= ntiles) return;
+    const Tile2D T = tiles[t];
+    const ShotDev &S = shots[T.shot];
+    const int lane = threadIdx.x;
+    Rev3Ctx<VEC> C;
+    C.pitch = S.L.pitch;
+    C.NX = S.L.NX;
+    C.NZr = S.L.NZr;
+    C.P0 = gp(S.fld[k & 1] + S.L.org);
+    C.P1 = gp(S.fld[(k + 1) & 1] + S.L.org);
+    C.M0 = gp(S.fld[2 + ((k + 1) & 1)] + S.L.org);
+    C.M1 = gp(S.fld[2 + (k & 1)] + S.L.org);
+    C.WP2 = gp(S.fld[4 + (k & 1)] + S.L.org);
+    C.WP3 = gp(S.fld[4 + ((k + 1) & 1)] + S.L.org);
+    C.WM2 = gp(S.fld[6 + ((k + 1) & 1)] + S.L.org);
+    C.WM3 = gp(S.fld[6 + (k & 1)] + S.L.org);
+    C.Dp = gp(S.Dp + S.L.org);
+    C.A0 = gp(S.acc0 + S.L.org);
+    C.A1 = gp(S.acc1 + S.L.org);
+    C.wav = S.wav + k;
+    C.sig = S.sig + (int64_t)k * S.nrec;
+    C.nrec = S.nrec;
+    C.ents = ents;
+    C.cont = cont;
+    C.lane = lane;
+    C.xs = T.x0;
+    C.x = T.x0 + lane * VEC;
+    C.z0 = T.z0;
+    C.z1 = T.z1;
+    C.iz0 = S.iz0;
+    C.iz1 = S.iz1;
+    C.s1end = T.s1end;
+    C.r1end = T.r1end;
+    C.s2end = T.s2end;
+    C.r2end = T.r2end;
+    __shared__ float isv[64 * VEC];
+    __shared__ int ihas[64 * VEC];
+#pragma unroll
+    for (int j = 0; j < VEC; ++j) ihas[lane * VEC + j] = 0;
+    __syncthreads();
+    C.isv = isv;
+    C.ihas = ihas;
+    C.live = C.x >= -kRadius && C.x < C.NX + kRadius;
+    C.own = own3<VEC>(C.x, C.xs, C.NX);
+    C.own_img = C.own && C.x + VEC > S.ix0 && C.x < S.ix1;
+    C.reinject = reinject != 0;
+
+    float q1p[9][VEC], q1m[9][VEC], q2p[9][VEC], q2m[9][VEC], q3p[9][VEC], q3m[9][VEC], qd[9][VEC];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j)
+            q1p[i][j] = q1m[i][j] = q2p[i][j] = q2m[i][j] = q3p[i][j] = q3m[i][j] = qd[i][j] = 0.f;
+        const int r = T.z0 - 12 + i;
+        if (i < 8 && C.live && stored_row(r, C.NZr)) {
+            ldv<VEC>(C.P0 + (int64_t)r * C.pitch + C.x, q1p[i]);
+            ldv<VEC>(C.M0 + (int64_t)r * C.pitch + C.x, q1m[i]);
+        }
+    }
+    int es1 = T.s1beg, er1 = T.r1beg, es2 = T.s2beg, er2 = T.r2beg;
+    const int nstep = T.z1 - T.z0 + 2 * kZUnroll;
+    const bool en0 = stored_row(T.z0 - 8, C.NZr);
+    f4v hp = halo_fetch<VEC>(C.P0 + (int64_t)(T.z0 - 8) * C.pitch, C.xs, C.NX, lane, en0);
+    f4v hm = halo_fetch<VEC>(C.M0 + (int64_t)(T.z0 - 8) * C.pitch, C.xs, C.NX, lane, en0);
+#define RTM_REV3_ROW(SS, ZZ) rev3_row<VEC, SS>(C, q1p, q1m, q2p, q2m, q3p, q3m, qd, hp, hm, ZZ, es1, er1, es2, er2)
+    RTM_MARCH2(RTM_REV3_ROW, nstep)
+#undef RTM_REV3_ROW
+    // time k - 2 terms into the owned cells of p^{k-3} and mu^{k-2}
+    const float *wav2 = S.wav + (k - 2);
+    if (C.reinject) {
+        for (int e = T.sbeg; e < T.send; ++e) {
+            const InjEnt E = ents[e];
+            if (owns<VEC>(E.x, C.xs, lane)) {
+                const int64_t o = (int64_t)E.z * C.pitch + E.x;
+                C.WP3[o] = fmaf(C.Dp[o], inj_sum(E, cont, wav2), C.WP3[o]);
+            }
+        }
+    }
+    inject_nodes(C.WM3, C.Dp, ents, T.rbeg, T.rend, cont, S.sig + (int64_t)(k - 2) * S.nrec, C.pitch, C.pitch);
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
 
@@ -952,6 +1401,32 @@ hipError_t launch_rev2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, i
     case 1: hipLaunchKernelGGL(rev2d_t2_kernel<1>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject); break;
     case 2: hipLaunchKernelGGL(rev2d_t2_kernel<2>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject); break;
     case 4: hipLaunchKernelGGL(rev2d_t2_kernel<4>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd2d_t3(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+                           const InjEnt *ents, const Contrib *cont, int n, hipStream_t st)
+{
+    dim3 grid(nslots), block(64);
+    switch (vec) {
+    case 1: hipLaunchKernelGGL(fwd2d_t3_kernel<1>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, n); break;
+    case 2: hipLaunchKernelGGL(fwd2d_t3_kernel<2>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, n); break;
+    case 4: hipLaunchKernelGGL(fwd2d_t3_kernel<4>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, n); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_rev2d_t3(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+                           const InjEnt *ents, const Contrib *cont, int k, int reinject, hipStream_t st)
+{
+    dim3 grid(nslots), block(64);
+    switch (vec) {
+    case 1: hipLaunchKernelGGL(rev2d_t3_kernel<1>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject); break;
+    case 2: hipLaunchKernelGGL(rev2d_t3_kernel<2>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject); break;
+    case 4: hipLaunchKernelGGL(rev2d_t3_kernel<4>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

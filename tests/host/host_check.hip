@@ -18,7 +18,8 @@ struct Sim {
     const ShotDev *base = nullptr;
     std::vector<ShotDev> host;
     int nsh = 1;
-    std::map<const float *, int> lev_of;
+    std::map<const float *, int> lev_of, mu_of;  // p and mu level held by each field
+    std::vector<int> fsteps, rsteps;               // forward and reverse steps, in launch order
     float *snaps = nullptr;
     int64_t ncell = 0;
     int stride = 1, phase = 0, last_k = 1 << 30;
@@ -39,6 +40,7 @@ hipError_t launch_fwd2d(int, int, const ShotDev *shots, const Tile2D *, int, int
     const ShotDev &T = SIM.tab(shots);
     if (SIM.lev_of[T.fld[n & 1]] != n) ++SIM.errors;
     SIM.lev_of[T.fld[(n + 1) & 1]] = n + 1;
+    SIM.fsteps.push_back(n);
     return hipSuccess;
 }
 hipError_t launch_fwd3d(int, int, const ShotDev *shots, const Tile3D *, int, int, const InjEnt *, const Contrib *,
@@ -54,6 +56,66 @@ hipError_t launch_fwd2d_t2(int, const ShotDev *shots, const Tile2D *, int, int, 
     const ShotDev &U = SIM.other(shots);
     SIM.lev_of[U.fld[(n + 1) & 1]] = n + 1;
     SIM.lev_of[U.fld[(n + 2) & 1]] = n + 2;
+    SIM.fsteps.push_back(n);
+    SIM.fsteps.push_back(n + 1);
+    return hipSuccess;
+}
+hipError_t launch_fwd2d_t3(int, const ShotDev *shots, const Tile2D *, int, int, const InjEnt *, const Contrib *,
+                           int n, hipStream_t)
+{
+    const ShotDev &T = SIM.tab(shots);
+    if (SIM.lev_of[T.fld[n & 1]] != n || SIM.lev_of[T.fld[(n + 1) & 1]] != n - 1) ++SIM.errors;
+    SIM.lev_of[T.fld[4 + (n & 1)]] = n + 2;
+    SIM.lev_of[T.fld[4 + ((n + 1) & 1)]] = n + 3;
+    for (int i = 0; i < 3; ++i) SIM.fsteps.push_back(n + i);
+    return hipSuccess;
+}
+hipError_t launch_inj_set(const ShotDev *shots, const InjEnt *, int, int, const Contrib *, int step, hipStream_t)
+{
+    const ShotDev &T = SIM.tab(shots);
+    SIM.mu_of[T.fld[2 + (step & 1)]] = step;
+    SIM.mu_of[T.fld[2 + ((step + 1) & 1)]] = step + 1;  // zero: cleared with the job's fields
+    return hipSuccess;
+}
+// Reverse steps read p^k, p^{k+1}, mu^{k+1}, mu^{k+2} from the current set.
+static void rev_reads(const ShotDev &T, int k)
+{
+    if (SIM.lev_of[T.fld[k & 1]] != k || SIM.lev_of[T.fld[(k + 1) & 1]] != k + 1) ++SIM.errors;
+    if (SIM.mu_of[T.fld[2 + ((k + 1) & 1)]] != k + 1 || SIM.mu_of[T.fld[2 + (k & 1)]] != k + 2) ++SIM.errors;
+}
+hipError_t launch_rev2d(int, int, bool, const ShotDev *shots, const Tile2D *, int, int, const InjEnt *,
+                        const Contrib *, int k, int, float *, hipStream_t)
+{
+    const ShotDev &T = SIM.tab(shots);
+    rev_reads(T, k);
+    SIM.lev_of[T.fld[(k + 1) & 1]] = k - 1;
+    SIM.mu_of[T.fld[2 + (k & 1)]] = k;
+    SIM.rsteps.push_back(k);
+    return hipSuccess;
+}
+hipError_t launch_rev2d_t2(int, const ShotDev *shots, const Tile2D *, int, int, const InjEnt *, const Contrib *,
+                           int k, int, hipStream_t)
+{
+    const ShotDev &T = SIM.tab(shots);
+    rev_reads(T, k);
+    SIM.lev_of[T.fld[4 + ((k + 1) & 1)]] = k - 1;
+    SIM.lev_of[T.fld[4 + (k & 1)]] = k - 2;
+    SIM.mu_of[T.fld[6 + (k & 1)]] = k;
+    SIM.mu_of[T.fld[6 + ((k + 1) & 1)]] = k - 1;
+    SIM.rsteps.push_back(k);
+    SIM.rsteps.push_back(k - 1);
+    return hipSuccess;
+}
+hipError_t launch_rev2d_t3(int, const ShotDev *shots, const Tile2D *, int, int, const InjEnt *, const Contrib *,
+                           int k, int, hipStream_t)
+{
+    const ShotDev &T = SIM.tab(shots);
+    rev_reads(T, k);
+    SIM.lev_of[T.fld[4 + (k & 1)]] = k - 2;
+    SIM.lev_of[T.fld[4 + ((k + 1) & 1)]] = k - 3;
+    SIM.mu_of[T.fld[6 + ((k + 1) & 1)]] = k - 1;
+    SIM.mu_of[T.fld[6 + (k & 1)]] = k - 2;
+    for (int i = 0; i < 3; ++i) SIM.rsteps.push_back(k - i);
     return hipSuccess;
 }
 hipError_t launch_snap_store(const ShotDev *shots, int shot, int lev, int64_t ninterior, float *out, hipStream_t)
@@ -97,11 +159,16 @@ static long g_bad = 0;
     } while (0)
 
 // Every entry of a tile's own lists lies in the cells the tile owns and
-// appears once; every first-step entry of a two-step tile lies in its strip
-// span and rows [z0 - 4, z1 + 4), sorted by row.
+// appears once; every first-step entry of a tile of S > 1 steps lies in its
+// strip span and rows [z0 - 4 (S - 1), z1 + 4 (S - 1)), every second-step
+// entry (S = 3) in the span and rows [z0 - 4, z1 + 4), sorted by row; and
+// every node lies in the first- and second-step lists of each tile whose
+// regions contain it.
 static void check_entries(const Job &J, const Tiling &T, const char *name)
 {
     const int span = 64 * T.tune.vec;
+    const int off = T.ndim == 2 && T.steps > 1 ? 4 * (T.steps - 1) : 0;
+    std::set<std::tuple<int, int, int, int, int>> listed;  // (tile, kind, z, y, x)
     for (int t = 0; t < T.count(); ++t) {
         auto lists = [&](int b, int e, int kind) {
             std::set<std::tuple<int, int, int>> seen;
@@ -117,14 +184,18 @@ static void check_entries(const Job &J, const Tiling &T, const char *name)
                           E.z >= tl.z0 && E.z < tl.z1 && E.x < g.NX && E.y < g.NY;
                 } else {
                     const Tile2D &tl = T.tiles[t];
+                    const int ext = kind >= 4 ? 4 : off;
                     if (kind >= 2)
-                        own = E.x >= tl.x0 && E.x < tl.x0 + span && E.z >= tl.z0 - 4 && E.z < tl.z1 + 4;
-                    else if (T.two_step)
-                        own = E.x >= tl.x0 + 4 && E.x < tl.x0 + span - 4 && E.z >= tl.z0 && E.z < tl.z1 && E.x < g.NX;
+                        own = off > 0 && (kind < 4 || T.steps == 3) && E.x >= tl.x0 && E.x < tl.x0 + span &&
+                              E.z >= tl.z0 - ext && E.z < tl.z1 + ext;
+                    else if (off > 0)
+                        own = E.x >= tl.x0 + off && E.x < tl.x0 + span - off && E.z >= tl.z0 && E.z < tl.z1 &&
+                              E.x < g.NX;
                     else
                         own = E.x >= tl.x0 && E.x < tl.x0 + span * T.tune.tx && E.z >= tl.z0 && E.z < tl.z1 &&
                               E.x < g.NX;
-                    if (kind >= 2 && i > b) CHECK(T.ents[i - 1].z <= E.z, "%s: first-step list unsorted", name);
+                    if (kind >= 2 && i > b) CHECK(T.ents[i - 1].z <= E.z, "%s: step list unsorted", name);
+                    listed.insert(std::make_tuple(t, kind, E.z, E.y, E.x));
                 }
                 CHECK(own, "%s tile %d kind %d: node (%d,%d,%d) not in the tile", name, t, kind, E.z, E.y, E.x);
                 CHECK(E.cbeg >= 0 && E.cend <= (int)T.cont.size() && E.cbeg < E.cend, "%s: bad contributions", name);
@@ -140,7 +211,29 @@ static void check_entries(const Job &J, const Tiling &T, const char *name)
             lists(tl.rbeg, tl.rend, 1);
             lists(tl.s1beg, tl.s1end, 2);
             lists(tl.r1beg, tl.r1end, 3);
+            lists(tl.s2beg, tl.s2end, 4);
+            lists(tl.r2beg, tl.r2end, 5);
         }
+    }
+    if (off == 0) return;
+    // completeness: each owned node, in every tile of its shot whose step
+    // regions contain it
+    for (int t = 0; t < T.count(); ++t) {
+        const Tile2D &tl = T.tiles[t];
+        for (int kind = 0; kind < 2; ++kind)
+            for (int i = kind == 0 ? tl.sbeg : tl.rbeg; i < (kind == 0 ? tl.send : tl.rend); ++i) {
+                const InjEnt &E = T.ents[i];
+                for (int u = 0; u < T.count(); ++u) {
+                    const Tile2D &o = T.tiles[u];
+                    if (o.shot != tl.shot || E.x < o.x0 || E.x >= o.x0 + span) continue;
+                    if (E.z >= o.z0 - off && E.z < o.z1 + off)
+                        CHECK(listed.count(std::make_tuple(u, kind + 2, E.z, E.y, E.x)),
+                              "%s: node (%d,%d) missing from tile %d's first-step list", name, E.z, E.x, u);
+                    if (T.steps == 3 && E.z >= o.z0 - 4 && E.z < o.z1 + 4)
+                        CHECK(listed.count(std::make_tuple(u, kind + 4, E.z, E.y, E.x)),
+                              "%s: node (%d,%d) missing from tile %d's second-step list", name, E.z, E.x, u);
+                }
+            }
     }
 }
 
@@ -262,22 +355,69 @@ static void storage_schedule(int ndim, int nt, int stride, int phase, int steps)
           SIM.errors);
 }
 
+// RTM launch schedule for S steps per launch: the forward launches take
+// steps 0 .. nt - 1 in order, each reading the levels it needs; the reverse
+// launches take steps nt - 1 .. 0 in order, each reading p^k, p^{k+1},
+// mu^{k+1}, mu^{k+2} from where the previous launches left them.
+static void rtm_schedule(int nt, int steps)
+{
+    rtm_grid_t gr{2, 6, 40, 1, 23, 10.0};
+    GridInfo g;
+    grid_info(&gr, &g);
+    rtm_set_steps_per_launch(RTM_OP_MODEL, steps);
+    rtm_set_steps_per_launch(RTM_OP_RTM, steps);
+    float src[3] = {17.3f, 0.f, 3.7f};
+    std::vector<float> rec;
+    for (int i = 0; i < 10; ++i) {
+        rec.push_back(0.5f + 3.7f * i);
+        rec.push_back(0.f);
+        rec.push_back(2.25f);
+    }
+    Job J;
+    std::vector<float> fake(1);
+    if (single_job(J, RTM_OP_RTM, g, fake.data(), 1e-3, nt, fake.data(), src, 10, rec.data(), 0)) {
+        CHECK(false, "rtm single_job failed: %s", t_err.c_str());
+        return;
+    }
+    std::vector<char> ws(J.ws.bytes + 256);
+    Dev D{(char *)(((uintptr_t)ws.data() + 255) & ~(uintptr_t)255)};
+    SIM = Sim();
+    fill_shot_devs(J, D, SIM.host);
+    SIM.base = D.at<ShotDev>(J.ws.shots);
+    SIM.lev_of[SIM.host[0].fld[0]] = 0;
+    SIM.lev_of[SIM.host[0].fld[1]] = -1;
+    const int rc = job_launch(J, D, nullptr, nullptr, false);
+    CHECK(rc == 0, "job_launch failed: %s", t_err.c_str());
+    bool ok = (int)SIM.fsteps.size() == nt && (int)SIM.rsteps.size() == nt;
+    for (int i = 0; ok && i < nt; ++i) ok = SIM.fsteps[i] == i && SIM.rsteps[i] == nt - 1 - i;
+    CHECK(ok, "rtm nt %d steps %d: forward %zu / reverse %zu steps out of order", nt, steps, SIM.fsteps.size(),
+          SIM.rsteps.size());
+    CHECK(SIM.errors == 0, "rtm nt %d steps %d: %ld schedule errors", nt, steps, SIM.errors);
+    rtm_set_steps_per_launch(RTM_OP_RTM, 2);
+}
+
 int main()
 {
     int cases = 0;
     for (int vec : {1, 2, 4})
         for (int tx : {1, 2, 4})
-            for (int steps : {1, 2}) {
-                tables(2, vec, tx, 1, steps == 2 ? 9 : 18, steps);
+            for (int steps : {1, 2, 3}) {
+                tables(2, vec, tx, 1, steps > 1 ? 9 : 18, steps);
                 ++cases;
             }
     tables(2, 4, 1, 1, 108, 2);
+    tables(2, 4, 1, 1, 108, 3);
+    for (int steps : {1, 2, 3})
+        for (int nt : {1, 2, 3, 4, 5, 6, 7, 20}) {
+            rtm_schedule(nt, steps);
+            ++cases;
+        }
     for (int vec : {1, 2})
         for (int ty : {4, 8}) {
             tables(3, vec, 1, ty, 18, 1);
             ++cases;
         }
-    for (int steps : {1, 2})
+    for (int steps : {1, 2, 3})
         for (int nt : {1, 2, 7, 8, 31})
             for (auto sp : {std::make_pair(1, 0), std::make_pair(3, 2), std::make_pair(10, 9), std::make_pair(4, 1)}) {
                 storage_schedule(2, nt, sp.first, sp.second, steps);

@@ -191,12 +191,14 @@ def test_tuning_invariance():
         assert np.array_equal(tr, outs[0][0]) and np.array_equal(im, outs[0][1])
 
 
-@pytest.mark.parametrize("nt", [150, 151])
+@pytest.mark.parametrize("nt", [150, 151, 152])
 def test_two_step_launches_bit_identical(nt):
-    """Two time steps per launch (overlapping strips, first step on a 4-cell
-    margin) give the same bits as one step per launch, for modeling (traces
-    and final panels) and RTM (num, den, image), for even and odd nt and
-    several strip widths; off-grid source and receivers near strip joins."""
+    """Two and three time steps per launch (overlapping strips, first step
+    on a 4- or 8-cell margin) give the same bits as one step per launch, for
+    modeling (traces and final panels), RTM (num, den, image) and the
+    gradient (its forward pass takes the multi-step launches), for every
+    nt mod 2 and mod 3 and several strip widths; off-grid source and
+    receivers near strip joins."""
     s = synth.config_small2d(nx=150, nz=41, nb=10, nt=nt)
     g, vg, vo = _setup(s)
     w = _t(s.wavelet)
@@ -204,13 +206,15 @@ def test_two_step_launches_bit_identical(nt):
     rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
     outs = []
     try:
-        for steps, vec, zseg in ((1, 1, 18), (2, 1, 9), (2, 2, 18), (2, 4, 36), (2, 1, 27), (2, 4, 9), (2, 4, 108)):
+        for steps, vec, zseg in ((1, 1, 18), (2, 1, 9), (2, 2, 18), (2, 4, 36), (2, 1, 27), (2, 4, 9), (2, 4, 108),
+                                 (3, 1, 9), (3, 2, 18), (3, 4, 36), (3, 1, 27), (3, 4, 9), (3, 4, 108), (3, 2, 9)):
             for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
                 rtm.rtm_set_tuning2d(op, vec, 1, zseg)
                 rtm.rtm_set_steps_per_launch(op, steps)
             tr, pl, pp = rtm.rtm_model_shot(g, vg, s.dt, w, s.src[0], s.rec, want_last=True)
             out = rtm.rtm_rtm_shot(g, vg, s.dt, w, s.src[0], s.rec, d_obs, want_numden=True)
-            outs.append([_n(tr), _n(pl), _n(pp), _n(out["num"]), _n(out["den"]), _n(out["image"])])
+            gv, gw = rtm.rtm_model_shot_vjp(g, vg, s.dt, w, s.src[0], s.rec, d_obs, want_wavelet_grad=True)
+            outs.append([_n(tr), _n(pl), _n(pp), _n(out["num"]), _n(out["den"]), _n(out["image"]), _n(gv), _n(gw)])
     finally:
         rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 0, 0)
         for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):

@@ -71,7 +71,7 @@ def _check_levels(out, vo, s, w, stride, phase, which):
 
 @pytest.mark.parametrize("name,stride,phase,steps", [
     ("small2d", 1, 0, 2), ("small2d", 10, 0, 1), ("small2d", 10, 0, 2), ("ragged2d", 7, 3, 2),
-    ("ragged2d", 4, 1, 1), ("c1", 10, 0, 2), ("odd2d", 3, 2, 2), ("odd2d", 5, 0, 1)])
+    ("ragged2d", 4, 1, 1), ("c1", 10, 0, 2), ("odd2d", 3, 2, 2), ("odd2d", 5, 0, 1), ("odd2d", 4, 1, 3)])
 def test_storage_shot_parity(name, stride, phase, steps):
     s = _case(name)
     rtm.rtm_set_steps_per_launch(rtm.RTM_OP_MODEL, steps)
