@@ -25,16 +25,16 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes of one reverse launch (48 shots, two steps per launch, shape vec 4,
-# tx 1, zseg 108) from two rocprofv3 counter runs: L2-to-memory read requests
-# by size (TCC_EA0_RDREQ_32B/64B/128B) and write requests (TCC_EA0_WRREQ,
-# TCC_EA0_WRREQ_64B; the rest are 32 B).  A 1 GiB device copy in the same
-# runs reads exactly 8388608 x 128 B and writes 16777216 x 64 B (twice that
-# for the 2 GiB copy of the bandwidth reference), so the
-# request counts are bytes without further scaling.  Valid only for the
-# kernel sources hashed here; reported as null once they change.
-PMC_REVERSE = {"sources_sha256_16": "6d94f9f1835cf946", "shots": 48, "shape": (4, 1, 108), "steps": 2,
-               "read_bytes": 24296201 * 128 + 10787 * 64, "write_bytes": 35718454 * 64 + (36733250 - 35718454) * 32}
+# HBM bytes of one reverse launch (48 shots, three steps per launch, shape
+# vec 2, tx 1, zseg 108) from two rocprofv3 counter runs: L2-to-memory read
+# requests by size (TCC_EA0_RDREQ_32B/64B/128B) and write requests
+# (TCC_EA0_WRREQ, TCC_EA0_WRREQ_64B; the rest are 32 B).  A 1 GiB device copy
+# in the same runs reads exactly 8388608 x 128 B and writes 16777216 x 64 B
+# (twice that for the 2 GiB copy of the bandwidth reference), so the request
+# counts are bytes without further scaling.  Valid only for the kernel
+# sources hashed here; reported as null once they change.
+PMC_REVERSE = {"sources_sha256_16": "2a21947e5a883b36", "shots": 48, "shape": (2, 1, 108), "steps": 3,
+               "read_bytes": 29106726 * 128 + 18889 * 64, "write_bytes": 36436740 * 64 + (36676552 - 36436740) * 32}
 KERNEL_SOURCES = ("prop2d.hip", "stencil.h", "common.h")
 
 

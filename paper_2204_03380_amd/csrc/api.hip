@@ -610,11 +610,15 @@ int64_t count_tiles(const Job &J, Tune t)
 // shot of a modest grid) would leave most of the 256 CUs idle, so the shape
 // is narrowed (fewer rows per tile first, then fewer floats per lane) until
 // the job has at least kMinWaves wavefronts or the smallest shape is
-// reached.  Results do not depend on the shape.
+// reached.  Such a job is latency-bound, where the wider overlaps of three
+// steps per launch cost more than the traffic they save, so it takes two
+// (a single 2301 x 751 shot: 25.1 us per step against 27.1 or more with
+// three, whatever the narrowed shape).  Results do not depend on the shape.
 constexpr int64_t kMinWaves = 256 * 16;
 
 Tune fit_tune(const Job &J, Tune t)
 {
+    if (!g_tune_exact.load() && t.steps > 2 && count_tiles(J, t) < kMinWaves) t.steps = 2;
     while (!g_tune_exact.load() && count_tiles(J, t) < kMinWaves) {
         if (t.zseg > kMinZseg) t.zseg = std::max(kMinZseg, t.zseg / 2 / kZUnroll * kZUnroll);
         else if (t.ty > 4) t.ty = 4;
