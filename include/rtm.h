@@ -141,13 +141,15 @@ int rtm_get_tuning2d(int op, int *vec, int *tx, int *zseg);
  * (strips overlap by 8 columns), and the two new levels go to a second set
  * of field buffers, so the level pairs cross HBM once per two steps.  With
  * 3 the strips overlap by 16 columns, the middle level stays in registers
- * and the last two levels are stored: the pairs cross HBM once per three
- * steps.  RTM_OP_MODEL sets it for every forward pass (modeling and the
- * forward pass of RTM and VJP jobs; modeling and storage RTM, which need
- * every level in memory, take 2 when 3 is set), RTM_OP_RTM for the imaging
- * reverse pass (the gradient pass and probed runs always take one step per
- * launch; the last nt mod S steps are taken one at a time).  Results are
- * bit-identical whatever the setting.  Returns RTM_EINVAL for other values. */
+ * (modeling stores it on the receiver rows only) and the last two levels
+ * are stored: the pairs cross HBM once per three steps.  RTM_OP_MODEL sets
+ * it for every forward pass (modeling and the forward pass of RTM and VJP
+ * jobs; storage RTM, which copies whole levels, takes 2 when 3 is set; a
+ * job too small to fill the GPU takes 2 unless RTM_TUNE_EXACT is set),
+ * RTM_OP_RTM for the imaging reverse pass (the gradient pass and probed
+ * runs always take one step per launch; the last nt mod S steps are taken
+ * one at a time).  Results are bit-identical whatever the setting.
+ * Returns RTM_EINVAL for other values. */
 int rtm_set_steps_per_launch(int op, int steps);
 int rtm_get_steps_per_launch(int op, int *steps);
 

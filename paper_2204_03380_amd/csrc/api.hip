@@ -32,7 +32,8 @@ hipError_t launch_fwd2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, i
 hipError_t launch_rev2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                            const InjEnt *ents, const Contrib *cont, int k, int reinject, hipStream_t st);
 hipError_t launch_fwd2d_t3(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
-                           const InjEnt *ents, const Contrib *cont, int n, hipStream_t st);
+                           const InjEnt *ents, const Contrib *cont, const SampleTask *stasks, int nsample, int n,
+                           hipStream_t st);
 hipError_t launch_rev2d_t3(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                            const InjEnt *ents, const Contrib *cont, int k, int reinject, hipStream_t st);
 hipError_t launch_recv2d(int vec, int tx, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
@@ -59,7 +60,7 @@ hipError_t launch_unpack(const Layout &L, const float *f, float *out, hipStream_
 hipError_t launch_transpose(const float *in, float *out, int64_t R, int64_t C, hipStream_t st);
 hipError_t launch_inj_set(const ShotDev *shots, const InjEnt *ents, int ebeg, int eend, const Contrib *cont, int step,
                           hipStream_t st);
-hipError_t launch_sample(const ShotDev *shots, const SampleTask *stasks, int ntask, int n, hipStream_t st);
+hipError_t launch_sample(const ShotDev *shots, const SampleTask *stasks, int ntask, int n, int slot, hipStream_t st);
 hipError_t launch_image(const ShotDev *shots, int shot, int64_t ninterior, unsigned *dmax_bits, float eps_rel,
                         float *image, int accumulate, float *num, float *den, hipStream_t st);
 hipError_t launch_grad(const ShotDev *shots, int shot, int64_t npad, const float *v_pad, float dt, float *grad,
@@ -336,6 +337,7 @@ struct Job {
     std::vector<int> rnode;
     std::vector<float> rw;
     std::vector<int64_t> rbase;      // per shot: offset of its receivers in rnode / rw (in receivers)
+    std::vector<std::array<int, 2>> srows;  // per shot: padded rows [lo, hi) holding receiver nodes
     std::vector<int> dslot;          // per shot: D' slot
     std::vector<int> slot_shot;      // per slot: first shot using it
     WsLayout ws;
@@ -349,8 +351,10 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Field buffers per shot: p (2 levels) and mu (2 levels); 2-D jobs keep a
 // second set for the multi-step kernels, so that the workspace size does not
-// depend on the launch shape.
-int nfields(int op, int ndim) { return (op == RTM_OP_MODEL ? 2 : 4) * (ndim == 2 ? 2 : 1); }
+// depend on the launch shape.  2-D modeling keeps, in the mu slot 2 of each
+// set, the middle level that three-step launches store on the receiver rows.
+int per_set(int op, int ndim) { return op == RTM_OP_MODEL ? (ndim == 2 ? 3 : 2) : 4; }
+int nfields(int op, int ndim) { return per_set(op, ndim) * (ndim == 2 ? 2 : 1); }
 int nfields(const Job &J) { return nfields(J.op, J.shots.empty() ? 3 : J.shots[0].g.ndim); }
 // Ops with the imaging sums num (acc0) and den (acc1).
 bool has_den(int op) { return op == RTM_OP_RTM || op == RTM_OP_STORAGE; }
@@ -392,9 +396,10 @@ WsLayout make_ws_layout(const Job &J, const Counts &c)
         const ShotIn &S = J.shots[i];
         const int64_t F = S.g.L.total;
         // fields 0..3: first set (p, p, mu, mu), 4..7: second set; a
-        // modeling job has only the two p levels of each set
+        // modeling job has the two p levels of each set (and in 2-D the
+        // middle-level slot 2)
         std::array<size_t, 8> f{0, 0, 0, 0, 0, 0, 0, 0};
-        const int per = J.op == RTM_OP_MODEL ? 2 : 4;  // fields per set
+        const int per = per_set(J.op, S.g.ndim);  // fields per set
         for (int k = 0; k < nf; ++k) f[(k / per) * 4 + k % per] = take(sizeof(float) * F);
         w.fld.push_back(f);
         w.acc0.push_back(J.op == RTM_OP_MODEL ? 0 : take(sizeof(float) * F));
@@ -635,12 +640,14 @@ int build_job_tables(Job &J)
     J.rnode.clear();
     J.rw.clear();
     J.rbase.clear();
+    J.srows.clear();
     J.dslot.clear();
     J.slot_shot.clear();
     int64_t base = 0;
     for (int s = 0; s < (int)J.shots.size(); ++s) {
         const ShotIn &S = J.shots[s];
         J.rbase.push_back(base);
+        std::array<int, 2> rows{1 << 30, 0};
         for (int r = 0; r < S.nrec; ++r) {
             PointOp rp;
             if (!make_point(S.g, &S.rec[3 * (size_t)r], &rp))
@@ -648,6 +655,8 @@ int build_job_tables(Job &J)
                             S.rec[3 * r], S.rec[3 * r + 1], S.rec[3 * r + 2]);
             for (int q = 0; q < kMaxNodes; ++q) {
                 if (q < rp.n) {
+                    rows[0] = std::min(rows[0], rp.z[q]);
+                    rows[1] = std::max(rows[1], rp.z[q] + 1);
                     J.rnode.push_back((int)((int64_t)rp.z[q] * S.g.L.plane + (int64_t)rp.y[q] * S.g.L.pitch + rp.x[q]));
                     J.rw.push_back((float)rp.w[q]);
                 } else {
@@ -657,6 +666,7 @@ int build_job_tables(Job &J)
             }
         }
         base += S.nrec;
+        J.srows.push_back(rows[1] > rows[0] ? rows : std::array<int, 2>{0, 0});
         for (int r0 = 0; r0 < S.nrec; r0 += 64) J.stasks.push_back(SampleTask{s, r0});
         int slot = -1;
         for (int d = 0; d < (int)J.slot_shot.size(); ++d) {
@@ -685,15 +695,14 @@ int build_job_tables(Job &J)
     }
     // Multi-step tilings (2-D): the forward one for every op, the reverse
     // one for imaging only (the gradient pass runs one step per launch).
-    // Three steps per launch never store the middle level, so modeling
-    // (which samples every level) and storage RTM (which copies stored
-    // levels) take two.
+    // Three steps per launch store the middle level only on the receiver
+    // rows, so storage RTM (which copies whole stored levels) takes two.
     J.fw2 = Tiling{};
     J.rv2 = Tiling{};
     J.fw2.ndim = J.rv2.ndim = ndim;
     if (ndim == 2 && J.fw.tune.steps >= 2) {
         J.fw2.tune = J.fw.tune;
-        J.fw2.steps = (J.op == RTM_OP_MODEL || J.op == RTM_OP_STORAGE) ? 2 : J.fw.tune.steps;
+        J.fw2.steps = J.op == RTM_OP_STORAGE ? 2 : J.fw.tune.steps;
         if ((rc = build_tiling(J, J.fw2, false))) return rc;
     }
     if (ndim == 2 && J.op == RTM_OP_RTM && J.rv.tune.steps >= 2) {
@@ -786,6 +795,8 @@ void fill_shot_devs(const Job &J, const Dev &D, std::vector<ShotDev> &out)
         d.iy1 = S.g.ndim == 3 ? S.g.nb + (int)S.g.ny : 1;
         d.iz0 = S.g.nb;
         d.iz1 = S.g.nb + (int)S.g.nz;
+        d.sz0 = J.srows[i][0];
+        d.sz1 = J.srows[i][1];
         d.L = S.g.L;
         ShotDev &x = out[nsh + i];
         x = d;
@@ -873,7 +884,9 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
     // must have a buffer.
     for (int i = 0; i < nsh; ++i) {
         const bool need_p = J.fw2.steps > 1 || J.rv2.steps > 1, need_mu = J.rv2.steps > 1;
-        if ((need_p && !(J.ws.fld[i][4] && J.ws.fld[i][5])) || (need_mu && !(J.ws.fld[i][6] && J.ws.fld[i][7])))
+        const bool need_mid = J.op == RTM_OP_MODEL && J.fw2.steps == 3;
+        if ((need_p && !(J.ws.fld[i][4] && J.ws.fld[i][5])) || (need_mu && !(J.ws.fld[i][6] && J.ws.fld[i][7])) ||
+            (need_mid && !(J.ws.fld[i][2] && J.ws.fld[i][6])))
             return fail(RTM_EINVAL, "internal: shot %d lacks the second field set of multi-step launches", i);
     }
     for (int d = 0; d < (int)J.slot_shot.size(); ++d) {
@@ -917,11 +930,19 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
         int rc = RTM_OK;
         int n = 0;
         if (fs == 3) {
-            // steps n .. n + 2 per launch (no sampling, no stored levels)
+            // steps n .. n + 2 per launch; each launch records d^{n-2},
+            // d^{n-1}, d^n (no stored levels: not for storage RTM)
             for (; n + 3 <= nt; n += 3) {
                 RTM_HIP(launch_fwd2d_t3(J.fw2.tune.vec, SH(), D.at<Tile2D>(J.ws.tiles_f2), J.fw2.count(),
-                                        J.fw2.nslots, D.at<InjEnt>(J.ws.ents_f2), D.at<Contrib>(J.ws.cont_f2), n, st));
+                                        J.fw2.nslots, D.at<InjEnt>(J.ws.ents_f2), D.at<Contrib>(J.ws.cont_f2),
+                                        sample ? stasks : nullptr, nsample, n, st));
                 cur ^= 1;
+            }
+            // the last launch's middle level (field 6 of the current table)
+            // and level n - 1, which a one-step launch would overwrite
+            if (sample && n >= 3) {
+                RTM_HIP(launch_sample(SH(), stasks, nsample, n - 2, 6, st));
+                RTM_HIP(launch_sample(SH(), stasks, nsample, n - 1, (n - 1) & 1, st));
             }
         } else if (two) {
             // steps n, n + 1 per launch; each launch records d^{n-1}, d^n
@@ -934,7 +955,7 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
                 if ((rc = keep(n + 1))) return rc;
             }
             // an odd last step overwrites level n - 1: record it first
-            if (sample && n < nt && n >= 1) RTM_HIP(launch_sample(SH(), stasks, nsample, n - 1, st));
+            if (sample && n < nt && n >= 1) RTM_HIP(launch_sample(SH(), stasks, nsample, n - 1, (n - 1) & 1, st));
         }
         for (; n < nt; ++n) {
             if ((rc = keep(n))) return rc;
@@ -947,8 +968,9 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
         }
         timer.finish();
         if (sample) {
-            if (fs == 2 && nt % 2 == 0 && nt >= 2) RTM_HIP(launch_sample(SH(), stasks, nsample, nt - 1, st));
-            RTM_HIP(launch_sample(SH(), stasks, nsample, nt, st));
+            if (fs == 2 && nt % 2 == 0 && nt >= 2)
+                RTM_HIP(launch_sample(SH(), stasks, nsample, nt - 1, (nt - 1) & 1, st));
+            RTM_HIP(launch_sample(SH(), stasks, nsample, nt, nt & 1, st));
         }
     }
     if (J.op == RTM_OP_MODEL) {

@@ -255,13 +255,14 @@ __global__ void inj_set_kernel(const ShotDev *__restrict__ shots, const InjEnt *
 }
 
 // d^n = R p^n for all receivers of every shot (used for the last sample).
-__global__ void sample_kernel(const ShotDev *__restrict__ shots, const SampleTask *__restrict__ stasks, int n)
+__global__ void sample_kernel(const ShotDev *__restrict__ shots, const SampleTask *__restrict__ stasks, int n,
+                              int slot)
 {
     const SampleTask task = stasks[blockIdx.x];
     const ShotDev &S = shots[task.shot];
     const int r = task.r0 + (int)threadIdx.x;
     if (r >= S.nrec) return;
-    const float *p = S.fld[n & 1] + S.L.org;
+    const float *p = S.fld[slot] + S.L.org;
     float s = 0.f;
     for (int q = 0; q < kMaxNodes; ++q) s = fmaf(S.rw[r * kMaxNodes + q], p[S.rnode[r * kMaxNodes + q]], s);
     S.rec_out[(int64_t)n * S.nrec + r] = s;
@@ -500,10 +501,10 @@ hipError_t launch_inj_set(const ShotDev *shots, const InjEnt *ents, int ebeg, in
     return hipGetLastError();
 }
 
-hipError_t launch_sample(const ShotDev *shots, const SampleTask *stasks, int ntask, int n, hipStream_t st)
+hipError_t launch_sample(const ShotDev *shots, const SampleTask *stasks, int ntask, int n, int slot, hipStream_t st)
 {
     if (ntask <= 0) return hipSuccess;
-    hipLaunchKernelGGL(sample_kernel, dim3(ntask), dim3(64), 0, st, shots, stasks, n);
+    hipLaunchKernelGGL(sample_kernel, dim3(ntask), dim3(64), 0, st, shots, stasks, n, slot);
     return hipGetLastError();
 }
 

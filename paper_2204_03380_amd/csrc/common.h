@@ -77,6 +77,7 @@ struct ShotDev {
     const float *rw;    // [nrec][kMaxNodes] interpolation weights (0 = unused)
     int nrec;
     int ix0, ix1, iy0, iy1, iz0, iz1;  // interior box, padded coordinates [lo, hi)
+    int sz0, sz1;       // padded rows [sz0, sz1) holding receiver nodes (2-D)
     Layout L;
 };
 

@@ -215,7 +215,7 @@ __global__ __launch_bounds__(64 * TX) void fwd2d_kernel(const ShotDev *__restric
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (b >= nslots) {
         const int task = (b - nslots) * TX + w;
-        if (task < nsample) sample_body(shots, stasks[task], n, lane);
+        if (task < nsample) sample_body(shots, stasks[task], n, n & 1, lane);
         return;
     }
     const int t = xcd_tile(b, nslots);
@@ -533,7 +533,7 @@ __global__ __launch_bounds__(64) void fwd2d_t2_kernel(const ShotDev *__restrict_
     if (b >= nslots) {
         const int t = b - nslots;
         const int level = t < nsample ? n - 1 : n;
-        if (level >= 0) sample_body(shots, stasks[t < nsample ? t : t - nsample], level, lane);
+        if (level >= 0) sample_body(shots, stasks[t < nsample ? t : t - nsample], level, level & 1, lane);
         return;
     }
     const int t = xcd_tile(b, nslots);
@@ -853,10 +853,11 @@ void rev2d_t2_kernel(const ShotDev *__restrict__ shots,
 // two's centre row r1 - 4 sits in slot S and step three's r1 - 8 in slot
 // (S + 5) % 9.  Steps one and two add their sources in the march (their
 // values feed the next step); step three's are added after the march by
-// the owner.  Only the last two levels are stored: level n + 1 never leaves
-// the registers, so the launch reads two levels and D' and writes two
-// levels once per three steps.  Every cell's arithmetic equals the one-step
-// kernel's, operation for operation.
+// the owner.  Only the last two levels are stored: level n + 1 leaves the
+// registers only on the rows that hold receiver nodes (modeling), so the
+// launch reads two levels and D' and writes two levels once per three
+// steps.  Every cell's arithmetic equals the one-step kernel's, operation
+// for operation.
 template <int VEC>
 __device__ __forceinline__ bool own3(int x, int xs, int NX)
 {
@@ -884,12 +885,13 @@ template <int VEC>
 struct Fwd3Ctx {
     const gfloat *pc, *pm;  // p^n, p^{n-1} (read set)
     gfloat *w2, *w3;        // p^{n+2}, p^{n+3} (write set)
+    gfloat *mid;            // p^{n+1} on the receiver rows (modeling)
     const gfloat *Dp;
     const float *wav;       // wavelet from time n
     const InjEnt *ents;
     const Contrib *cont;
     int64_t pitch;
-    int x, xs, NX, NZr, lane, z0, z1, e1end, e2end;
+    int x, xs, NX, NZr, lane, z0, z1, e1end, e2end, m0, m1;  // [m0, m1): rows of p^{n+1} to store
     bool live, own;
 };
 
@@ -936,6 +938,7 @@ __device__ __forceinline__ void fwd3_row(const Fwd3Ctx<VEC> &C, float (&q1)[9][V
         q2[a4][j] = v1[j];
         qd[a4][j] = d[j];
     }
+    if (C.own && r1 >= C.m0 && r1 < C.m1) stv<VEC>(C.mid + o1, v1);
     const float hz[4] = {0.f, 0.f, 0.f, 0.f};
     if (s >= 8 && r2 < C.z1 + 4) {
         exchange_row<VEC>(q2[a0], hz, hz, ext);
@@ -972,19 +975,32 @@ __device__ __forceinline__ void fwd3_row(const Fwd3Ctx<VEC> &C, float (&q1)[9][V
     }
 }
 
-// Steps n, n + 1 and n + 2 of every tile (no receiver sampling: level n + 1
-// is not stored).
+// Steps n, n + 1 and n + 2 of every tile.  With receiver sampling
+// (nsample > 0), the tiles also store p^{n+1} on the receiver rows into
+// field 2 of the shot (a modeling job's spare slot), and the workgroups
+// past the stencil slots record d^{n-2} (n >= 3: the previous launch's
+// middle level, in field 6, the same buffer seen from the exchanged set),
+// d^{n-1} (n > 0) and d^n from the read set.
 template <int VEC>
 __global__ __launch_bounds__(64) void fwd2d_t3_kernel(const ShotDev *__restrict__ shots,
                                                       const Tile2D *__restrict__ tiles, int ntiles, int nslots,
                                                       const InjEnt *__restrict__ ents,
-                                                      const Contrib *__restrict__ cont, int n)
+                                                      const Contrib *__restrict__ cont,
+                                                      const SampleTask *__restrict__ stasks, int nsample, int n)
 {
-    const int t = xcd_tile(blockIdx.x, nslots);
+    const int b = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (b >= nslots) {
+        const int t = b - nslots, g = t / nsample;  // g = 0, 1, 2: levels n - 2, n - 1, n
+        const int level = n - 2 + g;
+        if (level >= 0 && (g > 0 || n >= 3))
+            sample_body(shots, stasks[t - g * nsample], level, g == 0 ? 6 : (level & 1), lane);
+        return;
+    }
+    const int t = xcd_tile(b, nslots);
     if (t >= ntiles) return;
     const Tile2D T = tiles[t];
     const ShotDev &S = shots[T.shot];
-    const int lane = threadIdx.x;
     Fwd3Ctx<VEC> C;
     C.pitch = S.L.pitch;
     C.NX = S.L.NX;
@@ -993,6 +1009,9 @@ __global__ __launch_bounds__(64) void fwd2d_t3_kernel(const ShotDev *__restrict_
     C.pm = gp(S.fld[(n + 1) & 1] + S.L.org);
     C.w2 = gp(S.fld[4 + (n & 1)] + S.L.org);
     C.w3 = gp(S.fld[4 + ((n + 1) & 1)] + S.L.org);
+    C.mid = nsample > 0 ? gp(S.fld[2] + S.L.org) : nullptr;
+    C.m0 = nsample > 0 ? max(T.z0, S.sz0) : 0;
+    C.m1 = nsample > 0 ? min(T.z1, S.sz1) : 0;
     C.Dp = gp(S.Dp + S.L.org);
     C.wav = S.wav + n;
     C.ents = ents;
@@ -1407,13 +1426,14 @@ hipError_t launch_rev2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, i
 }
 
 hipError_t launch_fwd2d_t3(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
-                           const InjEnt *ents, const Contrib *cont, int n, hipStream_t st)
+                           const InjEnt *ents, const Contrib *cont, const SampleTask *stasks, int nsample, int n,
+                           hipStream_t st)
 {
-    dim3 grid(nslots), block(64);
+    dim3 grid(nslots + 3 * nsample), block(64);
     switch (vec) {
-    case 1: hipLaunchKernelGGL(fwd2d_t3_kernel<1>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, n); break;
-    case 2: hipLaunchKernelGGL(fwd2d_t3_kernel<2>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, n); break;
-    case 4: hipLaunchKernelGGL(fwd2d_t3_kernel<4>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, n); break;
+    case 1: hipLaunchKernelGGL(fwd2d_t3_kernel<1>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, stasks, nsample, n); break;
+    case 2: hipLaunchKernelGGL(fwd2d_t3_kernel<2>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, stasks, nsample, n); break;
+    case 4: hipLaunchKernelGGL(fwd2d_t3_kernel<4>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, stasks, nsample, n); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

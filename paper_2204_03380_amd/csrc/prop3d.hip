@@ -272,7 +272,7 @@ __global__ __launch_bounds__(64 * TY) void fwd3d_kernel(const ShotDev *__restric
     const int b = blockIdx.x;
     if (b >= nslots) {
         const int task = (b - nslots) * TY + (int)(threadIdx.x >> 6);
-        if (task < nsample) sample_body(shots, stasks[task], n, (int)(threadIdx.x & 63));
+        if (task < nsample) sample_body(shots, stasks[task], n, n & 1, (int)(threadIdx.x & 63));
         return;
     }
     const int t = xcd_tile(b, nslots);

@@ -230,13 +230,15 @@ __device__ __forceinline__ void ring_get(const EdgeRing<TX> &R, int s, int w, in
     }
 }
 
-// Receivers [r0, r0 + 64) of one shot: d[n][r] = sum_q w_q p^n[node_q].
-__device__ __forceinline__ void sample_body(const ShotDev *__restrict__ shots, SampleTask task, int n, int lane)
+// Receivers [r0, r0 + 64) of one shot: d[n][r] = sum_q w_q p^n[node_q],
+// with p^n held by field `slot` of the shot.
+__device__ __forceinline__ void sample_body(const ShotDev *__restrict__ shots, SampleTask task, int n, int slot,
+                                            int lane)
 {
     const ShotDev &S = shots[task.shot];
     int r = task.r0 + lane;
     if (r >= S.nrec) return;
-    const gfloat *p = gp(S.fld[n & 1] + S.L.org);
+    const gfloat *p = gp(S.fld[slot] + S.L.org);
     float s = 0.f;
 #pragma unroll
     for (int q = 0; q < kMaxNodes; ++q) {

@@ -20,6 +20,13 @@ struct Sim {
     int nsh = 1;
     std::map<const float *, int> lev_of, mu_of;  // p and mu level held by each field
     std::vector<int> fsteps, rsteps;               // forward and reverse steps, in launch order
+    std::map<int, int> sampled;                    // receiver samples recorded per level
+    // a sample of level n from field `slot` of table T
+    void sample(const ShotDev &T, int n, int slot)
+    {
+        if (lev_of.count(T.fld[slot]) == 0 || lev_of[T.fld[slot]] != n) ++errors;
+        sampled[n]++;
+    }
     float *snaps = nullptr;
     int64_t ncell = 0;
     int stride = 1, phase = 0, last_k = 1 << 30;
@@ -35,24 +42,29 @@ struct Sim {
 } SIM;
 
 hipError_t launch_fwd2d(int, int, const ShotDev *shots, const Tile2D *, int, int, const InjEnt *, const Contrib *,
-                        const SampleTask *, int, int n, hipStream_t)
+                        const SampleTask *stasks, int nsample, int n, hipStream_t)
 {
     const ShotDev &T = SIM.tab(shots);
     if (SIM.lev_of[T.fld[n & 1]] != n) ++SIM.errors;
+    if (stasks && nsample > 0) SIM.sample(T, n, n & 1);
     SIM.lev_of[T.fld[(n + 1) & 1]] = n + 1;
     SIM.fsteps.push_back(n);
     return hipSuccess;
 }
 hipError_t launch_fwd3d(int, int, const ShotDev *shots, const Tile3D *, int, int, const InjEnt *, const Contrib *,
-                        const SampleTask *, int, int n, hipStream_t)
+                        const SampleTask *stasks, int nsample, int n, hipStream_t)
 {
-    return launch_fwd2d(0, 0, shots, nullptr, 0, 0, nullptr, nullptr, nullptr, 0, n, nullptr);
+    return launch_fwd2d(0, 0, shots, nullptr, 0, 0, nullptr, nullptr, stasks, nsample, n, nullptr);
 }
 hipError_t launch_fwd2d_t2(int, const ShotDev *shots, const Tile2D *, int, int, const InjEnt *, const Contrib *,
-                           const SampleTask *, int, int n, hipStream_t)
+                           const SampleTask *stasks, int nsample, int n, hipStream_t)
 {
     const ShotDev &T = SIM.tab(shots);
     if (SIM.lev_of[T.fld[n & 1]] != n) ++SIM.errors;
+    if (stasks && nsample > 0) {
+        if (n > 0) SIM.sample(T, n - 1, (n - 1) & 1);
+        SIM.sample(T, n, n & 1);
+    }
     const ShotDev &U = SIM.other(shots);
     SIM.lev_of[U.fld[(n + 1) & 1]] = n + 1;
     SIM.lev_of[U.fld[(n + 2) & 1]] = n + 2;
@@ -61,13 +73,25 @@ hipError_t launch_fwd2d_t2(int, const ShotDev *shots, const Tile2D *, int, int, 
     return hipSuccess;
 }
 hipError_t launch_fwd2d_t3(int, const ShotDev *shots, const Tile2D *, int, int, const InjEnt *, const Contrib *,
-                           int n, hipStream_t)
+                           const SampleTask *stasks, int nsample, int n, hipStream_t)
 {
     const ShotDev &T = SIM.tab(shots);
     if (SIM.lev_of[T.fld[n & 1]] != n || SIM.lev_of[T.fld[(n + 1) & 1]] != n - 1) ++SIM.errors;
+    if (stasks && nsample > 0) {
+        if (n >= 3) SIM.sample(T, n - 2, 6);
+        if (n >= 1) SIM.sample(T, n - 1, (n - 1) & 1);
+        SIM.sample(T, n, n & 1);
+        if (!T.fld[2] || !T.fld[6] || T.sz1 <= T.sz0) ++SIM.errors;
+        SIM.lev_of[T.fld[2]] = n + 1;  // the middle level, on the receiver rows
+    }
     SIM.lev_of[T.fld[4 + (n & 1)]] = n + 2;
     SIM.lev_of[T.fld[4 + ((n + 1) & 1)]] = n + 3;
     for (int i = 0; i < 3; ++i) SIM.fsteps.push_back(n + i);
+    return hipSuccess;
+}
+hipError_t launch_sample(const ShotDev *shots, const SampleTask *, int ntask, int n, int slot, hipStream_t)
+{
+    if (ntask > 0) SIM.sample(SIM.tab(shots), n, slot);
     return hipSuccess;
 }
 hipError_t launch_inj_set(const ShotDev *shots, const InjEnt *, int, int, const Contrib *, int step, hipStream_t)
@@ -358,12 +382,15 @@ static void storage_schedule(int ndim, int nt, int stride, int phase, int steps)
 // RTM launch schedule for S steps per launch: the forward launches take
 // steps 0 .. nt - 1 in order, each reading the levels it needs; the reverse
 // launches take steps nt - 1 .. 0 in order, each reading p^k, p^{k+1},
-// mu^{k+1}, mu^{k+2} from where the previous launches left them.
+// mu^{k+1}, mu^{k+2} from where the previous launches left them.  Modeling:
+// the same forward order, and every level 0 .. nt recorded exactly once
+// from the field (or middle-level buffer) holding it.
 static void rtm_schedule(int nt, int steps)
 {
     rtm_grid_t gr{2, 6, 40, 1, 23, 10.0};
     GridInfo g;
     grid_info(&gr, &g);
+    rtm_set_tuning(RTM_TUNE_EXACT, 1, 0);  // small jobs would otherwise be narrowed to two steps
     rtm_set_steps_per_launch(RTM_OP_MODEL, steps);
     rtm_set_steps_per_launch(RTM_OP_RTM, steps);
     float src[3] = {17.3f, 0.f, 3.7f};
@@ -393,7 +420,30 @@ static void rtm_schedule(int nt, int steps)
     CHECK(ok, "rtm nt %d steps %d: forward %zu / reverse %zu steps out of order", nt, steps, SIM.fsteps.size(),
           SIM.rsteps.size());
     CHECK(SIM.errors == 0, "rtm nt %d steps %d: %ld schedule errors", nt, steps, SIM.errors);
+    // modeling: every level 0 .. nt recorded once, from the field holding it
+    Job M;
+    if (single_job(M, RTM_OP_MODEL, g, fake.data(), 1e-3, nt, fake.data(), src, 10, rec.data(), 0)) {
+        CHECK(false, "model single_job failed: %s", t_err.c_str());
+        return;
+    }
+    std::vector<char> wm(M.ws.bytes + 256);
+    Dev DM{(char *)(((uintptr_t)wm.data() + 255) & ~(uintptr_t)255)};
+    SIM = Sim();
+    fill_shot_devs(M, DM, SIM.host);
+    SIM.base = DM.at<ShotDev>(M.ws.shots);
+    SIM.lev_of[SIM.host[0].fld[0]] = 0;
+    SIM.lev_of[SIM.host[0].fld[1]] = -1;
+    CHECK(job_launch(M, DM, nullptr, nullptr, false) == 0, "model job_launch failed: %s", t_err.c_str());
+    bool all = (int)SIM.fsteps.size() == nt;
+    for (int i = 0; all && i < nt; ++i) all = SIM.fsteps[i] == i;
+    for (int k = 0; k <= nt; ++k) all = all && SIM.sampled[k] == 1;
+    CHECK(all && (int)SIM.sampled.size() == nt + 1, "model nt %d steps %d: levels not each recorded once", nt,
+          steps);
+    CHECK(SIM.errors == 0, "model nt %d steps %d: %ld schedule errors", nt, steps, SIM.errors);
+    CHECK(M.fw2.steps == (steps > 1 ? steps : 1) && J.rv2.steps == (steps > 1 ? steps : 1),
+          "nt %d: tilings of %d / %d steps, %d asked", nt, M.fw2.steps, J.rv2.steps, steps);
     rtm_set_steps_per_launch(RTM_OP_RTM, 2);
+    rtm_set_tuning(RTM_TUNE_EXACT, 0, 0);
 }
 
 int main()

@@ -13,7 +13,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2204_03380_amd", "csrc")
 RECORDERS = {"launch_fwd2d", "launch_fwd3d", "launch_fwd2d_t2", "launch_fwd2d_t3", "launch_snap_store", "launch_recv2d",
-             "launch_recv3d", "launch_inj_set", "launch_rev2d", "launch_rev2d_t2", "launch_rev2d_t3"}
+             "launch_recv3d", "launch_inj_set", "launch_rev2d", "launch_rev2d_t2", "launch_rev2d_t3", "launch_sample"}
 
 
 def _stubs(api_src):
