@@ -15,6 +15,8 @@
 #include <tuple>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "common.h"
 #include "rtm.h"
 
@@ -168,6 +170,15 @@ std::vector<PendingTiming> g_timing_pending;
 
 // Records an event pair around [begin, end) of a loop on `st`; the pair is
 // resolved later by rtm_timing_read, so no host synchronisation is added.
+// A roctx range over one pass of a job's launch sequence (host time of the
+// enqueues; shown by rocprofv3 --marker-trace, a no-op otherwise).
+struct PassRange {
+    explicit PassRange(const char *name) { roctxRangePushA(name); }
+    ~PassRange() { roctxRangePop(); }
+    PassRange(const PassRange &) = delete;
+    PassRange &operator=(const PassRange &) = delete;
+};
+
 struct LoopTimer {
     hipEvent_t a = nullptr, b = nullptr;
     int kind;
@@ -906,6 +917,7 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
     }
     // Forward pass (Algorithm 1; in RTM only the last two panels are kept).
     {
+        const PassRange pass("rtm:forward");
         const bool sample = J.op == RTM_OP_MODEL;
         const Tile2D *tiles = D.at<Tile2D>(J.ws.tiles_f);
         const InjEnt *ents = D.at<InjEnt>(J.ws.ents_f);
@@ -984,6 +996,7 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
     }
     // Reverse pass (Algorithm 3): mu^{nt} = D' h^2 R^T g^{nt}, mu^{nt+1} = 0,
     // then one fused launch per step k = nt-1 .. 0 (or per pair of steps).
+    const PassRange pass(J.op == RTM_OP_VJP ? "rtm:reverse_grad" : "rtm:reverse_image");
     const bool grad = J.op == RTM_OP_VJP;
     const Tile2D *tiles = D.at<Tile2D>(J.ws.tiles_r);
     const InjEnt *ents = D.at<InjEnt>(J.ws.ents_r);

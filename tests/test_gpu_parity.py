@@ -53,9 +53,12 @@ def _setup(s):
 
 @pytest.fixture(autouse=True)
 def _default_tuning():
+    steps = {op: rtm.rtm_get_steps_per_launch(op) for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM)}
     rtm.rtm_set_tuning2d(rtm.RTM_OP_MODEL, 1, 1, 18)
     rtm.rtm_set_tuning2d(rtm.RTM_OP_RTM, 1, 1, 18)
     yield
+    for op, n in steps.items():  # the library's steps per launch, whatever a test set
+        rtm.rtm_set_steps_per_launch(op, n)
 
 
 # ---------------------------------------------------------------------------
@@ -217,8 +220,6 @@ def test_two_step_launches_bit_identical(nt):
             outs.append([_n(tr), _n(pl), _n(pp), _n(out["num"]), _n(out["den"]), _n(out["image"]), _n(gv), _n(gw)])
     finally:
         rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 0, 0)
-        for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
-            rtm.rtm_set_steps_per_launch(op, 1)
     ref = oracle.rtm_shot(vo, s.h, s.nb, s.dt, s.wavelet.astype(np.float64), s.src[0], s.rec,
                           _n(d_obs).astype(np.float64), eps_rel=1e-3)
     assert rel_l2(outs[0][5], ref["image"]) < TOL
@@ -306,3 +307,37 @@ def test_check_finite_flag():
         rtm.rtm_rtm_shot(g, vg, s.dt, _t(w), s.src[0], s.rec, _t(tbad), flags=rtm.RTM_F_CHECK_FINITE)
     with pytest.raises(rtm.RtmError):
         rtm.rtm_model_shot_vjp(g, vg, s.dt, _t(w), s.src[0], s.rec, _t(tbad), flags=rtm.RTM_F_CHECK_FINITE)
+
+
+@pytest.mark.parametrize("vec,zseg", [(1, 9), (2, 18), (2, 108)])
+def test_three_step_modeling_receiver_rows(vec, zseg):
+    """Three-step modeling keeps the middle level only on the rows holding
+    receiver nodes, per shot: two shots on one grid with receivers on rows
+    that fall in different row tiles (off-grid depths spanning two rows,
+    the top and the last interior row, a single receiver) record the same
+    bits in one three-step batch as one-step single-shot calls."""
+    s = synth.config_small2d(nx=150, nz=41, nb=10, nt=121)
+    g, vg, vo = _setup(s)
+    w = _t(s.wavelet)
+    rec_a = np.array([[x, 0.0, z] for x, z in ((3.0, 0.0), (40.5, 13.75), (77.25, 22.5), (148.0, 40.0),
+                                               (100.0, 5.5), (120.75, 31.0))], np.float64)
+    rec_b = np.array([[61.5, 0.0, 9.25]], np.float64)
+    srcs = (s.src[0], np.array([99.5, 0.0, 20.25]))
+    rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
+    try:
+        rtm.rtm_set_tuning2d(rtm.RTM_OP_MODEL, 1, 1, 18)
+        rtm.rtm_set_steps_per_launch(rtm.RTM_OP_MODEL, 1)
+        ref = [_n(rtm.rtm_model_shot(g, vg, s.dt, w, src, rec)) for src, rec in zip(srcs, (rec_a, rec_b))]
+        rtm.rtm_set_tuning2d(rtm.RTM_OP_MODEL, vec, 1, zseg)
+        rtm.rtm_set_steps_per_launch(rtm.RTM_OP_MODEL, 3)
+        outs = [torch.empty((rec.shape[0], s.nt + 1), device=DEV) for rec in (rec_a, rec_b)]
+        plan = rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, vg, w, src, rec, traces_out=o)
+                                                for src, rec, o in zip(srcs, (rec_a, rec_b), outs)], s.dt, s.nt)
+        plan.run()
+        got = [_n(o) for o in outs]
+    finally:
+        rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 0, 0)
+    for a, b in zip(got, ref):
+        assert np.array_equal(a, b)
+    tr_o = oracle.model_shot(vo, s.h, s.nb, s.dt, s.wavelet.astype(np.float64), srcs[0], rec_a)
+    assert rel_l2(got[0], tr_o) < TOL

@@ -52,7 +52,8 @@ def test_host_tables_layout_and_storage_schedule(tmp_path):
     # link with the same compiler's sanitizer runtimes (host only: no device code in the object)
     clang = os.path.join(rocm, "llvm", "bin", "clang++")
     host_san = ["-fsanitize=address,undefined"]
-    subprocess.run([clang, obj, "-o", exe, *host_san, "-L", libdir, "-lamdhip64", "-Wl,-rpath," + libdir],
+    subprocess.run([clang, obj, "-o", exe, *host_san, "-L", libdir, "-lamdhip64", "-lrocprofiler-sdk-roctx",
+                    "-Wl,-rpath," + libdir],
                    check=True, capture_output=True, text=True)
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
