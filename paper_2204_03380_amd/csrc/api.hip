@@ -626,16 +626,31 @@ int64_t count_tiles(const Job &J, Tune t)
 // shot of a modest grid) would leave most of the 256 CUs idle, so the shape
 // is narrowed (fewer rows per tile first, then fewer floats per lane) until
 // the job has at least kMinWaves wavefronts or the smallest shape is
-// reached.  Such a job is latency-bound, where the wider overlaps of three
-// steps per launch cost more than the traffic they save, so it takes two
-// (a single 2301 x 751 shot: 25.1 us per step against 27.1 or more with
-// three, whatever the narrowed shape).  Results do not depend on the shape.
+// reached.  Results do not depend on the shape.
+//
+// Three steps per launch keep their shape down to kT3Mid wavefronts, take
+// half-height tiles down to kT3Small, and below that (one or two shots of a
+// survey grid, latency-bound) give way to two steps and the narrowing
+// above.  Measured per shot on 2301 x 751 batches (modeling + RTM): 2 shots
+// 26-28 us per step with two steps against 33+ with three; 4 and 8 shots
+// 26 and 18 us with three steps and half-height tiles against 27-29 and
+// 24-31 otherwise; 16 shots and more best at the configured shape.
 constexpr int64_t kMinWaves = 256 * 16;
+constexpr int64_t kT3Mid = 2048, kT3Small = 600;
 
 Tune fit_tune(const Job &J, Tune t)
 {
-    if (!g_tune_exact.load() && t.steps > 2 && count_tiles(J, t) < kMinWaves) t.steps = 2;
-    while (!g_tune_exact.load() && count_tiles(J, t) < kMinWaves) {
+    if (g_tune_exact.load()) return t;
+    if (t.steps > 2) {
+        const int64_t n = count_tiles(J, t);
+        if (n >= kT3Mid) return t;
+        if (n >= kT3Small) {
+            if (t.zseg >= 2 * kMinZseg) t.zseg = std::max(kMinZseg, t.zseg / 2 / kZUnroll * kZUnroll);
+            return t;
+        }
+        t.steps = 2;
+    }
+    while (count_tiles(J, t) < kMinWaves) {
         if (t.zseg > kMinZseg) t.zseg = std::max(kMinZseg, t.zseg / 2 / kZUnroll * kZUnroll);
         else if (t.ty > 4) t.ty = 4;
         else if (t.vec > 1) t.vec /= 2;
