@@ -314,6 +314,14 @@ def boundary_study(K=8, seed0=500):
     return {"model": name, "seeds": K, "rows": rows}
 
 
+def device_info():
+    """What the run was measured on (torch's view of device 0)."""
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    return {"name": p.name, "arch": p.gcnArchName, "compute_units": p.multi_processor_count,
+            "hbm_gib": round(p.total_memory / 2**30, 1), "l2_bytes": getattr(p, "L2_cache_size", None)}
+
+
 def copy_rate(dev, mib=2048, reps=5):
     """Device-to-device copy rate (read + write bytes / time) of a 2 GiB
     buffer: what a plain streaming kernel reaches on this GPU, beside the
@@ -545,6 +553,7 @@ def main():
             "reverse_image": round(rev_us, 3),
         },
         "wall_s": round(wall, 3),
+        "device": device_info(),
     }
     if not args.no_unet:
         line["unet_train_step"] = unet_report()
