@@ -341,3 +341,44 @@ def test_three_step_modeling_receiver_rows(vec, zseg):
         assert np.array_equal(a, b)
     tr_o = oracle.model_shot(vo, s.h, s.nb, s.dt, s.wavelet.astype(np.float64), srcs[0], rec_a)
     assert rel_l2(got[0], tr_o) < TOL
+
+
+def test_folded_grid_bench_launch_shape():
+    """The benchmark's launch configuration (three steps per launch, two
+    floats per lane, 108-row tiles, one tile list for several shots) on the
+    full 2301 x 751 folded-layer grid for 300 steps: a three-shot batch of
+    modeling and RTM, one shot's traces and image against the oracle, every
+    shot against one-step single-shot calls bit for bit."""
+    s = synth.config_c2(nshot=3, nt=300)
+    g, vg, vo = _setup(s)
+    w = _t(s.wavelet)
+    srcs = [s.src[i] for i in range(3)]
+    rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
+    try:
+        for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
+            rtm.rtm_set_tuning2d(op, 2, 1, 108)
+            rtm.rtm_set_steps_per_launch(op, 3)
+        traces = [torch.empty((s.rec.shape[0], s.nt + 1), device=DEV) for _ in srcs]
+        plan = rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, vg, w, x, s.rec, traces_out=t)
+                                                for x, t in zip(srcs, traces)], s.dt, s.nt)
+        plan.run()
+        imgs = [torch.empty(g.interior_shape, device=DEV) for _ in srcs]
+        plan = rtm.BatchPlan(rtm.RTM_OP_RTM, [rtm.BatchShot(g, vg, w, x, s.rec, traces_in=t, image=im)
+                                              for x, t, im in zip(srcs, traces, imgs)], s.dt, s.nt, eps_rel=EPS)
+        plan.run()
+        got_tr, got_im = [_n(t) for t in traces], [_n(im) for im in imgs]
+        for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
+            rtm.rtm_set_tuning2d(op, 1, 1, 18)
+            rtm.rtm_set_steps_per_launch(op, 1)
+        for x, tr, im in zip(srcs, got_tr, got_im):
+            ref_tr = rtm.rtm_model_shot(g, vg, s.dt, w, x, s.rec)
+            ref_im = rtm.rtm_rtm_shot(g, vg, s.dt, w, x, s.rec, ref_tr, eps_rel=EPS)["image"]
+            assert np.array_equal(tr, _n(ref_tr)) and np.array_equal(im, _n(ref_im))
+    finally:
+        rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 0, 0)
+    w64 = s.wavelet.astype(np.float64)
+    tr_o = oracle.model_shot(vo, s.h, s.nb, s.dt, w64, srcs[1], s.rec)
+    ref = oracle.rtm_shot(vo, s.h, s.nb, s.dt, w64, srcs[1], s.rec, got_tr[1].astype(np.float64), eps_rel=EPS)
+    e_tr, e_im = rel_l2(got_tr[1], tr_o), rel_l2(got_im[1], ref["image"])
+    print(f"bench launch shape: traces {e_tr:.2e} image {e_im:.2e}")
+    assert e_tr < TOL and e_im < TOL
