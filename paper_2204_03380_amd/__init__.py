@@ -123,10 +123,14 @@ def rtm_get_tuning2d(op: int):
 
 
 def rtm_set_steps_per_launch(op: int, steps: int) -> None:
+    """Time steps per 2-D launch, 1, 2 or 3: RTM_OP_MODEL for every forward
+    pass, RTM_OP_RTM for the imaging reverse pass.  Results are the same bits
+    whatever the setting; jobs too small to fill the GPU take fewer."""
     _lib.check(_lib.load().rtm_set_steps_per_launch(op, steps))
 
 
 def rtm_get_steps_per_launch(op: int) -> int:
+    """The configured time steps per 2-D launch of `op`."""
     v = ctypes.c_int(0)
     _lib.check(_lib.load().rtm_get_steps_per_launch(op, ctypes.byref(v)))
     return int(v.value)
