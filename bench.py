@@ -535,6 +535,7 @@ def main():
             "avg_launch_us": round(rev_us, 3),
             "algorithmic_bytes_per_launch": rev_bytes,
             "device_copy_GBps": copy_gbps,
+            "frac_of_device_copy": round(achieved / copy_gbps, 4) if copy_gbps else None,
             "steps_per_launch": steps_r,
             "per_step": {"us": round(per_step_us, 3),
                          "one_step_algorithmic_bytes": one_step_bytes,
