@@ -149,3 +149,14 @@ def test_band_options_validation():
                                       None) == _lib.RTM_EINVAL
     g = rtm.Grid(2, 20, 1, 12, 10.0, 4).c()
     assert lib.rtm_rbc_pad_ex(ctypes.byref(g), 0x1000, None, 0x2000, None, 0, None) == _lib.RTM_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: asked for more, it exits with status 2 and
+    says why, before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr and not r.stdout.strip()
