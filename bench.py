@@ -155,84 +155,99 @@ PAPER_STORAGE_GB = {"Table 2": 2.638, "Table 4": 132.062}
 PAPER_STRIDE = 10
 
 
-def paper_shapes(nb=50, reps_2d=400, reps_3d=60, kinds=("modeling", "rtm", "storage")):
+def paper_shapes(nb=50, kinds=("modeling", "rtm", "storage")):
     """Device time of one shot on each paper grid (synthetic smooth velocity;
-    runtime does not depend on the values) against the paper's times.
-    Modeling: a reduced number of steps, scaled to the paper's nt.  RTM with
-    reconstruction and with storage: the paper's full nt, the storage run
-    keeping every 10th level in device memory."""
+    runtime does not depend on the values) against the paper's times, at the
+    paper's full nt.  Modeling and RTM with reconstruction run as a one-shot
+    plan replayed as a hipGraph (tables built once, no launch gaps); RTM with
+    storage through rtm_storage_shot, keeping every 10th level in device
+    memory."""
     import numpy as np
     import torch
 
     import paper_2204_03380_amd as rtm
     import synth
     dev = torch.device("cuda:0")
+    gst = torch.cuda.Stream(device=dev)  # graph capture needs a stream other than the NULL stream
     out = []
     for kind, (nx, ny, nz), nt_paper, paper, table in PAPER_CASES:
         if kind not in kinds:
             continue
-        ndim = 2 if ny == 1 else 3
-        shape_int = (nz - 2 * nb, nx - 2 * nb) if ndim == 2 else (nz - 2 * nb, ny - 2 * nb, nx - 2 * nb)
-        if ndim == 2:
-            v = synth.random_model(shape_int, 7, 1500.0, 4000.0, sigma=4.0)
-        else:
-            v = synth.layered_salt_3d(shape_int[2], shape_int[1], shape_int[0], 7, vmax=4000.0, salt=False)
-        h = 10.0
-        dt = 0.45 * h / 4000.0 * (0.8 if ndim == 3 else 1.0)
-        g = rtm.Grid.for_model(v, h, nb)
-        vp = rtm.rtm_rbc_pad(g, torch.from_numpy(v).to(dev), 11, 0.0)
-        steps = (reps_2d if ndim == 2 else reps_3d) if kind == "modeling" else nt_paper
-        w = torch.from_numpy(synth.ricker(15.0, dt, steps)).to(dev)
-        src = np.array([shape_int[-1] / 2.0, (shape_int[1] / 2.0 if ndim == 3 else 0.0), 2.0])
-        if ndim == 2:
-            rec = synth.line_receivers(np.arange(0, shape_int[-1], 1, dtype=np.float64), 2.0)
-        else:
-            rec = synth.grid_receivers(np.arange(0, shape_int[-1], 2, dtype=np.float64),
-                                       np.arange(0, shape_int[1], 2, dtype=np.float64), 2.0)
-        extra = {}
-        if kind == "modeling":
-            run = lambda: rtm.rtm_model_shot(g, vp, dt, w, src, rec)  # noqa: E731
-        else:
-            d = rtm.rtm_model_shot(g, vp, dt, w, src, rec)
-        if kind == "rtm":
-            run = lambda: rtm.rtm_rtm_shot(g, vp, dt, w, src, rec, d)  # noqa: E731
-            extra["kept_levels"] = 2
-            extra["kept_GiB"] = round(2 * nx * ny * nz * 4 / 2 ** 30, 4)
-        if kind == "storage":
-            count = rtm.rtm_storage_count(steps, PAPER_STRIDE, 0)
-            snaps = torch.empty((count,) + tuple(g.interior_shape), dtype=torch.float32, device=dev)
-            run = lambda: rtm.rtm_storage_shot(g, vp, dt, w, src, rec, d, PAPER_STRIDE, 0, snapshots=snaps)  # noqa
-            extra["stride"] = PAPER_STRIDE
-            extra["kept_levels"] = count
-            extra["kept_GiB"] = round(snaps.numel() * 4 / 2 ** 30, 3)
-            extra["paper_stored_GB"] = PAPER_STORAGE_GB[table]
-        run()
+        # every allocation and call of a case on the capture stream, so that
+        # torch's reuse of freed memory stays ordered with the work using it
+        with torch.cuda.stream(gst):
+            out.append(_paper_case(rtm, synth, np, torch, dev, gst, nb, kind, nx, ny, nz, nt_paper, paper, table))
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        run()
-        e1.record()
-        e1.synchronize()
-        ms = e0.elapsed_time(e1)
-        props = {"modeling": 1, "rtm": 3, "storage": 2}[kind]
-        cells = nx * ny * nz
-        t_paper_nt = ms * 1e-3 * nt_paper / steps
-        row = {"case": f"{kind} {nx}x{nz}" if ndim == 2 else f"{kind} {nx}x{ny}x{nz}", "source": table,
-               "padded_cells": cells, "steps_timed": steps, "ms_per_step": round(ms / steps, 4),
-               "gcell_updates_per_s": round(cells * props * steps / (ms * 1e-3) / 1e9, 2),
-               "seconds_at_paper_nt": round(t_paper_nt, 4),
-               "paper_seconds": paper,
-               "speedup": {k: round(v_ / t_paper_nt, 1) for k, v_ in paper.items()}}
-        row.update(extra)
-        out.append(row)
-        print(json.dumps(row), file=sys.stderr, flush=True)
-        del vp
-        if kind != "modeling":
-            del d
-        if kind == "storage":
-            del snaps
         torch.cuda.empty_cache()
     return out
+
+
+def _paper_case(rtm, synth, np, torch, dev, gst, nb, kind, nx, ny, nz, nt_paper, paper, table):
+    """One row of paper_shapes (run with gst as the current stream)."""
+    ndim = 2 if ny == 1 else 3
+    shape_int = (nz - 2 * nb, nx - 2 * nb) if ndim == 2 else (nz - 2 * nb, ny - 2 * nb, nx - 2 * nb)
+    if ndim == 2:
+        v = synth.random_model(shape_int, 7, 1500.0, 4000.0, sigma=4.0)
+    else:
+        v = synth.layered_salt_3d(shape_int[2], shape_int[1], shape_int[0], 7, vmax=4000.0, salt=False)
+    h = 10.0
+    dt = 0.45 * h / 4000.0 * (0.8 if ndim == 3 else 1.0)
+    g = rtm.Grid.for_model(v, h, nb)
+    vp = rtm.rtm_rbc_pad(g, torch.from_numpy(v).to(dev), 11, 0.0)
+    steps = nt_paper
+    w = torch.from_numpy(synth.ricker(15.0, dt, steps)).to(dev)
+    src = np.array([shape_int[-1] / 2.0, (shape_int[1] / 2.0 if ndim == 3 else 0.0), 2.0])
+    if ndim == 2:
+        rec = synth.line_receivers(np.arange(0, shape_int[-1], 1, dtype=np.float64), 2.0)
+    else:
+        rec = synth.grid_receivers(np.arange(0, shape_int[-1], 2, dtype=np.float64),
+                                   np.arange(0, shape_int[1], 2, dtype=np.float64), 2.0)
+    extra = {}
+    plan = None
+    if kind == "modeling":
+        tr = torch.empty((rec.shape[0], steps + 1), dtype=torch.float32, device=dev)
+        plan = rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, vp, w, src, rec, traces_out=tr)], dt, steps,
+                             flags=rtm.RTM_F_GRAPH)
+        run = lambda: plan.run(gst)  # noqa: E731
+    else:
+        d = rtm.rtm_model_shot(g, vp, dt, w, src, rec)
+    if kind == "rtm":
+        im = torch.empty(g.interior_shape, dtype=torch.float32, device=dev)
+        plan = rtm.BatchPlan(rtm.RTM_OP_RTM, [rtm.BatchShot(g, vp, w, src, rec, traces_in=d, image=im)], dt,
+                             steps, flags=rtm.RTM_F_GRAPH)
+        run = lambda: plan.run(gst)  # noqa: E731
+        extra["kept_levels"] = 2
+        extra["kept_GiB"] = round(2 * nx * ny * nz * 4 / 2 ** 30, 4)
+    if kind == "storage":
+        count = rtm.rtm_storage_count(steps, PAPER_STRIDE, 0)
+        snaps = torch.empty((count,) + tuple(g.interior_shape), dtype=torch.float32, device=dev)
+        run = lambda: rtm.rtm_storage_shot(g, vp, dt, w, src, rec, d, PAPER_STRIDE, 0, snapshots=snaps)  # noqa
+        extra["stride"] = PAPER_STRIDE
+        extra["kept_levels"] = count
+        extra["kept_GiB"] = round(snaps.numel() * 4 / 2 ** 30, 3)
+        extra["paper_stored_GB"] = PAPER_STORAGE_GB[table]
+    run()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(gst)
+    run()
+    e1.record(gst)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    props = {"modeling": 1, "rtm": 3, "storage": 2}[kind]
+    cells = nx * ny * nz
+    t_paper_nt = ms * 1e-3 * nt_paper / steps
+    row = {"case": f"{kind} {nx}x{nz}" if ndim == 2 else f"{kind} {nx}x{ny}x{nz}", "source": table,
+           "padded_cells": cells, "steps_timed": steps, "ms_per_step": round(ms / steps, 4),
+           "gcell_updates_per_s": round(cells * props * steps / (ms * 1e-3) / 1e9, 2),
+           "seconds_at_paper_nt": round(t_paper_nt, 4),
+           "paper_seconds": paper,
+           "speedup": {k: round(v_ / t_paper_nt, 1) for k, v_ in paper.items()}}
+    row.update(extra)
+    print(json.dumps(row), file=sys.stderr, flush=True)
+    if plan is not None:
+        plan.free()
+    return row
 
 
 BAND_MODES = (("uniform factors", None), ("taper Gaussian h (alpha 0)", 0.0), ("taper midway (alpha 0.5)", 0.5),

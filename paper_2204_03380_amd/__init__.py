@@ -428,7 +428,15 @@ class BatchPlan:
             self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
 
     def run(self, stream: "torch.cuda.Stream" = None) -> None:
-        st = stream.cuda_stream if stream is not None else _stream(self.device)
+        """Runs the plan on `stream` (default: the current stream).  A stream
+        other than the current one first waits for the current one: the
+        workspace and the inputs were allocated and written there, and
+        memory that torch hands out on it may still be in use by work queued
+        on it."""
+        cur = torch.cuda.current_stream(self.device)
+        if stream is not None and stream.cuda_stream != cur.cuda_stream:
+            stream.wait_stream(cur)
+        st = stream.cuda_stream if stream is not None else cur.cuda_stream
         _lib.check(_lib.load().rtm_batch_run(self._plan, self.ws.data_ptr(), self.ws.numel(), st))
 
     def free(self) -> None:
