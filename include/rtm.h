@@ -146,9 +146,10 @@ int rtm_get_tuning2d(int op, int *vec, int *tx, int *zseg);
  * it for every forward pass (modeling and the forward pass of RTM and VJP
  * jobs; storage RTM, which copies whole levels, takes 2 when 3 is set; a
  * job too small to fill the GPU takes 2 unless RTM_TUNE_EXACT is set),
- * RTM_OP_RTM for the imaging reverse pass (the gradient pass and probed
- * runs always take one step per launch; the last nt mod S steps are taken
- * one at a time).  Results are bit-identical whatever the setting.
+ * RTM_OP_RTM for the imaging reverse pass and the gradient pass (which
+ * takes at most 2; probed runs take one step per launch; the last nt mod S
+ * steps are taken one at a time).  Results are bit-identical whatever the
+ * setting.
  * Returns RTM_EINVAL for other values. */
 int rtm_set_steps_per_launch(int op, int steps);
 int rtm_get_steps_per_launch(int op, int *steps);

@@ -31,8 +31,8 @@ hipError_t launch_rev2d(int vec, int tx, bool grad, const ShotDev *shots, const 
 hipError_t launch_fwd2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                            const InjEnt *ents, const Contrib *cont, const SampleTask *stasks, int nsample, int n,
                            hipStream_t st);
-hipError_t launch_rev2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
-                           const InjEnt *ents, const Contrib *cont, int k, int reinject, hipStream_t st);
+hipError_t launch_rev2d_t2(int vec, bool grad, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+                           const InjEnt *ents, const Contrib *cont, int k, int reinject, float *wadj, hipStream_t st);
 hipError_t launch_fwd2d_t3(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                            const InjEnt *ents, const Contrib *cont, const SampleTask *stasks, int nsample, int n,
                            hipStream_t st);
@@ -720,7 +720,7 @@ int build_job_tables(Job &J)
         if (rc) return rc;
     }
     // Multi-step tilings (2-D): the forward one for every op, the reverse
-    // one for imaging only (the gradient pass runs one step per launch).
+    // one for imaging (up to three steps) and the gradient (two).
     // Three steps per launch store the middle level only on the receiver
     // rows, so storage RTM (which copies whole stored levels) takes two.
     J.fw2 = Tiling{};
@@ -731,9 +731,9 @@ int build_job_tables(Job &J)
         J.fw2.steps = J.op == RTM_OP_STORAGE ? 2 : J.fw.tune.steps;
         if ((rc = build_tiling(J, J.fw2, false))) return rc;
     }
-    if (ndim == 2 && J.op == RTM_OP_RTM && J.rv.tune.steps >= 2) {
+    if (ndim == 2 && (J.op == RTM_OP_RTM || J.op == RTM_OP_VJP) && J.rv.tune.steps >= 2) {
         J.rv2.tune = J.rv.tune;
-        J.rv2.steps = J.rv.tune.steps;
+        J.rv2.steps = J.op == RTM_OP_VJP ? 2 : J.rv.tune.steps;  // the gradient pass: two steps at most
         if ((rc = build_tiling(J, J.rv2, true))) return rc;
     }
     return RTM_OK;
@@ -776,7 +776,7 @@ Counts bound_counts(const GridInfo &g, int op, int nrec)
         const int64_t t2 = ((g.NX + 47) / 48) * (g.L.NZr / kMinZseg);
         c.tiles_f2 = t2;
         c.ents_f2 = c.cont_f2 = 11 * kMaxNodes;
-        if (op == RTM_OP_RTM) {
+        if (op == RTM_OP_RTM || op == RTM_OP_VJP) {
             c.tiles_r2 = t2;
             c.ents_r2 = c.cont_r2 = 11 * (kMaxNodes + (int64_t)kMaxNodes * nrec);
         }
@@ -1040,7 +1040,7 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
     }
     const int reinject = (J.flags & RTM_F_NO_REINJECT) ? 0 : 1;
     const bool probing = probe && probe->snap_k >= 0;
-    const bool two = J.rv.ndim == 2 && J.rv2.steps > 1 && !grad && !probing;
+    const bool two = J.rv.ndim == 2 && J.rv2.steps > 1 && !probing;
     const int rs = two ? J.rv2.steps : 1;
     // wadj is recorded for a single-shot job only (its kernel argument is one
     // buffer); batched VJPs do not return wavelet gradients.
@@ -1055,8 +1055,9 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
         }
     } else if (two) {
         for (; k >= 1; k -= 2) {
-            RTM_HIP(launch_rev2d_t2(J.rv2.tune.vec, SH(), D.at<Tile2D>(J.ws.tiles_r2), J.rv2.count(), J.rv2.nslots,
-                                    D.at<InjEnt>(J.ws.ents_r2), D.at<Contrib>(J.ws.cont_r2), k, reinject, st));
+            RTM_HIP(launch_rev2d_t2(J.rv2.tune.vec, grad, SH(), D.at<Tile2D>(J.ws.tiles_r2), J.rv2.count(),
+                                    J.rv2.nslots, D.at<InjEnt>(J.ws.ents_r2), D.at<Contrib>(J.ws.cont_r2), k, reinject,
+                                    wadj, st));
             cur ^= 1;
         }
     }

@@ -609,23 +609,33 @@ struct Rev2Ctx {
     const gfloat *P0, *P1, *M0, *M1;  // p^k, p^{k+1}, mu^{k+1}, mu^{k+2} (read set)
     gfloat *WP1, *WP2, *WM1, *WM2;    // p^{k-1}, p^{k-2}, mu^k, mu^{k-1} (write set)
     const gfloat *Dp;
-    gfloat *A0, *A1;                  // num, den
+    gfloat *A0, *A1;                  // num, den (imaging) or G (gradient)
     const float *wav, *sig;           // wavelet and receiver signal at time k
     const InjEnt *ents;
     const Contrib *cont;
     float *isv;                       // LDS: receiver sums of one row (row_inject)
     int *ihas;
+    float *wadj;                      // gradient: wavelet-adjoint samples (nullable)
+    int k;
     int64_t pitch;
     int nrec;
-    int x, xs, NX, NZr, lane, z0, z1, iz0, iz1, s1end, r1end;
+    int x, xs, NX, NZr, lane, z0, z1, iz0, iz1, s1end, r1end, send;
     bool live, own, own_img, reinject;
 };
 
-template <int VEC, int S>
+// Gradient pair (GRAD): the imaging sums give way to the gradient sum of the
+// one-step kernel, G += mu^{k+1} D' (L p^k) on every owned cell, then, on a
+// source node, G += mu^{k+1} (D' s^k) and the wavelet-adjoint sample of
+// step k, and the same for step k - 1 with mu^k.  Both steps' terms land on
+// step two's row r2, where mu^{k+1} and mu^k are step two's previous and
+// centre levels; step one's D' L p^k waits four rows in the qa queue.  The
+// source nodes are the tile's own list (rows in [z0, z1)), walked in row
+// order.  The products and their order are the one-step kernel's.
+template <int VEC, bool GRAD, int S>
 __device__ __forceinline__ void rev2_row(const Rev2Ctx<VEC> &C, float (&q1p)[9][VEC], float (&q1m)[9][VEC],
                                          float (&q2p)[9][VEC], float (&q2m)[9][VEC], float (&qd)[9][VEC],
                                          float (&qa)[9][VEC], float (&qb)[9][VEC], f4v &hp, f4v &hm, int s,
-                                         int &es, int &er)
+                                         int &es, int &er, int &eo)
 {
     constexpr int a0 = S % 9, a1 = (S + 1) % 9, a2 = (S + 2) % 9, a3 = (S + 3) % 9, a4 = (S + 4) % 9,
                   a5 = (S + 5) % 9, a6 = (S + 6) % 9, a7 = (S + 7) % 9, a8 = (S + 8) % 9;
@@ -644,7 +654,7 @@ __device__ __forceinline__ void rev2_row(const Rev2Ctx<VEC> &C, float (&q1p)[9][
         ldv_s<VEC>(C.M1 + o1, m1);
         ldv_s<VEC>(C.Dp + o1, d);
     }
-    const bool img1 = C.own_img && r1 >= C.z0 && r1 < C.z1 && r1 >= C.iz0 && r1 < C.iz1;
+    const bool img1 = !GRAD && C.own_img && r1 >= C.z0 && r1 < C.z1 && r1 >= C.iz0 && r1 < C.iz1;
     if (img1) {
         ldv_s<VEC>(C.A0 + o1, qa[a4]);
         ldv_s<VEC>(C.A1 + o1, qb[a4]);
@@ -668,6 +678,7 @@ __device__ __forceinline__ void rev2_row(const Rev2Ctx<VEC> &C, float (&q1p)[9][
         const float c = q1p[a4][j], c2 = c + c;
         float lap = d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
         lap += d2(c2, q1p[a3][j], q1p[a5][j], q1p[a2][j], q1p[a6][j], q1p[a1][j], q1p[a7][j], q1p[a0][j], q1p[a8][j]);
+        if constexpr (GRAD) qa[a4][j] = d[j] * lap;  // D' L p^k of row r1, used at r2
         np[j] = fmaf(d[j], lap, c2 - p1[j]);
     }
     if constexpr (halo_ahead<VEC>())
@@ -711,7 +722,7 @@ __device__ __forceinline__ void rev2_row(const Rev2Ctx<VEC> &C, float (&q1p)[9][
     if (s >= 8 && r2 < C.z1) {
         const float hz[4] = {0.f, 0.f, 0.f, 0.f};
         const int64_t o2 = (int64_t)r2 * C.pitch + C.x;
-        float vp[VEC], vm[VEC];
+        float vp[VEC], vm[VEC], inc2[VEC];
         exchange_row<VEC>(q2p[a0], hz, hz, ext);
 #pragma unroll
         for (int j = 0; j < VEC; ++j) {
@@ -720,6 +731,7 @@ __device__ __forceinline__ void rev2_row(const Rev2Ctx<VEC> &C, float (&q1p)[9][
                 d2(c2, ext[3 + j], ext[5 + j], ext[2 + j], ext[6 + j], ext[1 + j], ext[7 + j], ext[j], ext[8 + j]);
             lap += d2(c2, q2p[a8][j], q2p[a1][j], q2p[a7][j], q2p[a2][j], q2p[a6][j], q2p[a3][j], q2p[a5][j],
                       q2p[a4][j]);
+            inc2[j] = qd[a0][j] * lap;
             vp[j] = fmaf(qd[a0][j], lap, c2 - q1p[a0][j]);
         }
         exchange_row<VEC>(q2m[a0], hz, hz, ext);
@@ -736,7 +748,45 @@ __device__ __forceinline__ void rev2_row(const Rev2Ctx<VEC> &C, float (&q1p)[9][
             stv<VEC>(C.WP2 + o2, vp);
             stv<VEC>(C.WM2 + o2, vm);
         }
-        if (C.own_img && r2 >= C.iz0 && r2 < C.iz1) {
+        if constexpr (GRAD) {
+            // source nodes of row r2 (the tile's own list): their terms of
+            // steps k and k - 1, in the one-step kernel's order
+            float sk[VEC], sk1[VEC];
+            bool hs[VEC];
+#pragma unroll
+            for (int j = 0; j < VEC; ++j) {
+                sk[j] = sk1[j] = 0.f;
+                hs[j] = false;
+            }
+            for (; eo < C.send && C.ents[eo].z == r2; ++eo) {
+                const InjEnt E = C.ents[eo];
+#pragma unroll
+                for (int j = 0; j < VEC; ++j)
+                    if (C.own && E.x == C.x + j) {
+                        sk[j] = inj_sum(E, C.cont, C.wav);
+                        sk1[j] = inj_sum(E, C.cont, C.wav - 1);
+                        hs[j] = true;
+                        if (C.wadj) {
+                            float wsum = 0.f;
+                            for (int c = E.cbeg; c < E.cend; ++c) wsum += C.cont[c].w;
+                            C.wadj[(int64_t)C.k * kMaxNodes + E.slot] = wsum * q1m[a0][j];
+                            C.wadj[(int64_t)(C.k - 1) * kMaxNodes + E.slot] = wsum * q2m[a0][j];
+                        }
+                    }
+            }
+            if (C.own) {
+                float gg[VEC];
+                ldv<VEC>(C.A0 + o2, gg);
+#pragma unroll
+                for (int j = 0; j < VEC; ++j) {
+                    gg[j] = fmaf(q1m[a0][j], qa[a0][j], gg[j]);
+                    if (hs[j]) gg[j] = fmaf(q1m[a0][j], qd[a0][j] * sk[j], gg[j]);
+                    gg[j] = fmaf(q2m[a0][j], inc2[j], gg[j]);
+                    if (hs[j]) gg[j] = fmaf(q2m[a0][j], qd[a0][j] * sk1[j], gg[j]);
+                }
+                stv<VEC>(C.A0 + o2, gg);
+            }
+        } else if (C.own_img && r2 >= C.iz0 && r2 < C.iz1) {
             float a[VEC], bb[VEC];
 #pragma unroll
             for (int j = 0; j < VEC; ++j) {
@@ -751,12 +801,11 @@ __device__ __forceinline__ void rev2_row(const Rev2Ctx<VEC> &C, float (&q1p)[9][
 
 // One float per lane fits in 82 registers; asking for 5 waves per SIMD
 // keeps the compiler there (it otherwise allocates 128, i.e. 4 waves).
-template <int VEC>
+template <int VEC, bool GRAD>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(VEC == 1 ? 5 : 1, 8)))
-void rev2d_t2_kernel(const ShotDev *__restrict__ shots,
-                                                      const Tile2D *__restrict__ tiles, int ntiles, int nslots,
-                                                      const InjEnt *__restrict__ ents,
-                                                      const Contrib *__restrict__ cont, int k, int reinject)
+void rev2d_t2_kernel(const ShotDev *__restrict__ shots, const Tile2D *__restrict__ tiles, int ntiles, int nslots,
+                     const InjEnt *__restrict__ ents, const Contrib *__restrict__ cont, int k, int reinject,
+                     float *__restrict__ wadj)
 {
     const int t = xcd_tile(blockIdx.x, nslots);
     if (t >= ntiles) return;
@@ -777,12 +826,14 @@ void rev2d_t2_kernel(const ShotDev *__restrict__ shots,
     C.WM2 = gp(S.fld[6 + ((k + 1) & 1)] + S.L.org);
     C.Dp = gp(S.Dp + S.L.org);
     C.A0 = gp(S.acc0 + S.L.org);
-    C.A1 = gp(S.acc1 + S.L.org);
+    C.A1 = GRAD ? nullptr : gp(S.acc1 + S.L.org);
     C.wav = S.wav + k;
     C.sig = S.sig + (int64_t)k * S.nrec;
     C.nrec = S.nrec;
     C.ents = ents;
     C.cont = cont;
+    C.wadj = wadj;
+    C.k = k;
     C.lane = lane;
     C.xs = T.x0;
     C.x = T.x0 + lane * VEC;
@@ -792,6 +843,7 @@ void rev2d_t2_kernel(const ShotDev *__restrict__ shots,
     C.iz1 = S.iz1;
     C.s1end = T.s1end;
     C.r1end = T.r1end;
+    C.send = T.send;
     __shared__ float isv[64 * VEC];
     __shared__ int ihas[64 * VEC];
 #pragma unroll
@@ -816,12 +868,12 @@ void rev2d_t2_kernel(const ShotDev *__restrict__ shots,
             ldv<VEC>(C.M0 + (int64_t)r * C.pitch + C.x, q1m[i]);
         }
     }
-    int es = T.s1beg, er = T.r1beg;
+    int es = T.s1beg, er = T.r1beg, eo = T.sbeg;
     const int nstep = T.z1 - T.z0 + kZUnroll;
     // strip-end halo of the first march row (z0 - 4 >= -4: stored)
     f4v hp = halo_fetch<VEC>(C.P0 + (int64_t)(T.z0 - 4) * C.pitch, C.xs, C.NX, lane, halo_ahead<VEC>());
     f4v hm = halo_fetch<VEC>(C.M0 + (int64_t)(T.z0 - 4) * C.pitch, C.xs, C.NX, lane, halo_ahead<VEC>());
-#define RTM_REV2_ROW(SS, ZZ) rev2_row<VEC, SS>(C, q1p, q1m, q2p, q2m, qd, qa, qb, hp, hm, ZZ, es, er)
+#define RTM_REV2_ROW(SS, ZZ) rev2_row<VEC, GRAD, SS>(C, q1p, q1m, q2p, q2m, qd, qa, qb, hp, hm, ZZ, es, er, eo)
     RTM_MARCH2(RTM_REV2_ROW, nstep)
 #undef RTM_REV2_ROW
     // time k - 1 terms into the owned cells of p^{k-2} and mu^{k-1}
@@ -1412,16 +1464,22 @@ hipError_t launch_fwd2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, i
     return hipGetLastError();
 }
 
-hipError_t launch_rev2d_t2(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
-                           const InjEnt *ents, const Contrib *cont, int k, int reinject, hipStream_t st)
+hipError_t launch_rev2d_t2(int vec, bool grad, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
+                           const InjEnt *ents, const Contrib *cont, int k, int reinject, float *wadj, hipStream_t st)
 {
     dim3 grid(nslots), block(64);
-    switch (vec) {
-    case 1: hipLaunchKernelGGL(rev2d_t2_kernel<1>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject); break;
-    case 2: hipLaunchKernelGGL(rev2d_t2_kernel<2>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject); break;
-    case 4: hipLaunchKernelGGL(rev2d_t2_kernel<4>, grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject); break;
+#define RTM_REV2T2(V, G) \
+    hipLaunchKernelGGL((rev2d_t2_kernel<V, G>), grid, block, 0, st, shots, tiles, ntiles, nslots, ents, cont, k, reinject, wadj)
+    switch (vec * 2 + (grad ? 1 : 0)) {
+    case 2: RTM_REV2T2(1, false); break;
+    case 3: RTM_REV2T2(1, true); break;
+    case 4: RTM_REV2T2(2, false); break;
+    case 5: RTM_REV2T2(2, true); break;
+    case 8: RTM_REV2T2(4, false); break;
+    case 9: RTM_REV2T2(4, true); break;
     default: return hipErrorInvalidValue;
     }
+#undef RTM_REV2T2
     return hipGetLastError();
 }
 

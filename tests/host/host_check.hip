@@ -117,8 +117,8 @@ hipError_t launch_rev2d(int, int, bool, const ShotDev *shots, const Tile2D *, in
     SIM.rsteps.push_back(k);
     return hipSuccess;
 }
-hipError_t launch_rev2d_t2(int, const ShotDev *shots, const Tile2D *, int, int, const InjEnt *, const Contrib *,
-                           int k, int, hipStream_t)
+hipError_t launch_rev2d_t2(int, bool, const ShotDev *shots, const Tile2D *, int, int, const InjEnt *,
+                           const Contrib *, int k, int, float *, hipStream_t)
 {
     const ShotDev &T = SIM.tab(shots);
     rev_reads(T, k);
@@ -420,6 +420,25 @@ static void rtm_schedule(int nt, int steps)
     CHECK(ok, "rtm nt %d steps %d: forward %zu / reverse %zu steps out of order", nt, steps, SIM.fsteps.size(),
           SIM.rsteps.size());
     CHECK(SIM.errors == 0, "rtm nt %d steps %d: %ld schedule errors", nt, steps, SIM.errors);
+    // gradient (two steps per launch at most): the same reverse order
+    Job V;
+    if (single_job(V, RTM_OP_VJP, g, fake.data(), 1e-3, nt, fake.data(), src, 10, rec.data(), 0)) {
+        CHECK(false, "vjp single_job failed: %s", t_err.c_str());
+        return;
+    }
+    std::vector<char> wv(V.ws.bytes + 256);
+    Dev DV{(char *)(((uintptr_t)wv.data() + 255) & ~(uintptr_t)255)};
+    SIM = Sim();
+    fill_shot_devs(V, DV, SIM.host);
+    SIM.base = DV.at<ShotDev>(V.ws.shots);
+    SIM.lev_of[SIM.host[0].fld[0]] = 0;
+    SIM.lev_of[SIM.host[0].fld[1]] = -1;
+    CHECK(job_launch(V, DV, nullptr, nullptr, false) == 0, "vjp job_launch failed: %s", t_err.c_str());
+    bool vok = (int)SIM.rsteps.size() == nt;
+    for (int i = 0; vok && i < nt; ++i) vok = SIM.rsteps[i] == nt - 1 - i;
+    CHECK(vok && SIM.errors == 0 && V.rv2.steps == (steps > 1 ? 2 : 1),
+          "vjp nt %d steps %d: reverse steps out of order or %ld schedule errors", nt, steps, SIM.errors);
+    check_layout(V, "vjp layout");
     // modeling: every level 0 .. nt recorded once, from the field holding it
     Job M;
     if (single_job(M, RTM_OP_MODEL, g, fake.data(), 1e-3, nt, fake.data(), src, 10, rec.data(), 0)) {
