@@ -174,7 +174,8 @@ struct WgCfg {
     static constexpr int RS = 4 / WS;
     static constexpr int CPW = CB / WS;
     static constexpr int SEG = 32;
-    static constexpr int LDS_U16 = SEG * (COUT + 3 * CIN);  // per row group
+    static constexpr int XW = SEG + 8;  // x^T row: voxels x0 - 1 .. x0 + 32, padded to whole 16-byte reads
+    static constexpr int LDS_U16 = SEG * COUT + XW * CIN;  // per row group
 };
 
 struct WgArgs {
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(WgArgs a)
     const int gt = wi * 64 + lane;  // thread index within the row group
     const int r16 = lane & 15, g = lane >> 4;
     uint16_t *dyT = lds + rg * C::LDS_U16;  // [COUT][SEG]
-    uint16_t *xT = dyT + COUT * SEG;        // [3][CIN][SEG]
+    uint16_t *xT = dyT + COUT * SEG;        // [CIN][XW]
     const int D = a.d, H = a.h, W = a.w;
     const int64_t r0 = a.rows * s / a.S, r1 = a.rows * (s + 1) / a.S;
     const bool centre = (q == 4);
@@ -232,8 +233,9 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(WgArgs a)
 #pragma unroll
                     for (int i = 0; i < 8; ++i) dyT[(c0 + i) * SEG + j] = e[i];
                 }
-                // x^T of the source row, voxels x0 - 1 .. x0 + 32, into the
-                // three shifted copies xT[dx][i][j] = x[x0 + j + dx - 1][i]
+                // x^T of the source row, xT[i][jj] = x[x0 + jj - 1][i] for
+                // jj = 0 .. 33 (one copy; the three x shifts are taken from
+                // it in registers below)
                 for (int c = gt; c < (SEG + 2) * CIN / 8; c += 64 * C::WS) {
                     const int jj = c / (CIN / 8), c0 = (c % (CIN / 8)) * 8;
                     const int xg = x0 + jj - 1;
@@ -241,12 +243,7 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(WgArgs a)
                     if (xg >= 0 && xg < W) v = *reinterpret_cast<const uint4 *>(a.x + ((src * W + xg) * CIN + c0));
                     const uint16_t *e = reinterpret_cast<const uint16_t *>(&v);
 #pragma unroll
-                    for (int dxi = 0; dxi < 3; ++dxi) {
-                        const int j = jj - dxi;
-                        if (j < 0 || j >= SEG) continue;
-#pragma unroll
-                        for (int i = 0; i < 8; ++i) xT[(dxi * CIN + c0 + i) * SEG + j] = e[i];
-                    }
+                    for (int i = 0; i < 8; ++i) xT[(c0 + i) * C::XW + jj] = e[i];
                 }
             }
             __syncthreads();
@@ -256,13 +253,20 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(WgArgs a)
                     const int co = (wi * C::CPW + cl) * 16 + r16;
                     const uint4 A = *reinterpret_cast<const uint4 *>(dyT + co * SEG + 8 * g);
 #pragma unroll
-                    for (int dxi = 0; dxi < 3; ++dxi)
-#pragma unroll
-                        for (int ib = 0; ib < C::IB; ++ib) {
-                            const uint4 B =
-                                *reinterpret_cast<const uint4 *>(xT + (dxi * CIN + ib * 16 + r16) * SEG + 8 * g);
-                            acc[cl][dxi][ib] = mfma16(A, B, acc[cl][dxi][ib]);
-                        }
+                    for (int ib = 0; ib < C::IB; ++ib) {
+                        // voxels 8g + dx .. 8g + dx + 7 of channel ib*16 + r16
+                        // for dx = 0, 1, 2: two aligned reads, then shifts
+                        // by 0, 1 and 2 bfloat16 elements
+                        const uint16_t *row = xT + (ib * 16 + r16) * C::XW + 8 * g;
+                        const uint4 L = *reinterpret_cast<const uint4 *>(row);
+                        const uint4 R = *reinterpret_cast<const uint4 *>(row + 8);
+                        const uint4 B1 = {(L.x >> 16) | (L.y << 16), (L.y >> 16) | (L.z << 16),
+                                          (L.z >> 16) | (L.w << 16), (L.w >> 16) | (R.x << 16)};
+                        const uint4 B2 = {L.y, L.z, L.w, R.x};
+                        acc[cl][0][ib] = mfma16(A, L, acc[cl][0][ib]);
+                        acc[cl][1][ib] = mfma16(A, B1, acc[cl][1][ib]);
+                        acc[cl][2][ib] = mfma16(A, B2, acc[cl][2][ib]);
+                    }
                 }
                 if (centre && gt < COUT) {
 #pragma unroll 8
