@@ -18,8 +18,10 @@
  *        y[p, o] = b[o] + sum_{t, i} w[o, t, i] x[p + off(t), i],
  *    tap t = (kz*3 + ky)*3 + kx, off(t) = (kz-1, ky-1, kx-1) in (z, y, x).
  *    Master weights are float32 [Cout][27][Cin].
- *  - Channel counts of a convolution must be 16, 32, 64 or 128 (a layer with
- *    fewer real channels is zero-padded to 16).
+ *  - Channel counts of a convolution must be 16, 32, 64 or 128, or the pair
+ *    (Cin, Cout) must be (1, 16) or (16, 1): the network's one-channel input
+ *    and output layers, which run on the vector units (too few products per
+ *    voxel for the matrix cores); the others run as bfloat16 MFMA.
  *  - Pointers are device pointers unless stated; device buffers belong to
  *    the caller; nothing is allocated.  Every call is asynchronous on
  *    `stream` (a hipStream_t, NULL = default stream) unless stated.
@@ -59,14 +61,16 @@ int unet_weight_pack(const unet_conv_desc_t *desc, const float *w, uint16_t *w_f
  *     out[p*Cout + o] = bf16(a + (skip ? skip[p*Cout + o] : 0))   (if out)
  * x: bfloat16 [N][D][H][W][Cin]; w_fwd from unet_weight_pack; skip: bfloat16
  * [..][Cout] or NULL.  1 <= y_channels <= Cout.  Outputs must not alias
- * inputs. */
+ * inputs.  x and w_fwd must be 16-byte aligned; for the (1, 16) pair also
+ * y, r, out and skip (stored and read as 16-byte vectors). */
 int unet_conv3d_fwd(const unet_conv_desc_t *desc, const uint16_t *x, const uint16_t *w_fwd, const float *bias,
                     int32_t relu, const uint16_t *skip, float *y, int32_t y_channels, uint16_t *r, uint16_t *out,
                     void *stream);
 
 /* Input gradient: dx[q, i] = sum_{t, o} w[o, t, i] dy[q - off(t), o], as the
  * forward kernel applied to dy with w_bwd.  dy: bfloat16 [..][Cout];
- * dx: float32 [..][Cin]. */
+ * dx: float32 [..][Cin].  dy and w_bwd must be 16-byte aligned; for the
+ * (16, 1) pair also dx. */
 int unet_conv3d_dgrad(const unet_conv_desc_t *desc, const uint16_t *dy, const uint16_t *w_bwd, float *dx,
                       void *stream);
 

@@ -323,6 +323,257 @@ hipError_t sum_parts(const float *part, int64_t P, int64_t n, float *tmp, float 
 }
 
 // ---------------------------------------------------------------------------
+// One-channel layers (the network's input and output): a 1 -> 16 or 16 -> 1
+// convolution is 432 multiply-adds per voxel, too thin for the matrix
+// cores, so one thread computes one voxel on the vector units.  Weights
+// (bfloat16, the packed layout [COUT][27][CIN]) are held in LDS as floats.
+// ---------------------------------------------------------------------------
+constexpr int kThin = 16;  // channels on the wide side
+
+__device__ __forceinline__ void thin_decode(int64_t v, int D, int H, int W, int &z, int &y, int &x)
+{
+    if (v <= 0xffffffffll) {  // 32-bit division, far cheaper than the 64-bit sequence
+        const uint32_t u = (uint32_t)v, t = u / (uint32_t)W, t2 = t / (uint32_t)H;
+        x = (int)(u - t * (uint32_t)W);
+        y = (int)(t - t2 * (uint32_t)H);
+        z = (int)(t2 % (uint32_t)D);
+        return;
+    }
+    const int64_t t = v / W;
+    x = (int)(v - t * W);
+    const int64_t t2 = t / H;
+    y = (int)(t - t2 * H);
+    z = (int)(t2 % D);
+}
+
+__device__ __forceinline__ bool thin_tap(int tap, int z, int y, int x, int D, int H, int W, int64_t HW,
+                                         int64_t &off)
+{
+    const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+    off = dz * HW + (int64_t)dy * W + dx;
+    return (unsigned)(z + dz) < (unsigned)D && (unsigned)(y + dy) < (unsigned)H && (unsigned)(x + dx) < (unsigned)W;
+}
+
+// The fused epilogue of conv_fwd_kernel for one voxel and channel.
+__device__ __forceinline__ void thin_store(const ConvArgs &a, int64_t v, int co, int cout, float acc)
+{
+    float val = acc + (a.bias ? a.bias[co] : 0.f);
+    if (a.relu) val = fmaxf(val, 0.f);
+    if (a.y && co < a.ych) a.y[v * a.ych + co] = val;
+    const int64_t o = v * cout + co;
+    if (a.r) a.r[o] = f2bf(val);
+    if (a.out) a.out[o] = f2bf(a.skip ? val + bf2f(a.skip[o]) : val);
+}
+
+// 1 -> 16 channels.  Weights in LDS as [tap][channel] so that one tap's
+// sixteen weights are four 16-byte reads; each channel sums its taps in
+// ascending order.
+__global__ __launch_bounds__(256) void conv_thin_in_kernel(ConvArgs a)
+{
+    __shared__ float4 wsh4[27 * kThin / 4];
+    float *wsh = reinterpret_cast<float *>(wsh4);
+    for (int i = threadIdx.x; i < kThin * 27; i += blockDim.x) wsh[(i % 27) * kThin + i / 27] = bf2f(a.wt[i]);
+    __syncthreads();
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= a.nvox) return;
+    int z, y, x;
+    thin_decode(v, a.d, a.h, a.w, z, y, x);
+    const int64_t HW = (int64_t)a.h * a.w;
+    float acc[kThin];
+#pragma unroll
+    for (int co = 0; co < kThin; ++co) acc[co] = 0.f;
+#pragma unroll 3
+    for (int t = 0; t < 27; ++t) {
+        int64_t off;
+        const float xt = thin_tap(t, z, y, x, a.d, a.h, a.w, HW, off) ? bf2f(a.x[v + off]) : 0.f;
+#pragma unroll
+        for (int q = 0; q < kThin / 4; ++q) {
+            const float4 w4 = wsh4[t * (kThin / 4) + q];
+            acc[4 * q] = fmaf(w4.x, xt, acc[4 * q]);
+            acc[4 * q + 1] = fmaf(w4.y, xt, acc[4 * q + 1]);
+            acc[4 * q + 2] = fmaf(w4.z, xt, acc[4 * q + 2]);
+            acc[4 * q + 3] = fmaf(w4.w, xt, acc[4 * q + 3]);
+        }
+    }
+    float val[kThin];
+#pragma unroll
+    for (int co = 0; co < kThin; ++co) {
+        const float t = acc[co] + (a.bias ? a.bias[co] : 0.f);
+        val[co] = a.relu ? fmaxf(t, 0.f) : t;
+    }
+    // the epilogue of thin_store for all 16 channels, as 16-byte stores
+    if (a.y) {
+        if (a.ych == kThin) {
+            float4 *py = reinterpret_cast<float4 *>(a.y + v * kThin);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) py[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
+        } else {
+#pragma unroll
+            for (int co = 0; co < kThin; ++co)
+                if (co < a.ych) a.y[v * a.ych + co] = val[co];
+        }
+    }
+    uint32_t rb[kThin / 2], ob[kThin / 2];
+#pragma unroll
+    for (int q = 0; q < kThin / 2; ++q) {
+        rb[q] = (uint32_t)f2bf(val[2 * q]) | ((uint32_t)f2bf(val[2 * q + 1]) << 16);
+        if (a.out) {
+            float o0 = val[2 * q], o1 = val[2 * q + 1];
+            if (a.skip) {
+                o0 += bf2f(a.skip[v * kThin + 2 * q]);
+                o1 += bf2f(a.skip[v * kThin + 2 * q + 1]);
+            }
+            ob[q] = (uint32_t)f2bf(o0) | ((uint32_t)f2bf(o1) << 16);
+        }
+    }
+    if (a.r) {
+        uint4 *pr = reinterpret_cast<uint4 *>(a.r + v * kThin);
+        pr[0] = make_uint4(rb[0], rb[1], rb[2], rb[3]);
+        pr[1] = make_uint4(rb[4], rb[5], rb[6], rb[7]);
+    }
+    if (a.out) {
+        uint4 *po = reinterpret_cast<uint4 *>(a.out + v * kThin);
+        po[0] = make_uint4(ob[0], ob[1], ob[2], ob[3]);
+        po[1] = make_uint4(ob[4], ob[5], ob[6], ob[7]);
+    }
+}
+
+// 16 -> 1 channel.
+__global__ __launch_bounds__(256) void conv_thin_out_kernel(ConvArgs a)
+{
+    __shared__ float wsh[27 * kThin];
+    for (int i = threadIdx.x; i < 27 * kThin; i += blockDim.x) wsh[i] = bf2f(a.wt[i]);
+    __syncthreads();
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= a.nvox) return;
+    int z, y, x;
+    thin_decode(v, a.d, a.h, a.w, z, y, x);
+    const int64_t HW = (int64_t)a.h * a.w;
+    float acc = 0.f;
+    for (int t = 0; t < 27; ++t) {
+        int64_t off;
+        if (!thin_tap(t, z, y, x, a.d, a.h, a.w, HW, off)) continue;
+        const uint4 *p = reinterpret_cast<const uint4 *>(a.x + (v + off) * kThin);
+        const uint4 c0 = p[0], c1 = p[1];
+        const uint16_t *e0 = reinterpret_cast<const uint16_t *>(&c0);
+        const uint16_t *e1 = reinterpret_cast<const uint16_t *>(&c1);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc = fmaf(wsh[t * kThin + i], bf2f(e0[i]), acc);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) acc = fmaf(wsh[t * kThin + 8 + i], bf2f(e1[i]), acc);
+    }
+    thin_store(a, v, 0, 1, acc);
+}
+
+// Weight gradient of a one-channel layer: dw[o][tap][i] = sum_v dy[v][o]
+// x[v + off(tap)][i] with (CIN, COUT) = (1, 16) or (16, 1).  Block (b, p)
+// sums voxels [b nvox / NB, (b + 1) nvox / NB) for the taps of plane
+// dz = p - 1; wave w of its three takes the three taps of row dy = w - 1,
+// lane l the voxels l, l + 64, ...; the lanes' sums are added by a fixed
+// butterfly and written as partial b, which sum_parts adds in a fixed
+// order.  The bias gradient is summed by wave 1 of plane 1.
+constexpr int kThinWgBlocks = 2048;
+
+template <bool IN1>
+__global__ __launch_bounds__(192) void wgrad_thin_kernel(const uint16_t *__restrict__ x,
+                                                         const uint16_t *__restrict__ dy, int64_t nvox, int D, int H,
+                                                         int W, float *__restrict__ part, float *__restrict__ bpart)
+{
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t v0 = nvox * blockIdx.x / gridDim.x, v1 = nvox * (blockIdx.x + 1) / gridDim.x;
+    const int64_t HW = (int64_t)H * W;
+    const int tap0 = blockIdx.y * 9 + wv * 3;
+    const bool bias_wave = blockIdx.y == 1 && wv == 1;
+    float acc[3][kThin], bacc[kThin];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int c = 0; c < kThin; ++c) acc[t][c] = 0.f;
+#pragma unroll
+    for (int c = 0; c < kThin; ++c) bacc[c] = 0.f;
+    for (int64_t v = v0 + lane; v < v1; v += 64) {
+        int z, y, xx;
+        thin_decode(v, D, H, W, z, y, xx);
+        float wide[kThin];
+        float thin_c = 0.f;
+        if (IN1) {  // dy is the 16-channel side at v
+            const uint4 *p = reinterpret_cast<const uint4 *>(dy + v * kThin);
+            const uint4 c0 = p[0], c1 = p[1];
+            const uint16_t *e0 = reinterpret_cast<const uint16_t *>(&c0);
+            const uint16_t *e1 = reinterpret_cast<const uint16_t *>(&c1);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                wide[i] = bf2f(e0[i]);
+                wide[8 + i] = bf2f(e1[i]);
+            }
+            if (bias_wave)
+#pragma unroll
+                for (int c = 0; c < kThin; ++c) bacc[c] += wide[c];
+        } else {    // dy is the one-channel side at v
+            thin_c = bf2f(dy[v]);
+            if (bias_wave) bacc[0] += thin_c;
+        }
+#pragma unroll
+        for (int t9 = 0; t9 < 3; ++t9) {
+            const int tap = tap0 + t9;
+            int64_t off;
+            if (!thin_tap(tap, z, y, xx, D, H, W, HW, off)) continue;
+            if (IN1) {
+                const float xt = bf2f(x[v + off]);
+#pragma unroll
+                for (int c = 0; c < kThin; ++c) acc[t9][c] = fmaf(wide[c], xt, acc[t9][c]);
+            } else {
+                const uint4 *p = reinterpret_cast<const uint4 *>(x + (v + off) * kThin);
+                const uint4 c0 = p[0], c1 = p[1];
+                const uint16_t *e0 = reinterpret_cast<const uint16_t *>(&c0);
+                const uint16_t *e1 = reinterpret_cast<const uint16_t *>(&c1);
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    acc[t9][i] = fmaf(thin_c, bf2f(e0[i]), acc[t9][i]);
+                    acc[t9][8 + i] = fmaf(thin_c, bf2f(e1[i]), acc[t9][8 + i]);
+                }
+            }
+        }
+    }
+    // butterfly over the 64 lanes (fixed order), lane 0 writes
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int c = 0; c < kThin; ++c) {
+            float sv = acc[t][c];
+#pragma unroll
+            for (int m = 32; m >= 1; m >>= 1) sv += __shfl_xor(sv, m, 64);
+            acc[t][c] = sv;
+        }
+#pragma unroll
+    for (int c = 0; c < kThin; ++c) {
+        float sv = bacc[c];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) sv += __shfl_xor(sv, m, 64);
+        bacc[c] = sv;
+    }
+    if (lane == 0) {
+        float *pb = part + (int64_t)blockIdx.x * 27 * kThin;
+#pragma unroll
+        for (int t9 = 0; t9 < 3; ++t9) {
+            const int tap = tap0 + t9;
+#pragma unroll
+            for (int c = 0; c < kThin; ++c) {
+                // (1, 16): dw[c][tap][0]; (16, 1): dw[0][tap][c]
+                pb[IN1 ? c * 27 + tap : tap * kThin + c] = acc[t9][c];
+            }
+        }
+        if (bias_wave) {
+            if (IN1)
+#pragma unroll
+                for (int c = 0; c < kThin; ++c) bpart[(int64_t)blockIdx.x * kThin + c] = bacc[c];
+            else
+                bpart[blockIdx.x] = bacc[0];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Element-wise and resampling kernels
 // ---------------------------------------------------------------------------
 __global__ void weight_pack_kernel(const float *__restrict__ w, int cin, int cout, uint16_t *__restrict__ wf,
@@ -524,13 +775,16 @@ int bad(const char *msg) { return rtm::set_error(RTM_EINVAL, msg); }
 
 bool ch_ok(int c) { return c == 16 || c == 32 || c == 64 || c == 128; }
 
+bool thin_pair(int ci, int co) { return (ci == 1 && co == kThin) || (ci == kThin && co == 1); }
+
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
 
 int check_desc(const unet_conv_desc_t *d)
 {
     if (!d) return bad("desc is NULL");
     if (d->n < 1 || d->d < 1 || d->h < 1 || d->w < 1) return bad("extents must be >= 1");
-    if (!ch_ok(d->cin) || !ch_ok(d->cout)) return bad("channel counts must be 16, 32, 64 or 128");
+    if (!(ch_ok(d->cin) && ch_ok(d->cout)) && !thin_pair(d->cin, d->cout))
+        return bad("channel counts must be 16, 32, 64 or 128, or the pair must be (1, 16) or (16, 1)");
     const int64_t nvox = (int64_t)d->n * d->d * d->h * d->w;
     if (nvox * (int64_t)(d->cin > d->cout ? d->cin : d->cout) >= ((int64_t)1 << 40))
         return bad("tensor too large");
@@ -559,6 +813,14 @@ int launch_fwd_ci(int co, const ConvArgs &a, hipStream_t st)
 
 int launch_fwd(int ci, int co, ConvArgs a, hipStream_t st)
 {
+    if (ci == 1 && co == kThin) {
+        hipLaunchKernelGGL(conv_thin_in_kernel, grid1(a.nvox), dim3(256), 0, st, a);
+        return 0;
+    }
+    if (ci == kThin && co == 1) {
+        hipLaunchKernelGGL(conv_thin_out_kernel, grid1(a.nvox), dim3(256), 0, st, a);
+        return 0;
+    }
     const int64_t waves = (a.nvox + 63) / 64;
     const int64_t blocks = (waves + 3) / 4;
     a.nblocks = (blocks + kNumXcd - 1) / kNumXcd * kNumXcd;
@@ -608,9 +870,23 @@ int wg_sizes_ci(int co, int64_t rows, int64_t *parts, int *S)
     return -1;
 }
 
+// One-channel layers: one partial per block of wgrad_thin_kernel, about
+// 256 voxels per block at the least.
+int thin_wg_blocks(int64_t nvox)
+{
+    int64_t b = nvox / 256;
+    if (b > kThinWgBlocks) b = kThinWgBlocks;
+    return b < 1 ? 1 : (int)b;
+}
+
 int wg_layout(const unet_conv_desc_t *d, int64_t *parts, int *S)
 {
     const int64_t rows = (int64_t)d->n * d->d * d->h;
+    if (thin_pair(d->cin, d->cout)) {
+        *S = thin_wg_blocks(rows * d->w);
+        *parts = *S;
+        return 0;
+    }
     switch (d->cin) {
     case 16: return wg_sizes_ci<16>(d->cout, rows, parts, S);
     case 32: return wg_sizes_ci<32>(d->cout, rows, parts, S);
@@ -695,6 +971,8 @@ int unet_conv3d_fwd(const unet_conv_desc_t *desc, const uint16_t *x, const uint1
     if (y && (y_channels < 1 || y_channels > desc->cout)) return bad("y_channels must be in [1, cout]");
     if (skip && !out) return bad("skip needs out");
     if (!aligned16(x) || !aligned16(w_fwd)) return bad("x and w_fwd must be 16-byte aligned");
+    if (desc->cin == 1 && !(aligned16(y) && aligned16(r) && aligned16(out) && aligned16(skip)))
+        return bad("for the (1, 16) pair y, r, out and skip must be 16-byte aligned");
     ConvArgs a{};
     a.x = x;
     a.wt = w_fwd;
@@ -721,6 +999,7 @@ int unet_conv3d_dgrad(const unet_conv_desc_t *desc, const uint16_t *dy, const ui
     if (int e = check_desc(desc)) return e;
     if (!dy || !w_bwd || !dx) return bad("dy, w_bwd and dx are required");
     if (!aligned16(dy) || !aligned16(w_bwd)) return bad("dy and w_bwd must be 16-byte aligned");
+    if (desc->cout == 1 && !aligned16(dx)) return bad("for the (16, 1) pair dx must be 16-byte aligned");
     ConvArgs a{};
     a.x = dy;
     a.wt = w_bwd;
@@ -778,7 +1057,14 @@ int unet_conv3d_wgrad(const unet_conv_desc_t *desc, const uint16_t *x, const uin
     a.w = desc->w;
     a.S = S;
     hipStream_t st = (hipStream_t)stream;
-    launch_wg(desc->cin, desc->cout, a, st);
+    if (desc->cin == 1)
+        hipLaunchKernelGGL(wgrad_thin_kernel<true>, dim3((unsigned)S, 3), dim3(192), 0, st, x, dy, a.rows * a.w, a.d,
+                           a.h, a.w, a.part, a.bpart);
+    else if (desc->cout == 1)
+        hipLaunchKernelGGL(wgrad_thin_kernel<false>, dim3((unsigned)S, 3), dim3(192), 0, st, x, dy, a.rows * a.w, a.d,
+                           a.h, a.w, a.part, a.bpart);
+    else
+        launch_wg(desc->cin, desc->cout, a, st);
     UNET_HIP(sum_parts(a.part, parts, nw, tmp_w, dw, st));
     if (db) UNET_HIP(sum_parts(a.bpart, parts, desc->cout, tmp_b, db, st));
     return RTM_OK;

@@ -18,8 +18,8 @@ additive skips, residual output):
     e4 = relu(c4(pool e3))    d3 = relu(c5(up e4)) + e3  d2 = relu(c6(up d3)) + e2
     d1 = relu(c7(up d2)) + e1 out = x + c8(d1)
 
-The one-channel input and output are stored as 16 channels (the extra
-channels and their weights are zero and stay zero under training).
+The one-channel input and output layers (c1: 1 -> 16, c8: 16 -> 1) run in
+the library's vector-unit kernels for those channel pairs.
 """
 from __future__ import annotations
 
@@ -34,10 +34,6 @@ from ._lib import UnetConvDesc, check, load
 LAYERS = (("c1", 1, 16), ("c2", 16, 32), ("c3", 32, 64), ("c4", 64, 128),
           ("c5", 128, 64), ("c6", 64, 32), ("c7", 32, 16), ("c8", 16, 1))
 _BF = torch.bfloat16
-
-
-def _pad(c):
-    return max(16, c)
 
 
 def _ptr(t):
@@ -154,19 +150,17 @@ class UNet:
         self.slots = {}
         off = 0
         for name, ci, co in LAYERS:
-            cip, cop = _pad(ci), _pad(co)
-            self.slots[name + ".w"] = (off, (cop, 27, cip))
-            off += cop * 27 * cip
-            self.slots[name + ".b"] = (off, (cop,))
-            off += cop
+            self.slots[name + ".w"] = (off, (co, 27, ci))
+            off += co * 27 * ci
+            self.slots[name + ".b"] = (off, (co,))
+            off += co
         self.nparam = off
         z = lambda: torch.zeros(off, dtype=torch.float32, device=self.dev)  # noqa: E731
         self.p, self.g, self.m, self.v = z(), z(), z(), z()
         self.wf, self.wb = {}, {}
         for name, ci, co in LAYERS:
-            cip, cop = _pad(ci), _pad(co)
-            self.wf[name] = torch.zeros((cop, 27 * cip), dtype=_BF, device=self.dev)
-            self.wb[name] = torch.zeros((cip, 27 * cop), dtype=_BF, device=self.dev)
+            self.wf[name] = torch.zeros((co, 27 * ci), dtype=_BF, device=self.dev)
+            self.wb[name] = torch.zeros((ci, 27 * co), dtype=_BF, device=self.dev)
         self.step_count = 0
         self._acts = None
         self._ws = None
@@ -181,11 +175,10 @@ class UNet:
     def set_params(self, P):
         host = np.zeros(self.nparam, np.float32)
         for name, ci, co in LAYERS:
-            off, (cop, _, cip) = self.slots[name + ".w"]
-            w = np.zeros((cop, 27, cip), np.float32)
-            w[:co, :, :ci] = np.transpose(np.asarray(P[name + ".w"]).reshape(co, ci, 27), (0, 2, 1))
+            off, _ = self.slots[name + ".w"]
+            w = np.transpose(np.asarray(P[name + ".w"], np.float32).reshape(co, ci, 27), (0, 2, 1))
             host[off:off + w.size] = w.ravel()
-            off, (cop,) = self.slots[name + ".b"]
+            off, _ = self.slots[name + ".b"]
             host[off:off + co] = np.asarray(P[name + ".b"])
         self.p.copy_(torch.from_numpy(host).to(self.dev))
         self.m.zero_()
@@ -197,8 +190,8 @@ class UNet:
         host = (self.p if buf is None else buf).detach().cpu().numpy().astype(np.float64)
         P = {}
         for name, ci, co in LAYERS:
-            off, (cop, _, cip) = self.slots[name + ".w"]
-            w = host[off:off + cop * 27 * cip].reshape(cop, 27, cip)[:co, :, :ci]
+            off, _ = self.slots[name + ".w"]
+            w = host[off:off + co * 27 * ci].reshape(co, 27, ci)
             P[name + ".w"] = np.transpose(w, (0, 2, 1)).reshape(co, ci, 3, 3, 3)
             off, _ = self.slots[name + ".b"]
             P[name + ".b"] = host[off:off + co].copy()
@@ -209,7 +202,7 @@ class UNet:
 
     def _pack(self):
         for name, ci, co in LAYERS:
-            weight_pack(self.view(self.p, name + ".w"), _pad(ci), _pad(co), self.wf[name], self.wb[name])
+            weight_pack(self.view(self.p, name + ".w"), ci, co, self.wf[name], self.wb[name])
 
     # -- buffers ------------------------------------------------------------
     def _buffers(self, shape):
@@ -227,9 +220,9 @@ class UNet:
         def f32(k, c):
             return torch.empty((vox[k], c), dtype=torch.float32, device=self.dev)
 
-        t = dict(x0=bf(0, 16), e1=bf(0, 16), p1=bf(1, 16), e2=bf(1, 32), p2=bf(2, 32), e3=bf(2, 64), p3=bf(3, 64),
+        t = dict(x0=bf(0, 1), e1=bf(0, 16), p1=bf(1, 16), e2=bf(1, 32), p2=bf(2, 32), e3=bf(2, 64), p3=bf(3, 64),
                  e4=bf(3, 128), u4=bf(2, 128), r5=bf(2, 64), d3=bf(2, 64), u3=bf(1, 64), r6=bf(1, 32), d2=bf(1, 32),
-                 u2=bf(0, 32), r7=bf(0, 16), d1=bf(0, 16), y8=f32(0, 1), out=f32(0, 1), gy8=bf(0, 16),
+                 u2=bf(0, 32), r7=bf(0, 16), d1=bf(0, 16), y8=f32(0, 1), out=f32(0, 1), gy8=bf(0, 1),
                  g_d1=f32(0, 16), gp7=bf(0, 16), g_u2=f32(0, 32), g_d2=f32(1, 32), gp6=bf(1, 32), g_u3=f32(1, 64),
                  g_d3=f32(2, 64), gp5=bf(2, 64), g_u4=f32(2, 128), g_e4=f32(3, 128), gp4=bf(3, 128),
                  g_p3=f32(3, 64), gp3=bf(2, 64), g_p2=f32(2, 32), gp2=bf(1, 32), g_p1=f32(1, 16), gp1=bf(0, 16))
@@ -242,8 +235,8 @@ class UNet:
 
     @staticmethod
     def _conv_levels():
-        return ((0, 16, 16), (1, 16, 32), (2, 32, 64), (3, 64, 128), (2, 128, 64), (1, 64, 32), (0, 32, 16),
-                (0, 16, 16))
+        return ((0, 1, 16), (1, 16, 32), (2, 32, 64), (3, 64, 128), (2, 128, 64), (1, 64, 32), (0, 32, 16),
+                (0, 16, 1))
 
     # -- forward / backward ---------------------------------------------------
     def forward(self, img, target=None, want_loss=True):
@@ -254,8 +247,8 @@ class UNet:
         t = self._buffers(shape)
         s = t["s"]
         b = lambda k: self.view(self.p, k)  # noqa: E731
-        embed(img, 16, 1.0, t["x0"])
-        conv3d_fwd(s[0], 16, 16, t["x0"], self.wf["c1"], b("c1.b"), True, out=t["e1"])
+        embed(img, 1, 1.0, t["x0"])
+        conv3d_fwd(s[0], 1, 16, t["x0"], self.wf["c1"], b("c1.b"), True, out=t["e1"])
         pool2(s[0], 16, t["e1"], t["p1"])
         conv3d_fwd(s[1], 16, 32, t["p1"], self.wf["c2"], b("c2.b"), True, out=t["e2"])
         pool2(s[1], 32, t["e2"], t["p2"])
@@ -268,8 +261,8 @@ class UNet:
         conv3d_fwd(s[1], 64, 32, t["u3"], self.wf["c6"], b("c6.b"), True, skip=t["e2"], r=t["r6"], out=t["d2"])
         up2(s[1], 32, t["d2"], t["u2"])
         conv3d_fwd(s[0], 32, 16, t["u2"], self.wf["c7"], b("c7.b"), True, skip=t["e1"], r=t["r7"], out=t["d1"])
-        conv3d_fwd(s[0], 16, 16, t["d1"], self.wf["c8"], b("c8.b"), False, y=t["y8"], y_channels=1)
-        loss = mse(img, t["y8"], target, t["out"], t["gy8"] if target is not None else None, 16,
+        conv3d_fwd(s[0], 16, 1, t["d1"], self.wf["c8"], b("c8.b"), False, y=t["y8"], y_channels=1)
+        loss = mse(img, t["y8"], target, t["out"], t["gy8"] if target is not None else None, 1,
                    self._mse_ws, want_loss=want_loss and target is not None)
         return t["out"].view(shape), loss
 
@@ -285,7 +278,7 @@ class UNet:
             if gx is not None:
                 conv3d_dgrad(s[k], ci, co, gp, self.wb[name], gx)
 
-        layer("c8", 0, 16, 16, t["d1"], t["gy8"], t["g_d1"])
+        layer("c8", 0, 16, 1, t["d1"], t["gy8"], t["g_d1"])
         relu_grad(s[0], 16, t["g_d1"], None, None, t["r7"], t["gp7"])
         layer("c7", 0, 32, 16, t["u2"], t["gp7"], t["g_u2"])
         up2_bwd(s[1], 32, t["g_u2"], t["g_d2"])
@@ -302,7 +295,7 @@ class UNet:
         relu_grad(s[1], 32, t["g_d2"], None, t["g_p2"], t["e2"], t["gp2"])
         layer("c2", 1, 16, 32, t["p1"], t["gp2"], t["g_p1"])
         relu_grad(s[0], 16, t["g_d1"], None, t["g_p1"], t["e1"], t["gp1"])
-        layer("c1", 0, 16, 16, t["x0"], t["gp1"])
+        layer("c1", 0, 1, 16, t["x0"], t["gp1"])
 
     def step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         self.step_count += 1
@@ -332,10 +325,10 @@ def layer_timings(net: UNet, img, target, reps=5):
     s = t["s"]
     n_img = img.shape[0]
     wsb = net._ws
-    plan = (("c1", 0, 16, 16, "x0", "e1", None, "gp1", None), ("c2", 1, 16, 32, "p1", "e2", None, "gp2", "g_p1"),
+    plan = (("c1", 0, 1, 16, "x0", "e1", None, "gp1", None), ("c2", 1, 16, 32, "p1", "e2", None, "gp2", "g_p1"),
             ("c3", 2, 32, 64, "p2", "e3", None, "gp3", "g_p2"), ("c4", 3, 64, 128, "p3", "e4", None, "gp4", "g_p3"),
             ("c5", 2, 128, 64, "u4", "d3", "e3", "gp5", "g_u4"), ("c6", 1, 64, 32, "u3", "d2", "e2", "gp6", "g_u3"),
-            ("c7", 0, 32, 16, "u2", "d1", "e1", "gp7", "g_u2"), ("c8", 0, 16, 16, "d1", None, None, "gy8", "g_d1"))
+            ("c7", 0, 32, 16, "u2", "d1", "e1", "gp7", "g_u2"), ("c8", 0, 16, 1, "d1", None, None, "gy8", "g_d1"))
     real = {n: (ci, co) for n, ci, co in LAYERS}
     b = lambda k: net.view(net.p, k)  # noqa: E731
     G = lambda k: net.view(net.g, k)  # noqa: E731
