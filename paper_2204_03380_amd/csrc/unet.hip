@@ -307,8 +307,17 @@ __global__ void sum_parts_kernel(const float *__restrict__ part, int64_t P, int6
     if (i >= n) return;
     const int64_t p0 = (int64_t)blockIdx.y * chunk;
     const int64_t p1 = p0 + chunk < P ? p0 + chunk : P;
+    // eight loads in flight, then added in the same increasing order
     float s = 0.f;
-    for (int64_t p = p0; p < p1; ++p) s += part[p * n + i];
+    int64_t p = p0;
+    for (; p + 8 <= p1; p += 8) {
+        float v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = part[(p + k) * n + i];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += v[k];
+    }
+    for (; p < p1; ++p) s += part[p * n + i];
     out[(int64_t)blockIdx.y * n + i] = s;
 }
 
