@@ -71,16 +71,19 @@ struct ConvArgs {
 
 // ---------------------------------------------------------------------------
 // Forward convolution (and input gradient with flipped weights).  One
-// wavefront computes 64 consecutive voxels x all COUT channels; the four
-// 16-voxel row blocks share each weight fragment and each activation
-// fragment feeds COUT / 16 MFMAs.
+// wavefront computes 64 consecutive voxels x CBW blocks of 16 output
+// channels (blockIdx.y selects the blocks; CBW = COUT / 16 unless a small
+// grid splits the channels over more wavefronts); the four 16-voxel row
+// blocks share each weight fragment and each activation fragment feeds CBW
+// MFMAs.  Every output element is the same sequence of MFMAs whatever CBW.
 // ---------------------------------------------------------------------------
-template <int CIN, int COUT>
+template <int CIN, int COUT, int CBW = COUT / 16>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a)
 {
     constexpr int K = 27 * CIN;
     constexpr int KP = (K + 31) / 32 * 32;
-    constexpr int CB = COUT / 16;
+    constexpr int CB = CBW;
+    const int cbase = blockIdx.y * CBW * 16;
     const int lane = threadIdx.x & 63;
     const int r16 = lane & 15, g = lane >> 4;
     const int64_t blk = xcd_block(blockIdx.x, a.nblocks);
@@ -128,17 +131,17 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a)
         uint4 B[CB];
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb)
-            B[cb] = tv ? *reinterpret_cast<const uint4 *>(a.wt + (int64_t)(cb * 16 + r16) * K + kk) : zero;
+            B[cb] = tv ? *reinterpret_cast<const uint4 *>(a.wt + (int64_t)(cbase + cb * 16 + r16) * K + kk) : zero;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(A[rb], B[cb], acc[rb][cb]);
     }
 
-    // Epilogue: lane holds voxels vb + rb*16 + 4g + e of channel cb*16 + r16.
+    // Epilogue: lane holds voxels vb + rb*16 + 4g + e of channel cbase + cb*16 + r16.
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb) {
-        const int co = cb * 16 + r16;
+        const int co = cbase + cb * 16 + r16;
         const float bias = a.bias ? a.bias[co] : 0.f;
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
@@ -802,10 +805,18 @@ int check_desc(const unet_conv_desc_t *d)
 
 dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
+// Grids of fewer wavefronts than the chip has SIMDs (the coarse levels)
+// split the output channels four ways (or as far as they go).
+constexpr int64_t kFwdSplitWaves = 1024;
+
 template <int CI, int CO>
 void launch_fwd_t(const ConvArgs &a, hipStream_t st)
 {
-    hipLaunchKernelGGL((conv_fwd_kernel<CI, CO>), dim3((unsigned)a.nblocks), dim3(256), 0, st, a);
+    constexpr int CB = CO / 16, CBW = CB >= 4 ? CB / 4 : 1;
+    if (CB > 1 && (a.nvox + 63) / 64 < kFwdSplitWaves)
+        hipLaunchKernelGGL((conv_fwd_kernel<CI, CO, CBW>), dim3((unsigned)a.nblocks, CB / CBW), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL((conv_fwd_kernel<CI, CO>), dim3((unsigned)a.nblocks), dim3(256), 0, st, a);
 }
 
 template <int CI>
