@@ -806,15 +806,19 @@ int check_desc(const unet_conv_desc_t *d)
 dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
 // Grids of fewer wavefronts than the chip has SIMDs (the coarse levels)
-// split the output channels four ways (or as far as they go).
+// split the output channels: four ways below a quarter of the SIMDs, two
+// ways above (each split re-reads the activations once more).
 constexpr int64_t kFwdSplitWaves = 1024;
 
 template <int CI, int CO>
 void launch_fwd_t(const ConvArgs &a, hipStream_t st)
 {
-    constexpr int CB = CO / 16, CBW = CB >= 4 ? CB / 4 : 1;
-    if (CB > 1 && (a.nvox + 63) / 64 < kFwdSplitWaves)
-        hipLaunchKernelGGL((conv_fwd_kernel<CI, CO, CBW>), dim3((unsigned)a.nblocks, CB / CBW), dim3(256), 0, st, a);
+    constexpr int CB = CO / 16, CBW4 = CB >= 4 ? CB / 4 : 1, CBW2 = CB >= 2 ? CB / 2 : 1;
+    const int64_t waves = (a.nvox + 63) / 64;
+    if (CB > 1 && waves < kFwdSplitWaves / 4)
+        hipLaunchKernelGGL((conv_fwd_kernel<CI, CO, CBW4>), dim3((unsigned)a.nblocks, CB / CBW4), dim3(256), 0, st, a);
+    else if (CB > 1 && waves < kFwdSplitWaves)
+        hipLaunchKernelGGL((conv_fwd_kernel<CI, CO, CBW2>), dim3((unsigned)a.nblocks, CB / CBW2), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((conv_fwd_kernel<CI, CO>), dim3((unsigned)a.nblocks), dim3(256), 0, st, a);
 }

@@ -88,6 +88,20 @@ def test_conv_forward_parity(ci, co):
     assert np.array_equal(host(out), U.bf16(yg + skip.astype(np.float32)))
 
 
+@pytest.mark.parametrize("ci,co,shape", [(128, 64, (1, 8, 8, 300)), (64, 128, (1, 2, 4, 300))])
+def test_conv_forward_channel_split_grids(ci, co, shape):
+    """Grids of 300 and 38 wavefronts, which split the output channels two
+    and four ways over the grid: same bar as the other forward tests."""
+    _, x, wo, b = _operands(shape, ci, co, 5 + ci + co)
+    wf, _ = pack(wo)
+    y = torch.empty((x.shape[0], co), dtype=torch.float32, device=DEV)
+    N.conv3d_fwd(shape, ci, co, bf_tensor(x), wf, f32(b), False, y=y)
+    ref = from_cf([U.conv3d(xc, U.bf16(wo), b) for xc in to_cf(x, shape, ci)])
+    e = rel_l2(host(y), ref)
+    print(f"conv fwd {ci}->{co} {shape}: rel-L2 {e:.2e}")
+    assert e < 1e-5
+
+
 @pytest.mark.parametrize("ci,co", PAIRS)
 def test_conv_dgrad_parity(ci, co):
     shape = (1, 6, 5, 41)
