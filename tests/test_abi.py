@@ -160,3 +160,36 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr and not r.stdout.strip()
+
+
+def test_unet_channel_pairs_on_the_host():
+    """The convolution entry points take two of 16/32/64/128 channels or the
+    one-channel pairs (1, 16) and (16, 1); anything else is rejected before
+    any launch.  The one-channel weight gradient's workspace holds one
+    partial of 27*16 weights and 16 (or 1) biases per block, for at most
+    2048 blocks of at least 256 voxels, plus the two-pass chunk sums."""
+    lib = _lib.load()
+    sz = ctypes.c_size_t(0)
+
+    def ws(shape, ci, co):
+        d = _lib.UnetConvDesc(*shape, ci, co)
+        return lib.unet_wgrad_ws_bytes(ctypes.byref(d), ctypes.byref(sz)), sz.value
+
+    def rnd(b):
+        return (b + 255) // 256 * 256
+
+    for ci, co in ((16, 16), (32, 64), (128, 64), (1, 16), (16, 1)):
+        rc, b = ws((1, 8, 8, 8), ci, co)
+        assert rc == _lib.RTM_OK and b > 0, (ci, co)
+    for ci, co in ((1, 32), (32, 1), (1, 1), (8, 16), (16, 8), (2, 16), (0, 16)):
+        rc, _ = ws((1, 8, 8, 8), ci, co)
+        assert rc == _lib.RTM_EINVAL, (ci, co)
+    # (1, 16) at 64^3: 262144 / 256 = 1024 blocks, one chunk sum per 32 partials
+    rc, b = ws((1, 64, 64, 64), 1, 16)
+    assert rc == _lib.RTM_OK and b == rnd(1024 * 432 * 4) + rnd(1024 * 16 * 4) + rnd(32 * 432 * 4) + rnd(32 * 16 * 4)
+    # (16, 1) at 128^3: capped at 2048 blocks
+    rc, b = ws((1, 128, 128, 128), 16, 1)
+    assert rc == _lib.RTM_OK and b == rnd(2048 * 432 * 4) + rnd(2048 * 4) + rnd(64 * 432 * 4) + rnd(64 * 4)
+    # tiny images still get one block
+    rc, b = ws((1, 2, 2, 2), 1, 16)
+    assert rc == _lib.RTM_OK and b == rnd(432 * 4) + rnd(16 * 4) + rnd(432 * 4) + rnd(16 * 4)
