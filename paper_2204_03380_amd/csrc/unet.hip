@@ -691,29 +691,52 @@ __global__ void up2_bwd_kernel(int n, int d, int h, int w, int c, const float *_
     gc[i] = s;
 }
 
+// VEC consecutive channels of one voxel per thread (VEC divides c); the
+// fine-to-coarse index is decoded once, in 32-bit arithmetic when it fits.
+template <int VEC>
 __global__ void relu_grad_kernel(int n, int d, int h, int w, int c, const float *__restrict__ g1,
                                  const float *__restrict__ g2, const float *__restrict__ gp,
                                  const uint16_t *__restrict__ mask, uint16_t *__restrict__ out)
 {
     const int64_t total = (int64_t)n * d * h * w * c;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    float g = g1[i];
-    if (g2) g += g2[i];
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+    if (i0 >= total) return;
+    float g[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) g[e] = g1[i0 + e];
+    if (g2)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) g[e] += g2[i0 + e];
     if (gp) {
-        int64_t t = i;
-        const int ch = (int)(t % c);
-        t /= c;
-        const int xf = (int)(t % w);
-        t /= w;
-        const int yf = (int)(t % h);
-        t /= h;
-        const int zf = (int)(t % d);
-        const int64_t nn = t / d;
+        int ch, xf, yf, zf;
+        int64_t nn;
+        if (total <= 0xffffffffll) {
+            uint32_t t = (uint32_t)i0;
+            ch = (int)(t % (uint32_t)c);
+            t /= (uint32_t)c;
+            xf = (int)(t % (uint32_t)w);
+            t /= (uint32_t)w;
+            yf = (int)(t % (uint32_t)h);
+            t /= (uint32_t)h;
+            zf = (int)(t % (uint32_t)d);
+            nn = t / (uint32_t)d;
+        } else {
+            int64_t t = i0;
+            ch = (int)(t % c);
+            t /= c;
+            xf = (int)(t % w);
+            t /= w;
+            yf = (int)(t % h);
+            t /= h;
+            zf = (int)(t % d);
+            nn = t / d;
+        }
         const int64_t vc = ((nn * (d / 2) + zf / 2) * (h / 2) + yf / 2) * (w / 2) + xf / 2;
-        g += gp[vc * c + ch] * 0.125f;
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) g[e] += gp[vc * c + ch + e] * 0.125f;
     }
-    out[i] = bf2f(mask[i]) > 0.f ? f2bf(g) : (uint16_t)0;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) out[i0 + e] = bf2f(mask[i0 + e]) > 0.f ? f2bf(g[e]) : (uint16_t)0;
 }
 
 constexpr int kMseBlocks = 1024;
@@ -1146,8 +1169,12 @@ int unet_relu_grad(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const 
     if (n < 1 || d < 1 || h < 1 || w < 1 || c < 1 || !g1 || !mask || !out) return bad("invalid relu_grad arguments");
     if (g_pool && ((d | h | w) & 1)) return bad("g_pool needs even extents");
     const int64_t total = (int64_t)n * d * h * w * c;
-    hipLaunchKernelGGL(relu_grad_kernel, grid1(total), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c, g1, g2,
-                       g_pool, mask, out);
+    if (c % 4 == 0)
+        hipLaunchKernelGGL(relu_grad_kernel<4>, grid1(total / 4), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c, g1,
+                           g2, g_pool, mask, out);
+    else
+        hipLaunchKernelGGL(relu_grad_kernel<1>, grid1(total), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c, g1, g2,
+                           g_pool, mask, out);
     UNET_HIP(hipGetLastError());
     return RTM_OK;
 }

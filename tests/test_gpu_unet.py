@@ -139,6 +139,29 @@ def test_conv_wgrad_parity_and_determinism(ci, co):
     assert e < 1e-5 and eb < 1e-5
 
 
+@pytest.mark.parametrize("c,with_g2", [(32, True), (32, False), (6, True)])
+def test_relu_grad_float32_exact(c, with_g2):
+    """relu_grad in float32 arithmetic, order g1 (+ g2) + g_pool/8, then one
+    bfloat16 rounding, masked: equal bit for bit to the same float32 steps
+    in numpy (4 channels per thread when 4 divides c, else one)."""
+    rng = np.random.default_rng(c + 2 * with_g2)
+    shape = (2, 6, 4, 10)
+    n, d, h, w = shape
+    cs = (n, d // 2, h // 2, w // 2)
+    nf = n * d * h * w
+    g1 = rng.standard_normal((nf, c)).astype(np.float32)
+    g2 = rng.standard_normal((nf, c)).astype(np.float32) if with_g2 else None
+    gp = rng.standard_normal((int(np.prod(cs)), c)).astype(np.float32)
+    mask = U.bf16(np.maximum(rng.standard_normal((nf, c)), 0))
+    out = torch.empty((nf, c), dtype=torch.bfloat16, device=DEV)
+    N.relu_grad(shape, c, f32(g1), f32(g2) if with_g2 else None, f32(gp), bf_tensor(mask), out)
+    up = gp.reshape(n, d // 2, h // 2, w // 2, c).repeat(2, 1).repeat(2, 2).repeat(2, 3).reshape(nf, c)
+    g = g1 + g2 if with_g2 else g1.copy()
+    g = g + up * np.float32(0.125)
+    ref = np.where(mask > 0, U.bf16(g.astype(np.float64)), 0.0)
+    assert np.array_equal(host(out), ref)
+
+
 def test_resampling_and_elementwise_kernels():
     rng = np.random.default_rng(3)
     shape, c = (2, 6, 4, 10), 32
