@@ -297,17 +297,28 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(WgArgs a)
     if (centre && gt < COUT) a.bpart[p * COUT + gt] = bacc;
 }
 
-// Fixed-order sum of P partial arrays of n floats: out[c][i] = sum of
-// partials c*chunk .. min(P, (c+1)*chunk) - 1 in increasing order (blockIdx.y
-// = c).  Two passes (chunks, then the chunk sums) give the same result on
-// every run.
+// Fixed-order sum of P partial arrays: out[c][i] = sum of partials
+// c*chunk .. min(P, (c+1)*chunk) - 1 in increasing order (blockIdx.y = c).
+// Two passes (chunks, then the chunk sums) give the same result on every
+// run.  One launch per pass covers two arrays (the weights, n0 floats per
+// partial, then the biases, n1), each summed on its own.
 constexpr int kSumChunk = 32;
 
-__global__ void sum_parts_kernel(const float *__restrict__ part, int64_t P, int64_t n, int chunk,
-                                 float *__restrict__ out)
+struct SumSet {
+    const float *part;
+    float *out;
+    int64_t n;
+};
+
+__global__ void sum_parts_kernel(SumSet s0, SumSet s1, int64_t P, int chunk)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool first = i < s0.n;
+    if (!first) i -= s0.n;
+    const SumSet &S = first ? s0 : s1;
+    if (i >= S.n) return;
+    const int64_t n = S.n;
+    const float *part = S.part;
     const int64_t p0 = (int64_t)blockIdx.y * chunk;
     const int64_t p1 = p0 + chunk < P ? p0 + chunk : P;
     // eight loads in flight, then added in the same increasing order
@@ -321,16 +332,20 @@ __global__ void sum_parts_kernel(const float *__restrict__ part, int64_t P, int6
         for (int k = 0; k < 8; ++k) s += v[k];
     }
     for (; p < p1; ++p) s += part[p * n + i];
-    out[(int64_t)blockIdx.y * n + i] = s;
+    S.out[(int64_t)blockIdx.y * n + i] = s;
 }
 
-hipError_t sum_parts(const float *part, int64_t P, int64_t n, float *tmp, float *out, hipStream_t st)
+// Sums P partials of n0 and of n1 floats (n1 may be 0) through tmp0 / tmp1
+// (Q = ceil(P / chunk) chunk sums each) into out0 / out1.
+hipError_t sum_parts(const float *part0, int64_t n0, float *tmp0, float *out0, const float *part1, int64_t n1,
+                     float *tmp1, float *out1, int64_t P, hipStream_t st)
 {
     const int64_t Q = (P + kSumChunk - 1) / kSumChunk;
-    const dim3 g1((unsigned)((n + 255) / 256), (unsigned)Q);
-    hipLaunchKernelGGL(sum_parts_kernel, g1, dim3(256), 0, st, part, P, n, kSumChunk, tmp);
-    hipLaunchKernelGGL(sum_parts_kernel, dim3((unsigned)((n + 255) / 256), 1), dim3(256), 0, st, tmp, Q, n, (int)Q,
-                       out);
+    const unsigned bx = (unsigned)((n0 + n1 + 255) / 256);
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(bx, (unsigned)Q), dim3(256), 0, st, SumSet{part0, tmp0, n0},
+                       SumSet{part1, tmp1, n1}, P, kSumChunk);
+    hipLaunchKernelGGL(sum_parts_kernel, dim3(bx, 1), dim3(256), 0, st, SumSet{tmp0, out0, n0},
+                       SumSet{tmp1, out1, n1}, Q, (int)Q);
     return hipGetLastError();
 }
 
@@ -1112,8 +1127,7 @@ int unet_conv3d_wgrad(const unet_conv_desc_t *desc, const uint16_t *x, const uin
                            a.h, a.w, a.part, a.bpart);
     else
         launch_wg(desc->cin, desc->cout, a, st);
-    UNET_HIP(sum_parts(a.part, parts, nw, tmp_w, dw, st));
-    if (db) UNET_HIP(sum_parts(a.bpart, parts, desc->cout, tmp_b, db, st));
+    UNET_HIP(sum_parts(a.part, nw, tmp_w, dw, a.bpart, db ? desc->cout : 0, tmp_b, db, parts, st));
     return RTM_OK;
 }
 
