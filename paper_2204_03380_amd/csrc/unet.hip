@@ -113,7 +113,8 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a)
 
     const uint4 zero = {0u, 0u, 0u, 0u};
     const int64_t HW = (int64_t)H * W;
-#pragma unroll 2
+    constexpr int UF = CB <= 2 ? 4 : 2;  // narrow waves keep more activation loads in flight
+#pragma unroll UF
     for (int kc = 0; kc < KP; kc += 32) {
         const int kk = kc + 8 * g;
         const int tap = kk / CIN;
