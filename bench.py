@@ -83,24 +83,53 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(survey, nt_sample):
+def _cpu_model():
+    """The host CPU's model name and the logical CPUs this process may use."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"model": name, "logical_cpus": os.cpu_count(), "usable_cpus": usable}
+
+
+def cpu_baseline(survey, nt_sample, nt_one_thread=200):
     """The FP64 oracle on a bounded sample of the same workload: one shot
-    (the first, on-grid source), modeling + RTM, nt_sample steps."""
+    (the first, on-grid source), modeling + RTM, nt_sample steps with the
+    oracle's default threads, and nt_one_thread steps on one thread."""
     import numpy as np
 
     import oracle
     s = survey
     v_pad = oracle.rbc_pad(s.v_int, s.nb, s.seed, 0.0)
-    w = s.wavelet[:nt_sample].astype(np.float64)
-    t0 = time.perf_counter()
-    d = oracle.model_shot(v_pad, s.h, s.nb, s.dt, w, s.src[0], s.rec)
-    oracle.rtm_shot(v_pad, s.h, s.nb, s.dt, w, s.src[0], s.rec, d, eps_rel=1e-3)
-    sec = time.perf_counter() - t0
-    updates = v_pad.size * nt_sample * 4
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": updates / sec / 1e9, "unit": "Gcell-updates/s", "cores": cores, "kind": "oracle",
+
+    def run(nt):
+        w = s.wavelet[:nt].astype(np.float64)
+        t0 = time.perf_counter()
+        d = oracle.model_shot(v_pad, s.h, s.nb, s.dt, w, s.src[0], s.rec)
+        oracle.rtm_shot(v_pad, s.h, s.nb, s.dt, w, s.src[0], s.rec, d, eps_rel=1e-3)
+        return time.perf_counter() - t0
+
+    cores = oracle.set_threads(0)
+    sec = run(nt_sample)
+    oracle.set_threads(1)
+    sec1 = run(nt_one_thread)
+    oracle.set_threads(cores)
+    rate = lambda nt, t: v_pad.size * nt * 4 / t / 1e9  # noqa: E731
+    return {"value": rate(nt_sample, sec), "unit": "Gcell-updates/s", "cores": cores, "kind": "oracle",
             "sample": f"1 shot, modeling + RTM (4 propagations), {nt_sample} of {s.nt} steps, FP64, "
-                      f"{sec:.1f} s"}
+                      f"{sec:.1f} s on {cores} threads",
+            "host_cpu": _cpu_model(), "fp_env": oracle.fp_env(),
+            "one_thread": {"value": rate(nt_one_thread, sec1), "unit": "Gcell-updates/s",
+                           "sample": f"same shot, {nt_one_thread} steps, {sec1:.1f} s on 1 thread"}}
 
 
 def unet_report(steps=10):
@@ -338,24 +367,36 @@ def device_info():
 
 
 def copy_rate(dev, mib=2048, reps=5):
-    """Device-to-device copy rate (read + write bytes / time) of a 2 GiB
-    buffer: what a plain streaming kernel reaches on this GPU, beside the
-    8 TB/s peak."""
+    """Device-to-device copy rates (read + write bytes / time) of a 2 GiB
+    buffer: torch's copy, and the library's streaming copy kernel (16-byte
+    nontemporal loads and stores) at a few grid sizes, the best of which is
+    the measured bandwidth reference for the propagation kernels."""
     import torch
+
+    import paper_2204_03380_amd as rtm
     a = torch.ones(mib << 18, dtype=torch.float32, device=dev)
     b = torch.empty_like(a)
-    b.copy_(a)
-    torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e1.record()
-    e1.synchronize()
-    gbps = 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return 2 * a.numel() * 4 * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+
+    out = {"torch_copy_GBps": round(timed(lambda: b.copy_(a)), 1), "stream_copy_GBps": {}}
+    for bpc in (2, 4, 8, 16):
+        out["stream_copy_GBps"][bpc] = round(timed(lambda: rtm.rtm_stream_copy(a, b, bpc)), 1)
+    assert torch.equal(a, b)
+    best = max(out["stream_copy_GBps"].items(), key=lambda kv: kv[1])
+    out["best_stream_copy"] = {"blocks_per_cu": best[0], "GBps": best[1]}
     del a, b
     torch.cuda.empty_cache()
-    return round(gbps, 1)
+    return out
 
 
 def main():
@@ -404,7 +445,8 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    copy_gbps = copy_rate(dev)
+    copy = copy_rate(dev)
+    copy_gbps = copy["best_stream_copy"]["GBps"]
     if args.vec and args.zseg:
         rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, args.vec, args.zseg)
         rtm.rtm_set_tuning(rtm.RTM_OP_RTM, args.vec, args.zseg)
@@ -475,24 +517,34 @@ def main():
     plain_shots = groups[0][:min(B, args.plain_shots)]
     torch.cuda.synchronize()
     p0 = time.perf_counter()
-    plain_imgs = []
+    plain = []
     for i in plain_shots:
         d = rtm.rtm_model_shot(g, v_pad, s.dt, wav, s.src[i], s.rec)
-        plain_imgs.append(rtm.rtm_rtm_shot(g, v_pad, s.dt, wav, s.src[i], s.rec, d, eps_rel=1e-3)["image"])
+        plain.append((d, rtm.rtm_rtm_shot(g, v_pad, s.dt, wav, s.src[i], s.rec, d, eps_rel=1e-3)["image"]))
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - p0
-    one = torch.zeros_like(stack)
-    check = rtm.BatchPlan(rtm.RTM_OP_RTM, [rtm.BatchShot(g, v_pad, wav, s.src[i], s.rec, traces_in=traces[j],
-                                                         image=one) for j, i in enumerate(plain_shots)],
-                          s.dt, nt, eps_rel=1e-3, flags=rtm.RTM_F_ACCUMULATE, ws=ws)
+    # The batched side of the comparison is the timed configuration itself:
+    # the first group's modeling plan as timed, then an RTM plan of the same
+    # B shots at the same launch shape writing one image per shot.  Its launch
+    # count (loop timing) shows which kernel ran.
     mp0, _ = plans[0]
     mp0.run()
-    check.run()
-    ref = torch.zeros_like(stack)
-    for im in plain_imgs:
-        ref += im
+    imgs = torch.empty((B,) + tuple(g.interior_shape), dtype=torch.float32, device=dev)
+    check = rtm.BatchPlan(rtm.RTM_OP_RTM, [rtm.BatchShot(g, v_pad, wav, s.src[i], s.rec, traces_in=traces[j],
+                                                         image=imgs[j]) for j, i in enumerate(groups[0])],
+                          s.dt, nt, eps_rel=1e-3, ws=ws)
     torch.cuda.synchronize()
-    batch_vs_plain = float(torch.linalg.norm(one - ref) / torch.linalg.norm(ref))
+    rtm.rtm_timing_read()
+    rtm.rtm_timing_enable(True)
+    check.run()
+    torch.cuda.synchronize()
+    rtm.rtm_timing_enable(False)
+    check_launches = rtm.rtm_timing_read()["reverse_image"][1]
+    check.free()
+    tr_equal = all(torch.equal(d, traces[j]) for j, (d, _) in enumerate(plain))
+    batch_vs_plain = max(float(torch.linalg.norm(imgs[j] - im) / torch.linalg.norm(im))
+                         for j, (_, im) in enumerate(plain))
+    del imgs, plain
 
     # Dominant kernel: the fused reverse kernel (two stencils, imaging sums),
     # one launch covering the B shots of a batch and one to three time steps.
@@ -509,10 +561,15 @@ def main():
     achieved = rev_bytes / (rev_us * 1e-6) / 1e9
     one_step_bytes = B * (28 * cells + 16 * interior)
     per_step_us = rev_us / steps_r
+    traffic = reverse_traffic(B, rev_shape, steps_r)
     rev_kernel = (f"rev2d_t{steps_r}_kernel<{rev_shape[0]}> ({steps_r} reverse steps per launch: reconstruction + "
                   f"receiver field + imaging, {B} shots per launch)" if steps_r >= 2 else
                   f"rev2d_kernel<{rev_shape[0]},false,{rev_shape[1]}> (fused reconstruction + receiver field + "
                   f"imaging, {B} shots per launch)")
+    # the reverse launches of the check plan: nt // steps multi-step launches
+    # plus the nt % steps single steps
+    check_kernel = (f"rev2d_t{steps_r}_kernel<{rev_shape[0]}> at the timed shape, {B} shots"
+                    if check_launches == nt // steps_r + nt % steps_r else f"{check_launches} launches")
     fwd_ms, fwd_n = loops["model_forward"]
     rf_ms, rf_n = loops["rtm_forward"]
     line = {
@@ -546,22 +603,37 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": reverse_traffic(B, rev_shape, steps_r),
+            "traffic": traffic,
             "avg_launch_us": round(rev_us, 3),
             "algorithmic_bytes_per_launch": rev_bytes,
-            "device_copy_GBps": copy_gbps,
-            "frac_of_device_copy": round(achieved / copy_gbps, 4) if copy_gbps else None,
+            "fractions": {
+                "compulsory": round(achieved / HBM_PEAK_GBS, 4),
+                "counter_traffic": (round(traffic / (rev_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)
+                                    if traffic else None),
+                "one_step_equivalent": round(one_step_bytes / (per_step_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                "note": (f"compulsory: this kernel's minimum bytes per launch ({steps_r} steps read p^k, p^(k+1), "
+                         "mu^(k+1), mu^(k+2), D' once and write the last two levels of both fields, 36 B per "
+                         "padded cell, plus num and den read and written once, 16 B per interior cell) over the "
+                         "measured launch time; counter_traffic: the HBM bytes the counters saw per launch over "
+                         "the same time; one_step_equivalent: a one-step kernel's minimum bytes per step (28 B "
+                         "per padded cell + 16 B per interior cell) over the measured time per step, which "
+                         "exceeds 1 because the steps of a launch share one pass over memory"),
+            },
+            "stream_copy_GBps": copy_gbps,
+            "frac_of_stream_copy": round(achieved / copy_gbps, 4) if copy_gbps else None,
+            "copy_reference": copy,
             "steps_per_launch": steps_r,
             "per_step": {"us": round(per_step_us, 3),
                          "one_step_algorithmic_bytes": one_step_bytes,
-                         "equivalent_GBps": round(one_step_bytes / (per_step_us * 1e-6) / 1e9, 1),
-                         "note": "rate a one-step kernel would need to move its own minimum bytes in the "
-                                 "time of one step"},
+                         "equivalent_GBps": round(one_step_bytes / (per_step_us * 1e-6) / 1e9, 1)},
         },
         "rtm_shots_per_s": {"batched": round(shots / (dev_ms * 1e-3), 4),
                             "plain": round(len(plain_shots) / plain_s, 4),
                             "image_rel_l2_batched_vs_plain": batch_vs_plain,
-                            "note": "one shot = modeling + RTM; plain = sequential single-shot calls"},
+                            "traces_equal_batched_vs_plain": tr_equal,
+                            "checked_kernel": check_kernel,
+                            "note": "one shot = modeling + RTM; plain = sequential single-shot calls; the check "
+                                    f"compares {len(plain_shots)} shots of a {B}-shot plan at the timed shape"},
         "steps_per_launch": {"forward": steps_f, "reverse": steps_r},
         "loop_us_per_launch": {
             "model_forward": round(fwd_ms * 1e3 / max(fwd_n, 1), 3),

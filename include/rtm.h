@@ -124,7 +124,9 @@ const char *rtm_last_error(void);
  * synchronised with concurrent calls. */
 #define RTM_TUNE_EXACT 0x100
 int rtm_set_tuning(int op, int vec, int zseg);
-/* Current launch shape for `op` (same selection as rtm_set_tuning). */
+/* Current launch shape for `op` (same selection as rtm_set_tuning);
+ * op RTM_TUNE_EXACT returns the no-narrowing setting (0 or 1) in *vec and 0
+ * in *zseg. */
 int rtm_get_tuning(int op, int *vec, int *zseg);
 
 /* Full 2-D launch shape: as rtm_set_tuning plus tx in {1, 2, 4}
@@ -405,6 +407,16 @@ int rtm_window_accumulate(int64_t nz, int64_t nx_global, int64_t x0, int64_t wid
 int rtm_misfit_ws_bytes(size_t *bytes);
 int rtm_l2_misfit(int64_t n, const float *d, const float *d_obs, float *residual, double *J, void *ws,
                   size_t ws_bytes, void *stream);
+
+/* Streaming device-to-device copy of `bytes` bytes (16-byte loads and
+ * stores, each read and written once), queued on `stream`: the measured
+ * bandwidth reference for the propagation kernels' roofline (a plain
+ * streaming kernel of known traffic, 2 * bytes per call).  src and dst are
+ * device buffers that must not overlap; both addresses and `bytes` must be
+ * multiples of 16 (RTM_EINVAL otherwise).  blocks_per_cu in [1, 64] sets the
+ * grid: 256 workgroups of 256 threads per unit, each striding over the
+ * buffer. */
+int rtm_stream_copy(const void *src, void *dst, size_t bytes, int blocks_per_cu, void *stream);
 
 #ifdef __cplusplus
 }

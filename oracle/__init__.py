@@ -44,6 +44,10 @@ def _load():
                                      P, P, c_int, P, P, c_int, c_double, P, P, P, P, P, c_int, P, P]
         lib.orc_rtm_storage_shot.argtypes = [c_int, c_long, c_long, c_long, c_int, c_double, P, c_double, c_int,
                                              P, P, c_int, P, P, c_int, c_int, c_double, P, P, P]
+        lib.orc_set_threads.argtypes = [c_int]
+        lib.orc_set_threads.restype = c_int
+        lib.orc_fp_env.argtypes = []
+        lib.orc_fp_env.restype = c_int
         for f in ("orc_rbc_pad", "orc_pad_adjoint", "orc_laplacian", "orc_model_shot", "orc_rtm_shot",
                   "orc_rtm_storage_shot", "orc_rbc_pad_ex", "orc_pad_adjoint_ex", "orc_taper"):
             getattr(lib, f).restype = c_int
@@ -221,3 +225,16 @@ def rtm_storage_shot(v_pad, h, nb, dt, wavelet, src, rec, g, stride, phase=0, ep
                                       _ptr(out["den"]), _ptr(out["image"]))
     _check(rc, "orc_rtm_storage_shot")
     return out
+
+
+def set_threads(n: int = 0) -> int:
+    """Threads the oracle's parallel loops use from now on (n >= 1; 0 only
+    queries); returns the count in effect."""
+    return int(_load().orc_set_threads(int(n)))
+
+
+def fp_env() -> dict:
+    """Denormal handling of the oracle's floating point: flush-to-zero and
+    denormals-are-zero flags of the calling thread."""
+    v = int(_load().orc_fp_env())
+    return {"ftz": bool(v & 1), "daz": bool(v & 2)}

@@ -25,9 +25,13 @@
  * fused or reordered beyond what the definition itself states.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <xmmintrin.h>
 
 /* ------------------------------------------------------------------ */
 /* Grid bookkeeping                                                    */
@@ -665,4 +669,29 @@ int orc_rtm_storage_shot(int ndim, long nx, long ny, long nz, int nb, double h, 
     free(den);
     free(rp);
     return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Run environment of the timed baseline (no arithmetic)               */
+/* ------------------------------------------------------------------ */
+
+/* Threads of the parallel loops from now on (n >= 1); returns the count in
+ * effect afterwards. */
+int orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
+/* The calling thread's SSE control state: bit 0 set if denormal results are
+ * flushed to zero (FTZ), bit 1 if denormal inputs are read as zero (DAZ). */
+int orc_fp_env(void)
+{
+    const unsigned csr = _mm_getcsr();
+    return ((csr >> 15) & 1u) | (((csr >> 6) & 1u) << 1);
 }

@@ -93,6 +93,40 @@ def conv3d_wgrad(x, dy):
     return dw, dy.sum(axis=(1, 2, 3))
 
 
+def conv3d_at(x, w, b, points):
+    """Forward convolution at chosen voxels only, from the definition:
+    y[o, p] = b[o] + sum_{i, k} w[o, i, k] x[i, p + k - 1], with x = 0 outside.
+    points: (n, 3) integer (z, y, x); returns (n, Cout)."""
+    C, D, H, W = x.shape
+    x = np.asarray(x, np.float64)
+    out = np.zeros((len(points), w.shape[0]))
+    for j, (z, y, xx) in enumerate(np.asarray(points, np.int64)):
+        acc = np.zeros(w.shape[0]) if b is None else np.asarray(b, np.float64).copy()
+        for kz, ky, kx in _taps():
+            q = (z + kz - 1, y + ky - 1, xx + kx - 1)
+            if 0 <= q[0] < D and 0 <= q[1] < H and 0 <= q[2] < W:
+                acc += w[:, :, kz, ky, kx] @ x[:, q[0], q[1], q[2]]
+        out[j] = acc
+    return out
+
+
+def conv3d_dgrad_at(dy, w, points):
+    """Input gradient at chosen voxels only, from the definition:
+    dx[i, q] = sum_{o, k} w[o, i, k] dy[o, q - k + 1], dy = 0 outside.
+    points: (n, 3) integer (z, y, x); returns (n, Cin)."""
+    O, D, H, W = dy.shape
+    dy = np.asarray(dy, np.float64)
+    out = np.zeros((len(points), w.shape[1]))
+    for j, (z, y, xx) in enumerate(np.asarray(points, np.int64)):
+        acc = np.zeros(w.shape[1])
+        for kz, ky, kx in _taps():
+            q = (z - kz + 1, y - ky + 1, xx - kx + 1)
+            if 0 <= q[0] < D and 0 <= q[1] < H and 0 <= q[2] < W:
+                acc += w[:, :, kz, ky, kx].T @ dy[:, q[0], q[1], q[2]]
+        out[j] = acc
+    return out
+
+
 def pool2(x):
     """Mean over 2x2x2 blocks."""
     C, D, H, W = x.shape

@@ -24,6 +24,8 @@ __all__ = [
     "rtm_nyquist_stride", "rtm_storage_count", "rtm_storage_shot", "RTM_OP_STORAGE",
     "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD", "RTM_F_ACCUMULATE", "RTM_F_GRAPH", "RTM_F_CHECK_FINITE", "RTM_TUNE_EXACT",
     "BatchShot", "BatchPlan", "rtm_window_extract", "rtm_window_accumulate", "rtm_l2_misfit",
+    "rtm_set_tuning2d", "rtm_get_tuning2d", "rtm_set_steps_per_launch", "rtm_get_steps_per_launch",
+    "tuning_snapshot", "tuning_restore", "rtm_stream_copy",
 ]
 
 
@@ -141,6 +143,26 @@ def rtm_get_tuning(op: int):
     v, z = ctypes.c_int(0), ctypes.c_int(0)
     _lib.check(_lib.load().rtm_get_tuning(op, ctypes.byref(v), ctypes.byref(z)))
     return int(v.value), int(z.value)
+
+
+def tuning_snapshot() -> dict:
+    """The process-wide launch settings (2-D and 3-D shapes, 2-D steps per
+    launch, the no-narrowing flag), for tuning_restore."""
+    snap = {"exact": rtm_get_tuning(RTM_TUNE_EXACT)[0]}
+    for op in (RTM_OP_MODEL, RTM_OP_RTM):
+        snap[("2d", op)] = rtm_get_tuning2d(op)
+        snap[("steps", op)] = rtm_get_steps_per_launch(op)
+        snap[("3d", op)] = rtm_get_tuning3d(op)
+    return snap
+
+
+def tuning_restore(snap: dict) -> None:
+    """Sets the launch settings recorded by tuning_snapshot."""
+    rtm_set_tuning(RTM_TUNE_EXACT, int(snap["exact"]), 0)
+    for op in (RTM_OP_MODEL, RTM_OP_RTM):
+        rtm_set_tuning2d(op, *snap[("2d", op)])
+        rtm_set_steps_per_launch(op, snap[("steps", op)])
+        rtm_set_tuning3d(op, *snap[("3d", op)])
 
 
 LOOP_KINDS = ("model_forward", "rtm_forward", "reverse_image", "reverse_grad")
@@ -356,6 +378,20 @@ def rtm_l2_misfit(d: torch.Tensor, d_obs: torch.Tensor, want_residual: bool = Tr
     return J, r
 
 
+def rtm_stream_copy(src: torch.Tensor, dst: torch.Tensor, blocks_per_cu: int = 8) -> None:
+    """dst <- src with the library's streaming copy kernel (the bandwidth
+    reference of the measurements); both contiguous device tensors of the
+    same byte size, a multiple of 16."""
+    for t, name in ((src, "src"), (dst, "dst")):
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous CUDA (HIP) tensor")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("src and dst differ in size")
+    _lib.check(_lib.load().rtm_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, int(blocks_per_cu),
+                                           _stream(src.device)))
+
+
 @dataclass
 class BatchShot:
     """One shot of a batch (see rtm_shot_desc_t): its grid, padded model,
@@ -427,17 +463,35 @@ class BatchPlan:
         else:
             self.ws = torch.empty(max(self.ws_bytes, 256), dtype=torch.uint8, device=self.device)
 
+    def tensors(self):
+        """Every device tensor the plan's runs read or write: the workspace,
+        then each shot's buffers."""
+        out = [self.ws]
+        for s in self._shots:
+            out += [t for t in (s.v_pad, s.wavelet, s.traces_in, s.traces_out, s.image, s.grad_v_pad)
+                    if t is not None]
+        return out
+
     def run(self, stream: "torch.cuda.Stream" = None) -> None:
-        """Runs the plan on `stream` (default: the current stream).  A stream
-        other than the current one first waits for the current one: the
-        workspace and the inputs were allocated and written there, and
-        memory that torch hands out on it may still be in use by work queued
-        on it."""
+        """Runs the plan on `stream` (default: the current stream).
+
+        On a stream other than the current one, both orders of torch's
+        stream-ordered memory reuse are covered: the stream first waits for
+        the current one (the workspace and inputs were allocated and written
+        there, and memory torch hands out on it may still be read by work
+        queued on it), and every tensor the run touches is marked as used on
+        `stream` (record_stream), so that freeing one on the current stream
+        afterwards does not let torch hand its memory out again before the
+        run has finished with it."""
         cur = torch.cuda.current_stream(self.device)
-        if stream is not None and stream.cuda_stream != cur.cuda_stream:
+        side = stream is not None and stream.cuda_stream != cur.cuda_stream
+        if side:
             stream.wait_stream(cur)
         st = stream.cuda_stream if stream is not None else cur.cuda_stream
         _lib.check(_lib.load().rtm_batch_run(self._plan, self.ws.data_ptr(), self.ws.numel(), st))
+        if side:
+            for t in self.tensors():
+                t.record_stream(stream)
 
     def free(self) -> None:
         if getattr(self, "_plan", None) is not None and self._plan.value:

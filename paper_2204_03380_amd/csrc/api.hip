@@ -51,6 +51,7 @@ hipError_t launch_recv3d(int vec, int ty, const ShotDev *shots, const Tile3D *ti
 // aux.hip
 hipError_t launch_vrange(const float *v, int64_t n, unsigned *maxmin2, hipStream_t st);
 hipError_t launch_vmax(const float *v, int64_t n, unsigned *out, hipStream_t st);
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t units, int blocks_per_cu, hipStream_t st);
 hipError_t launch_rbc_pad(int ndim, int nb, int64_t nx, int64_t ny, int64_t nz, const float *v_int, uint64_t seed,
                           float v_cap, const unsigned *cap_bits, const BandOpts &o, float *v_pad, hipStream_t st);
 hipError_t launch_pad_adjoint(int ndim, int nb, int64_t nx, int64_t ny, int64_t nz, const float *v_int,
@@ -1337,6 +1338,11 @@ int rtm_get_tuning3d(int op, int *vec, int *ty, int *zseg)
 int rtm_get_tuning(int op, int *vec, int *zseg)
 {
     if (!vec || !zseg) return fail(RTM_EINVAL, "NULL output");
+    if (op == RTM_TUNE_EXACT) {
+        *vec = g_tune_exact.load();
+        *zseg = 0;
+        return RTM_OK;
+    }
     if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
     Tune t = get_tune(op == RTM_OP_MODEL ? 0 : 1, 2);
     *vec = t.vec;
@@ -1681,6 +1687,19 @@ int rtm_l2_misfit(int64_t n, const float *d, const float *d_obs, float *residual
     if (!ws || ws_bytes < misfit_ws_bytes() || ((uintptr_t)ws & 255))
         return fail(RTM_EWORKSPACE, "misfit workspace of %zu aligned bytes needed", misfit_ws_bytes());
     RTM_HIP(launch_misfit(d, d_obs, residual, n, ws, J, (hipStream_t)stream));
+    return RTM_OK;
+}
+
+int rtm_stream_copy(const void *src, void *dst, size_t bytes, int blocks_per_cu, void *stream)
+{
+    t_err.clear();
+    if (!src || !dst) return fail(RTM_EINVAL, "NULL buffer");
+    if (((uintptr_t)src & 15) || ((uintptr_t)dst & 15) || (bytes & 15))
+        return fail(RTM_EINVAL, "buffers and size must be multiples of 16 bytes");
+    if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(RTM_EINVAL, "blocks_per_cu must be in [1, 64]");
+    const uintptr_t a = (uintptr_t)src, b = (uintptr_t)dst;
+    if (a < b + bytes && b < a + bytes && bytes > 0) return fail(RTM_EINVAL, "buffers overlap");
+    RTM_HIP(launch_stream_copy(src, dst, (int64_t)(bytes / 16), blocks_per_cu, (hipStream_t)stream));
     return RTM_OK;
 }
 

@@ -430,12 +430,51 @@ static PadDims pad_dims(int ndim, int nb, int64_t nx, int64_t ny, int64_t nz)
     return d;
 }
 
+// Streaming copy of n 16-byte units: the bandwidth reference of the
+// measurements (a plain read-once, write-once kernel of known size).  Each
+// thread keeps kCopyUnroll independent 16-byte loads in flight; a block's
+// loads of one round are contiguous (kBlock x 16 B per unrolled slot), and
+// blocks stride over the buffer in whole rounds.
+constexpr int kCopyUnroll = 4;
+typedef float copy4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kBlock) void stream_copy_kernel(const copy4 *__restrict__ src,
+                                                             copy4 *__restrict__ dst, int64_t n)
+{
+    const int64_t round = (int64_t)kBlock * kCopyUnroll;
+    for (int64_t base = (int64_t)blockIdx.x * round; base < n; base += (int64_t)gridDim.x * round) {
+        copy4 v[kCopyUnroll];
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) {
+            const int64_t i = base + (int64_t)u * kBlock + threadIdx.x;
+            if (i < n) v[u] = __builtin_nontemporal_load(src + i);
+        }
+#pragma unroll
+        for (int u = 0; u < kCopyUnroll; ++u) {
+            const int64_t i = base + (int64_t)u * kBlock + threadIdx.x;
+            if (i < n) __builtin_nontemporal_store(v[u], dst + i);
+        }
+    }
+}
+
 hipError_t launch_vrange(const float *v, int64_t n, unsigned *maxmin2, hipStream_t st)
 {
     hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(64), 0, st, maxmin2, 1, 0u);
     hipLaunchKernelGGL(set_u32_kernel, dim3(1), dim3(64), 0, st, maxmin2 + 1, 1, 0xffffffffu);
     hipLaunchKernelGGL(vmax_bits_kernel, dim3(grid_reduce(n)), dim3(kBlock), 0, st, v, n, maxmin2);
     hipLaunchKernelGGL(vmin_bits_kernel, dim3(grid_reduce(n)), dim3(kBlock), 0, st, v, n, maxmin2 + 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void *src, void *dst, int64_t units, int blocks_per_cu, hipStream_t st)
+{
+    if (units <= 0) return hipSuccess;
+    const int64_t round = (int64_t)kBlock * kCopyUnroll;
+    int64_t b = (units + round - 1) / round;
+    const int64_t cap = (int64_t)256 * blocks_per_cu;
+    if (b > cap) b = cap;
+    hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)b), dim3(kBlock), 0, st, (const copy4 *)src, (copy4 *)dst,
+                       units);
     return hipGetLastError();
 }
 

@@ -11,3 +11,19 @@ if ROOT not in sys.path:
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU and the built HIP library")
     config.addinivalue_line("markers", "slow: long-running CPU check")
+
+
+@pytest.fixture(autouse=True)
+def _restore_launch_settings(request):
+    """The library's launch shapes and steps per launch are process-wide:
+    every GPU test gets them back as it found them, so that which kernel a
+    test exercises does not depend on the tests run before it."""
+    if request.node.get_closest_marker("gpu") is None:
+        yield
+        return
+    import paper_2204_03380_amd as rtm
+    snap = rtm.tuning_snapshot()
+    try:
+        yield
+    finally:
+        rtm.tuning_restore(snap)

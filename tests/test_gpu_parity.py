@@ -347,38 +347,91 @@ def test_folded_grid_bench_launch_shape():
     """The benchmark's launch configuration (three steps per launch, two
     floats per lane, 108-row tiles, one tile list for several shots) on the
     full 2301 x 751 folded-layer grid for 300 steps: a three-shot batch of
-    modeling and RTM, one shot's traces and image against the oracle, every
-    shot against one-step single-shot calls bit for bit."""
+    modeling and RTM.  The half-cell shot's GPU traces against the oracle's;
+    its GPU image, migrated from the oracle's traces, against the oracle's
+    image of the same traces; every shot against one-step single-shot calls
+    on the same inputs, bit for bit."""
     s = synth.config_c2(nshot=3, nt=300)
     g, vg, vo = _setup(s)
     w = _t(s.wavelet)
-    srcs = [s.src[i] for i in range(3)]
-    rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
-    try:
-        for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
-            rtm.rtm_set_tuning2d(op, 2, 1, 108)
-            rtm.rtm_set_steps_per_launch(op, 3)
-        traces = [torch.empty((s.rec.shape[0], s.nt + 1), device=DEV) for _ in srcs]
-        plan = rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, vg, w, x, s.rec, traces_out=t)
-                                                for x, t in zip(srcs, traces)], s.dt, s.nt)
-        plan.run()
-        imgs = [torch.empty(g.interior_shape, device=DEV) for _ in srcs]
-        plan = rtm.BatchPlan(rtm.RTM_OP_RTM, [rtm.BatchShot(g, vg, w, x, s.rec, traces_in=t, image=im)
-                                              for x, t, im in zip(srcs, traces, imgs)], s.dt, s.nt, eps_rel=EPS)
-        plan.run()
-        got_tr, got_im = [_n(t) for t in traces], [_n(im) for im in imgs]
-        for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
-            rtm.rtm_set_tuning2d(op, 1, 1, 18)
-            rtm.rtm_set_steps_per_launch(op, 1)
-        for x, tr, im in zip(srcs, got_tr, got_im):
-            ref_tr = rtm.rtm_model_shot(g, vg, s.dt, w, x, s.rec)
-            ref_im = rtm.rtm_rtm_shot(g, vg, s.dt, w, x, s.rec, ref_tr, eps_rel=EPS)["image"]
-            assert np.array_equal(tr, _n(ref_tr)) and np.array_equal(im, _n(ref_im))
-    finally:
-        rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 0, 0)
     w64 = s.wavelet.astype(np.float64)
+    srcs = [s.src[i] for i in range(3)]
     tr_o = oracle.model_shot(vo, s.h, s.nb, s.dt, w64, srcs[1], s.rec)
-    ref = oracle.rtm_shot(vo, s.h, s.nb, s.dt, w64, srcs[1], s.rec, got_tr[1].astype(np.float64), eps_rel=EPS)
+    rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
+    for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
+        rtm.rtm_set_tuning2d(op, 2, 1, 108)
+        rtm.rtm_set_steps_per_launch(op, 3)
+    traces = [torch.empty((s.rec.shape[0], s.nt + 1), device=DEV) for _ in srcs]
+    plan = rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, vg, w, x, s.rec, traces_out=t)
+                                            for x, t in zip(srcs, traces)], s.dt, s.nt)
+    plan.run()
+    got_tr = [_n(t) for t in traces]
+    d_in = [traces[0], _t(tr_o), traces[2]]  # the half-cell shot migrates the oracle's data
+    imgs = [torch.empty(g.interior_shape, device=DEV) for _ in srcs]
+    plan = rtm.BatchPlan(rtm.RTM_OP_RTM, [rtm.BatchShot(g, vg, w, x, s.rec, traces_in=t, image=im)
+                                          for x, t, im in zip(srcs, d_in, imgs)], s.dt, s.nt, eps_rel=EPS)
+    plan.run()
+    got_im = [_n(im) for im in imgs]
+    for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
+        rtm.rtm_set_tuning2d(op, 1, 1, 18)
+        rtm.rtm_set_steps_per_launch(op, 1)
+    for x, tr, d, im in zip(srcs, got_tr, d_in, got_im):
+        ref_tr = rtm.rtm_model_shot(g, vg, s.dt, w, x, s.rec)
+        ref_im = rtm.rtm_rtm_shot(g, vg, s.dt, w, x, s.rec, d, eps_rel=EPS)["image"]
+        assert np.array_equal(tr, _n(ref_tr)) and np.array_equal(im, _n(ref_im))
+    ref = oracle.rtm_shot(vo, s.h, s.nb, s.dt, w64, srcs[1], s.rec, tr_o, eps_rel=EPS)
     e_tr, e_im = rel_l2(got_tr[1], tr_o), rel_l2(got_im[1], ref["image"])
     print(f"bench launch shape: traces {e_tr:.2e} image {e_im:.2e}")
     assert e_tr < TOL and e_im < TOL
+
+
+def test_image_normalisation_interior_max():
+    """The water level of Eq. (3)'s ratio uses the maximum of den over the
+    interior crop.  On a crafted case where the padded grid's maximum is
+    more than 1.5 times the interior's (only the source cell of a 4 x 4
+    interior has a velocity; the band corner that takes it collects more
+    illumination than the source), the GPU image matches the oracle's."""
+    nb, h = 6, 10.0
+    v = np.zeros((4, 4), np.float32)
+    v[0, 0] = 1500.0
+    g = rtm.Grid.for_model(v, h, nb)
+    vg = rtm.rtm_rbc_pad(g, _t(v), 3, 0.0)
+    vo = oracle.rbc_pad(v, nb, 3, 0.0)
+    assert np.array_equal(_n(vg), vo)
+    dt = 0.5 * h / (1.3 * 1500.0)
+    w = synth.ricker(25.0, dt, 400)
+    src, rec = np.array([0.0, 0.0, 0.0]), np.array([[0.0, 0.0, 0.0]])
+    d_o = oracle.model_shot(vo, h, nb, dt, w.astype(np.float64), src, rec)
+    for eps in (1e-3, 0.5):
+        out = rtm.rtm_rtm_shot(g, vg, dt, _t(w), src, rec, _t(d_o), eps_rel=eps, want_numden=True)
+        ref = oracle.rtm_shot(vo, h, nb, dt, w.astype(np.float64), src, rec, d_o, eps_rel=eps)
+        e = {k: rel_l2(_n(out[k]), ref[k]) for k in ("num", "den", "image")}
+        print(f"interior max, eps {eps}: {e}")
+        assert max(e.values()) < TOL
+
+
+def test_two_layer_long_record_reflector():
+    """The two-layer 201 x 201 model recorded for 1.5 s (nt 3000, past the
+    interface's two-way time), direct wave removed: GPU traces against the
+    oracle's, the GPU image of the oracle's data against the oracle's image,
+    and the GPU image's laterally averaged amplitude peaking within two
+    cells of the interface at iz = 100."""
+    s = synth.config_c1(nt=3000)
+    g, vg, vo = _setup(s)
+    w, w64 = _t(s.wavelet), s.wavelet.astype(np.float64)
+    vh = np.full_like(s.v_int, s.v_int[0, 0])
+    cap = float(s.v_int.max())
+    vhg = rtm.rtm_rbc_pad(g, _t(vh), s.seed, cap)
+    vho = oracle.rbc_pad(vh, s.nb, s.seed, cap)
+    d = rtm.rtm_model_shot(g, vg, s.dt, w, s.src[0], s.rec) - rtm.rtm_model_shot(g, vhg, s.dt, w, s.src[0], s.rec)
+    d_o = (oracle.model_shot(vo, s.h, s.nb, s.dt, w64, s.src[0], s.rec)
+           - oracle.model_shot(vho, s.h, s.nb, s.dt, w64, s.src[0], s.rec))
+    e_tr = rel_l2(_n(d), d_o)
+    im = _n(rtm.rtm_rtm_shot(g, vg, s.dt, w, s.src[0], s.rec, _t(d_o), eps_rel=EPS)["image"])
+    ref = oracle.rtm_shot(vo, s.h, s.nb, s.dt, w64, s.src[0], s.rec, d_o, eps_rel=EPS)["image"]
+    e_im = rel_l2(im, ref)
+    prof = np.abs(im[:, 50:151]).mean(axis=1)
+    z = 10 + int(np.argmax(prof[10:]))
+    print(f"two-layer long record: reflection data {e_tr:.2e}, image {e_im:.2e}, reflector at iz = {z}")
+    assert e_tr < TOL and e_im < TOL
+    assert abs(z - 100) <= 2

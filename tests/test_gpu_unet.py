@@ -250,3 +250,58 @@ def test_network_forward_and_gradients_vs_oracle():
     assert max(errs.values()) < 1e-3, errs
     # the one-channel layers hold only their real weights
     assert net.slots["c1.w"][1] == (16, 27, 1) and net.slots["c8.w"][1] == (1, 27, 16)
+
+
+# The eight convolutions of the crosstalk network on a 128^3 image, each at
+# the size it runs at (name, cin, cout, cube edge).
+NET128 = (("c1", 1, 16, 128), ("c2", 16, 32, 64), ("c3", 32, 64, 32), ("c4", 64, 128, 16),
+          ("c5", 128, 64, 32), ("c6", 64, 32, 64), ("c7", 32, 16, 128), ("c8", 16, 1, 128))
+
+
+def _sample_points(n, rng, count=3000):
+    """Random voxels of an n^3 cube plus its corners and face centres."""
+    pts = rng.integers(0, n, (count, 3))
+    e = (0, n - 1)
+    corners = np.array([(a, b, c) for a in e for b in e for c in e])
+    m = n // 2
+    faces = np.array([(0, m, m), (n - 1, m, m), (m, 0, m), (m, n - 1, m), (m, m, 0), (m, m, n - 1)])
+    return np.concatenate([pts, corners, faces])
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("name,ci,co,n", NET128, ids=[r[0] for r in NET128])
+def test_layer_parity_at_training_size(name, ci, co, n):
+    """Each convolution of the 128^3 network at its real size (the one-
+    channel weight gradients at their block cap, the coarse levels on their
+    split grids): forward and input gradient on sampled voxels (faces and
+    corners included) and the weight and bias gradients in full, against the
+    oracle on the same bfloat16 operands."""
+    rng = np.random.default_rng(1000 + ci * 7 + co)
+    shape = (1, n, n, n)
+    nvox = n ** 3
+    x = U.bf16(rng.standard_normal((nvox, ci)).astype(np.float32))
+    dy = U.bf16(rng.standard_normal((nvox, co)).astype(np.float32))
+    wo = U.bf16(rng.standard_normal((co, ci, 3, 3, 3)) * np.sqrt(2.0 / (27 * ci)))
+    b = rng.standard_normal(co) * 0.1
+    wf, wb = pack(wo)
+    xt, dyt = bf_tensor(x), bf_tensor(dy)
+    y = torch.empty((nvox, co), dtype=torch.float32, device=DEV)
+    N.conv3d_fwd(shape, ci, co, xt, wf, f32(b), False, y=y)
+    dx = torch.empty((nvox, ci), dtype=torch.float32, device=DEV)
+    N.conv3d_dgrad(shape, ci, co, dyt, wb, dx)
+    ws = torch.empty(N.wgrad_ws_bytes(shape, ci, co), dtype=torch.uint8, device=DEV)
+    dw = torch.empty((co, 27, ci), dtype=torch.float32, device=DEV)
+    db = torch.empty(co, dtype=torch.float32, device=DEV)
+    N.conv3d_wgrad(shape, ci, co, xt, dyt, dw, db, ws)
+    pts = _sample_points(n, rng)
+    flat = (pts[:, 0] * n + pts[:, 1]) * n + pts[:, 2]
+    x_cf = x.reshape(n, n, n, ci).transpose(3, 0, 1, 2)
+    dy_cf = dy.reshape(n, n, n, co).transpose(3, 0, 1, 2)
+    e_f = rel_l2(host(y)[flat], U.conv3d_at(x_cf, wo, b, pts))
+    e_d = rel_l2(host(dx)[flat], U.conv3d_dgrad_at(dy_cf, wo, pts))
+    del y, dx
+    ref_w, ref_b = U.conv3d_wgrad(x_cf, dy_cf)
+    ref_w = np.transpose(ref_w.reshape(co, ci, 27), (0, 2, 1))
+    e_w, e_b = rel_l2(host(dw), ref_w), rel_l2(host(db), ref_b)
+    print(f"{name} {ci}->{co} at {n}^3: fwd {e_f:.2e} dgrad {e_d:.2e} wgrad {e_w:.2e} bias {e_b:.2e}")
+    assert max(e_f, e_d, e_w, e_b) < 1e-5

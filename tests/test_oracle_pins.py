@@ -456,15 +456,80 @@ def test_image_numerator_identity():
         assert abs(fd - num[iz, ix]) <= 1e-6 * abs(num[iz, ix]) + 1e-9 * np.abs(num).max(), (iz, ix, fd, num[iz, ix])
 
 
-def test_image_normalisation():
-    """Eq. (3): image = num / (den + eps max den) on the interior."""
-    s = synth.config_small2d(nt=150)
-    vp = oracle.rbc_pad(s.v_int, s.nb, 23, 0.0)
-    d = oracle.model_shot(vp, s.h, s.nb, s.dt, s.wavelet, s.src[0], s.rec)
-    for eps in (0.0, 1e-6, 1e-2):
-        out = oracle.rtm_shot(vp, s.h, s.nb, s.dt, s.wavelet, s.src[0], s.rec, d, eps_rel=eps)
-        ref = out["num"] / (out["den"] + eps * out["den"].max())
-        assert np.allclose(out["image"], ref, rtol=1e-14, atol=0)
+def _dense_den(vp, h, nb, dt, w, src_node):
+    """den = sum_{k < nt} (p^k)^2 on the whole padded grid, from a dense-matrix
+    leapfrog (Kronecker-sum Laplacian with independently derived weights)
+    with an on-grid source."""
+    NZ, NX = vp.shape
+    A = _dense_laplacian_2d(NZ, NX, h)
+    D = (vp.astype(np.float64).ravel() * dt) ** 2
+    B = np.zeros(NZ * NX)
+    B[(src_node[1] + nb) * NX + src_node[0] + nb] = 1.0 / h ** 2
+    p0, pm, den = np.zeros(NZ * NX), np.zeros(NZ * NX), np.zeros(NZ * NX)
+    for n in range(len(w)):
+        den += p0 * p0
+        pm, p0 = p0, 2 * p0 - pm + D * (A @ p0 + B * w[n])
+    return den.reshape(NZ, NX)
+
+
+def test_image_normalisation_takes_the_interior_max():
+    """Eq. (3) with the water level: image = num / (den + eps max den), the
+    maximum taken over the interior crop (the image's domain), not over the
+    padded grid.  Crafted so that the two maxima differ: of a 4 x 4 interior
+    only the source cell has a velocity (the other cells never move, a wall),
+    so the wave lives in the source cell and the band corner that takes its
+    velocity, where a 25 Hz wavelet leaves more illumination than at the
+    source.  den over the padded grid comes from a dense-matrix leapfrog."""
+    nb, h = 6, 10.0
+    v = np.zeros((4, 4), np.float32)
+    v[0, 0] = 1500.0
+    vp = oracle.rbc_pad(v, nb, 3, 0.0)
+    dt = 0.5 * h / (1.3 * 1500.0)
+    w = synth.ricker(25.0, dt, 400).astype(np.float64)
+    src, rec = np.array([0.0, 0.0, 0.0]), np.array([[0.0, 0.0, 0.0]])
+    d = oracle.model_shot(vp, h, nb, dt, w, src, rec)
+    den_pad = _dense_den(vp, h, nb, dt, w, (0, 0))
+    m_int, m_pad = den_pad[nb:nb + 4, nb:nb + 4].max(), den_pad.max()
+    assert m_pad > 1.5 * m_int  # the case tells the two readings apart
+    for eps in (0.0, 1e-3, 0.5):
+        out = oracle.rtm_shot(vp, h, nb, dt, w, src, rec, d, eps_rel=eps)
+        assert np.allclose(out["den"], den_pad[nb:nb + 4, nb:nb + 4], rtol=1e-9, atol=1e-12 * m_int)
+        live = out["den"] > 0
+        ref = out["num"][live] / (out["den"][live] + eps * m_int)
+        assert np.allclose(out["image"][live], ref, rtol=1e-12, atol=0)
+        if eps > 0:
+            wrong = out["num"][live] / (out["den"][live] + eps * m_pad)
+            assert not np.allclose(out["image"][live], wrong, rtol=1e-4, atol=0)
+            assert not out["image"][~live].any()  # num = 0 where den = 0
+
+
+def _reflector_image(s):
+    """Image of the two-layer shot with the direct wave removed (the same shot
+    recorded on the homogeneous model of the source layer, same band seed,
+    subtracted), so that the data hold the interface reflection."""
+    w = s.wavelet.astype(np.float64)
+    vp = oracle.rbc_pad(s.v_int, s.nb, s.seed, 0.0)
+    vh = np.full_like(s.v_int, s.v_int[0, 0])
+    vph = oracle.rbc_pad(vh, s.nb, s.seed, float(s.v_int.max()))
+    d = oracle.model_shot(vp, s.h, s.nb, s.dt, w, s.src[0], s.rec)
+    d -= oracle.model_shot(vph, s.h, s.nb, s.dt, w, s.src[0], s.rec)
+    return oracle.rtm_shot(vp, s.h, s.nb, s.dt, w, s.src[0], s.rec, d, eps_rel=1e-3)["image"]
+
+
+def test_reflector_depth_two_layer():
+    """Image physics, not only parity: the 201 x 201 two-layer model
+    (1500 m/s above iz = 100, 2500 m/s from it), recorded for 1.5 s (nt
+    3000, past the 1.31 s two-way time of the interface), migrated with the
+    imaging condition of Eq. (3).  The image amplitude averaged over the
+    central half of the line peaks, below the first ten rows, within two
+    cells of the interface, well above the profile's typical level."""
+    s = synth.config_c1(nt=3000)
+    im = _reflector_image(s)
+    prof = np.abs(im[:, 50:151]).mean(axis=1)
+    z = 10 + int(np.argmax(prof[10:]))
+    print(f"reflector at iz = {z}; profile peak {prof[z]:.3g}, median {np.median(prof[10:]):.3g}")
+    assert abs(z - 100) <= 2
+    assert prof[z] > 5.0 * np.median(prof[10:])
 
 
 # ---------------------------------------------------------------------------

@@ -51,6 +51,24 @@ def test_conv3d_brute_force():
     assert np.allclose(U.conv3d(x, w, b), _brute_conv(x, w, b), rtol=0, atol=1e-12)
 
 
+def test_pointwise_forms_match_the_brute_force_and_adjoint():
+    """conv3d_at equals the brute-force sum at every voxel of a small tensor
+    (faces and corners included); conv3d_dgrad_at satisfies the dot-product
+    identity <conv(x), dy> = <x, dgrad(dy)> voxel by voxel summed."""
+    rng = np.random.default_rng(7)
+    x = rng.standard_normal((3, 4, 3, 5))
+    w = rng.standard_normal((2, 3, 3, 3, 3))
+    b = rng.standard_normal(2)
+    pts = np.argwhere(np.ones(x.shape[1:], bool))
+    y = U.conv3d_at(x, w, b, pts)
+    ref = _brute_conv(x, w, b)
+    assert np.allclose(y, ref.reshape(2, -1).T, rtol=0, atol=1e-12)
+    dy = rng.standard_normal((2,) + x.shape[1:])
+    dx = U.conv3d_dgrad_at(dy, w, pts)
+    lhs = np.sum(_brute_conv(x, w, np.zeros(2)) * dy)
+    assert abs(lhs - np.sum(x.reshape(3, -1).T * dx)) < 1e-10 * abs(lhs)
+
+
 def test_conv3d_delta_response():
     # a unit impulse at p0 gives y[o, p0 - k + 1] = w[o, 0, k]
     rng = np.random.default_rng(2)
