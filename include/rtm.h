@@ -289,6 +289,27 @@ int rtm_rtm_shot(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t 
                  const rtm_probe_t *probe, uint32_t flags, void *ws, size_t ws_bytes,
                  void *stream);
 
+/* rtm_rtm_shot for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation with no workspace argument and no probe.
+ * Its scratch is a fixed array of RTM_NOALLOC_SCRATCH_BYTES bytes inside the
+ * library, one per GPU, held from the library's load until the process
+ * ends; the call allocates no device memory.  A shot whose
+ * rtm_workspace_bytes(RTM_OP_RTM) exceeds that size is refused with
+ * RTM_EWORKSPACE before any work is queued (the 201 x 201 two-layer shot
+ * with its 40-cell band and 1000 steps needs about 6.3 MiB; a 1201 x 300
+ * window with a 40-cell band and 2000 steps about 36 MiB).  The array
+ * keeps the last call's contents, and every field the run reads is cleared
+ * first, so results do not depend on earlier calls.
+ * All calls on one GPU share its array: calls that overlap in time on one
+ * GPU (other streams or host threads) race and give wrong results; order
+ * them.  Other arguments, flags and errors as in rtm_rtm_shot. */
+#define RTM_NOALLOC_SCRATCH_BYTES (64u << 20)
+int rtm_rtm_shot_noalloc(const rtm_grid_t *grid, const float *v_pad, double dt, int32_t nt,
+                         const float *wavelet, const float *src, int32_t nrec, const float *rec,
+                         const float *traces, float eps_rel, float *image, float *num, float *den,
+                         uint32_t flags, void *stream);
+
 /* Snapshot step of the stored source wavefield (Eq. (7)): the Nyquist
  * interval 1 / (2 (f_max - f_min)) of a source band [f_min, f_max] Hz, in
  * whole time steps of dt seconds, at least 1.  Host only.

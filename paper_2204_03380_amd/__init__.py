@@ -25,7 +25,7 @@ __all__ = [
     "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD", "RTM_F_ACCUMULATE", "RTM_F_GRAPH", "RTM_F_CHECK_FINITE", "RTM_TUNE_EXACT",
     "BatchShot", "BatchPlan", "rtm_window_extract", "rtm_window_accumulate", "rtm_l2_misfit",
     "rtm_set_tuning2d", "rtm_get_tuning2d", "rtm_set_steps_per_launch", "rtm_get_steps_per_launch",
-    "tuning_snapshot", "tuning_restore", "rtm_stream_copy",
+    "tuning_snapshot", "tuning_restore", "rtm_stream_copy", "rtm_rtm_shot_noalloc",
 ]
 
 
@@ -273,6 +273,32 @@ def rtm_rtm_shot(grid: Grid, v_pad: torch.Tensor, dt: float, wavelet: torch.Tens
         out["num"].data_ptr() if want_numden else None, out["den"].data_ptr() if want_numden else None,
         ctypes.byref(probe) if probe is not None else None, int(flags), ws.data_ptr(), ws.numel(), _stream(dev)))
     return out
+
+
+def rtm_rtm_shot_noalloc(grid: Grid, v_pad: torch.Tensor, dt: float, wavelet: torch.Tensor, src, rec,
+                         traces: torch.Tensor, image: torch.Tensor, eps_rel: float = 1e-3, num: torch.Tensor = None,
+                         den: torch.Tensor = None, flags: int = 0) -> torch.Tensor:
+    """rtm_rtm_shot into caller-provided outputs, with the library's fixed
+    scratch array instead of a workspace: allocates no device memory (the
+    outputs are given).  Returns image."""
+    dev = v_pad.device
+    _dev(v_pad, "v_pad", grid.padded_shape)
+    nt = int(wavelet.numel())
+    _dev(wavelet, "wavelet", (nt,))
+    src = _pos(src, "src")[0].copy()
+    rec = _pos(rec, "rec")
+    nrec = rec.shape[0]
+    _dev(traces, "traces", (nrec, nt + 1))
+    _dev(image, "image", grid.interior_shape)
+    for t, name in ((num, "num"), (den, "den")):
+        if t is not None:
+            _dev(t, name, grid.interior_shape)
+    g = grid.c()
+    _lib.check(_lib.load().rtm_rtm_shot_noalloc(
+        ctypes.byref(g), v_pad.data_ptr(), float(dt), nt, wavelet.data_ptr(), _fp(src), nrec, _fp(rec),
+        traces.data_ptr(), float(eps_rel), image.data_ptr(), num.data_ptr() if num is not None else None,
+        den.data_ptr() if den is not None else None, int(flags), _stream(dev)))
+    return image
 
 
 def rtm_nyquist_stride(dt: float, f_max: float, f_min: float = 0.0) -> int:
