@@ -78,6 +78,9 @@ def parse():
     ap.add_argument("--boundary-study", action="store_true",
                     help="instead of the survey benchmark: RTM crosstalk of one shot for the band setups (uniform "
                          "random factors, Eqs. (4)-(5) tapers, free surface)")
+    ap.add_argument("--persistent-study", action="store_true",
+                    help="instead of the survey benchmark: batch plans run eagerly, as a hipGraph and as persistent "
+                         "passes, on the uneven-aperture windows and single shots of the paper's 2-D grids")
     ap.add_argument("--paper-kinds", default="modeling,rtm,storage",
                     help="with --paper-shapes: comma-separated kinds to run")
     return ap.parse_args()
@@ -358,6 +361,91 @@ def boundary_study(K=8, seed0=500):
     return {"model": name, "seeds": K, "rows": rows}
 
 
+def persistent_study(reps=2):
+    """Device time of batch plans run three ways: the default launch per
+    one to three time steps (eager), the same schedule replayed as a
+    hipGraph, and the persistent passes (one launch per pass, per-shot
+    progress counters, one step per pass over a tile).  Workloads: the 64
+    uneven-aperture windows (nt 2000; modeling of the observed data, then
+    the gradient pass) and single shots at the paper's 2-D grid sizes
+    (modeling, nt 8000)."""
+    import numpy as np
+    import torch
+
+    import paper_2204_03380_amd as rtm
+    import synth
+    dev = torch.device("cuda:0")
+    gst = torch.cuda.Stream(device=dev)
+    rows = []
+
+    def timed(run):
+        run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(gst)
+        for _ in range(reps):
+            run()
+        e1.record(gst)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    def modes(make, name, cell_steps):
+        out = {"workload": name}
+        for mode, flags in (("launch_per_steps", 0), ("graph", rtm.RTM_F_GRAPH), ("persistent", rtm.RTM_F_PERSISTENT)):
+            plans = make(flags)
+            ms = timed(lambda: [p.run(gst) for p in plans])
+            out[mode] = {"ms": round(ms, 3), "gcell_updates_per_s": round(cell_steps / (ms * 1e-3) / 1e9, 2)}
+            for p in plans:
+                p.free()
+        print(json.dumps(out), file=sys.stderr, flush=True)
+        rows.append(out)
+
+    with torch.cuda.stream(gst):
+        s = synth.config_c4()
+        windows = [(int(a), int(b)) for a, b in s.extra["windows"]]
+        vt = torch.from_numpy(s.v_int).to(dev)
+        w = torch.from_numpy(s.wavelet).to(dev)
+        shots = []
+        for i, (x0, wd) in enumerate(windows):
+            v = rtm.rtm_window_extract(vt, x0, wd)
+            g = rtm.Grid.for_model(v, s.h, s.nb)
+            vp = rtm.rtm_rbc_pad(g, v, 1000 + i, 3500.0)
+            rec = synth.line_receivers(np.arange(wd, dtype=np.float64), 2.0)
+            tr = torch.zeros((wd, s.nt + 1), device=dev)
+            gv = torch.empty(g.padded_shape, device=dev)
+            shots.append((g, vp, s.src[i], rec, tr, gv))
+        cells = sum(g.padded_shape[0] * g.padded_shape[1] for g, *_ in shots)
+
+        def c4(flags):
+            m = rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, vp, w, src, rec, traces_out=tr)
+                                                 for g, vp, src, rec, tr, gv in shots], s.dt, s.nt, flags=flags)
+            v = rtm.BatchPlan(rtm.RTM_OP_VJP, [rtm.BatchShot(g, vp, w, src, rec, traces_in=tr, grad_v_pad=gv)
+                                               for g, vp, src, rec, tr, gv in shots], s.dt, s.nt, flags=flags)
+            return [m, v]
+
+        modes(c4, "64 uneven-aperture windows (401-1201 x 300, nb 40), nt 2000: modeling + gradient pass",
+              cells * s.nt * 4)
+        del shots
+        for nx, nz, nt in ((837, 294, 8000), (1574, 534, 8000)):
+            nb = 50
+            v = synth.random_model((nz - 2 * nb, nx - 2 * nb), 7, 1500.0, 4000.0, sigma=4.0)
+            g = rtm.Grid.for_model(v, 10.0, nb)
+            vp = rtm.rtm_rbc_pad(g, torch.from_numpy(v).to(dev), 11, 0.0)
+            dt = 0.45 * 10.0 / 4000.0
+            ww = torch.from_numpy(synth.ricker(15.0, dt, nt)).to(dev)
+            rec = synth.line_receivers(np.arange(0, nx - 2 * nb, 1, dtype=np.float64), 2.0)
+            src = np.array([(nx - 2 * nb) / 2.0, 0.0, 2.0])
+            tr = torch.empty((rec.shape[0], nt + 1), device=dev)
+
+            def one(flags):
+                return [rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, vp, ww, src, rec, traces_out=tr)], dt, nt,
+                                      flags=flags)]
+
+            modes(one, f"single shot {nx}x{nz} (padded), modeling, nt {nt}", nx * nz * nt)
+    torch.cuda.synchronize()
+    return rows
+
+
 def device_info():
     """What the run was measured on (torch's view of device 0)."""
     import torch
@@ -414,6 +502,13 @@ def main():
                           "higher_is_better": False, "dtype": "f32", "data": "synthetic", **out}), flush=True)
         return
 
+    if args.persistent_study:
+        rows = persistent_study()
+        print(json.dumps({"metric": "batch plan device time: launch per step(s), hipGraph, persistent passes",
+                          "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+                          "rows": rows}), flush=True)
+        return
+
     if args.paper_shapes:
         rows = paper_shapes(kinds=tuple(args.paper_kinds.split(",")))
         print(json.dumps({"metric": "single-shot time at the paper's grid sizes", "unit": "s", "n_gpus": 1,
@@ -456,6 +551,8 @@ def main():
         v_tmp = rtm.rtm_rbc_pad(g, v_int, s.seed, 0.0)
         tuned = autotune.tune_batch(g, v_tmp, wav, [s.src[i] for i in range(B)], s.rec, s.dt, nt_probe=90, reps=2)
         del v_tmp
+        # the timed batch runs exactly the configuration the tuner picked for it
+        rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
     fwd_shape = rtm.rtm_get_tuning2d(rtm.RTM_OP_MODEL)   # (vec, tx, zseg)
     rev_shape = rtm.rtm_get_tuning2d(rtm.RTM_OP_RTM)
 
@@ -515,6 +612,8 @@ def main():
     # Plain per-shot calls on the same GPU (modeling + RTM), same shots as
     # the first batch; their images must equal the batched ones bit for bit.
     plain_shots = groups[0][:min(B, args.plain_shots)]
+    exact = rtm.rtm_get_tuning(rtm.RTM_TUNE_EXACT)[0]
+    rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 0, 0)  # single shots take the library's shapes for small jobs
     torch.cuda.synchronize()
     p0 = time.perf_counter()
     plain = []
@@ -523,6 +622,7 @@ def main():
         plain.append((d, rtm.rtm_rtm_shot(g, v_pad, s.dt, wav, s.src[i], s.rec, d, eps_rel=1e-3)["image"]))
     torch.cuda.synchronize()
     plain_s = time.perf_counter() - p0
+    rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, exact, 0)
     # The batched side of the comparison is the timed configuration itself:
     # the first group's modeling plan as timed, then an RTM plan of the same
     # B shots at the same launch shape writing one image per shot.  Its launch
@@ -594,7 +694,10 @@ def main():
             "propagations_per_shot": 4,
             "launch_shape": {"forward": {"vec": fwd_shape[0], "tx": fwd_shape[1], "zseg": fwd_shape[2]},
                              "reverse": {"vec": rev_shape[0], "tx": rev_shape[1], "zseg": rev_shape[2]},
-                             "autotuned": tuned is not None},
+                             "autotuned": tuned is not None,
+                             "tuner": ({"forward_us_per_step": round(tuned["forward"][-1], 3),
+                                        "reverse_us_per_step": round(tuned["reverse"][-1], 3),
+                                        "candidates": len(tuned["table"])} if tuned else None)},
         },
         "roofline": {
             "bound": "hbm",

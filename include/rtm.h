@@ -24,7 +24,10 @@
  *    are NX = nx + 2nb, NZ = nz + 2nb, NY = ny + 2nb (3-D) or 1 (2-D).
  *    Dense fields are row-major [NZ][NY][NX] (x fastest); interior-sized
  *    fields are [nz][ny][nx].  Outside the padded grid the wavefield is zero
- *    (the Dirichlet condition stated with Eq. (1)).
+ *    (the Dirichlet condition stated with Eq. (1)).  A padded field, with the
+ *    library's internal row and plane padding, must hold fewer than 2^31
+ *    floats (about 2.0e9 cells; 1250^3 fits, 1300^3 does not): larger grids
+ *    are refused with RTM_EINVAL, so cell offsets always fit 32 bits.
  *  - Positions are float triples (x, y, z) in interior grid units, 0-based,
  *    relative to interior cell (0, 0, 0); y is ignored in 2-D.  Off-grid
  *    positions use multilinear interpolation weights for both injection and
@@ -84,6 +87,16 @@ extern "C" {
                                   hipGraph on the first run and replay it on
                                   later runs with the same workspace and
                                   stream (stream must not be NULL) */
+#define RTM_F_PERSISTENT 0x20u  /* 2-D batch: each pass (forward, reverse) is
+                                  one launch of a resident grid that walks
+                                  every time step, each shot's step waiting
+                                  only for that shot's previous step (per-
+                                  shot progress counters); one strip per
+                                  workgroup, one step per pass over a tile.
+                                  rtm_batch_run then synchronises the
+                                  stream at the end and returns RTM_EHIP if
+                                  a bounded wait gave up (the grid was not
+                                  resident).  Not with RTM_F_GRAPH. */
 #define RTM_F_CHECK_FINITE 0x10u /* single-shot calls: after the run, check
                                   the outputs (traces, image, or velocity
                                   gradient) for NaN / Inf; synchronises the
@@ -161,6 +174,14 @@ int rtm_get_steps_per_launch(int op, int *steps);
  * planes per tile (a multiple of 9).  Same rules as rtm_set_tuning. */
 int rtm_set_tuning3d(int op, int vec, int ty, int zseg);
 int rtm_get_tuning3d(int op, int *vec, int *ty, int *zseg);
+
+/* Bounded wait of RTM_F_PERSISTENT passes, process-wide: a workgroup that
+ * waits longer than `ms` milliseconds for its shot's previous step gives
+ * up, the pass ends and rtm_batch_run returns RTM_EHIP (default 4000 ms;
+ * [0, 3.6e6]).  Lowering it forces that path, for tests of the failure
+ * handling.  Not synchronised with concurrent calls. */
+int rtm_set_persist_wait(double ms);
+int rtm_get_persist_wait(double *ms);
 
 /* Event timing of the time loops, for measurement.  While enabled, every
  * propagation call records a HIP event pair on its stream around each of
@@ -395,7 +416,8 @@ typedef struct rtm_plan rtm_plan_t;
  * current launch shapes, and returns an opaque plan (host memory only)
  * plus the workspace size its runs need.  op is RTM_OP_MODEL, RTM_OP_RTM
  * or RTM_OP_VJP; flags: RTM_F_SKIP_CHECK, RTM_F_NO_REINJECT (RTM),
- * RTM_F_ACCUMULATE (RTM), RTM_F_GRAPH.  eps_rel as in rtm_rtm_shot. */
+ * RTM_F_ACCUMULATE (RTM), RTM_F_GRAPH, RTM_F_PERSISTENT (2-D).  eps_rel as
+ * in rtm_rtm_shot. */
 int rtm_batch_plan(int op, int32_t nshots, const rtm_shot_desc_t *shots, double dt, int32_t nt,
                    float eps_rel, uint32_t flags, rtm_plan_t **plan, size_t *ws_bytes);
 

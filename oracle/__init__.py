@@ -44,6 +44,9 @@ def _load():
                                      P, P, c_int, P, P, c_int, c_double, P, P, P, P, P, c_int, P, P]
         lib.orc_rtm_storage_shot.argtypes = [c_int, c_long, c_long, c_long, c_int, c_double, P, c_double, c_int,
                                              P, P, c_int, P, P, c_int, c_int, c_double, P, P, P]
+        lib.orc_rtm_shot_panels.argtypes = [c_int, c_long, c_long, c_long, c_int, c_double, P, c_double, c_int,
+                                            P, P, c_int, P, P, c_int, c_double, P, P, P, P, P]
+        lib.orc_rtm_shot_panels.restype = c_int
         lib.orc_set_threads.argtypes = [c_int]
         lib.orc_set_threads.restype = c_int
         lib.orc_fp_env.argtypes = []
@@ -197,6 +200,30 @@ def rtm_shot(v_pad, h, nb, dt, wavelet, src, rec, g, reinject=True, eps_rel=1e-6
         out["w_adj"] = wadj
     if snap_k >= 0:
         out["snap_p"], out["snap_mu"] = sp, sm
+    return out
+
+
+def rtm_shot_from_panels(v_pad, h, nb, dt, wavelet, src, rec, g, p_last, p_prev, reinject=True, eps_rel=1e-6):
+    """rtm_shot whose reverse pass starts from given final panels p^nt,
+    p^(nt-1) (as model_shot(..., want_last=True) returns them) instead of
+    recomputing the forward pass; returns num, den, image."""
+    v_pad = np.ascontiguousarray(v_pad, dtype=np.float32)
+    ndim, nx, ny, nz = _dims(v_pad.shape, nb)
+    w = np.ascontiguousarray(wavelet, dtype=np.float64)
+    nt = w.shape[0]
+    src, rec = _geom(src, rec)
+    nrec = rec.shape[0]
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    assert g.shape == (nrec, nt + 1)
+    pl = np.ascontiguousarray(p_last, dtype=np.float64)
+    pp = np.ascontiguousarray(p_prev, dtype=np.float64)
+    assert pl.shape == v_pad.shape and pp.shape == v_pad.shape
+    ishape = (nz, nx) if ndim == 2 else (nz, ny, nx)
+    out = {k: np.empty(ishape, np.float64) for k in ("num", "den", "image")}
+    rc = _load().orc_rtm_shot_panels(ndim, nx, ny, nz, nb, h, _ptr(v_pad), dt, nt, _ptr(w), _ptr(src), nrec,
+                                     _ptr(rec), _ptr(g), int(bool(reinject)), eps_rel, _ptr(out["num"]),
+                                     _ptr(out["den"]), _ptr(out["image"]), _ptr(pl), _ptr(pp))
+    _check(rc, "orc_rtm_shot_panels")
     return out
 
 

@@ -246,14 +246,31 @@ static const double OG_C0 = -205.0 / 72.0;
 static const double OG_CM[5] = {0.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0};
 
 /* out = L_h p: the sum over axes of the 1-D second-difference operator,
- * divided by h^2, with p = 0 outside the padded grid. */
+ * divided by h^2, with p = 0 outside the padded grid.  Cells at least four
+ * cells from every face read their neighbours directly; the others through
+ * og_at, which supplies the zeros outside.  Both evaluate the same sum in
+ * the same order. */
 static void og_laplacian(const og_grid *g, const double *p, double *out)
 {
     const double inv_h2 = 1.0 / (g->h * g->h);
+    const long sy = g->NX, sz = g->NX * g->NY;
 #pragma omp parallel for schedule(static)
     for (long z = 0; z < g->NZ; ++z)
         for (long y = 0; y < g->NY; ++y)
             for (long x = 0; x < g->NX; ++x) {
+                const int inner = x >= 4 && x < g->NX - 4 && z >= 4 && z < g->NZ - 4 &&
+                                  (g->ndim == 2 || (y >= 4 && y < g->NY - 4));
+                if (inner) {
+                    const long j = og_index(g, z, y, x);
+                    double s = g->ndim * OG_C0 * p[j];
+                    for (int m = 1; m <= 4; ++m) {
+                        s += OG_CM[m] * (p[j + m] + p[j - m]);
+                        s += OG_CM[m] * (p[j + m * sz] + p[j - m * sz]);
+                        if (g->ndim == 3) s += OG_CM[m] * (p[j + m * sy] + p[j - m * sy]);
+                    }
+                    out[j] = s * inv_h2;
+                    continue;
+                }
                 double s = g->ndim * OG_C0 * og_at(g, p, z, y, x);
                 for (int m = 1; m <= 4; ++m) {
                     s += OG_CM[m] * (og_at(g, p, z, y, x + m) + og_at(g, p, z, y, x - m));
@@ -440,11 +457,12 @@ int orc_model_shot(int ndim, long nx, long ny, long nz, int nb, double h, const 
  *   snap_p, snap_mu  padded reconstructed p^snap_k and mu^snap_k,
  *                    for 0 <= snap_k <= nt-2 (snap_k < 0: none).
  * Returns 0, -1 or -3. */
-int orc_rtm_shot(int ndim, long nx, long ny, long nz, int nb, double h, const float *v_pad,
-                 double dt, int nt, const double *w, const double *src, int nrec,
-                 const double *rec, const double *g_in, int reinject, double eps_rel,
-                 double *num_out, double *den_out, double *image, double *grad_pad,
-                 double *w_adj, int snap_k, double *snap_p, double *snap_mu)
+static int og_rtm(int ndim, long nx, long ny, long nz, int nb, double h, const float *v_pad,
+                  double dt, int nt, const double *w, const double *src, int nrec,
+                  const double *rec, const double *g_in, int reinject, double eps_rel,
+                  double *num_out, double *den_out, double *image, double *grad_pad,
+                  double *w_adj, int snap_k, double *snap_p, double *snap_mu,
+                  const double *start_last, const double *start_prev)
 {
     og_grid g;
     og_point sp, *rp = NULL;
@@ -469,12 +487,17 @@ int orc_rtm_shot(int ndim, long nx, long ny, long nz, int nb, double h, const fl
     double *src_term = (double *)calloc(n, sizeof(double));
     for (long i = 0; i < n; ++i) D[i] = ((double)v_pad[i] * dt) * ((double)v_pad[i] * dt);
 
-    /* Forward: pa = p^n, pb = p^(n-1). */
-    for (int it = 0; it < nt; ++it) {
-        og_step(&g, D, pa, pb, pb, lap, &sp, w[it], NULL);
-        double *t = pa;
-        pa = pb;
-        pb = t;
+    /* Forward: pa = p^n, pb = p^(n-1); or the two panels given. */
+    if (start_last && start_prev) {
+        memcpy(pa, start_last, sizeof(double) * n);
+        memcpy(pb, start_prev, sizeof(double) * n);
+    } else {
+        for (int it = 0; it < nt; ++it) {
+            og_step(&g, D, pa, pb, pb, lap, &sp, w[it], NULL);
+            double *t = pa;
+            pa = pb;
+            pb = t;
+        }
     }
     /* Now pa = p^nt, pb = p^(nt-1).  Rename for the reverse pass:
      * P1 = p^(k+1), P0 = p^k; M1 = mu^(k+2), M0 = mu^(k+1). */
@@ -502,6 +525,7 @@ int orc_rtm_shot(int ndim, long nx, long ny, long nz, int nb, double h, const fl
          * it with mu^(k+1).  The reconstruction re-injects the source term
          * unless reinject = 0 (Eq. (6) as written, with a zero right side). */
         og_laplacian(&g, P0, lap);
+#pragma omp parallel for schedule(static)
         for (long i = 0; i < n; ++i) src_term[i] = 0.0;
         for (int q = 0; q < sp.n; ++q) src_term[sp.idx[q]] += sp.w[q] / hd * w[k];
 #pragma omp parallel for schedule(static)
@@ -565,6 +589,31 @@ int orc_rtm_shot(int ndim, long nx, long ny, long nz, int nb, double h, const fl
     free(src_term);
     free(rp);
     return 0;
+}
+
+int orc_rtm_shot(int ndim, long nx, long ny, long nz, int nb, double h, const float *v_pad,
+                 double dt, int nt, const double *w, const double *src, int nrec,
+                 const double *rec, const double *g_in, int reinject, double eps_rel,
+                 double *num_out, double *den_out, double *image, double *grad_pad,
+                 double *w_adj, int snap_k, double *snap_p, double *snap_mu)
+{
+    return og_rtm(ndim, nx, ny, nz, nb, h, v_pad, dt, nt, w, src, nrec, rec, g_in, reinject, eps_rel,
+                  num_out, den_out, image, grad_pad, w_adj, snap_k, snap_p, snap_mu, NULL, NULL);
+}
+
+/* orc_rtm_shot with the forward pass replaced by its result: p_last = p^nt
+ * and p_prev = p^(nt-1) (padded, as orc_model_shot returns them), from
+ * which the reverse pass starts.  Equal to orc_rtm_shot when the panels
+ * come from orc_model_shot on the same inputs. */
+int orc_rtm_shot_panels(int ndim, long nx, long ny, long nz, int nb, double h, const float *v_pad,
+                        double dt, int nt, const double *w, const double *src, int nrec,
+                        const double *rec, const double *g_in, int reinject, double eps_rel,
+                        double *num_out, double *den_out, double *image, const double *p_last,
+                        const double *p_prev)
+{
+    if (!p_last || !p_prev) return -1;
+    return og_rtm(ndim, nx, ny, nz, nb, h, v_pad, dt, nt, w, src, nrec, rec, g_in, reinject, eps_rel,
+                  num_out, den_out, image, NULL, NULL, -1, NULL, NULL, p_last, p_prev);
 }
 
 /* ------------------------------------------------------------------ */

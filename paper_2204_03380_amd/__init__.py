@@ -15,17 +15,18 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (RTM_F_ACCUMULATE, RTM_F_CHECK_FINITE, RTM_F_GRAPH, RTM_F_NO_REINJECT, RTM_F_SKIP_CHECK, RTM_OP_MODEL,
+from ._lib import (RTM_F_ACCUMULATE, RTM_F_CHECK_FINITE, RTM_F_GRAPH, RTM_F_PERSISTENT, RTM_F_NO_REINJECT, RTM_F_SKIP_CHECK, RTM_OP_MODEL,
                    RTM_OP_RBC_PAD, RTM_OP_RTM, RTM_OP_STORAGE, RTM_OP_VJP, RTM_TUNE_EXACT, RtmError)
 
 __all__ = [
     "Grid", "RtmError", "rtm_workspace_bytes", "rtm_set_tuning", "rtm_get_tuning", "rtm_set_tuning3d", "rtm_get_tuning3d", "rtm_timing_enable", "rtm_timing_read", "rtm_rbc_pad", "rtm_pad_adjoint",
     "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "RTM_F_SKIP_CHECK", "RTM_F_NO_REINJECT",
     "rtm_nyquist_stride", "rtm_storage_count", "rtm_storage_shot", "RTM_OP_STORAGE",
-    "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD", "RTM_F_ACCUMULATE", "RTM_F_GRAPH", "RTM_F_CHECK_FINITE", "RTM_TUNE_EXACT",
+    "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD", "RTM_F_ACCUMULATE", "RTM_F_GRAPH", "RTM_F_CHECK_FINITE", "RTM_TUNE_EXACT", "RTM_F_PERSISTENT",
     "BatchShot", "BatchPlan", "rtm_window_extract", "rtm_window_accumulate", "rtm_l2_misfit",
     "rtm_set_tuning2d", "rtm_get_tuning2d", "rtm_set_steps_per_launch", "rtm_get_steps_per_launch",
     "tuning_snapshot", "tuning_restore", "rtm_stream_copy", "rtm_rtm_shot_noalloc",
+    "rtm_set_persist_wait", "rtm_get_persist_wait",
 ]
 
 
@@ -163,6 +164,17 @@ def tuning_restore(snap: dict) -> None:
         rtm_set_tuning2d(op, *snap[("2d", op)])
         rtm_set_steps_per_launch(op, snap[("steps", op)])
         rtm_set_tuning3d(op, *snap[("3d", op)])
+
+
+def rtm_set_persist_wait(ms: float) -> None:
+    """Bounded wait (milliseconds) of RTM_F_PERSISTENT passes."""
+    _lib.check(_lib.load().rtm_set_persist_wait(float(ms)))
+
+
+def rtm_get_persist_wait() -> float:
+    v = ctypes.c_double(0.0)
+    _lib.check(_lib.load().rtm_get_persist_wait(ctypes.byref(v)))
+    return float(v.value)
 
 
 LOOP_KINDS = ("model_forward", "rtm_forward", "reverse_image", "reverse_grad")

@@ -33,7 +33,7 @@ EXPORTS = (
     "rtm_pad_adjoint", "rtm_model_shot", "rtm_rtm_shot", "rtm_nyquist_stride", "rtm_storage_count",
     "rtm_storage_shot", "rtm_model_shot_vjp", "rtm_batch_plan", "rtm_batch_run",
     "rtm_batch_free", "rtm_window_extract", "rtm_window_accumulate", "rtm_misfit_ws_bytes", "rtm_l2_misfit",
-    "rtm_stream_copy", "rtm_rtm_shot_noalloc",
+    "rtm_stream_copy", "rtm_rtm_shot_noalloc", "rtm_set_persist_wait", "rtm_get_persist_wait",
     "unet_weight_pack", "unet_conv3d_fwd", "unet_conv3d_dgrad", "unet_wgrad_ws_bytes", "unet_conv3d_wgrad",
     "unet_embed", "unet_pool2", "unet_up2", "unet_up2_bwd", "unet_relu_grad", "unet_mse_ws_bytes", "unet_mse",
     "unet_adam",
@@ -42,6 +42,7 @@ EXPORTS = (
 RTM_F_ACCUMULATE = 0x4
 RTM_F_GRAPH = 0x8
 RTM_F_CHECK_FINITE = 0x10
+RTM_F_PERSISTENT = 0x20
 
 
 class RtmGrid(ctypes.Structure):
@@ -125,6 +126,8 @@ def load():
         "rtm_l2_misfit": ([I64, P, P, P, P, P, SZ, P], ctypes.c_int),
         "rtm_window_accumulate": ([I64, I64, I64, I64, P, P, P], ctypes.c_int),
         "rtm_stream_copy": ([P, P, SZ, ctypes.c_int, P], ctypes.c_int),
+        "rtm_set_persist_wait": ([D], ctypes.c_int),
+        "rtm_get_persist_wait": ([ctypes.POINTER(D)], ctypes.c_int),
         "rtm_rtm_shot_noalloc": ([G, P, D, I32, P, P, I32, P, P, F, P, P, P, U32, P], ctypes.c_int),
         "unet_weight_pack": ([C, P, P, P, P], ctypes.c_int),
         "unet_conv3d_fwd": ([C, P, P, P, I32, P, P, I32, P, P, P], ctypes.c_int),

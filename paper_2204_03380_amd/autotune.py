@@ -1,13 +1,15 @@
-"""Launch-shape autotuner for the 2-D propagation kernels.
+"""Launch-shape autotuner for the propagation kernels.
 
-For a given batch (grid, model, shots), times short runs of the forward
-and the fused reverse kernels for each candidate shape (floats per lane
-`vec`, strips per workgroup `tx` in 2-D or rows per workgroup `ty` in 3-D,
-rows or planes per tile `zseg`) with the library's event timing, keeps the
-fastest shape per kernel and installs it.  Results do
-not depend on the shape (the kernels compute every cell the same way), so
-tuning only changes speed.  Choices can be cached in a JSON file keyed by
-the batch signature.
+For a given batch (grid, model, shots), times short runs of the forward and
+the fused reverse passes for each candidate launch configuration with the
+library's event timing, keeps the fastest per pass and installs it.  A 2-D
+candidate is (steps per launch, floats per lane `vec`, strips per workgroup
+`tx`, rows per tile `zseg`); a 3-D one is (vec, rows per workgroup `ty`,
+planes per tile `zseg`).  Candidates are compared by device time per time
+step, so configurations that advance one, two or three steps per launch
+compete on equal terms.  Results do not depend on the configuration (every
+cell is computed by the same arithmetic), so tuning only changes speed.
+Choices can be cached in a JSON file keyed by the batch signature.
 """
 from __future__ import annotations
 
@@ -18,9 +20,13 @@ from typing import Iterable, Sequence
 import torch
 
 from . import (RTM_F_SKIP_CHECK, RTM_OP_MODEL, RTM_OP_RTM, RTM_TUNE_EXACT, BatchPlan, BatchShot, Grid,
-               rtm_set_tuning, rtm_set_tuning2d, rtm_set_tuning3d, rtm_timing_enable, rtm_timing_read)
+               rtm_get_tuning, rtm_set_steps_per_launch, rtm_set_tuning, rtm_set_tuning2d, rtm_set_tuning3d,
+               rtm_timing_enable, rtm_timing_read)
 
-DEFAULT_SHAPES = tuple((v, x, z) for v in (1, 2, 4) for x in (1, 4) for z in (9, 18, 36, 72, 108))
+# (steps, vec, tx, zseg): the multi-step kernels take one strip per workgroup
+DEFAULT_SHAPES = (tuple((3, v, 1, z) for v in (1, 2, 4) for z in (54, 108, 216)) +
+                  tuple((2, v, 1, z) for v in (2, 4) for z in (36, 108)) +
+                  tuple((1, v, x, z) for v in (1, 2, 4) for x in (1, 4) for z in (18, 36)))
 DEFAULT_SHAPES_3D = tuple((v, y, z) for v in (1, 2, 4) for y in (4, 8) for z in (18, 36))
 
 
@@ -28,29 +34,29 @@ def signature(grid: Grid, nshots: int) -> str:
     return f"{grid.ndim}d:{grid.nx}x{grid.ny}x{grid.nz}:nb{grid.nb}:shots{nshots}"
 
 
-def _install(shape, op, ndim):
-    """2-D: (vec, zseg) keeps the strips per workgroup, (vec, tx, zseg)
-    sets them; 3-D: (vec, ty, zseg)."""
+def install(shape, op, ndim):
+    """Sets the launch configuration of `op`'s kernels: 2-D (steps, vec,
+    tx, zseg); 3-D (vec, ty, zseg)."""
     if ndim == 3:
         rtm_set_tuning3d(op, *shape)
-    elif len(shape) == 3:
-        rtm_set_tuning2d(op, *shape)
     else:
-        rtm_set_tuning(op, *shape)
+        steps, vec, tx, zseg = shape
+        rtm_set_tuning2d(op, vec, tx, zseg)
+        rtm_set_steps_per_launch(op, steps)
 
 
-def _time_shape(shape, grid, v_pad, wavelet, srcs, rec, dt, nt_probe, reps, ws):
-    _install(shape, RTM_OP_MODEL, grid.ndim)
-    _install(shape, RTM_OP_RTM, grid.ndim)
+def _time_shape(shape, grid, v_pad, wavelet, srcs, rec, dt, nt_probe, reps):
+    install(shape, RTM_OP_MODEL, grid.ndim)
+    install(shape, RTM_OP_RTM, grid.ndim)
     dev = v_pad.device
     w = wavelet[:nt_probe].contiguous()
     nrec = len(rec)
     traces = [torch.zeros((nrec, nt_probe + 1), dtype=torch.float32, device=dev) for _ in srcs]
     image = torch.zeros(grid.interior_shape, dtype=torch.float32, device=dev)
     mp = BatchPlan(RTM_OP_MODEL, [BatchShot(grid, v_pad, w, s, rec, traces_out=t) for s, t in zip(srcs, traces)],
-                   dt, nt_probe, flags=RTM_F_SKIP_CHECK, ws=ws)
+                   dt, nt_probe, flags=RTM_F_SKIP_CHECK)
     rp = BatchPlan(RTM_OP_RTM, [BatchShot(grid, v_pad, w, s, rec, traces_in=t, image=image)
-                                for s, t in zip(srcs, traces)], dt, nt_probe, flags=RTM_F_SKIP_CHECK, ws=ws)
+                                for s, t in zip(srcs, traces)], dt, nt_probe, flags=RTM_F_SKIP_CHECK)
     mp.run()
     rp.run()  # warm
     torch.cuda.synchronize()
@@ -62,21 +68,24 @@ def _time_shape(shape, grid, v_pad, wavelet, srcs, rec, dt, nt_probe, reps, ws):
     torch.cuda.synchronize()
     rtm_timing_enable(False)
     t = rtm_timing_read()
-    fwd = t["model_forward"][0] * 1e3 / max(t["model_forward"][1], 1)
-    rev = t["reverse_image"][0] * 1e3 / max(t["reverse_image"][1], 1)
-    ws_needed = max(mp.ws_bytes, rp.ws_bytes)
+    steps = reps * nt_probe
+    fwd = t["model_forward"][0] * 1e3 / steps   # us per time step
+    rev = t["reverse_image"][0] * 1e3 / steps
     mp.free()
     rp.free()
-    return fwd, rev, ws_needed
+    return fwd, rev
 
 
 def tune_batch(grid: Grid, v_pad: torch.Tensor, wavelet: torch.Tensor, srcs: Sequence, rec, dt: float,
                nt_probe: int = 120, reps: int = 2, shapes: Iterable = None,
                cache_path: str | None = None, verbose: bool = False) -> dict:
-    """Picks and installs the fastest forward and reverse shapes for a batch
-    of shots on one grid.  Shapes are (vec, tx, zseg) or (vec, zseg) in 2-D
-    and (vec, ty, zseg) in 3-D.  Returns {"forward": (*shape, us), "reverse": (*shape, us),
-    "table": {...}}."""
+    """Picks and installs the fastest forward and reverse configurations for
+    a batch of shots on one grid (see the module docstring for the shape
+    tuples), each timed exactly as given (no narrowing).  nt_probe should be
+    a multiple of 6 so that every steps-per-launch setting divides it.
+    Returns {"forward": (*shape, us per step), "reverse": (*shape, us per
+    step), "table": {shape: (forward us, reverse us)}}.  The no-narrowing
+    setting is left as it was."""
     if shapes is None:
         shapes = DEFAULT_SHAPES_3D if grid.ndim == 3 else DEFAULT_SHAPES
     key = signature(grid, len(srcs))
@@ -84,24 +93,27 @@ def tune_batch(grid: Grid, v_pad: torch.Tensor, wavelet: torch.Tensor, srcs: Seq
         cache = json.load(open(cache_path))
         if key in cache:
             res = cache[key]
-            _install(tuple(res["forward"][:-1]), RTM_OP_MODEL, grid.ndim)
-            _install(tuple(res["reverse"][:-1]), RTM_OP_RTM, grid.ndim)
+            install(tuple(res["forward"][:-1]), RTM_OP_MODEL, grid.ndim)
+            install(tuple(res["reverse"][:-1]), RTM_OP_RTM, grid.ndim)
             return res
     table = {}
     best_f = best_r = None
-    rtm_set_tuning(RTM_TUNE_EXACT, 1, 0)   # time each shape as given
-    for shape in shapes:
-        fwd, rev, _ = _time_shape(shape, grid, v_pad, wavelet, srcs, rec, dt, nt_probe, reps, None)
-        table["x".join(str(v) for v in shape)] = (fwd, rev)
-        if verbose:
-            print(f"  shape {shape}: forward {fwd:9.2f} us  reverse {rev:9.2f} us", flush=True)
-        if best_f is None or fwd < best_f[-1]:
-            best_f = (*shape, fwd)
-        if best_r is None or rev < best_r[-1]:
-            best_r = (*shape, rev)
-    rtm_set_tuning(RTM_TUNE_EXACT, 0, 0)
-    _install(tuple(best_f[:-1]), RTM_OP_MODEL, grid.ndim)
-    _install(tuple(best_r[:-1]), RTM_OP_RTM, grid.ndim)
+    exact = rtm_get_tuning(RTM_TUNE_EXACT)[0]
+    rtm_set_tuning(RTM_TUNE_EXACT, 1, 0)   # time each configuration as given
+    try:
+        for shape in shapes:
+            fwd, rev = _time_shape(shape, grid, v_pad, wavelet, srcs, rec, dt, nt_probe, reps)
+            table["x".join(str(v) for v in shape)] = (fwd, rev)
+            if verbose:
+                print(f"  {shape}: forward {fwd:9.3f} us/step  reverse {rev:9.3f} us/step", flush=True)
+            if best_f is None or fwd < best_f[-1]:
+                best_f = (*shape, fwd)
+            if best_r is None or rev < best_r[-1]:
+                best_r = (*shape, rev)
+    finally:
+        rtm_set_tuning(RTM_TUNE_EXACT, exact, 0)
+    install(tuple(best_f[:-1]), RTM_OP_MODEL, grid.ndim)
+    install(tuple(best_r[:-1]), RTM_OP_RTM, grid.ndim)
     res = {"forward": best_f, "reverse": best_r, "table": table}
     if cache_path:
         cache = json.load(open(cache_path)) if os.path.exists(cache_path) else {}

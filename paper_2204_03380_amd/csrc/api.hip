@@ -38,6 +38,14 @@ hipError_t launch_fwd2d_t3(int vec, const ShotDev *shots, const Tile2D *tiles, i
                            hipStream_t st);
 hipError_t launch_rev2d_t3(int vec, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                            const InjEnt *ents, const Contrib *cont, int k, int reinject, hipStream_t st);
+hipError_t launch_fwd2d_persist(int vec, const ShotDev *shots, const Tile2D *tiles, const PItem *items, int nitems,
+                                const int *shot_items, const InjEnt *ents, const Contrib *cont,
+                                const SampleTask *stasks, int n0, int nsteps, unsigned *cnt, unsigned *status,
+                                double wait_ms, hipStream_t st);
+hipError_t launch_rev2d_persist(int vec, bool grad, const ShotDev *shots, const Tile2D *tiles, const PItem *items,
+                                int nitems, const int *shot_items, const InjEnt *ents, const Contrib *cont, int k0,
+                                int nsteps, int reinject, float *wadj, unsigned *cnt, unsigned *status,
+                                double wait_ms, hipStream_t st);
 hipError_t launch_recv2d(int vec, int tx, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                          const InjEnt *ents, const Contrib *cont, int k, const float *snap, hipStream_t st);
 // prop3d.hip
@@ -135,6 +143,7 @@ struct Tune {
 std::atomic<int> g_tune2d_fwd{(2 << 28) | (1 << 24) | (2 << 16) | 108};
 std::atomic<int> g_tune2d_rev{(2 << 28) | (1 << 24) | (2 << 16) | 108};
 std::atomic<int> g_tune_exact{0};  // 1: never narrow the configured shapes
+std::atomic<double> g_persist_wait_ms{4000.0};  // bounded wait of persistent passes
 
 // 3-D shapes: (vec << 24) | (ty << 16) | zseg; defaults from a sweep on
 // the 612 x 612 x 356 padded layered-salt grid.
@@ -323,6 +332,7 @@ struct Counts {
     int64_t tiles_f2 = 0, ents_f2 = 0, cont_f2 = 0;  // multi-step tilings (2-D)
     int64_t tiles_r2 = 0, ents_r2 = 0, cont_r2 = 0;
     int64_t stasks = 0, rnode = 0;
+    int64_t pitems_f = 0, pitems_r = 0;  // persistent passes: work items
 };
 
 // Byte offsets of every device buffer inside the workspace.
@@ -330,6 +340,7 @@ struct WsLayout {
     size_t scal = 0, shots = 0, tiles_f = 0, ents_f = 0, cont_f = 0, tiles_r = 0, ents_r = 0, cont_r = 0;
     size_t tiles_f2 = 0, ents_f2 = 0, cont_f2 = 0, tiles_r2 = 0, ents_r2 = 0, cont_r2 = 0;
     size_t stasks = 0, rnode = 0, rw = 0;
+    size_t pitems_f = 0, pitems_r = 0, pnum = 0, pcnt = 0;  // persistent passes
     std::vector<size_t> dp;                  // per D' slot
     std::vector<std::array<size_t, 8>> fld;  // per shot
     std::vector<size_t> acc0, acc1, trint, wadj;
@@ -352,6 +363,10 @@ struct Job {
     std::vector<std::array<int, 2>> srows;  // per shot: padded rows [lo, hi) holding receiver nodes
     std::vector<int> dslot;          // per shot: D' slot
     std::vector<int> slot_shot;      // per slot: first shot using it
+    // persistent passes (RTM_F_PERSISTENT): work items and per-shot item
+    // counts of the forward and reverse passes
+    std::vector<PItem> pitems_f, pitems_r;
+    std::vector<int> pnum;           // [0, nsh): forward, [nsh, 2 nsh): reverse
     WsLayout ws;
     // hipGraph of the launch schedule (plans with RTM_F_GRAPH)
     hipGraphExec_t gexec = nullptr;
@@ -402,6 +417,12 @@ WsLayout make_ws_layout(const Job &J, const Counts &c)
     w.stasks = take(sizeof(SampleTask) * c.stasks);
     w.rnode = take(sizeof(int) * c.rnode * kMaxNodes);
     w.rw = take(sizeof(float) * c.rnode * kMaxNodes);
+    if (c.pitems_f > 0) {
+        w.pitems_f = take(sizeof(PItem) * c.pitems_f);
+        w.pitems_r = take(sizeof(PItem) * std::max<int64_t>(c.pitems_r, 1));
+        w.pnum = take(sizeof(int) * 2 * (size_t)nsh);
+        w.pcnt = take(sizeof(unsigned) * ((size_t)nsh + 1));  // per-shot counters, then the status word
+    }
     for (int d = 0; d < nslot; ++d) w.dp.push_back(take(sizeof(float) * J.shots[J.slot_shot[d]].g.L.total));
     const int nf = nfields(J);
     for (int i = 0; i < nsh; ++i) {
@@ -684,6 +705,7 @@ int build_job_tables(Job &J)
                 if (q < rp.n) {
                     rows[0] = std::min(rows[0], rp.z[q]);
                     rows[1] = std::max(rows[1], rp.z[q] + 1);
+                    // below L.total, which grid_info keeps under 2^31: fits an int
                     J.rnode.push_back((int)((int64_t)rp.z[q] * S.g.L.plane + (int64_t)rp.y[q] * S.g.L.pitch + rp.x[q]));
                     J.rw.push_back((float)rp.w[q]);
                 } else {
@@ -710,15 +732,45 @@ int build_job_tables(Job &J)
         J.dslot.push_back(slot);
     }
     const int ndim = J.shots[0].g.ndim;
+    const bool persist = (J.flags & RTM_F_PERSISTENT) != 0;
     J.fw.ndim = J.rv.ndim = J.fw2.ndim = J.rv2.ndim = ndim;
     J.fw.tune = fit_tune(J, get_tune(0, ndim));
+    if (persist) {
+        // one strip per workgroup, one step per item
+        J.fw.tune.tx = 1;
+        J.fw.tune.steps = 1;
+    }
     int rc = build_tiling(J, J.fw, false);
     if (rc) return rc;
     if (J.op != RTM_OP_MODEL) {
         // the storage reverse pass steps one field, as the forward pass does
         J.rv.tune = fit_tune(J, get_tune(J.op == RTM_OP_STORAGE ? 0 : 1, ndim));
+        if (persist) {
+            J.rv.tune.tx = 1;
+            J.rv.tune.steps = 1;
+        }
         rc = build_tiling(J, J.rv, true);
         if (rc) return rc;
+    }
+    J.pitems_f.clear();
+    J.pitems_r.clear();
+    J.pnum.clear();
+    if (persist) {
+        const int nsh = (int)J.shots.size();
+        J.pnum.assign(2 * (size_t)nsh, 0);
+        for (int t = 0; t < (int)J.fw.tiles.size(); ++t) {
+            J.pitems_f.push_back(PItem{t, J.fw.tiles[t].shot});
+            J.pnum[J.fw.tiles[t].shot]++;
+        }
+        if (J.op == RTM_OP_MODEL)
+            for (int k = 0; k < (int)J.stasks.size(); ++k) {
+                J.pitems_f.push_back(PItem{-1 - k, J.stasks[k].shot});
+                J.pnum[J.stasks[k].shot]++;
+            }
+        for (int t = 0; t < (int)J.rv.tiles.size(); ++t) {
+            J.pitems_r.push_back(PItem{t, J.rv.tiles[t].shot});
+            J.pnum[nsh + J.rv.tiles[t].shot]++;
+        }
     }
     // Multi-step tilings (2-D): the forward one for every op, the reverse
     // one for imaging (up to three steps) and the gradient (two).
@@ -757,6 +809,8 @@ Counts exact_counts(const Job &J)
     c.cont_r2 = J.rv2.cont.size();
     c.stasks = J.stasks.size();
     c.rnode = J.rnode.size() / kMaxNodes;
+    c.pitems_f = J.pitems_f.size();
+    c.pitems_r = J.pitems_r.size();
     return c;
 }
 
@@ -863,6 +917,11 @@ int job_upload_and_check(const Job &J, const Dev &D, std::vector<ShotDev> &shot_
     if ((rc = upload(D, J.ws.stasks, J.stasks, st))) return rc;
     if ((rc = upload(D, J.ws.rnode, J.rnode, st))) return rc;
     if ((rc = upload(D, J.ws.rw, J.rw, st))) return rc;
+    if (!J.pitems_f.empty()) {
+        if ((rc = upload(D, J.ws.pitems_f, J.pitems_f, st))) return rc;
+        if ((rc = upload(D, J.ws.pitems_r, J.pitems_r, st))) return rc;
+        if ((rc = upload(D, J.ws.pnum, J.pnum, st))) return rc;
+    }
     const int nslot = (int)J.slot_shot.size();
     std::vector<unsigned> vr(2 * (size_t)nslot, 0u);
     const bool check = !(J.flags & RTM_F_SKIP_CHECK);
@@ -943,7 +1002,8 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
         const int nsample = sample ? (int)J.stasks.size() : 0;
         const bool two = J.fw.ndim == 2 && J.fw2.steps > 1;
         const int fs = two ? J.fw2.steps : 1;
-        LoopTimer timer(sample ? kLoopModelFwd : kLoopRtmFwd, nt / fs + nt % fs, st, timed);
+        const bool persist = !J.pitems_f.empty();
+        LoopTimer timer(sample ? kLoopModelFwd : kLoopRtmFwd, persist ? 1 : nt / fs + nt % fs, st, timed);
         // Storage RTM: copy the interior of each stored level p^m once it
         // is current (before the step that overwrites p^{m-1} with p^{m+1}).
         auto keep = [&](int m) -> int {
@@ -957,6 +1017,16 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
         };
         int rc = RTM_OK;
         int n = 0;
+        if (persist) {
+            // every forward step in one launch; counters and status start at zero
+            unsigned *cnt = D.at<unsigned>(J.ws.pcnt);
+            RTM_HIP(launch_fill((float *)cnt, nsh + 1, 0.f, st));
+            RTM_HIP(launch_fwd2d_persist(J.fw.tune.vec, SH(), tiles, D.at<PItem>(J.ws.pitems_f),
+                                         (int)J.pitems_f.size(), D.at<int>(J.ws.pnum), ents, cont,
+                                         sample ? stasks : nullptr, 0, nt, cnt, cnt + nsh, g_persist_wait_ms.load(),
+                                         st));
+            n = nt;
+        }
         if (fs == 3) {
             // steps n .. n + 2 per launch; each launch records d^{n-2},
             // d^{n-1}, d^n (no stored levels: not for storage RTM)
@@ -1046,8 +1116,18 @@ int job_launch(const Job &J, const Dev &D, hipStream_t st, const rtm_probe_t *pr
     // wadj is recorded for a single-shot job only (its kernel argument is one
     // buffer); batched VJPs do not return wavelet gradients.
     float *wadj = (grad && nsh == 1 && J.shots[0].grad_wavelet) ? D.at<float>(J.ws.wadj[0]) : nullptr;
-    LoopTimer timer(grad ? kLoopRevGrad : kLoopRevImage, nt / rs + nt % rs, st, timed && !probing);
+    const bool persist = !J.pitems_f.empty() && !probing;
+    LoopTimer timer(grad ? kLoopRevGrad : kLoopRevImage, persist ? 1 : nt / rs + nt % rs, st, timed && !probing);
     int k = nt - 1;
+    if (persist) {
+        // every reverse step in one launch; the status word keeps the forward pass's
+        unsigned *cnt = D.at<unsigned>(J.ws.pcnt);
+        RTM_HIP(launch_fill((float *)cnt, nsh, 0.f, st));
+        RTM_HIP(launch_rev2d_persist(J.rv.tune.vec, grad, SH(), tiles, D.at<PItem>(J.ws.pitems_r),
+                                     (int)J.pitems_r.size(), D.at<int>(J.ws.pnum) + nsh, ents, cont, nt - 1, nt,
+                                     reinject, wadj, cnt, cnt + nsh, g_persist_wait_ms.load(), st));
+        k = -1;
+    }
     if (rs == 3) {
         for (; k >= 2; k -= 3) {
             RTM_HIP(launch_rev2d_t3(J.rv2.tune.vec, SH(), D.at<Tile2D>(J.ws.tiles_r2), J.rv2.count(), J.rv2.nslots,
@@ -1350,6 +1430,20 @@ int rtm_get_tuning(int op, int *vec, int *zseg)
     return RTM_OK;
 }
 
+int rtm_set_persist_wait(double ms)
+{
+    if (!(ms >= 0.0) || !(ms <= 3.6e6)) return fail(RTM_EINVAL, "wait limit must be in [0, 3.6e6] ms");
+    g_persist_wait_ms = ms;
+    return RTM_OK;
+}
+
+int rtm_get_persist_wait(double *ms)
+{
+    if (!ms) return fail(RTM_EINVAL, "NULL output");
+    *ms = g_persist_wait_ms.load();
+    return RTM_OK;
+}
+
 int rtm_timing_enable(int on)
 {
     g_timing_on = on ? 1 : 0;
@@ -1561,6 +1655,10 @@ int rtm_batch_plan(int op, int32_t nshots, const rtm_shot_desc_t *descs, double 
     if (nt < 1) return fail(RTM_EINVAL, "nt must be >= 1");
     if (op == RTM_OP_RTM && (!(eps_rel >= 0.f) || !std::isfinite(eps_rel)))
         return fail(RTM_EINVAL, "eps_rel must be finite and >= 0");
+    if ((flags & RTM_F_PERSISTENT) && (flags & RTM_F_GRAPH))
+        return fail(RTM_EINVAL, "RTM_F_PERSISTENT checks its run's status and cannot be combined with RTM_F_GRAPH");
+    if ((flags & RTM_F_PERSISTENT) && descs[0].grid.ndim != 2)
+        return fail(RTM_EINVAL, "RTM_F_PERSISTENT is implemented for 2-D shots");
     rtm_plan *P = new (std::nothrow) rtm_plan;
     if (!P) return fail(RTM_EINVAL, "out of host memory");
     Job &J = P->job;
@@ -1619,6 +1717,18 @@ int rtm_batch_run(rtm_plan_t *plan, void *ws, size_t ws_bytes, void *stream)
     Dev D{(char *)ws};
     std::vector<ShotDev> shot_devs;
     if ((rc = job_upload_and_check(J, D, shot_devs, st))) return rc;
+    if (J.flags & RTM_F_PERSISTENT) {
+        if ((rc = job_launch(J, D, st, nullptr, true))) return rc;
+        unsigned status = 0;
+        RTM_HIP(hipMemcpyAsync(&status, D.at<unsigned>(J.ws.pcnt) + J.shots.size(), sizeof status,
+                               hipMemcpyDeviceToHost, st));
+        RTM_HIP(hipStreamSynchronize(st));
+        if (status)
+            return fail(RTM_EHIP, "persistent run stopped: a workgroup waited more than %g ms for its shot's "
+                                  "previous step (not all workgroups resident?); outputs are invalid",
+                        g_persist_wait_ms.load());
+        return RTM_OK;
+    }
     if (!(J.flags & RTM_F_GRAPH)) return job_launch(J, D, st, nullptr, true);
     if (!st) return fail(RTM_EINVAL, "RTM_F_GRAPH needs a non-NULL stream (the NULL stream cannot be captured)");
     if (J.gexec && (J.g_ws != ws || J.g_st != st)) {

@@ -132,6 +132,15 @@ struct SampleTask {
     int r0;
 };
 
+// Work item of a persistent pass (one launch for all time steps): a tile
+// (idx >= 0) or a receiver sampling task (idx = -1 - task) of shot `shot`.
+// Each item of a shot waits, at time step r of the pass, until the shot's
+// counter shows all of the shot's items of step r - 1 done.
+struct PItem {
+    int idx;
+    int shot;
+};
+
 // Band options of the random-boundary padding (Eqs. (4)-(5) taper, free
 // surface): passed to the padding kernels by value.
 constexpr int kMaxTaper = 256;

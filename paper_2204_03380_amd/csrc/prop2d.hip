@@ -20,6 +20,8 @@
 // Fields are stored with a zero halo and the scaled velocity term
 // D' = (v dt / h)^2 is zero there, so updating a halo cell reproduces zero;
 // lanes past the grid edge only have to skip their loads and stores.
+#include <atomic>
+
 #include "stencil.h"
 
 namespace rtm {
@@ -205,24 +207,12 @@ __device__ __forceinline__ void rev_row(const RevCtx<VEC> &C, float (&qp)[9][VEC
 // that stored it (same thread, so program order makes the value visible).
 // A workgroup of TX wavefronts covers TX adjacent strips of one tile.
 template <int VEC, int TX>
-__global__ __launch_bounds__(64 * TX) void fwd2d_kernel(const ShotDev *__restrict__ shots,
-                                                        const Tile2D *__restrict__ tiles, int ntiles, int nslots,
-                                                        const InjEnt *__restrict__ ents,
-                                                        const Contrib *__restrict__ cont,
-                                                        const SampleTask *__restrict__ stasks, int nsample, int n)
+__device__ __forceinline__ void fwd2d_tile(const ShotDev *__restrict__ shots, const Tile2D *__restrict__ tiles, int t,
+                                           const InjEnt *__restrict__ ents, const Contrib *__restrict__ cont, int n,
+                                           int w, int lane, EdgeRing<TX> &ring)
 {
-    const int b = blockIdx.x;
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    if (b >= nslots) {
-        const int task = (b - nslots) * TX + w;
-        if (task < nsample) sample_body(shots, stasks[task], n, n & 1, lane);
-        return;
-    }
-    const int t = xcd_tile(b, nslots);
-    if (t >= ntiles) return;  // whole workgroup
     const Tile2D T = tiles[t];
     const ShotDev &S = shots[T.shot];
-    __shared__ EdgeRing<TX> ring;
     FwdCtx<VEC> C;
     C.pitch = S.L.pitch;
     C.NX = S.L.NX;
@@ -262,6 +252,26 @@ __global__ __launch_bounds__(64 * TX) void fwd2d_kernel(const ShotDev *__restric
     }
 }
 
+template <int VEC, int TX>
+__global__ __launch_bounds__(64 * TX) void fwd2d_kernel(const ShotDev *__restrict__ shots,
+                                                        const Tile2D *__restrict__ tiles, int ntiles, int nslots,
+                                                        const InjEnt *__restrict__ ents,
+                                                        const Contrib *__restrict__ cont,
+                                                        const SampleTask *__restrict__ stasks, int nsample, int n)
+{
+    const int b = blockIdx.x;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (b >= nslots) {
+        const int task = (b - nslots) * TX + w;
+        if (task < nsample) sample_body(shots, stasks[task], n, n & 1, lane);
+        return;
+    }
+    const int t = xcd_tile(b, nslots);
+    if (t >= ntiles) return;  // whole workgroup
+    __shared__ EdgeRing<TX> ring;
+    fwd2d_tile<VEC, TX>(shots, tiles, t, ents, cont, n, w, lane, ring);
+}
+
 // Reverse step k of every tile, Eqs. (2), (3) and (6) in one pass:
 //   p^{k-1} = 2 p^k - p^{k+1} + D' (L p^k + s^k)         (reconstruction)
 //   mu^k    = 2 mu^{k+1} - mu^{k+2} + D' (L mu^{k+1} + r^k)  (receiver field)
@@ -275,6 +285,80 @@ __global__ __launch_bounds__(64 * TX) void fwd2d_kernel(const ShotDev *__restric
 // With one float per lane the reverse kernel fits in 64 registers; asking
 // for 8 waves per SIMD then hides more latency (measured: 4.5 vs 4.2 TB/s
 // on 16 shots of the 2301 x 751 grid).  Wider lanes would spill.
+// rev2d_kernel's tile body as a function, for the persistent pass.  The
+// kernel keeps its own copy of the body: compiled through this function,
+// its one-float-per-lane instance (held to 64 registers for 8 waves per
+// SIMD) spills 156 bytes per lane, while the copy fits.
+template <int VEC, bool GRAD, int TX>
+__device__ __forceinline__ void rev2d_tile(const ShotDev *__restrict__ shots, const Tile2D *__restrict__ tiles, int t,
+                                           const InjEnt *__restrict__ ents, const Contrib *__restrict__ cont, int k,
+                                           int reinject, float *__restrict__ wadj, int w, int lane,
+                                           EdgeRing<TX> &ring_p, EdgeRing<TX> &ring_m)
+{
+    const Tile2D T = tiles[t];
+    const ShotDev &S = shots[T.shot];
+    RevCtx<VEC> C;
+    C.pitch = S.L.pitch;
+    C.NX = S.L.NX;
+    C.P0 = gp(S.fld[k & 1] + S.L.org);
+    C.P1 = gp(S.fld[(k + 1) & 1] + S.L.org);
+    C.M0 = gp(S.fld[2 + ((k + 1) & 1)] + S.L.org);
+    C.M1 = gp(S.fld[2 + (k & 1)] + S.L.org);
+    C.Dp = gp(S.Dp + S.L.org);
+    C.A0 = gp(S.acc0 + S.L.org);
+    C.A1 = GRAD ? nullptr : gp(S.acc1 + S.L.org);
+    C.lane = lane;
+    C.w = w;
+    C.x0 = T.x0 + w * 64 * VEC;
+    C.x = C.x0 + lane * VEC;
+    C.live = C.x < C.NX + kRadius;
+    C.own = C.x < C.NX;
+    // Lanes whose cells overlap the interior accumulate the image sums (their
+    // other cells lie in the band or halo, whose sums are never read).
+    C.own_img = C.own && C.x + VEC > S.ix0 && C.x < S.ix1;
+    C.iz0 = S.iz0;
+    C.iz1 = S.iz1;
+    C.reinject = reinject != 0;
+
+    float qp[9][VEC], qm[9][VEC];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+#pragma unroll
+        for (int j = 0; j < VEC; ++j) qp[i][j] = qm[i][j] = 0.f;
+        if (C.live) {
+            ldv<VEC>(C.P0 + (int64_t)(T.z0 - 4 + i) * C.pitch + C.x, qp[i]);
+            ldv<VEC>(C.M0 + (int64_t)(T.z0 - 4 + i) * C.pitch + C.x, qm[i]);
+        }
+        if constexpr (TX > 1)
+            if (i >= 4) {
+                ring_put<VEC, TX>(ring_p, i - 4, w, lane, qp[i]);
+                ring_put<VEC, TX>(ring_m, i - 4, w, lane, qm[i]);
+            }
+    }
+    f4v hp = f4v{0.f, 0.f, 0.f, 0.f}, hm = hp;  // (the reverse rows load their halo in-step)
+#define RTM_REV_ROW(SS, ZZ) rev_row<VEC, GRAD, TX, SS>(C, qp, qm, ZZ, ring_p, ring_m, hp, hm)
+    RTM_MARCH(RTM_REV_ROW)
+#undef RTM_REV_ROW
+    // Source term at step k: reconstruction (re-injection), gradient, wavelet adjoint.
+    const float *wav = S.wav + k;
+    for (int e = T.sbeg; e < T.send; ++e) {
+        const InjEnt E = ents[e];
+        if (owns<VEC>(E.x, C.x0, C.lane)) {
+            const int64_t o = (int64_t)E.z * C.pitch + E.x;
+            const float sv = inj_sum(E, cont, wav);
+            if (C.reinject) C.P1[o] = fmaf(C.Dp[o], sv, C.P1[o]);
+            if (GRAD) C.A0[o] = fmaf(C.M0[o], C.Dp[o] * sv, C.A0[o]);
+            if (wadj) {
+                float wsum = 0.f;
+                for (int c = E.cbeg; c < E.cend; ++c) wsum += cont[c].w;
+                wadj[(int64_t)k * kMaxNodes + E.slot] = wsum * C.M0[o];
+            }
+        }
+    }
+    // Receiver term: mu^k += D' R^T g^k.
+    inject_nodes(C.M1, C.Dp, ents, T.rbeg, T.rend, cont, S.sig + (int64_t)k * S.nrec, C.pitch, C.pitch);
+}
+
 template <int VEC, bool GRAD, int TX>
 __global__ __launch_bounds__(64 * TX) __attribute__((amdgpu_waves_per_eu(VEC == 1 ? 8 : 1, 8)))
 void rev2d_kernel(const ShotDev *__restrict__ shots, const Tile2D *__restrict__ tiles, int ntiles, int nslots,
@@ -1359,8 +1443,194 @@ void rev2d_t3_kernel(const ShotDev *__restrict__ shots, const Tile2D *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// Persistent passes: one launch for all time steps of a pass
+// ---------------------------------------------------------------------------
+//
+// A grid small enough to be resident as a whole (sized from the occupancy
+// of the kernel) walks the pass's work items (tiles, and in modeling the
+// receiver sampling tasks) step after step: workgroup b takes items b,
+// b + G, b + 2G, ... of every step.  The steps of different shots are not
+// tied to each other: an item of shot s at step r waits only until the
+// counter of shot s shows all of that shot's items of step r - 1 done
+// (r * items(s) completions), so a shot with little work runs ahead of a
+// larger one.  One wave per workgroup: after an item the wave makes its
+// stores visible to the whole GPU (agent-scope release fence, which also
+// writes them back from this XCD's L2) and lane 0 increments the counter;
+// a waiting wave's lane 0 reads the counter, and once it suffices the wave
+// takes an agent-scope acquire fence (dropping stale L1/L2 lines) before
+// touching the fields.  Every wait is bounded: after `limit` ticks of the
+// constant 100 MHz clock, or as soon as another workgroup has given up, the
+// waiting workgroup sets *status and returns, so a grid that cannot make
+// progress (not all workgroups resident) still ends.
+
+// Waits until *cnt >= target (lane 0 polls); false if the pass was abandoned.
+__device__ __forceinline__ bool persist_wait(unsigned *cnt, unsigned target, unsigned *status, uint64_t limit,
+                                             int lane)
+{
+    int ok = 1;
+    if (lane == 0) {
+        const uint64_t t0 = wall_clock64();
+        while (__hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u ||
+                wall_clock64() - t0 > limit) {
+                ok = 0;
+                break;
+            }
+            __builtin_amdgcn_s_sleep(1);
+        }
+        if (!ok) __hip_atomic_store(status, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    ok = __builtin_amdgcn_readfirstlane(ok);
+    if (ok) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok != 0;
+}
+
+// Publishes the item just done: this wave's stores, then the count.
+__device__ __forceinline__ void persist_done(unsigned *cnt, int lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    if (lane == 0) __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Forward steps n0 .. n0 + nsteps - 1 (fwd2d_kernel's step, one strip per
+// workgroup), with the sampling tasks of each step when stasks != nullptr.
+template <int VEC>
+__global__ __launch_bounds__(64) void fwd2d_persist_kernel(const ShotDev *__restrict__ shots,
+                                                           const Tile2D *__restrict__ tiles,
+                                                           const PItem *__restrict__ items, int nitems,
+                                                           const int *__restrict__ shot_items,
+                                                           const InjEnt *__restrict__ ents,
+                                                           const Contrib *__restrict__ cont,
+                                                           const SampleTask *__restrict__ stasks, int n0, int nsteps,
+                                                           unsigned *cnt, unsigned *status, uint64_t limit)
+{
+    const int lane = threadIdx.x & 63;
+    __shared__ EdgeRing<1> ring;
+    for (int r = 0; r < nsteps; ++r) {
+        const int n = n0 + r;
+        for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+            const PItem it = items[i];
+            if (!persist_wait(cnt + it.shot, (unsigned)r * (unsigned)shot_items[it.shot], status, limit, lane)) return;
+            if (it.idx >= 0) {
+                fwd2d_tile<VEC, 1>(shots, tiles, it.idx, ents, cont, n, 0, lane, ring);
+            } else {
+                sample_body(shots, stasks[-1 - it.idx], n, n & 1, lane);
+            }
+            persist_done(cnt + it.shot, lane);
+        }
+    }
+}
+
+// Reverse steps k0, k0 - 1, ..., k0 - nsteps + 1 (rev2d_kernel's step).
+template <int VEC, bool GRAD>
+__global__ __launch_bounds__(64) void rev2d_persist_kernel(const ShotDev *__restrict__ shots, const Tile2D *__restrict__ tiles,
+                          const PItem *__restrict__ items, int nitems, const int *__restrict__ shot_items,
+                          const InjEnt *__restrict__ ents, const Contrib *__restrict__ cont, int k0, int nsteps,
+                          int reinject, float *__restrict__ wadj, unsigned *cnt, unsigned *status, uint64_t limit)
+{
+    const int lane = threadIdx.x & 63;
+    __shared__ EdgeRing<1> ring_p, ring_m;
+    for (int r = 0; r < nsteps; ++r) {
+        const int k = k0 - r;
+        for (int i = blockIdx.x; i < nitems; i += gridDim.x) {
+            const PItem it = items[i];
+            if (!persist_wait(cnt + it.shot, (unsigned)r * (unsigned)shot_items[it.shot], status, limit, lane)) return;
+            rev2d_tile<VEC, GRAD, 1>(shots, tiles, it.idx, ents, cont, k, reinject, wadj, 0, lane, ring_p, ring_m);
+            persist_done(cnt + it.shot, lane);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host launchers
 // ---------------------------------------------------------------------------
+
+// Workgroups of a persistent launch: at most what the GPU holds resident at
+// once (occupancy of the kernel times the compute units), at most nitems;
+// and the bounded wait in ticks of the constant clock.
+template <class K>
+hipError_t persist_grid(K kernel, int nitems, double wait_ms, int *grid, uint64_t *limit)
+{
+    int dev = 0, cus = 0, per_cu = 0, khz = 0;
+    hipError_t e;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess) return e;
+    if ((e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev)) != hipSuccess) return e;
+    if ((e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64, 0)) != hipSuccess) return e;
+    if (per_cu < 1 || cus < 1) return hipErrorInvalidConfiguration;
+    const int64_t g = std::min<int64_t>((int64_t)per_cu * cus, nitems);
+    *grid = (int)std::max<int64_t>(g, 1);
+    *limit = (uint64_t)((double)(khz > 0 ? khz : 100000) * wait_ms);
+    return hipSuccess;
+}
+
+template <int V>
+hipError_t fwd2d_persist_launch(const ShotDev *shots, const Tile2D *tiles, const PItem *items, int nitems,
+                                const int *shot_items, const InjEnt *ents, const Contrib *cont,
+                                const SampleTask *stasks, int n0, int nsteps, unsigned *cnt, unsigned *status,
+                                double wait_ms, hipStream_t st)
+{
+    int grid = 0;
+    uint64_t limit = 0;
+    hipError_t e = persist_grid(fwd2d_persist_kernel<V>, nitems, wait_ms, &grid, &limit);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((fwd2d_persist_kernel<V>), dim3(grid), dim3(64), 0, st, shots, tiles, items, nitems,
+                       shot_items, ents, cont, stasks, n0, nsteps, cnt, status, limit);
+    return hipGetLastError();
+}
+
+template <int V, bool G>
+hipError_t rev2d_persist_launch(const ShotDev *shots, const Tile2D *tiles, const PItem *items, int nitems,
+                                const int *shot_items, const InjEnt *ents, const Contrib *cont, int k0, int nsteps,
+                                int reinject, float *wadj, unsigned *cnt, unsigned *status, double wait_ms,
+                                hipStream_t st)
+{
+    int grid = 0;
+    uint64_t limit = 0;
+    hipError_t e = persist_grid(rev2d_persist_kernel<V, G>, nitems, wait_ms, &grid, &limit);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((rev2d_persist_kernel<V, G>), dim3(grid), dim3(64), 0, st, shots, tiles, items, nitems,
+                       shot_items, ents, cont, k0, nsteps, reinject, wadj, cnt, status, limit);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd2d_persist(int vec, const ShotDev *shots, const Tile2D *tiles, const PItem *items, int nitems,
+                                const int *shot_items, const InjEnt *ents, const Contrib *cont,
+                                const SampleTask *stasks, int n0, int nsteps, unsigned *cnt, unsigned *status,
+                                double wait_ms, hipStream_t st)
+{
+    if (nitems < 1 || nsteps < 1) return hipSuccess;
+    switch (vec) {
+    case 1: return fwd2d_persist_launch<1>(shots, tiles, items, nitems, shot_items, ents, cont, stasks, n0, nsteps, cnt,
+                                           status, wait_ms, st);
+    case 2: return fwd2d_persist_launch<2>(shots, tiles, items, nitems, shot_items, ents, cont, stasks, n0, nsteps, cnt,
+                                           status, wait_ms, st);
+    case 4: return fwd2d_persist_launch<4>(shots, tiles, items, nitems, shot_items, ents, cont, stasks, n0, nsteps, cnt,
+                                           status, wait_ms, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_rev2d_persist(int vec, bool grad, const ShotDev *shots, const Tile2D *tiles, const PItem *items,
+                                int nitems, const int *shot_items, const InjEnt *ents, const Contrib *cont, int k0,
+                                int nsteps, int reinject, float *wadj, unsigned *cnt, unsigned *status,
+                                double wait_ms, hipStream_t st)
+{
+    if (nitems < 1 || nsteps < 1) return hipSuccess;
+#define RTM_REVP(V, G) \
+    rev2d_persist_launch<V, G>(shots, tiles, items, nitems, shot_items, ents, cont, k0, nsteps, reinject, wadj, cnt, \
+                               status, wait_ms, st)
+    switch (vec * 2 + (grad ? 1 : 0)) {
+    case 2: return RTM_REVP(1, false);
+    case 3: return RTM_REVP(1, true);
+    case 4: return RTM_REVP(2, false);
+    case 5: return RTM_REVP(2, true);
+    case 8: return RTM_REVP(4, false);
+    case 9: return RTM_REVP(4, true);
+    default: return hipErrorInvalidValue;
+    }
+#undef RTM_REVP
+}
 
 hipError_t launch_fwd2d(int vec, int tx, const ShotDev *shots, const Tile2D *tiles, int ntiles, int nslots,
                         const InjEnt *ents, const Contrib *cont, const SampleTask *stasks, int nsample, int n,

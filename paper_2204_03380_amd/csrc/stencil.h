@@ -51,26 +51,12 @@ __device__ __forceinline__ void ldv(const gfloat *p, float (&v)[VEC])
     }
 }
 
-// Streams read or written once per step: non-temporal hints (RTM_NT_STREAMS).
-#ifndef RTM_NT_STREAMS
-#define RTM_NT_STREAMS 0
-#endif
+// Loads and stores of the arrays a launch streams through once (the _s
+// forms mark those call sites; they are the plain accesses).
 template <int VEC>
 __device__ __forceinline__ void ldv_s(const gfloat *p, float (&v)[VEC])
 {
-#if RTM_NT_STREAMS
-    if constexpr (VEC == 4) {
-        const f4v t = __builtin_nontemporal_load((const gf4v *)p);
-        v[0] = t.x; v[1] = t.y; v[2] = t.z; v[3] = t.w;
-    } else if constexpr (VEC == 2) {
-        const f2v t = __builtin_nontemporal_load((const gf2v *)p);
-        v[0] = t.x; v[1] = t.y;
-    } else {
-        v[0] = __builtin_nontemporal_load(p);
-    }
-#else
     ldv<VEC>(p, v);
-#endif
 }
 
 template <int VEC>
@@ -79,17 +65,7 @@ __device__ __forceinline__ void stv(gfloat *p, const float (&v)[VEC]);
 template <int VEC>
 __device__ __forceinline__ void stv_s(gfloat *p, const float (&v)[VEC])
 {
-#if RTM_NT_STREAMS
-    if constexpr (VEC == 4) {
-        __builtin_nontemporal_store(f4v{v[0], v[1], v[2], v[3]}, (gf4v *)p);
-    } else if constexpr (VEC == 2) {
-        __builtin_nontemporal_store(f2v{v[0], v[1]}, (gf2v *)p);
-    } else {
-        __builtin_nontemporal_store(v[0], p);
-    }
-#else
     stv<VEC>(p, v);
-#endif
 }
 
 template <int VEC>

@@ -27,3 +27,13 @@ def _restore_launch_settings(request):
         yield
     finally:
         rtm.tuning_restore(snap)
+
+
+@pytest.fixture
+def progress(capsys):
+    """Prints a line past pytest's output capture, at once: long tests mark
+    the end of each step with it, so that a long run is visibly alive."""
+    def say(msg):
+        with capsys.disabled():
+            print(f"  [{msg}]", flush=True)
+    return say

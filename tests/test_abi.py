@@ -45,6 +45,14 @@ def test_workspace_bytes_and_grid_validation():
         assert e.value.status == _lib.RTM_EINVAL
     with pytest.raises(rtm.RtmError):
         rtm.rtm_workspace_bytes(g, 7, 1, 1)
+    # every extent is allowed on its own, but a field of 2^31 floats or more
+    # is refused (cell offsets are 32-bit), in 3-D and in 2-D
+    assert rtm.rtm_workspace_bytes(rtm.Grid(3, 1250, 1250, 1250, 10.0, 0), rtm.RTM_OP_MODEL, 1, 1) > 0
+    for big in (rtm.Grid(3, 1300, 1300, 1300, 10.0, 0), rtm.Grid(3, 200000, 10, 1000, 10.0, 0),
+                rtm.Grid(2, 60000, 1, 40000, 10.0, 0)):
+        with pytest.raises(rtm.RtmError) as e:
+            rtm.rtm_workspace_bytes(big, rtm.RTM_OP_MODEL, 1, 1)
+        assert e.value.status == _lib.RTM_EINVAL and "2^31" in str(e.value)
 
 
 def test_set_tuning_validation():
@@ -193,3 +201,40 @@ def test_unet_channel_pairs_on_the_host():
     # tiny images still get one block
     rc, b = ws((1, 2, 2, 2), 1, 16)
     assert rc == _lib.RTM_OK and b == rnd(432 * 4) + rnd(16 * 4) + rnd(432 * 4) + rnd(16 * 4)
+
+
+def test_persistent_plan_validation_on_the_host():
+    """RTM_F_PERSISTENT: refused with RTM_F_GRAPH and for 3-D shots at plan
+    time (no device work; fake device addresses are never dereferenced);
+    the wait limit is range-checked and read back."""
+    lib = _lib.load()
+
+    def plan(grid, flags):
+        d = _lib.RtmShotDesc()
+        d.grid = grid.c()
+        d.v_pad, d.wavelet, d.traces_out = 0x10000, 0x20000, 0x30000
+        d.src[0], d.src[1], d.src[2] = 2.0, 1.0 if grid.ndim == 3 else 0.0, 2.0
+        rec = np.ascontiguousarray(np.array([[1.0, 1.0 if grid.ndim == 3 else 0.0, 2.0]], np.float32))
+        d.nrec, d.rec = 1, rec.ctypes.data
+        out, ws = ctypes.c_void_p(), ctypes.c_size_t()
+        rc = lib.rtm_batch_plan(rtm.RTM_OP_MODEL, 1, ctypes.byref(d), 1e-3, 20, 1e-3, flags, ctypes.byref(out),
+                                ctypes.byref(ws))
+        if rc == 0:
+            lib.rtm_batch_free(out)
+        return rc, ws.value
+
+    g2 = rtm.Grid(2, 30, 1, 20, 10.0, 4)
+    rc, ws_p = plan(g2, rtm.RTM_F_PERSISTENT)
+    assert rc == 0
+    rc, ws_n = plan(g2, 0)
+    assert rc == 0 and ws_p > ws_n  # work items, counters and status word
+    assert plan(g2, rtm.RTM_F_PERSISTENT | rtm.RTM_F_GRAPH)[0] == _lib.RTM_EINVAL
+    assert plan(rtm.Grid(3, 10, 10, 10, 10.0, 2), rtm.RTM_F_PERSISTENT)[0] == _lib.RTM_EINVAL
+    old = rtm.rtm_get_persist_wait()
+    assert old == 4000.0
+    for bad in (-1.0, float("nan"), 4e6):
+        with pytest.raises(rtm.RtmError):
+            rtm.rtm_set_persist_wait(bad)
+    rtm.rtm_set_persist_wait(250.0)
+    assert rtm.rtm_get_persist_wait() == 250.0
+    rtm.rtm_set_persist_wait(old)

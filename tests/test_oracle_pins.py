@@ -368,6 +368,27 @@ def test_time_reversal(ndim):
     assert worst <= 1e-10 * pmax, worst / pmax
 
 
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_rtm_from_given_panels_equals_full_rtm(ndim):
+    """Starting the reverse pass from the final panels that modeling returns
+    gives the migration of the full call bit for bit (both reconstructions
+    start from the same p^nt, p^(nt-1))."""
+    if ndim == 2:
+        s = synth.config_small2d(nt=160)
+        v, nb, src, rec = s.v_int, s.nb, s.src[0], s.rec
+    else:
+        v = synth.random_model((12, 11, 14), 4, 1600, 2600)
+        nb, src = 4, np.array([6.5, 5.0, 2.25])
+        rec = synth.grid_receivers(np.arange(0, 14, 3), np.arange(0, 11, 3), 2.0)
+    vp = oracle.rbc_pad(v, nb, 8, 0.0)
+    w = synth.ricker(25.0, 1e-3, 160).astype(np.float64)
+    d, pl, pp = oracle.model_shot(vp, 10.0, nb, 1e-3, w, src, rec, want_last=True)
+    full = oracle.rtm_shot(vp, 10.0, nb, 1e-3, w, src, rec, d, eps_rel=1e-3)
+    part = oracle.rtm_shot_from_panels(vp, 10.0, nb, 1e-3, w, src, rec, d, pl, pp, eps_rel=1e-3)
+    for k in ("num", "den", "image"):
+        assert np.array_equal(full[k], part[k]), k
+
+
 def test_reconstruction_without_reinjection_differs_only_early():
     """Eq. (6) as written (zero right-hand side) is exact once the wavelet
     has ended but not while it is still active."""
