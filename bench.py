@@ -71,6 +71,9 @@ def parse():
                          "known size, to scale hardware byte counters)")
     ap.add_argument("--autotune", action="store_true", help="pick launch shapes with the autotuner first")
     ap.add_argument("--no-unet", action="store_true", help="skip the learned-filter training-step timing")
+    ap.add_argument("--no-c3", action="store_true", help="skip the full-size 3-D shot")
+    ap.add_argument("--unet-only", action="store_true",
+                    help="instead of the survey benchmark: only the crosstalk filter's 128^3 training-step timing")
     ap.add_argument("--paper-shapes", action="store_true",
                     help="instead of the survey benchmark: single-shot modeling and RTM at the grid sizes of the "
                          "paper's Tables 1-4 (modeling timed over a shortened nt and scaled to the paper's nt; "
@@ -163,6 +166,61 @@ def unet_report(steps=10):
             "train_step_ms": round(e0.elapsed_time(e1) / steps, 3),
             "conv_ms": round(conv_ms, 3), "conv_tflops": round(gflop / conv_ms, 2),
             "layers": [{k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()} for r in layers]}
+
+
+def c3_report(nt=4000):
+    """One shot of the 3-D layered-salt workload at full size (512 x 512 x 256
+    interior, 612 x 612 x 356 padded, nt 4000, 65 536 receivers): modeling
+    of the observed data, then RTM (forward, fused reverse, image), timed
+    with events; Gcell-updates/s over the four propagations, and the fused
+    reverse kernel's rate on its algorithmic bytes (one step per launch:
+    28 B per padded cell + 16 B per interior cell)."""
+    import numpy as np
+    import torch
+
+    import paper_2204_03380_amd as rtm
+    import synth
+    dev = torch.device("cuda:0")
+    s = synth.config_c3(nt=nt)
+    g = rtm.Grid.for_model(s.v_int, s.h, s.nb)
+    vp = rtm.rtm_rbc_pad(g, torch.from_numpy(s.v_int).to(dev), s.seed, 0.0)
+    w = torch.from_numpy(s.wavelet).to(dev)
+    cells = int(np.prod(g.padded_shape))
+    interior = int(s.v_int.size)
+    torch.cuda.synchronize()
+    rtm.rtm_timing_read()
+    rtm.rtm_timing_enable(True)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    d = rtm.rtm_model_shot(g, vp, s.dt, w, s.src[0], s.rec)
+    e1.record()
+    im = rtm.rtm_rtm_shot(g, vp, s.dt, w, s.src[0], s.rec, d, eps_rel=1e-3)["image"]
+    e2.record()
+    e2.synchronize()
+    rtm.rtm_timing_enable(False)
+    loops = rtm.rtm_timing_read()
+    assert torch.isfinite(im).all()
+    t_model, t_rtm = e0.elapsed_time(e1) * 1e-3, e1.elapsed_time(e2) * 1e-3
+    rev_ms, rev_n = loops["reverse_image"]
+    fwd_ms, fwd_n = loops["rtm_forward"]
+    rev_us, fwd_us = rev_ms * 1e3 / max(rev_n, 1), fwd_ms * 1e3 / max(fwd_n, 1)
+    rev_bytes = 28 * cells + 16 * interior
+    fwd_bytes = 16 * cells
+    vec_f, ty_f, z_f = rtm.rtm_get_tuning3d(rtm.RTM_OP_MODEL)
+    vec_r, ty_r, z_r = rtm.rtm_get_tuning3d(rtm.RTM_OP_RTM)
+    del d, im
+    torch.cuda.empty_cache()
+    return {"workload": f"layered salt 3-D 512x512x256 @ 10 m, nb 50, nt {nt}, 12 Hz, 256x256 receivers: one shot "
+                        "modeled then migrated",
+            "padded_cells": cells, "model_s": round(t_model, 3), "rtm_s": round(t_rtm, 3),
+            "value": round(cells * nt * 4 / (t_model + t_rtm) / 1e9, 2), "unit": "Gcell-updates/s",
+            "roofline": {"bound": "hbm", "kernel": f"rev3d_kernel<{vec_r},{ty_r},false> (fused reverse, one step)",
+                         "avg_launch_us": round(rev_us, 2), "algorithmic_bytes_per_launch": rev_bytes,
+                         "achieved": round(rev_bytes / (rev_us * 1e-6) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(rev_bytes / (rev_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)},
+            "forward": {"kernel": f"fwd3d_kernel<{vec_f},{ty_f}>", "avg_launch_us": round(fwd_us, 2),
+                        "achieved_GBps": round(fwd_bytes / (fwd_us * 1e-6) / 1e9, 1),
+                        "frac": round(fwd_bytes / (fwd_us * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
 # The paper's single-shot times (seconds) on its hardware: one V100 (OpenACC)
@@ -502,6 +560,12 @@ def main():
                           "higher_is_better": False, "dtype": "f32", "data": "synthetic", **out}), flush=True)
         return
 
+    if args.unet_only:
+        print(json.dumps({"metric": "crosstalk filter training step (128^3, forward + backward + Adam)",
+                          "unit": "ms", "n_gpus": 1, "higher_is_better": False, "dtype": "bf16 (fp32 accumulation)",
+                          "data": "synthetic", "unet_train_step": unet_report()}), flush=True)
+        return
+
     if args.persistent_study:
         rows = persistent_study()
         print(json.dumps({"metric": "batch plan device time: launch per step(s), hipGraph, persistent passes",
@@ -746,6 +810,8 @@ def main():
         "wall_s": round(wall, 3),
         "device": device_info(),
     }
+    if not args.no_c3:
+        line["c3"] = c3_report()
     if not args.no_unet:
         line["unet_train_step"] = unet_report()
     if not args.no_cpu_baseline:

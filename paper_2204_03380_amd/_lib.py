@@ -36,7 +36,7 @@ EXPORTS = (
     "rtm_stream_copy", "rtm_rtm_shot_noalloc", "rtm_set_persist_wait", "rtm_get_persist_wait",
     "unet_weight_pack", "unet_conv3d_fwd", "unet_conv3d_dgrad", "unet_wgrad_ws_bytes", "unet_conv3d_wgrad",
     "unet_embed", "unet_pool2", "unet_up2", "unet_up2_bwd", "unet_relu_grad", "unet_mse_ws_bytes", "unet_mse",
-    "unet_adam",
+    "unet_adam", "unet_set_conv_lds", "unet_get_conv_lds",
 )
 
 RTM_F_ACCUMULATE = 0x4
@@ -142,6 +142,8 @@ def load():
         "unet_mse_ws_bytes": ([I64, ctypes.POINTER(SZ)], ctypes.c_int),
         "unet_mse": ([I64, I32, P, P, P, P, P, ctypes.POINTER(D), P, SZ, P], ctypes.c_int),
         "unet_adam": ([I64, P, P, P, P, D, D, D, D, I32, P], ctypes.c_int),
+        "unet_set_conv_lds": ([I32], ctypes.c_int),
+        "unet_get_conv_lds": ([ctypes.POINTER(I32)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

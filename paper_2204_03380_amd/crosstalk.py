@@ -126,13 +126,16 @@ class PairSet:
 
 
 def train(net: UNet, data: PairSet, epochs: int, lr: float = 1e-3, batch: int = 1, seed: int = 0,
-          lr_decay: float = 1.0, flips: bool = True, log=None):
+          lr_decay: float = 1.0, flips: bool = True, log=None, warmup: int = 0):
     """Adam on the mean squared error; returns the mean loss of each epoch.
     With flips, each sample is mirrored along x and/or y at random (the
     acquisition and the crosstalk statistics have no preferred lateral
-    direction)."""
+    direction).  The learning rate rises linearly over the first `warmup`
+    epochs (per step) to `lr`, then decays by `lr_decay` per epoch."""
     rng = np.random.default_rng(seed)
     hist = []
+    steps_per_epoch = (len(data) + batch - 1) // batch
+    step = 0
 
     def aug(a, f):
         dims = [d for d, on in ((-1, f & 1), (-2, f & 2)) if on]
@@ -146,10 +149,13 @@ def train(net: UNet, data: PairSet, epochs: int, lr: float = 1e-3, batch: int = 
             fl = rng.integers(0, 4, len(idx)) if flips else np.zeros(len(idx), int)
             x = torch.stack([aug(data.inputs[j], f) for j, f in zip(idx, fl)])
             t = torch.stack([aug(data.targets[j], f) for j, f in zip(idx, fl)])
-            tot += net.train_step(x, t, lr)
+            ramp = min(1.0, (step + 1) / (warmup * steps_per_epoch)) if warmup > 0 else 1.0
+            tot += net.train_step(x, t, lr * ramp)
             cnt += 1
+            step += 1
         hist.append(tot / cnt)
-        lr *= lr_decay
+        if ep >= warmup:
+            lr *= lr_decay
         if log:
             log(f"epoch {ep + 1}/{epochs}: loss {hist[-1]:.5f}")
     return hist
@@ -234,6 +240,8 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=10)
     ap.add_argument("--batch", type=int, default=1)
     ap.add_argument("--lr", type=float, default=3e-4)
+    ap.add_argument("--lr-decay", type=float, default=0.97, help="learning-rate factor per epoch after the warm-up")
+    ap.add_argument("--warmup", type=int, default=0, help="epochs of linear learning-rate warm-up")
     ap.add_argument("--nt", type=int, default=1100)
     ap.add_argument("--infer-shape", default=None,
                     help="after training, migrate one model of this interior shape NZ,NY,NX (multiples of 8) with "
@@ -253,7 +261,7 @@ def main(argv=None):
     train_set, test_set = data.split(set(range(a.geometries - a.held_out, a.geometries)))
     net = UNet(seed=0)
     t0 = time.time()
-    hist = train(net, train_set, a.epochs, a.lr, a.batch, lr_decay=0.97, log=log)
+    hist = train(net, train_set, a.epochs, a.lr, a.batch, lr_decay=a.lr_decay, log=log, warmup=a.warmup)
     torch.cuda.synchronize()
     t_train = time.time() - t0
     den = Denoiser(net)

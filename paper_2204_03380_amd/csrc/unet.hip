@@ -11,6 +11,7 @@
 // B[8 (l / 16) + e][l % 16]; the 4 results of lane l are D[4 (l / 16) + e][l % 16].
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 
@@ -157,6 +158,149 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a)
                 if (a.r) a.r[o] = f2bf(val);
                 if (a.out) a.out[o] = f2bf(a.skip ? val + bf2f(a.skip[o]) : val);
             }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Forward convolution with the input staged in LDS (layers of at most 32
+// input and 32 output channels on grids that give enough workgroups: the
+// full-resolution level).  A workgroup of four
+// wavefronts owns an x-segment of 64 voxels of four consecutive y rows (one
+// row per wavefront) and marches z over lz planes.  The input planes z - 1,
+// z, z + 1 of the segment's halo (6 rows of 66 voxels, all channels) sit in
+// a three-plane LDS ring, so every activation fragment of the 27 taps is
+// read from LDS instead of L1/L2.  The next plane is fetched into registers
+// while the current one is computed, then written to the ring slot that the
+// previous plane left.  Each output element is the same MFMA sequence as in
+// conv_fwd_kernel (same K order, same fragments), so results are equal bit
+// for bit.
+// ---------------------------------------------------------------------------
+constexpr int kLdsX = 64, kLdsY = 4;
+
+template <int CIN>
+struct LdsTile {
+    static constexpr int XW = kLdsX + 2, YW = kLdsY + 2;
+    static constexpr int PLANE = YW * XW * CIN;       // bf16 elements per plane
+    static constexpr int VPR = CIN / 8;               // 16-byte vectors per voxel
+    static constexpr int NV = YW * XW * VPR;          // vectors per plane
+    static constexpr int PER = (NV + 255) / 256;      // vectors per thread
+};
+
+// Plane z of the halo tile into registers (zeros outside the grid).
+template <int CIN>
+__device__ __forceinline__ void lds_fetch(const ConvArgs &a, uint4 (&v)[LdsTile<CIN>::PER], int64_t nbase, int z,
+                                          int y0, int x0)
+{
+    using T = LdsTile<CIN>;
+    const bool zin = (unsigned)z < (unsigned)a.d;
+#pragma unroll
+    for (int k = 0; k < T::PER; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        const int c8 = i % T::VPR, vox = i / T::VPR;
+        const int xx = vox % T::XW, yy = vox / T::XW;
+        const int gx = x0 - 1 + xx, gy = y0 - 1 + yy;
+        v[k] = uint4{0u, 0u, 0u, 0u};
+        if (i < T::NV && zin && (unsigned)gx < (unsigned)a.w && (unsigned)gy < (unsigned)a.h)
+            v[k] = *reinterpret_cast<const uint4 *>(a.x + (((nbase + z) * a.h + gy) * a.w + gx) * CIN + c8 * 8);
+    }
+}
+
+template <int CIN>
+__device__ __forceinline__ void lds_store(uint16_t *dst, const uint4 (&v)[LdsTile<CIN>::PER])
+{
+    using T = LdsTile<CIN>;
+#pragma unroll
+    for (int k = 0; k < T::PER; ++k) {
+        const int i = threadIdx.x + 256 * k;
+        if (i < T::NV) *reinterpret_cast<uint4 *>(dst + (int64_t)(i / T::VPR) * CIN + (i % T::VPR) * 8) = v[k];
+    }
+}
+
+template <int CIN, int COUT>
+__global__ __launch_bounds__(256) void conv_fwd_lds_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z, int lz,
+                                                           int64_t ntiles)
+{
+    using T = LdsTile<CIN>;
+    constexpr int K = 27 * CIN;
+    constexpr int KP = (K + 31) / 32 * 32;  // chunks past tap 26 are zero, as in conv_fwd_kernel
+    constexpr int CB = COUT / 16;
+    __shared__ __attribute__((aligned(16))) uint16_t ring[3 * T::PLANE];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int r16 = lane & 15, g = lane >> 4;
+    int64_t b = xcd_block(blockIdx.x, a.nblocks);
+    if (b >= ntiles) return;  // whole workgroup, before any barrier (the grid is a multiple of 8)
+    const int tx = (int)(b % tiles_x);
+    b /= tiles_x;
+    const int ty = (int)(b % tiles_y);
+    b /= tiles_y;
+    const int tz = (int)(b % tiles_z);
+    const int64_t n = b / tiles_z;
+    const int x0 = tx * kLdsX, y0 = ty * kLdsY, z0 = tz * lz;
+    const int z1 = min(z0 + lz, a.d);
+    const int64_t nbase = n * a.d;               // first plane of this sample
+    const int yw = y0 + wave;                    // this wavefront's output row
+    const bool row_ok = yw < a.h;
+    const uint4 zero = {0u, 0u, 0u, 0u};
+
+    uint4 next[T::PER];
+    lds_fetch<CIN>(a, next, nbase, z0 - 1, y0, x0);
+    lds_store<CIN>(ring + ((z0 + 2) % 3) * T::PLANE, next);
+    lds_fetch<CIN>(a, next, nbase, z0, y0, x0);
+    lds_store<CIN>(ring + (z0 % 3) * T::PLANE, next);
+    lds_fetch<CIN>(a, next, nbase, z0 + 1, y0, x0);
+    for (int z = z0; z < z1; ++z) {
+        lds_store<CIN>(ring + ((z + 1) % 3) * T::PLANE, next);  // the slot plane z - 2 left
+        __syncthreads();
+        if (z + 1 < z1) lds_fetch<CIN>(a, next, nbase, z + 2, y0, x0);  // in flight during this plane
+        f32x4 acc[4][CB];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+        for (int kc = 0; kc < KP; kc += 32) {
+            const int kk = kc + 8 * g;
+            const int tap = kk / CIN;
+            const int ci0 = kk - tap * CIN;
+            const bool tv = tap < 27;
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const uint16_t *pl = ring + ((z + dz + 3) % 3) * T::PLANE + ((wave + 1 + dy) * T::XW + 1 + dx) * CIN + ci0;
+            uint4 A[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) A[rb] = tv ? *reinterpret_cast<const uint4 *>(pl + (rb * 16 + r16) * CIN) : zero;
+            uint4 B[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+                B[cb] = tv ? *reinterpret_cast<const uint4 *>(a.wt + (int64_t)(cb * 16 + r16) * K + kk) : zero;
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(A[rb], B[cb], acc[rb][cb]);
+        }
+        // Epilogue: lane holds voxels x0 + rb*16 + 4g + e of channel cb*16 + r16.
+        if (row_ok) {
+            const int64_t vrow = ((nbase + z) * a.h + yw) * (int64_t)a.w;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const int co = cb * 16 + r16;
+                const float bias = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int xo = x0 + rb * 16 + 4 * g + e;
+                        if (xo >= a.w) continue;
+                        const int64_t v = vrow + xo;
+                        float val = acc[rb][cb][e] + bias;
+                        if (a.relu) val = fmaxf(val, 0.f);
+                        if (a.y && co < a.ych) a.y[v * a.ych + co] = val;
+                        const int64_t o = v * COUT + co;
+                        if (a.r) a.r[o] = f2bf(val);
+                        if (a.out) a.out[o] = f2bf(a.skip ? val + bf2f(a.skip[o]) : val);
+                    }
+            }
+        }
+        __syncthreads();  // every wave is done with plane z - 1's slot before it is refilled
     }
 }
 
@@ -844,6 +988,11 @@ int check_desc(const unet_conv_desc_t *d)
 
 dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)((n + bs - 1) / bs)); }
 
+// LDS-staged forward convolution for the layers it covers (1: on), and the
+// workgroup counts that choose it.
+std::atomic<int> g_conv_lds{1};
+constexpr int64_t kLdsBlocks = 1024, kLdsMinBlocks = 512;
+
 // Grids of fewer wavefronts than the chip has SIMDs (the coarse levels)
 // split the output channels: four ways below a quarter of the SIMDs, two
 // ways above (each split re-reads the activations once more).
@@ -853,6 +1002,23 @@ template <int CI, int CO>
 void launch_fwd_t(const ConvArgs &a, hipStream_t st)
 {
     constexpr int CB = CO / 16, CBW4 = CB >= 4 ? CB / 4 : 1, CBW2 = CB >= 2 ? CB / 2 : 1;
+    if constexpr (CI <= 32 && CO <= 32) {
+        // z-chunks sized for about kLdsBlocks workgroups, 4 to 16 planes;
+        // grids that give fewer than kLdsMinBlocks take the direct kernel
+        const int tx = (a.w + kLdsX - 1) / kLdsX, ty = (a.h + kLdsY - 1) / kLdsY;
+        const int64_t nsamp = a.nvox / ((int64_t)a.d * a.h * a.w);
+        const int64_t cols = (int64_t)tx * ty * nsamp;
+        const int lz = (int)std::min<int64_t>(16, std::max<int64_t>(4, cols * a.d / kLdsBlocks));
+        const int tz = (a.d + lz - 1) / lz;
+        const int64_t tiles = cols * tz;
+        if (a.w >= kLdsX && tiles >= kLdsMinBlocks && g_conv_lds.load()) {
+            ConvArgs b = a;
+            b.nblocks = (tiles + kNumXcd - 1) / kNumXcd * kNumXcd;
+            hipLaunchKernelGGL((conv_fwd_lds_kernel<CI, CO>), dim3((unsigned)b.nblocks), dim3(256), 0, st, b, tx, ty,
+                               tz, lz, tiles);
+            return;
+        }
+    }
     const int64_t waves = (a.nvox + 63) / 64;
     if (CB > 1 && waves < kFwdSplitWaves / 4)
         hipLaunchKernelGGL((conv_fwd_kernel<CI, CO, CBW4>), dim3((unsigned)a.nblocks, CB / CBW4), dim3(256), 0, st, a);
@@ -1052,6 +1218,22 @@ int unet_conv3d_fwd(const unet_conv_desc_t *desc, const uint16_t *x, const uint1
     a.ych = y ? y_channels : 0;
     if (launch_fwd(desc->cin, desc->cout, a, (hipStream_t)stream)) return bad("unsupported channel pair");
     UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+int unet_set_conv_lds(int32_t lds)
+{
+    rtm::clear_error();
+    if (lds != 0 && lds != 1) return bad("lds must be 0 or 1");
+    g_conv_lds = lds;
+    return RTM_OK;
+}
+
+int unet_get_conv_lds(int32_t *lds)
+{
+    rtm::clear_error();
+    if (!lds) return bad("NULL output");
+    *lds = g_conv_lds.load();
     return RTM_OK;
 }
 

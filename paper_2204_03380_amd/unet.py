@@ -113,6 +113,18 @@ def mse(img, y, target, out, gy, channels, ws, want_loss=True):
     return loss.value if want_loss else None
 
 
+def set_conv_lds(on: bool) -> None:
+    """Forward and input-gradient convolutions of <= 32 input channels on
+    grids >= 64 voxels wide stage their input in LDS (default) or not."""
+    check(load().unet_set_conv_lds(1 if on else 0))
+
+
+def get_conv_lds() -> bool:
+    v = ctypes.c_int32(0)
+    check(load().unet_get_conv_lds(ctypes.byref(v)))
+    return bool(v.value)
+
+
 def adam(p, g, m, v, lr, b1, b2, eps, step):
     check(load().unet_adam(p.numel(), _ptr(p), _ptr(g), _ptr(m), _ptr(v), float(lr), float(b1), float(b2),
                            float(eps), int(step), _st()))

@@ -15,23 +15,30 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.timeout(600)
 def test_filter_gain_over_plain_image_on_held_out_geometry():
-    n, K, nt, G = 64, 8, 600, 60
+    """Two networks trained from different seeds (initial weights, sample
+    order, flips) on 56 geometries: each is switched on by four validation
+    geometries and gains at least 4% over the plain image on eight other
+    held-out geometries (single geometries range from 0.92 to 1.41 across
+    seeds, so the test set is the larger one).  The learning rate warms up
+    over two epochs, which makes the training leave its initial loss
+    plateau whatever the seed (without the warm-up, one seed stayed on it
+    through all 30 epochs: gain 1.03)."""
+    n, K, nt, G = 64, 8, 600, 68
     models = [synth.layered_salt_3d(n, n, n, 900 + i) for i in range(G)]
     data = X.build_dataset(models, 10.0, 16, 1e-3, synth.ricker(15.0, 1e-3, nt), K)
     assert len(data) == G * K
-    train_set, test_set = data.split(set(range(G - 4, G)))
-    net = UNet(seed=0)
-    hist = X.train(net, train_set, epochs=30, lr=3e-4, batch=4, lr_decay=0.97, log=print)
-    den = X.Denoiser(net)
-    res = den.validate(test_set)
-    print("held-out geometries:", res)
-    assert np.isfinite(hist).all() and hist[-1] < hist[0]
-    # training is deterministic (fixed-order reductions, seeded order and
-    # flips), but where it leaves its loss plateau depends on float32
-    # summation order: builds with the same arithmetic in another order have
-    # reached held-out gains from 1.03 to 1.09 here.  The bar asks for a
-    # clear gain over the plain image, above the fallback rule's 1.
-    assert res["gain"] > 1.02 and den.enabled
+    train_set, held = data.split(set(range(56, G)))
+    test_set, val_set = held.split(set(range(56, 60)))
+    for seed in (0, 1):
+        net = UNet(seed=seed)
+        hist = X.train(net, train_set, epochs=30, lr=1e-3, batch=4, seed=seed, lr_decay=0.95, warmup=2)
+        den = X.Denoiser(net)
+        val = den.validate(val_set)
+        res = X.evaluate(net, test_set)
+        print(f"seed {seed}: loss {hist[0]:.5f} -> {hist[-1]:.5f}; validation gain {val['gain']:.4f}, "
+              f"test gain {res['gain']:.4f} ({res['pairs']} pairs)")
+        assert np.isfinite(hist).all() and hist[-1] < hist[0]
+        assert den.enabled and res["gain"] > 1.04
     img, used = den(test_set.inputs[0])
     assert used and img.shape == test_set.inputs[0].shape and bool(torch.isfinite(img).all())
 

@@ -305,3 +305,41 @@ def test_layer_parity_at_training_size(name, ci, co, n):
     e_w, e_b = rel_l2(host(dw), ref_w), rel_l2(host(db), ref_b)
     print(f"{name} {ci}->{co} at {n}^3: fwd {e_f:.2e} dgrad {e_d:.2e} wgrad {e_w:.2e} bias {e_b:.2e}")
     assert max(e_f, e_d, e_w, e_b) < 1e-5
+
+
+# Channel pairs the LDS-staged kernel takes (<= 32 input and output
+# channels), as forward layers or as the flipped input-gradient convolutions.
+LDS_PAIRS = ((16, 16), (16, 32), (32, 16), (32, 32))
+
+
+@pytest.mark.parametrize("ci,co", LDS_PAIRS)
+def test_lds_staged_convolution_equals_direct(ci, co):
+    """On a ragged grid wide and large enough for the LDS-staged kernel
+    (partial x-segment, y-rows and z-chunk, two samples) its forward
+    convolution with the fused epilogue and its input gradient equal the
+    direct kernel bit for bit, and the forward matches the oracle."""
+    shape = (2, 67, 31, 131)
+    rng, x, wo, b = _operands(shape, ci, co, 77 + ci + co)
+    wf, wb = pack(wo)
+    skip = U.bf16(rng.standard_normal((x.shape[0], co)))
+    dy = U.bf16(rng.standard_normal((x.shape[0], co)))
+    outs = []
+    try:
+        for lds in (True, False):
+            N.set_conv_lds(lds)
+            y = torch.empty((x.shape[0], co), dtype=torch.float32, device=DEV)
+            r = torch.empty((x.shape[0], co), dtype=torch.bfloat16, device=DEV)
+            out = torch.empty_like(r)
+            N.conv3d_fwd(shape, ci, co, bf_tensor(x), wf, f32(b), True, skip=bf_tensor(skip), y=y, r=r, out=out)
+            dx = torch.empty((x.shape[0], ci), dtype=torch.float32, device=DEV)
+            N.conv3d_dgrad(shape, ci, co, bf_tensor(dy), wb, dx)
+            outs.append((y, r, out, dx))
+    finally:
+        N.set_conv_lds(True)
+    for a, c in zip(*outs):
+        assert torch.equal(a, c)
+    y0 = outs[0][0]
+    ref = np.maximum(from_cf([U.conv3d(xc, U.bf16(wo), b) for xc in to_cf(x, shape, ci)]), 0.0)
+    e = rel_l2(host(y0), ref)
+    print(f"LDS conv {ci}->{co} {shape}: equal to the direct kernel; forward vs oracle {e:.2e}")
+    assert e < 1e-5
