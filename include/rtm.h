@@ -170,8 +170,10 @@ int rtm_set_steps_per_launch(int op, int steps);
 int rtm_get_steps_per_launch(int op, int *steps);
 
 /* Launch shape of the 3-D kernels: vec floats per lane (x strips of
- * 64 * vec cells), ty in {4, 8} wavefronts per workgroup (rows in y), zseg
- * planes per tile (a multiple of 9).  Same rules as rtm_set_tuning. */
+ * 64 * vec cells), ty in {4, 8, 16} wavefronts per workgroup (rows in y),
+ * zseg planes per tile (a multiple of 9).  ty 16 (1024-thread workgroups)
+ * takes vec 1 or 2 for RTM_OP_MODEL and vec 1 for RTM_OP_RTM / RTM_OP_VJP.
+ * Same rules as rtm_set_tuning. */
 int rtm_set_tuning3d(int op, int vec, int ty, int zseg);
 int rtm_get_tuning3d(int op, int *vec, int *ty, int *zseg);
 

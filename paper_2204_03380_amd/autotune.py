@@ -27,7 +27,8 @@ from . import (RTM_F_SKIP_CHECK, RTM_OP_MODEL, RTM_OP_RTM, RTM_TUNE_EXACT, Batch
 DEFAULT_SHAPES = (tuple((3, v, 1, z) for v in (1, 2, 4) for z in (54, 108, 216)) +
                   tuple((2, v, 1, z) for v in (2, 4) for z in (36, 108)) +
                   tuple((1, v, x, z) for v in (1, 2, 4) for x in (1, 4) for z in (18, 36)))
-DEFAULT_SHAPES_3D = tuple((v, y, z) for v in (1, 2, 4) for y in (4, 8) for z in (18, 36))
+DEFAULT_SHAPES_3D = (tuple((v, y, z) for v in (1, 2, 4) for y in (4, 8) for z in (18, 36)) +
+                     tuple((v, 16, z) for v in (1, 2) for z in (18, 36)))
 
 
 def signature(grid: Grid, nshots: int) -> str:
@@ -45,9 +46,18 @@ def install(shape, op, ndim):
         rtm_set_steps_per_launch(op, steps)
 
 
+def reverse_capable(shape, ndim) -> bool:
+    """The fused 3-D reverse kernel takes 16-row workgroups at vec 1 only
+    (a lane's registers are capped at 128 there)."""
+    return not (ndim == 3 and shape[1] == 16 and shape[0] != 1)
+
+
 def _time_shape(shape, grid, v_pad, wavelet, srcs, rec, dt, nt_probe, reps):
+    """(forward, reverse) us per step; reverse is inf for a shape only the
+    forward kernels take (the reverse then runs at vec 1, untimed)."""
+    rev_ok = reverse_capable(shape, grid.ndim)
     install(shape, RTM_OP_MODEL, grid.ndim)
-    install(shape, RTM_OP_RTM, grid.ndim)
+    install(shape if rev_ok else (1, *shape[1:]), RTM_OP_RTM, grid.ndim)
     dev = v_pad.device
     w = wavelet[:nt_probe].contiguous()
     nrec = len(rec)
@@ -70,7 +80,7 @@ def _time_shape(shape, grid, v_pad, wavelet, srcs, rec, dt, nt_probe, reps):
     t = rtm_timing_read()
     steps = reps * nt_probe
     fwd = t["model_forward"][0] * 1e3 / steps   # us per time step
-    rev = t["reverse_image"][0] * 1e3 / steps
+    rev = t["reverse_image"][0] * 1e3 / steps if rev_ok else float("inf")
     mp.free()
     rp.free()
     return fwd, rev

@@ -481,15 +481,14 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
         const int nys = T.ndim == 3 ? (g.NY + ty - 1) / ty : 1;
         const int nzs = (NZr + T.tune.zseg - 1) / T.tune.zseg;
         const int tbase = T.count();
-        // 2-D tiles are numbered row band by row band, so that workgroups on
-        // adjacent strips run back to back on one XCD and share the strip-end
-        // lines in its L2 (measured 3-7 % faster than strip by strip).
-        const bool rowmajor = T.ndim == 2;
-        const int n_outer = rowmajor ? nzs : ns, n_inner = rowmajor ? ns : nzs;
-        for (int oi = 0; oi < n_outer; ++oi)
-            for (int ys = 0; ys < nys; ++ys)
-                for (int ii = 0; ii < n_inner; ++ii) {
-                    const int xs = rowmajor ? ii : oi, zs = rowmajor ? oi : ii;
+        // Tiles are numbered band by band in z, strip by strip within a band
+        // and (3-D) y tile by y tile within a strip, so that the workgroups
+        // that share lines run back to back on one XCD: adjacent 2-D strips
+        // share their strip-end columns (measured 3-7 % faster than strip by
+        // strip), adjacent 3-D y tiles the 4-row halos above and below.
+        for (int zs = 0; zs < nzs; ++zs)
+            for (int xs = 0; xs < ns; ++xs)
+                for (int ys = 0; ys < nys; ++ys) {
                     const int z0 = zs * T.tune.zseg, z1 = std::min(z0 + T.tune.zseg, NZr);
                     if (T.ndim == 3) {
                         Tile3D t{};
@@ -508,9 +507,9 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
                         T.tiles.push_back(t);
                     }
                 }
+        // (2-D multi-step: x is an owned column)
         auto tile_of = [&](int z, int y, int x) {
-            if (rowmajor) return tbase + (z / T.tune.zseg) * ns + x / strip;  // (multi-step: owned columns)
-            return tbase + ((x / strip) * nys + (T.ndim == 3 ? y / ty : 0)) * nzs + z / T.tune.zseg;
+            return tbase + ((z / T.tune.zseg) * ns + x / strip) * nys + (T.ndim == 3 ? y / ty : 0);
         };
         PointOp sp;
         if (!make_point(g, S.src, &sp))
@@ -1394,7 +1393,11 @@ int rtm_get_tuning2d(int op, int *vec, int *tx, int *zseg)
 int rtm_set_tuning3d(int op, int vec, int ty, int zseg)
 {
     if (vec != 1 && vec != 2 && vec != 4) return fail(RTM_EINVAL, "vec must be 1, 2 or 4");
-    if (ty != 4 && ty != 8) return fail(RTM_EINVAL, "ty must be 4 or 8");
+    if (ty != 4 && ty != 8 && ty != 16) return fail(RTM_EINVAL, "ty must be 4, 8 or 16");
+    // 16-row workgroups (1024 threads, at most 128 registers a lane): the
+    // forward update at vec 1 or 2, the fused reverse at vec 1 only.
+    if (ty == 16 && (vec > 2 || (op != RTM_OP_MODEL && vec != 1)))
+        return fail(RTM_EINVAL, "ty 16 needs vec 1 (reverse) or vec <= 2 (forward)");
     if (zseg < kMinZseg || zseg > 4095 || zseg % kZUnroll != 0)
         return fail(RTM_EINVAL, "zseg must be a multiple of %d in [%d, 4095]", kZUnroll, kMinZseg);
     int packed = (vec << 24) | (ty << 16) | zseg;

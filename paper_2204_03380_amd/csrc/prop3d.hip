@@ -429,6 +429,12 @@ hipError_t launch_fwd3d(int vec, int ty, const ShotDev *shots, const Tile3D *til
         case 4: RTM_F3(4, 8); break;
         default: return hipErrorInvalidValue;
         }
+    } else if (ty == 16) {
+        switch (vec) {
+        case 1: RTM_F3(1, 16); break;
+        case 2: RTM_F3(2, 16); break;
+        default: return hipErrorInvalidValue;
+        }
     } else {
         return hipErrorInvalidValue;
     }
@@ -453,6 +459,8 @@ hipError_t launch_rev3d(int vec, int ty, bool grad, const ShotDev *shots, const 
         if (grad) { RTM_R3V(4, true) } else { RTM_R3V(4, false) }
     } else if (ty == 8) {
         if (grad) { RTM_R3V(8, true) } else { RTM_R3V(8, false) }
+    } else if (ty == 16 && vec == 1) {
+        if (grad) { RTM_R3(1, 16, true); } else { RTM_R3(1, 16, false); }
     } else {
         return hipErrorInvalidValue;
     }
@@ -483,6 +491,12 @@ hipError_t launch_recv3d(int vec, int ty, const ShotDev *shots, const Tile3D *ti
         RTM_RC3V(4)
     } else if (ty == 8) {
         RTM_RC3V(8)
+    } else if (ty == 16) {
+        switch (vec) {
+        case 1: RTM_RC3(1, 16); break;
+        case 2: RTM_RC3(2, 16); break;
+        default: return hipErrorInvalidValue;
+        }
     } else {
         return hipErrorInvalidValue;
     }

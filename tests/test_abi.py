@@ -73,6 +73,25 @@ def test_set_tuning_validation():
     rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 18)
 
 
+def test_set_tuning3d_validation():
+    old_f, old_r = rtm.rtm_get_tuning3d(rtm.RTM_OP_MODEL), rtm.rtm_get_tuning3d(rtm.RTM_OP_RTM)
+    try:
+        for op, vec, ty, zseg in ((rtm.RTM_OP_MODEL, 1, 2, 18),     # ty must be 4, 8 or 16
+                                  (rtm.RTM_OP_MODEL, 4, 16, 18),    # 16 rows: vec <= 2
+                                  (rtm.RTM_OP_RTM, 2, 16, 18),      # 16 rows, reverse: vec 1
+                                  (rtm.RTM_OP_VJP, 2, 16, 18),
+                                  (rtm.RTM_OP_RTM, 1, 16, 10)):     # zseg not a multiple of 9
+            with pytest.raises(rtm.RtmError):
+                rtm.rtm_set_tuning3d(op, vec, ty, zseg)
+        rtm.rtm_set_tuning3d(rtm.RTM_OP_MODEL, 2, 16, 27)
+        rtm.rtm_set_tuning3d(rtm.RTM_OP_RTM, 1, 16, 18)
+        assert rtm.rtm_get_tuning3d(rtm.RTM_OP_MODEL) == (2, 16, 27)
+        assert rtm.rtm_get_tuning3d(rtm.RTM_OP_RTM) == (1, 16, 18)
+    finally:
+        rtm.rtm_set_tuning3d(rtm.RTM_OP_MODEL, *old_f)
+        rtm.rtm_set_tuning3d(rtm.RTM_OP_RTM, *old_r)
+
+
 def _call_model(grid, nt=10, src=(5.0, 0.0, 3.0), rec=((1.0, 0.0, 2.0),), ws_bytes=None, ws=0x100000,
                 nrec=None, traces=0x3000):
     """Call rtm_model_shot with fake (never dereferenced) device addresses:

@@ -100,9 +100,11 @@ def test_launch_shape_invariance_3d():
     outs = []
     rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
     try:
-        for vec, ty, zseg in ((1, 4, 9), (2, 8, 18), (4, 8, 36), (2, 4, 27), (1, 8, 9)):
-            rtm.rtm_set_tuning3d(rtm.RTM_OP_MODEL, vec, ty, zseg)
-            rtm.rtm_set_tuning3d(rtm.RTM_OP_RTM, vec, ty, zseg)
+        # (forward shape, reverse shape); 16-row workgroups at vec 1 and 2
+        for fs, rs in (((1, 4, 9),) * 2, ((2, 8, 18),) * 2, ((4, 8, 36),) * 2, ((2, 4, 27),) * 2,
+                       ((1, 8, 9),) * 2, ((1, 16, 9),) * 2, ((2, 16, 18), (1, 16, 27))):
+            rtm.rtm_set_tuning3d(rtm.RTM_OP_MODEL, *fs)
+            rtm.rtm_set_tuning3d(rtm.RTM_OP_RTM, *rs)
             tr = _n(rtm.rtm_model_shot(g, vg, dt, w, src, rec))
             im = _n(rtm.rtm_rtm_shot(g, vg, dt, w, src, rec, d)["image"])
             outs.append((tr, im))
@@ -111,6 +113,33 @@ def test_launch_shape_invariance_3d():
     for tr, im in outs[1:]:
         assert np.array_equal(tr, outs[0][0]) and np.array_equal(im, outs[0][1])
 
+
+
+def test_sixteen_row_workgroups_vjp_and_storage():
+    """The gradient kernel and the storage receiver pass with 16-row
+    workgroups (forward update at vec 2, reverse at vec 1) give the same
+    bits as with 8-row ones, on a grid whose 33 padded rows leave a
+    one-row y tile."""
+    v, nb, src, rec, h, dt, nt = _small3d((20, 21, 75), nt=90)
+    g, vg, vo = _setup(v, nb)
+    w = _t(synth.ricker(25.0, dt, nt))
+    d = rtm.rtm_model_shot(g, vg, dt, w, src, rec)
+    gt = _t(np.random.default_rng(2).standard_normal(tuple(d.shape)).astype(np.float32))
+    outs = []
+    rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
+    try:
+        for fs, rs in (((2, 8, 18), (1, 8, 18)), ((2, 16, 18), (1, 16, 18)), ((1, 16, 27), (1, 16, 9))):
+            rtm.rtm_set_tuning3d(rtm.RTM_OP_MODEL, *fs)
+            rtm.rtm_set_tuning3d(rtm.RTM_OP_RTM, *rs)
+            gv, gw = rtm.rtm_model_shot_vjp(g, vg, dt, w, src, rec, gt, want_wavelet_grad=True)
+            st = rtm.rtm_storage_shot(g, vg, dt, w, src, rec, d, 4, 1, want_numden=True)
+            outs.append([_n(gv), _n(gw), _n(st["num"]), _n(st["den"]), _n(st["snapshots"])])
+    finally:
+        rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 0, 0)
+    assert np.any(outs[0][0]) and np.any(outs[0][2])
+    for o in outs[1:]:
+        for a, b in zip(o, outs[0]):
+            assert np.array_equal(a, b)
 
 @pytest.mark.timeout(600)
 def test_layered_salt_full_grid_reduced_nt():
