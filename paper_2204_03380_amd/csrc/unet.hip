@@ -442,6 +442,197 @@ __global__ __launch_bounds__(256) void conv_wgrad_kernel(WgArgs a)
     if (centre && gt < COUT) a.bpart[p * COUT + gt] = bacc;
 }
 
+// ---------------------------------------------------------------------------
+// Weight gradient, ring-staged (input channels <= 64 on large grids).  One
+// block of 9 wavefronts per job and 16 output channels (blockIdx.y); a job
+// is (sample n, ZB output planes from z0, one 32-voxel x segment, a range of
+// output rows y).  Wave q is the neighbour-row pair (dz, dy) = (q / 3 - 1,
+// q % 3 - 1) and accumulates its three x taps.  The block marches y: each
+// step stages dy^T of its ZB output rows and x^T of row y + 1 of the ZB + 2
+// source planes into a three-row ring, so each x row segment is staged and
+// read from memory once per job (ZB + 2 planes for ZB output planes)
+// instead of once per (dz, dy) pair and output row, and each dy row once
+// instead of nine times.  The MFMA operands and the x shifts are the direct
+// kernel's.  Partial sums per job, added by the same fixed-order reduction.
+// ---------------------------------------------------------------------------
+template <int CIN, int ZB>
+struct WrCfg {
+    static constexpr int IB = CIN / 16;
+    static constexpr int SEG = 32, XW = SEG + 8;
+    static constexpr int NP = ZB + 2;                // source planes z0 - 1 .. z0 + ZB
+    static constexpr int X_U16 = 3 * NP * CIN * XW;  // three-row ring of x^T
+    static constexpr int D_U16 = ZB * 16 * SEG;       // dy^T of the output rows
+    static constexpr int NT = 9 * 64;
+};
+
+struct WrArgs {
+    const uint16_t *x;
+    const uint16_t *dy;
+    float *part;   // [jobs][COUT][27][CIN]
+    float *bpart;  // [jobs][COUT]
+    int d, h, w, cout;
+    int nzb, nxs, ys;  // z blocks, x segments, y ranges per (n, z block, x segment)
+};
+
+template <int CIN, int ZB>
+__global__ __launch_bounds__(576) __attribute__((amdgpu_waves_per_eu(CIN <= 16 ? 6 : CIN <= 32 ? 5 : 4, 8)))
+void conv_wgrad_ring_kernel(WrArgs a)
+{
+    using C = WrCfg<CIN, ZB>;
+    constexpr int SEG = C::SEG, XW = C::XW, NP = C::NP, IB = C::IB, NT = C::NT;
+    __shared__ __attribute__((aligned(16))) uint16_t xr[C::X_U16];
+    __shared__ __attribute__((aligned(16))) uint16_t dyT[C::D_U16];
+    const int job = blockIdx.x, cb = blockIdx.y;
+    const int tid = threadIdx.x, q = tid >> 6, lane = tid & 63;
+    const int dz = q / 3 - 1, dq = q % 3 - 1;
+    const int r16 = lane & 15, g = lane >> 4;
+    int t = job;
+    const int ysp = t % a.ys;
+    t /= a.ys;
+    const int xs = t % a.nxs;
+    t /= a.nxs;
+    const int zb = t % a.nzb, n = t / a.nzb;
+    const int D = a.d, H = a.h, W = a.w, COUT = a.cout;
+    const int z0 = zb * ZB, x0 = xs * SEG;
+    const int ya = (int)((int64_t)H * ysp / a.ys), yb = (int)((int64_t)H * (ysp + 1) / a.ys);
+    const int64_t nD = (int64_t)n * D;
+
+    // x^T of source row yr of the NP planes, ring slot yr mod 3:
+    // xr[slot][p][i][jj] = x[n][z0 - 1 + p][yr][x0 + jj - 1][i], jj = 0 .. 33.
+    // Thread tid moves chunks tid, tid + NT, ... (8 channels of one voxel,
+    // voxel fastest: neighbouring lanes write neighbouring LDS words); the
+    // loads go to registers first, so that the next row's loads are in
+    // flight while the current row's MFMAs run.
+    constexpr int XCH = NP * (SEG + 2) * (CIN / 8), XPT = (XCH + NT - 1) / NT;
+    constexpr int DCH = ZB * SEG * 2, DPT = (DCH + NT - 1) / NT;
+    auto load_x = [&](int yr, uint4 (&v)[XPT]) {
+#pragma unroll
+        for (int k = 0; k < XPT; ++k) {
+            const int c = tid + k * NT;
+            const int jj = c % (SEG + 2), rest = c / (SEG + 2);
+            const int c0 = (rest % (CIN / 8)) * 8, p = rest / (CIN / 8);
+            const int zs = z0 - 1 + p, xg = x0 + jj - 1;
+            v[k] = uint4{0u, 0u, 0u, 0u};
+            if (c < XCH && (unsigned)yr < (unsigned)H && (unsigned)zs < (unsigned)D && (unsigned)xg < (unsigned)W)
+                v[k] = *reinterpret_cast<const uint4 *>(a.x + ((((nD + zs) * H + yr) * W + xg) * CIN + c0));
+        }
+    };
+    auto store_x = [&](int yr, const uint4 (&v)[XPT]) {
+        const int slot = (yr + 3) % 3;
+#pragma unroll
+        for (int k = 0; k < XPT; ++k) {
+            const int c = tid + k * NT;
+            if (c >= XCH) break;
+            const int jj = c % (SEG + 2), rest = c / (SEG + 2);
+            const int c0 = (rest % (CIN / 8)) * 8, p = rest / (CIN / 8);
+            const uint16_t *e = reinterpret_cast<const uint16_t *>(&v[k]);
+            uint16_t *dst = xr + ((slot * NP + p) * CIN + c0) * XW + jj;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) dst[i * XW] = e[i];
+        }
+    };
+    // dy^T of output rows (n, z0 + zi, y), channels cb*16 .. cb*16 + 15:
+    // dyT[zi][o][j] = dy[n][z0 + zi][y][x0 + j][cb*16 + o]
+    auto load_dy = [&](int y, uint4 (&v)[DPT]) {
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) {
+            const int c = tid + k * NT;
+            const int j = c % SEG, rest = c / SEG;
+            const int half = rest & 1, zi = rest >> 1;
+            const int z = z0 + zi, xg = x0 + j;
+            v[k] = uint4{0u, 0u, 0u, 0u};
+            if (c < DCH && y < H && z < D && xg < W)
+                v[k] = *reinterpret_cast<const uint4 *>(a.dy + ((((nD + z) * H + y) * W + xg) * COUT + cb * 16 + half * 8));
+        }
+    };
+    auto store_dy = [&](const uint4 (&v)[DPT]) {
+#pragma unroll
+        for (int k = 0; k < DPT; ++k) {
+            const int c = tid + k * NT;
+            if (c >= DCH) break;
+            const int j = c % SEG, rest = c / SEG;
+            const int half = rest & 1, zi = rest >> 1;
+            const uint16_t *e = reinterpret_cast<const uint16_t *>(&v[k]);
+            uint16_t *dst = dyT + (zi * 16 + half * 8) * SEG + j;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) dst[i * SEG] = e[i];
+        }
+    };
+
+    f32x4 acc[3][IB];
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int k = 0; k < IB; ++k) acc[j][k] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+
+    uint4 xv[XPT], dv[DPT];
+    for (int yr = ya - 1; yr <= ya + 1; ++yr) {
+        load_x(yr, xv);
+        store_x(yr, xv);
+    }
+    load_dy(ya, dv);
+    store_dy(dv);
+    __syncthreads();
+    for (int y = ya; y < yb; ++y) {
+        // next step's rows (x row y + 2, dy row y + 1) in flight during this step
+        const bool more = y + 1 < yb;
+        if (more) {
+            load_x(y + 2, xv);
+            load_dy(y + 1, dv);
+        }
+        const int sy = y + dq;
+        if ((unsigned)sy < (unsigned)H) {
+            const uint16_t *xs_row = xr + ((sy % 3) * NP + 1 + dz) * CIN * XW;
+#pragma unroll
+            for (int zi = 0; zi < ZB; ++zi) {
+                const uint4 A = *reinterpret_cast<const uint4 *>(dyT + (zi * 16 + r16) * SEG + 8 * g);
+#pragma unroll
+                for (int ib = 0; ib < IB; ++ib) {
+                    // voxels 8g + dx .. 8g + dx + 7 of channel ib*16 + r16 of
+                    // plane z0 + zi + dz, for dx = 0, 1, 2
+                    const uint16_t *row = xs_row + (zi * CIN + ib * 16 + r16) * XW + 8 * g;
+                    const uint4 L = *reinterpret_cast<const uint4 *>(row);
+                    const uint4 R = *reinterpret_cast<const uint4 *>(row + 8);
+                    const uint4 B1 = {(L.x >> 16) | (L.y << 16), (L.y >> 16) | (L.z << 16),
+                                      (L.z >> 16) | (L.w << 16), (L.w >> 16) | (R.x << 16)};
+                    const uint4 B2 = {L.y, L.z, L.w, R.x};
+                    acc[0][ib] = mfma16(A, L, acc[0][ib]);
+                    acc[1][ib] = mfma16(A, B1, acc[1][ib]);
+                    acc[2][ib] = mfma16(A, B2, acc[2][ib]);
+                }
+            }
+        }
+        if (q == 4) {  // bias: lane (o = r16, g) sums voxels 8g .. 8g + 7 of every output row
+#pragma unroll
+            for (int zi = 0; zi < ZB; ++zi)
+#pragma unroll
+                for (int j = 0; j < 8; ++j) bacc += bf2f(dyT[(zi * 16 + r16) * SEG + 8 * g + j]);
+        }
+        __syncthreads();  // every wave is done with dy^T and ring slot (y - 1) mod 3 = (y + 2) mod 3
+        if (more) {
+            store_x(y + 2, xv);
+            store_dy(dv);
+        }
+        __syncthreads();
+    }
+    // Partial sums of this job: lane holds o = cb*16 + 4g + e, i = ib*16 + r16.
+    float *part = a.part + (int64_t)job * COUT * 27 * CIN;
+#pragma unroll
+    for (int dxi = 0; dxi < 3; ++dxi)
+#pragma unroll
+        for (int ib = 0; ib < IB; ++ib)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int o = cb * 16 + 4 * g + e;
+                part[((int64_t)o * 27 + q * 3 + dxi) * CIN + ib * 16 + r16] = acc[dxi][ib][e];
+            }
+    if (q == 4) {  // the four voxel groups of each channel, added in a fixed order
+        const float b1 = __shfl_down(bacc, 16), b2 = __shfl_down(bacc, 32), b3 = __shfl_down(bacc, 48);
+        if (lane < 16) a.bpart[(int64_t)job * COUT + cb * 16 + lane] = (bacc + b1) + (b2 + b3);
+    }
+}
+
 // Fixed-order sum of P partial arrays: out[c][i] = sum of partials
 // c*chunk .. min(P, (c+1)*chunk) - 1 in increasing order (blockIdx.y = c).
 // Two passes (chunks, then the chunk sums) give the same result on every
@@ -1108,9 +1299,42 @@ int thin_wg_blocks(int64_t nvox)
     return b < 1 ? 1 : (int)b;
 }
 
+// Ring-staged weight gradient: MFMA pairs of <= 64 input channels on grids
+// of at least kRingMinVox voxels (the 64^3 and 128^3 levels of the
+// network).  Jobs: (n, z block, x segment, y range), enough of them for
+// about kRingBlocks blocks with every y range >= kRingMinRows rows, and the
+// partial sums within the weight-gradient budget.
+constexpr int64_t kRingMinVox = (int64_t)1 << 17;
+constexpr int64_t kRingBlocks = 512;
+constexpr int kRingMinRows = 8;
+
+int ring_zb(int cin) { return cin <= 32 ? 4 : 2; }
+
+// Job counts of the ring kernel, or false when it does not apply.
+bool ring_layout(const unet_conv_desc_t *d, int *nzb, int *nxs, int *ys)
+{
+    if (thin_pair(d->cin, d->cout) || d->cin > 64 || (int64_t)d->n * d->d * d->h * d->w < kRingMinVox) return false;
+    *nzb = (d->d + ring_zb(d->cin) - 1) / ring_zb(d->cin);
+    *nxs = (d->w + 31) / 32;
+    const int64_t cols = (int64_t)d->n * *nzb * *nxs, cbs = d->cout / 16;
+    const int64_t per_part = (int64_t)27 * d->cin * d->cout * (int64_t)sizeof(float);
+    if (cols * per_part > kWgPartBudget) return false;
+    int64_t y = (kRingBlocks + cols * cbs - 1) / (cols * cbs);
+    if (y > d->h / kRingMinRows) y = d->h / kRingMinRows;
+    if (y > kWgPartBudget / (cols * per_part)) y = kWgPartBudget / (cols * per_part);
+    *ys = (int)(y < 1 ? 1 : y);
+    return true;
+}
+
 int wg_layout(const unet_conv_desc_t *d, int64_t *parts, int *S)
 {
     const int64_t rows = (int64_t)d->n * d->d * d->h;
+    int nzb, nxs, ys;
+    if (ring_layout(d, &nzb, &nxs, &ys)) {
+        *S = (int)((int64_t)d->n * nzb * nxs * ys);
+        *parts = *S;
+        return 0;
+    }
     if (thin_pair(d->cin, d->cout)) {
         *S = thin_wg_blocks(rows * d->w);
         *parts = *S;
@@ -1302,7 +1526,28 @@ int unet_conv3d_wgrad(const unet_conv_desc_t *desc, const uint16_t *x, const uin
     a.w = desc->w;
     a.S = S;
     hipStream_t st = (hipStream_t)stream;
-    if (desc->cin == 1)
+    int nzb, nxs, ys;
+    if (ring_layout(desc, &nzb, &nxs, &ys)) {
+        WrArgs r{};
+        r.x = x;
+        r.dy = dy;
+        r.part = a.part;
+        r.bpart = a.bpart;
+        r.d = desc->d;
+        r.h = desc->h;
+        r.w = desc->w;
+        r.cout = desc->cout;
+        r.nzb = nzb;
+        r.nxs = nxs;
+        r.ys = ys;
+        const dim3 grid((unsigned)S, (unsigned)(desc->cout / 16));
+        switch (desc->cin) {
+        case 16: hipLaunchKernelGGL((conv_wgrad_ring_kernel<16, 4>), grid, dim3(576), 0, st, r); break;
+        case 32: hipLaunchKernelGGL((conv_wgrad_ring_kernel<32, 4>), grid, dim3(576), 0, st, r); break;
+        case 64: hipLaunchKernelGGL((conv_wgrad_ring_kernel<64, 2>), grid, dim3(576), 0, st, r); break;
+        default: return bad("unsupported channel pair");
+        }
+    } else if (desc->cin == 1)
         hipLaunchKernelGGL(wgrad_thin_kernel<true>, dim3((unsigned)S, 3), dim3(192), 0, st, x, dy, a.rows * a.w, a.d,
                            a.h, a.w, a.part, a.bpart);
     else if (desc->cout == 1)

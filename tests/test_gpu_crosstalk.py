@@ -15,21 +15,24 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.timeout(600)
 def test_filter_gain_over_plain_image_on_held_out_geometry():
-    """Two networks trained from different seeds (initial weights, sample
-    order, flips) on 56 geometries: each is switched on by four validation
-    geometries and gains at least 4% over the plain image on eight other
-    held-out geometries (single geometries range from 0.92 to 1.41 across
-    seeds, so the test set is the larger one).  The learning rate warms up
-    over two epochs, which makes the training leave its initial loss
-    plateau whatever the seed (without the warm-up, one seed stayed on it
-    through all 30 epochs: gain 1.03)."""
+    """Three networks trained from different seeds (initial weights, sample
+    order, flips) on 56 geometries.  Each is switched on by four validation
+    geometries and does better than the plain image on eight other held-out
+    geometries; the one the validation split prefers gains at least 8% on
+    them.  Training either leaves its initial loss plateau (loss 0.007 ->
+    0.004, test gains 1.08-1.21 in a 20-run study of seeds and schedules) or
+    stays on it through the 30 epochs (loss 0.0064, gains 1.05-1.06; a
+    quarter of the runs, which runs depending on float32 summation order),
+    and the validation gain tells the two apart, so model selection on the
+    validation split is what makes the result robust."""
     n, K, nt, G = 64, 8, 600, 68
     models = [synth.layered_salt_3d(n, n, n, 900 + i) for i in range(G)]
     data = X.build_dataset(models, 10.0, 16, 1e-3, synth.ricker(15.0, 1e-3, nt), K)
     assert len(data) == G * K
     train_set, held = data.split(set(range(56, G)))
     test_set, val_set = held.split(set(range(56, 60)))
-    for seed in (0, 1):
+    best = None
+    for seed in (0, 1, 2):
         net = UNet(seed=seed)
         hist = X.train(net, train_set, epochs=30, lr=1e-3, batch=4, seed=seed, lr_decay=0.95, warmup=2)
         den = X.Denoiser(net)
@@ -38,7 +41,12 @@ def test_filter_gain_over_plain_image_on_held_out_geometry():
         print(f"seed {seed}: loss {hist[0]:.5f} -> {hist[-1]:.5f}; validation gain {val['gain']:.4f}, "
               f"test gain {res['gain']:.4f} ({res['pairs']} pairs)")
         assert np.isfinite(hist).all() and hist[-1] < hist[0]
-        assert den.enabled and res["gain"] > 1.04
+        assert den.enabled and res["gain"] > 1.0
+        if best is None or val["gain"] > best[0]:
+            best = (val["gain"], res["gain"], den)
+    print(f"validation-selected network: test gain {best[1]:.4f}")
+    assert best[1] > 1.08
+    den = best[2]
     img, used = den(test_set.inputs[0])
     assert used and img.shape == test_set.inputs[0].shape and bool(torch.isfinite(img).all())
 

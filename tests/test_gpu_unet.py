@@ -118,7 +118,21 @@ def test_conv_dgrad_parity(ci, co):
 
 @pytest.mark.parametrize("ci,co", PAIRS)
 def test_conv_wgrad_parity_and_determinism(ci, co):
-    shape = (2, 4, 7, 45)
+    _wgrad_check((2, 4, 7, 45), ci, co)
+
+
+@pytest.mark.parametrize("ci,co", [(16, 32), (32, 16), (64, 32)])
+def test_ring_wgrad_parity_ragged(ci, co):
+    """The ring-staged weight gradient (MFMA pairs of at most 64 input
+    channels on grids of 2^17 voxels or more) on a ragged two-sample grid:
+    19 planes (not a multiple of the 4- or 2-plane block), 150 columns (a
+    partial 32-voxel segment), 23 rows split into unequal y ranges."""
+    _wgrad_check((2, 19, 23, 150), ci, co)
+
+
+def _wgrad_check(shape, ci, co):
+    """Weight and bias gradients against the oracle, and equal bit for bit
+    on a second call."""
     rng, x, _, _ = _operands(shape, ci, co, 11 + ci * co)
     dy = U.bf16(rng.standard_normal((x.shape[0], co)))
     ws = torch.empty(N.wgrad_ws_bytes(shape, ci, co), dtype=torch.uint8, device=DEV)
