@@ -249,13 +249,17 @@ PAPER_STORAGE_GB = {"Table 2": 2.638, "Table 4": 132.062}
 PAPER_STRIDE = 10
 
 
+PAPER_3D_SHAPES = tuple((v, y, z, o) for v, y, z in ((1, 4, 18), (1, 8, 18), (2, 8, 18), (1, 4, 36)) for o in (0, 1))
+
+
 def paper_shapes(nb=50, kinds=("modeling", "rtm", "storage")):
     """Device time of one shot on each paper grid (synthetic smooth velocity;
     runtime does not depend on the values) against the paper's times, at the
     paper's full nt.  Modeling and RTM with reconstruction run as a one-shot
     plan replayed as a hipGraph (tables built once, no launch gaps); RTM with
     storage through rtm_storage_shot, keeping every 10th level in device
-    memory."""
+    memory.  3-D grids first run the autotuner over PAPER_3D_SHAPES (36
+    steps per candidate) and record its choice."""
     import numpy as np
     import torch
 
@@ -298,6 +302,15 @@ def _paper_case(rtm, synth, np, torch, dev, gst, nb, kind, nx, ny, nz, nt_paper,
                                    np.arange(0, shape_int[1], 2, dtype=np.float64), 2.0)
     extra = {}
     plan = None
+    snap = None
+    if ndim == 3:
+        # 3-D: the autotuner picks shapes and tile order for this grid (the
+        # faster tile order depends on the grid)
+        from paper_2204_03380_amd import autotune
+        snap = rtm.tuning_snapshot()
+        res = autotune.tune_batch(g, vp, w, [src], rec, dt, nt_probe=36, reps=1, shapes=PAPER_3D_SHAPES)
+        extra["launch_shape"] = {"forward": list(res["forward"][:-1]), "reverse": list(res["reverse"][:-1]),
+                                 "fields": "vec, rows per workgroup, planes per tile, z-innermost tile order"}
     if kind == "modeling":
         tr = torch.empty((rec.shape[0], steps + 1), dtype=torch.float32, device=dev)
         plan = rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, vp, w, src, rec, traces_out=tr)], dt, steps,
@@ -338,6 +351,8 @@ def _paper_case(rtm, synth, np, torch, dev, gst, nb, kind, nx, ny, nz, nt_paper,
            "paper_seconds": paper,
            "speedup": {k: round(v_ / t_paper_nt, 1) for k, v_ in paper.items()}}
     row.update(extra)
+    if snap is not None:
+        rtm.tuning_restore(snap)
     print(json.dumps(row), file=sys.stderr, flush=True)
     if plan is not None:
         plan.free()

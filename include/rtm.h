@@ -177,6 +177,18 @@ int rtm_get_steps_per_launch(int op, int *steps);
 int rtm_set_tuning3d(int op, int vec, int ty, int zseg);
 int rtm_get_tuning3d(int op, int *vec, int *ty, int *zseg);
 
+/* Numbering of the 3-D tiles, process-wide per operation (RTM_OP_MODEL: the
+ * forward kernels; RTM_OP_RTM / RTM_OP_VJP: the reverse ones): z_inner 0
+ * (default) numbers them z band by z band with the y tiles innermost,
+ * z_inner 1 x strip by x strip with the z bands innermost.  Workgroups are
+ * dealt to the XCDs in that order, so it decides which tiles share an L2;
+ * results do not depend on it (every cell's arithmetic is the same).  The
+ * faster order depends on the grid (the autotuner tries both).
+ * rtm_set_tuning3d keeps it.  RTM_EINVAL for z_inner other than 0 or 1 or an
+ * unknown op. */
+int rtm_set_tile_order3d(int op, int z_inner);
+int rtm_get_tile_order3d(int op, int *z_inner);
+
 /* Bounded wait of RTM_F_PERSISTENT passes, process-wide: a workgroup that
  * waits longer than `ms` milliseconds for its shot's previous step gives
  * up, the pass ends and rtm_batch_run returns RTM_EHIP (default 4000 ms;

@@ -19,7 +19,7 @@ from ._lib import (RTM_F_ACCUMULATE, RTM_F_CHECK_FINITE, RTM_F_GRAPH, RTM_F_PERS
                    RTM_OP_RBC_PAD, RTM_OP_RTM, RTM_OP_STORAGE, RTM_OP_VJP, RTM_TUNE_EXACT, RtmError)
 
 __all__ = [
-    "Grid", "RtmError", "rtm_workspace_bytes", "rtm_set_tuning", "rtm_get_tuning", "rtm_set_tuning3d", "rtm_get_tuning3d", "rtm_timing_enable", "rtm_timing_read", "rtm_rbc_pad", "rtm_pad_adjoint",
+    "Grid", "RtmError", "rtm_workspace_bytes", "rtm_set_tuning", "rtm_get_tuning", "rtm_set_tuning3d", "rtm_get_tuning3d", "rtm_set_tile_order3d", "rtm_get_tile_order3d", "rtm_timing_enable", "rtm_timing_read", "rtm_rbc_pad", "rtm_pad_adjoint",
     "rtm_model_shot", "rtm_rtm_shot", "rtm_model_shot_vjp", "RTM_F_SKIP_CHECK", "RTM_F_NO_REINJECT",
     "rtm_nyquist_stride", "rtm_storage_count", "rtm_storage_shot", "RTM_OP_STORAGE",
     "RTM_OP_MODEL", "RTM_OP_RTM", "RTM_OP_VJP", "RTM_OP_RBC_PAD", "RTM_F_ACCUMULATE", "RTM_F_GRAPH", "RTM_F_CHECK_FINITE", "RTM_TUNE_EXACT", "RTM_F_PERSISTENT",
@@ -114,6 +114,17 @@ def rtm_get_tuning3d(op: int):
     return int(v.value), int(y.value), int(z.value)
 
 
+def rtm_set_tile_order3d(op: int, z_inner: int) -> None:
+    """3-D tile numbering: 0 y tiles innermost (default), 1 z bands innermost."""
+    _lib.check(_lib.load().rtm_set_tile_order3d(op, int(z_inner)))
+
+
+def rtm_get_tile_order3d(op: int) -> int:
+    z = ctypes.c_int()
+    _lib.check(_lib.load().rtm_get_tile_order3d(op, ctypes.byref(z)))
+    return z.value
+
+
 def rtm_set_tuning2d(op: int, vec: int, tx: int, zseg: int) -> None:
     _lib.check(_lib.load().rtm_set_tuning2d(op, vec, tx, zseg))
 
@@ -147,13 +158,14 @@ def rtm_get_tuning(op: int):
 
 
 def tuning_snapshot() -> dict:
-    """The process-wide launch settings (2-D and 3-D shapes, 2-D steps per
-    launch, the no-narrowing flag), for tuning_restore."""
+    """The process-wide launch settings (2-D and 3-D shapes, the 3-D tile
+    order, 2-D steps per launch, the no-narrowing flag), for tuning_restore."""
     snap = {"exact": rtm_get_tuning(RTM_TUNE_EXACT)[0]}
     for op in (RTM_OP_MODEL, RTM_OP_RTM):
         snap[("2d", op)] = rtm_get_tuning2d(op)
         snap[("steps", op)] = rtm_get_steps_per_launch(op)
         snap[("3d", op)] = rtm_get_tuning3d(op)
+        snap[("order3d", op)] = rtm_get_tile_order3d(op)
     return snap
 
 
@@ -164,6 +176,7 @@ def tuning_restore(snap: dict) -> None:
         rtm_set_tuning2d(op, *snap[("2d", op)])
         rtm_set_steps_per_launch(op, snap[("steps", op)])
         rtm_set_tuning3d(op, *snap[("3d", op)])
+        rtm_set_tile_order3d(op, snap[("order3d", op)])
 
 
 def rtm_set_persist_wait(ms: float) -> None:

@@ -28,7 +28,7 @@ RTM_F_NO_REINJECT = 0x2
 EXPORTS = (
     "rtm_abi_version", "rtm_last_error", "rtm_set_tuning", "rtm_get_tuning", "rtm_set_tuning2d",
     "rtm_get_tuning2d", "rtm_set_steps_per_launch", "rtm_get_steps_per_launch", "rtm_set_tuning3d",
-    "rtm_get_tuning3d", "rtm_timing_enable", "rtm_timing_read",
+    "rtm_get_tuning3d", "rtm_set_tile_order3d", "rtm_get_tile_order3d", "rtm_timing_enable", "rtm_timing_read",
     "rtm_workspace_bytes", "rtm_rbc_pad", "rtm_rbc_pad_ex", "rtm_pad_adjoint_ex",
     "rtm_pad_adjoint", "rtm_model_shot", "rtm_rtm_shot", "rtm_nyquist_stride", "rtm_storage_count",
     "rtm_storage_shot", "rtm_model_shot_vjp", "rtm_batch_plan", "rtm_batch_run",
@@ -102,6 +102,8 @@ def load():
         "rtm_get_steps_per_launch": ([ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rtm_set_tuning3d": ([ctypes.c_int] * 4, ctypes.c_int),
         "rtm_get_tuning3d": ([ctypes.c_int] + [ctypes.POINTER(ctypes.c_int)] * 3, ctypes.c_int),
+        "rtm_set_tile_order3d": ([ctypes.c_int, ctypes.c_int], ctypes.c_int),
+        "rtm_get_tile_order3d": ([ctypes.c_int, ctypes.POINTER(ctypes.c_int)], ctypes.c_int),
         "rtm_timing_enable": ([ctypes.c_int], ctypes.c_int),
         "rtm_timing_read": ([ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
         "rtm_workspace_bytes": ([G, ctypes.c_int, I32, I32, ctypes.POINTER(SZ)], ctypes.c_int),

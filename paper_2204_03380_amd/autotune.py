@@ -5,7 +5,8 @@ the fused reverse passes for each candidate launch configuration with the
 library's event timing, keeps the fastest per pass and installs it.  A 2-D
 candidate is (steps per launch, floats per lane `vec`, strips per workgroup
 `tx`, rows per tile `zseg`); a 3-D one is (vec, rows per workgroup `ty`,
-planes per tile `zseg`).  Candidates are compared by device time per time
+planes per tile `zseg`, tile order: 0 y tiles innermost, 1 z bands
+innermost).  Candidates are compared by device time per time
 step, so configurations that advance one, two or three steps per launch
 compete on equal terms.  Results do not depend on the configuration (every
 cell is computed by the same arithmetic), so tuning only changes speed.
@@ -20,15 +21,16 @@ from typing import Iterable, Sequence
 import torch
 
 from . import (RTM_F_SKIP_CHECK, RTM_OP_MODEL, RTM_OP_RTM, RTM_TUNE_EXACT, BatchPlan, BatchShot, Grid,
-               rtm_get_tuning, rtm_set_steps_per_launch, rtm_set_tuning, rtm_set_tuning2d, rtm_set_tuning3d,
-               rtm_timing_enable, rtm_timing_read)
+               rtm_get_tuning, rtm_set_steps_per_launch, rtm_set_tile_order3d, rtm_set_tuning, rtm_set_tuning2d,
+               rtm_set_tuning3d, rtm_timing_enable, rtm_timing_read)
 
 # (steps, vec, tx, zseg): the multi-step kernels take one strip per workgroup
 DEFAULT_SHAPES = (tuple((3, v, 1, z) for v in (1, 2, 4) for z in (54, 108, 216)) +
                   tuple((2, v, 1, z) for v in (2, 4) for z in (36, 108)) +
                   tuple((1, v, x, z) for v in (1, 2, 4) for x in (1, 4) for z in (18, 36)))
-DEFAULT_SHAPES_3D = (tuple((v, y, z) for v in (1, 2, 4) for y in (4, 8) for z in (18, 36)) +
-                     tuple((v, 16, z) for v in (1, 2) for z in (18, 36)))
+DEFAULT_SHAPES_3D = tuple((v, y, z, o) for v, y, z in ((1, 4, 18), (1, 8, 18), (2, 8, 18), (1, 4, 36), (2, 8, 36),
+                                                      (4, 8, 18), (1, 16, 18), (2, 16, 36))
+                          for o in (0, 1))
 
 
 def signature(grid: Grid, nshots: int) -> str:
@@ -37,9 +39,11 @@ def signature(grid: Grid, nshots: int) -> str:
 
 def install(shape, op, ndim):
     """Sets the launch configuration of `op`'s kernels: 2-D (steps, vec,
-    tx, zseg); 3-D (vec, ty, zseg)."""
+    tx, zseg); 3-D (vec, ty, zseg) or (vec, ty, zseg, z_inner tile order)."""
     if ndim == 3:
-        rtm_set_tuning3d(op, *shape)
+        rtm_set_tuning3d(op, *shape[:3])
+        if len(shape) > 3:
+            rtm_set_tile_order3d(op, shape[3])
     else:
         steps, vec, tx, zseg = shape
         rtm_set_tuning2d(op, vec, tx, zseg)

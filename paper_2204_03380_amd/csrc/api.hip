@@ -132,6 +132,7 @@ struct Tune {
     int ty;  // 3-D: wavefronts (y rows) per workgroup
     int tx;  // 2-D: wavefronts (adjacent strips) per workgroup
     int steps = 1;  // 2-D: time steps per launch (1, 2 or 3)
+    int zin = 0;    // 3-D: tiles numbered with z innermost (else y innermost)
 };
 
 // 2-D shapes: ((steps - 1) << 28) | (tx << 24) | (vec << 16) | zseg;
@@ -145,7 +146,7 @@ std::atomic<int> g_tune2d_rev{(2 << 28) | (1 << 24) | (2 << 16) | 108};
 std::atomic<int> g_tune_exact{0};  // 1: never narrow the configured shapes
 std::atomic<double> g_persist_wait_ms{4000.0};  // bounded wait of persistent passes
 
-// 3-D shapes: (vec << 24) | (ty << 16) | zseg; defaults from a sweep on
+// 3-D shapes: (vec << 24) | (ty << 16) | (z_inner << 15) | zseg; defaults from a sweep on
 // the 612 x 612 x 356 padded layered-salt grid (us per step: forward 556 at
 // vec 1, 4 rows, 18 planes against 575 at vec 2, 8 rows; reverse 1353).
 std::atomic<int> g_tune3d_fwd{(1 << 24) | (4 << 16) | 18};
@@ -155,7 +156,9 @@ Tune get_tune(int which, int ndim)
 {
     if (ndim == 3) {
         int v = (which == 0 ? g_tune3d_fwd : g_tune3d_rev).load();
-        return Tune{v >> 24, v & 0xffff, (v >> 16) & 0xff, 1};
+        Tune t{v >> 24, v & 0x7fff, (v >> 16) & 0xff, 1};
+        t.zin = (v >> 15) & 1;
+        return t;
     }
     int v = (which == 0 ? g_tune2d_fwd : g_tune2d_rev).load();
     return Tune{(v >> 16) & 0xff, v & 0xffff, 1, (v >> 24) & 0xf, ((v >> 28) & 0x3) + 1};
@@ -486,10 +489,16 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
         // and (3-D) y tile by y tile within a strip, so that the workgroups
         // that share lines run back to back on one XCD: adjacent 2-D strips
         // share their strip-end columns (measured 3-7 % faster than strip by
-        // strip), adjacent 3-D y tiles the 4-row halos above and below.
-        for (int zs = 0; zs < nzs; ++zs)
-            for (int xs = 0; xs < ns; ++xs)
-                for (int ys = 0; ys < nys; ++ys) {
+        // strip), adjacent 3-D y tiles the 4-row halos above and below.  A
+        // 3-D tuning may number them z innermost instead (x strip, then y
+        // tile, then z band), which some grids prefer (the better order
+        // depends on the grid: measured, not derived).
+        const bool zin = T.ndim == 3 && T.tune.zin;
+        const int nA = zin ? ns : nzs, nB = zin ? nys : ns, nC = zin ? nzs : nys;
+        for (int ia = 0; ia < nA; ++ia)
+            for (int ib = 0; ib < nB; ++ib)
+                for (int ic = 0; ic < nC; ++ic) {
+                    const int zs = zin ? ic : ia, xs = zin ? ia : ib, ys = zin ? ib : ic;
                     const int z0 = zs * T.tune.zseg, z1 = std::min(z0 + T.tune.zseg, NZr);
                     if (T.ndim == 3) {
                         Tile3D t{};
@@ -510,6 +519,7 @@ int build_tiling(Job &J, Tiling &T, bool with_receivers)
                 }
         // (2-D multi-step: x is an owned column)
         auto tile_of = [&](int z, int y, int x) {
+            if (zin) return tbase + ((x / strip) * nys + y / ty) * nzs + z / T.tune.zseg;
             return tbase + ((z / T.tune.zseg) * ns + x / strip) * nys + (T.ndim == 3 ? y / ty : 0);
         };
         PointOp sp;
@@ -1401,10 +1411,26 @@ int rtm_set_tuning3d(int op, int vec, int ty, int zseg)
         return fail(RTM_EINVAL, "ty 16 needs vec 1 (reverse) or vec <= 2 (forward)");
     if (zseg < kMinZseg || zseg > 4095 || zseg % kZUnroll != 0)
         return fail(RTM_EINVAL, "zseg must be a multiple of %d in [%d, 4095]", kZUnroll, kMinZseg);
-    int packed = (vec << 24) | (ty << 16) | zseg;
-    if (op == RTM_OP_MODEL) g_tune3d_fwd = packed;
-    else if (op == RTM_OP_RTM || op == RTM_OP_VJP) g_tune3d_rev = packed;
-    else return fail(RTM_EINVAL, "unknown op %d", op);
+    if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
+    std::atomic<int> &g = op == RTM_OP_MODEL ? g_tune3d_fwd : g_tune3d_rev;
+    g = (vec << 24) | (ty << 16) | (g.load() & (1 << 15)) | zseg;  // the tile order is kept
+    return RTM_OK;
+}
+
+int rtm_set_tile_order3d(int op, int z_inner)
+{
+    if (z_inner != 0 && z_inner != 1) return fail(RTM_EINVAL, "z_inner must be 0 or 1");
+    if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
+    std::atomic<int> &g = op == RTM_OP_MODEL ? g_tune3d_fwd : g_tune3d_rev;
+    g = (g.load() & ~(1 << 15)) | (z_inner << 15);
+    return RTM_OK;
+}
+
+int rtm_get_tile_order3d(int op, int *z_inner)
+{
+    if (!z_inner) return fail(RTM_EINVAL, "NULL output");
+    if (op != RTM_OP_MODEL && op != RTM_OP_RTM && op != RTM_OP_VJP) return fail(RTM_EINVAL, "unknown op %d", op);
+    *z_inner = get_tune(op == RTM_OP_MODEL ? 0 : 1, 3).zin;
     return RTM_OK;
 }
 

@@ -87,9 +87,22 @@ def test_set_tuning3d_validation():
         rtm.rtm_set_tuning3d(rtm.RTM_OP_RTM, 1, 16, 18)
         assert rtm.rtm_get_tuning3d(rtm.RTM_OP_MODEL) == (2, 16, 27)
         assert rtm.rtm_get_tuning3d(rtm.RTM_OP_RTM) == (1, 16, 18)
+        # tile order: 0 or 1, per operation, kept by rtm_set_tuning3d
+        for bad_order in (-1, 2):
+            with pytest.raises(rtm.RtmError):
+                rtm.rtm_set_tile_order3d(rtm.RTM_OP_RTM, bad_order)
+        with pytest.raises(rtm.RtmError):
+            rtm.rtm_set_tile_order3d(99, 1)
+        assert rtm.rtm_get_tile_order3d(rtm.RTM_OP_RTM) == 0
+        rtm.rtm_set_tile_order3d(rtm.RTM_OP_RTM, 1)
+        rtm.rtm_set_tuning3d(rtm.RTM_OP_RTM, 1, 8, 36)
+        assert rtm.rtm_get_tile_order3d(rtm.RTM_OP_RTM) == 1 and rtm.rtm_get_tile_order3d(rtm.RTM_OP_MODEL) == 0
+        assert rtm.rtm_get_tile_order3d(rtm.RTM_OP_VJP) == 1  # the reverse kernels' setting
     finally:
         rtm.rtm_set_tuning3d(rtm.RTM_OP_MODEL, *old_f)
         rtm.rtm_set_tuning3d(rtm.RTM_OP_RTM, *old_r)
+        rtm.rtm_set_tile_order3d(rtm.RTM_OP_MODEL, 0)
+        rtm.rtm_set_tile_order3d(rtm.RTM_OP_RTM, 0)
 
 
 def _call_model(grid, nt=10, src=(5.0, 0.0, 3.0), rec=((1.0, 0.0, 2.0),), ws_bytes=None, ws=0x100000,

@@ -64,3 +64,34 @@ def test_tuner_installs_its_fastest_candidate():
         assert rtm.rtm_get_tuning2d(op) == (vec, tx, zseg)
         assert rtm.rtm_get_steps_per_launch(op) == steps
     assert rtm.rtm_get_tuning(rtm.RTM_TUNE_EXACT)[0] == 0  # left as found
+
+
+def test_tuner_3d_with_tile_orders():
+    """3-D candidates (vec, rows per workgroup, planes per tile, tile order)
+    on a small layered grid: the table covers every candidate, the fastest
+    forward and reverse shapes and orders are installed (a forward-only
+    candidate has no reverse time), and a shot migrated under the installed
+    configuration equals the default one bit for bit."""
+    v = synth.layered_salt_3d(44, 37, 30, 5)
+    h, nb, dt, nt = 10.0, 8, 1e-3, 60
+    g = rtm.Grid.for_model(v, h, nb)
+    vp = rtm.rtm_rbc_pad(g, torch.from_numpy(v).to(DEV), 2, 0.0)
+    w = torch.from_numpy(synth.ricker(15.0, dt, nt)).to(DEV)
+    src = np.array([21.5, 18.0, 2.0])
+    xs, ys = np.meshgrid(np.arange(0, 44, 3, dtype=np.float64), np.arange(0, 37, 3, dtype=np.float64), indexing="xy")
+    rec = np.stack([xs.ravel(), ys.ravel(), np.full(xs.size, 2.0)], 1).astype(np.float32)
+    d = rtm.rtm_model_shot(g, vp, dt, w, src, rec)
+    ref = rtm.rtm_rtm_shot(g, vp, dt, w, src, rec, d)["image"]
+    shapes = ((1, 4, 18, 0), (1, 4, 18, 1), (2, 8, 9, 1), (2, 16, 9, 0))
+    res = autotune.tune_batch(g, vp, w, [src], rec, dt, nt_probe=36, reps=1, shapes=shapes)
+    print("3-D tuner table (us per step, forward / reverse):", res["table"])
+    assert len(res["table"]) == len(shapes)
+    assert res["table"]["2x16x9x0"][1] == float("inf")
+    for op, key in ((rtm.RTM_OP_MODEL, "forward"), (rtm.RTM_OP_RTM, "reverse")):
+        best = tuple(res[key][:-1])
+        assert best in shapes
+        assert rtm.rtm_get_tuning3d(op) == best[:3] and rtm.rtm_get_tile_order3d(op) == best[3]
+    rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
+    d2 = rtm.rtm_model_shot(g, vp, dt, w, src, rec)
+    im2 = rtm.rtm_rtm_shot(g, vp, dt, w, src, rec, d2)["image"]
+    assert torch.equal(d2, d) and torch.equal(im2, ref)

@@ -100,11 +100,14 @@ def test_launch_shape_invariance_3d():
     outs = []
     rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
     try:
-        # (forward shape, reverse shape); 16-row workgroups at vec 1 and 2
-        for fs, rs in (((1, 4, 9),) * 2, ((2, 8, 18),) * 2, ((4, 8, 36),) * 2, ((2, 4, 27),) * 2,
-                       ((1, 8, 9),) * 2, ((1, 16, 9),) * 2, ((2, 16, 18), (1, 16, 27))):
+        # (forward shape, reverse shape[, tile order]); 16-row workgroups at vec 1 and 2
+        for fs, rs, *order in (((1, 4, 9),) * 2, ((2, 8, 18),) * 2, ((4, 8, 36),) * 2, ((2, 4, 27),) * 2,
+                               ((1, 8, 9),) * 2, ((1, 16, 9),) * 2, ((2, 16, 18), (1, 16, 27)),
+                               ((1, 4, 9), (1, 4, 9), 1), ((2, 8, 18), (1, 8, 27), 1)):
             rtm.rtm_set_tuning3d(rtm.RTM_OP_MODEL, *fs)
             rtm.rtm_set_tuning3d(rtm.RTM_OP_RTM, *rs)
+            for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
+                rtm.rtm_set_tile_order3d(op, order[0] if order else 0)
             tr = _n(rtm.rtm_model_shot(g, vg, dt, w, src, rec))
             im = _n(rtm.rtm_rtm_shot(g, vg, dt, w, src, rec, d)["image"])
             outs.append((tr, im))
@@ -117,9 +120,9 @@ def test_launch_shape_invariance_3d():
 
 def test_sixteen_row_workgroups_vjp_and_storage():
     """The gradient kernel and the storage receiver pass with 16-row
-    workgroups (forward update at vec 2, reverse at vec 1) give the same
-    bits as with 8-row ones, on a grid whose 33 padded rows leave a
-    one-row y tile."""
+    workgroups (forward update at vec 2, reverse at vec 1) and with the
+    z-innermost tile order give the same bits as with 8-row ones, on a grid
+    whose 33 padded rows leave a one-row y tile."""
     v, nb, src, rec, h, dt, nt = _small3d((20, 21, 75), nt=90)
     g, vg, vo = _setup(v, nb)
     w = _t(synth.ricker(25.0, dt, nt))
@@ -128,9 +131,12 @@ def test_sixteen_row_workgroups_vjp_and_storage():
     outs = []
     rtm.rtm_set_tuning(rtm.RTM_TUNE_EXACT, 1, 0)
     try:
-        for fs, rs in (((2, 8, 18), (1, 8, 18)), ((2, 16, 18), (1, 16, 18)), ((1, 16, 27), (1, 16, 9))):
+        for fs, rs, order in (((2, 8, 18), (1, 8, 18), 0), ((2, 16, 18), (1, 16, 18), 0), ((1, 16, 27), (1, 16, 9), 0),
+                              ((2, 8, 18), (1, 4, 9), 1)):
             rtm.rtm_set_tuning3d(rtm.RTM_OP_MODEL, *fs)
             rtm.rtm_set_tuning3d(rtm.RTM_OP_RTM, *rs)
+            for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
+                rtm.rtm_set_tile_order3d(op, order)
             gv, gw = rtm.rtm_model_shot_vjp(g, vg, dt, w, src, rec, gt, want_wavelet_grad=True)
             st = rtm.rtm_storage_shot(g, vg, dt, w, src, rec, d, 4, 1, want_numden=True)
             outs.append([_n(gv), _n(gw), _n(st["num"]), _n(st["den"]), _n(st["snapshots"])])
