@@ -828,113 +828,146 @@ __global__ __launch_bounds__(256) void conv_thin_out_kernel(ConvArgs a)
     thin_store(a, v, 0, 1, acc);
 }
 
-// Weight gradient of a one-channel layer: dw[o][tap][i] = sum_v dy[v][o]
-// x[v + off(tap)][i] with (CIN, COUT) = (1, 16) or (16, 1).  Block (b, p)
-// sums voxels [b nvox / NB, (b + 1) nvox / NB) for the taps of plane
-// dz = p - 1; wave w of its three takes the three taps of row dy = w - 1,
-// lane l the voxels l, l + 64, ...; the lanes' sums are added by a fixed
-// butterfly and written as partial b, which sum_parts adds in a fixed
-// order.  The bias gradient is summed by wave 1 of plane 1.
-constexpr int kThinWgBlocks = 2048;
+// ---------------------------------------------------------------------------
+// Weight gradient of the one-channel layers on the matrix cores.  With W the
+// 16-channel operand (dy of the 1 -> 16 layer, x of the 16 -> 1 layer) and
+// T the one-channel one (x, resp. dy), the MFMA takes A = W^T [16 channels]
+// [32 voxels of an output row segment] and B[k][t] = T at voxel k moved by
+// tap t = (dz, dy, dx) (27 taps in two 16-column tiles), so that
+// C[c][t] = sum_k W[k][c] T[k + off(t)].  For 1 -> 16 that is dw[c][t]; for
+// 16 -> 1, dw[t][c] = sum_u x[u][c] dy[u - off(t)] is C[c][26 - t].  A job
+// is (n, 4 planes, a 32-voxel x segment, a y range) as in the ring kernel;
+// wave w of the block takes output plane z0 + w, the block marches y with a
+// three-row ring of T rows of the 6 planes z0 - 1 .. z0 + 4 (x^T of the
+// voxels x0 - 1 .. x0 + 32), and each wave writes its own partial sums.
+// ---------------------------------------------------------------------------
+constexpr int kThinZB = 4, kThinSeg = 32, kThinXW = kThinSeg + 8, kThinNP = kThinZB + 2;
+
+struct WtArgs {
+    const uint16_t *w16;  // the 16-channel operand, channels-last
+    const uint16_t *t1;   // the one-channel operand
+    float *part;          // [jobs * 4][432]
+    float *bpart;         // [jobs * 4][16 or 1]
+    int d, h, w;
+    int nzb, nxs, ys;
+};
 
 template <bool IN1>
-__global__ __launch_bounds__(192) void wgrad_thin_kernel(const uint16_t *__restrict__ x,
-                                                         const uint16_t *__restrict__ dy, int64_t nvox, int D, int H,
-                                                         int W, float *__restrict__ part, float *__restrict__ bpart)
+__global__ __launch_bounds__(256) void wgrad_thin_mfma_kernel(WtArgs a)
 {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int64_t v0 = nvox * blockIdx.x / gridDim.x, v1 = nvox * (blockIdx.x + 1) / gridDim.x;
-    const int64_t HW = (int64_t)H * W;
-    const int tap0 = blockIdx.y * 9 + wv * 3;
-    const bool bias_wave = blockIdx.y == 1 && wv == 1;
-    float acc[3][kThin], bacc[kThin];
-#pragma unroll
-    for (int t = 0; t < 3; ++t)
-#pragma unroll
-        for (int c = 0; c < kThin; ++c) acc[t][c] = 0.f;
-#pragma unroll
-    for (int c = 0; c < kThin; ++c) bacc[c] = 0.f;
-    for (int64_t v = v0 + lane; v < v1; v += 64) {
-        int z, y, xx;
-        thin_decode(v, D, H, W, z, y, xx);
-        float wide[kThin];
-        float thin_c = 0.f;
-        if (IN1) {  // dy is the 16-channel side at v
-            const uint4 *p = reinterpret_cast<const uint4 *>(dy + v * kThin);
-            const uint4 c0 = p[0], c1 = p[1];
-            const uint16_t *e0 = reinterpret_cast<const uint16_t *>(&c0);
-            const uint16_t *e1 = reinterpret_cast<const uint16_t *>(&c1);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                wide[i] = bf2f(e0[i]);
-                wide[8 + i] = bf2f(e1[i]);
-            }
-            if (bias_wave)
-#pragma unroll
-                for (int c = 0; c < kThin; ++c) bacc[c] += wide[c];
-        } else {    // dy is the one-channel side at v
-            thin_c = bf2f(dy[v]);
-            if (bias_wave) bacc[0] += thin_c;
+    constexpr int SEG = kThinSeg, XW = kThinXW, NP = kThinNP, ZB = kThinZB, C16 = kThin;
+    __shared__ __attribute__((aligned(16))) uint16_t tr[3 * NP * XW];       // ring of T rows
+    __shared__ __attribute__((aligned(16))) uint16_t wT[ZB * C16 * SEG];    // W^T of the output rows
+    const int job = blockIdx.x, tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+    const int r16 = lane & 15, g = lane >> 4;
+    int t = job;
+    const int ysp = t % a.ys;
+    t /= a.ys;
+    const int xs = t % a.nxs;
+    t /= a.nxs;
+    const int zb = t % a.nzb, n = t / a.nzb;
+    const int D = a.d, H = a.h, W = a.w;
+    const int z0 = zb * ZB, x0 = xs * SEG;
+    const int ya = (int)((int64_t)H * ysp / a.ys), yb = (int)((int64_t)H * (ysp + 1) / a.ys);
+    const int64_t nD = (int64_t)n * D;
+
+    // T row yr of the NP planes into ring slot yr mod 3: tr[slot][p][jj] =
+    // T[n][z0 - 1 + p][yr][x0 + jj - 1], jj = 0 .. 33 (one value per thread)
+    auto stage_t = [&](int yr) {
+        const int slot = (yr + 3) % 3;
+        for (int c = tid; c < NP * (SEG + 2); c += 256) {
+            const int jj = c % (SEG + 2), p = c / (SEG + 2);
+            const int zs = z0 - 1 + p, xg = x0 + jj - 1;
+            uint16_t v = 0;
+            if ((unsigned)yr < (unsigned)H && (unsigned)zs < (unsigned)D && (unsigned)xg < (unsigned)W)
+                v = a.t1[((nD + zs) * H + yr) * W + xg];
+            tr[(slot * NP + p) * XW + jj] = v;
         }
+    };
+    // W^T of output rows (n, z0 + zi, y): wT[zi][c][j] = W[n][z0 + zi][y][x0 + j][c]
+    auto stage_w = [&](int y) {
+        for (int c = tid; c < ZB * SEG * 2; c += 256) {
+            const int j = c % SEG, rest = c / SEG;
+            const int half = rest & 1, zi = rest >> 1;
+            const int z = z0 + zi, xg = x0 + j;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if (z < D && xg < W)
+                v = *reinterpret_cast<const uint4 *>(a.w16 + (((nD + z) * H + y) * W + xg) * C16 + half * 8);
+            const uint16_t *e = reinterpret_cast<const uint16_t *>(&v);
+            uint16_t *dst = wT + (zi * C16 + half * 8) * SEG + j;
 #pragma unroll
-        for (int t9 = 0; t9 < 3; ++t9) {
-            const int tap = tap0 + t9;
-            int64_t off;
-            if (!thin_tap(tap, z, y, xx, D, H, W, HW, off)) continue;
-            if (IN1) {
-                const float xt = bf2f(x[v + off]);
+            for (int i = 0; i < 8; ++i) dst[i * SEG] = e[i];
+        }
+    };
+
+    // this lane's taps in the two column tiles: t = tt * 16 + r16
+    int tdz[2], tdy[2], tsh[2];
+    bool tok[2];
 #pragma unroll
-                for (int c = 0; c < kThin; ++c) acc[t9][c] = fmaf(wide[c], xt, acc[t9][c]);
-            } else {
-                const uint4 *p = reinterpret_cast<const uint4 *>(x + (v + off) * kThin);
-                const uint4 c0 = p[0], c1 = p[1];
-                const uint16_t *e0 = reinterpret_cast<const uint16_t *>(&c0);
-                const uint16_t *e1 = reinterpret_cast<const uint16_t *>(&c1);
+    for (int tt = 0; tt < 2; ++tt) {
+        const int tap = tt * 16 + r16;
+        tok[tt] = tap < 27;
+        tdz[tt] = tap / 9 - 1;
+        tdy[tt] = (tap / 3) % 3 - 1;
+        tsh[tt] = tap % 3;  // jj shift: voxel x0 + k + dx sits at jj = k + dx + 1
+    }
+    f32x4 acc[2] = {f32x4{0.f, 0.f, 0.f, 0.f}, f32x4{0.f, 0.f, 0.f, 0.f}};
+    float bacc = 0.f;
+
+    stage_t(ya - 1);
+    stage_t(ya);
+    for (int y = ya; y < yb; ++y) {
+        stage_t(y + 1);
+        stage_w(y);
+        __syncthreads();
+        const uint4 A = *reinterpret_cast<const uint4 *>(wT + (wv * C16 + r16) * SEG + 8 * g);
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    acc[t9][i] = fmaf(thin_c, bf2f(e0[i]), acc[t9][i]);
-                    acc[t9][8 + i] = fmaf(thin_c, bf2f(e1[i]), acc[t9][8 + i]);
-                }
+        for (int tt = 0; tt < 2; ++tt) {
+            uint4 B = {0u, 0u, 0u, 0u};
+            const int sy = y + tdy[tt];
+            if (tok[tt] && (unsigned)sy < (unsigned)H) {
+                const uint16_t *row = tr + ((sy % 3) * NP + wv + 1 + tdz[tt]) * XW + 8 * g;
+                const uint4 L = *reinterpret_cast<const uint4 *>(row);
+                const uint4 R = *reinterpret_cast<const uint4 *>(row + 8);
+                const uint4 B1 = {(L.x >> 16) | (L.y << 16), (L.y >> 16) | (L.z << 16),
+                                  (L.z >> 16) | (L.w << 16), (L.w >> 16) | (R.x << 16)};
+                const uint4 B2 = {L.y, L.z, L.w, R.x};
+                B = tsh[tt] == 0 ? L : (tsh[tt] == 1 ? B1 : B2);
             }
+            acc[tt] = mfma16(A, B, acc[tt]);
+        }
+        if (IN1) {  // bias of the 16 channels: lane (c = r16, g) sums voxels 8g .. 8g + 7
+#pragma unroll
+            for (int j = 0; j < 8; ++j) bacc += bf2f(wT[(wv * C16 + r16) * SEG + 8 * g + j]);
+        } else if (lane < SEG) {  // bias of the one channel: dy of this output row, one voxel per lane
+            bacc += bf2f(tr[((y % 3) * NP + wv + 1) * XW + lane + 1]);
+        }
+        __syncthreads();  // every wave is done with this step's ring slot and W^T
+    }
+    // partial sums of (job, wave): lane holds c = 4g + e, t = tt*16 + r16
+    const int64_t pw = (int64_t)job * ZB + wv;
+    float *part = a.part + pw * 27 * C16;
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+        if (!tok[tt]) continue;
+        const int tap = tt * 16 + r16;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int c = 4 * g + e;
+            // (1, 16): dw[c][tap][0]; (16, 1): dw[0][26 - tap][c]
+            part[IN1 ? c * 27 + tap : (26 - tap) * C16 + c] = acc[tt][e];
         }
     }
-    // butterfly over the 64 lanes (fixed order), lane 0 writes
+    if (IN1) {  // the four voxel groups of each channel, in a fixed order
+        const float b1 = __shfl_down(bacc, 16), b2 = __shfl_down(bacc, 32), b3 = __shfl_down(bacc, 48);
+        if (lane < 16) a.bpart[pw * C16 + lane] = (bacc + b1) + (b2 + b3);
+    } else {  // fixed butterfly over the lanes
 #pragma unroll
-    for (int t = 0; t < 3; ++t)
-#pragma unroll
-        for (int c = 0; c < kThin; ++c) {
-            float sv = acc[t][c];
-#pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) sv += __shfl_xor(sv, m, 64);
-            acc[t][c] = sv;
-        }
-#pragma unroll
-    for (int c = 0; c < kThin; ++c) {
-        float sv = bacc[c];
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) sv += __shfl_xor(sv, m, 64);
-        bacc[c] = sv;
-    }
-    if (lane == 0) {
-        float *pb = part + (int64_t)blockIdx.x * 27 * kThin;
-#pragma unroll
-        for (int t9 = 0; t9 < 3; ++t9) {
-            const int tap = tap0 + t9;
-#pragma unroll
-            for (int c = 0; c < kThin; ++c) {
-                // (1, 16): dw[c][tap][0]; (16, 1): dw[0][tap][c]
-                pb[IN1 ? c * 27 + tap : tap * kThin + c] = acc[t9][c];
-            }
-        }
-        if (bias_wave) {
-            if (IN1)
-#pragma unroll
-                for (int c = 0; c < kThin; ++c) bpart[(int64_t)blockIdx.x * kThin + c] = bacc[c];
-            else
-                bpart[blockIdx.x] = bacc[0];
-        }
+        for (int m = 32; m >= 1; m >>= 1) bacc += __shfl_xor(bacc, m, 64);
+        if (lane == 0) a.bpart[pw] = bacc;
     }
 }
+
 
 // ---------------------------------------------------------------------------
 // Element-wise and resampling kernels
@@ -1290,13 +1323,20 @@ int wg_sizes_ci(int co, int64_t rows, int64_t *parts, int *S)
     return -1;
 }
 
-// One-channel layers: one partial per block of wgrad_thin_kernel, about
-// 256 voxels per block at the least.
-int thin_wg_blocks(int64_t nvox)
+// One-channel layers on the matrix cores: jobs as in the ring kernel (4
+// planes, 32-voxel x segments, y ranges of >= kThinMinRows rows), about
+// kThinMfmaBlocks of them; one partial per wavefront (4 per job).
+constexpr int64_t kThinMfmaBlocks = 2048;
+constexpr int kThinMinRows = 8;
+
+void thin_layout(const unet_conv_desc_t *d, int *nzb, int *nxs, int *ys)
 {
-    int64_t b = nvox / 256;
-    if (b > kThinWgBlocks) b = kThinWgBlocks;
-    return b < 1 ? 1 : (int)b;
+    *nzb = (d->d + kThinZB - 1) / kThinZB;
+    *nxs = (d->w + kThinSeg - 1) / kThinSeg;
+    const int64_t cols = (int64_t)d->n * *nzb * *nxs;
+    int64_t y = (kThinMfmaBlocks + cols - 1) / cols;
+    if (y > d->h / kThinMinRows) y = d->h / kThinMinRows;
+    *ys = (int)(y < 1 ? 1 : y);
 }
 
 // Ring-staged weight gradient: MFMA pairs of <= 64 input channels on grids
@@ -1336,8 +1376,9 @@ int wg_layout(const unet_conv_desc_t *d, int64_t *parts, int *S)
         return 0;
     }
     if (thin_pair(d->cin, d->cout)) {
-        *S = thin_wg_blocks(rows * d->w);
-        *parts = *S;
+        thin_layout(d, &nzb, &nxs, &ys);
+        *S = (int)((int64_t)d->n * nzb * nxs * ys);
+        *parts = (int64_t)*S * kThinZB;
         return 0;
     }
     switch (d->cin) {
@@ -1547,13 +1588,22 @@ int unet_conv3d_wgrad(const unet_conv_desc_t *desc, const uint16_t *x, const uin
         case 64: hipLaunchKernelGGL((conv_wgrad_ring_kernel<64, 2>), grid, dim3(576), 0, st, r); break;
         default: return bad("unsupported channel pair");
         }
-    } else if (desc->cin == 1)
-        hipLaunchKernelGGL(wgrad_thin_kernel<true>, dim3((unsigned)S, 3), dim3(192), 0, st, x, dy, a.rows * a.w, a.d,
-                           a.h, a.w, a.part, a.bpart);
-    else if (desc->cout == 1)
-        hipLaunchKernelGGL(wgrad_thin_kernel<false>, dim3((unsigned)S, 3), dim3(192), 0, st, x, dy, a.rows * a.w, a.d,
-                           a.h, a.w, a.part, a.bpart);
-    else
+    } else if (thin_pair(desc->cin, desc->cout)) {
+        WtArgs t{};
+        const bool in1 = desc->cin == 1;
+        t.w16 = in1 ? dy : x;
+        t.t1 = in1 ? x : dy;
+        t.part = a.part;
+        t.bpart = a.bpart;
+        t.d = desc->d;
+        t.h = desc->h;
+        t.w = desc->w;
+        thin_layout(desc, &t.nzb, &t.nxs, &t.ys);
+        if (in1)
+            hipLaunchKernelGGL(wgrad_thin_mfma_kernel<true>, dim3((unsigned)S), dim3(256), 0, st, t);
+        else
+            hipLaunchKernelGGL(wgrad_thin_mfma_kernel<false>, dim3((unsigned)S), dim3(256), 0, st, t);
+    } else
         launch_wg(desc->cin, desc->cout, a, st);
     UNET_HIP(sum_parts(a.part, nw, tmp_w, dw, a.bpart, db ? desc->cout : 0, tmp_b, db, parts, st));
     return RTM_OK;

@@ -206,8 +206,9 @@ def test_unet_channel_pairs_on_the_host():
     """The convolution entry points take two of 16/32/64/128 channels or the
     one-channel pairs (1, 16) and (16, 1); anything else is rejected before
     any launch.  The one-channel weight gradient's workspace holds one
-    partial of 27*16 weights and 16 (or 1) biases per block, for at most
-    2048 blocks of at least 256 voxels, plus the two-pass chunk sums."""
+    partial of 27*16 weights and 16 (or 1) biases per wavefront, four per
+    job (n, 4 planes, a 32-voxel x segment, a y range of at least 8 rows,
+    about 2048 jobs), plus the two-pass chunk sums."""
     lib = _lib.load()
     sz = ctypes.c_size_t(0)
 
@@ -218,21 +219,29 @@ def test_unet_channel_pairs_on_the_host():
     def rnd(b):
         return (b + 255) // 256 * 256
 
+    def thin_bytes(parts, nb):
+        q = (parts + 31) // 32
+        return rnd(parts * 432 * 4) + rnd(parts * nb * 4) + rnd(q * 432 * 4) + rnd(q * nb * 4)
+
     for ci, co in ((16, 16), (32, 64), (128, 64), (1, 16), (16, 1)):
         rc, b = ws((1, 8, 8, 8), ci, co)
         assert rc == _lib.RTM_OK and b > 0, (ci, co)
     for ci, co in ((1, 32), (32, 1), (1, 1), (8, 16), (16, 8), (2, 16), (0, 16)):
         rc, _ = ws((1, 8, 8, 8), ci, co)
         assert rc == _lib.RTM_EINVAL, (ci, co)
-    # (1, 16) at 64^3: 262144 / 256 = 1024 blocks, one chunk sum per 32 partials
+    # (1, 16) at 64^3: 16 plane blocks x 2 segments, y ranges capped at 64 / 8:
+    # 256 jobs, 1024 partials
     rc, b = ws((1, 64, 64, 64), 1, 16)
-    assert rc == _lib.RTM_OK and b == rnd(1024 * 432 * 4) + rnd(1024 * 16 * 4) + rnd(32 * 432 * 4) + rnd(32 * 16 * 4)
-    # (16, 1) at 128^3: capped at 2048 blocks
+    assert rc == _lib.RTM_OK and b == thin_bytes(1024, 16)
+    # (16, 1) at 128^3: 32 x 4 columns x 16 y ranges = 2048 jobs
     rc, b = ws((1, 128, 128, 128), 16, 1)
-    assert rc == _lib.RTM_OK and b == rnd(2048 * 432 * 4) + rnd(2048 * 4) + rnd(64 * 432 * 4) + rnd(64 * 4)
-    # tiny images still get one block
+    assert rc == _lib.RTM_OK and b == thin_bytes(8192, 1)
+    # ragged two-sample grid: 2 x ceil(19 / 4) x ceil(70 / 32) = 30 columns, 23 // 8 = 2 y ranges
+    rc, b = ws((2, 19, 23, 70), 1, 16)
+    assert rc == _lib.RTM_OK and b == thin_bytes(4 * 60, 16)
+    # tiny images still get one job
     rc, b = ws((1, 2, 2, 2), 1, 16)
-    assert rc == _lib.RTM_OK and b == rnd(432 * 4) + rnd(16 * 4) + rnd(432 * 4) + rnd(16 * 4)
+    assert rc == _lib.RTM_OK and b == thin_bytes(4, 16)
 
 
 def test_persistent_plan_validation_on_the_host():

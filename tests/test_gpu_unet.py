@@ -121,12 +121,13 @@ def test_conv_wgrad_parity_and_determinism(ci, co):
     _wgrad_check((2, 4, 7, 45), ci, co)
 
 
-@pytest.mark.parametrize("ci,co", [(16, 32), (32, 16), (64, 32)])
+@pytest.mark.parametrize("ci,co", [(16, 32), (32, 16), (64, 32), (1, 16), (16, 1)])
 def test_ring_wgrad_parity_ragged(ci, co):
-    """The ring-staged weight gradient (MFMA pairs of at most 64 input
-    channels on grids of 2^17 voxels or more) on a ragged two-sample grid:
-    19 planes (not a multiple of the 4- or 2-plane block), 150 columns (a
-    partial 32-voxel segment), 23 rows split into unequal y ranges."""
+    """The ring-staged weight gradients (MFMA pairs of at most 64 input
+    channels on grids of 2^17 voxels or more, and the one-channel pairs on
+    the matrix cores at any size) on a ragged two-sample grid: 19 planes
+    (not a multiple of the 4- or 2-plane block), 150 columns (a partial
+    32-voxel segment), 23 rows split into unequal y ranges."""
     _wgrad_check((2, 19, 23, 150), ci, co)
 
 
