@@ -25,17 +25,17 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 
-# HBM bytes of one reverse launch (48 shots, three steps per launch, shape
+# HBM bytes of one reverse launch (240 shots, three steps per launch, shape
 # vec 2, tx 1, zseg 108) from two rocprofv3 counter runs: L2-to-memory read
 # requests by size (TCC_EA0_RDREQ_32B/64B/128B) and write requests
 # (TCC_EA0_WRREQ, TCC_EA0_WRREQ_64B; the rest are 32 B).  A 1 GiB device copy
 # in the same runs reads exactly 8388608 x 128 B and writes 16777216 x 64 B
 # (twice that for the 2 GiB copy of the bandwidth reference), so the request
 # counts are bytes without further scaling.  Valid only for the kernel
-# sources hashed here; reported as null once they change.
-PMC_REVERSE = {"sources_sha256_16": "adcdf4334ec8bdf9", "shots": 48, "shape": (2, 1, 108), "steps": 3,
-               "read_bytes": 29123969 * 128 + 19286 * 64 + (29143255 - 29123969 - 19286) * 32,
-               "write_bytes": 36436856 * 64 + (36676667 - 36436856) * 32}
+# sources hashed here and this batch; reported as null otherwise.
+PMC_REVERSE = {"sources_sha256_16": "adcdf4334ec8bdf9", "shots": 240, "shape": (2, 1, 108), "steps": 3,
+               "read_bytes": 151012277 * 128 + 71862 * 64 + (151084139 - 151012277 - 71862) * 32,
+               "write_bytes": 182277108 * 64 + (183476177 - 182277108) * 32}
 KERNEL_SOURCES = ("prop2d.hip", "stencil.h", "common.h")
 
 
@@ -56,10 +56,10 @@ def reverse_traffic(B, shape, steps=1):
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--shots-per-step", type=int, default=48,
-                    help="shots per step; 5 steps of 48 cover the 240-shot survey once")
+    ap.add_argument("--shots-per-step", type=int, default=240,
+                    help="shots per step (one launch carries them all); 240 = the whole survey, resident in HBM")
     ap.add_argument("--plain-shots", type=int, default=2, help="shots timed through the plain per-shot calls")
     ap.add_argument("--vec", type=int, default=0, help="floats per lane of both propagation kernels (0: tuned)")
     ap.add_argument("--zseg", type=int, default=0, help="rows per tile of both kernels, a multiple of 9 (0: tuned)")
@@ -650,21 +650,22 @@ def main():
     stack = torch.zeros(g.interior_shape, dtype=torch.float32, device=dev)
     ngroups = max(1, nshot // B)
     groups = [[(k * B + j) % nshot for j in range(B)] for k in range(ngroups)]
+    # one workspace for every plan (they run one after another on one
+    # stream), sized for the largest: groups of other source positions can
+    # need more than the first
     plans = []
-    ws = None
     for grp in groups:
         mp = rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, v_pad, wav, s.src[i], s.rec, traces_out=traces[j])
-                                              for j, i in enumerate(grp)], s.dt, nt, ws=ws)
-        if ws is None:
-            need = mp.ws_bytes
+                                              for j, i in enumerate(grp)], s.dt, nt)
         rp = rtm.BatchPlan(rtm.RTM_OP_RTM, [rtm.BatchShot(g, v_pad, wav, s.src[i], s.rec, traces_in=traces[j],
                                                           image=stack) for j, i in enumerate(grp)],
-                           s.dt, nt, eps_rel=1e-3, flags=rtm.RTM_F_ACCUMULATE, ws=ws)
-        if ws is None:
-            ws = torch.empty(max(need, rp.ws_bytes), dtype=torch.uint8, device=dev)
-            mp.bind_workspace(ws)
-            rp.bind_workspace(ws)
+                           s.dt, nt, eps_rel=1e-3, flags=rtm.RTM_F_ACCUMULATE)
         plans.append((mp, rp))
+    ws = torch.empty(max(max(mp.ws_bytes, rp.ws_bytes) for mp, rp in plans), dtype=torch.uint8, device=dev)
+    for mp, rp in plans:
+        mp.bind_workspace(ws)
+        rp.bind_workspace(ws)
+    torch.cuda.empty_cache()
 
     def step(i):
         rtm.rtm_rbc_pad(g, v_int, s.seed, 0.0, out=v_pad)
@@ -780,6 +781,7 @@ def main():
             "padded_cells": cells,
             "shots_per_step": B,
             "propagations_per_shot": 4,
+            "workspace_bytes": int(ws.numel()),
             "launch_shape": {"forward": {"vec": fwd_shape[0], "tx": fwd_shape[1], "zseg": fwd_shape[2]},
                              "reverse": {"vec": rev_shape[0], "tx": rev_shape[1], "zseg": rev_shape[2]},
                              "autotuned": tuned is not None,

@@ -2,7 +2,7 @@
 the GPU against the FP64 oracle (rel-L2 <= 1e-4) where the oracle can
 follow in bounded time:
 
-- the folded-layer survey batch exactly as the benchmark times it (48
+- the folded-layer survey batch exactly as the benchmark times it (all 240
   shots of the 2301 x 751 grid per launch, three steps per launch, two
   floats per lane, 108-row tiles) at its full 5000 steps;
 - the layered-salt 3-D grid at full size (612 x 612 x 356 padded) for 400
@@ -45,12 +45,12 @@ def _n(t):
 
 @pytest.mark.timeout(900)
 def test_folded_survey_bench_batch_full_nt(progress):
-    """The benchmark's 48-shot batch at its launch shape and full nt 5000.
+    """The benchmark's 240-shot batch at its launch shape and full nt 5000.
     Shot 1 (source at a half cell): GPU traces against the oracle's, and the
     GPU image of the oracle's traces against the oracle's image.  Shots 0
-    and 47: traces and images equal, bit for bit, one-step single-shot calls
-    on the same inputs."""
-    nt, B = 5000, 48
+    and 239: traces and images equal, bit for bit, one-step single-shot
+    calls on the same inputs."""
+    nt, B = 5000, 240
     s = synth.config_c2(nshot=B, nt=nt)
     g = rtm.Grid.for_model(s.v_int, s.h, s.nb)
     vg = rtm.rtm_rbc_pad(g, _t(s.v_int), s.seed, 0.0)
@@ -64,7 +64,7 @@ def test_folded_survey_bench_batch_full_nt(progress):
     for op in (rtm.RTM_OP_MODEL, rtm.RTM_OP_RTM):
         rtm.rtm_set_tuning2d(op, 2, 1, 108)
         rtm.rtm_set_steps_per_launch(op, 3)
-    progress("GPU: 48-shot modeling and RTM batches")
+    progress(f"GPU: {B}-shot modeling and RTM batches")
     traces = [torch.empty((s.rec.shape[0], nt + 1), device=DEV) for _ in srcs]
     plan = rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, vg, w, x, s.rec, traces_out=t)
                                             for x, t in zip(srcs, traces)], s.dt, nt)
