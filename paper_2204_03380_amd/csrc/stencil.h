@@ -149,11 +149,17 @@ __device__ __forceinline__ f4v halo_fetch(const gfloat *row, int x0, int NX, int
     return t;
 }
 
+// exchange_row reads hl only in lane 0 (the lane a right shift leaves
+// without a source) and hr only in lane 63, which are the lanes that loaded
+// the left and the right halo: both are the fetched values as they are, with
+// no per-lane selection and no second set of registers.
 __device__ __forceinline__ void halo_split(f4v t, int lane, float (&hl)[4], float (&hr)[4])
 {
-    const bool left = lane == 0, right = lane == 63;
-    hl[0] = left ? t.x : 0.f; hl[1] = left ? t.y : 0.f; hl[2] = left ? t.z : 0.f; hl[3] = left ? t.w : 0.f;
-    hr[0] = right ? t.x : 0.f; hr[1] = right ? t.y : 0.f; hr[2] = right ? t.z : 0.f; hr[3] = right ? t.w : 0.f;
+    (void)lane;
+    hl[0] = hr[0] = t.x;
+    hl[1] = hr[1] = t.y;
+    hl[2] = hr[2] = t.z;
+    hl[3] = hr[3] = t.w;
 }
 
 // Strip-end halo of one row for a wave inside a workgroup of strips: only
