@@ -995,6 +995,34 @@ __global__ void embed_kernel(int64_t nvox, int ch, const float *__restrict__ img
     x[i] = (i - v * ch) == 0 ? f2bf(img[v] * scale) : (uint16_t)0;
 }
 
+// Index i of an [n][d][h][w][cg] array as (g, x, y, z, n), in 32-bit
+// arithmetic when the array has fewer than 2^32 elements.
+__device__ __forceinline__ void decode5(int64_t i, int64_t total, int cg, int w, int h, int d, int &g, int &x, int &y,
+                                        int &z, int64_t &nn)
+{
+    if (total <= 0xffffffffll) {
+        uint32_t t = (uint32_t)i;
+        g = (int)(t % (uint32_t)cg);
+        t /= (uint32_t)cg;
+        x = (int)(t % (uint32_t)w);
+        t /= (uint32_t)w;
+        y = (int)(t % (uint32_t)h);
+        t /= (uint32_t)h;
+        z = (int)(t % (uint32_t)d);
+        nn = t / (uint32_t)d;
+    } else {
+        int64_t t = i;
+        g = (int)(t % cg);
+        t /= cg;
+        x = (int)(t % w);
+        t /= w;
+        y = (int)(t % h);
+        t /= h;
+        z = (int)(t % d);
+        nn = t / d;
+    }
+}
+
 // One thread per (coarse voxel, 8-channel group).
 __global__ void pool2_kernel(int n, int d, int h, int w, int c, const uint16_t *__restrict__ x,
                              uint16_t *__restrict__ y)
@@ -1003,15 +1031,9 @@ __global__ void pool2_kernel(int n, int d, int h, int w, int c, const uint16_t *
     const int64_t total = (int64_t)n * d2 * h2 * w2 * cg;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
-    int64_t t = i;
-    const int gi = (int)(t % cg);
-    t /= cg;
-    const int xo = (int)(t % w2);
-    t /= w2;
-    const int yo = (int)(t % h2);
-    t /= h2;
-    const int zo = (int)(t % d2);
-    const int64_t nn = t / d2;
+    int gi, xo, yo, zo;
+    int64_t nn;
+    decode5(i, total, cg, w2, h2, d2, gi, xo, yo, zo, nn);
     float s[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int k = 0; k < 8; ++k) {
         const int64_t v = ((nn * d + 2 * zo + (k >> 2)) * h + 2 * yo + ((k >> 1) & 1)) * w + 2 * xo + (k & 1);
@@ -1036,43 +1058,38 @@ __global__ void up2_kernel(int n, int d, int h, int w, int c, const uint16_t *__
     const int64_t total = (int64_t)n * D * H * W * cg;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
-    int64_t t = i;
-    const int gi = (int)(t % cg);
-    t /= cg;
-    const int xf = (int)(t % W);
-    t /= W;
-    const int yf = (int)(t % H);
-    t /= H;
-    const int zf = (int)(t % D);
-    const int64_t nn = t / D;
+    int gi, xf, yf, zf;
+    int64_t nn;
+    decode5(i, total, cg, W, H, D, gi, xf, yf, zf, nn);
     const int64_t vc = ((nn * d + zf / 2) * h + yf / 2) * w + xf / 2;
     const int64_t vf = ((nn * D + zf) * H + yf) * W + xf;
     *reinterpret_cast<uint4 *>(y + vf * c + gi * 8) = *reinterpret_cast<const uint4 *>(x + vc * c + gi * 8);
 }
 
-// One thread per (coarse voxel, channel): sum of the 8 children in a fixed order.
+// One thread per (coarse voxel, VEC consecutive channels): each channel's sum
+// of the 8 children in a fixed order; the index is decoded once, in 32-bit
+// arithmetic when it fits.
+template <int VEC>
 __global__ void up2_bwd_kernel(int n, int d, int h, int w, int c, const float *__restrict__ gf,
                                float *__restrict__ gc)
 {
     const int64_t total = (int64_t)n * d * h * w * c;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    int64_t t = i;
-    const int ch = (int)(t % c);
-    t /= c;
-    const int xc = (int)(t % w);
-    t /= w;
-    const int yc = (int)(t % h);
-    t /= h;
-    const int zc = (int)(t % d);
-    const int64_t nn = t / d;
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+    if (i0 >= total) return;
+    int ch, xc, yc, zc;
+    int64_t nn;
+    decode5(i0, total, c, w, h, d, ch, xc, yc, zc, nn);
     const int D = 2 * d, H = 2 * h, W = 2 * w;
-    float s = 0.f;
+    float s[VEC];
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) s[e] = 0.f;
     for (int k = 0; k < 8; ++k) {
         const int64_t v = ((nn * D + 2 * zc + (k >> 2)) * H + 2 * yc + ((k >> 1) & 1)) * W + 2 * xc + (k & 1);
-        s += gf[v * c + ch];
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) s[e] += gf[v * c + ch + e];
     }
-    gc[i] = s;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) gc[i0 + e] = s[e];
 }
 
 // VEC consecutive channels of one voxel per thread (VEC divides c); the
@@ -1648,8 +1665,12 @@ int unet_up2_bwd(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const fl
     rtm::clear_error();
     if (n < 1 || d < 1 || h < 1 || w < 1 || c < 1 || !g_fine || !g_coarse) return bad("invalid up2_bwd arguments");
     const int64_t total = (int64_t)n * d * h * w * c;
-    hipLaunchKernelGGL(up2_bwd_kernel, grid1(total), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c, g_fine,
-                       g_coarse);
+    if (c % 4 == 0)
+        hipLaunchKernelGGL(up2_bwd_kernel<4>, grid1(total / 4), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c,
+                           g_fine, g_coarse);
+    else
+        hipLaunchKernelGGL(up2_bwd_kernel<1>, grid1(total), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c, g_fine,
+                           g_coarse);
     UNET_HIP(hipGetLastError());
     return RTM_OK;
 }
