@@ -656,16 +656,15 @@ def main():
     plans = []
     for grp in groups:
         mp = rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, v_pad, wav, s.src[i], s.rec, traces_out=traces[j])
-                                              for j, i in enumerate(grp)], s.dt, nt)
+                                              for j, i in enumerate(grp)], s.dt, nt, defer_workspace=True)
         rp = rtm.BatchPlan(rtm.RTM_OP_RTM, [rtm.BatchShot(g, v_pad, wav, s.src[i], s.rec, traces_in=traces[j],
                                                           image=stack) for j, i in enumerate(grp)],
-                           s.dt, nt, eps_rel=1e-3, flags=rtm.RTM_F_ACCUMULATE)
+                           s.dt, nt, eps_rel=1e-3, flags=rtm.RTM_F_ACCUMULATE, defer_workspace=True)
         plans.append((mp, rp))
     ws = torch.empty(max(max(mp.ws_bytes, rp.ws_bytes) for mp, rp in plans), dtype=torch.uint8, device=dev)
     for mp, rp in plans:
         mp.bind_workspace(ws)
         rp.bind_workspace(ws)
-    torch.cuda.empty_cache()
 
     def step(i):
         rtm.rtm_rbc_pad(g, v_int, s.seed, 0.0, out=v_pad)

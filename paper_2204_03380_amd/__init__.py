@@ -460,10 +460,13 @@ class BatchShot:
 
 class BatchPlan:
     """rtm_batch_plan / rtm_batch_run / rtm_batch_free over torch tensors.
-    The plan keeps references to every tensor it was given."""
+    The plan keeps references to every tensor it was given.  The workspace
+    is `ws` if given, else one of its own (`ws_bytes`), or none yet with
+    `defer_workspace=True` (for plans that will share one workspace sized
+    for the largest of them: `bind_workspace` before `run`)."""
 
     def __init__(self, op: int, shots, dt: float, nt: int, eps_rel: float = 1e-3, flags: int = 0,
-                 ws: torch.Tensor = None):
+                 ws: torch.Tensor = None, defer_workspace: bool = False):
         self._shots = list(shots)
         n = len(self._shots)
         descs = (_lib.RtmShotDesc * n)()
@@ -503,7 +506,8 @@ class BatchPlan:
         self._plan = plan
         self.ws_bytes = int(ws.value)
         self.ws = None
-        self.bind_workspace(shared_ws)
+        if shared_ws is not None or not defer_workspace:
+            self.bind_workspace(shared_ws)
 
     def bind_workspace(self, ws: torch.Tensor = None) -> None:
         """Use `ws` (uint8, at least ws_bytes) as workspace, else allocate one."""
@@ -534,6 +538,8 @@ class BatchPlan:
         `stream` (record_stream), so that freeing one on the current stream
         afterwards does not let torch hand its memory out again before the
         run has finished with it."""
+        if self.ws is None:
+            raise RuntimeError("BatchPlan.run: no workspace bound (defer_workspace=True needs bind_workspace first)")
         cur = torch.cuda.current_stream(self.device)
         side = stream is not None and stream.cuda_stream != cur.cuda_stream
         if side:

@@ -78,3 +78,19 @@ def test_current_stream_run_records_nothing(monkeypatch):
     plan.run(_Stream(111))  # the current stream passed explicitly
     assert calls == [111, 111]
     assert log == [] and cur.waited == []
+
+
+def test_run_without_a_bound_workspace_is_refused(monkeypatch):
+    """A plan made with defer_workspace=True has no workspace until
+    bind_workspace: run() raises before any device call."""
+    log, calls = [], []
+    _patch(monkeypatch, _Stream(111), calls)
+    plan = _plan(log)
+    plan.ws = None
+    try:
+        plan.run()
+    except RuntimeError as e:
+        assert "no workspace" in str(e)
+    else:
+        raise AssertionError("run() without a workspace was not refused")
+    assert calls == []
