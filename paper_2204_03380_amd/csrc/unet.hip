@@ -216,6 +216,19 @@ __device__ __forceinline__ void lds_store(uint16_t *dst, const uint4 (&v)[LdsTil
     }
 }
 
+// Depth of conv_fwd_lds_kernel's weight ring: the largest divisor of the
+// chunk count whose fragments fit in 40 registers; 1 (no ring: each chunk
+// loads its own fragments) for two output blocks over 27 chunks, where the
+// unrolled march would need more registers than two waves per SIMD allow.
+constexpr int lds_weight_depth(int nch, int cb)
+{
+    if (cb > 1 && nch > 14) return 1;
+    int best = 1;
+    for (int d = 1; d <= nch; ++d)
+        if (nch % d == 0 && d * cb * 4 <= 40) best = d;
+    return best;
+}
+
 template <int CIN, int COUT>
 __global__ __launch_bounds__(256) void conv_fwd_lds_kernel(ConvArgs a, int tiles_x, int tiles_y, int tiles_z, int lz,
                                                            int64_t ntiles)
@@ -242,6 +255,25 @@ __global__ __launch_bounds__(256) void conv_fwd_lds_kernel(ConvArgs a, int tiles
     const bool row_ok = yw < a.h;
     const uint4 zero = {0u, 0u, 0u, 0u};
 
+    // Weight fragments run PD chunks ahead of their MFMAs through a ring of
+    // registers (PD divides the chunk count, so chunk c of every plane uses
+    // slot c mod PD and the ring carries on from one plane to the next:
+    // the weights are the same for every plane).  One load per chunk
+    // waited on right away would leave each chunk waiting a full memory
+    // latency.
+    constexpr int NCH = KP / 32;
+    constexpr int PD = lds_weight_depth(NCH, CB);
+    auto load_b = [&](int c, uint4(&B)[CB]) {
+        const int kk = c * 32 + 8 * g;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+            B[cb] = kk / CIN < 27 ? *reinterpret_cast<const uint4 *>(a.wt + (int64_t)(cb * 16 + r16) * K + kk) : zero;
+    };
+    uint4 Bq[PD][CB];
+    if constexpr (PD > 1) {
+#pragma unroll
+        for (int i = 0; i < PD; ++i) load_b(i, Bq[i]);
+    }
     uint4 next[T::PER];
     lds_fetch<CIN>(a, next, nbase, z0 - 1, y0, x0);
     lds_store<CIN>(ring + ((z0 + 2) % 3) * T::PLANE, next);
@@ -257,9 +289,8 @@ __global__ __launch_bounds__(256) void conv_fwd_lds_kernel(ConvArgs a, int tiles
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 4
-        for (int kc = 0; kc < KP; kc += 32) {
-            const int kk = kc + 8 * g;
+        auto chunk = [&](int c, const uint4(&B)[CB]) {
+            const int kk = c * 32 + 8 * g;
             const int tap = kk / CIN;
             const int ci0 = kk - tap * CIN;
             const bool tv = tap < 27;
@@ -268,14 +299,42 @@ __global__ __launch_bounds__(256) void conv_fwd_lds_kernel(ConvArgs a, int tiles
             uint4 A[4];
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb) A[rb] = tv ? *reinterpret_cast<const uint4 *>(pl + (rb * 16 + r16) * CIN) : zero;
-            uint4 B[CB];
-#pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
-                B[cb] = tv ? *reinterpret_cast<const uint4 *>(a.wt + (int64_t)(cb * 16 + r16) * K + kk) : zero;
 #pragma unroll
             for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(A[rb], B[cb], acc[rb][cb]);
+        };
+        if constexpr (PD > 1) {
+#pragma unroll
+            for (int c = 0; c < NCH; ++c) {
+                chunk(c, Bq[c % PD]);
+                load_b((c + PD) % NCH, Bq[c % PD]);  // chunk c + PD, of this plane or the next
+                // the scheduler would otherwise sink each load to its use
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        } else {
+#pragma unroll 4
+            for (int kc = 0; kc < KP; kc += 32) {
+                const int kk = kc + 8 * g;
+                const int tap = kk / CIN;
+                const int ci0 = kk - tap * CIN;
+                const bool tv = tap < 27;
+                const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+                const uint16_t *pl =
+                    ring + ((z + dz + 3) % 3) * T::PLANE + ((wave + 1 + dy) * T::XW + 1 + dx) * CIN + ci0;
+                uint4 A[4];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+                    A[rb] = tv ? *reinterpret_cast<const uint4 *>(pl + (rb * 16 + r16) * CIN) : zero;
+                uint4 B[CB];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    B[cb] = tv ? *reinterpret_cast<const uint4 *>(a.wt + (int64_t)(cb * 16 + r16) * K + kk) : zero;
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(A[rb], B[cb], acc[rb][cb]);
+            }
         }
         // Epilogue: lane holds voxels x0 + rb*16 + 4g + e of channel cb*16 + r16.
         if (row_ok) {
