@@ -117,3 +117,38 @@ def test_batch_stack_same_grid_and_graph_replay():
         side.synchronize()
         assert np.array_equal(_n(stack), ref), f"replay {rep}"
         del junk
+
+
+def test_plans_sharing_one_deferred_workspace():
+    """A modeling plan and an RTM plan made with defer_workspace=True refuse
+    to run before a workspace is bound; bound to one workspace sized for the
+    larger, run one after the other on one stream, they give the same traces
+    and stacked image as single-shot calls, bit for bit."""
+    rtm.rtm_set_tuning(rtm.RTM_OP_MODEL, 1, 18)
+    rtm.rtm_set_tuning(rtm.RTM_OP_RTM, 1, 18)
+    s = synth.config_small2d(nx=97, nz=45, nb=10, nt=150)
+    g = rtm.Grid.for_model(s.v_int, s.h, s.nb)
+    vp = rtm.rtm_rbc_pad(g, _t(s.v_int), s.seed, 0.0)
+    w = _t(s.wavelet)
+    srcs = [np.array([x, 0.0, 3.0]) for x in (12.0, 47.5, 80.25)]
+    traces = [torch.zeros((s.rec.shape[0], s.nt + 1), device=DEV) for _ in srcs]
+    stack = torch.zeros(g.interior_shape, device=DEV)
+    mp = rtm.BatchPlan(rtm.RTM_OP_MODEL, [rtm.BatchShot(g, vp, w, x, s.rec, traces_out=t)
+                                          for x, t in zip(srcs, traces)], s.dt, s.nt, defer_workspace=True)
+    rp = rtm.BatchPlan(rtm.RTM_OP_RTM, [rtm.BatchShot(g, vp, w, x, s.rec, traces_in=t, image=stack)
+                                        for x, t in zip(srcs, traces)], s.dt, s.nt, eps_rel=1e-3,
+                       flags=rtm.RTM_F_ACCUMULATE, defer_workspace=True)
+    assert mp.ws is None and rp.ws is None
+    with pytest.raises(RuntimeError):
+        mp.run()
+    ws = torch.empty(max(mp.ws_bytes, rp.ws_bytes), dtype=torch.uint8, device=DEV)
+    mp.bind_workspace(ws)
+    rp.bind_workspace(ws)
+    mp.run()
+    rp.run()
+    ref = torch.zeros(g.interior_shape, device=DEV)
+    for x, t in zip(srcs, traces):
+        d = rtm.rtm_model_shot(g, vp, s.dt, w, x, s.rec)
+        assert torch.equal(d, t)
+        ref += rtm.rtm_rtm_shot(g, vp, s.dt, w, x, s.rec, d, eps_rel=1e-3)["image"]
+    assert np.array_equal(_n(stack), _n(ref))
