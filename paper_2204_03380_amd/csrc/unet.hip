@@ -78,6 +78,77 @@ struct ConvArgs {
 // blocks share each weight fragment and each activation fragment feeds CBW
 // MFMAs.  Every output element is the same sequence of MFMAs whatever CBW.
 // ---------------------------------------------------------------------------
+// The fused epilogue of a convolution for channels c0 .. c0 + 7 of voxel v
+// (val: the sums before bias): bias, ReLU, the float output y, the stored
+// bfloat16 value r, and out (plus the skip input), as 16-byte accesses.
+template <int COUT>
+__device__ __forceinline__ void epi_store8(const ConvArgs &a, int64_t v, int c0, float (&val)[8])
+{
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        val[j] += a.bias ? a.bias[c0 + j] : 0.f;
+        if (a.relu) val[j] = fmaxf(val[j], 0.f);
+    }
+    if (a.y) {
+        if (a.ych == COUT) {
+            float4 *py = reinterpret_cast<float4 *>(a.y + v * COUT + c0);
+            py[0] = make_float4(val[0], val[1], val[2], val[3]);
+            py[1] = make_float4(val[4], val[5], val[6], val[7]);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (c0 + j < a.ych) a.y[v * a.ych + c0 + j] = val[j];
+        }
+    }
+    const int64_t o = v * COUT + c0;
+    if (a.r) {
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = (uint32_t)f2bf(val[2 * q]) | ((uint32_t)f2bf(val[2 * q + 1]) << 16);
+        *reinterpret_cast<uint4 *>(a.r + o) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    if (a.out) {
+        float ov[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) ov[j] = val[j];
+        if (a.skip) {
+            const uint4 sk = *reinterpret_cast<const uint4 *>(a.skip + o);
+            const uint16_t *se = reinterpret_cast<const uint16_t *>(&sk);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) ov[j] = val[j] + bf2f(se[j]);
+        }
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) w[q] = (uint32_t)f2bf(ov[2 * q]) | ((uint32_t)f2bf(ov[2 * q + 1]) << 16);
+        *reinterpret_cast<uint4 *>(a.out + o) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
+// Stages rows 2*half, 2*half + 1 of a wavefront's MFMA accumulators for one
+// 16-channel block (lane (r16, g): voxels rb*16 + 4g + e of channel r16) in
+// its own LDS scratch of 32 voxels x kEpiStride floats, and returns the 8
+// channels 8*hh .. 8*hh + 7 of voxel vl = lane mod 32 (hh = lane / 32).
+constexpr int kEpiStride = 20;  // 16 channels per voxel row, padded to spread the banks, 16-byte aligned
+
+__device__ __forceinline__ void epi_transpose(float *scr, const f32x4 (&acc2)[2], int lane, float (&val)[8])
+{
+    const int r16 = lane & 15, g = lane >> 4, vl = lane & 31, hh = lane >> 5;
+#pragma unroll
+    for (int rbl = 0; rbl < 2; ++rbl)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) scr[(rbl * 16 + 4 * g + e) * kEpiStride + r16] = acc2[rbl][e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const float4 s0 = *reinterpret_cast<const float4 *>(scr + vl * kEpiStride + 8 * hh);
+    const float4 s1 = *reinterpret_cast<const float4 *>(scr + vl * kEpiStride + 8 * hh + 4);
+    val[0] = s0.x; val[1] = s0.y; val[2] = s0.z; val[3] = s0.w;
+    val[4] = s1.x; val[5] = s1.y; val[6] = s1.z; val[7] = s1.w;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();  // reads done before the scratch is written again
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int CIN, int COUT, int CBW = COUT / 16>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a)
 {
@@ -140,25 +211,20 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a)
             for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(A[rb], B[cb], acc[rb][cb]);
     }
 
-    // Epilogue: lane holds voxels vb + rb*16 + 4g + e of channel cbase + cb*16 + r16.
+    // Epilogue through the wavefront's LDS scratch (the MFMA layout would
+    // store two bytes per lane per voxel): 8 channels of one voxel per lane.
+    __shared__ __attribute__((aligned(16))) float escr[4][32 * kEpiStride];
+    float *scr = escr[threadIdx.x >> 6];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) {
-        const int co = cbase + cb * 16 + r16;
-        const float bias = a.bias ? a.bias[co] : 0.f;
+    for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t v = vb + rb * 16 + 4 * g + e;
-                if (v >= a.nvox) continue;
-                float val = acc[rb][cb][e] + bias;
-                if (a.relu) val = fmaxf(val, 0.f);
-                if (a.y && co < a.ych) a.y[v * a.ych + co] = val;
-                const int64_t o = v * COUT + co;
-                if (a.r) a.r[o] = f2bf(val);
-                if (a.out) a.out[o] = f2bf(a.skip ? val + bf2f(a.skip[o]) : val);
-            }
-    }
+        for (int half = 0; half < 2; ++half) {
+            const f32x4 acc2[2] = {acc[2 * half][cb], acc[2 * half + 1][cb]};
+            float val[8];
+            epi_transpose(scr, acc2, lane, val);
+            const int64_t v = vb + half * 32 + (lane & 31);
+            if (v < a.nvox) epi_store8<COUT>(a, v, cbase + cb * 16 + 8 * (lane >> 5), val);
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -336,30 +402,22 @@ __global__ __launch_bounds__(256) void conv_fwd_lds_kernel(ConvArgs a, int tiles
                     for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(A[rb], B[cb], acc[rb][cb]);
             }
         }
-        // Epilogue: lane holds voxels x0 + rb*16 + 4g + e of channel cb*16 + r16.
-        if (row_ok) {
-            const int64_t vrow = ((nbase + z) * a.h + yw) * (int64_t)a.w;
+        // Epilogue through LDS (the slot of plane z - 1, free once every wave
+        // is past its MFMAs): 8 channels of one voxel per lane.
+        __syncthreads();  // every wave is done with plane z - 1's slot
+        float *scr = reinterpret_cast<float *>(ring + ((z + 2) % 3) * T::PLANE) + wave * (32 * kEpiStride);
+        const int64_t vrow = ((nbase + z) * a.h + yw) * (int64_t)a.w;
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) {
-                const int co = cb * 16 + r16;
-                const float bias = a.bias ? a.bias[co] : 0.f;
+        for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-                for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int xo = x0 + rb * 16 + 4 * g + e;
-                        if (xo >= a.w) continue;
-                        const int64_t v = vrow + xo;
-                        float val = acc[rb][cb][e] + bias;
-                        if (a.relu) val = fmaxf(val, 0.f);
-                        if (a.y && co < a.ych) a.y[v * a.ych + co] = val;
-                        const int64_t o = v * COUT + co;
-                        if (a.r) a.r[o] = f2bf(val);
-                        if (a.out) a.out[o] = f2bf(a.skip ? val + bf2f(a.skip[o]) : val);
-                    }
+            for (int half = 0; half < 2; ++half) {
+                const f32x4 acc2[2] = {acc[2 * half][cb], acc[2 * half + 1][cb]};
+                float val[8];
+                epi_transpose(scr, acc2, lane, val);
+                const int xo = x0 + half * 32 + (lane & 31);
+                if (row_ok && xo < a.w) epi_store8<COUT>(a, vrow + xo, cb * 16 + 8 * (lane >> 5), val);
             }
-        }
-        __syncthreads();  // every wave is done with plane z - 1's slot before it is refilled
+        __syncthreads();  // every wave is done with its scratch before the slot is refilled
     }
 }
 
