@@ -52,6 +52,18 @@ typedef struct {
  * Either output may be NULL. */
 int unet_weight_pack(const unet_conv_desc_t *desc, const float *w, uint16_t *w_fwd, uint16_t *w_bwd, void *stream);
 
+/* One layer of unet_weight_pack_many. */
+typedef struct {
+    const float *w;
+    int32_t cin, cout;
+    uint16_t *w_fwd, *w_bwd;
+} unet_pack_item_t;
+
+/* unet_weight_pack for `count` layers (1 .. UNET_PACK_MAX, host array) in
+ * one launch: the same bits as one call per layer. */
+#define UNET_PACK_MAX 16
+int unet_weight_pack_many(int32_t count, const unet_pack_item_t *items, void *stream);
+
 /* Forward convolution on bfloat16 operands with float32 accumulation
  * (MFMA), plus a fused epilogue.  For each output (p, o) with o < y_channels
  * (for y) or o < Cout (for r and out):
@@ -73,6 +85,14 @@ int unet_conv3d_fwd(const unet_conv_desc_t *desc, const uint16_t *x, const uint1
  * (16, 1) pair also dx. */
 int unet_conv3d_dgrad(const unet_conv_desc_t *desc, const uint16_t *dy, const uint16_t *w_bwd, float *dx,
                       void *stream);
+
+/* unet_conv3d_dgrad, and in the same pass the gradient through the ReLU of
+ * the layer below, whose stored output is `mask` (bfloat16 [..][Cin]):
+ *     g_out[q, i] = bf16(dx[q, i]) if mask[q, i] > 0, else 0
+ * (bfloat16 [..][Cin]; what unet_relu_grad gives for g1 = dx alone, bit for
+ * bit).  mask and g_out 16-byte aligned, Cin a multiple of 8. */
+int unet_conv3d_dgrad_relu(const unet_conv_desc_t *desc, const uint16_t *dy, const uint16_t *w_bwd, float *dx,
+                           const uint16_t *mask, uint16_t *g_out, void *stream);
 
 /* Workspace of unet_conv3d_wgrad in bytes (host only, no device work). */
 int unet_wgrad_ws_bytes(const unet_conv_desc_t *desc, size_t *bytes);
@@ -101,6 +121,13 @@ int unet_up2(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const uint16
  * of g_fine (N, 2D, 2H, 2W, C); float32. */
 int unet_up2_bwd(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const float *g_fine, float *g_coarse,
                  void *stream);
+
+/* unet_up2_bwd, and in the same pass the gradient through the ReLU of the
+ * coarse level, whose stored output is `mask` (bfloat16, extents of
+ * g_coarse): g_out = bf16(g_coarse) where mask > 0, else 0 (what
+ * unet_relu_grad gives for g1 = g_coarse alone, bit for bit). */
+int unet_up2_bwd_relu(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const float *g_fine, float *g_coarse,
+                      const uint16_t *mask, uint16_t *g_out, void *stream);
 
 /* Gradient through a ReLU whose stored output is `mask` (bfloat16, same
  * extents (N, D, H, W, C)):

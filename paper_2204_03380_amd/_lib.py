@@ -34,8 +34,9 @@ EXPORTS = (
     "rtm_storage_shot", "rtm_model_shot_vjp", "rtm_batch_plan", "rtm_batch_run",
     "rtm_batch_free", "rtm_window_extract", "rtm_window_accumulate", "rtm_misfit_ws_bytes", "rtm_l2_misfit",
     "rtm_stream_copy", "rtm_rtm_shot_noalloc", "rtm_set_persist_wait", "rtm_get_persist_wait",
-    "unet_weight_pack", "unet_conv3d_fwd", "unet_conv3d_dgrad", "unet_wgrad_ws_bytes", "unet_conv3d_wgrad",
-    "unet_embed", "unet_pool2", "unet_up2", "unet_up2_bwd", "unet_relu_grad", "unet_mse_ws_bytes", "unet_mse",
+    "unet_weight_pack", "unet_weight_pack_many", "unet_conv3d_fwd", "unet_conv3d_dgrad", "unet_conv3d_dgrad_relu", "unet_wgrad_ws_bytes",
+    "unet_conv3d_wgrad", "unet_embed", "unet_pool2", "unet_up2", "unet_up2_bwd", "unet_up2_bwd_relu",
+    "unet_relu_grad", "unet_mse_ws_bytes", "unet_mse",
     "unet_adam", "unet_set_conv_lds", "unet_get_conv_lds",
 )
 
@@ -60,6 +61,14 @@ class RtmShotDesc(ctypes.Structure):
 class UnetConvDesc(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("d", ctypes.c_int32), ("h", ctypes.c_int32), ("w", ctypes.c_int32),
                 ("cin", ctypes.c_int32), ("cout", ctypes.c_int32)]
+
+
+class UnetPackItem(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_void_p), ("cin", ctypes.c_int32), ("cout", ctypes.c_int32), ("w_fwd", ctypes.c_void_p),
+                ("w_bwd", ctypes.c_void_p)]
+
+
+UNET_PACK_MAX = 16
 
 
 class RtmRbcOpts(ctypes.Structure):
@@ -132,14 +141,17 @@ def load():
         "rtm_get_persist_wait": ([ctypes.POINTER(D)], ctypes.c_int),
         "rtm_rtm_shot_noalloc": ([G, P, D, I32, P, P, I32, P, P, F, P, P, P, U32, P], ctypes.c_int),
         "unet_weight_pack": ([C, P, P, P, P], ctypes.c_int),
+        "unet_weight_pack_many": ([ctypes.c_int32, ctypes.POINTER(UnetPackItem), P], ctypes.c_int),
         "unet_conv3d_fwd": ([C, P, P, P, I32, P, P, I32, P, P, P], ctypes.c_int),
         "unet_conv3d_dgrad": ([C, P, P, P, P], ctypes.c_int),
+        "unet_conv3d_dgrad_relu": ([C, P, P, P, P, P, P], ctypes.c_int),
         "unet_wgrad_ws_bytes": ([C, ctypes.POINTER(SZ)], ctypes.c_int),
         "unet_conv3d_wgrad": ([C, P, P, P, P, P, SZ, P], ctypes.c_int),
         "unet_embed": ([I64, I32, P, F, P, P], ctypes.c_int),
         "unet_pool2": ([I32] * 5 + [P, P, P], ctypes.c_int),
         "unet_up2": ([I32] * 5 + [P, P, P], ctypes.c_int),
         "unet_up2_bwd": ([I32] * 5 + [P, P, P], ctypes.c_int),
+        "unet_up2_bwd_relu": ([I32] * 5 + [P, P, P, P, P], ctypes.c_int),
         "unet_relu_grad": ([I32] * 5 + [P, P, P, P, P, P], ctypes.c_int),
         "unet_mse_ws_bytes": ([I64, ctypes.POINTER(SZ)], ctypes.c_int),
         "unet_mse": ([I64, I32, P, P, P, P, P, ctypes.POINTER(D), P, SZ, P], ctypes.c_int),

@@ -63,6 +63,8 @@ struct ConvArgs {
     float *y;
     uint16_t *r;
     uint16_t *out;
+    const uint16_t *mask;  // with gout: gout = bf16(y) where mask > 0, else 0 (a ReLU gradient)
+    uint16_t *gout;
     int64_t nvox;
     int d, h, w;
     int relu;
@@ -101,6 +103,16 @@ __device__ __forceinline__ void epi_store8(const ConvArgs &a, int64_t v, int c0,
         }
     }
     const int64_t o = v * COUT + c0;
+    if (a.gout) {  // the next layer's ReLU gradient (a.ych == COUT)
+        const uint4 mk = *reinterpret_cast<const uint4 *>(a.mask + o);
+        const uint16_t *me = reinterpret_cast<const uint16_t *>(&mk);
+        uint32_t w[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            w[q] = (uint32_t)(bf2f(me[2 * q]) > 0.f ? f2bf(val[2 * q]) : (uint16_t)0) |
+                   ((uint32_t)(bf2f(me[2 * q + 1]) > 0.f ? f2bf(val[2 * q + 1]) : (uint16_t)0) << 16);
+        *reinterpret_cast<uint4 *>(a.gout + o) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
     if (a.r) {
         uint32_t w[4];
 #pragma unroll
@@ -911,6 +923,23 @@ __global__ __launch_bounds__(256) void conv_thin_in_kernel(ConvArgs a)
         pr[0] = make_uint4(rb[0], rb[1], rb[2], rb[3]);
         pr[1] = make_uint4(rb[4], rb[5], rb[6], rb[7]);
     }
+    if (a.gout) {  // the next layer's ReLU gradient
+        const uint4 *pm = reinterpret_cast<const uint4 *>(a.mask + v * kThin);
+        const uint4 m0 = pm[0], m1 = pm[1];
+        const uint16_t *me0 = reinterpret_cast<const uint16_t *>(&m0);
+        const uint16_t *me1 = reinterpret_cast<const uint16_t *>(&m1);
+        uint32_t gb[kThin / 2];
+#pragma unroll
+        for (int q = 0; q < kThin / 2; ++q) {
+            const uint16_t *me = q < 4 ? me0 : me1;
+            const int k = (2 * q) & 7;
+            gb[q] = (uint32_t)(bf2f(me[k]) > 0.f ? f2bf(val[2 * q]) : (uint16_t)0) |
+                    ((uint32_t)(bf2f(me[k + 1]) > 0.f ? f2bf(val[2 * q + 1]) : (uint16_t)0) << 16);
+        }
+        uint4 *pg = reinterpret_cast<uint4 *>(a.gout + v * kThin);
+        pg[0] = make_uint4(gb[0], gb[1], gb[2], gb[3]);
+        pg[1] = make_uint4(gb[4], gb[5], gb[6], gb[7]);
+    }
     if (a.out) {
         uint4 *po = reinterpret_cast<uint4 *>(a.out + v * kThin);
         po[0] = make_uint4(ob[0], ob[1], ob[2], ob[3]);
@@ -1103,6 +1132,30 @@ __global__ void weight_pack_kernel(const float *__restrict__ w, int cin, int cou
     if (wb) wb[(int64_t)ci * 27 * cout + (int64_t)(26 - t) * cout + co] = b;
 }
 
+// weight_pack_kernel over several layers: element i of the concatenation
+// of their weights (start[k] the first element of layer k).
+struct PackSet {
+    unet_pack_item_t item[UNET_PACK_MAX];
+    int64_t start[UNET_PACK_MAX + 1];
+    int count;
+};
+
+__global__ void weight_pack_many_kernel(PackSet P)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.start[P.count]) return;
+    int k = 0;
+    while (i >= P.start[k + 1]) ++k;
+    const unet_pack_item_t &L = P.item[k];
+    const int64_t j = i - P.start[k];
+    const int ci = (int)(j % L.cin);
+    const int t = (int)((j / L.cin) % 27);
+    const int co = (int)(j / (27 * (int64_t)L.cin));
+    const uint16_t b = f2bf(L.w[j]);
+    if (L.w_fwd) L.w_fwd[j] = b;
+    if (L.w_bwd) L.w_bwd[(int64_t)ci * 27 * L.cout + (int64_t)(26 - t) * L.cout + co] = b;
+}
+
 __global__ void embed_kernel(int64_t nvox, int ch, const float *__restrict__ img, float scale,
                              uint16_t *__restrict__ x)
 {
@@ -1188,7 +1241,7 @@ __global__ void up2_kernel(int n, int d, int h, int w, int c, const uint16_t *__
 // arithmetic when it fits.
 template <int VEC>
 __global__ void up2_bwd_kernel(int n, int d, int h, int w, int c, const float *__restrict__ gf,
-                               float *__restrict__ gc)
+                               float *__restrict__ gc, const uint16_t *__restrict__ mask, uint16_t *__restrict__ gout)
 {
     const int64_t total = (int64_t)n * d * h * w * c;
     const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * VEC;
@@ -1207,6 +1260,9 @@ __global__ void up2_bwd_kernel(int n, int d, int h, int w, int c, const float *_
     }
 #pragma unroll
     for (int e = 0; e < VEC; ++e) gc[i0 + e] = s[e];
+    if (gout)  // the ReLU gradient of the coarse level
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) gout[i0 + e] = bf2f(mask[i0 + e]) > 0.f ? f2bf(s[e]) : (uint16_t)0;
 }
 
 // VEC consecutive channels of one voxel per thread (VEC divides c); the
@@ -1588,6 +1644,24 @@ int unet_weight_pack(const unet_conv_desc_t *desc, const float *w, uint16_t *w_f
     return RTM_OK;
 }
 
+int unet_weight_pack_many(int32_t count, const unet_pack_item_t *items, void *stream)
+{
+    rtm::clear_error();
+    if (count < 1 || count > UNET_PACK_MAX || !items) return bad("count must be in [1, UNET_PACK_MAX], items non-NULL");
+    PackSet P{};
+    P.count = count;
+    P.start[0] = 0;
+    for (int k = 0; k < count; ++k) {
+        const unet_pack_item_t &L = items[k];
+        if (!L.w || L.cin < 1 || L.cout < 1) return bad("each item needs w and positive channel counts");
+        P.item[k] = L;
+        P.start[k + 1] = P.start[k] + (int64_t)L.cout * 27 * L.cin;
+    }
+    hipLaunchKernelGGL(weight_pack_many_kernel, grid1(P.start[count]), dim3(256), 0, (hipStream_t)stream, P);
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
 int unet_conv3d_fwd(const unet_conv_desc_t *desc, const uint16_t *x, const uint16_t *w_fwd, const float *bias,
                     int32_t relu, const uint16_t *skip, float *y, int32_t y_channels, uint16_t *r, uint16_t *out,
                     void *stream)
@@ -1636,18 +1710,23 @@ int unet_get_conv_lds(int32_t *lds)
     return RTM_OK;
 }
 
-int unet_conv3d_dgrad(const unet_conv_desc_t *desc, const uint16_t *dy, const uint16_t *w_bwd, float *dx,
-                      void *stream)
+static int dgrad_impl(const unet_conv_desc_t *desc, const uint16_t *dy, const uint16_t *w_bwd, float *dx,
+                      const uint16_t *mask, uint16_t *g_out, void *stream)
 {
     rtm::clear_error();
     if (int e = check_desc(desc)) return e;
     if (!dy || !w_bwd || !dx) return bad("dy, w_bwd and dx are required");
     if (!aligned16(dy) || !aligned16(w_bwd)) return bad("dy and w_bwd must be 16-byte aligned");
     if (desc->cout == 1 && !aligned16(dx)) return bad("for the (16, 1) pair dx must be 16-byte aligned");
+    if ((mask != nullptr) != (g_out != nullptr)) return bad("mask and g_out go together");
+    if (mask && (!aligned16(mask) || !aligned16(g_out) || desc->cin % 8 != 0))
+        return bad("mask and g_out must be 16-byte aligned, with a multiple of 8 input channels");
     ConvArgs a{};
     a.x = dy;
     a.wt = w_bwd;
     a.y = dx;
+    a.mask = mask;
+    a.gout = g_out;
     a.nvox = (int64_t)desc->n * desc->d * desc->h * desc->w;
     a.d = desc->d;
     a.h = desc->h;
@@ -1656,6 +1735,22 @@ int unet_conv3d_dgrad(const unet_conv_desc_t *desc, const uint16_t *dy, const ui
     if (launch_fwd(desc->cout, desc->cin, a, (hipStream_t)stream)) return bad("unsupported channel pair");
     UNET_HIP(hipGetLastError());
     return RTM_OK;
+}
+
+int unet_conv3d_dgrad(const unet_conv_desc_t *desc, const uint16_t *dy, const uint16_t *w_bwd, float *dx,
+                      void *stream)
+{
+    return dgrad_impl(desc, dy, w_bwd, dx, nullptr, nullptr, stream);
+}
+
+int unet_conv3d_dgrad_relu(const unet_conv_desc_t *desc, const uint16_t *dy, const uint16_t *w_bwd, float *dx,
+                           const uint16_t *mask, uint16_t *g_out, void *stream)
+{
+    if (!mask || !g_out) {
+        rtm::clear_error();
+        return bad("mask and g_out are required");
+    }
+    return dgrad_impl(desc, dy, w_bwd, dx, mask, g_out, stream);
 }
 
 int unet_wgrad_ws_bytes(const unet_conv_desc_t *desc, size_t *bytes)
@@ -1776,20 +1871,36 @@ int unet_up2(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const uint16
     return RTM_OK;
 }
 
-int unet_up2_bwd(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const float *g_fine, float *g_coarse,
-                 void *stream)
+static int up2_bwd_impl(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const float *g_fine, float *g_coarse,
+                        const uint16_t *mask, uint16_t *g_out, void *stream)
 {
     rtm::clear_error();
     if (n < 1 || d < 1 || h < 1 || w < 1 || c < 1 || !g_fine || !g_coarse) return bad("invalid up2_bwd arguments");
     const int64_t total = (int64_t)n * d * h * w * c;
     if (c % 4 == 0)
         hipLaunchKernelGGL(up2_bwd_kernel<4>, grid1(total / 4), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c,
-                           g_fine, g_coarse);
+                           g_fine, g_coarse, mask, g_out);
     else
         hipLaunchKernelGGL(up2_bwd_kernel<1>, grid1(total), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c, g_fine,
-                           g_coarse);
+                           g_coarse, mask, g_out);
     UNET_HIP(hipGetLastError());
     return RTM_OK;
+}
+
+int unet_up2_bwd(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const float *g_fine, float *g_coarse,
+                 void *stream)
+{
+    return up2_bwd_impl(n, d, h, w, c, g_fine, g_coarse, nullptr, nullptr, stream);
+}
+
+int unet_up2_bwd_relu(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const float *g_fine, float *g_coarse,
+                      const uint16_t *mask, uint16_t *g_out, void *stream)
+{
+    if (!mask || !g_out) {
+        rtm::clear_error();
+        return bad("mask and g_out are required");
+    }
+    return up2_bwd_impl(n, d, h, w, c, g_fine, g_coarse, mask, g_out, stream);
 }
 
 int unet_relu_grad(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const float *g1, const float *g2,

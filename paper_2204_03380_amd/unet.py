@@ -57,6 +57,15 @@ def weight_pack(w, cin, cout, w_fwd, w_bwd):
                                   _st()))
 
 
+def weight_pack_many(layers):
+    """weight_pack for [(w, cin, cout, w_fwd, w_bwd), ...] in one launch."""
+    from ._lib import UnetPackItem
+    items = (UnetPackItem * len(layers))()
+    for it, (w, cin, cout, wf, wb) in zip(items, layers):
+        it.w, it.cin, it.cout, it.w_fwd, it.w_bwd = _ptr(w), cin, cout, _ptr(wf), _ptr(wb)
+    check(load().unet_weight_pack_many(len(layers), items, _st()))
+
+
 def conv3d_fwd(shape, cin, cout, x, w_fwd, bias=None, relu=False, skip=None, y=None, y_channels=None, r=None,
                out=None):
     ych = (y_channels or cout) if y is not None else 0
@@ -64,8 +73,14 @@ def conv3d_fwd(shape, cin, cout, x, w_fwd, bias=None, relu=False, skip=None, y=N
                                  _ptr(skip), _ptr(y), ych, _ptr(r), _ptr(out), _st()))
 
 
-def conv3d_dgrad(shape, cin, cout, dy, w_bwd, dx):
-    check(load().unet_conv3d_dgrad(ctypes.byref(_desc(shape, cin, cout)), _ptr(dy), _ptr(w_bwd), _ptr(dx), _st()))
+def conv3d_dgrad(shape, cin, cout, dy, w_bwd, dx, mask=None, g_out=None):
+    """Input gradient dx; with mask (the layer below's stored ReLU output)
+    also g_out, the gradient through that ReLU, in the same pass."""
+    if mask is None and g_out is None:
+        check(load().unet_conv3d_dgrad(ctypes.byref(_desc(shape, cin, cout)), _ptr(dy), _ptr(w_bwd), _ptr(dx), _st()))
+    else:
+        check(load().unet_conv3d_dgrad_relu(ctypes.byref(_desc(shape, cin, cout)), _ptr(dy), _ptr(w_bwd), _ptr(dx),
+                                            _ptr(mask), _ptr(g_out), _st()))
 
 
 def wgrad_ws_bytes(shape, cin, cout):
@@ -91,8 +106,13 @@ def up2(shape, c, x, y):
     check(load().unet_up2(*shape, c, _ptr(x), _ptr(y), _st()))
 
 
-def up2_bwd(shape, c, g_fine, g_coarse):
-    check(load().unet_up2_bwd(*shape, c, _ptr(g_fine), _ptr(g_coarse), _st()))
+def up2_bwd(shape, c, g_fine, g_coarse, mask=None, g_out=None):
+    """Adjoint of up2; with mask (the coarse level's stored ReLU output) also
+    g_out, the gradient through that ReLU, in the same pass."""
+    if mask is None and g_out is None:
+        check(load().unet_up2_bwd(*shape, c, _ptr(g_fine), _ptr(g_coarse), _st()))
+    else:
+        check(load().unet_up2_bwd_relu(*shape, c, _ptr(g_fine), _ptr(g_coarse), _ptr(mask), _ptr(g_out), _st()))
 
 
 def relu_grad(shape, c, g1, g2, g_pool, mask, out):
@@ -213,8 +233,8 @@ class UNet:
         return self.get_params(self.g)
 
     def _pack(self):
-        for name, ci, co in LAYERS:
-            weight_pack(self.view(self.p, name + ".w"), ci, co, self.wf[name], self.wb[name])
+        weight_pack_many([(self.view(self.p, name + ".w"), ci, co, self.wf[name], self.wb[name])
+                          for name, ci, co in LAYERS])
 
     # -- buffers ------------------------------------------------------------
     def _buffers(self, shape):
@@ -285,22 +305,20 @@ class UNet:
         G = lambda k: self.view(self.g, k)  # noqa: E731
         ws = self._ws
 
-        def layer(name, k, ci, co, x, gp, gx=None):
+        def layer(name, k, ci, co, x, gp, gx=None, mask=None, g_out=None):
             conv3d_wgrad(s[k], ci, co, x, gp, G(name + ".w"), G(name + ".b"), ws)
             if gx is not None:
-                conv3d_dgrad(s[k], ci, co, gp, self.wb[name], gx)
+                conv3d_dgrad(s[k], ci, co, gp, self.wb[name], gx, mask, g_out)
 
-        layer("c8", 0, 16, 1, t["d1"], t["gy8"], t["g_d1"])
-        relu_grad(s[0], 16, t["g_d1"], None, None, t["r7"], t["gp7"])
+        # the ReLU gradients that take one input are fused into the pass
+        # that produces it (the input gradient of c8, the upsampling adjoints)
+        layer("c8", 0, 16, 1, t["d1"], t["gy8"], t["g_d1"], t["r7"], t["gp7"])
         layer("c7", 0, 32, 16, t["u2"], t["gp7"], t["g_u2"])
-        up2_bwd(s[1], 32, t["g_u2"], t["g_d2"])
-        relu_grad(s[1], 32, t["g_d2"], None, None, t["r6"], t["gp6"])
+        up2_bwd(s[1], 32, t["g_u2"], t["g_d2"], t["r6"], t["gp6"])
         layer("c6", 1, 64, 32, t["u3"], t["gp6"], t["g_u3"])
-        up2_bwd(s[2], 64, t["g_u3"], t["g_d3"])
-        relu_grad(s[2], 64, t["g_d3"], None, None, t["r5"], t["gp5"])
+        up2_bwd(s[2], 64, t["g_u3"], t["g_d3"], t["r5"], t["gp5"])
         layer("c5", 2, 128, 64, t["u4"], t["gp5"], t["g_u4"])
-        up2_bwd(s[3], 128, t["g_u4"], t["g_e4"])
-        relu_grad(s[3], 128, t["g_e4"], None, None, t["e4"], t["gp4"])
+        up2_bwd(s[3], 128, t["g_u4"], t["g_e4"], t["e4"], t["gp4"])
         layer("c4", 3, 64, 128, t["p3"], t["gp4"], t["g_p3"])
         relu_grad(s[2], 64, t["g_d3"], None, t["g_p3"], t["e3"], t["gp3"])
         layer("c3", 2, 32, 64, t["p2"], t["gp3"], t["g_p2"])

@@ -358,3 +358,63 @@ def test_lds_staged_convolution_equals_direct(ci, co):
     e = rel_l2(host(y0), ref)
     print(f"LDS conv {ci}->{co} {shape}: equal to the direct kernel; forward vs oracle {e:.2e}")
     assert e < 1e-5
+
+
+@pytest.mark.parametrize("ci,co,shape", [(16, 1, (2, 9, 7, 70)), (16, 32, (2, 67, 31, 131)), (64, 128, (1, 6, 5, 9)),
+                                         (32, 64, (2, 7, 6, 11))])
+def test_dgrad_with_fused_relu_gradient(ci, co, shape):
+    """The input gradient with the layer below's ReLU gradient fused in
+    (one-channel, LDS-staged and direct kernels): dx equals the plain input
+    gradient and g_out equals unet_relu_grad of that dx, bit for bit."""
+    rng, x, wo, b = _operands(shape, ci, co, 5 + ci + co)
+    _, wb = pack(wo)
+    nv = x.shape[0]
+    dy = bf_tensor(U.bf16(rng.standard_normal((nv, co))))
+    mask = bf_tensor(U.bf16(np.maximum(rng.standard_normal((nv, ci)), 0)))
+    dx0 = torch.empty((nv, ci), dtype=torch.float32, device=DEV)
+    N.conv3d_dgrad(shape, ci, co, dy, wb, dx0)
+    g0 = torch.empty((nv, ci), dtype=torch.bfloat16, device=DEV)
+    N.relu_grad(shape, ci, dx0, None, None, mask, g0)
+    dx1 = torch.empty_like(dx0)
+    g1 = torch.empty_like(g0)
+    N.conv3d_dgrad(shape, ci, co, dy, wb, dx1, mask, g1)
+    assert torch.equal(dx1, dx0) and torch.equal(g1, g0)
+    assert bool((host(g1) != 0).any())
+
+
+@pytest.mark.parametrize("c", [32, 6])
+def test_up2_bwd_with_fused_relu_gradient(c):
+    """The upsampling adjoint with the coarse level's ReLU gradient fused in
+    equals up2_bwd followed by relu_grad, bit for bit (4 channels per thread
+    and 1)."""
+    rng = np.random.default_rng(c)
+    shape = (2, 3, 4, 5)
+    nc = int(np.prod(shape))
+    gf = f32(rng.standard_normal((nc * 8, c)).astype(np.float32))
+    mask = bf_tensor(U.bf16(np.maximum(rng.standard_normal((nc, c)), 0)))
+    gc0 = torch.empty((nc, c), dtype=torch.float32, device=DEV)
+    N.up2_bwd(shape, c, gf, gc0)
+    o0 = torch.empty((nc, c), dtype=torch.bfloat16, device=DEV)
+    N.relu_grad(shape, c, gc0, None, None, mask, o0)
+    gc1 = torch.empty_like(gc0)
+    o1 = torch.empty_like(o0)
+    N.up2_bwd(shape, c, gf, gc1, mask, o1)
+    assert torch.equal(gc1, gc0) and torch.equal(o1, o0)
+
+
+def test_weight_pack_many_equals_per_layer_packing():
+    """One launch for several layers packs the same bits as one call each."""
+    rng = np.random.default_rng(9)
+    layers = [(1, 16), (16, 32), (64, 128), (16, 1)]
+    singles, many = [], []
+    for ci, co in layers:
+        w = f32(rng.standard_normal((co, 27 * ci)).astype(np.float32))
+        a = (torch.empty((co, 27 * ci), dtype=torch.bfloat16, device=DEV),
+             torch.empty((ci, 27 * co), dtype=torch.bfloat16, device=DEV))
+        b = (torch.zeros_like(a[0]), torch.zeros_like(a[1]))
+        N.weight_pack(w, ci, co, *a)
+        singles.append(a)
+        many.append((w, ci, co) + b)
+    N.weight_pack_many(many)
+    for a, (_, _, _, bf, bb) in zip(singles, many):
+        assert torch.equal(a[0], bf) and torch.equal(a[1], bb)
