@@ -332,6 +332,25 @@ class UNet:
         adam(self.p, self.g, self.m, self.v, lr, b1, b2, eps, self.step_count)
         self._pack()
 
+    def capture_pass(self, img, target):
+        """A HIP graph of one forward (without the loss read-back) and
+        backward pass on these fixed input and target tensors: replaying it
+        does what forward(img, target, want_loss=False) and backward() do,
+        with one launch from the host instead of one per kernel.  step()
+        stays outside the graph (its bias correction depends on the step
+        count); replay, then step(), is one training step.  Buffers are
+        made by a first eager pass; the graph keeps reading the network's
+        parameter, packed-weight and activation tensors, which stay in place."""
+        self.forward(img, target, want_loss=False)
+        self.backward()
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            self.forward(img, target, want_loss=False)
+            self.backward()
+        torch.cuda.synchronize()
+        return graph
+
     def train_step(self, img, target, lr=1e-3):
         _, loss = self.forward(img, target)
         self.backward()

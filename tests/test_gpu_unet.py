@@ -418,3 +418,33 @@ def test_weight_pack_many_equals_per_layer_packing():
     N.weight_pack_many(many)
     for a, (_, _, _, bf, bb) in zip(singles, many):
         assert torch.equal(a[0], bf) and torch.equal(a[1], bb)
+
+
+def test_captured_pass_matches_eager_training():
+    """Three training steps as graph replay + step() give the same
+    parameters, bit for bit, as three eager steps from the same start, with
+    eager work and synchronisation between the replays."""
+    g = torch.Generator(device=DEV).manual_seed(3)
+    img = torch.randn((1, 16, 16, 16), device=DEV, generator=g)
+    tgt = img + 0.1 * torch.randn((1, 16, 16, 16), device=DEV, generator=g)
+    eager = N.UNet(seed=1)
+    graphed = N.UNet(seed=1)
+    # the identity start (zero output layer) gives zero gradients below it at
+    # step one; two eager steps first make every layer's gradient nonzero
+    for net in (eager, graphed):
+        for _ in range(2):
+            net.train_step(img, tgt, 1e-3)
+    graph = graphed.capture_pass(img, tgt)
+    for k in range(3):
+        eager.forward(img, tgt, want_loss=False)
+        eager.backward()
+        eager.step(1e-3)
+        junk = torch.randn(1 << 18, device=DEV).sum()  # eager work between replays
+        torch.cuda.synchronize()
+        graph.replay()
+        graphed.step(1e-3)
+        torch.cuda.synchronize()
+        assert torch.equal(graphed.p, eager.p), f"step {k}"
+        assert torch.equal(graphed.g, eager.g), f"step {k}"
+        del junk
+    assert bool((eager.g != 0).any())
