@@ -142,7 +142,7 @@ def cpu_baseline(survey, nt_sample, nt_one_thread=200):
                            "sample": f"same shot, {nt_one_thread} steps, {sec1:.1f} s on 1 thread"}}
 
 
-def unet_report(steps=10):
+def unet_report(steps=30):
     """Training step of the learned crosstalk filter on one 128^3 image
     (forward, backward, Adam) and each convolution's MFMA throughput."""
     import torch
@@ -152,7 +152,7 @@ def unet_report(steps=10):
     img = torch.randn((1, 128, 128, 128), device="cuda", generator=g)
     tgt = img + 0.1 * torch.randn((1, 128, 128, 128), device="cuda", generator=g)
     net = U.UNet(seed=0)
-    for _ in range(2):
+    for _ in range(3):
         net.train_step(img, tgt, 1e-4)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()

@@ -105,6 +105,32 @@ int unet_wgrad_ws_bytes(const unet_conv_desc_t *desc, size_t *bytes);
 int unet_conv3d_wgrad(const unet_conv_desc_t *desc, const uint16_t *x, const uint16_t *dy, float *dw, float *db,
                       void *ws, size_t ws_bytes, void *stream);
 
+/* unet_conv3d_wgrad in two halves, so that a training step can reduce the
+ * split-K partials of all its layers in one pass at the end of the backward
+ * pass instead of one pass per layer.
+ *
+ * unet_conv3d_wgrad_partial writes the partial sums of one layer into ws
+ * (same size and alignment rules as unet_conv3d_wgrad; one workspace per
+ * layer whose reduction is still pending).  unet_wgrad_reduce_many then
+ * reduces `count` layers (1 .. UNET_WGRAD_MAX, host array of items) in two
+ * launches: for each item, dw and db (db may be NULL) get the same bits
+ * unet_conv3d_wgrad would give for the same desc, x and dy.  An item's ws
+ * must hold that layer's partials (written on the same stream, or ordered
+ * before this call by the caller) and must not be shared with another item:
+ * the reduction keeps its chunk sums in ws. */
+int unet_conv3d_wgrad_partial(const unet_conv_desc_t *desc, const uint16_t *x, const uint16_t *dy, void *ws,
+                              size_t ws_bytes, void *stream);
+
+typedef struct {
+    unet_conv_desc_t desc;
+    void *ws;
+    size_t ws_bytes;
+    float *dw, *db;
+} unet_wgrad_item_t;
+
+#define UNET_WGRAD_MAX 16
+int unet_wgrad_reduce_many(int32_t count, const unet_wgrad_item_t *items, void *stream);
+
 /* Network input: x[v][c] = bf16(img[v] * scale) for c == 0, 0 for c > 0;
  * img float32 [nvox], x bfloat16 [nvox][channels]. */
 int unet_embed(int64_t nvox, int32_t channels, const float *img, float scale, uint16_t *x, void *stream);

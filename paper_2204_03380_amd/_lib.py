@@ -35,7 +35,7 @@ EXPORTS = (
     "rtm_batch_free", "rtm_window_extract", "rtm_window_accumulate", "rtm_misfit_ws_bytes", "rtm_l2_misfit",
     "rtm_stream_copy", "rtm_rtm_shot_noalloc", "rtm_set_persist_wait", "rtm_get_persist_wait",
     "unet_weight_pack", "unet_weight_pack_many", "unet_conv3d_fwd", "unet_conv3d_dgrad", "unet_conv3d_dgrad_relu", "unet_wgrad_ws_bytes",
-    "unet_conv3d_wgrad", "unet_embed", "unet_pool2", "unet_up2", "unet_up2_bwd", "unet_up2_bwd_relu",
+    "unet_conv3d_wgrad", "unet_conv3d_wgrad_partial", "unet_wgrad_reduce_many", "unet_embed", "unet_pool2", "unet_up2", "unet_up2_bwd", "unet_up2_bwd_relu",
     "unet_relu_grad", "unet_mse_ws_bytes", "unet_mse",
     "unet_adam", "unet_set_conv_lds", "unet_get_conv_lds",
 )
@@ -69,6 +69,14 @@ class UnetPackItem(ctypes.Structure):
 
 
 UNET_PACK_MAX = 16
+
+
+class UnetWgradItem(ctypes.Structure):
+    _fields_ = [("desc", UnetConvDesc), ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
+                ("dw", ctypes.c_void_p), ("db", ctypes.c_void_p)]
+
+
+UNET_WGRAD_MAX = 16
 
 
 class RtmRbcOpts(ctypes.Structure):
@@ -147,6 +155,8 @@ def load():
         "unet_conv3d_dgrad_relu": ([C, P, P, P, P, P, P], ctypes.c_int),
         "unet_wgrad_ws_bytes": ([C, ctypes.POINTER(SZ)], ctypes.c_int),
         "unet_conv3d_wgrad": ([C, P, P, P, P, P, SZ, P], ctypes.c_int),
+        "unet_conv3d_wgrad_partial": ([C, P, P, P, SZ, P], ctypes.c_int),
+        "unet_wgrad_reduce_many": ([ctypes.c_int32, ctypes.POINTER(UnetWgradItem), P], ctypes.c_int),
         "unet_embed": ([I64, I32, P, F, P, P], ctypes.c_int),
         "unet_pool2": ([I32] * 5 + [P, P, P], ctypes.c_int),
         "unet_up2": ([I32] * 5 + [P, P, P], ctypes.c_int),

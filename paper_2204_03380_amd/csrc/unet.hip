@@ -775,16 +775,18 @@ struct SumSet {
     int64_t n;
 };
 
-__global__ void sum_parts_kernel(SumSet s0, SumSet s1, int64_t P, int chunk)
+// One 256-thread block of the reduction: block column bx, chunk row by.
+__device__ __forceinline__ void sum_parts_block(const SumSet &s0, const SumSet &s1, int64_t P, int chunk,
+                                                int64_t bx, int64_t by)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t i = bx * blockDim.x + threadIdx.x;
     const bool first = i < s0.n;
     if (!first) i -= s0.n;
     const SumSet &S = first ? s0 : s1;
     if (i >= S.n) return;
     const int64_t n = S.n;
     const float *part = S.part;
-    const int64_t p0 = (int64_t)blockIdx.y * chunk;
+    const int64_t p0 = by * chunk;
     const int64_t p1 = p0 + chunk < P ? p0 + chunk : P;
     // eight loads in flight, then added in the same increasing order
     float s = 0.f;
@@ -797,7 +799,33 @@ __global__ void sum_parts_kernel(SumSet s0, SumSet s1, int64_t P, int chunk)
         for (int k = 0; k < 8; ++k) s += v[k];
     }
     for (; p < p1; ++p) s += part[p * n + i];
-    S.out[(int64_t)blockIdx.y * n + i] = s;
+    S.out[by * n + i] = s;
+}
+
+__global__ void sum_parts_kernel(SumSet s0, SumSet s1, int64_t P, int chunk)
+{
+    sum_parts_block(s0, s1, P, chunk, blockIdx.x, blockIdx.y);
+}
+
+// Several layers' reductions in one launch: layer k owns the flat block
+// range [start[k], start[k+1]), laid out as rows of bx[k] blocks, one row per
+// chunk.  Each block does what sum_parts_kernel's block (column, row) does
+// for that layer, so the sums are the same bits.
+struct SumMany {
+    SumSet w[UNET_WGRAD_MAX], b[UNET_WGRAD_MAX];
+    int64_t P[UNET_WGRAD_MAX];
+    int32_t chunk[UNET_WGRAD_MAX], bx[UNET_WGRAD_MAX];
+    int64_t start[UNET_WGRAD_MAX + 1];
+    int32_t count;
+};
+
+__global__ void sum_parts_many_kernel(SumMany m)
+{
+    const int64_t f = blockIdx.x;
+    int k = 0;
+    while (k + 1 < m.count && f >= m.start[k + 1]) ++k;
+    const int64_t local = f - m.start[k];
+    sum_parts_block(m.w[k], m.b[k], m.P[k], m.chunk[k], local % m.bx[k], local / m.bx[k]);
 }
 
 // Sums P partials of n0 and of n1 floats (n1 may be 0) through tmp0 / tmp1
@@ -1477,8 +1505,12 @@ int launch_fwd(int ci, int co, ConvArgs a, hipStream_t st)
 }
 
 // Row splits of the weight gradient: enough workgroups to fill the chip
-// (9 x splits, several per CU) while every group keeps >= 4 rows and the
-// partial sums stay within a fixed budget.
+// (9 x splits) while every group keeps >= 8 rows (16 with 128 input
+// channels) and the partial sums stay within a fixed budget.  Each split
+// writes a whole partial weight gradient, so on the coarse grids, where a
+// split covers a few hundred voxels, the partials are most of the traffic:
+// measured on the 16^3 and 32^3 levels, 8 and 16 rows beat 4 (and 16 rows
+// lose at 32 channels).
 constexpr int kWgMaxSplits = 512;
 constexpr int64_t kWgPartBudget = (int64_t)64 << 20;
 
@@ -1486,7 +1518,7 @@ template <int CI, int CO>
 int wg_splits(int64_t rows)
 {
     constexpr int RS = WgCfg<CI, CO>::RS;
-    int64_t s = rows / (4 * RS);
+    int64_t s = rows / ((CI >= 128 ? 16 : 8) * RS);
     const int64_t by_budget = kWgPartBudget / ((int64_t)RS * 27 * CI * CO * (int64_t)sizeof(float));
     if (s > by_budget) s = by_budget;
     if (s > kWgMaxSplits) s = kWgMaxSplits;
@@ -1532,10 +1564,13 @@ void thin_layout(const unet_conv_desc_t *d, int *nzb, int *nxs, int *ys)
 // Ring-staged weight gradient: MFMA pairs of <= 64 input channels on grids
 // of at least kRingMinVox voxels (the 64^3 and 128^3 levels of the
 // network).  Jobs: (n, z block, x segment, y range), enough of them for
-// about kRingBlocks blocks with every y range >= kRingMinRows rows, and the
-// partial sums within the weight-gradient budget.
+// about ring_blocks(cin) blocks with every y range >= kRingMinRows rows, and
+// the partial sums within the weight-gradient budget.  Measured: 16 input
+// channels (four-plane blocks of little work) want 512 blocks, 32 and 64
+// want 256 (fewer partials; 384 or 128 blocks split the y extent unevenly and
+// lose 30-90%).
 constexpr int64_t kRingMinVox = (int64_t)1 << 17;
-constexpr int64_t kRingBlocks = 512;
+int64_t ring_blocks(int cin) { return cin == 16 ? 512 : 256; }
 constexpr int kRingMinRows = 8;
 
 int ring_zb(int cin) { return cin <= 32 ? 4 : 2; }
@@ -1549,7 +1584,7 @@ bool ring_layout(const unet_conv_desc_t *d, int *nzb, int *nxs, int *ys)
     const int64_t cols = (int64_t)d->n * *nzb * *nxs, cbs = d->cout / 16;
     const int64_t per_part = (int64_t)27 * d->cin * d->cout * (int64_t)sizeof(float);
     if (cols * per_part > kWgPartBudget) return false;
-    int64_t y = (kRingBlocks + cols * cbs - 1) / (cols * cbs);
+    int64_t y = (ring_blocks(d->cin) + cols * cbs - 1) / (cols * cbs);
     if (y > d->h / kRingMinRows) y = d->h / kRingMinRows;
     if (y > kWgPartBudget / (cols * per_part)) y = kWgPartBudget / (cols * per_part);
     *ys = (int)(y < 1 ? 1 : y);
@@ -1625,6 +1660,91 @@ int check_resample(int n, int d, int h, int w, int c)
 {
     if (n < 1 || d < 1 || h < 1 || w < 1) return bad("extents must be >= 1");
     if (c < 8 || c % 8) return bad("channels must be a positive multiple of 8");
+    return RTM_OK;
+}
+
+// The parts of a weight-gradient workspace (layout at wg_bytes).
+struct WgWs {
+    float *part, *bpart, *tmp_w, *tmp_b;
+    int64_t parts, nw;
+    int S;
+};
+
+int wg_ws_split(const unet_conv_desc_t *desc, void *ws, size_t ws_bytes, WgWs *o)
+{
+    if (wg_layout(desc, &o->parts, &o->S)) return bad("unsupported channel pair");
+    if (!ws || ws_bytes < wg_bytes(desc, o->parts) || ((uintptr_t)ws & 255u))
+        return rtm::set_error(RTM_EWORKSPACE, "workspace missing, too small or not 256-byte aligned");
+    o->nw = (int64_t)desc->cout * 27 * desc->cin;
+    const int64_t q = (o->parts + kSumChunk - 1) / kSumChunk;
+    char *base = static_cast<char *>(ws);
+    o->part = reinterpret_cast<float *>(base);
+    base += rnd256(o->parts * o->nw * sizeof(float));
+    o->bpart = reinterpret_cast<float *>(base);
+    base += rnd256(o->parts * desc->cout * sizeof(float));
+    o->tmp_w = reinterpret_cast<float *>(base);
+    base += rnd256(q * o->nw * sizeof(float));
+    o->tmp_b = reinterpret_cast<float *>(base);
+    return RTM_OK;
+}
+
+// The split-K pass: one partial weight and bias gradient per part.
+void wg_partials(const unet_conv_desc_t *desc, const uint16_t *x, const uint16_t *dy, const WgWs &w, hipStream_t st)
+{
+    WgArgs a{};
+    a.x = x;
+    a.dy = dy;
+    a.part = w.part;
+    a.bpart = w.bpart;
+    a.rows = (int64_t)desc->n * desc->d * desc->h;
+    a.d = desc->d;
+    a.h = desc->h;
+    a.w = desc->w;
+    a.S = w.S;
+    int nzb, nxs, ys;
+    if (ring_layout(desc, &nzb, &nxs, &ys)) {
+        WrArgs r{};
+        r.x = x;
+        r.dy = dy;
+        r.part = a.part;
+        r.bpart = a.bpart;
+        r.d = desc->d;
+        r.h = desc->h;
+        r.w = desc->w;
+        r.cout = desc->cout;
+        r.nzb = nzb;
+        r.nxs = nxs;
+        r.ys = ys;
+        const dim3 grid((unsigned)w.S, (unsigned)(desc->cout / 16));
+        switch (desc->cin) {
+        case 16: hipLaunchKernelGGL((conv_wgrad_ring_kernel<16, 4>), grid, dim3(576), 0, st, r); break;
+        case 32: hipLaunchKernelGGL((conv_wgrad_ring_kernel<32, 4>), grid, dim3(576), 0, st, r); break;
+        default: hipLaunchKernelGGL((conv_wgrad_ring_kernel<64, 2>), grid, dim3(576), 0, st, r); break;
+        }
+    } else if (thin_pair(desc->cin, desc->cout)) {
+        WtArgs t{};
+        const bool in1 = desc->cin == 1;
+        t.w16 = in1 ? dy : x;
+        t.t1 = in1 ? x : dy;
+        t.part = a.part;
+        t.bpart = a.bpart;
+        t.d = desc->d;
+        t.h = desc->h;
+        t.w = desc->w;
+        thin_layout(desc, &t.nzb, &t.nxs, &t.ys);
+        if (in1)
+            hipLaunchKernelGGL(wgrad_thin_mfma_kernel<true>, dim3((unsigned)w.S), dim3(256), 0, st, t);
+        else
+            hipLaunchKernelGGL(wgrad_thin_mfma_kernel<false>, dim3((unsigned)w.S), dim3(256), 0, st, t);
+    } else
+        launch_wg(desc->cin, desc->cout, a, st);
+}
+
+int wg_check(const unet_conv_desc_t *desc, const uint16_t *x, const uint16_t *dy)
+{
+    if (int e = check_desc(desc)) return e;
+    if (!x || !dy) return bad("x and dy are required");
+    if (!aligned16(x) || !aligned16(dy)) return bad("x and dy must be 16-byte aligned");
     return RTM_OK;
 }
 
@@ -1765,76 +1885,69 @@ int unet_wgrad_ws_bytes(const unet_conv_desc_t *desc, size_t *bytes)
     return RTM_OK;
 }
 
+
 int unet_conv3d_wgrad(const unet_conv_desc_t *desc, const uint16_t *x, const uint16_t *dy, float *dw, float *db,
                       void *ws, size_t ws_bytes, void *stream)
 {
     rtm::clear_error();
-    if (int e = check_desc(desc)) return e;
-    if (!x || !dy || !dw) return bad("x, dy and dw are required");
-    if (!aligned16(x) || !aligned16(dy)) return bad("x and dy must be 16-byte aligned");
-    int64_t parts;
-    int S;
-    if (wg_layout(desc, &parts, &S)) return bad("unsupported channel pair");
-    if (!ws || ws_bytes < wg_bytes(desc, parts) || ((uintptr_t)ws & 255u))
-        return rtm::set_error(RTM_EWORKSPACE, "workspace missing, too small or not 256-byte aligned");
-    const int64_t nw = (int64_t)desc->cout * 27 * desc->cin;
-    WgArgs a{};
-    a.x = x;
-    a.dy = dy;
-    char *base = static_cast<char *>(ws);
-    const int64_t q = (parts + kSumChunk - 1) / kSumChunk;
-    a.part = reinterpret_cast<float *>(base);
-    base += rnd256(parts * nw * sizeof(float));
-    a.bpart = reinterpret_cast<float *>(base);
-    base += rnd256(parts * desc->cout * sizeof(float));
-    float *tmp_w = reinterpret_cast<float *>(base);
-    base += rnd256(q * nw * sizeof(float));
-    float *tmp_b = reinterpret_cast<float *>(base);
-    a.rows = (int64_t)desc->n * desc->d * desc->h;
-    a.d = desc->d;
-    a.h = desc->h;
-    a.w = desc->w;
-    a.S = S;
+    if (int e = wg_check(desc, x, dy)) return e;
+    if (!dw) return bad("dw is required");
+    WgWs w;
+    if (int e = wg_ws_split(desc, ws, ws_bytes, &w)) return e;
     hipStream_t st = (hipStream_t)stream;
-    int nzb, nxs, ys;
-    if (ring_layout(desc, &nzb, &nxs, &ys)) {
-        WrArgs r{};
-        r.x = x;
-        r.dy = dy;
-        r.part = a.part;
-        r.bpart = a.bpart;
-        r.d = desc->d;
-        r.h = desc->h;
-        r.w = desc->w;
-        r.cout = desc->cout;
-        r.nzb = nzb;
-        r.nxs = nxs;
-        r.ys = ys;
-        const dim3 grid((unsigned)S, (unsigned)(desc->cout / 16));
-        switch (desc->cin) {
-        case 16: hipLaunchKernelGGL((conv_wgrad_ring_kernel<16, 4>), grid, dim3(576), 0, st, r); break;
-        case 32: hipLaunchKernelGGL((conv_wgrad_ring_kernel<32, 4>), grid, dim3(576), 0, st, r); break;
-        case 64: hipLaunchKernelGGL((conv_wgrad_ring_kernel<64, 2>), grid, dim3(576), 0, st, r); break;
-        default: return bad("unsupported channel pair");
-        }
-    } else if (thin_pair(desc->cin, desc->cout)) {
-        WtArgs t{};
-        const bool in1 = desc->cin == 1;
-        t.w16 = in1 ? dy : x;
-        t.t1 = in1 ? x : dy;
-        t.part = a.part;
-        t.bpart = a.bpart;
-        t.d = desc->d;
-        t.h = desc->h;
-        t.w = desc->w;
-        thin_layout(desc, &t.nzb, &t.nxs, &t.ys);
-        if (in1)
-            hipLaunchKernelGGL(wgrad_thin_mfma_kernel<true>, dim3((unsigned)S), dim3(256), 0, st, t);
-        else
-            hipLaunchKernelGGL(wgrad_thin_mfma_kernel<false>, dim3((unsigned)S), dim3(256), 0, st, t);
-    } else
-        launch_wg(desc->cin, desc->cout, a, st);
-    UNET_HIP(sum_parts(a.part, nw, tmp_w, dw, a.bpart, db ? desc->cout : 0, tmp_b, db, parts, st));
+    wg_partials(desc, x, dy, w, st);
+    UNET_HIP(sum_parts(w.part, w.nw, w.tmp_w, dw, w.bpart, db ? desc->cout : 0, w.tmp_b, db, w.parts, st));
+    return RTM_OK;
+}
+
+int unet_conv3d_wgrad_partial(const unet_conv_desc_t *desc, const uint16_t *x, const uint16_t *dy, void *ws,
+                              size_t ws_bytes, void *stream)
+{
+    rtm::clear_error();
+    if (int e = wg_check(desc, x, dy)) return e;
+    WgWs w;
+    if (int e = wg_ws_split(desc, ws, ws_bytes, &w)) return e;
+    wg_partials(desc, x, dy, w, (hipStream_t)stream);
+    UNET_HIP(hipGetLastError());
+    return RTM_OK;
+}
+
+int unet_wgrad_reduce_many(int32_t count, const unet_wgrad_item_t *items, void *stream)
+{
+    rtm::clear_error();
+    if (count < 1 || count > UNET_WGRAD_MAX || !items)
+        return bad("count must be in [1, UNET_WGRAD_MAX], items non-NULL");
+    SumMany m1{}, m2{};
+    m1.count = m2.count = count;
+    for (int k = 0; k < count; ++k) {
+        const unet_wgrad_item_t &it = items[k];
+        if (int e = check_desc(&it.desc)) return e;
+        if (!it.dw) return bad("dw is required for every item");
+        WgWs w;
+        if (int e = wg_ws_split(&it.desc, it.ws, it.ws_bytes, &w)) return e;
+        const int64_t n1 = it.db ? it.desc.cout : 0;
+        const int64_t q = (w.parts + kSumChunk - 1) / kSumChunk;
+        const int32_t bx = (int32_t)((w.nw + n1 + 255) / 256);
+        // the two passes of sum_parts: chunks of kSumChunk partials, then
+        // the chunk sums
+        m1.w[k] = SumSet{w.part, w.tmp_w, w.nw};
+        m1.b[k] = SumSet{w.bpart, w.tmp_b, n1};
+        m1.P[k] = w.parts;
+        m1.chunk[k] = kSumChunk;
+        m1.bx[k] = bx;
+        m1.start[k + 1] = m1.start[k] + (int64_t)bx * q;
+        m2.w[k] = SumSet{w.tmp_w, it.dw, w.nw};
+        m2.b[k] = SumSet{w.tmp_b, it.db, n1};
+        m2.P[k] = q;
+        m2.chunk[k] = (int32_t)q;
+        m2.bx[k] = bx;
+        m2.start[k + 1] = m2.start[k] + bx;
+    }
+    if (m1.start[count] > 0x7fffffff) return bad("reduction too large for one launch");
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(sum_parts_many_kernel, dim3((unsigned)m1.start[count]), dim3(256), 0, st, m1);
+    hipLaunchKernelGGL(sum_parts_many_kernel, dim3((unsigned)m2.start[count]), dim3(256), 0, st, m2);
+    UNET_HIP(hipGetLastError());
     return RTM_OK;
 }
 

@@ -94,6 +94,24 @@ def conv3d_wgrad(shape, cin, cout, x, dy, dw, db, ws):
                                    _ptr(ws), ws.numel(), _st()))
 
 
+def conv3d_wgrad_partial(shape, cin, cout, x, dy, ws):
+    """The split-K pass of conv3d_wgrad: partial sums into ws, reduced later
+    by wgrad_reduce_many."""
+    check(load().unet_conv3d_wgrad_partial(ctypes.byref(_desc(shape, cin, cout)), _ptr(x), _ptr(dy), _ptr(ws),
+                                           ws.numel(), _st()))
+
+
+def wgrad_reduce_many(layers):
+    """Reduces [(shape, cin, cout, ws, dw, db), ...] (partials written by
+    conv3d_wgrad_partial) in two launches; dw and db get conv3d_wgrad's bits."""
+    from ._lib import UnetWgradItem
+    items = (UnetWgradItem * len(layers))()
+    for it, (shape, cin, cout, ws, dw, db) in zip(items, layers):
+        it.desc = _desc(shape, cin, cout)
+        it.ws, it.ws_bytes, it.dw, it.db = _ptr(ws), ws.numel(), _ptr(dw), _ptr(db)
+    check(load().unet_wgrad_reduce_many(len(layers), items, _st()))
+
+
 def embed(img, channels, scale, x):
     check(load().unet_embed(img.numel(), channels, _ptr(img), float(scale), _ptr(x), _st()))
 
@@ -259,8 +277,13 @@ class UNet:
                  g_d3=f32(2, 64), gp5=bf(2, 64), g_u4=f32(2, 128), g_e4=f32(3, 128), gp4=bf(3, 128),
                  g_p3=f32(3, 64), gp3=bf(2, 64), g_p2=f32(2, 32), gp2=bf(1, 32), g_p1=f32(1, 16), gp1=bf(0, 16))
         t["s"] = s
-        ws = max(wgrad_ws_bytes(s[k], ci, co) for k, ci, co in self._conv_levels())
-        self._ws = torch.empty(ws, dtype=torch.uint8, device=self.dev)
+        # one weight-gradient workspace per layer (256-byte aligned slices of
+        # one buffer): the partials of all layers wait for one reduction at
+        # the end of backward()
+        sizes = [(wgrad_ws_bytes(s[k], ci, co) + 255) // 256 * 256 for k, ci, co in self._conv_levels()]
+        self._ws = torch.empty(sum(sizes), dtype=torch.uint8, device=self.dev)
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        self._wg_ws = {name: self._ws[int(offs[i]):int(offs[i + 1])] for i, (name, _, _) in enumerate(LAYERS)}
         self._mse_ws = torch.empty(mse_ws_bytes(vox[0]), dtype=torch.uint8, device=self.dev)
         self._acts = _Acts(shape, t)
         return t
@@ -303,10 +326,10 @@ class UNet:
         t = self._acts.t
         s = t["s"]
         G = lambda k: self.view(self.g, k)  # noqa: E731
-        ws = self._ws
+        wsl = self._wg_ws
 
         def layer(name, k, ci, co, x, gp, gx=None, mask=None, g_out=None):
-            conv3d_wgrad(s[k], ci, co, x, gp, G(name + ".w"), G(name + ".b"), ws)
+            conv3d_wgrad_partial(s[k], ci, co, x, gp, wsl[name])
             if gx is not None:
                 conv3d_dgrad(s[k], ci, co, gp, self.wb[name], gx, mask, g_out)
 
@@ -326,6 +349,8 @@ class UNet:
         layer("c2", 1, 16, 32, t["p1"], t["gp2"], t["g_p1"])
         relu_grad(s[0], 16, t["g_d1"], None, t["g_p1"], t["e1"], t["gp1"])
         layer("c1", 0, 1, 16, t["x0"], t["gp1"])
+        wgrad_reduce_many([(s[k], ci, co, wsl[name], G(name + ".w"), G(name + ".b"))
+                           for (name, ci, co), (k, _, _) in zip(LAYERS, self._conv_levels())])
 
     def step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         self.step_count += 1

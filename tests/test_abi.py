@@ -244,6 +244,37 @@ def test_unet_channel_pairs_on_the_host():
     assert rc == _lib.RTM_OK and b == thin_bytes(4, 16)
 
 
+def test_wgrad_reduce_many_validation_on_the_host():
+    """The batched reduction rejects a count outside [1, UNET_WGRAD_MAX], a
+    missing item array or dw, an unsupported channel pair and a workspace
+    that is missing, short or misaligned, all before any launch (the
+    pointers below are never dereferenced)."""
+    lib = _lib.load()
+    sz = ctypes.c_size_t(0)
+    d = _lib.UnetConvDesc(1, 8, 8, 8, 16, 32)
+    assert lib.unet_wgrad_ws_bytes(ctypes.byref(d), ctypes.byref(sz)) == _lib.RTM_OK
+    need = sz.value
+
+    def call(count, **kw):
+        items = (_lib.UnetWgradItem * max(count, 1))()
+        for it in items:
+            it.desc = kw.get("desc", d)
+            it.ws, it.ws_bytes, it.dw, it.db = kw.get("ws", 4096), kw.get("ws_bytes", need), kw.get("dw", 8192), None
+        return lib.unet_wgrad_reduce_many(count, items, None)
+
+    assert call(0) == _lib.RTM_EINVAL
+    assert call(_lib.UNET_WGRAD_MAX + 1) == _lib.RTM_EINVAL
+    assert lib.unet_wgrad_reduce_many(1, None, None) == _lib.RTM_EINVAL
+    assert call(2, dw=None) == _lib.RTM_EINVAL
+    assert call(1, desc=_lib.UnetConvDesc(1, 8, 8, 8, 8, 16)) == _lib.RTM_EINVAL
+    for kw in ({"ws": None}, {"ws_bytes": need - 1}, {"ws": 4096 + 128}):
+        assert call(1, **kw) == _lib.RTM_EWORKSPACE, kw
+    assert "workspace" in lib.rtm_last_error().decode()
+    # the partial pass takes the same workspace rules
+    assert lib.unet_conv3d_wgrad_partial(ctypes.byref(d), 4096, 4096, 4096, need - 1, None) == _lib.RTM_EWORKSPACE
+    assert lib.unet_conv3d_wgrad_partial(ctypes.byref(d), None, 4096, 4096, need, None) == _lib.RTM_EINVAL
+
+
 def test_persistent_plan_validation_on_the_host():
     """RTM_F_PERSISTENT: refused with RTM_F_GRAPH and for 3-D shots at plan
     time (no device work; fake device addresses are never dereferenced);

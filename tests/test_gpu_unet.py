@@ -420,6 +420,39 @@ def test_weight_pack_many_equals_per_layer_packing():
         assert torch.equal(a[0], bf) and torch.equal(a[1], bb)
 
 
+def test_wgrad_partial_and_reduce_many_equal_per_layer_wgrad():
+    """The partial pass per layer plus one batched reduction gives the bits of
+    one conv3d_wgrad call per layer, for every partial layout: the
+    one-channel pairs on the matrix cores, the ring-staged pairs (64^3), the
+    plain split-K kernel on the coarse grids; one item without a bias."""
+    rng = np.random.default_rng(21)
+    cases = [((1, 64, 64, 64), 1, 16), ((1, 64, 64, 64), 16, 1), ((1, 64, 64, 64), 16, 32),
+             ((1, 64, 64, 64), 32, 16), ((1, 32, 32, 32), 64, 32), ((1, 16, 16, 16), 64, 128),
+             ((1, 16, 16, 16), 128, 64), ((2, 8, 12, 20), 32, 64)]
+    singles, items = [], []
+    for i, (shape, ci, co) in enumerate(cases):
+        nvox = int(np.prod(shape))
+        xt = bf_tensor(U.bf16(rng.standard_normal((nvox, ci)).astype(np.float32)))
+        dyt = bf_tensor(U.bf16(rng.standard_normal((nvox, co)).astype(np.float32)))
+        nb = N.wgrad_ws_bytes(shape, ci, co)
+        ws1 = torch.empty(nb, dtype=torch.uint8, device=DEV)
+        ws2 = torch.empty(nb, dtype=torch.uint8, device=DEV)
+        dw1 = torch.empty((co, 27, ci), dtype=torch.float32, device=DEV)
+        db1 = torch.empty(co, dtype=torch.float32, device=DEV)
+        N.conv3d_wgrad(shape, ci, co, xt, dyt, dw1, db1, ws1)
+        dw2 = torch.full_like(dw1, float("nan"))
+        db2 = None if i == 2 else torch.full_like(db1, float("nan"))
+        N.conv3d_wgrad_partial(shape, ci, co, xt, dyt, ws2)
+        singles.append((dw1, db1))
+        items.append((shape, ci, co, ws2, dw2, db2))
+    N.wgrad_reduce_many(items)
+    torch.cuda.synchronize()
+    for (dw1, db1), (shape, ci, co, _, dw2, db2) in zip(singles, items):
+        assert torch.equal(dw1, dw2), (shape, ci, co)
+        assert db2 is None or torch.equal(db1, db2), (shape, ci, co)
+        assert float(dw1.abs().max()) > 0
+
+
 def test_captured_pass_matches_eager_training():
     """Three training steps as graph replay + step() give the same
     parameters, bit for bit, as three eager steps from the same start, with
