@@ -186,8 +186,9 @@ int unet_adam(int64_t n, float *p, const float *g, float *m, float *v, double lr
 
 /* Kernel choice of unet_conv3d_fwd and unet_conv3d_dgrad, process-wide:
  * with lds = 1 (the default) convolutions of at most 32 input and 32
- * output channels on grids at least 64 voxels wide and large enough for 512
- * workgroups of 64 x 4 x (4 to 16) output voxels stage their input in LDS
+ * output channels, and of 64 input and 32 output channels, on grids at
+ * least 64 voxels wide and large enough for 256 workgroups of 64 x 4 x
+ * (4 to 16) output voxels stage their input in LDS
  * (one load per activation instead of one per tap); lds = 0 runs every
  * layer on the direct kernel.  Both compute each output element by the same sequence of
  * matrix-core operations, so results are equal bit for bit; the switch is

@@ -152,8 +152,9 @@ def mse(img, y, target, out, gy, channels, ws, want_loss=True):
 
 
 def set_conv_lds(on: bool) -> None:
-    """Forward and input-gradient convolutions of <= 32 input channels on
-    grids >= 64 voxels wide stage their input in LDS (default) or not."""
+    """Forward and input-gradient convolutions of <= 32 input and output
+    channels, and 64 -> 32, on grids >= 64 voxels wide stage their input in
+    LDS (default) or not."""
     check(load().unet_set_conv_lds(1 if on else 0))
 
 

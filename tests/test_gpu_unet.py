@@ -323,8 +323,9 @@ def test_layer_parity_at_training_size(name, ci, co, n):
 
 
 # Channel pairs the LDS-staged kernel takes (<= 32 input and output
-# channels), as forward layers or as the flipped input-gradient convolutions.
-LDS_PAIRS = ((16, 16), (16, 32), (32, 16), (32, 32))
+# channels, and 64 -> 32), as forward layers or as the flipped input-gradient
+# convolutions.
+LDS_PAIRS = ((16, 16), (16, 32), (32, 16), (32, 32), (64, 32))
 
 
 @pytest.mark.parametrize("ci,co", LDS_PAIRS)
