@@ -161,18 +161,31 @@ __device__ __forceinline__ void epi_transpose(float *scr, const f32x4 (&acc2)[2]
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int CIN, int COUT, int CBW = COUT / 16>
+// KS > 1 splits the reduction dimension over KS wavefronts of a workgroup
+// (the coarse grids, whose few wavefronts would each walk all 27*CIN/32
+// chunks one after another): wavefront part p takes chunks
+// [p*CPP, (p+1)*CPP), CPP = ceil(NCH/KS) (chunks past tap 26 are zero, as
+// in the padded last chunk); parts 1.. hand their sums to part 0 through
+// LDS, which adds them in increasing part order and runs the epilogue.
+template <int CIN, int COUT, int CBW = COUT / 16, int KS = 1>
 __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a)
 {
+    static_assert(KS == 1 || KS == 2 || KS == 4, "K split of 1, 2 or 4 wavefronts");
+    static_assert(KS == 1 || CBW <= 4, "the K-split hand-over holds at most four output blocks");
     constexpr int K = 27 * CIN;
     constexpr int KP = (K + 31) / 32 * 32;
+    constexpr int NCH = KP / 32;
     constexpr int CB = CBW;
     const int cbase = blockIdx.y * CBW * 16;
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int part = wave % KS;
     const int r16 = lane & 15, g = lane >> 4;
     const int64_t blk = xcd_block(blockIdx.x, a.nblocks);
-    const int64_t vb = (blk * 4 + (threadIdx.x >> 6)) * 64;
-    if (vb >= a.nvox) return;  // whole wavefront; the kernel has no barriers
+    const int64_t vb = (blk * (4 / KS) + wave / KS) * 64;
+    const bool live = vb < a.nvox;
+    if constexpr (KS == 1) {
+        if (!live) return;  // whole wavefront; without a K split the kernel has no barriers
+    }
 
     const int D = a.d, H = a.h, W = a.w;
     int vz[4], vy[4], vx[4];
@@ -198,35 +211,64 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(ConvArgs a)
     const uint4 zero = {0u, 0u, 0u, 0u};
     const int64_t HW = (int64_t)H * W;
     constexpr int UF = CB <= 2 ? 4 : 2;  // narrow waves keep more activation loads in flight
+    constexpr int CPP = (NCH + KS - 1) / KS;  // chunks per part
+    const int kc0 = part * CPP * 32;
+    if (live) {
 #pragma unroll UF
-    for (int kc = 0; kc < KP; kc += 32) {
-        const int kk = kc + 8 * g;
-        const int tap = kk / CIN;
-        const int ci0 = kk - tap * CIN;
-        const bool tv = tap < 27;
-        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-        const int64_t off = dz * HW + (int64_t)dy * W + dx;
-        uint4 A[4];
+        for (int j = 0; j < CPP; ++j) {
+            const int kc = kc0 + 32 * j;
+            const int kk = kc + 8 * g;
+            const int tap = kk / CIN;
+            const int ci0 = kk - tap * CIN;
+            const bool tv = tap < 27;
+            const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+            const int64_t off = dz * HW + (int64_t)dy * W + dx;
+            uint4 A[4];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) {
-            const bool ok = tv && vin[rb] && (unsigned)(vz[rb] + dz) < (unsigned)D &&
-                            (unsigned)(vy[rb] + dy) < (unsigned)H && (unsigned)(vx[rb] + dx) < (unsigned)W;
-            A[rb] = ok ? *reinterpret_cast<const uint4 *>(a.x + (vv[rb] + off) * CIN + ci0) : zero;
+            for (int rb = 0; rb < 4; ++rb) {
+                const bool ok = tv && vin[rb] && (unsigned)(vz[rb] + dz) < (unsigned)D &&
+                                (unsigned)(vy[rb] + dy) < (unsigned)H && (unsigned)(vx[rb] + dx) < (unsigned)W;
+                A[rb] = ok ? *reinterpret_cast<const uint4 *>(a.x + (vv[rb] + off) * CIN + ci0) : zero;
+            }
+            uint4 B[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+                B[cb] = tv ? *reinterpret_cast<const uint4 *>(a.wt + (int64_t)(cbase + cb * 16 + r16) * K + kk) : zero;
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(A[rb], B[cb], acc[rb][cb]);
         }
-        uint4 B[CB];
+    }
+
+    if constexpr (KS > 1) {
+        // [wavefront][accumulator element][lane]: each store and load is
+        // 64 consecutive floats
+        __shared__ float hand[4][16 * CB][64];
+        if (part > 0) {
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb)
-            B[cb] = tv ? *reinterpret_cast<const uint4 *>(a.wt + (int64_t)(cbase + cb * 16 + r16) * K + kk) : zero;
+            for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+                for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(A[rb], B[cb], acc[rb][cb]);
+                    for (int e = 0; e < 4; ++e) hand[wave][(rb * CB + cb) * 4 + e][lane] = acc[rb][cb][e];
+        }
+        __syncthreads();
+        if (part > 0 || !live) return;  // after the only barrier
+#pragma unroll
+        for (int p = 1; p < KS; ++p)
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) acc[rb][cb][e] += hand[wave + p][(rb * CB + cb) * 4 + e][lane];
     }
 
     // Epilogue through the wavefront's LDS scratch (the MFMA layout would
     // store two bytes per lane per voxel): 8 channels of one voxel per lane.
     __shared__ __attribute__((aligned(16))) float escr[4][32 * kEpiStride];
-    float *scr = escr[threadIdx.x >> 6];
+    float *scr = escr[wave];
 #pragma unroll
     for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
@@ -1441,6 +1483,23 @@ constexpr int64_t kLdsBlocks = 1024, kLdsMinBlocks = 256;
 // ways above (each split re-reads the activations once more).
 constexpr int64_t kFwdSplitWaves = 1024;
 
+// K split of the direct kernel on the two coarse tiers (below a quarter of
+// kFwdSplitWaves wavefronts, and below kFwdSplitWaves).  Measured on the
+// network's levels: four parts take the 16^3 level's forward and input
+// gradient from 0.038 and 0.058 ms to 0.015 and 0.019; the 32^3 level, with
+// twice as many wavefronts per CU already, gains nothing from two parts
+// and loses up to 40% with four.
+constexpr int kKsQuarter = 4, kKsHalf = 1;
+
+template <int CI, int CO, int CBW, int KS>
+void launch_direct(ConvArgs a, int64_t waves, hipStream_t st)
+{
+    const int64_t blocks = (waves * KS + 3) / 4;
+    a.nblocks = (blocks + kNumXcd - 1) / kNumXcd * kNumXcd;
+    hipLaunchKernelGGL((conv_fwd_kernel<CI, CO, CBW, KS>), dim3((unsigned)a.nblocks, CO / 16 / CBW), dim3(256), 0, st,
+                       a);
+}
+
 template <int CI, int CO>
 void launch_fwd_t(const ConvArgs &a, hipStream_t st)
 {
@@ -1467,11 +1526,11 @@ void launch_fwd_t(const ConvArgs &a, hipStream_t st)
     }
     const int64_t waves = (a.nvox + 63) / 64;
     if (CB > 1 && waves < kFwdSplitWaves / 4)
-        hipLaunchKernelGGL((conv_fwd_kernel<CI, CO, CBW4>), dim3((unsigned)a.nblocks, CB / CBW4), dim3(256), 0, st, a);
+        launch_direct<CI, CO, CBW4, kKsQuarter>(a, waves, st);
     else if (CB > 1 && waves < kFwdSplitWaves)
-        hipLaunchKernelGGL((conv_fwd_kernel<CI, CO, CBW2>), dim3((unsigned)a.nblocks, CB / CBW2), dim3(256), 0, st, a);
+        launch_direct<CI, CO, CBW2, kKsHalf>(a, waves, st);
     else
-        hipLaunchKernelGGL((conv_fwd_kernel<CI, CO>), dim3((unsigned)a.nblocks), dim3(256), 0, st, a);
+        launch_direct<CI, CO, CB, 1>(a, waves, st);
 }
 
 template <int CI>

@@ -15,16 +15,17 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.timeout(600)
 def test_filter_gain_over_plain_image_on_held_out_geometry():
-    """Three networks trained from different seeds (initial weights, sample
+    """Six networks trained from different seeds (initial weights, sample
     order, flips) on 56 geometries.  Each is switched on by four validation
     geometries and does better than the plain image on eight other held-out
     geometries; the one the validation split prefers gains at least 8% on
     them.  Training either leaves its initial loss plateau (loss 0.007 ->
-    0.004, test gains 1.08-1.21 in a 20-run study of seeds and schedules) or
-    stays on it through the 30 epochs (loss 0.0064, gains 1.05-1.06; a
-    quarter of the runs, which runs depending on float32 summation order),
-    and the validation gain tells the two apart, so model selection on the
-    validation split is what makes the result robust."""
+    0.004-0.006, test gains 1.10-1.22) or stays on it through the 30 epochs
+    (loss 0.0064, gains 1.05-1.06): a quarter to a third of the runs in
+    studies of 20 and 12 runs, which runs depending on float32 summation
+    order.  The validation gain tells the two apart, so model selection on
+    the validation split over six seeds is what makes the result robust
+    (all six stay on the plateau in about one of 700 orderings)."""
     n, K, nt, G = 64, 8, 600, 68
     models = [synth.layered_salt_3d(n, n, n, 900 + i) for i in range(G)]
     data = X.build_dataset(models, 10.0, 16, 1e-3, synth.ricker(15.0, 1e-3, nt), K)
@@ -32,7 +33,7 @@ def test_filter_gain_over_plain_image_on_held_out_geometry():
     train_set, held = data.split(set(range(56, G)))
     test_set, val_set = held.split(set(range(56, 60)))
     best = None
-    for seed in (0, 1, 2):
+    for seed in range(6):
         net = UNet(seed=seed)
         hist = X.train(net, train_set, epochs=30, lr=1e-3, batch=4, seed=seed, lr_decay=0.95, warmup=2)
         den = X.Denoiser(net)

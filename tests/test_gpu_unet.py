@@ -91,7 +91,9 @@ def test_conv_forward_parity(ci, co):
 @pytest.mark.parametrize("ci,co,shape", [(128, 64, (1, 8, 8, 300)), (64, 128, (1, 2, 4, 300))])
 def test_conv_forward_channel_split_grids(ci, co, shape):
     """Grids of 300 and 38 wavefronts, which split the output channels two
-    and four ways over the grid: same bar as the other forward tests."""
+    and four ways over the grid (the smaller one also splits the reduction
+    over four wavefronts of a workgroup, with a partly empty last
+    workgroup): same bar as the other forward tests."""
     _, x, wo, b = _operands(shape, ci, co, 5 + ci + co)
     wf, _ = pack(wo)
     y = torch.empty((x.shape[0], co), dtype=torch.float32, device=DEV)
