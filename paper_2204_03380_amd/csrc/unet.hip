@@ -1306,6 +1306,26 @@ __global__ void up2_kernel(int n, int d, int h, int w, int c, const uint16_t *__
     *reinterpret_cast<uint4 *>(y + vf * c + gi * 8) = *reinterpret_cast<const uint4 *>(x + vc * c + gi * 8);
 }
 
+// out[e] = g[e] where mask[e] > 0, else 0, in bfloat16, for VEC consecutive
+// elements; VEC = 4 reads the mask and writes out as one 8-byte access each
+// (both 8-byte aligned: the launch checks the base pointers).
+template <int VEC>
+__device__ __forceinline__ void relu_mask_store(const uint16_t *mask, const float (&g)[VEC], uint16_t *out)
+{
+    if constexpr (VEC == 4) {
+        const uint2 m = *reinterpret_cast<const uint2 *>(mask);
+        const uint16_t mk[4] = {(uint16_t)(m.x & 0xffffu), (uint16_t)(m.x >> 16), (uint16_t)(m.y & 0xffffu),
+                                (uint16_t)(m.y >> 16)};
+        uint32_t o[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) o[e] = bf2f(mk[e]) > 0.f ? f2bf(g[e]) : 0u;
+        *reinterpret_cast<uint2 *>(out) = uint2{o[0] | (o[1] << 16), o[2] | (o[3] << 16)};
+    } else {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) out[e] = bf2f(mask[e]) > 0.f ? f2bf(g[e]) : (uint16_t)0;
+    }
+}
+
 // One thread per (coarse voxel, VEC consecutive channels): each channel's sum
 // of the 8 children in a fixed order; the index is decoded once, in 32-bit
 // arithmetic when it fits.
@@ -1331,8 +1351,7 @@ __global__ void up2_bwd_kernel(int n, int d, int h, int w, int c, const float *_
 #pragma unroll
     for (int e = 0; e < VEC; ++e) gc[i0 + e] = s[e];
     if (gout)  // the ReLU gradient of the coarse level
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) gout[i0 + e] = bf2f(mask[i0 + e]) > 0.f ? f2bf(s[e]) : (uint16_t)0;
+        relu_mask_store<VEC>(mask + i0, s, gout + i0);
 }
 
 // VEC consecutive channels of one voxel per thread (VEC divides c); the
@@ -1379,8 +1398,7 @@ __global__ void relu_grad_kernel(int n, int d, int h, int w, int c, const float 
 #pragma unroll
         for (int e = 0; e < VEC; ++e) g[e] += gp[vc * c + ch + e] * 0.125f;
     }
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) out[i0 + e] = bf2f(mask[i0 + e]) > 0.f ? f2bf(g[e]) : (uint16_t)0;
+    relu_mask_store<VEC>(mask + i0, g, out + i0);
 }
 
 constexpr int kMseBlocks = 1024;
@@ -1457,6 +1475,7 @@ bool ch_ok(int c) { return c == 16 || c == 32 || c == 64 || c == 128; }
 bool thin_pair(int ci, int co) { return (ci == 1 && co == kThin) || (ci == kThin && co == 1); }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+bool aligned8(const void *p) { return ((uintptr_t)p & 7u) == 0; }
 
 int check_desc(const unet_conv_desc_t *d)
 {
@@ -2053,7 +2072,7 @@ static int up2_bwd_impl(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, c
     rtm::clear_error();
     if (n < 1 || d < 1 || h < 1 || w < 1 || c < 1 || !g_fine || !g_coarse) return bad("invalid up2_bwd arguments");
     const int64_t total = (int64_t)n * d * h * w * c;
-    if (c % 4 == 0)
+    if (c % 4 == 0 && aligned8(mask) && aligned8(g_out))
         hipLaunchKernelGGL(up2_bwd_kernel<4>, grid1(total / 4), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c,
                            g_fine, g_coarse, mask, g_out);
     else
@@ -2086,7 +2105,7 @@ int unet_relu_grad(int32_t n, int32_t d, int32_t h, int32_t w, int32_t c, const 
     if (n < 1 || d < 1 || h < 1 || w < 1 || c < 1 || !g1 || !mask || !out) return bad("invalid relu_grad arguments");
     if (g_pool && ((d | h | w) & 1)) return bad("g_pool needs even extents");
     const int64_t total = (int64_t)n * d * h * w * c;
-    if (c % 4 == 0)
+    if (c % 4 == 0 && aligned8(mask) && aligned8(out))
         hipLaunchKernelGGL(relu_grad_kernel<4>, grid1(total / 4), dim3(256), 0, (hipStream_t)stream, n, d, h, w, c, g1,
                            g2, g_pool, mask, out);
     else
