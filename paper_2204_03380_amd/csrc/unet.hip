@@ -941,9 +941,13 @@ __global__ __launch_bounds__(256) void conv_thin_in_kernel(ConvArgs a)
     for (int i = threadIdx.x; i < kThin * 27; i += blockDim.x) wsh[(i % 27) * kThin + i / 27] = bf2f(a.wt[i]);
     __syncthreads();
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= a.nvox) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t vbase = v - lane;  // the wavefront's first voxel
+    // whole wavefronts only: the stores at the end are shared by its lanes
+    if (vbase >= a.nvox) return;
+    const bool live = v < a.nvox;
     int z, y, x;
-    thin_decode(v, a.d, a.h, a.w, z, y, x);
+    thin_decode(live ? v : vbase, a.d, a.h, a.w, z, y, x);
     const int64_t HW = (int64_t)a.h * a.w;
     float acc[kThin];
 #pragma unroll
@@ -951,7 +955,7 @@ __global__ __launch_bounds__(256) void conv_thin_in_kernel(ConvArgs a)
 #pragma unroll 3
     for (int t = 0; t < 27; ++t) {
         int64_t off;
-        const float xt = thin_tap(t, z, y, x, a.d, a.h, a.w, HW, off) ? bf2f(a.x[v + off]) : 0.f;
+        const float xt = thin_tap(t, z, y, x, a.d, a.h, a.w, HW, off) && live ? bf2f(a.x[v + off]) : 0.f;
 #pragma unroll
         for (int q = 0; q < kThin / 4; ++q) {
             const float4 w4 = wsh4[t * (kThin / 4) + q];
@@ -967,13 +971,48 @@ __global__ __launch_bounds__(256) void conv_thin_in_kernel(ConvArgs a)
         const float t = acc[co] + (a.bias ? a.bias[co] : 0.f);
         val[co] = a.relu ? fmaxf(t, 0.f) : t;
     }
-    // the epilogue of thin_store for all 16 channels, as 16-byte stores
+    // The epilogue of thin_store for all 16 channels.  Each output goes
+    // through the wavefront's LDS rows (voxel lane, kEpiStride floats) so
+    // that a store instruction writes 1 KB contiguous across the lanes
+    // instead of 16 bytes per lane at a 32- or 64-byte stride.
+    __shared__ __attribute__((aligned(16))) float tscr[4][64 * kEpiStride];
+    float *scr = tscr[threadIdx.x >> 6];
+    const int nlive = (int)(a.nvox - vbase < 64 ? a.nvox - vbase : 64);
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
+    // 16 bfloat16 (two 16-byte chunks) per voxel
+    auto store_bf16 = [&](uint16_t *dst, const uint32_t (&w)[kThin / 2]) {
+        uint4 *row = reinterpret_cast<uint4 *>(scr + lane * kEpiStride);
+        row[0] = make_uint4(w[0], w[1], w[2], w[3]);
+        row[1] = make_uint4(w[4], w[5], w[6], w[7]);
+        wave_sync();
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int chunk = k * 64 + lane, vox = chunk >> 1;
+            if (vox < nlive)
+                *reinterpret_cast<uint4 *>(dst + vbase * kThin + chunk * 8) =
+                    *reinterpret_cast<const uint4 *>(scr + vox * kEpiStride + 4 * (chunk & 1));
+        }
+        wave_sync();  // reads done before the rows are written again
+    };
     if (a.y) {
         if (a.ych == kThin) {
-            float4 *py = reinterpret_cast<float4 *>(a.y + v * kThin);
+            float4 *row = reinterpret_cast<float4 *>(scr + lane * kEpiStride);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) py[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
-        } else {
+            for (int q = 0; q < 4; ++q) row[q] = make_float4(val[4 * q], val[4 * q + 1], val[4 * q + 2], val[4 * q + 3]);
+            wave_sync();
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const int chunk = k * 64 + lane, vox = chunk >> 2;
+                if (vox < nlive)
+                    *reinterpret_cast<float4 *>(a.y + vbase * kThin + chunk * 4) =
+                        *reinterpret_cast<const float4 *>(scr + vox * kEpiStride + 4 * (chunk & 3));
+            }
+            wave_sync();
+        } else if (live) {
 #pragma unroll
             for (int co = 0; co < kThin; ++co)
                 if (co < a.ych) a.y[v * a.ych + co] = val[co];
@@ -985,21 +1024,21 @@ __global__ __launch_bounds__(256) void conv_thin_in_kernel(ConvArgs a)
         rb[q] = (uint32_t)f2bf(val[2 * q]) | ((uint32_t)f2bf(val[2 * q + 1]) << 16);
         if (a.out) {
             float o0 = val[2 * q], o1 = val[2 * q + 1];
-            if (a.skip) {
+            if (a.skip && live) {
                 o0 += bf2f(a.skip[v * kThin + 2 * q]);
                 o1 += bf2f(a.skip[v * kThin + 2 * q + 1]);
             }
             ob[q] = (uint32_t)f2bf(o0) | ((uint32_t)f2bf(o1) << 16);
         }
     }
-    if (a.r) {
-        uint4 *pr = reinterpret_cast<uint4 *>(a.r + v * kThin);
-        pr[0] = make_uint4(rb[0], rb[1], rb[2], rb[3]);
-        pr[1] = make_uint4(rb[4], rb[5], rb[6], rb[7]);
-    }
+    if (a.r) store_bf16(a.r, rb);
     if (a.gout) {  // the next layer's ReLU gradient
-        const uint4 *pm = reinterpret_cast<const uint4 *>(a.mask + v * kThin);
-        const uint4 m0 = pm[0], m1 = pm[1];
+        uint4 m0 = make_uint4(0u, 0u, 0u, 0u), m1 = m0;
+        if (live) {
+            const uint4 *pm = reinterpret_cast<const uint4 *>(a.mask + v * kThin);
+            m0 = pm[0];
+            m1 = pm[1];
+        }
         const uint16_t *me0 = reinterpret_cast<const uint16_t *>(&m0);
         const uint16_t *me1 = reinterpret_cast<const uint16_t *>(&m1);
         uint32_t gb[kThin / 2];
@@ -1010,15 +1049,9 @@ __global__ __launch_bounds__(256) void conv_thin_in_kernel(ConvArgs a)
             gb[q] = (uint32_t)(bf2f(me[k]) > 0.f ? f2bf(val[2 * q]) : (uint16_t)0) |
                     ((uint32_t)(bf2f(me[k + 1]) > 0.f ? f2bf(val[2 * q + 1]) : (uint16_t)0) << 16);
         }
-        uint4 *pg = reinterpret_cast<uint4 *>(a.gout + v * kThin);
-        pg[0] = make_uint4(gb[0], gb[1], gb[2], gb[3]);
-        pg[1] = make_uint4(gb[4], gb[5], gb[6], gb[7]);
+        store_bf16(a.gout, gb);
     }
-    if (a.out) {
-        uint4 *po = reinterpret_cast<uint4 *>(a.out + v * kThin);
-        po[0] = make_uint4(ob[0], ob[1], ob[2], ob[3]);
-        po[1] = make_uint4(ob[4], ob[5], ob[6], ob[7]);
-    }
+    if (a.out) store_bf16(a.out, ob);
 }
 
 // 16 -> 1 channel.
