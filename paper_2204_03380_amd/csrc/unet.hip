@@ -813,7 +813,11 @@ void conv_wgrad_ring_kernel(WrArgs a)
 // Two passes (chunks, then the chunk sums) give the same result on every
 // run.  One launch per pass covers two arrays (the weights, n0 floats per
 // partial, then the biases, n1), each summed on its own.
-constexpr int kSumChunk = 32;
+// Partials per chunk of the first pass: 32, or 128 from 2048 partials on
+// (the one-channel layers at 128^3 have 8192: 32 per chunk left 256 chunk
+// sums for the second pass, a chain of dependent loads per thread).
+constexpr int64_t kSumChunk = 32, kSumChunkLarge = 128, kSumLargeFrom = 2048;
+inline int64_t sum_chunk(int64_t P) { return P >= kSumLargeFrom ? kSumChunkLarge : kSumChunk; }
 
 struct SumSet {
     const float *part;
@@ -879,10 +883,10 @@ __global__ void sum_parts_many_kernel(SumMany m)
 hipError_t sum_parts(const float *part0, int64_t n0, float *tmp0, float *out0, const float *part1, int64_t n1,
                      float *tmp1, float *out1, int64_t P, hipStream_t st)
 {
-    const int64_t Q = (P + kSumChunk - 1) / kSumChunk;
+    const int64_t C = sum_chunk(P), Q = (P + C - 1) / C;
     const unsigned bx = (unsigned)((n0 + n1 + 255) / 256);
     hipLaunchKernelGGL(sum_parts_kernel, dim3(bx, (unsigned)Q), dim3(256), 0, st, SumSet{part0, tmp0, n0},
-                       SumSet{part1, tmp1, n1}, P, kSumChunk);
+                       SumSet{part1, tmp1, n1}, P, (int)C);
     hipLaunchKernelGGL(sum_parts_kernel, dim3(bx, 1), dim3(256), 0, st, SumSet{tmp0, out0, n0},
                        SumSet{tmp1, out1, n1}, Q, (int)Q);
     return hipGetLastError();
@@ -1745,7 +1749,7 @@ size_t rnd256(size_t b) { return (b + 255) & ~(size_t)255; }
 size_t wg_bytes(const unet_conv_desc_t *d, int64_t parts)
 {
     const size_t nw = (size_t)d->cout * 27 * d->cin;
-    const size_t q = (size_t)((parts + kSumChunk - 1) / kSumChunk);
+    const size_t q = (size_t)((parts + sum_chunk(parts) - 1) / sum_chunk(parts));
     return rnd256(parts * nw * sizeof(float)) + rnd256(parts * d->cout * sizeof(float)) +
            rnd256(q * nw * sizeof(float)) + rnd256(q * d->cout * sizeof(float));
 }
@@ -1799,7 +1803,7 @@ int wg_ws_split(const unet_conv_desc_t *desc, void *ws, size_t ws_bytes, WgWs *o
     if (!ws || ws_bytes < wg_bytes(desc, o->parts) || ((uintptr_t)ws & 255u))
         return rtm::set_error(RTM_EWORKSPACE, "workspace missing, too small or not 256-byte aligned");
     o->nw = (int64_t)desc->cout * 27 * desc->cin;
-    const int64_t q = (o->parts + kSumChunk - 1) / kSumChunk;
+    const int64_t q = (o->parts + sum_chunk(o->parts) - 1) / sum_chunk(o->parts);
     char *base = static_cast<char *>(ws);
     o->part = reinterpret_cast<float *>(base);
     base += rnd256(o->parts * o->nw * sizeof(float));
@@ -2049,14 +2053,14 @@ int unet_wgrad_reduce_many(int32_t count, const unet_wgrad_item_t *items, void *
         WgWs w;
         if (int e = wg_ws_split(&it.desc, it.ws, it.ws_bytes, &w)) return e;
         const int64_t n1 = it.db ? it.desc.cout : 0;
-        const int64_t q = (w.parts + kSumChunk - 1) / kSumChunk;
+        const int64_t q = (w.parts + sum_chunk(w.parts) - 1) / sum_chunk(w.parts);
         const int32_t bx = (int32_t)((w.nw + n1 + 255) / 256);
-        // the two passes of sum_parts: chunks of kSumChunk partials, then
+        // the two passes of sum_parts: chunks of sum_chunk(P) partials, then
         // the chunk sums
         m1.w[k] = SumSet{w.part, w.tmp_w, w.nw};
         m1.b[k] = SumSet{w.bpart, w.tmp_b, n1};
         m1.P[k] = w.parts;
-        m1.chunk[k] = kSumChunk;
+        m1.chunk[k] = (int32_t)sum_chunk(w.parts);
         m1.bx[k] = bx;
         m1.start[k + 1] = m1.start[k] + (int64_t)bx * q;
         m2.w[k] = SumSet{w.tmp_w, it.dw, w.nw};

@@ -220,7 +220,8 @@ def test_unet_channel_pairs_on_the_host():
         return (b + 255) // 256 * 256
 
     def thin_bytes(parts, nb):
-        q = (parts + 31) // 32
+        chunk = 128 if parts >= 2048 else 32  # partials per first-pass chunk
+        q = (parts + chunk - 1) // chunk
         return rnd(parts * 432 * 4) + rnd(parts * nb * 4) + rnd(q * 432 * 4) + rnd(q * nb * 4)
 
     for ci, co in ((16, 16), (32, 64), (128, 64), (1, 16), (16, 1)):
