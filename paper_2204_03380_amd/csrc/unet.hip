@@ -1276,6 +1276,32 @@ __global__ void embed_kernel(int64_t nvox, int ch, const float *__restrict__ img
     x[i] = (i - v * ch) == 0 ? f2bf(img[v] * scale) : (uint16_t)0;
 }
 
+// embed_kernel for eight consecutive elements per thread, stored as one
+// 16-byte vector (the element count a multiple of 8, x 16-byte aligned).
+__global__ void embed8_kernel(int64_t nvox, int ch, const float *__restrict__ img, float scale,
+                              uint16_t *__restrict__ x)
+{
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 8;
+    if (i0 >= nvox * ch) return;
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t h[2];
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int64_t i = i0 + 2 * q + e;
+            if (ch == 1) {
+                h[e] = f2bf(img[i] * scale);
+            } else {
+                const int64_t v = i / ch;
+                h[e] = (i - v * ch) == 0 ? f2bf(img[v] * scale) : 0u;
+            }
+        }
+        w[q] = h[0] | (h[1] << 16);
+    }
+    *reinterpret_cast<uint4 *>(x + i0) = make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 // Index i of an [n][d][h][w][cg] array as (g, x, y, z, n), in 32-bit
 // arithmetic when the array has fewer than 2^32 elements.
 __device__ __forceinline__ void decode5(int64_t i, int64_t total, int cg, int w, int h, int d, int &g, int &x, int &y,
@@ -1460,6 +1486,44 @@ __global__ void mse_kernel(int64_t nvox, int ch, const float *__restrict__ img, 
             if (gy) {
                 gy[v * ch] = f2bf(gscale * df);
                 for (int k = 1; k < ch; ++k) gy[v * ch + k] = 0;
+            }
+        }
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int k = 128; k > 0; k >>= 1) {
+        if ((int)threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// mse_kernel for one channel, four voxels per step: 16-byte loads of img, y
+// and tgt, a 16-byte store of out and an 8-byte store of gy (nvox a multiple
+// of 4; the launch checks the alignments).  out and gy get the same bits;
+// the loss sums the same squares in another order.
+__global__ void mse4_kernel(int64_t nvox, const float *__restrict__ img, const float *__restrict__ y,
+                            const float *__restrict__ tgt, float *__restrict__ out, uint16_t *__restrict__ gy,
+                            double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    const float gscale = 2.0f / (float)nvox;
+    const int64_t n4 = nvox / 4;
+    for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n4; q += (int64_t)gridDim.x * blockDim.x) {
+        const float4 a = reinterpret_cast<const float4 *>(img)[q], b = reinterpret_cast<const float4 *>(y)[q];
+        const float o[4] = {a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w};
+        if (out) reinterpret_cast<float4 *>(out)[q] = make_float4(o[0], o[1], o[2], o[3]);
+        if (tgt) {
+            const float4 t = reinterpret_cast<const float4 *>(tgt)[q];
+            const float df[4] = {o[0] - t.x, o[1] - t.y, o[2] - t.z, o[3] - t.w};
+#pragma unroll
+            for (int e = 0; e < 4; ++e) s += (double)df[e] * (double)df[e];
+            if (gy) {
+                uint32_t g[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) g[e] = f2bf(gscale * df[e]);
+                reinterpret_cast<uint2 *>(gy)[q] = uint2{g[0] | (g[1] << 16), g[2] | (g[3] << 16)};
             }
         }
     }
@@ -2082,8 +2146,12 @@ int unet_embed(int64_t nvox, int32_t channels, const float *img, float scale, ui
 {
     rtm::clear_error();
     if (nvox < 1 || channels < 1 || !img || !x) return bad("invalid embed arguments");
-    hipLaunchKernelGGL(embed_kernel, grid1(nvox * channels), dim3(256), 0, (hipStream_t)stream, nvox, channels, img,
-                       scale, x);
+    if ((nvox * channels) % 8 == 0 && aligned16(x))
+        hipLaunchKernelGGL(embed8_kernel, grid1(nvox * channels / 8), dim3(256), 0, (hipStream_t)stream, nvox, channels,
+                           img, scale, x);
+    else
+        hipLaunchKernelGGL(embed_kernel, grid1(nvox * channels), dim3(256), 0, (hipStream_t)stream, nvox, channels, img,
+                           scale, x);
     UNET_HIP(hipGetLastError());
     return RTM_OK;
 }
@@ -2178,9 +2246,15 @@ int unet_mse(int64_t nvox, int32_t channels, const float *img, const float *y, c
         return rtm::set_error(RTM_EWORKSPACE, "workspace missing or too small");
     hipStream_t st = (hipStream_t)stream;
     double *part = static_cast<double *>(ws);
-    int nb = (int)((nvox + 255) / 256);
-    if (nb > kMseBlocks) nb = kMseBlocks;
-    hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, st, nvox, channels, img, y, target, out, gy, part);
+    int nb;
+    if (channels == 1 && nvox % 4 == 0 && aligned16(img) && aligned16(y) && aligned16(target) && aligned16(out) &&
+        aligned8(gy)) {
+        nb = (int)std::min<int64_t>(kMseBlocks, (nvox / 4 + 255) / 256);
+        hipLaunchKernelGGL(mse4_kernel, dim3(nb), dim3(256), 0, st, nvox, img, y, target, out, gy, part);
+    } else {
+        nb = (int)std::min<int64_t>(kMseBlocks, (nvox + 255) / 256);
+        hipLaunchKernelGGL(mse_kernel, dim3(nb), dim3(256), 0, st, nvox, channels, img, y, target, out, gy, part);
+    }
     if (target) {
         hipLaunchKernelGGL(mse_final_kernel, dim3(1), dim3(256), 0, st, part, nb, nvox, part + kMseBlocks);
         if (loss) {
