@@ -1251,6 +1251,9 @@ struct PackSet {
     int count;
 };
 
+// SMALL: every layer has fewer than 2^32 weights, so the index is split in
+// 32-bit arithmetic (the 64-bit divisions are emulated in software).
+template <bool SMALL>
 __global__ void weight_pack_many_kernel(PackSet P)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -1259,9 +1262,17 @@ __global__ void weight_pack_many_kernel(PackSet P)
     while (i >= P.start[k + 1]) ++k;
     const unet_pack_item_t &L = P.item[k];
     const int64_t j = i - P.start[k];
-    const int ci = (int)(j % L.cin);
-    const int t = (int)((j / L.cin) % 27);
-    const int co = (int)(j / (27 * (int64_t)L.cin));
+    int ci, t, co;
+    if constexpr (SMALL) {
+        const uint32_t j32 = (uint32_t)j, jt = j32 / (uint32_t)L.cin;
+        ci = (int)(j32 - jt * (uint32_t)L.cin);
+        t = (int)(jt % 27u);
+        co = (int)(jt / 27u);
+    } else {
+        ci = (int)(j % L.cin);
+        t = (int)((j / L.cin) % 27);
+        co = (int)(j / (27 * (int64_t)L.cin));
+    }
     const uint16_t b = f2bf(L.w[j]);
     if (L.w_fwd) L.w_fwd[j] = b;
     if (L.w_bwd) L.w_bwd[(int64_t)ci * 27 * L.cout + (int64_t)(26 - t) * L.cout + co] = b;
@@ -1968,7 +1979,12 @@ int unet_weight_pack_many(int32_t count, const unet_pack_item_t *items, void *st
         P.item[k] = L;
         P.start[k + 1] = P.start[k] + (int64_t)L.cout * 27 * L.cin;
     }
-    hipLaunchKernelGGL(weight_pack_many_kernel, grid1(P.start[count]), dim3(256), 0, (hipStream_t)stream, P);
+    bool small = true;
+    for (int k = 0; k < count; ++k) small = small && P.start[k + 1] - P.start[k] < ((int64_t)1 << 32);
+    if (small)
+        hipLaunchKernelGGL(weight_pack_many_kernel<true>, grid1(P.start[count]), dim3(256), 0, (hipStream_t)stream, P);
+    else
+        hipLaunchKernelGGL(weight_pack_many_kernel<false>, grid1(P.start[count]), dim3(256), 0, (hipStream_t)stream, P);
     UNET_HIP(hipGetLastError());
     return RTM_OK;
 }
